@@ -1,0 +1,163 @@
+"""Oracle: the particle-mesh gravity operators in float64.
+
+Follows Sec. 2.1 of the paper: the density is interpolated onto a uniform cubic mesh
+(cloud-in-cell, "CIC", Sec. 2.3), Fourier transformed, multiplied by the Poisson
+kernel of eq. (2), differentiated spectrally as in eq. (3), transformed back, and the
+force is interpolated back to the particles with the same CIC weights
+("inverse force interpolation", Fig. 2).
+
+Readings where the paper is silent:
+  * CIC is node-centred: u = x n_g, i = floor(u), f = u - i, weights (1 - f, f) on
+    nodes i and i+1 (mod n_g) per axis, product over the three axes;
+  * the Poisson kernel carries Plummer softening of eps = soft_cells mesh cells:
+    G(k) = -4 pi G eps K1(k eps) / k, the Fourier transform of -G / sqrt(r^2 + eps^2);
+    it tends to eq. (2)'s -4 pi G / k^2 as eps -> 0; G(0) = 0 removes the mean density;
+  * the gradient factor -i k_a is zeroed on the Nyquist index n_a = -n_g/2 so the
+    real-space difference operator stays real and odd.
+
+Pins (tests/test_oracle_pins.py): kernel against the Fourier transform of the Plummer
+density computed by quadrature and against the eps -> 0 limit; FFT path against
+explicit DFT sums; mass conservation; zero self-force; momentum conservation; inverse
+square law against Ewald sums; Zel'dovich plane-wave response and growth.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.special
+
+FOUR_PI = 4.0 * np.pi
+
+
+def _corner_weights(x: np.ndarray, n_g: int):
+    """Yield (flat node index, weight, per-axis (w, sign)) for the 8 CIC corners."""
+    u = np.asarray(x, dtype=np.float64) * n_g
+    i = np.floor(u)
+    f = u - i
+    i = i.astype(np.int64) % n_g
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                d = (dx, dy, dz)
+                ws = []
+                for a in range(3):
+                    ws.append(f[:, a] if d[a] else 1.0 - f[:, a])
+                idx = (((i[:, 2] + dz) % n_g) * n_g + (i[:, 1] + dy) % n_g) * n_g \
+                    + (i[:, 0] + dx) % n_g
+                yield idx, ws, d
+
+
+def deposit(x: np.ndarray, mass, n_g: int) -> np.ndarray:
+    """CIC mass density rho(c) = Delta^-3 sum_i m_i W(x_i - x_c); returns [z][y][x]."""
+    x = np.asarray(x, dtype=np.float64)
+    m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (x.shape[0],))
+    rho = np.zeros(n_g ** 3, dtype=np.float64)
+    for idx, ws, _ in _corner_weights(x, n_g):
+        rho += np.bincount(idx, weights=m * ws[0] * ws[1] * ws[2], minlength=n_g ** 3)
+    return rho.reshape(n_g, n_g, n_g) * float(n_g) ** 3
+
+
+def deposit_species(species, n_g: int) -> np.ndarray:
+    """Both species onto the same mesh (Sec. 2.1 footnote): list of (x, mass)."""
+    rho = np.zeros((n_g, n_g, n_g), dtype=np.float64)
+    for x, m in species:
+        rho += deposit(x, m, n_g)
+    return rho
+
+
+def wave_numbers(n_g: int):
+    """Integer wave numbers on numpy's rfft grid: (nz, ny, nx) broadcastable."""
+    f = np.fft.fftfreq(n_g, d=1.0 / n_g)
+    fx = np.fft.rfftfreq(n_g, d=1.0 / n_g)
+    return f[:, None, None], f[None, :, None], fx[None, None, :]
+
+
+def plummer_kernel_k(k: np.ndarray, eps: float, G: float) -> np.ndarray:
+    """-4 pi G eps K1(k eps) / k for k > 0 (eps > 0), -4 pi G / k^2 for eps = 0; 0 at k=0."""
+    k = np.asarray(k, dtype=np.float64)
+    out = np.zeros_like(k)
+    pos = k > 0
+    if eps > 0:
+        out[pos] = -FOUR_PI * G * eps * scipy.special.k1(k[pos] * eps) / k[pos]
+    else:
+        out[pos] = -FOUR_PI * G / (k[pos] * k[pos])
+    return out
+
+
+def green(n_g: int, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI) -> np.ndarray:
+    """Kernel on the rfft grid [z][y][x<=n/2]; depends on |n|^2 only."""
+    nz, ny, nx = wave_numbers(n_g)
+    k = 2.0 * np.pi * np.sqrt(nz * nz + ny * ny + nx * nx)
+    return plummer_kernel_k(k, soft_cells / n_g, G)
+
+
+def gradient_factors(n_g: int):
+    """-i k_a per axis on the rfft grid, zero on the Nyquist index."""
+    nz, ny, nx = wave_numbers(n_g)
+    out = []
+    for nn in (nx, ny, nz):
+        kk = 2.0 * np.pi * np.where(np.abs(nn) == n_g // 2, 0.0, nn)
+        out.append(-1j * kk)
+    return out  # x, y, z
+
+
+def force_mesh(rho: np.ndarray, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI) -> np.ndarray:
+    """Acceleration mesh a[3][z][y][x] from density: eqs. (2)-(3) with F = m a."""
+    n_g = rho.shape[0]
+    phi_k = green(n_g, soft_cells, G) * np.fft.rfftn(rho)
+    a = np.empty((3, n_g, n_g, n_g), dtype=np.float64)
+    for ax, fac in enumerate(gradient_factors(n_g)):
+        a[ax] = np.fft.irfftn(fac * phi_k, s=(n_g, n_g, n_g), axes=(0, 1, 2))
+    return a
+
+
+def interpolate(a: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """CIC gather a_i = sum_c W(x_i - x_c) a(c) for each component; returns [n][3]."""
+    n_g = a.shape[1]
+    flat = a.reshape(3, -1)
+    out = np.zeros((x.shape[0], 3), dtype=np.float64)
+    for idx, ws, _ in _corner_weights(x, n_g):
+        w = ws[0] * ws[1] * ws[2]
+        for c in range(3):
+            out[:, c] += w * flat[c, idx]
+    return out
+
+
+def scatter_vector(x: np.ndarray, g: np.ndarray, n_g: int) -> np.ndarray:
+    """Transpose of interpolate: mu_a(c) = sum_i W(x_i - x_c) g_ia; returns [3][z][y][x]."""
+    mu = np.zeros((3, n_g ** 3), dtype=np.float64)
+    for idx, ws, _ in _corner_weights(x, n_g):
+        w = ws[0] * ws[1] * ws[2]
+        for c in range(3):
+            mu[c] += np.bincount(idx, weights=w * g[:, c], minlength=n_g ** 3)
+    return mu.reshape(3, n_g, n_g, n_g)
+
+
+def gather_grad(mesh: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """sum_c grad_x W(x_i - x_c) f(c) for a scalar mesh f; returns [n][3].
+
+    The weight per axis is (1 - f) or f with f = u - floor(u), so its derivative with
+    respect to x is -n_g or +n_g; the derivative at f = 0 is taken one-sided, with the
+    node assignment that floor gives.
+    """
+    n_g = mesh.shape[0]
+    flat = mesh.reshape(-1)
+    out = np.zeros((x.shape[0], 3), dtype=np.float64)
+    for idx, ws, d in _corner_weights(x, n_g):
+        val = flat[idx]
+        for a in range(3):
+            s = n_g if d[a] else -n_g
+            prod = s * val
+            for b in range(3):
+                if b != a:
+                    prod = prod * ws[b]
+            out[:, a] += prod
+    return out
+
+
+def accelerations(species, n_g: int, soft_cells: float = 1.0,
+                  G: float = 1.0 / FOUR_PI):
+    """Full PM force: list of (x, mass) -> (list of a_i [n][3], mesh a[3][...])."""
+    rho = deposit_species(species, n_g)
+    a = force_mesh(rho, soft_cells, G)
+    return [interpolate(a, x) for x, _ in species], a, rho

@@ -1,0 +1,269 @@
+"""Pins of the FP64 oracle's mesh operators against facts fixed by the paper and by
+mathematics, not by the oracle itself (CPU only).
+
+Each test names what would break if the oracle had a plausible mistake: a dropped
+factor, a wrong sign or index, a transposed operand, a wrong normalisation.
+"""
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.special
+
+from oracle import mesh
+
+G = 1.0 / (4.0 * np.pi)
+
+
+# ------------------------------------------------------------------ P1 kernel --
+
+def plummer_density_ft(k, eps):
+    """Fourier transform of the unit-mass Plummer density by quadrature.
+
+    rho_P(r) = 3 eps^2 / (4 pi (r^2 + eps^2)^(5/2)); its transform is
+    4 pi int_0^inf rho_P(r) r^2 sin(k r)/(k r) dr, evaluated with QUADPACK's Fourier
+    integral routine. Independent of any Bessel function.
+    """
+    f = lambda r: 4.0 * np.pi * 3.0 * eps * eps / (4.0 * np.pi) * r / \
+        ((r * r + eps * eps) ** 2.5) / k
+    val, _ = scipy.integrate.quad(f, 0.0, np.inf, weight="sin", wvar=k, limlst=200)
+    return val
+
+
+@pytest.mark.parametrize("eps", [1.0 / 64, 1.0 / 256, 2.0 / 128])
+def test_kernel_is_fourier_transform_of_plummer_potential(eps):
+    # Poisson (eq. 1): -k^2 phi(k) = 4 pi G rho(k); for a Plummer sphere the potential
+    # is -G/sqrt(r^2+eps^2), so the softened kernel must equal -4 pi G rho_P(k) / k^2.
+    for n in [1, 3, 10, 37, 90]:
+        k = 2.0 * np.pi * n
+        if k * eps > 6.0:
+            continue
+        expect = -4.0 * np.pi * G * plummer_density_ft(k, eps) / (k * k)
+        got = mesh.plummer_kernel_k(np.array([k]), eps, G)[0]
+        assert abs(got / expect - 1.0) < 1e-9, (n, got, expect)
+
+
+def test_kernel_unsoftened_limit_is_eq2():
+    k = 2.0 * np.pi * np.array([1.0, 2.0, 5.0, 11.0])
+    base = -4.0 * np.pi * G / k ** 2
+    assert np.allclose(mesh.plummer_kernel_k(k, 0.0, G), base, rtol=0, atol=0)
+    # eps -> 0: eps K1(k eps)/k -> 1/k^2 with correction O((k eps)^2 log(k eps))
+    for eps in [1e-3, 1e-5, 1e-7]:
+        r = mesh.plummer_kernel_k(k, eps, G) / base
+        x = k * eps
+        assert np.all(np.abs(r - 1.0) <= x * x * (np.abs(np.log(x)) + 1.0))
+    assert mesh.plummer_kernel_k(np.array([0.0]), 0.1, G)[0] == 0.0
+
+
+# ------------------------------------------------------- brute force tiny boxes --
+
+def brute_deposit(x, m, n):
+    rho = np.zeros((n, n, n))
+    for p in range(x.shape[0]):
+        u = x[p] * n
+        i = [int(np.floor(c)) for c in u]
+        f = [u[a] - i[a] for a in range(3)]
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    w = (f[0] if dx else 1 - f[0]) * (f[1] if dy else 1 - f[1]) * \
+                        (f[2] if dz else 1 - f[2])
+                    rho[(i[2] + dz) % n, (i[1] + dy) % n, (i[0] + dx) % n] += m[p] * w
+    return rho * n ** 3
+
+
+def brute_force_mesh(rho):
+    """Explicit DFT sums (no FFT), kernel from its formula, Nyquist zeroed."""
+    n = rho.shape[0]
+    c = np.arange(n)
+    sn = np.where(c < n // 2, c, c - n)  # signed wave numbers in [-n/2, n/2)
+    # forward DFT by explicit sums over all nodes
+    E = np.exp(-2j * np.pi * np.outer(sn, c) / n)  # [wave, node]
+    rk = np.einsum("az,by,cx,zyx->abc", E, E, E, rho.astype(complex))
+    NZ, NY, NX = np.meshgrid(sn, sn, sn, indexing="ij")
+    kk = 2 * np.pi * np.sqrt(NX ** 2 + NY ** 2 + NZ ** 2)
+    eps = 1.0 / n
+    g = np.zeros_like(kk)
+    pos = kk > 0
+    g[pos] = -4 * np.pi * G * eps * scipy.special.k1(kk[pos] * eps) / kk[pos]
+    out = np.zeros((3, n, n, n))
+    Einv = np.exp(2j * np.pi * np.outer(c, sn) / n)  # [node, wave]
+    for ax, NN in enumerate((NX, NY, NZ)):
+        kax = 2 * np.pi * np.where(NN == -n // 2, 0, NN)
+        ak = -1j * kax * g * rk
+        a = np.einsum("za,yb,xc,abc->zyx", Einv, Einv, Einv, ak) / n ** 3
+        assert np.max(np.abs(a.imag)) < 1e-10 * (np.max(np.abs(a.real)) + 1e-300)
+        out[ax] = a.real
+    return out
+
+
+@pytest.mark.parametrize("n,npart", [(4, 5), (6, 7), (8, 16)])
+def test_tiny_box_brute_force(n, npart):
+    rng = np.random.default_rng(n)
+    x = rng.random((npart, 3))
+    m = rng.random(npart) + 0.5
+    rho = mesh.deposit(x, m, n)
+    assert np.allclose(rho, brute_deposit(x, m, n), rtol=1e-13, atol=1e-13 * rho.max())
+    a = mesh.force_mesh(rho)
+    ab = brute_force_mesh(rho)
+    scale = np.max(np.abs(ab))
+    assert np.max(np.abs(a - ab)) <= 1e-12 * scale
+    # interpolation by explicit loops
+    ai = mesh.interpolate(a, x)
+    for p in range(npart):
+        u = x[p] * n
+        i = np.floor(u).astype(int)
+        f = u - i
+        acc = np.zeros(3)
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    w = (f[0] if dx else 1 - f[0]) * (f[1] if dy else 1 - f[1]) * \
+                        (f[2] if dz else 1 - f[2])
+                    acc += w * a[:, (i[2] + dz) % n, (i[1] + dy) % n, (i[0] + dx) % n]
+        assert np.allclose(ai[p], acc, rtol=1e-13, atol=1e-13 * scale)
+
+
+# ----------------------------------------------------------- conservation laws --
+
+def test_mass_conservation():
+    rng = np.random.default_rng(3)
+    for n in (8, 16, 32):
+        x = rng.random((1000, 3))
+        m = rng.random(1000)
+        rho = mesh.deposit(x, m, n)
+        assert abs(rho.sum() / n ** 3 - m.sum()) <= 1e-14 * m.sum() * 10
+
+
+def test_zero_self_force():
+    rng = np.random.default_rng(4)
+    n = 16
+    scale = G * 1.0 * n * n  # |a| of a unit mass one cell away, order of magnitude
+    for _ in range(100):
+        x = rng.random((1, 3))
+        (ai,), _, _ = mesh.accelerations([(x, 1.0)], n)
+        assert np.max(np.abs(ai)) <= 1e-13 * scale
+
+
+def test_momentum_conservation_two_species():
+    rng = np.random.default_rng(5)
+    n = 16
+    xc = rng.random((300, 3))
+    xn = rng.random((2400, 3))
+    mc, mn = 1.0 / 300, 0.01 / 2400
+    (ac, an), _, _ = mesh.accelerations([(xc, mc), (xn, mn)], n)
+    p = mc * ac.sum(0) + mn * an.sum(0)
+    s = mc * np.abs(ac).sum() + mn * np.abs(an).sum()
+    assert np.max(np.abs(p)) <= 1e-13 * s
+
+
+# ------------------------------------------------------------ inverse square --
+
+def ewald_newton(r, alpha=2.0, nreal=3, nk=10):
+    """Periodic Newtonian acceleration of a unit mass at the origin (G = 1/4pi),
+    unit box, uniform neutralising background: textbook Ewald summation."""
+    r = np.asarray(r, dtype=np.float64)
+    acc = np.zeros(3)
+    rng_ = range(-nreal, nreal + 1)
+    for i in rng_:
+        for j in rng_:
+            for k in rng_:
+                d = r - np.array([i, j, k], dtype=np.float64)
+                s = np.linalg.norm(d)
+                acc -= d / s ** 3 * (scipy.special.erfc(alpha * s)
+                                     + 2 * alpha * s / np.sqrt(np.pi) * np.exp(-(alpha * s) ** 2))
+    h = np.arange(-nk, nk + 1)
+    HX, HY, HZ = np.meshgrid(h, h, h, indexing="ij")
+    H = np.stack([HX.ravel(), HY.ravel(), HZ.ravel()], 1)
+    H = H[np.any(H != 0, axis=1)]
+    kv = 2 * np.pi * H
+    k2 = np.sum(kv * kv, 1)
+    fac = 4 * np.pi / k2 * np.exp(-k2 / (4 * alpha * alpha)) * np.sin(kv @ r)
+    acc -= (fac[:, None] * kv).sum(0)
+    return G * acc
+
+
+def test_inverse_square_far_from_softening():
+    # A point mass far from the softening scale pulls with G m r / |r|^3 (periodic
+    # images via Ewald), reduced by the Plummer factor r^3/(r^2+eps^2)^(3/2).
+    n = 64
+    rng = np.random.default_rng(7)
+    src = rng.random(3)
+    for rc in (8.0, 12.0, 16.0):
+        dirs = rng.standard_normal((12, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        xt = np.mod(src + dirs * rc / n, 1.0)
+        x = np.vstack([src[None, :], xt])
+        m = np.concatenate([[1.0], np.zeros(len(xt))])
+        rho = mesh.deposit(x, m, n)
+        a = mesh.force_mesh(rho)
+        ai = mesh.interpolate(a, xt)
+        errs = []
+        for p in range(len(xt)):
+            d = dirs[p] * rc / n
+            ref = ewald_newton(d)
+            rr = rc / n
+            eps = 1.0 / n
+            ref = ref * rr ** 3 / (rr * rr + eps * eps) ** 1.5
+            errs.append(np.linalg.norm(ai[p] - ref) / np.linalg.norm(ref))
+        rms = np.sqrt(np.mean(np.square(errs)))
+        assert rms < 0.01, (rc, rms)
+
+
+# -------------------------------------------------------- Zel'dovich plane wave --
+
+def plane_wave(n, amp_cells):
+    i = (np.arange(n) + 0.5) / n  # particles at cell centres
+    qz, qy, qx = np.meshgrid(i, i, i, indexing="ij")
+    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], 1)
+    A = amp_cells / n
+    x = q.copy()
+    x[:, 0] = np.mod(q[:, 0] + A * np.sin(2 * np.pi * q[:, 0]), 1.0)
+    return q, x, A
+
+
+def transfer(n, soft=1.0):
+    k = 2 * np.pi
+    eps = soft / n
+    D = 1.0 / n
+    return k * eps * scipy.special.k1(k * eps) * np.sin(k * D) / (k * D)
+
+
+def test_zeldovich_plane_wave_force():
+    # Linear response of a single plane wave on a cell-centred lattice: the CIC deposit
+    # is exactly a central difference of psi, the kernel multiplies by eps k K1(k eps),
+    # the interpolation averages two nodes; the projection of a_x on sin(2 pi q) is
+    # T(k) * A with T = k eps K1(k eps) sin(k Delta)/(k Delta) (4 pi G rho = 1).
+    n = 32
+    q, x, A = plane_wave(n, 0.05)
+    (ai,), _, _ = mesh.accelerations([(x, 1.0 / n ** 3)], n)
+    s = np.sin(2 * np.pi * q[:, 0])
+    proj = np.sum(ai[:, 0] * s) / np.sum(s * s)
+    assert abs(proj / (transfer(n) * A) - 1.0) < 1e-10
+    assert np.max(np.abs(ai[:, 1:])) < 1e-12 * np.max(np.abs(ai[:, 0]))
+
+
+@pytest.mark.slow
+def test_zeldovich_plane_wave_growth():
+    # Kick-drift leapfrog from rest: the mode amplitude obeys the discrete recurrence
+    # psi_{k+1} = (2 + h^2 T) psi_k - psi_{k-1}, psi_{-1} = psi_0 (the half-step
+    # velocity v_{-1/2} is zero), and approaches the continuum solution at rest at
+    # t = -h/2, cosh(sqrt(T) (t + h/2)) / cosh(sqrt(T) h/2), as h -> 0.
+    from oracle.step import step_float
+    n, h, K = 16, 0.01, 100
+    q, x, A = plane_wave(n, 0.05)
+    v = np.zeros_like(x)
+    m = 1.0 / n ** 3
+    T = transfer(n)
+    s = np.sin(2 * np.pi * q[:, 0])
+    prev, cur = A, A
+    for _ in range(K):
+        (out,), _ = step_float([(x, v, m)], n, h, h)
+        x, v = out
+        prev, cur = cur, (2 + h * h * T) * cur - prev
+        disp = np.mod(x[:, 0] - q[:, 0] + 0.5, 1.0) - 0.5
+    proj = np.sum(disp * s) / np.sum(s * s)
+    assert abs(proj / cur - 1.0) < 1e-4
+    sT = np.sqrt(T)
+    cont = A * np.cosh(sT * (K * h + h / 2)) / np.cosh(sT * h / 2)
+    assert abs(cur / cont - 1.0) < 1e-4
