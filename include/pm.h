@@ -1,0 +1,232 @@
+/*
+ * pm.h - C ABI of the MI355X particle-mesh (PM) step with compressed particles.
+ *
+ * The library advances a periodic box of two particle species (cold dark matter and
+ * neutrinos) by one particle-mesh gravity step, as described in Emberson et al.,
+ * "Cosmological neutrino simulations at extreme scale" (arXiv:1611.01545):
+ *   - cloud-in-cell (CIC) mass deposit of all species on one mesh (Sec. 2.1 and its
+ *     footnote; CIC is named in Sec. 2.3),
+ *   - FFT solution of the Poisson equation, eqs. (1)-(2), and the spectral force of
+ *     eq. (3), with Plummer softening of the kernel,
+ *   - CIC interpolation of the force back to the particles (Fig. 2,
+ *     "inverse_force_interpolation"),
+ *   - a kick-drift leapfrog update,
+ * on particles stored in the compressed phase-space format of Sec. 2.4: per-cell
+ * particle counts (one byte, 255 + a 4-byte count as escape), one byte per axis of
+ * position offset inside the cell and a 2-byte velocity histogram index per axis.
+ *
+ * Conventions for every entry point:
+ *   - box side 1; positions in [0, 1); mesh arrays are float [z][y][x] (x fastest);
+ *     particle float arrays are [n][3] with columns x, y, z;
+ *   - all pointers documented "device" are device memory on the context's GPU; the
+ *     caller owns them and keeps them alive until the work is done;
+ *   - calls validate their arguments on the host, then enqueue asynchronously on the
+ *     context's HIP stream and return; errors detected on the device (capacity
+ *     exceeded, out-of-range input) are latched and returned by pm_sync();
+ *   - counts and indices are 64-bit;
+ *   - a context is not thread-safe; calls on one context are ordered by its stream.
+ *
+ * Status codes: PM_OK on success; PM_ERR_ARG for a null or inconsistent argument;
+ * PM_ERR_SHAPE for mesh/cell sizes the library does not support; PM_ERR_NOMEM when a
+ * device allocation fails; PM_ERR_DEVICE when a HIP call fails; PM_ERR_CAPACITY when
+ * an output buffer is too small (pm_last_error_detail reports the size needed);
+ * PM_ERR_CORRUPT for a byte stream that fails its integrity checks; PM_ERR_RANGE for
+ * non-finite input.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pm_status {
+  PM_OK = 0,
+  PM_ERR_ARG = 1,
+  PM_ERR_SHAPE = 2,
+  PM_ERR_NOMEM = 3,
+  PM_ERR_DEVICE = 4,
+  PM_ERR_CAPACITY = 5,
+  PM_ERR_CORRUPT = 6,
+  PM_ERR_RANGE = 7
+} pm_status;
+
+typedef struct pm_context* pm_ctx;
+
+/* Sizes and physics constants of a context.
+ *   n_mesh     PM mesh side n_g: a power of two, 8 <= n_mesh <= 2048.
+ *   n_cell     compression mesh side n_c (Sec. 2.4 uses (n_p/2)^3 cells): a power of
+ *              two, 1 <= n_cell <= 1024, dividing n_mesh, n_mesh/n_cell <= 16.
+ *   brick      cells per brick side B of the stream order: a power of two dividing
+ *              n_cell, B <= 8. Cells are ordered brick by brick (x fastest), and x
+ *              fastest inside a brick; B = 1 is plain row-major order.
+ *   flags      0.
+ *   G          gravitational constant (1/(4 pi) makes 4 pi G = 1).
+ *   soft_cells Plummer softening length in mesh cells (>= 0). */
+typedef struct pm_config {
+  int64_t n_mesh;
+  int64_t n_cell;
+  int32_t brick;
+  int32_t flags;
+  double G;
+  double soft_cells;
+} pm_config;
+
+/* Device-resident header of one compressed species (32 bytes).
+ *   v_max  half-range of the velocity histogram (the paper keeps it in the file
+ *          header, one per species, Sec. 2.4);
+ *   j_min, j_max  smallest / largest velocity code present (65536 / -1 if none);
+ *   flags  0 for a valid state;
+ *   n_esc  number of escape entries in use. */
+typedef struct pm_shdr {
+  float v_max;
+  int32_t j_min;
+  int32_t j_max;
+  int32_t flags;
+  int64_t n_esc;
+  int64_t reserved;
+} pm_shdr;
+
+enum { PM_FLOAT = 0, PM_COMPRESSED = 1 };
+
+/* One particle species.
+ *   layout  PM_FLOAT: x, v are device float [n][3] (positions in [0,1)).
+ *           PM_COMPRESSED: count, pos, vel, esc, hdr describe the Sec. 2.4 format:
+ *             count  device uint8 [n_cell^3], one per cell in stream order; 255 means
+ *                    "see the escape table";
+ *             pos    device uint8 [n][3], position offset inside the cell, in units
+ *                    of 1/(256 n_cell);
+ *             vel    device uint16 [n][3], velocity bin in [0, 65535] over
+ *                    [-v_max, v_max];
+ *             esc    device uint64 [cap_esc][2], (cell, count) for every cell with
+ *                    count >= 255, sorted by cell;
+ *             hdr    device pm_shdr.
+ *   n       particle count (>= 0); mass  mass per particle. */
+typedef struct pm_species {
+  int32_t layout;
+  int32_t reserved;
+  int64_t n;
+  double mass;
+  float* x;
+  float* v;
+  uint8_t* count;
+  uint8_t* pos;
+  uint16_t* vel;
+  uint64_t* esc;
+  int64_t cap_esc;
+  pm_shdr* hdr;
+} pm_species;
+
+/* Message for a status code (static string). */
+const char* pm_status_str(pm_status s);
+
+/* Create a context on the current HIP device; `stream` is a hipStream_t (NULL for
+ * the default stream). Builds the gravity-kernel table in float64 on the GPU. */
+pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out);
+pm_status pm_destroy(pm_ctx ctx);
+
+/* Wait for all enqueued work; return the first latched device error (and clear it). */
+pm_status pm_sync(pm_ctx ctx);
+/* After PM_ERR_CAPACITY: the capacity (elements) that would have been needed. */
+pm_status pm_last_error_detail(pm_ctx ctx, int64_t* needed);
+
+/* Compress float particles (Sec. 2.4): v_max = largest |v_a| of the species; cells of
+ * the n_cell^3 mesh in stream order; particles of a cell in input order.
+ * in: PM_FLOAT; out: PM_COMPRESSED with out->n == in->n. perm (device int64 [n],
+ * nullable) receives, for each stream position, the input index of that particle. */
+pm_status pm_encode(pm_ctx ctx, const pm_species* in, pm_species* out, int64_t* perm);
+
+/* Decompress to bin centres, in stream order (Sec. 2.4, used for restarts).
+ * in: PM_COMPRESSED; out: PM_FLOAT with out->n == in->n. */
+pm_status pm_decode(pm_ctx ctx, const pm_species* in, pm_species* out);
+
+/* CIC mass density rho(c) = Delta^-3 sum_s m_s sum_i W(x_i - x_c) of all species
+ * (Sec. 2.1 footnote: both species on the same mesh). rho: device float [n_mesh^3].
+ * Species must all be PM_FLOAT or all PM_COMPRESSED. Deterministic: contributions are
+ * summed in 64-bit fixed point. */
+pm_status pm_deposit(pm_ctx ctx, const pm_species* sp, int n_sp, float* rho);
+
+/* Accelerations a_a(c) from a density mesh, eqs. (2)-(3): a = IDFT(-i k G(k) DFT(rho))
+ * with the softened kernel G(k) = -4 pi G eps K1(k eps)/k, G(0) = 0, eps =
+ * soft_cells/n_mesh, and k_a = 0 on the Nyquist index. acc: device float
+ * [3][n_mesh^3]; rho may alias acc (component x). a_max (device float, nullable)
+ * receives max |a_a(c)| over the mesh. rho is not preserved when it aliases acc. */
+pm_status pm_force(pm_ctx ctx, const float* rho, float* acc, float* a_max);
+
+/* Interpolate acc to the particles (CIC), kick v' = v + c_kick a, drift
+ * x' = x + c_drift v' (mod 1). PM_FLOAT: in and out may be the same arrays.
+ * PM_COMPRESSED: in and out must be distinct; positions drift in fixed point
+ * (u' = u + floor(v' c_drift 256 n_cell + 1/2)), velocities are re-binned with
+ * v_max' = the smallest power of two >= max|v_decoded| + |c_kick| a_max, and the
+ * stream is re-sorted stably into cell order. a_max: device float from pm_force
+ * (required for PM_COMPRESSED). */
+pm_status pm_kick_drift(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp,
+                        const float* acc, const float* a_max, double c_kick,
+                        double c_drift);
+
+/* pm_kick_drift that also reports, per species, the re-sort of compressed streams:
+ * perm[s] (device int64 [n], nullable) receives for each new stream position the
+ * old stream position of that particle (identity for PM_FLOAT). The format stores no
+ * particle identities (Sec. 2.4); this map is what carries cotangents and test
+ * comparisons across the re-sort. perm is a host array of n_sp device pointers. */
+pm_status pm_kick_drift_perm(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp,
+                             const float* acc, const float* a_max, double c_kick,
+                             double c_drift, int64_t* const* perm);
+
+/* One full step (deposit, force, kick-drift) with c_kick = c_drift = dt, using the
+ * context's own mesh buffers. Same layout rules as pm_kick_drift. */
+pm_status pm_step(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp, double dt);
+
+/* Adjoint of pm_step at state `in` (straight-through for the quantisation of
+ * compressed states). lam_x1, lam_v1: per species device float [n][3] cotangents of
+ * the step's outputs, in the output's particle order; lam_x0, lam_v0: results, in
+ * the input's particle order. Arrays are passed as arrays of n_sp device pointers
+ * (host arrays of pointers). */
+pm_status pm_step_vjp(pm_ctx ctx, const pm_species* in, int n_sp, double dt,
+                      float* const* lam_x1, float* const* lam_v1, float* const* lam_x0,
+                      float* const* lam_v0);
+
+/* Density loss L = sum_c (rho(c) - rho_t(c))^2 of the species' CIC density against a
+ * target mesh (device float [n_mesh^3]); loss (device double, nullable) and
+ * dL/dx per species (host array of n_sp device float [n][3] pointers). */
+pm_status pm_loss_density_vjp(pm_ctx ctx, const pm_species* sp, int n_sp,
+                              const float* rho_target, double* loss,
+                              float* const* lam_x);
+
+/* Float64 global reductions (on the GPU): out[0] = sum_c rho(c) Delta^3 (rho may be
+ * NULL, then 0), out[1] = sum_i m_i, out[2..4] = sum_i m_i v_i, out[5..7] = 0.
+ * out: device double[8]. Compressed species use decoded velocities. */
+pm_status pm_reduce(pm_ctx ctx, const pm_species* sp, int n_sp, const float* rho,
+                    double* out);
+
+/* Byte stream of one compressed species (Sec. 2.4 layout): a 64-byte header
+ * {"PMC1", version 1, species_id, brick, N, n_cell, v_max, 0, mass, checksum,
+ * body length}, then for every cell its count byte (255 + uint32 count when >= 255)
+ * followed by its particles' 9-byte records (x, y, z bytes; vx, vy, vz little-endian
+ * uint16). The checksum is sum_i (2 i + 1) b_i mod 2^64 over the body bytes.
+ * buf: device uint8 [cap]; used: device int64 (bytes written). */
+pm_status pm_pack(pm_ctx ctx, const pm_species* sp, int32_t species_id, uint8_t* buf,
+                  int64_t cap, int64_t* used);
+/* Exact stream length of a compressed species (host value; synchronises). */
+pm_status pm_pack_size(pm_ctx ctx, const pm_species* sp, int64_t* bytes);
+
+/* Parse and verify a byte stream held in HOST memory into a compressed species
+ * (synchronous). Checks magic, version, brick and n_cell against the context, body
+ * length, checksum, and that the counts sum to N == out->n; returns PM_ERR_CORRUPT
+ * otherwise. The species mass and id from the header are returned via the pointers
+ * (nullable). */
+pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species* out,
+                    double* mass, int32_t* species_id);
+
+/* Diagnostics: copy the float32 kernel table G(|n|^2)/n_mesh^3 (device float
+ * [3 (n_mesh/2)^2 + 1], indexed by the integer |n|^2). */
+pm_status pm_kernel_table(pm_ctx ctx, float* out, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

@@ -1,0 +1,437 @@
+// The C ABI of libpm (include/pm.h): argument checks, context and scratch management,
+// and the order of the kernel launches of each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pm_common.h"
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2_i(int64_t v) {
+  int r = 0;
+  while ((int64_t)1 << (r + 1) <= v) ++r;
+  return r;
+}
+
+pm_status check_species(const pm_context* c, const pm_species* s, bool need_float_ptrs) {
+  if (!s) return PM_ERR_ARG;
+  if (s->n < 0 || s->n >= ((int64_t)1 << 32) - 1) return PM_ERR_ARG;
+  if (!(s->mass >= 0.0) || !std::isfinite(s->mass)) return PM_ERR_ARG;
+  if (s->layout == PM_FLOAT) {
+    if (s->n > 0 && need_float_ptrs && (!s->x || !s->v)) return PM_ERR_ARG;
+    return PM_OK;
+  }
+  if (s->layout == PM_COMPRESSED) {
+    if (!s->count || !s->hdr) return PM_ERR_ARG;
+    if (s->n > 0 && (!s->pos || !s->vel)) return PM_ERR_ARG;
+    if (s->cap_esc < 0 || (s->cap_esc > 0 && !s->esc)) return PM_ERR_ARG;
+    return PM_OK;
+  }
+  return PM_ERR_ARG;
+}
+
+pm_status ensure_step_meshes(pm_context* c) {
+  if (c->mesh) return PM_OK;
+  const int64_t n3 = c->g.ng * c->g.ng * c->g.ng;
+  if (hipMalloc(&c->mesh, (size_t)3 * n3 * sizeof(float)) != hipSuccess) {
+    c->mesh = nullptr;
+    return PM_ERR_NOMEM;
+  }
+  return PM_OK;
+}
+
+}  // namespace
+
+void* scratch(pm_context* c, int id, size_t bytes) {
+  DevBuf& b = c->scratch[id];
+  if (bytes == 0) bytes = 1;
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    hipStreamSynchronize(c->stream);  // the old buffer may still be in use
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;  // headroom against repeated growth
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    return nullptr;
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+// pm_kick.hip
+pm_status run_kick_compressed_off(pm_context* c, const pm_species* in, pm_species* out,
+                                  const int64_t* off_in, const float* acc, const float* amax,
+                                  double ck, double cd, int64_t* perm);
+int deposit_tile_cells(const Geom& g);
+
+extern "C" {
+
+const char* pm_status_str(pm_status s) {
+  switch (s) {
+    case PM_OK: return "ok";
+    case PM_ERR_ARG: return "invalid argument";
+    case PM_ERR_SHAPE: return "unsupported mesh or cell size";
+    case PM_ERR_NOMEM: return "device allocation failed";
+    case PM_ERR_DEVICE: return "HIP call failed";
+    case PM_ERR_CAPACITY: return "output capacity exceeded";
+    case PM_ERR_CORRUPT: return "corrupt or inconsistent compressed data";
+    case PM_ERR_RANGE: return "value out of range";
+  }
+  return "unknown status";
+}
+
+pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out) {
+  if (!cfg || !out) return PM_ERR_ARG;
+  *out = nullptr;
+  const int64_t ng = cfg->n_mesh, nc = cfg->n_cell, B = cfg->brick;
+  if (!is_pow2(ng) || ng < 8 || ng > 2048) return PM_ERR_SHAPE;
+  if (!is_pow2(nc) || nc > 1024 || nc > ng || ng / nc > 16) return PM_ERR_SHAPE;
+  if (!is_pow2(B) || B > 8 || B > nc) return PM_ERR_SHAPE;
+  if (!(cfg->soft_cells >= 0.0) || !std::isfinite(cfg->soft_cells)) return PM_ERR_ARG;
+  if (!std::isfinite(cfg->G)) return PM_ERR_ARG;
+  if (cfg->flags != 0) return PM_ERR_ARG;
+  pm_context* c = new (std::nothrow) pm_context();
+  if (!c) return PM_ERR_NOMEM;
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return PM_ERR_DEVICE;
+  }
+  Geom& g = c->g;
+  g.ng = ng;
+  g.nc = nc;
+  g.B = (int32_t)B;
+  g.r = (int32_t)(ng / nc);
+  g.lgB = ilog2_i(B);
+  g.lgnb = ilog2_i(nc / B);
+  g.ncell3 = nc * nc * nc;
+  g.nbrick = (nc / B) * (nc / B) * (nc / B);
+  g.S = 256 * nc;
+  pm_status s = PM_OK;
+  if (hipMalloc(&c->err, sizeof(DevErr)) != hipSuccess ||
+      hipMalloc(&c->amax, 64) != hipSuccess ||
+      hipMalloc(&c->nyq, (size_t)3 * ng * ng * sizeof(float2)) != hipSuccess) {
+    s = PM_ERR_NOMEM;
+  }
+  if (s == PM_OK && hipMemsetAsync(c->err, 0, sizeof(DevErr), c->stream) != hipSuccess)
+    s = PM_ERR_DEVICE;
+  if (s == PM_OK) s = build_kernel_table(c);
+  if (s == PM_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = PM_ERR_DEVICE;
+  if (s != PM_OK) {
+    pm_destroy(c);
+    return s;
+  }
+  *out = c;
+  return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx c) {
+  if (!c) return PM_ERR_ARG;
+  hipStreamSynchronize(c->stream);
+  hipFree(c->ktab);
+  hipFree(c->tw);
+  hipFree(c->mesh);
+  hipFree(c->nyq);
+  hipFree(c->err);
+  hipFree(c->amax);
+  for (auto& b : c->scratch)
+    if (b.p) hipFree(b.p);
+  delete c;
+  return PM_OK;
+}
+
+pm_status pm_sync(pm_ctx c) {
+  if (!c) return PM_ERR_ARG;
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  DevErr e{};
+  PM_HIP_CHECK(hipMemcpy(&e, c->err, sizeof(DevErr), hipMemcpyDeviceToHost));
+  if (e.bits == 0) return PM_OK;
+  c->last_detail = e.detail;
+  DevErr z{};
+  PM_HIP_CHECK(hipMemcpy(c->err, &z, sizeof(DevErr), hipMemcpyHostToDevice));
+  if (e.bits & ERRBIT_CAPACITY) return PM_ERR_CAPACITY;
+  if (e.bits & ERRBIT_CORRUPT) return PM_ERR_CORRUPT;
+  if (e.bits & ERRBIT_RANGE) return PM_ERR_RANGE;
+  return PM_ERR_ARG;
+}
+
+pm_status pm_last_error_detail(pm_ctx c, int64_t* needed) {
+  if (!c || !needed) return PM_ERR_ARG;
+  *needed = c->last_detail;
+  return PM_OK;
+}
+
+pm_status pm_encode(pm_ctx c, const pm_species* in, pm_species* out, int64_t* perm) {
+  if (!c || !in || !out) return PM_ERR_ARG;
+  pm_status s;
+  if ((s = check_species(c, in, true)) != PM_OK || in->layout != PM_FLOAT) return PM_ERR_ARG;
+  if ((s = check_species(c, out, false)) != PM_OK || out->layout != PM_COMPRESSED)
+    return PM_ERR_ARG;
+  if (out->n != in->n) return PM_ERR_ARG;
+  return run_encode(c, in, out, perm);
+}
+
+pm_status pm_decode(pm_ctx c, const pm_species* in, pm_species* out) {
+  if (!c || !in || !out) return PM_ERR_ARG;
+  if (check_species(c, in, false) != PM_OK || in->layout != PM_COMPRESSED) return PM_ERR_ARG;
+  if (check_species(c, out, true) != PM_OK || out->layout != PM_FLOAT) return PM_ERR_ARG;
+  if (out->n != in->n) return PM_ERR_ARG;
+  return run_decode(c, in, out);
+}
+
+pm_status pm_deposit(pm_ctx c, const pm_species* sp, int n_sp, float* rho) {
+  if (!c || !sp || !rho || n_sp <= 0 || n_sp > 4) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i)
+    if (check_species(c, &sp[i], true) != PM_OK) return PM_ERR_ARG;
+  return run_deposit(c, sp, n_sp, rho);
+}
+
+pm_status pm_force(pm_ctx c, const float* rho, float* acc, float* a_max) {
+  if (!c || !rho || !acc) return PM_ERR_ARG;
+  const int64_t n3 = c->g.ng * c->g.ng * c->g.ng;
+  // rho may alias the x component only
+  if (rho != acc && rho + n3 > acc && rho < acc + 3 * n3) return PM_ERR_ARG;
+  return run_force(c, rho, acc, c->nyq, a_max ? a_max : c->amax);
+}
+
+static pm_status kick_all(pm_context* c, const pm_species* in, pm_species* out, int n_sp,
+                          const float* acc, const float* a_max, double ck, double cd,
+                          int64_t* const* offs, int64_t* const* perm = nullptr) {
+  for (int i = 0; i < n_sp; ++i) {
+    pm_status s;
+    if (in[i].layout == PM_FLOAT) {
+      s = run_kick_float(c, &in[i], &out[i], acc, ck, cd);
+      if (s == PM_OK && perm && perm[i]) s = run_iota(c, perm[i], in[i].n);
+    } else {
+      int64_t* off = offs ? offs[i] : nullptr;
+      if (!off) {
+        off = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+        if (!off) return PM_ERR_NOMEM;
+        if ((s = run_cell_offsets(c, &in[i], off)) != PM_OK) return s;
+      }
+      s = run_kick_compressed_off(c, &in[i], &out[i], off, acc, a_max, ck, cd,
+                                  perm ? perm[i] : nullptr);
+    }
+    if (s != PM_OK) return s;
+  }
+  return PM_OK;
+}
+
+static pm_status check_kick_args(pm_context* c, const pm_species* in, pm_species* out,
+                                 int n_sp) {
+  if (!in || !out || n_sp <= 0 || n_sp > 4) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i) {
+    if (check_species(c, &in[i], true) != PM_OK) return PM_ERR_ARG;
+    if (check_species(c, &out[i], true) != PM_OK) return PM_ERR_ARG;
+    if (in[i].layout != out[i].layout || in[i].n != out[i].n) return PM_ERR_ARG;
+    if (in[i].layout != in[0].layout) return PM_ERR_ARG;
+    if (in[i].layout == PM_COMPRESSED &&
+        (in[i].pos == out[i].pos || in[i].vel == out[i].vel || in[i].count == out[i].count ||
+         in[i].hdr == out[i].hdr))
+      return PM_ERR_ARG;
+  }
+  return PM_OK;
+}
+
+pm_status pm_kick_drift(pm_ctx c, const pm_species* in, pm_species* out, int n_sp,
+                        const float* acc, const float* a_max, double c_kick, double c_drift) {
+  if (!c || !acc) return PM_ERR_ARG;
+  pm_status s = check_kick_args(c, in, out, n_sp);
+  if (s != PM_OK) return s;
+  if (!std::isfinite(c_kick) || !std::isfinite(c_drift)) return PM_ERR_ARG;
+  if (in[0].layout == PM_COMPRESSED && !a_max) return PM_ERR_ARG;
+  return kick_all(c, in, out, n_sp, acc, a_max, c_kick, c_drift, nullptr);
+}
+
+pm_status pm_kick_drift_perm(pm_ctx c, const pm_species* in, pm_species* out, int n_sp,
+                             const float* acc, const float* a_max, double c_kick,
+                             double c_drift, int64_t* const* perm) {
+  if (!c || !acc || !perm) return PM_ERR_ARG;
+  pm_status s = check_kick_args(c, in, out, n_sp);
+  if (s != PM_OK) return s;
+  if (!std::isfinite(c_kick) || !std::isfinite(c_drift)) return PM_ERR_ARG;
+  if (in[0].layout == PM_COMPRESSED && !a_max) return PM_ERR_ARG;
+  return kick_all(c, in, out, n_sp, acc, a_max, c_kick, c_drift, nullptr, perm);
+}
+
+pm_status pm_step(pm_ctx c, const pm_species* in, pm_species* out, int n_sp, double dt) {
+  if (!c) return PM_ERR_ARG;
+  pm_status s = check_kick_args(c, in, out, n_sp);
+  if (s != PM_OK) return s;
+  if (!std::isfinite(dt)) return PM_ERR_ARG;
+  if ((s = ensure_step_meshes(c)) != PM_OK) return s;
+  float* mesh = c->mesh;
+  if (in[0].layout == PM_COMPRESSED) {
+    int64_t* offs[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int i = 0; i < n_sp; ++i) {
+      offs[i] = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+      if (!offs[i]) return PM_ERR_NOMEM;
+      if ((s = run_cell_offsets(c, &in[i], offs[i])) != PM_OK) return s;
+    }
+    if ((s = run_deposit_tile(c, in, n_sp, offs, mesh)) != PM_OK) return s;
+    if ((s = run_force(c, mesh, mesh, c->nyq, c->amax)) != PM_OK) return s;
+    return kick_all(c, in, out, n_sp, mesh, c->amax, dt, dt, offs);
+  }
+  if ((s = run_deposit(c, in, n_sp, mesh)) != PM_OK) return s;
+  if ((s = run_force(c, mesh, mesh, c->nyq, c->amax)) != PM_OK) return s;
+  return kick_all(c, in, out, n_sp, mesh, c->amax, dt, dt, nullptr);
+}
+
+pm_status pm_step_vjp(pm_ctx c, const pm_species* in, int n_sp, double dt,
+                      float* const* lam_x1, float* const* lam_v1, float* const* lam_x0,
+                      float* const* lam_v0) {
+  if (!c || !in || n_sp <= 0 || n_sp > 4 || !lam_x1 || !lam_v1 || !lam_x0 || !lam_v0)
+    return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i) {
+    if (check_species(c, &in[i], true) != PM_OK || in[i].layout != in[0].layout)
+      return PM_ERR_ARG;
+    if (in[i].n > 0 && (!lam_x1[i] || !lam_v1[i] || !lam_x0[i] || !lam_v0[i]))
+      return PM_ERR_ARG;
+  }
+  if (!std::isfinite(dt)) return PM_ERR_ARG;
+  pm_status s = ensure_step_meshes(c);
+  if (s != PM_OK) return s;
+  return run_step_vjp(c, in, n_sp, dt, lam_x1, lam_v1, lam_x0, lam_v0);
+}
+
+pm_status pm_loss_density_vjp(pm_ctx c, const pm_species* sp, int n_sp, const float* rho_t,
+                              double* loss, float* const* lam_x) {
+  if (!c || !sp || n_sp <= 0 || n_sp > 4 || !rho_t || !lam_x) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i) {
+    if (check_species(c, &sp[i], true) != PM_OK || sp[i].layout != sp[0].layout)
+      return PM_ERR_ARG;
+    if (sp[i].n > 0 && !lam_x[i]) return PM_ERR_ARG;
+  }
+  pm_status s = ensure_step_meshes(c);
+  if (s != PM_OK) return s;
+  return run_loss_vjp(c, sp, n_sp, rho_t, loss, lam_x);
+}
+
+pm_status pm_reduce(pm_ctx c, const pm_species* sp, int n_sp, const float* rho, double* out) {
+  if (!c || !out || n_sp < 0 || n_sp > 4 || (n_sp > 0 && !sp)) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i)
+    if (check_species(c, &sp[i], true) != PM_OK) return PM_ERR_ARG;
+  return run_reduce(c, sp, n_sp, rho, out);
+}
+
+pm_status pm_pack(pm_ctx c, const pm_species* sp, int32_t species_id, uint8_t* buf,
+                  int64_t cap, int64_t* used) {
+  if (!c || !sp || !buf || !used || cap < 64) return PM_ERR_ARG;
+  if (check_species(c, sp, false) != PM_OK || sp->layout != PM_COMPRESSED) return PM_ERR_ARG;
+  return run_pack(c, sp, species_id, buf, cap, used);
+}
+
+pm_status pm_pack_size(pm_ctx c, const pm_species* sp, int64_t* bytes) {
+  if (!c || !sp || !bytes) return PM_ERR_ARG;
+  if (check_species(c, sp, false) != PM_OK || sp->layout != PM_COMPRESSED) return PM_ERR_ARG;
+  pm_shdr h;
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  PM_HIP_CHECK(hipMemcpy(&h, sp->hdr, sizeof(h), hipMemcpyDeviceToHost));
+  *bytes = 64 + 9 * sp->n + c->g.ncell3 + 4 * h.n_esc;
+  return PM_OK;
+}
+
+pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, double* mass,
+                    int32_t* species_id) {
+  if (!c || !buf || !out || len < 0) return PM_ERR_ARG;
+  if (check_species(c, out, false) != PM_OK || out->layout != PM_COMPRESSED) return PM_ERR_ARG;
+  if (len < 64) return PM_ERR_CORRUPT;
+  uint32_t ver, sid, brick;
+  uint64_t n, nc, csum, blen;
+  float vmax;
+  double m;
+  if (std::memcmp(buf, "PMC1", 4) != 0) return PM_ERR_CORRUPT;
+  std::memcpy(&ver, buf + 4, 4);
+  std::memcpy(&sid, buf + 8, 4);
+  std::memcpy(&brick, buf + 12, 4);
+  std::memcpy(&n, buf + 16, 8);
+  std::memcpy(&nc, buf + 24, 8);
+  std::memcpy(&vmax, buf + 32, 4);
+  std::memcpy(&m, buf + 40, 8);
+  std::memcpy(&csum, buf + 48, 8);
+  std::memcpy(&blen, buf + 56, 8);
+  if (ver != 1 || brick != (uint32_t)c->g.B || nc != (uint64_t)c->g.nc) return PM_ERR_CORRUPT;
+  if (blen != (uint64_t)(len - 64) || n != (uint64_t)out->n) return PM_ERR_CORRUPT;
+  if (!(vmax >= 0.f) || !std::isfinite(vmax)) return PM_ERR_CORRUPT;
+  const uint8_t* body = buf + 64;
+  uint64_t cs = 0;
+  for (uint64_t i = 0; i < blen; ++i) cs += (2ull * i + 1ull) * body[i];
+  if (cs != csum) return PM_ERR_CORRUPT;
+  const int64_t ncell = c->g.ncell3;
+  std::vector<uint8_t> count((size_t)ncell);
+  std::vector<uint64_t> esc;
+  std::vector<uint8_t> pos((size_t)n * 3);
+  std::vector<uint16_t> vel((size_t)n * 3);
+  uint64_t off = 0, p = 0;
+  int32_t jmin = 65536, jmax = -1;
+  for (int64_t cc = 0; cc < ncell; ++cc) {
+    if (off >= blen) return PM_ERR_CORRUPT;
+    uint64_t k = body[off++];
+    if (k == 255) {
+      if (off + 4 > blen) return PM_ERR_CORRUPT;
+      uint32_t kk;
+      std::memcpy(&kk, body + off, 4);
+      off += 4;
+      if (kk < 255) return PM_ERR_CORRUPT;
+      k = kk;
+      esc.push_back((uint64_t)cc);
+      esc.push_back(k);
+    }
+    count[(size_t)cc] = (uint8_t)(k >= 255 ? 255 : k);
+    if (p + k > n || off + 9 * k > blen) return PM_ERR_CORRUPT;
+    for (uint64_t q = 0; q < k; ++q, ++p, off += 9) {
+      const uint8_t* r = body + off;
+      pos[3 * p] = r[0];
+      pos[3 * p + 1] = r[1];
+      pos[3 * p + 2] = r[2];
+      for (int a = 0; a < 3; ++a) {
+        uint16_t w = (uint16_t)(r[3 + 2 * a] | (r[4 + 2 * a] << 8));
+        vel[3 * p + a] = w;
+        jmin = w < jmin ? w : jmin;
+        jmax = w > jmax ? w : jmax;
+      }
+    }
+  }
+  if (p != n || off != blen) return PM_ERR_CORRUPT;
+  const int64_t n_esc = (int64_t)esc.size() / 2;
+  if (n_esc > out->cap_esc) {
+    c->last_detail = n_esc;
+    return PM_ERR_CAPACITY;
+  }
+  pm_shdr h{};
+  h.v_max = vmax;
+  h.j_min = jmin;
+  h.j_max = jmax;
+  h.n_esc = n_esc;
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  PM_HIP_CHECK(hipMemcpy(out->count, count.data(), (size_t)ncell, hipMemcpyHostToDevice));
+  if (n > 0) {
+    PM_HIP_CHECK(hipMemcpy(out->pos, pos.data(), pos.size(), hipMemcpyHostToDevice));
+    PM_HIP_CHECK(hipMemcpy(out->vel, vel.data(), vel.size() * 2, hipMemcpyHostToDevice));
+  }
+  if (n_esc > 0)
+    PM_HIP_CHECK(hipMemcpy(out->esc, esc.data(), esc.size() * 8, hipMemcpyHostToDevice));
+  PM_HIP_CHECK(hipMemcpy(out->hdr, &h, sizeof(h), hipMemcpyHostToDevice));
+  if (mass) *mass = m;
+  if (species_id) *species_id = (int32_t)sid;
+  return PM_OK;
+}
+
+pm_status pm_kernel_table(pm_ctx c, float* out, int64_t cap) {
+  if (!c || !out || cap < c->ktab_n) return PM_ERR_ARG;
+  PM_HIP_CHECK(hipMemcpyAsync(out, c->ktab, (size_t)c->ktab_n * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream));
+  return PM_OK;
+}
+
+}  // extern "C"

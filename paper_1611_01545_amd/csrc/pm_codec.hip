@@ -1,0 +1,463 @@
+// The compressed phase-space format of Sec. 2.4 on the GPU: encode from float
+// particles, decode to bin centres, per-cell offsets of a compressed stream, the
+// count/escape table, the byte stream and the float64 global reductions.
+#include <cstring>
+
+#include "pm_codec.h"
+#include "pm_scan.h"
+
+using namespace pmscan;
+
+namespace {
+
+constexpr int T256 = 256;
+
+__global__ void k_init_hdr(pm_shdr* h) {
+  h->v_max = 0.f;
+  h->j_min = 65536;
+  h->j_max = -1;
+  h->flags = 0;
+  h->n_esc = 0;
+  h->reserved = 0;
+}
+
+// v_max of a species: largest |v_a| (bit pattern of a non-negative float orders
+// like an unsigned integer).
+__global__ __launch_bounds__(T256) void k_absmax(const float* v, int64_t n3, pm_shdr* h,
+                                                DevErr* err) {
+  float m = 0.f;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * T256) {
+    float a = fabsf(v[i]);
+    if (!(a <= 3.0e38f)) bad = true;
+    else m = fmaxf(m, a);
+  }
+  for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax((unsigned int*)&h->v_max, __float_as_uint(m));
+  if (bad) latch_error(err, ERRBIT_RANGE);
+}
+
+__global__ __launch_bounds__(T256) void k_encode_keys(const float* x, int64_t n, Geom g,
+                                                     uint32_t* keys, uint32_t* vals,
+                                                     DevErr* err) {
+  int64_t p = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (p >= n) return;
+  uint32_t u[3];
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ok &= pos_code(x[3 * p + a], g.S, u[a]);
+  if (!ok) latch_error(err, ERRBIT_RANGE);
+  keys[p] = cell_key(g, u[0] >> 8, u[1] >> 8, u[2] >> 8);
+  vals[p] = (uint32_t)p;
+}
+
+__device__ inline void wave_minmax_to_hdr(int jmin, int jmax, pm_shdr* h) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    jmin = min(jmin, __shfl_xor(jmin, d, 64));
+    jmax = max(jmax, __shfl_xor(jmax, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (jmin < 65536) atomicMin(&h->j_min, jmin);
+    if (jmax >= 0) atomicMax(&h->j_max, jmax);
+  }
+}
+
+__global__ __launch_bounds__(T256) void k_encode_gather(
+    const float* x, const float* v, int64_t n, Geom g, const uint32_t* keys_sorted,
+    const uint32_t* idx_sorted, uint8_t* pos, uint16_t* vel, int64_t* perm,
+    uint32_t* count32, pm_shdr* h) {
+  int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  int jmin = 65536, jmax = -1;
+  if (j < n) {
+    uint32_t p = idx_sorted[j];
+    float vmax = h->v_max;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      uint32_t u;
+      pos_code(x[3 * (int64_t)p + a], g.S, u);
+      pos[3 * j + a] = (uint8_t)(u & 255u);
+      int c = vel_code(v[3 * (int64_t)p + a], vmax);
+      vel[3 * j + a] = (uint16_t)c;
+      jmin = min(jmin, c);
+      jmax = max(jmax, c);
+    }
+    if (perm) perm[j] = (int64_t)p;
+    atomicAdd(&count32[keys_sorted[j]], 1u);
+  }
+  wave_minmax_to_hdr(jmin, jmax, h);
+}
+
+// Full count -> u8 byte and escape flag (count >= 255).
+struct CountSrc {
+  const uint32_t* c32;
+  const uint64_t* c64;
+  __device__ uint32_t operator()(int64_t i) const {
+    return c32 ? c32[i] : (uint32_t)(c64[i] & 0xffffffffull);
+  }
+};
+
+__global__ __launch_bounds__(T256) void k_count_bytes(CountSrc src, int64_t ncell,
+                                                     uint8_t* count, uint32_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (i >= ncell) return;
+  uint32_t c = src(i);
+  count[i] = (uint8_t)(c >= 255u ? 255u : c);
+  flag[i] = c >= 255u ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(T256) void k_escapes(CountSrc src, int64_t ncell,
+                                                 const int64_t* foff, uint64_t* esc,
+                                                 int64_t cap, pm_shdr* h, DevErr* err) {
+  int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (i == 0) {
+    int64_t ne = foff[ncell];
+    h->n_esc = ne;
+    if (ne > cap) latch_error(err, ERRBIT_CAPACITY, ne);
+  }
+  if (i >= ncell) return;
+  uint32_t c = src(i);
+  if (c >= 255u) {
+    int64_t k = foff[i];
+    if (k < cap) {
+      esc[2 * k] = (uint64_t)i;
+      esc[2 * k + 1] = (uint64_t)c;
+    }
+  }
+}
+
+__global__ void k_check_total(const int64_t* off, int64_t ncell, int64_t n, DevErr* err) {
+  if (off[ncell] != n) latch_error(err, ERRBIT_CORRUPT);
+}
+
+__device__ inline int64_t find_cell(const int64_t* off, int64_t ncell, int64_t j) {
+  // largest c with off[c] <= j (cells with zero particles are skipped)
+  int64_t lo = 0, hi = ncell;  // off[lo] <= j < off[hi]
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= j) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(T256) void k_decode(const uint8_t* pos, const uint16_t* vel,
+                                                const pm_shdr* h, const int64_t* off,
+                                                int64_t n, Geom g, float* x, float* v) {
+  int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (j >= n) return;
+  uint32_t cell[3];
+  key_cell(g, (uint32_t)find_cell(off, g.ncell3, j), cell[0], cell[1], cell[2]);
+  float vmax = h->v_max;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uint32_t u = (cell[a] << 8) | pos[3 * j + a];
+    x[3 * j + a] = pos_decode(u, g.S);
+    v[3 * j + a] = vel_decode(vel[3 * j + a], vmax);
+  }
+}
+
+// ---------------------------------------------------------------- byte stream --
+struct GetPackBytes {
+  const int64_t* off;
+  __device__ int64_t operator()(int64_t c) const {
+    int64_t k = off[c + 1] - off[c];
+    return 1 + (k >= 255 ? 4 : 0) + 9 * k;
+  }
+};
+
+__global__ __launch_bounds__(T256) void k_pack_cells(const int64_t* off, const int64_t* boff,
+                                                    int64_t ncell, uint8_t* body,
+                                                    int64_t cap_body, uint64_t* csum) {
+  int64_t c = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  uint64_t s = 0;
+  if (c < ncell && boff[ncell] <= cap_body) {
+    int64_t k = off[c + 1] - off[c];
+    int64_t o = boff[c];
+    if (k >= 255) {
+      uint8_t b[5] = {255, (uint8_t)(k & 255), (uint8_t)((k >> 8) & 255),
+                      (uint8_t)((k >> 16) & 255), (uint8_t)((k >> 24) & 255)};
+      for (int q = 0; q < 5; ++q) {
+        body[o + q] = b[q];
+        s += (2ull * (uint64_t)(o + q) + 1ull) * b[q];
+      }
+    } else {
+      body[o] = (uint8_t)k;
+      s += (2ull * (uint64_t)o + 1ull) * (uint64_t)k;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)csum, (unsigned long long)s);
+}
+
+__global__ __launch_bounds__(T256) void k_pack_records(const uint8_t* pos, const uint16_t* vel,
+                                                      const int64_t* off, const int64_t* boff,
+                                                      int64_t n, int64_t ncell, uint8_t* body,
+                                                      int64_t cap_body, uint64_t* csum) {
+  int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  uint64_t s = 0;
+  if (j < n && boff[ncell] <= cap_body) {
+    int64_t c = find_cell(off, ncell, j);
+    int64_t k = off[c + 1] - off[c];
+    int64_t o = boff[c] + (k >= 255 ? 5 : 1) + 9 * (j - off[c]);
+    if (o + 9 > boff[ncell]) return;  // counts inconsistent with n (latched elsewhere)
+    uint8_t b[9];
+    b[0] = pos[3 * j];
+    b[1] = pos[3 * j + 1];
+    b[2] = pos[3 * j + 2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      uint16_t w = vel[3 * j + a];
+      b[3 + 2 * a] = (uint8_t)(w & 255);
+      b[4 + 2 * a] = (uint8_t)(w >> 8);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      body[o + q] = b[q];
+      s += (2ull * (uint64_t)(o + q) + 1ull) * b[q];
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)csum, (unsigned long long)s);
+}
+
+__global__ void k_pack_header(uint8_t* buf, int64_t cap, const int64_t* boff, int64_t ncell,
+                              const uint64_t* csum, const pm_shdr* h, int32_t sid, int32_t B,
+                              int64_t n, int64_t nc, double mass, int64_t* used,
+                              DevErr* err) {
+  int64_t body = boff[ncell];
+  int64_t total = PM_STREAM_HEADER + body;
+  *used = total;
+  if (total > cap) {
+    latch_error(err, ERRBIT_CAPACITY, total);
+    return;
+  }
+  uint8_t hb[PM_STREAM_HEADER];
+  for (int i = 0; i < PM_STREAM_HEADER; ++i) hb[i] = 0;
+  auto put = [&](int o, const void* p, int len) {
+    const uint8_t* q = (const uint8_t*)p;
+    for (int i = 0; i < len; ++i) hb[o + i] = q[i];
+  };
+  const char magic[4] = {'P', 'M', 'C', '1'};
+  uint32_t ver = 1, usid = (uint32_t)sid, ub = (uint32_t)B, zero = 0;
+  uint64_t un = (uint64_t)n, unc = (uint64_t)nc, cs = *csum, ubl = (uint64_t)body;
+  float vmax = h->v_max;
+  put(0, magic, 4);
+  put(4, &ver, 4);
+  put(8, &usid, 4);
+  put(12, &ub, 4);
+  put(16, &un, 8);
+  put(24, &unc, 8);
+  put(32, &vmax, 4);
+  put(36, &zero, 4);
+  put(40, &mass, 8);
+  put(48, &cs, 8);
+  put(56, &ubl, 8);
+  for (int i = 0; i < PM_STREAM_HEADER; ++i) buf[i] = hb[i];
+}
+
+// ------------------------------------------------------------------ reductions --
+constexpr int RED_BLOCKS = 512;
+
+__global__ __launch_bounds__(T256) void k_reduce_mesh(const float* rho, int64_t n,
+                                                     double* part) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * T256)
+    s += (double)rho[i];
+  __shared__ double lw[T256 / 64];
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0) lw[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = lw[0] + lw[1] + lw[2] + lw[3];
+}
+
+__global__ __launch_bounds__(T256) void k_reduce_particles(pm_species sp, double* part) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x; j < sp.n;
+       j += (int64_t)gridDim.x * T256) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float vv = sp.layout == PM_FLOAT ? sp.v[3 * j + a]
+                                       : vel_decode(sp.vel[3 * j + a], sp.hdr->v_max);
+      s[a] += (double)vv;
+    }
+  }
+  __shared__ double lw[3][T256 / 64];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    for (int d = 32; d >= 1; d >>= 1) s[a] += __shfl_xor(s[a], d, 64);
+    if ((threadIdx.x & 63) == 0) lw[a][threadIdx.x >> 6] = s[a];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    int a = threadIdx.x;
+    part[3 * blockIdx.x + a] = lw[a][0] + lw[a][1] + lw[a][2] + lw[a][3];
+  }
+}
+
+__global__ void k_reduce_final(const double* pmesh, int nmesh_part, double cell_vol,
+                               const double* ppart, int n_sp, const double* masses,
+                               const int64_t* counts, double* out) {
+  // fixed-order final sums (deterministic)
+  double m = 0.0;
+  for (int i = 0; i < nmesh_part; ++i) m += pmesh[i];
+  out[0] = m * cell_vol;
+  double mt = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+  for (int s = 0; s < n_sp; ++s) {
+    mt += masses[s] * (double)counts[s];
+    double sx = 0, sy = 0, sz = 0;
+    for (int b = 0; b < RED_BLOCKS; ++b) {
+      const double* q = ppart + 3 * (int64_t)(s * RED_BLOCKS + b);
+      sx += q[0];
+      sy += q[1];
+      sz += q[2];
+    }
+    px += masses[s] * sx;
+    py += masses[s] * sy;
+    pz += masses[s] * sz;
+  }
+  out[1] = mt;
+  out[2] = px;
+  out[3] = py;
+  out[4] = pz;
+  out[5] = out[6] = out[7] = 0.0;
+}
+
+}  // namespace
+
+pm_status run_cell_offsets(pm_context* c, const pm_species* sp, int64_t* off) {
+  pm_status s = scan_counts(c, sp->count, sp->esc, sp->hdr, c->g.ncell3, off);
+  if (s != PM_OK) return s;
+  hipLaunchKernelGGL(k_check_total, dim3(1), dim3(1), 0, c->stream, off, c->g.ncell3, sp->n,
+                     c->err);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status run_finalize_counts(pm_context* c, const uint32_t* cnt32, const uint64_t* cnt64,
+                              pm_species* out) {
+  const int64_t nc3 = c->g.ncell3;
+  uint32_t* flag = (uint32_t*)scratch(c, SC_FLAG, (size_t)nc3 * 4);
+  int64_t* foff = (int64_t*)scratch(c, SC_FOFF, (size_t)(nc3 + 1) * 8);
+  if (!flag || !foff) return PM_ERR_NOMEM;
+  CountSrc src{cnt32, cnt64};
+  unsigned nb = (unsigned)cdiv(nc3, T256);
+  hipLaunchKernelGGL(k_count_bytes, dim3(nb), dim3(T256), 0, c->stream, src, nc3, out->count,
+                     flag);
+  PM_LAUNCH_CHECK();
+  pm_status s = scan_u32(c, flag, nc3, foff);
+  if (s != PM_OK) return s;
+  hipLaunchKernelGGL(k_escapes, dim3(nb), dim3(T256), 0, c->stream, src, nc3, foff, out->esc,
+                     out->cap_esc, out->hdr, c->err);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64_t* perm) {
+  const int64_t n = in->n;
+  const Geom& g = c->g;
+  hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(1), 0, c->stream, out->hdr);
+  PM_LAUNCH_CHECK();
+  uint32_t* cnt32 = (uint32_t*)scratch(c, SC_COUNT32, (size_t)g.ncell3 * 4);
+  if (!cnt32) return PM_ERR_NOMEM;
+  pm_status s = launch_fill_u32(c, cnt32, g.ncell3, 0u);
+  if (s != PM_OK) return s;
+  if (n > 0) {
+    int64_t blocks = cdiv(3 * n, T256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(T256), 0, c->stream, in->v,
+                       3 * n, out->hdr, c->err);
+    uint32_t* ka = (uint32_t*)scratch(c, SC_KEYA, (size_t)n * 4);
+    uint32_t* va = (uint32_t*)scratch(c, SC_VALA, (size_t)n * 4);
+    uint32_t* kb = (uint32_t*)scratch(c, SC_KEYB, (size_t)n * 4);
+    uint32_t* vb = (uint32_t*)scratch(c, SC_VALB, (size_t)n * 4);
+    if (!ka || !va || !kb || !vb) return PM_ERR_NOMEM;
+    unsigned nbk = (unsigned)cdiv(n, T256);
+    hipLaunchKernelGGL(k_encode_keys, dim3(nbk), dim3(T256), 0, c->stream, in->x, n, g, ka,
+                       va, c->err);
+    PM_LAUNCH_CHECK();
+    int bits = 3 * (g.lgB + g.lgnb);
+    s = radix_sort_pairs(c, &ka, &va, &kb, &vb, n, bits);
+    if (s != PM_OK) return s;
+    hipLaunchKernelGGL(k_encode_gather, dim3(nbk), dim3(T256), 0, c->stream, in->x, in->v, n,
+                       g, ka, va, out->pos, out->vel, perm, cnt32, out->hdr);
+    PM_LAUNCH_CHECK();
+  }
+  return run_finalize_counts(c, cnt32, nullptr, out);
+}
+
+pm_status run_decode(pm_context* c, const pm_species* in, pm_species* out) {
+  const int64_t n = in->n;
+  int64_t* off = (int64_t*)scratch(c, SC_OFF, (size_t)(c->g.ncell3 + 1) * 8);
+  if (!off) return PM_ERR_NOMEM;
+  pm_status s = run_cell_offsets(c, in, off);
+  if (s != PM_OK || n == 0) return s;
+  hipLaunchKernelGGL(k_decode, dim3((unsigned)cdiv(n, T256)), dim3(T256), 0, c->stream,
+                     in->pos, in->vel, in->hdr, off, n, c->g, out->x, out->v);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status run_pack(pm_context* c, const pm_species* sp, int32_t sid, uint8_t* buf,
+                   int64_t cap, int64_t* used) {
+  const int64_t nc3 = c->g.ncell3;
+  int64_t* off = (int64_t*)scratch(c, SC_OFF, (size_t)(nc3 + 1) * 8);
+  int64_t* boff = (int64_t*)scratch(c, SC_FOFF, (size_t)(nc3 + 1) * 8);
+  uint64_t* csum = (uint64_t*)scratch(c, SC_MISC, 64);
+  if (!off || !boff || !csum) return PM_ERR_NOMEM;
+  pm_status s = run_cell_offsets(c, sp, off);
+  if (s != PM_OK) return s;
+  s = scan_generic_pack(c, off, nc3, boff);
+  if (s != PM_OK) return s;
+  s = launch_fill_u64(c, csum, 1, 0ull);
+  if (s != PM_OK) return s;
+  int64_t cap_body = cap - PM_STREAM_HEADER;
+  uint8_t* body = buf + PM_STREAM_HEADER;
+  hipLaunchKernelGGL(k_pack_cells, dim3((unsigned)cdiv(nc3, T256)), dim3(T256), 0, c->stream,
+                     off, boff, nc3, body, cap_body, csum);
+  if (sp->n > 0)
+    hipLaunchKernelGGL(k_pack_records, dim3((unsigned)cdiv(sp->n, T256)), dim3(T256), 0,
+                       c->stream, sp->pos, sp->vel, off, boff, sp->n, nc3, body, cap_body,
+                       csum);
+  hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, c->stream, buf, cap, boff, nc3, csum,
+                     sp->hdr, sid, c->g.B, sp->n, c->g.nc, sp->mass, used, c->err);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_t* out) {
+  return scan_generic(c, GetPackBytes{off}, n, out);
+}
+
+pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
+                     double* out) {
+  if (n_sp < 0 || n_sp > 8) return PM_ERR_ARG;
+  double* part = (double*)scratch(c, SC_MISC, (size_t)(RED_BLOCKS * (3 * 8 + 1) + 32) * 8);
+  if (!part) return PM_ERR_NOMEM;
+  double* pmesh = part;
+  double* ppart = part + RED_BLOCKS;
+  double* meta = ppart + 3 * 8 * RED_BLOCKS;  // masses[8], counts[8] (as bits)
+  double hm[16];
+  for (int s = 0; s < 8; ++s) {
+    hm[s] = s < n_sp ? sp[s].mass : 0.0;
+    int64_t cnt = s < n_sp ? sp[s].n : 0;
+    std::memcpy(&hm[8 + s], &cnt, 8);
+  }
+  PM_HIP_CHECK(hipMemcpyAsync(meta, hm, sizeof(hm), hipMemcpyHostToDevice, c->stream));
+  int nmp = 0;
+  if (rho) {
+    nmp = RED_BLOCKS;
+    hipLaunchKernelGGL(k_reduce_mesh, dim3(RED_BLOCKS), dim3(T256), 0, c->stream, rho,
+                       c->g.ng * c->g.ng * c->g.ng, pmesh);
+  }
+  for (int s = 0; s < n_sp; ++s)
+    hipLaunchKernelGGL(k_reduce_particles, dim3(RED_BLOCKS), dim3(T256), 0, c->stream, sp[s],
+                       ppart + 3 * (int64_t)s * RED_BLOCKS);
+  double dv = 1.0 / ((double)c->g.ng * c->g.ng * c->g.ng);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1), 0, c->stream, pmesh, nmp, dv, ppart,
+                     n_sp, meta, (const int64_t*)(meta + 8), out);
+  PM_LAUNCH_CHECK();
+  // the host staging array must outlive the async copy
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return PM_OK;
+}

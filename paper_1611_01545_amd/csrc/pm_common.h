@@ -1,0 +1,186 @@
+// Internal declarations shared by the HIP translation units of libpm.
+// Not part of the public ABI (see include/pm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pm.h"
+
+// ---------------------------------------------------------------- error latch --
+// Device-side errors are OR-ed into a context word and returned by pm_sync().
+enum : int32_t {
+  ERRBIT_CAPACITY = 1,
+  ERRBIT_CORRUPT = 2,
+  ERRBIT_RANGE = 4,
+  ERRBIT_ARG = 8,
+};
+
+struct DevErr {
+  int32_t bits;
+  int32_t pad;
+  int64_t detail;  // e.g. capacity needed
+};
+
+__device__ inline void latch_error(DevErr* e, int32_t bit, int64_t detail = 0) {
+  atomicOr(&e->bits, bit);
+  if (detail) atomicMax((unsigned long long*)&e->detail, (unsigned long long)detail);
+}
+
+// ----------------------------------------------------------------- geometry --
+// Cell keys: bricks of B^3 cells in x-fastest order, cells x-fastest inside a brick.
+struct Geom {
+  int64_t ng;      // mesh side
+  int64_t nc;      // compression-cell side
+  int32_t B;       // brick side (cells)
+  int32_t r;       // ng / nc
+  int32_t lgB;     // log2(B)
+  int32_t lgnb;    // log2(nc / B)
+  int64_t ncell3;  // nc^3
+  int64_t nbrick;  // (nc/B)^3
+  int64_t S;       // 256 nc (position codes per box side)
+};
+
+__host__ __device__ inline uint32_t cell_key(const Geom& g, uint32_t cx, uint32_t cy,
+                                             uint32_t cz) {
+  uint32_t m = (uint32_t)g.B - 1;
+  uint32_t bx = cx >> g.lgB, by = cy >> g.lgB, bz = cz >> g.lgB;
+  uint32_t b = (((bz << g.lgnb) + by) << g.lgnb) + bx;
+  uint32_t l = ((((cz & m) << g.lgB) + (cy & m)) << g.lgB) + (cx & m);
+  return (b << (3 * g.lgB)) + l;
+}
+
+__host__ __device__ inline void key_cell(const Geom& g, uint32_t key, uint32_t& cx,
+                                         uint32_t& cy, uint32_t& cz) {
+  uint32_t m = (uint32_t)g.B - 1;
+  uint32_t b = key >> (3 * g.lgB), l = key & ((1u << (3 * g.lgB)) - 1);
+  uint32_t nbm = (1u << g.lgnb) - 1;
+  cx = ((b & nbm) << g.lgB) + (l & m);
+  cy = (((b >> g.lgnb) & nbm) << g.lgB) + ((l >> g.lgB) & m);
+  cz = ((b >> (2 * g.lgnb)) << g.lgB) + (l >> (2 * g.lgB));
+}
+
+// --------------------------------------------------------------- scratch pool --
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct pm_context {
+  pm_config cfg;
+  hipStream_t stream;
+  int device;
+  Geom g;
+  // gravity kernel table G(|n|^2)/n^3 (float) and twiddles exp(-2 pi i k/n), k<n
+  float* ktab = nullptr;
+  int64_t ktab_n = 0;
+  float2* tw = nullptr;
+  // owned meshes for pm_step: 3 x ng^3 floats + 3 Nyquist planes (complex ng^2)
+  float* mesh = nullptr;
+  float2* nyq = nullptr;
+  DevErr* err = nullptr;
+  float* amax = nullptr;  // device scalar
+  // grow-on-demand scratch
+  DevBuf scratch[32];
+  int64_t last_detail = 0;
+};
+
+enum ScratchId {
+  SC_OFF = 0,      // int64 [ncell3+1] cell offsets (species A)
+  SC_OFF2,         // int64 [ncell3+1] new cell offsets
+  SC_CNT,          // uint64 [ncell3] counts (stay | arrivals-before << 32)
+  SC_BSUM,         // int64 block sums for scans
+  SC_KEYA,         // uint32 [N]
+  SC_VALA,         // uint32 [N]
+  SC_KEYB,         // uint32 [N]
+  SC_VALB,         // uint32 [N]
+  SC_HIST,         // uint32 radix histograms
+  SC_HOFF,         // int64 radix offsets
+  SC_TPOS,         // uint8 [N][3]
+  SC_TVEL,         // uint16 [N][3]
+  SC_TDST,         // uint32 [N]
+  SC_MCNT,         // uint32 [nbrick] movers per brick
+  SC_MOFF,         // int64 [nbrick+1]
+  SC_ACC64,        // uint64 [ng^3] fixed-point accumulator (float layout deposit)
+  SC_FLAG,         // uint32 [ncell3] escape flags / misc
+  SC_FOFF,         // int64 [ncell3+1] flag offsets
+  SC_MISC,         // small
+  SC_VJP,          // float scratch for the adjoint
+  SC_VJP2,
+  SC_COUNT32,      // uint32 [ncell3]
+  SC_SPOFF0,       // int64 [ncell3+1] cell offsets of species 0..3
+  SC_SPOFF1,
+  SC_SPOFF2,
+  SC_SPOFF3,
+  SC_N
+};
+
+void* scratch(pm_context* c, int id, size_t bytes);  // grows; nullptr on failure
+
+#define PM_HIP_CHECK(expr)                         \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return PM_ERR_DEVICE;    \
+  } while (0)
+
+#define PM_LAUNCH_CHECK()                          \
+  do {                                             \
+    hipError_t _e = hipGetLastError();             \
+    if (_e != hipSuccess) return PM_ERR_DEVICE;    \
+  } while (0)
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ launch wrappers --
+// scan / sort / fill (pm_scan.hip)
+pm_status launch_fill_u32(pm_context* c, uint32_t* p, int64_t n, uint32_t v);
+pm_status launch_fill_u64(pm_context* c, uint64_t* p, int64_t n, uint64_t v);
+pm_status run_iota(pm_context* c, int64_t* p, int64_t n);  // p[i] = i
+// exclusive scans into int64 out[n+1]
+pm_status scan_u32(pm_context* c, const uint32_t* in, int64_t n, int64_t* out);
+pm_status scan_u64lo(pm_context* c, const uint64_t* in, int64_t n, int64_t* out);
+pm_status scan_counts(pm_context* c, const uint8_t* count, const uint64_t* esc,
+                      const pm_shdr* hdr, int64_t n, int64_t* out);
+// stable LSD radix sort of (key, val) pairs on the low `bits` of key; results land in
+// *keys/*vals (which may be swapped with the alternate buffers).
+pm_status radix_sort_pairs(pm_context* c, uint32_t** keys, uint32_t** vals,
+                           uint32_t** keys_alt, uint32_t** vals_alt, int64_t n,
+                           int bits);
+
+// codec (pm_codec.hip)
+pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64_t* perm);
+pm_status run_decode(pm_context* c, const pm_species* in, pm_species* out);
+pm_status run_cell_offsets(pm_context* c, const pm_species* sp, int64_t* off);
+pm_status run_finalize_counts(pm_context* c, const uint32_t* cnt32, const uint64_t* cnt64,
+                              pm_species* out);
+pm_status run_pack(pm_context* c, const pm_species* sp, int32_t sid, uint8_t* buf,
+                   int64_t cap, int64_t* used);
+pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
+                     double* out);
+
+// deposit (pm_deposit.hip)
+pm_status run_deposit(pm_context* c, const pm_species* sp, int n_sp, float* rho);
+pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
+                           int64_t* const* offs, float* rho);
+
+// FFT (pm_fft.hip)
+pm_status build_kernel_table(pm_context* c);
+pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq,
+                    float* amax);
+// adjoint transform: nu = sum_a IDFT(+i k_a G DFT(mu_a)); mu in acc[3] (destroyed),
+// result written to acc component 0.
+pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq);
+
+// kick-drift (pm_kick.hip)
+pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
+                         const float* acc, double ck, double cd);
+pm_status run_kick_compressed(pm_context* c, const pm_species* in, pm_species* out,
+                              const float* acc, const float* amax, double ck, double cd,
+                              uint32_t* perm_new_to_old);
+
+// adjoint (pm_adjoint.hip)
+pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
+                       float* const* lx1, float* const* lv1, float* const* lx0,
+                       float* const* lv0);
+pm_status run_loss_vjp(pm_context* c, const pm_species* sp, int n_sp, const float* rho_t,
+                       double* loss, float* const* lam_x);

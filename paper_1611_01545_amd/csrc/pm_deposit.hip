@@ -1,0 +1,253 @@
+// Cloud-in-cell mass deposit (Sec. 2.1; CIC is named in Sec. 2.3), both species on
+// one mesh (Sec. 2.1 footnote).
+//
+// Compressed particles are cell-sorted, so a workgroup owns a cube of R^3 mesh nodes
+// (R = T r, T compression cells of r mesh cells each) and gathers exactly the
+// particles that can reach those nodes: its own T^3 cells plus the one-cell shell
+// on the -x/-y/-z faces, whose particles reach the tile's lowest node plane through
+// their upper CIC corner. Every node has exactly one owner, so the tile is written
+// with plain stores and no mesh-wide atomics or halo pass are needed. The paper's
+// CPU code avoids write races with a strided loop over cells (Sec. 2.3); here the
+// races inside the tile are resolved by LDS atomics.
+//
+// Weights are exact: a compressed position sits at the bin centre (2u+1)/(512 n_c),
+// i.e. at (2u+1) r / 512 mesh cells, so each axis weight is an integer multiple of
+// 1/512 and their product an integer multiple of 2^-27. Contributions are summed as
+// 64-bit fixed point (units of m_max 2^-32), which makes the deposit independent of
+// the order of the atomics: every run, and the recomputation in the adjoint, gives
+// bit-identical densities.
+#include "pm_codec.h"
+#include "pm_scan.h"
+
+namespace {
+
+constexpr int DEP_THREADS = 256;
+constexpr int MAX_SP = 4;
+
+struct DepSpecies {
+  int64_t n;           // particles (bounds guard against inconsistent counts)
+  const uint8_t* pos;
+  const int64_t* off;  // [ncell3 + 1]
+  double scale;        // 32 m_s / m_max: fixed-point units per exact 2^-27 weight
+};
+struct DepArgs {
+  DepSpecies sp[MAX_SP];
+  int n_sp;
+  int T;   // tile side in cells
+  int r;   // mesh cells per compression cell
+  int R;   // tile side in nodes
+  double unit;  // density per fixed-point unit: m_max 2^-32 n_g^3
+};
+
+__device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+__global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g, float* rho) {
+  extern __shared__ unsigned char smem[];
+  const int T = A.T, R = A.R, r = A.r;
+  const int E = T + 1;              // extended cells per side
+  const int NE = E * E * E;
+  const int R3 = R * R * R;
+  __shared__ int64_t lw[DEP_THREADS / 64 + 1];
+  unsigned long long* acc = (unsigned long long*)smem;
+  int* pre = (int*)(acc + R3);      // [NE + 1] particle prefix over extended cells
+  const int nt = (int)(g.nc / T);
+  const int tx = blockIdx.x % nt, ty = (blockIdx.x / nt) % nt, tz = blockIdx.x / (nt * nt);
+  const int ncs = (int)g.nc;
+
+  for (int i = threadIdx.x; i < R3; i += DEP_THREADS) acc[i] = 0ull;
+
+  for (int s = 0; s < A.n_sp; ++s) {
+    const DepSpecies sp = A.sp[s];
+    // counts of the extended cells, then an exclusive prefix (single pass per wave)
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += DEP_THREADS) {
+      int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+      int cx = wrapc(tx * T + ex - 1, ncs), cy = wrapc(ty * T + ey - 1, ncs),
+          cz = wrapc(tz * T + ez - 1, ncs);
+      uint32_t key = cell_key(g, cx, cy, cz);
+      pre[e + 1] = (int)(sp.off[key + 1] - sp.off[key]);
+    }
+    __syncthreads();
+    {
+      // block-wide inclusive prefix of pre[1..NE]: each thread owns K consecutive
+      const int K = (NE + DEP_THREADS - 1) / DEP_THREADS;
+      const int e0 = 1 + threadIdx.x * K;
+      int loc = 0;
+      for (int k = 0; k < K; ++k)
+        if (e0 + k <= NE) loc += pre[e0 + k];
+      int base = (int)pmscan::block_excl_scan(loc, lw, nullptr);
+      for (int k = 0; k < K; ++k)
+        if (e0 + k <= NE) {
+          base += pre[e0 + k];
+          pre[e0 + k] = base;
+        }
+      if (threadIdx.x == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    const int P = pre[NE];
+    for (int q = threadIdx.x; q < P; q += DEP_THREADS) {
+      // extended cell of flat particle q: largest e with pre[e] <= q
+      int lo = 0, hi = NE;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= q) lo = mid; else hi = mid;
+      }
+      const int e = lo;
+      const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+      const int cx = wrapc(tx * T + ex - 1, ncs), cy = wrapc(ty * T + ey - 1, ncs),
+                cz = wrapc(tz * T + ez - 1, ncs);
+      const uint32_t key = cell_key(g, cx, cy, cz);
+      const int64_t j = sp.off[key] + (q - pre[e]);
+      if (j >= sp.n) continue;  // counts inconsistent with n (latched by the offset check)
+      int li[3], f[3];
+      const int le[3] = {ex - 1, ey - 1, ez - 1};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        int gl = (2 * (int)sp.pos[3 * j + a] + 1) * r;  // position inside the cell, 1/512 mesh cell
+        li[a] = le[a] * r + (gl >> 9);
+        f[a] = gl & 511;
+      }
+#pragma unroll
+      for (int dz = 0; dz < 2; ++dz) {
+        int nz = li[2] + dz;
+        int wz = dz ? f[2] : 512 - f[2];
+        if (nz < 0 || nz >= R || wz == 0) continue;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          int ny = li[1] + dy;
+          int wy = dy ? f[1] : 512 - f[1];
+          if (ny < 0 || ny >= R || wy == 0) continue;
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            int nx = li[0] + dx;
+            int wx = dx ? f[0] : 512 - f[0];
+            if (nx < 0 || nx >= R || wx == 0) continue;
+            int64_t W = (int64_t)wx * wy * wz;  // exact, units of 2^-27
+            unsigned long long qv = (unsigned long long)__double2ll_rn((double)W * sp.scale);
+            atomicAdd(&acc[(nz * R + ny) * R + nx], qv);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t ng = g.ng;
+  for (int i = threadIdx.x; i < R3; i += DEP_THREADS) {
+    int lx = i % R, ly = (i / R) % R, lz = i / (R * R);
+    int64_t gx = (int64_t)tx * R + lx, gy = (int64_t)ty * R + ly, gz = (int64_t)tz * R + lz;
+    rho[(gz * ng + gy) * ng + gx] = (float)((double)acc[i] * A.unit);
+  }
+}
+
+// ---------------------------------------------------------- float-layout path --
+// Unsorted float particles: fixed-point weights accumulated with 64-bit global atomics
+// (still order independent), then converted.
+__global__ __launch_bounds__(256) void k_deposit_float(const float* x, int64_t n, int64_t ng,
+                                                      double scale,
+                                                      unsigned long long* acc) {
+  int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  int64_t i[3];
+  double f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double u = (double)x[3 * p + a] * (double)ng;  // exact (ng a power of two)
+    double fl = floor(u);
+    f[a] = u - fl;
+    int64_t k = (int64_t)fl % ng;
+    i[a] = k < 0 ? k + ng : k;
+  }
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+        unsigned long long q = (unsigned long long)__double2ll_rn(w * scale);
+        if (!q) continue;
+        int64_t nz = (i[2] + dz) % ng, ny = (i[1] + dy) % ng, nx = (i[0] + dx) % ng;
+        atomicAdd(&acc[(nz * ng + ny) * ng + nx], q);
+      }
+}
+
+__global__ __launch_bounds__(256) void k_fixed_to_float(const unsigned long long* acc, int64_t n,
+                                                       double unit, float* rho) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) rho[i] = (float)((double)acc[i] * unit);
+}
+
+}  // namespace
+
+int deposit_tile_cells(const Geom& g) {
+  int T = 16 / g.r;
+  if (T < 1) T = 1;
+  if (T > g.nc) T = (int)g.nc;
+  return T;
+}
+
+pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
+                           int64_t* const* offs, float* rho) {
+  const Geom& g = c->g;
+  if (n_sp > MAX_SP) return PM_ERR_ARG;
+  double mmax = 0.0;
+  for (int s = 0; s < n_sp; ++s) mmax = fmax(mmax, sp[s].mass);
+  DepArgs A{};
+  A.n_sp = 0;
+  for (int s = 0; s < n_sp; ++s) {
+    if (sp[s].n == 0 || sp[s].mass == 0.0) continue;
+    A.sp[A.n_sp].n = sp[s].n;
+    A.sp[A.n_sp].pos = sp[s].pos;
+    A.sp[A.n_sp].off = offs[s];
+    A.sp[A.n_sp].scale = 32.0 * (sp[s].mass / mmax);
+    A.n_sp++;
+  }
+  A.r = g.r;
+  A.T = deposit_tile_cells(g);
+  A.R = A.T * g.r;
+  double ng3 = (double)g.ng * g.ng * g.ng;
+  A.unit = mmax > 0 ? mmax * 0x1p-32 * ng3 : 0.0;
+  int nt = (int)(g.nc / A.T);
+  size_t lds = (size_t)A.R * A.R * A.R * 8 + ((size_t)(A.T + 1) * (A.T + 1) * (A.T + 1) + 1) * 4;
+  hipLaunchKernelGGL(k_deposit_tile, dim3((unsigned)((int64_t)nt * nt * nt)), dim3(DEP_THREADS),
+                     lds, c->stream, A, g, rho);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status run_deposit(pm_context* c, const pm_species* sp, int n_sp, float* rho) {
+  const Geom& g = c->g;
+  if (n_sp <= 0 || n_sp > MAX_SP) return PM_ERR_ARG;
+  int layout = sp[0].layout;
+  for (int s = 1; s < n_sp; ++s)
+    if (sp[s].layout != layout) return PM_ERR_ARG;
+  if (layout == PM_COMPRESSED) {
+    int64_t* offs[MAX_SP];
+    for (int s = 0; s < n_sp; ++s) {
+      offs[s] = (int64_t*)scratch(c, SC_SPOFF0 + s, (size_t)(g.ncell3 + 1) * 8);
+      if (!offs[s]) return PM_ERR_NOMEM;
+      pm_status st = run_cell_offsets(c, &sp[s], offs[s]);
+      if (st != PM_OK) return st;
+    }
+    return run_deposit_tile(c, sp, n_sp, offs, rho);
+  }
+  // float layout
+  const int64_t n3 = g.ng * g.ng * g.ng;
+  unsigned long long* acc = (unsigned long long*)scratch(c, SC_ACC64, (size_t)n3 * 8);
+  if (!acc) return PM_ERR_NOMEM;
+  pm_status st = launch_fill_u64(c, (uint64_t*)acc, n3, 0ull);
+  if (st != PM_OK) return st;
+  double mmax = 0.0;
+  for (int s = 0; s < n_sp; ++s) mmax = fmax(mmax, sp[s].mass);
+  for (int s = 0; s < n_sp; ++s) {
+    if (sp[s].n == 0 || sp[s].mass == 0.0) continue;
+    double scale = 0x1p32 * (sp[s].mass / mmax);
+    hipLaunchKernelGGL(k_deposit_float, dim3((unsigned)cdiv(sp[s].n, 256)), dim3(256), 0,
+                       c->stream, sp[s].x, sp[s].n, g.ng, scale, acc);
+  }
+  double unit = mmax > 0 ? mmax * 0x1p-32 * (double)n3 : 0.0;
+  hipLaunchKernelGGL(k_fixed_to_float, dim3((unsigned)cdiv(n3, 256)), dim3(256), 0, c->stream,
+                     acc, n3, unit, rho);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}

@@ -1,0 +1,744 @@
+// FFT solution of the Poisson equation (Sec. 2.1, eqs. (1)-(3)) on a periodic mesh.
+//
+// The paper transforms each tile with three threaded 1-D FFTW calls, one per
+// dimension (Sec. 2.3). Here every axis pass is one HBM pass over the mesh, and the
+// passes are fused so that the four transforms of a step (one forward, three
+// inverse) cost 5 sweeps instead of 12:
+//   X  r2c      rho(x) -> rho~(kx)                     rows, in place, Nyquist column
+//                                                      kx = n/2 kept in a side plane
+//   Y  fwd      -> rho~(kx, ky)                        columns, in place
+//   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table), inverse
+//               z FFT twice: T1 = IFFT_z(G rho~), T2 = IFFT_z(-i k_z G rho~)
+//   Y  inv      U1 = IFFT_y(T1), U2 = IFFT_y(-i k_y T1), U3 = IFFT_y(T2)
+//   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
+//               max |a| for the velocity bound of the re-encode
+// The gradient factor -i k_a follows eq. (3) and is zero on the Nyquist index; the
+// 1/n^3 of the inverse transform is folded into the kernel table.
+//
+// A line of N points is transformed as N = T x E (four-step): each of T threads holds
+// E points strided by T, does an E-point DFT in registers, multiplies by twiddles,
+// exchanges through LDS, and finishes with T-point DFTs in registers. Column passes
+// give each workgroup W adjacent columns so that every global access is a W x 8 byte
+// run; row passes give each workgroup several whole rows.
+#include <type_traits>
+
+#include "pm_common.h"
+
+namespace {
+
+// ------------------------------------------------------ compile-time twiddles --
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double y) {
+  double term = y, s = y;
+  for (int i = 1; i < 30; ++i) {
+    term *= -y * y / ((2.0 * i) * (2.0 * i + 1.0));
+    s += term;
+  }
+  return s;
+}
+constexpr double taylor_cos(double y) {
+  double term = 1.0, s = 1.0;
+  for (int i = 1; i < 30; ++i) {
+    term *= -y * y / ((2.0 * i - 1.0) * (2.0 * i));
+    s += term;
+  }
+  return s;
+}
+// cos and sin of the angle 2 pi k / m, exact at multiples of pi/2.
+constexpr double turn_cos(long k, long m) {
+  k %= m;
+  if (k < 0) k += m;
+  long q = (4 * k) / m, rem = 4 * k - q * m;
+  double y = (kPi / 2) * (double)rem / (double)m;
+  double s = taylor_sin(y), c = taylor_cos(y);
+  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+constexpr double turn_sin(long k, long m) {
+  k %= m;
+  if (k < 0) k += m;
+  long q = (4 * k) / m, rem = 4 * k - q * m;
+  double y = (kPi / 2) * (double)rem / (double)m;
+  double s = taylor_sin(y), c = taylor_cos(y);
+  return q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+template <int I, int N>
+struct SFor {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&& f) {
+    if constexpr (I < N) {
+      f(std::integral_constant<int, I>{});
+      SFor<I + 1, N>::run(f);
+    }
+  }
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// In-register DFT of M points (natural order in and out); SIGN = -1 forward,
+// +1 inverse (unnormalised). Radix-2 decimation in frequency, twiddles are
+// compile-time constants.
+template <int M, int SIGN>
+__device__ __forceinline__ void dft_reg(float2* a) {
+  if constexpr (M > 1) {
+    constexpr int L = ilog2(M);
+    SFor<0, L>::run([&](auto s_) {
+      constexpr int s = decltype(s_)::value;
+      constexpr int len = M >> s, half = len >> 1;
+      SFor<0, M / 2>::run([&](auto b_) {
+        constexpr int b = decltype(b_)::value;
+        constexpr int blk = b / half, j = b % half;
+        constexpr int i0 = blk * len + j, i1 = i0 + half;
+        float2 u = a[i0], w = a[i1];
+        a[i0] = make_float2(u.x + w.x, u.y + w.y);
+        float dx = u.x - w.x, dy = u.y - w.y;
+        if constexpr (j == 0) {
+          a[i1] = make_float2(dx, dy);
+        } else {
+          constexpr float wr = (float)turn_cos(j, len);
+          constexpr float wi = (float)(SIGN * turn_sin(j, len));
+          a[i1] = make_float2(dx * wr - dy * wi, dx * wi + dy * wr);
+        }
+      });
+    });
+    float2 t[M];
+    SFor<0, M>::run([&](auto i_) {
+      constexpr int i = decltype(i_)::value;
+      t[i] = a[bitrev(i, L)];
+    });
+    SFor<0, M>::run([&](auto i_) {
+      constexpr int i = decltype(i_)::value;
+      a[i] = t[i];
+    });
+  }
+}
+
+template <int N>
+struct Plan {
+  static constexpr int LG = ilog2(N);
+  static constexpr int T = 1 << (LG / 2);  // threads per line
+  static constexpr int E = N / T;          // points per thread in the natural layout
+  static constexpr int V = E / T;          // virtual threads per thread (1 or 2)
+  static constexpr int TP = T + 1;         // padded LDS row
+};
+
+// LDS exchange buffer accessor for one line: element (k1, t) at base + k1*TP + t.
+// Natural layout: thread t holds a[n1] = x[t + T n1], n1 < E.
+// Transposed layout: thread t holds b[v*T + k2] = X[(t + T v) + E k2], v < V, k2 < T.
+//
+// nat_to_tr: N-point DFT (SIGN) of a line held in natural layout, result in transposed
+// layout. tw: table exp(-2 pi i j / n) with stride `tws` = n / N.
+template <int N, int SIGN>
+__device__ __forceinline__ void nat_to_tr(float2 (&a)[Plan<N>::E], int t, float* lds,
+                                          const float2* __restrict__ tw, int tws,
+                                          int twmask) {
+  using P = Plan<N>;
+  dft_reg<P::E, SIGN>(a);
+#pragma unroll
+  for (int k1 = 1; k1 < P::E; ++k1) {
+    float2 w = tw[((t * k1) * tws) & twmask];
+    a[k1] = (SIGN < 0) ? cmul(a[k1], w) : cmulc(a[k1], w);
+  }
+  // exchange real parts, then imaginary parts (halves the LDS footprint)
+  float2 b[P::E];
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int k1 = 0; k1 < P::E; ++k1) lds[k1 * P::TP + t] = part ? a[k1].y : a[k1].x;
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        float q = lds[(t + P::T * v) * P::TP + k2];
+        if (part) b[v * P::T + k2].y = q; else b[v * P::T + k2].x = q;
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < P::V; ++v) dft_reg<P::T, SIGN>(&b[v * P::T]);
+#pragma unroll
+  for (int i = 0; i < P::E; ++i) a[i] = b[i];
+}
+
+// tr_to_nat: N-point DFT (SIGN) of a line held in transposed layout, result in natural
+// layout.
+template <int N, int SIGN>
+__device__ __forceinline__ void tr_to_nat(float2 (&b)[Plan<N>::E], int t, float* lds,
+                                          const float2* __restrict__ tw, int tws,
+                                          int twmask) {
+  using P = Plan<N>;
+#pragma unroll
+  for (int v = 0; v < P::V; ++v) {
+    dft_reg<P::T, SIGN>(&b[v * P::T]);
+    const int k1 = t + P::T * v;
+#pragma unroll
+    for (int n1 = 1; n1 < P::T; ++n1) {
+      float2 w = tw[((n1 * k1) * tws) & twmask];
+      b[v * P::T + n1] = (SIGN < 0) ? cmul(b[v * P::T + n1], w) : cmulc(b[v * P::T + n1], w);
+    }
+  }
+  float2 a[P::E];
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int n1 = 0; n1 < P::T; ++n1) {
+        float2 q = b[v * P::T + n1];
+        lds[(t + P::T * v) * P::TP + n1] = part ? q.y : q.x;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < P::E; ++k1) {
+      float q = lds[k1 * P::TP + t];
+      if (part) a[k1].y = q; else a[k1].x = q;
+    }
+    __syncthreads();
+  }
+  dft_reg<P::E, SIGN>(a);
+#pragma unroll
+  for (int i = 0; i < P::E; ++i) b[i] = a[i];
+}
+
+// ------------------------------------------------------------- column passes --
+// Lines l = (l1, l2): element e of line l at base + l1*s1 + l2*s2 + e*es (complex
+// units). A workgroup takes W consecutive l1 (s1 = 1 gives W*8-byte runs) and one l2.
+struct Lines {
+  int64_t s1, s2, es;
+  int64_t L1;      // number of l1 values
+  int kx_mode;     // 0: kx = l1; 1: kx = kx_fixed
+  int ky_mode;     // 0: ky = l2; 1: ky = l1
+  int kx_fixed;
+};
+
+template <int W>
+constexpr int col_cs(int per_col) {  // padded per-column stride, spreads LDS banks
+  int want = 32 / W;
+  int r = per_col % 32;
+  return per_col + ((want - r) % 32 + 32) % 32;
+}
+
+__device__ __forceinline__ int signed_k(int k, int n) { return k < n / 2 ? k : k - n; }
+// 2 pi k_a for the gradient, zero on the Nyquist index
+__device__ __forceinline__ float grad_k(int k, int n) {
+  return (k == n / 2) ? 0.f : 6.283185307179586f * (float)signed_k(k, n);
+}
+
+// Generic c2c column FFT: out0 = FFT_SIGN(in); if out1, out1 = FFT_SIGN(-i k(e) in)
+// where k(e) is the line's own wave number (used for -i k_y in the inverse y pass).
+template <int N, int W, int SIGN>
+__global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, float2* out0,
+                                                            float2* out1, Lines d,
+                                                            const float2* __restrict__ tw,
+                                                            int tws, int twmask, int n) {
+  using P = Plan<N>;
+  constexpr int CS = col_cs<W>(P::E * P::TP);
+  __shared__ float lds[W * CS];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int64_t l1 = (int64_t)blockIdx.x * W + c;
+  const bool ok = l1 < d.L1;
+  const int64_t base = l1 * d.s1 + (int64_t)blockIdx.y * d.s2;
+  float* my = lds + c * CS;
+  float2 a[P::E];
+#pragma unroll
+  for (int n1 = 0; n1 < P::E; ++n1)
+    a[n1] = ok ? in[base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
+  float2 g[P::E];
+  if (out1) {
+#pragma unroll
+    for (int n1 = 0; n1 < P::E; ++n1) {
+      float k = grad_k(t + P::T * n1, n);
+      g[n1] = make_float2(k * a[n1].y, -k * a[n1].x);  // -i k (x + i y) = k y - i k x
+    }
+  }
+  nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
+  if (ok) {
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2)
+        out0[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = a[v * P::T + k2];
+  }
+  if (out1) {  // uniform branch
+    nat_to_tr<N, SIGN>(g, t, my, tw, tws, twmask);
+    if (ok) {
+#pragma unroll
+      for (int v = 0; v < P::V; ++v)
+#pragma unroll
+        for (int k2 = 0; k2 < P::T; ++k2)
+          out1[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = g[v * P::T + k2];
+    }
+  }
+}
+
+// Fused z pass. MODE 0 (force): in0 -> out0 = IFFT(G F), out1 = IFFT(-i k_z G F) with
+// F = FFT(in0). MODE 1 (adjoint): out0 = IFFT(G sum_a (+i k_a) FFT(in_a)).
+template <int N, int W, int MODE>
+__global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
+    const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
+    Lines d, const float2* __restrict__ tw, int tws, int twmask, int n,
+    const float* __restrict__ ktab) {
+  using P = Plan<N>;
+  constexpr int CS = col_cs<W>(P::E * P::TP);
+  __shared__ float lds[W * CS];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int64_t l1 = (int64_t)blockIdx.x * W + c;
+  const bool ok = l1 < d.L1;
+  const int64_t base = l1 * d.s1 + (int64_t)blockIdx.y * d.s2;
+  float* my = lds + c * CS;
+  const int kx = d.kx_mode ? d.kx_fixed : (int)l1;
+  const int ky = d.ky_mode ? (int)l1 : (int)blockIdx.y;
+  const int sx = signed_k(kx, n), sy = signed_k(ky, n);
+  const int nxy2 = sx * sx + sy * sy;
+  float2 acc[P::E];
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int n1 = 0; n1 < P::E; ++n1)
+      acc[n1] = ok ? in0[base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
+    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+    float2 g[P::E];
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const int kz = (t + P::T * v) + P::E * k2;
+        const int sz = signed_k(kz, n);
+        const float G = ktab[nxy2 + sz * sz];
+        float2 f = acc[v * P::T + k2];
+        f = make_float2(G * f.x, G * f.y);
+        acc[v * P::T + k2] = f;
+        const float kk = grad_k(kz, n);
+        g[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
+      }
+    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
+    if (ok) {
+#pragma unroll
+      for (int n1 = 0; n1 < P::E; ++n1) out0[base + (int64_t)(t + P::T * n1) * d.es] = acc[n1];
+    }
+    tr_to_nat<N, +1>(g, t, my, tw, tws, twmask);
+    if (ok) {
+#pragma unroll
+      for (int n1 = 0; n1 < P::E; ++n1) out1[base + (int64_t)(t + P::T * n1) * d.es] = g[n1];
+    }
+  } else {
+    const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
+#pragma unroll
+    for (int i = 0; i < P::E; ++i) acc[i] = make_float2(0.f, 0.f);
+    const float2* ins[3] = {in0, in1, in2};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      float2 f[P::E];
+#pragma unroll
+      for (int n1 = 0; n1 < P::E; ++n1)
+        f[n1] = ok ? ins[ax][base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
+      nat_to_tr<N, -1>(f, t, my, tw, tws, twmask);
+#pragma unroll
+      for (int v = 0; v < P::V; ++v)
+#pragma unroll
+        for (int k2 = 0; k2 < P::T; ++k2) {
+          const int kz = (t + P::T * v) + P::E * k2;
+          const float k = ax == 0 ? kxg : ax == 1 ? kyg : grad_k(kz, n);
+          float2 q = f[v * P::T + k2];
+          // + i k (x + i y) = -k y + i k x
+          acc[v * P::T + k2].x += -k * q.y;
+          acc[v * P::T + k2].y += k * q.x;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const int kz = (t + P::T * v) + P::E * k2;
+        const int sz = signed_k(kz, n);
+        const float G = ktab[nxy2 + sz * sz];
+        acc[v * P::T + k2].x *= G;
+        acc[v * P::T + k2].y *= G;
+      }
+    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
+    if (ok) {
+#pragma unroll
+      for (int n1 = 0; n1 < P::E; ++n1) out0[base + (int64_t)(t + P::T * n1) * d.es] = acc[n1];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- row passes --
+// A real row of n = 2M floats is the complex row z[m] = x[2m] + i x[2m+1] of M points.
+// Workgroup: R rows x T threads, threads of a row consecutive (coalesced rows).
+template <int M>
+constexpr int row_lds_floats() {
+  using P = Plan<M>;
+  int ex = P::E * P::TP;    // exchange buffer (floats)
+  int st = 2 * (M + 1);     // complex staging of the row
+  return ex > st ? ex : st;
+}
+// rows per workgroup: up to 256 threads and about 80 KB of LDS (two groups per CU)
+template <int M>
+constexpr int rows_per_wg() {
+  constexpr int T = Plan<M>::T;
+  int r = 256 / T;
+  if (r > 16) r = 16;
+  int lim = 20480 / row_lds_floats<M>();
+  if (r > lim) r = lim;
+  return r < 1 ? 1 : r;
+}
+
+// X r2c: in real rows (nrows x n floats) -> out main rows (M complex) + nyq[row].
+template <int M>
+__global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
+    const float* in, float2* out, float2* nyq, int64_t nrows, const float2* __restrict__ tw,
+    int twmask) {
+  using P = Plan<M>;
+  constexpr int R = rows_per_wg<M>();
+  constexpr int LF = row_lds_floats<M>();
+  __shared__ float lds[R * LF];
+  const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
+  const int64_t row = (int64_t)blockIdx.x * R + rr;
+  const bool ok = row < nrows;
+  float* my = lds + rr * LF;
+  const float2* zin = (const float2*)(in + row * 2 * M);
+  float2 a[P::E];
+#pragma unroll
+  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = ok ? zin[t + P::T * n1] : make_float2(0.f, 0.f);
+  // M-point DFT: tw table is for n = 2M points, stride 2
+  nat_to_tr<M, -1>(a, t, my, tw, 2, twmask);
+  // stage Z in natural order
+  float2* zs = (float2*)my;
+#pragma unroll
+  for (int v = 0; v < P::V; ++v)
+#pragma unroll
+    for (int k2 = 0; k2 < P::T; ++k2) zs[(t + P::T * v) + P::E * k2] = a[v * P::T + k2];
+  __syncthreads();
+  float2* o = out + row * M;
+#pragma unroll
+  for (int j = 0; j < P::E; ++j) {
+    const int k = t + P::T * j;
+    float2 zk = zs[k];
+    float2 zm = zs[(M - k) & (M - 1)];  // Z[M - k], Z[M] = Z[0]
+    // A = (Z[k] + conj Z[M-k]) / 2, B = -i (Z[k] - conj Z[M-k]) / 2, X = A + W^k B
+    float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    float2 w = tw[k];
+    float2 wb = cmul(w, B);
+    float2 X = make_float2(A.x + wb.x, A.y + wb.y);
+    if (k == 0) X = make_float2(zk.x + zk.y, 0.f);
+    if (ok) o[k] = X;
+  }
+  if (ok && t == 0) nyq[row] = make_float2(zs[0].x - zs[0].y, 0.f);
+}
+
+// X c2r: in main rows (M complex) + nyq[row] -> out real rows; optional -i k_x factor;
+// max |out| into amax (float bits, non-negative).
+template <int M>
+__global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
+    const float2* in, const float2* nyq, float* out, int64_t nrows, int grad,
+    const float2* __restrict__ tw, int twmask, unsigned int* amax) {
+  using P = Plan<M>;
+  constexpr int R = rows_per_wg<M>();
+  constexpr int LF = row_lds_floats<M>();
+  __shared__ float lds[R * LF];
+  const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
+  const int64_t row = (int64_t)blockIdx.x * R + rr;
+  const bool ok = row < nrows;
+  float* my = lds + rr * LF;
+  float2* xs = (float2*)my;
+  const float2* xi = in + row * M;
+  const int n = 2 * M;
+#pragma unroll
+  for (int j = 0; j < P::E; ++j) {
+    const int k = t + P::T * j;
+    float2 X = ok ? xi[k] : make_float2(0.f, 0.f);
+    if (grad) {
+      float kk = grad_k(k, n);
+      X = make_float2(kk * X.y, -kk * X.x);
+    }
+    xs[k] = X;
+  }
+  if (t == 0) {
+    float2 X = ok ? nyq[row] : make_float2(0.f, 0.f);
+    xs[M] = grad ? make_float2(0.f, 0.f) : X;  // -i k_x is zero on the Nyquist index
+  }
+  __syncthreads();
+  float2 a[P::E];
+#pragma unroll
+  for (int n1 = 0; n1 < P::E; ++n1) {
+    const int k = t + P::T * n1;
+    float2 xk = xs[k], xm = xs[M - k];
+    // Z = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k])
+    float2 s = make_float2(xk.x + xm.x, xk.y - xm.y);
+    float2 dd = make_float2(xk.x - xm.x, xk.y + xm.y);
+    float2 wd = cmulc(dd, tw[k]);  // W^{-k} d
+    a[n1] = make_float2(s.x - wd.y, s.y + wd.x);
+  }
+  __syncthreads();
+  nat_to_tr<M, +1>(a, t, my, tw, 2, twmask);
+  float2* zo = (float2*)(out + row * 2 * M);
+  float m = 0.f;
+#pragma unroll
+  for (int v = 0; v < P::V; ++v)
+#pragma unroll
+    for (int k2 = 0; k2 < P::T; ++k2) {
+      float2 z = a[v * P::T + k2];
+      if (ok) zo[(t + P::T * v) + P::E * k2] = z;
+      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+    }
+  if (amax) {
+    for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+  }
+}
+
+// ---------------------------------------------------------------- kernel table --
+// K1(x) = int_0^inf exp(-x cosh s) cosh s ds by the trapezoidal rule, which converges
+// exponentially fast for this analytic, doubly-exponentially decaying integrand.
+__device__ double bessel_k1(double x) {
+  const double h = 0.0625;
+  double sum = 0.5 * exp(-x);
+  for (int j = 1; j < 20000; ++j) {
+    double s = j * h;
+    double ch = cosh(s);
+    double term = exp(-x * ch) * ch;
+    sum += term;
+    if (term < 1e-19 * sum) break;
+  }
+  return sum * h;
+}
+
+__global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, double eps) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nent) return;
+  double val = 0.0;
+  if (q > 0) {
+    double k = 2.0 * 3.141592653589793238462643 * sqrt((double)q);
+    double g;
+    if (eps > 0) g = -4.0 * 3.141592653589793238462643 * G * eps * bessel_k1(k * eps) / k;
+    else g = -4.0 * 3.141592653589793238462643 * G / (k * k);
+    val = g / ((double)n * (double)n * (double)n);
+  }
+  ktab[q] = (float)val;
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+// ------------------------------------------------------------------ dispatch --
+template <int N>
+constexpr int col_w() {
+  int w = 16384 / N;
+  if (w > 16) w = 16;
+  if (w < 1) w = 1;
+  return w;
+}
+
+struct FftCtx {
+  pm_context* c;
+  int n;
+  int twmask;
+};
+
+template <int N>
+pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, const Lines& d,
+                  int64_t L2, int sign) {
+  constexpr int W = col_w<N>();
+  dim3 grid((unsigned)cdiv(d.L1, W), (unsigned)L2);
+  dim3 block(W * Plan<N>::T);
+  if (sign < 0)
+    hipLaunchKernelGGL((k_col_fft<N, W, -1>), grid, block, 0, f.c->stream, in, o0, o1, d,
+                       f.c->tw, 1, f.twmask, f.n);
+  else
+    hipLaunchKernelGGL((k_col_fft<N, W, 1>), grid, block, 0, f.c->stream, in, o0, o1, d,
+                       f.c->tw, 1, f.twmask, f.n);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+template <int N>
+pm_status col_zconv(const FftCtx& f, int mode, const float2* i0, const float2* i1,
+                    const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
+  constexpr int W = col_w<N>();
+  dim3 grid((unsigned)cdiv(d.L1, W), (unsigned)L2);
+  dim3 block(W * Plan<N>::T);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_col_zconv<N, W, 0>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
+                       o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
+  else
+    hipLaunchKernelGGL((k_col_zconv<N, W, 1>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
+                       o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+template <int M>
+pm_status row_r2c(const FftCtx& f, const float* in, float2* out, float2* nyq) {
+  constexpr int R = rows_per_wg<M>();
+  int64_t nrows = (int64_t)f.n * f.n;
+  hipLaunchKernelGGL(k_row_r2c<M>, dim3((unsigned)cdiv(nrows, R)), dim3(R * Plan<M>::T), 0,
+                     f.c->stream, in, out, nyq, nrows, f.c->tw, f.twmask);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+template <int M>
+pm_status row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* out, int grad,
+                  unsigned int* amax) {
+  constexpr int R = rows_per_wg<M>();
+  int64_t nrows = (int64_t)f.n * f.n;
+  hipLaunchKernelGGL(k_row_c2r<M>, dim3((unsigned)cdiv(nrows, R)), dim3(R * Plan<M>::T), 0,
+                     f.c->stream, in, nyq, out, nrows, grad, f.c->tw, f.twmask, amax);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+// Size dispatch: the column length is n, the row length (complex) n/2.
+#define PM_FFT_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048)
+
+pm_status d_col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, const Lines& d,
+                    int64_t L2, int sign) {
+  switch (f.n) {
+#define CASE(N) \
+  case N: return col_fft<N>(f, in, o0, o1, d, L2, sign);
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return PM_ERR_SHAPE;
+}
+pm_status d_col_zconv(const FftCtx& f, int mode, const float2* i0, const float2* i1,
+                      const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
+  switch (f.n) {
+#define CASE(N) \
+  case N: return col_zconv<N>(f, mode, i0, i1, i2, o0, o1, d, L2);
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return PM_ERR_SHAPE;
+}
+pm_status d_row_r2c(const FftCtx& f, const float* in, float2* out, float2* nyq) {
+  switch (f.n) {
+#define CASE(N) \
+  case N: return row_r2c<N / 2>(f, in, out, nyq);
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return PM_ERR_SHAPE;
+}
+pm_status d_row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* out, int grad,
+                    unsigned int* amax) {
+  switch (f.n) {
+#define CASE(N) \
+  case N: return row_c2r<N / 2>(f, in, nyq, out, grad, amax);
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return PM_ERR_SHAPE;
+}
+
+// Line descriptors of the half-spectrum layout: main [z][y][kx < n/2] and the Nyquist
+// plane nyq[z][y] (kx = n/2).
+Lines lines_y_main(int n) {  // l1 = kx, l2 = z, element = y
+  int64_t M = n / 2;
+  return Lines{1, (int64_t)n * M, M, M, 0, 1, 0};
+}
+Lines lines_y_nyq(int n) {  // l1 = z, element = y
+  return Lines{n, 0, 1, n, 1, 1, n / 2};
+}
+Lines lines_z_main(int n) {  // l1 = kx, l2 = y, element = z
+  int64_t M = n / 2;
+  return Lines{1, M, (int64_t)n * M, M, 0, 0, 0};
+}
+Lines lines_z_nyq(int n) {  // l1 = y, element = z
+  return Lines{1, 0, n, n, 1, 1, n / 2};
+}
+
+}  // namespace
+
+pm_status build_kernel_table(pm_context* c) {
+  const int64_t n = c->g.ng;
+  c->ktab_n = 3 * (n / 2) * (n / 2) + 1;
+  PM_HIP_CHECK(hipMalloc(&c->ktab, (size_t)c->ktab_n * sizeof(float)));
+  double eps = c->cfg.soft_cells / (double)n;
+  hipLaunchKernelGGL(k_build_ktab, dim3((unsigned)cdiv(c->ktab_n, 256)), dim3(256), 0,
+                     c->stream, c->ktab, c->ktab_n, n, c->cfg.G, eps);
+  PM_LAUNCH_CHECK();
+  // twiddles exp(-2 pi i k / n), k < n, built in float64 on the host
+  float2* h = (float2*)malloc(sizeof(float2) * n);
+  if (!h) return PM_ERR_NOMEM;
+  for (int64_t k = 0; k < n; ++k) {
+    double a = -2.0 * 3.141592653589793238462643 * (double)k / (double)n;
+    h[k] = make_float2((float)cos(a), (float)sin(a));
+  }
+  hipError_t e = hipMalloc(&c->tw, sizeof(float2) * n);
+  if (e == hipSuccess) e = hipMemcpy(c->tw, h, sizeof(float2) * n, hipMemcpyHostToDevice);
+  free(h);
+  if (e != hipSuccess) return PM_ERR_DEVICE;
+  return PM_OK;
+}
+
+pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, float* amax) {
+  const int n = (int)c->g.ng;
+  const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  FftCtx f{c, n, n - 1};
+  float2* A0 = (float2*)acc;
+  float2* A1 = (float2*)(acc + n3);
+  float2* A2 = (float2*)(acc + 2 * n3);
+  float2 *N0 = nyq, *N1 = nyq + n2, *N2 = nyq + 2 * n2;
+  pm_status s;
+  if (amax) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, (unsigned int*)amax);
+    PM_LAUNCH_CHECK();
+  }
+  // X r2c (out of place allowed: rho -> acc x component)
+  if ((s = d_row_r2c(f, rho, A0, N0)) != PM_OK) return s;
+  // Y forward
+  Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
+  if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, -1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
+  // Z fused: T1 -> A0, T2 -> A2
+  Lines zm = lines_z_main(n), zn = lines_z_nyq(n);
+  if ((s = d_col_zconv(f, 0, A0, nullptr, nullptr, A0, A2, zm, n)) != PM_OK) return s;
+  if ((s = d_col_zconv(f, 0, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
+  // Y inverse: U1 -> A0, U2 (-i k_y) -> A1, U3 -> A2
+  if ((s = d_col_fft(f, A0, A0, A1, ym, n, +1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, N0, N0, N1, yn, 1, +1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, A2, A2, nullptr, ym, n, +1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, N2, N2, nullptr, yn, 1, +1)) != PM_OK) return s;
+  // X c2r
+  unsigned int* am = (unsigned int*)amax;
+  if ((s = d_row_c2r(f, A0, N0, (float*)A0, 1, am)) != PM_OK) return s;
+  if ((s = d_row_c2r(f, A1, N1, (float*)A1, 0, am)) != PM_OK) return s;
+  if ((s = d_row_c2r(f, A2, N2, (float*)A2, 0, am)) != PM_OK) return s;
+  return PM_OK;
+}
+
+pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
+  const int n = (int)c->g.ng;
+  const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  FftCtx f{c, n, n - 1};
+  float2* A[3] = {(float2*)acc, (float2*)(acc + n3), (float2*)(acc + 2 * n3)};
+  float2* Nq[3] = {nyq, nyq + n2, nyq + 2 * n2};
+  pm_status s;
+  Lines ym = lines_y_main(n), yn = lines_y_nyq(n), zm = lines_z_main(n), zn = lines_z_nyq(n);
+  for (int ax = 0; ax < 3; ++ax) {
+    if ((s = d_row_r2c(f, (const float*)A[ax], A[ax], Nq[ax])) != PM_OK) return s;
+    if ((s = d_col_fft(f, A[ax], A[ax], nullptr, ym, n, -1)) != PM_OK) return s;
+    if ((s = d_col_fft(f, Nq[ax], Nq[ax], nullptr, yn, 1, -1)) != PM_OK) return s;
+  }
+  if ((s = d_col_zconv(f, 1, A[0], A[1], A[2], A[0], nullptr, zm, n)) != PM_OK) return s;
+  if ((s = d_col_zconv(f, 1, Nq[0], Nq[1], Nq[2], Nq[0], nullptr, zn, 1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, A[0], A[0], nullptr, ym, n, +1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, Nq[0], Nq[0], nullptr, yn, 1, +1)) != PM_OK) return s;
+  if ((s = d_row_c2r(f, A[0], Nq[0], (float*)A[0], 0, nullptr)) != PM_OK) return s;
+  return PM_OK;
+}

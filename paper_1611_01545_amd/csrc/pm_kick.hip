@@ -1,0 +1,426 @@
+// CIC force interpolation (Fig. 2 "inverse_force_interpolation"), kick and drift, fused
+// with the re-encode of compressed particles and the stable re-sort of the stream into
+// cell order (Sec. 2.4: particles are written cell by cell).
+//
+// Compressed path, per species:
+//   k_vmax_next     v_max' = smallest power of two >= V + |c_k| A_max (V: largest
+//                   decoded |v| of the input, from its extreme velocity codes; A_max:
+//                   largest |a| on the mesh). Interpolation is a convex combination of
+//                   mesh values, so no kicked component exceeds the bound.
+//   k_kick_brick    one workgroup per brick of B^3 cells, particles in stream order:
+//                   decode, gather a from the 8 CIC nodes, v' = v + c_k a, fixed-point
+//                   drift u' = u + floor(v' c_d S + 1/2), new codes. Particles that
+//                   stay inside the brick get their stable rank inside their new cell;
+//                   the others ("movers") are listed with (new cell, old index).
+//   movers          compacted in old order, stably radix-sorted by new cell.
+//   k_arrivals      per new cell: arrivals, and how many of them come from earlier
+//                   bricks (they precede the cell's stayers in stream order).
+//   scan            new cell offsets.
+//   k_place_*       stayers and movers written at their final stream positions.
+#include "pm_codec.h"
+#include "pm_scan.h"
+
+namespace {
+
+constexpr int KT = 256;  // threads per workgroup
+constexpr uint32_t MOVER = 0xffffffffu;
+constexpr uint32_t RANK_BITS = 23;
+constexpr uint32_t RANK_LIMIT = (1u << RANK_BITS) - 1;
+
+// ------------------------------------------------------------ float layout --
+__global__ __launch_bounds__(KT) void k_kick_float(const float* x, const float* v, float* xo,
+                                                  float* vo, int64_t n, const float* acc,
+                                                  int64_t ng, float ck, float cd) {
+  int64_t p = (int64_t)blockIdx.x * KT + threadIdx.x;
+  if (p >= n) return;
+  const int64_t n3 = ng * ng * ng;
+  int64_t i[3];
+  float f[3], xv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    xv[a] = x[3 * p + a];
+    float u = xv[a] * (float)ng;  // exact (ng a power of two)
+    float fl = floorf(u);
+    f[a] = u - fl;
+    int64_t k = (int64_t)fl % ng;
+    i[a] = k < 0 ? k + ng : k;
+  }
+  float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        float w = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) * (dz ? f[2] : 1.f - f[2]);
+        int64_t node = (((i[2] + dz) % ng) * ng + (i[1] + dy) % ng) * ng + (i[0] + dx) % ng;
+        ax += w * acc[node];
+        ay += w * acc[n3 + node];
+        az += w * acc[2 * n3 + node];
+      }
+  const float a3[3] = {ax, ay, az};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float v1 = v[3 * p + a] + ck * a3[a];
+    float x1 = xv[a] + cd * v1;
+    x1 -= floorf(x1);
+    if (x1 >= 1.f) x1 = 0.f;
+    vo[3 * p + a] = v1;
+    xo[3 * p + a] = x1;
+  }
+}
+
+// ------------------------------------------------------- compressed layout --
+__global__ void k_vmax_next(const pm_shdr* hin, pm_shdr* hout, const float* amax, double ck,
+                            int64_t n) {
+  double V = 0.0;
+  if (n > 0 && hin->j_max >= 0) {
+    double a = fabs((double)vel_decode((uint32_t)hin->j_min, hin->v_max));
+    double b = fabs((double)vel_decode((uint32_t)hin->j_max, hin->v_max));
+    V = a > b ? a : b;
+  }
+  double bound = V + fabs(ck) * (double)(*amax);
+  float vm = 0.f;
+  if (bound > 0.0) {
+    int e;
+    double m = frexp(bound, &e);
+    vm = (float)(m == 0.5 ? bound : ldexp(1.0, e));
+  }
+  hout->v_max = vm;
+  hout->j_min = 65536;
+  hout->j_max = -1;
+  hout->flags = 0;
+  hout->n_esc = 0;
+  hout->reserved = 0;
+}
+
+struct KickArgs {
+  int64_t n;
+  const uint8_t* pos;
+  const uint16_t* vel;
+  const pm_shdr* hin;
+  pm_shdr* hout;
+  const int64_t* off;   // input cell offsets [ncell3 + 1]
+  const float* acc;     // [3][ng^3]
+  float ck;
+  double cdS;           // c_d * S (position codes per unit velocity)
+  uint8_t* tpos;        // new codes, old stream order
+  uint16_t* tvel;
+  uint32_t* tdst;       // (new local cell << 23) | rank, or MOVER
+  uint64_t* cnt;        // per cell: stayers (low 32 bits)
+  uint32_t* mkey;       // movers: new cell key, at [brick start + mover rank]
+  uint32_t* midx;       // movers: old stream index
+  uint32_t* mcnt;       // movers per brick
+};
+
+__global__ __launch_bounds__(KT) void k_kick_brick(KickArgs A, Geom g, DevErr* err) {
+  const int B = g.B, B3 = B * B * B;
+  extern __shared__ unsigned char smem[];
+  int64_t* loff = (int64_t*)smem;                  // [B3 + 1] input offsets of the brick
+  uint32_t* run = (uint32_t*)(loff + B3 + 1);      // [B3 + 1] running counts (B3 = movers)
+  uint32_t* wcnt = run + (B3 + 1);                 // [4][B3 + 1] per-wave counts
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+  const int64_t b = blockIdx.x;
+  const uint32_t kbase = (uint32_t)(b * B3);
+  for (int i = threadIdx.x; i <= B3; i += KT) {
+    loff[i] = A.off[kbase + i];
+    run[i] = 0;
+  }
+  __syncthreads();
+  const int64_t j0 = min(loff[0], A.n), j1 = min(loff[B3], A.n);
+  const float vmax_in = A.hin->v_max;
+  const float vmax_out = A.hout->v_max;
+  const int64_t ng = g.ng, n3 = ng * ng * ng;
+  const int r = g.r;
+  const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
+  int jmin = 65536, jmax = -1;
+  bool bad = false;
+  for (int64_t base = j0; base < j1; base += KT) {
+    for (int i = threadIdx.x; i < 4 * (B3 + 1); i += KT) wcnt[i] = 0;
+    __syncthreads();
+    const int64_t j = base + threadIdx.x;
+    const bool valid = j < j1;
+    uint32_t digit = 0;
+    uint32_t newkey = 0;
+    if (valid) {
+      // local cell of j: largest l with loff[l] <= j
+      int lo = 0, hi = B3;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (loff[mid] <= j) lo = mid; else hi = mid;
+      }
+      uint32_t cx, cy, cz;
+      key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
+      const uint32_t cell[3] = {cx, cy, cz};
+      uint32_t u[3];
+      int li[3];
+      float f[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        u[a] = (cell[a] << 8) | A.pos[3 * j + a];
+        const int64_t gg = (2 * (int64_t)u[a] + 1) * r;  // 1/512 mesh cells
+        li[a] = (int)(gg >> 9);
+        f[a] = (float)(gg & 511) * (1.0f / 512.0f);
+      }
+      float acc3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
+                        (dz ? f[2] : 1.f - f[2]);
+            int64_t nz = li[2] + dz, ny = li[1] + dy, nx = li[0] + dx;
+            nz -= nz >= ng ? ng : 0;
+            ny -= ny >= ng ? ng : 0;
+            nx -= nx >= ng ? ng : 0;
+            const int64_t node = (nz * ng + ny) * ng + nx;
+            acc3[0] += wgt * A.acc[node];
+            acc3[1] += wgt * A.acc[n3 + node];
+            acc3[2] += wgt * A.acc[2 * n3 + node];
+          }
+      uint32_t un[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float v0 = vel_decode(A.vel[3 * j + a], vmax_in);
+        const float v1 = v0 + A.ck * acc3[a];
+        const double d = floor((double)v1 * A.cdS + 0.5);
+        if (!(fabs(d) < 4.0e15)) bad = true;
+        int64_t q = ((int64_t)u[a] + (int64_t)(bad ? 0.0 : d)) % g.S;
+        un[a] = (uint32_t)(q < 0 ? q + g.S : q);
+        const int jc = vel_code(v1, vmax_out);
+        A.tpos[3 * j + a] = (uint8_t)(un[a] & 255u);
+        A.tvel[3 * j + a] = (uint16_t)jc;
+        jmin = min(jmin, jc);
+        jmax = max(jmax, jc);
+      }
+      newkey = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
+      digit = (newkey >= kbase && newkey < kbase + (uint32_t)B3) ? newkey - kbase : (uint32_t)B3;
+    }
+    // stable multi-split of this chunk by digit (new local cell, or B3 for movers)
+    uint64_t match = __ballot(valid);
+    for (int bit = 0; bit < nbits; ++bit) {
+      uint64_t m = __ballot(valid && ((digit >> bit) & 1u));
+      match &= ((digit >> bit) & 1u) ? m : ~m;
+    }
+    const uint32_t rk = (uint32_t)__popcll(match & lt);
+    if (valid && rk == 0) wcnt[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = run[digit];
+      for (int q = 0; q < w; ++q) pre += wcnt[q * (B3 + 1) + digit];
+      const uint32_t rank = pre + rk;
+      if (digit < (uint32_t)B3) {
+        if (rank >= RANK_LIMIT) bad = true;
+        A.tdst[j] = (digit << RANK_BITS) | (rank & RANK_LIMIT);
+      } else {
+        A.tdst[j] = MOVER;
+        A.mkey[j0 + rank] = newkey;
+        A.midx[j0 + rank] = (uint32_t)j;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= B3; i += KT) {
+      uint32_t add = 0;
+      for (int q = 0; q < 4; ++q) add += wcnt[q * (B3 + 1) + i];
+      run[i] += add;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < B3; i += KT) A.cnt[kbase + i] = (uint64_t)run[i];
+  if (threadIdx.x == 0) A.mcnt[b] = run[B3];
+  if (bad) latch_error(err, ERRBIT_RANGE);
+  for (int d = 32; d >= 1; d >>= 1) {
+    jmin = min(jmin, __shfl_xor(jmin, d, 64));
+    jmax = max(jmax, __shfl_xor(jmax, d, 64));
+  }
+  if (lane == 0) {
+    if (jmin < 65536) atomicMin(&A.hout->j_min, jmin);
+    if (jmax >= 0) atomicMax(&A.hout->j_max, jmax);
+  }
+}
+
+// movers of brick b sit at [off[b B^3], off[b B^3] + mcnt[b]); gather them in old order
+__global__ __launch_bounds__(KT) void k_compact_movers(const int64_t* off, const uint32_t* mcnt,
+                                                      const int64_t* moff, int B3,
+                                                      const uint32_t* mkey, const uint32_t* midx,
+                                                      uint32_t* okey, uint32_t* oidx) {
+  const int64_t b = blockIdx.x;
+  const int64_t src = off[b * B3], dst = moff[b];
+  const uint32_t m = mcnt[b];
+  for (uint32_t i = threadIdx.x; i < m; i += KT) {
+    okey[dst + i] = mkey[src + i];
+    oidx[dst + i] = midx[src + i];
+  }
+}
+
+__device__ inline int64_t lower_bound_u32(const uint32_t* a, int64_t lo, int64_t hi, uint32_t v) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// per group of sorted movers with the same new cell: add arrivals (low 32 bits) and
+// arrivals from earlier bricks (high 32 bits) to the cell's count
+__global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uint32_t* sidx,
+                                                int64_t nm, const int64_t* off_in, int B3,
+                                                uint64_t* cnt) {
+  int64_t s = (int64_t)blockIdx.x * KT + threadIdx.x;
+  if (s >= nm) return;
+  const uint32_t k = skey[s];
+  if (s > 0 && skey[s - 1] == k) return;  // group leader only
+  const int64_t ge = lower_bound_u32(skey, s, nm, k + 1);
+  const int64_t bstart = off_in[(int64_t)(k / (uint32_t)B3) * B3];  // first old index of the cell's brick
+  const int64_t nb = lower_bound_u32(sidx, s, ge, (uint32_t)bstart) - s;
+  atomicAdd((unsigned long long*)&cnt[k], (unsigned long long)(((uint64_t)nb << 32) | (uint64_t)(ge - s)));
+}
+
+__global__ __launch_bounds__(KT) void k_place_stayers(const int64_t* off_in, const uint32_t* tdst,
+                                                     const uint8_t* tpos, const uint16_t* tvel,
+                                                     const uint64_t* cnt, const int64_t* off_new,
+                                                     int B3, uint8_t* pos, uint16_t* vel,
+                                                     int64_t* perm, int64_t n, DevErr* err) {
+  const int64_t b = blockIdx.x;
+  const int64_t kbase = b * B3;
+  const int64_t j0 = min(off_in[kbase], n), j1 = min(off_in[kbase + B3], n);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += KT) {
+    const uint32_t d = tdst[j];
+    if (d == MOVER) continue;
+    const int64_t key = kbase + (d >> RANK_BITS);
+    const int64_t dst = off_new[key] + (int64_t)(cnt[key] >> 32) + (d & RANK_LIMIT);
+    if (dst < 0 || dst >= n) {
+      latch_error(err, ERRBIT_CORRUPT);
+      continue;
+    }
+    pos[3 * dst] = tpos[3 * j];
+    pos[3 * dst + 1] = tpos[3 * j + 1];
+    pos[3 * dst + 2] = tpos[3 * j + 2];
+    vel[3 * dst] = tvel[3 * j];
+    vel[3 * dst + 1] = tvel[3 * j + 1];
+    vel[3 * dst + 2] = tvel[3 * j + 2];
+    if (perm) perm[dst] = j;
+  }
+}
+
+__global__ __launch_bounds__(KT) void k_place_movers(const uint32_t* skey, const uint32_t* sidx,
+                                                    int64_t nm, const uint8_t* tpos,
+                                                    const uint16_t* tvel, const uint64_t* cnt,
+                                                    const int64_t* off_new, uint8_t* pos,
+                                                    uint16_t* vel, int64_t* perm, int64_t n,
+                                                    DevErr* err) {
+  int64_t s = (int64_t)blockIdx.x * KT + threadIdx.x;
+  if (s >= nm) return;
+  const uint32_t k = skey[s];
+  const int64_t gs = lower_bound_u32(skey, 0, s, k);
+  const int64_t ge = lower_bound_u32(skey, s, nm, k + 1);
+  const uint64_t cv = cnt[k];
+  const int64_t before = (int64_t)(cv >> 32), total = (int64_t)(cv & 0xffffffffull);
+  const int64_t stay = total - (ge - gs);
+  const int64_t jg = s - gs;
+  const int64_t dst = off_new[k] + (jg < before ? jg : stay + jg);
+  const int64_t j = sidx[s];
+  if (dst < 0 || dst >= n || j >= n) {
+    latch_error(err, ERRBIT_CORRUPT);
+    return;
+  }
+  pos[3 * dst] = tpos[3 * j];
+  pos[3 * dst + 1] = tpos[3 * j + 1];
+  pos[3 * dst + 2] = tpos[3 * j + 2];
+  vel[3 * dst] = tvel[3 * j];
+  vel[3 * dst + 1] = tvel[3 * j + 1];
+  vel[3 * dst + 2] = tvel[3 * j + 2];
+  if (perm) perm[dst] = j;
+}
+
+__global__ void k_read_total(const int64_t* moff, int64_t nb, int64_t* out) { *out = moff[nb]; }
+
+}  // namespace
+
+pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
+                         const float* acc, double ck, double cd) {
+  if (in->n == 0) return PM_OK;
+  hipLaunchKernelGGL(k_kick_float, dim3((unsigned)cdiv(in->n, KT)), dim3(KT), 0, c->stream,
+                     in->x, in->v, out->x, out->v, in->n, acc, c->g.ng, (float)ck, (float)cd);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+// perm (device int64 [n], nullable): new stream position -> old stream position.
+pm_status run_kick_compressed_off(pm_context* c, const pm_species* in, pm_species* out,
+                                  const int64_t* off_in, const float* acc, const float* amax,
+                                  double ck, double cd, int64_t* perm) {
+  const Geom& g = c->g;
+  const int64_t n = in->n;
+  const int B3 = g.B * g.B * g.B;
+  hipLaunchKernelGGL(k_vmax_next, dim3(1), dim3(1), 0, c->stream, in->hdr, out->hdr, amax, ck,
+                     n);
+  PM_LAUNCH_CHECK();
+  uint64_t* cnt = (uint64_t*)scratch(c, SC_CNT, (size_t)g.ncell3 * 8);
+  int64_t* off_new = (int64_t*)scratch(c, SC_OFF2, (size_t)(g.ncell3 + 1) * 8);
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  uint8_t* tpos = (uint8_t*)scratch(c, SC_TPOS, nn * 3);
+  uint16_t* tvel = (uint16_t*)scratch(c, SC_TVEL, nn * 6);
+  uint32_t* tdst = (uint32_t*)scratch(c, SC_TDST, nn * 4);
+  uint32_t* mkey = (uint32_t*)scratch(c, SC_KEYA, nn * 4);
+  uint32_t* midx = (uint32_t*)scratch(c, SC_VALA, nn * 4);
+  uint32_t* skey = (uint32_t*)scratch(c, SC_KEYB, nn * 4);
+  uint32_t* sidx = (uint32_t*)scratch(c, SC_VALB, nn * 4);
+  uint32_t* mcnt = (uint32_t*)scratch(c, SC_MCNT, (size_t)g.nbrick * 4);
+  int64_t* moff = (int64_t*)scratch(c, SC_MOFF, (size_t)(g.nbrick + 1) * 8);
+  int64_t* nmv = (int64_t*)scratch(c, SC_MISC, 64);
+  if (!cnt || !off_new || !tpos || !tvel || !tdst || !mkey || !midx || !skey || !sidx ||
+      !mcnt || !moff || !nmv)
+    return PM_ERR_NOMEM;
+  KickArgs A{n, in->pos, in->vel, in->hdr, out->hdr, off_in, acc, (float)ck,
+             cd * (double)g.S, tpos, tvel, tdst, cnt, mkey, midx, mcnt};
+  size_t lds = (size_t)(B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * 5;
+  hipLaunchKernelGGL(k_kick_brick, dim3((unsigned)g.nbrick), dim3(KT), lds, c->stream, A, g,
+                     c->err);
+  PM_LAUNCH_CHECK();
+  pm_status s = scan_u32(c, mcnt, g.nbrick, moff);
+  if (s != PM_OK) return s;
+  // the mover count is data dependent: read it back (one small synchronisation)
+  int64_t nm = 0;
+  PM_HIP_CHECK(hipMemcpyAsync(&nm, moff + g.nbrick, 8, hipMemcpyDeviceToHost, c->stream));
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  if (nm > 0) {
+    hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
+                       off_in, mcnt, moff, B3, mkey, midx, skey, sidx);
+    PM_LAUNCH_CHECK();
+    // stable sort (old order preserved inside each new cell)
+    uint32_t *k1 = skey, *v1 = sidx, *k2 = mkey, *v2 = midx;
+    s = radix_sort_pairs(c, &k1, &v1, &k2, &v2, nm, 3 * (g.lgB + g.lgnb));
+    if (s != PM_OK) return s;
+    skey = k1;
+    sidx = v1;
+    hipLaunchKernelGGL(k_arrivals, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream, skey,
+                       sidx, nm, off_in, B3, cnt);
+    PM_LAUNCH_CHECK();
+  }
+  s = scan_u64lo(c, cnt, g.ncell3, off_new);
+  if (s != PM_OK) return s;
+  hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream, off_in,
+                     tdst, tpos, tvel, cnt, off_new, B3, out->pos, out->vel, perm, n, c->err);
+  PM_LAUNCH_CHECK();
+  if (nm > 0) {
+    hipLaunchKernelGGL(k_place_movers, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream,
+                       skey, sidx, nm, tpos, tvel, cnt, off_new, out->pos, out->vel, perm, n,
+                       c->err);
+    PM_LAUNCH_CHECK();
+  }
+  return run_finalize_counts(c, nullptr, cnt, out);
+}
+
+pm_status run_kick_compressed(pm_context* c, const pm_species* in, pm_species* out,
+                              const float* acc, const float* amax, double ck, double cd,
+                              uint32_t* /*unused*/) {
+  int64_t* off = (int64_t*)scratch(c, SC_OFF, (size_t)(c->g.ncell3 + 1) * 8);
+  if (!off) return PM_ERR_NOMEM;
+  pm_status s = run_cell_offsets(c, in, off);
+  if (s != PM_OK) return s;
+  return run_kick_compressed_off(c, in, out, off, acc, amax, ck, cd, nullptr);
+}

@@ -1,0 +1,149 @@
+// Device-wide building blocks: fills, exclusive scans into 64-bit offsets, and a
+// stable LSD radix sort of (uint32 key, uint32 value) pairs. They serve the cell
+// ordering of the compressed format (a stable counting order of particles by cell,
+// Sec. 2.4 "linked list" reused for compression).
+#include "pm_scan.h"
+
+using namespace pmscan;
+
+namespace {
+
+// ------------------------------------------------------------------ radix sort --
+constexpr int RS_THREADS = 256;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
+                                                        int shift, int64_t nblk,
+                                                        uint32_t* hist) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    int64_t i = base + r * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
+                                                           const uint32_t* vin, int64_t n,
+                                                           int shift, int64_t nblk,
+                                                           const int64_t* hoff,
+                                                           uint32_t* kout, uint32_t* vout) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  run[threadIdx.x] = 0;
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    if (base + r * RS_THREADS >= n) break;  // uniform across the block
+#pragma unroll
+    for (int q = 0; q < RS_THREADS / 64; ++q) wcnt[q][threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = base + r * RS_THREADS + threadIdx.x;
+    bool valid = i < n;
+    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t val = valid ? vin[i] : 0u;
+    uint32_t d = (key >> shift) & 255u;
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      uint64_t m = __ballot(valid && ((d >> b) & 1u));
+      match &= ((d >> b) & 1u) ? m : ~m;
+    }
+    uint32_t rank = (uint32_t)__popcll(match & lt);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = run[d];
+      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+      int64_t dst = hoff[(int64_t)d * nblk + blockIdx.x] + pre + rank;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    {
+      uint32_t add = 0;
+#pragma unroll
+      for (int q = 0; q < RS_THREADS / 64; ++q) add += wcnt[q][threadIdx.x];
+      run[threadIdx.x] += add;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_iota(int64_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+}  // namespace
+
+pm_status run_iota(pm_context* c, int64_t* p, int64_t n) {
+  if (n <= 0) return PM_OK;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, p, n);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status launch_fill_u32(pm_context* c, uint32_t* p, int64_t n, uint32_t v) {
+  if (n <= 0) return PM_OK;
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, c->stream, p,
+                     n, v);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status launch_fill_u64(pm_context* c, uint64_t* p, int64_t n, uint64_t v) {
+  if (n <= 0) return PM_OK;
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, c->stream, p,
+                     n, v);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status scan_u32(pm_context* c, const uint32_t* in, int64_t n, int64_t* out) {
+  return scan_generic(c, GetU32{in}, n, out);
+}
+pm_status scan_u64lo(pm_context* c, const uint64_t* in, int64_t n, int64_t* out) {
+  return scan_generic(c, GetU64Lo{in}, n, out);
+}
+pm_status scan_counts(pm_context* c, const uint8_t* count, const uint64_t* esc,
+                      const pm_shdr* hdr, int64_t n, int64_t* out) {
+  return scan_generic(c, GetCount{count, esc, hdr}, n, out);
+}
+
+pm_status radix_sort_pairs(pm_context* c, uint32_t** keys, uint32_t** vals,
+                           uint32_t** keys_alt, uint32_t** vals_alt, int64_t n,
+                           int bits) {
+  if (n <= 1 || bits <= 0) return PM_OK;
+  int64_t nblk = cdiv(n, RS_TILE);
+  uint32_t* hist = (uint32_t*)scratch(c, SC_HIST, (size_t)nblk * 256 * sizeof(uint32_t));
+  int64_t* hoff = (int64_t*)scratch(c, SC_HOFF, ((size_t)nblk * 256 + 1) * sizeof(int64_t));
+  if (!hist || !hoff) return PM_ERR_NOMEM;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, c->stream,
+                       *keys, n, shift, nblk, hist);
+    PM_LAUNCH_CHECK();
+    pm_status s = scan_u32(c, hist, nblk * 256, hoff);
+    if (s != PM_OK) return s;
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, c->stream,
+                       *keys, *vals, n, shift, nblk, hoff, *keys_alt, *vals_alt);
+    PM_LAUNCH_CHECK();
+    uint32_t* t = *keys;
+    *keys = *keys_alt;
+    *keys_alt = t;
+    t = *vals;
+    *vals = *vals_alt;
+    *vals_alt = t;
+  }
+  return PM_OK;
+}

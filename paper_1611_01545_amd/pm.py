@@ -1,0 +1,315 @@
+"""Python binding of libpm: argument marshalling around the C ABI (include/pm.h).
+
+Every step of the particle-mesh path runs in libpm's HIP kernels; this module only
+allocates device tensors with torch, fills the C structs and checks status codes.
+Functions keep the names of the C entry points (pm_encode -> PMContext.encode, ...).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PM_COMPRESSED, PM_FLOAT, PmConfig, PmSpecies, check
+
+G_UNIT = 1.0 / (4.0 * math.pi)  # 4 pi G = 1
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class FloatSpecies:
+    x: torch.Tensor  # float32 [n, 3] on the device
+    v: torch.Tensor
+    mass: float
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def c(self) -> PmSpecies:
+        s = PmSpecies()
+        s.layout = PM_FLOAT
+        s.n = self.n
+        s.mass = self.mass
+        s.x = _ptr(self.x)
+        s.v = _ptr(self.v)
+        return s
+
+
+@dataclass
+class CompressedSpecies:
+    count: torch.Tensor  # uint8 [n_cell^3]
+    pos: torch.Tensor    # uint8 [n, 3]
+    vel: torch.Tensor    # int16 [n, 3] holding uint16 codes
+    esc: torch.Tensor    # int64 [cap, 2] holding uint64 (cell, count)
+    hdr: torch.Tensor    # uint8 [32]: pm_shdr
+    mass: float
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def c(self) -> PmSpecies:
+        s = PmSpecies()
+        s.layout = PM_COMPRESSED
+        s.n = self.n
+        s.mass = self.mass
+        s.count = _ptr(self.count)
+        s.pos = _ptr(self.pos)
+        s.vel = _ptr(self.vel)
+        s.esc = _ptr(self.esc)
+        s.cap_esc = int(self.esc.shape[0])
+        s.hdr = _ptr(self.hdr)
+        return s
+
+    def header(self) -> dict:
+        h = self.hdr.cpu().numpy().tobytes()
+        v_max, j_min, j_max, flags, n_esc, _ = np_struct_unpack(h)
+        return {"v_max": np.float32(v_max), "j_min": j_min, "j_max": j_max, "flags": flags,
+                "n_esc": n_esc}
+
+
+def np_struct_unpack(h: bytes):
+    import struct
+    return struct.unpack("<fiiiqq", h)
+
+
+def _species_array(species):
+    arr = (PmSpecies * len(species))()
+    for i, s in enumerate(species):
+        arr[i] = s.c()
+    return arr
+
+
+class PMContext:
+    """A libpm context: one mesh size, one compression-cell size, one HIP stream."""
+
+    def __init__(self, n_mesh: int, n_cell: int, brick: int | None = None,
+                 G: float = G_UNIT, soft_cells: float = 1.0, device: str = "cuda"):
+        self.lib = _lib.lib()
+        dev = torch.device(device)
+        if dev.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("libpm needs a ROCm GPU (torch.cuda unavailable)")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        torch.cuda.set_device(self.device)
+        if brick is None:
+            brick = max(1, min(8, n_cell, 16 // max(1, n_mesh // n_cell)))
+        self.n_mesh, self.n_cell, self.brick = n_mesh, n_cell, brick
+        self.G, self.soft_cells = G, soft_cells
+        cfg = PmConfig(n_mesh, n_cell, brick, 0, G, soft_cells)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(self.lib.pm_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h)), "pm_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- allocation --
+    def float_species(self, x, v, mass: float) -> FloatSpecies:
+        x = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
+        v = torch.as_tensor(v, dtype=torch.float32).to(self.device).contiguous()
+        return FloatSpecies(x.reshape(-1, 3), v.reshape(-1, 3), float(mass))
+
+    def empty_compressed(self, n: int, mass: float, cap_esc: int | None = None) -> CompressedSpecies:
+        if cap_esc is None:
+            cap_esc = max(16, n // 255 + 1)
+        d = self.device
+        return CompressedSpecies(
+            count=torch.empty(self.n_cell ** 3, dtype=torch.uint8, device=d),
+            pos=torch.empty((n, 3), dtype=torch.uint8, device=d),
+            vel=torch.empty((n, 3), dtype=torch.int16, device=d),
+            esc=torch.zeros((cap_esc, 2), dtype=torch.int64, device=d),
+            hdr=torch.zeros(32, dtype=torch.uint8, device=d),
+            mass=float(mass))
+
+    def empty_like(self, s):
+        if isinstance(s, FloatSpecies):
+            return FloatSpecies(torch.empty_like(s.x), torch.empty_like(s.v), s.mass)
+        return self.empty_compressed(s.n, s.mass, int(s.esc.shape[0]))
+
+    # ------------------------------------------------------------ the calls --
+    def sync(self):
+        check(self.lib.pm_sync(self.h), "pm_sync")
+
+    def last_error_detail(self) -> int:
+        v = ctypes.c_int64()
+        check(self.lib.pm_last_error_detail(self.h, ctypes.byref(v)), "pm_last_error_detail")
+        return v.value
+
+    def encode(self, fs: FloatSpecies, want_perm: bool = False, cap_esc: int | None = None):
+        out = self.empty_compressed(fs.n, fs.mass, cap_esc)
+        perm = torch.empty(fs.n, dtype=torch.int64, device=self.device) if want_perm else None
+        a, b = fs.c(), out.c()
+        check(self.lib.pm_encode(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(perm)),
+              "pm_encode")
+        return (out, perm) if want_perm else out
+
+    def decode(self, cs: CompressedSpecies) -> FloatSpecies:
+        out = FloatSpecies(torch.empty((cs.n, 3), dtype=torch.float32, device=self.device),
+                           torch.empty((cs.n, 3), dtype=torch.float32, device=self.device),
+                           cs.mass)
+        a, b = cs.c(), out.c()
+        check(self.lib.pm_decode(self.h, ctypes.byref(a), ctypes.byref(b)), "pm_decode")
+        return out
+
+    def deposit(self, species, rho: torch.Tensor | None = None) -> torch.Tensor:
+        n = self.n_mesh
+        if rho is None:
+            rho = torch.empty((n, n, n), dtype=torch.float32, device=self.device)
+        arr = _species_array(species)
+        check(self.lib.pm_deposit(self.h, arr, len(species), _ptr(rho)), "pm_deposit")
+        return rho
+
+    def force(self, rho: torch.Tensor, acc: torch.Tensor | None = None,
+              a_max: torch.Tensor | None = None):
+        """Acceleration mesh [3, n, n, n] and max |a| (device float tensor)."""
+        n = self.n_mesh
+        if acc is None:
+            acc = torch.empty((3, n, n, n), dtype=torch.float32, device=self.device)
+        if a_max is None:
+            a_max = torch.zeros(1, dtype=torch.float32, device=self.device)
+        check(self.lib.pm_force(self.h, _ptr(rho), _ptr(acc), _ptr(a_max)), "pm_force")
+        return acc, a_max
+
+    def kick_drift(self, species, acc, a_max, c_kick: float, c_drift: float, out=None):
+        if out is None:
+            out = [self.empty_like(s) for s in species]
+        a, b = _species_array(species), _species_array(out)
+        check(self.lib.pm_kick_drift(self.h, a, b, len(species), _ptr(acc), _ptr(a_max),
+                                     float(c_kick), float(c_drift)), "pm_kick_drift")
+        return out
+
+    def kick_drift_perm(self, species, acc, a_max, c_kick: float, c_drift: float, out=None):
+        """kick_drift plus, per species, new stream position -> old stream position."""
+        if out is None:
+            out = [self.empty_like(s) for s in species]
+        perms = [torch.empty(s.n, dtype=torch.int64, device=self.device) for s in species]
+        a, b = _species_array(species), _species_array(out)
+        pp = (ctypes.c_void_p * len(species))(*[_ptr(p) for p in perms])
+        check(self.lib.pm_kick_drift_perm(self.h, a, b, len(species), _ptr(acc), _ptr(a_max),
+                                          float(c_kick), float(c_drift), pp),
+              "pm_kick_drift_perm")
+        return out, perms
+
+    def step(self, species, dt: float, out=None):
+        if out is None:
+            out = [self.empty_like(s) for s in species]
+        a, b = _species_array(species), _species_array(out)
+        check(self.lib.pm_step(self.h, a, b, len(species), float(dt)), "pm_step")
+        return out
+
+    def step_vjp(self, species, dt: float, lam_x1, lam_v1):
+        ns = len(species)
+        lam_x0 = [torch.empty_like(t) for t in lam_x1]
+        lam_v0 = [torch.empty_like(t) for t in lam_v1]
+        ptrs = lambda ts: (ctypes.c_void_p * ns)(*[_ptr(t.contiguous()) for t in ts])
+        lx1 = [t.contiguous() for t in lam_x1]
+        lv1 = [t.contiguous() for t in lam_v1]
+        arr = _species_array(species)
+        check(self.lib.pm_step_vjp(self.h, arr, ns, float(dt), ptrs(lx1), ptrs(lv1),
+                                   ptrs(lam_x0), ptrs(lam_v0)), "pm_step_vjp")
+        return lam_x0, lam_v0
+
+    def loss_density_vjp(self, species, rho_target: torch.Tensor):
+        ns = len(species)
+        lam = [torch.empty((s.n, 3), dtype=torch.float32, device=self.device) for s in species]
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        arr = _species_array(species)
+        check(self.lib.pm_loss_density_vjp(self.h, arr, ns, _ptr(rho_target.contiguous()),
+                                           _ptr(loss),
+                                           (ctypes.c_void_p * ns)(*[_ptr(t) for t in lam])),
+              "pm_loss_density_vjp")
+        return loss, lam
+
+    def reduce(self, species, rho: torch.Tensor | None = None) -> np.ndarray:
+        out = torch.zeros(8, dtype=torch.float64, device=self.device)
+        arr = _species_array(species) if species else None
+        check(self.lib.pm_reduce(self.h, arr, len(species), _ptr(rho), _ptr(out)), "pm_reduce")
+        return out.cpu().numpy()
+
+    def pack_size(self, cs: CompressedSpecies) -> int:
+        v = ctypes.c_int64()
+        a = cs.c()
+        check(self.lib.pm_pack_size(self.h, ctypes.byref(a), ctypes.byref(v)), "pm_pack_size")
+        return v.value
+
+    def pack(self, cs: CompressedSpecies, species_id: int = 0) -> bytes:
+        size = self.pack_size(cs)
+        buf = torch.empty(max(size, 64), dtype=torch.uint8, device=self.device)
+        used = torch.zeros(1, dtype=torch.int64, device=self.device)
+        a = cs.c()
+        check(self.lib.pm_pack(self.h, ctypes.byref(a), int(species_id), _ptr(buf), size,
+                               _ptr(used)), "pm_pack")
+        self.sync()
+        return buf[: int(used.item())].cpu().numpy().tobytes()
+
+    def unpack(self, data: bytes, n: int, cap_esc: int | None = None):
+        out = self.empty_compressed(n, 0.0, cap_esc)
+        a = out.c()
+        mass = ctypes.c_double()
+        sid = ctypes.c_int32()
+        raw = (ctypes.c_uint8 * len(data)).from_buffer_copy(data)
+        check(self.lib.pm_unpack(self.h, ctypes.cast(raw, ctypes.c_void_p), len(data),
+                                 ctypes.byref(a), ctypes.byref(mass), ctypes.byref(sid)),
+              "pm_unpack")
+        out.mass = mass.value
+        return out, sid.value
+
+    def kernel_table(self) -> torch.Tensor:
+        m = self.n_mesh // 2
+        t = torch.empty(3 * m * m + 1, dtype=torch.float32, device=self.device)
+        check(self.lib.pm_kernel_table(self.h, _ptr(t), t.numel()), "pm_kernel_table")
+        return t
+
+    # ------------------------------------------------------- host transfers --
+    def to_host(self, cs: CompressedSpecies) -> dict:
+        """Compressed species -> the oracle's state dict (numpy arrays)."""
+        self.sync()
+        h = cs.header()
+        esc = cs.esc[: h["n_esc"]].cpu().numpy().astype(np.uint64).reshape(-1, 2)
+        return {"n_c": self.n_cell, "brick": self.brick,
+                "count": cs.count.cpu().numpy(), "esc": esc,
+                "pos": cs.pos.cpu().numpy(),
+                "vel": cs.vel.cpu().numpy().view(np.uint16),
+                "v_max": h["v_max"], "j_min": h["j_min"], "j_max": h["j_max"]}
+
+    def from_host(self, st: dict, mass: float, cap_esc: int | None = None) -> CompressedSpecies:
+        """Oracle state dict -> device compressed species (header j_min/j_max derived)."""
+        import struct
+        n = int(st["pos"].shape[0])
+        cs = self.empty_compressed(n, mass, cap_esc)
+        cs.count.copy_(torch.from_numpy(np.ascontiguousarray(st["count"])))
+        if n:
+            cs.pos.copy_(torch.from_numpy(np.ascontiguousarray(st["pos"])))
+            cs.vel.copy_(torch.from_numpy(np.ascontiguousarray(st["vel"]).view(np.int16)))
+        esc = np.asarray(st["esc"], dtype=np.uint64).reshape(-1, 2)
+        if esc.shape[0] > cs.esc.shape[0]:
+            raise ValueError("escape table larger than capacity")
+        if esc.shape[0]:
+            cs.esc[: esc.shape[0]].copy_(torch.from_numpy(esc.view(np.int64)))
+        vel = np.asarray(st["vel"])
+        jmin = int(vel.min()) if n else 65536
+        jmax = int(vel.max()) if n else -1
+        h = struct.pack("<fiiiqq", float(st["v_max"]), jmin, jmax, 0, esc.shape[0], 0)
+        cs.hdr.copy_(torch.frombuffer(bytearray(h), dtype=torch.uint8))
+        return cs

@@ -122,7 +122,7 @@ def cdm_zeldovich(n_p: int, n_mesh: int, n_s: float, sigma_cells: float, seed: i
     dk *= amp
     psi = np.empty((n3, 3), dtype=np.float64)
     for col, nn in ((0, nx), (1, ny), (2, nz)):
-        comp = np.fft.irfftn(1j * nn * inv_k2 * dk, s=(n_p, n_p, n_p))
+        comp = np.fft.irfftn(1j * nn * inv_k2 * dk, s=(n_p, n_p, n_p), axes=(0, 1, 2))
         psi[:, col] = comp.reshape(-1)
         del comp
     del dk

@@ -1,0 +1,312 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: the compressed codec, stream order, counts and byte streams are bit-exact;
+density |d rho| <= 1e-5 max(|rho|, mean rho); forces relative RMS <= 1e-4; float-path
+positions <= 1e-6 box units; compressed codes equal except in the tie zone where the
+oracle's pre-floor value lies within the propagated force tolerance of an integer.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (assert_state_equal, ctx, density_close, frac_dist, rel_rms,
+                      small_two_species)
+from oracle import codec, mesh, step
+
+pytestmark = pytest.mark.gpu
+
+
+def _encode_both(c, wl, brick):
+    states, dev = [], []
+    for sp in wl.species:
+        st = codec.encode(sp.x, sp.v, wl.n_cell, brick)
+        fs = c.float_species(sp.x, sp.v, sp.mass)
+        cs, perm = c.encode(fs, want_perm=True)
+        states.append(st)
+        dev.append((cs, perm))
+    return states, dev
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_kernel_table(n):
+    c = ctx(n, n // 2)
+    t = c.kernel_table().cpu().numpy().astype(np.float64)
+    q = np.arange(t.size, dtype=np.float64)
+    ref = mesh.plummer_kernel_k(2 * np.pi * np.sqrt(q), 1.0 / n, 1 / (4 * np.pi)) / n ** 3
+    nz = ref != 0
+    assert t[0] == 0.0
+    assert np.max(np.abs(t[nz] / ref[nz] - 1)) < 2e-7
+
+
+@pytest.mark.parametrize("n_p_c,n_mesh,brick", [(16, 32, 4), (16, 32, 1), (32, 64, 8)])
+def test_encode_decode_bit_exact(n_p_c, n_mesh, brick):
+    wl = small_two_species(n_p_c, n_mesh)
+    c = ctx(n_mesh, wl.n_cell, brick)
+    states, dev = _encode_both(c, wl, brick)
+    for st, (cs, perm) in zip(states, dev):
+        h = c.to_host(cs)
+        assert_state_equal(h, st)
+        assert np.array_equal(perm.cpu().numpy(), st["perm"])
+        fs = c.decode(cs)
+        c.sync()
+        xo, vo = codec.decode(st)
+        assert np.array_equal(fs.x.cpu().numpy(), xo)
+        assert np.array_equal(fs.v.cpu().numpy(), vo)
+
+
+def test_encode_escape_and_edges():
+    rng = np.random.default_rng(3)
+    n_c, n_mesh, brick = 8, 32, 2
+    n = 5000
+    x = rng.random((n, 3)).astype(np.float32)
+    x[:700] = np.float32(0.51)             # one cell with 700 particles
+    x[700:1000] = np.float32(0.0)          # 300 at the origin corner
+    x[1000, :] = np.float32(1.0 - 2 ** -24)
+    x[1001, :] = np.float32(-1e-9)
+    x[1002, :] = np.float32(1.0)
+    v = rng.standard_normal((n, 3)).astype(np.float32)
+    v[5] = [3.5, -3.5, 0.0]
+    c = ctx(n_mesh, n_c, brick)
+    st = codec.encode(x, v, n_c, brick)
+    cs, perm = c.encode(c.float_species(x, v, 1.0 / n), want_perm=True)
+    h = c.to_host(cs)
+    assert st["esc"].shape[0] == 2
+    assert_state_equal(h, st)
+    assert np.array_equal(perm.cpu().numpy(), st["perm"])
+    assert (h["j_min"], h["j_max"]) == (int(st["vel"].min()), int(st["vel"].max()))
+
+
+def test_encode_capacity_error():
+    from paper_1611_01545_amd._lib import PMError
+    n_c = 4
+    x = np.full((600, 3), 0.3, np.float32)
+    v = np.zeros((600, 3), np.float32)
+    c = ctx(16, n_c, 1)
+    cs = c.encode(c.float_species(x, v, 1.0), cap_esc=0)
+    with pytest.raises(PMError) as e:
+        c.sync()
+    assert "CAPACITY" in str(e.value)
+    assert c.last_error_detail() == 1
+
+
+def test_empty_species():
+    c = ctx(16, 8, 2)
+    x = np.zeros((0, 3), np.float32)
+    cs = c.encode(c.float_species(x, x, 1.0))
+    h = c.to_host(cs)
+    assert h["count"].sum() == 0 and h["v_max"] == 0
+
+
+@pytest.mark.parametrize("n_p_c,n_mesh", [(16, 32), (16, 64), (32, 64)])
+def test_deposit_compressed(n_p_c, n_mesh):
+    wl = small_two_species(n_p_c, n_mesh)
+    c = ctx(n_mesh, wl.n_cell)
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    rho = c.deposit(dev).cpu().numpy()
+    c.sync()
+    sts = [c.to_host(d) for d in dev]
+    ref = mesh.deposit_species([(codec.decode(s)[0].astype(np.float64), sp.mass)
+                                for s, sp in zip(sts, wl.species)], n_mesh)
+    assert density_close(rho, ref) <= 1e-5
+    # deterministic: a second deposit is bit-identical
+    rho2 = c.deposit(dev).cpu().numpy()
+    assert np.array_equal(rho, rho2)
+
+
+def test_deposit_float():
+    wl = make_plain()
+    c = ctx(wl.n_mesh, wl.n_cell)
+    sp = wl.species[0]
+    rho = c.deposit([c.float_species(sp.x, sp.v, sp.mass)]).cpu().numpy()
+    ref = mesh.deposit(sp.x.astype(np.float64), sp.mass, wl.n_mesh)
+    assert density_close(rho, ref) <= 1e-5
+
+
+def make_plain():
+    from pmsynth import make_workload
+    return make_workload("plain_cdm_64")
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
+def test_force_random_density(n):
+    rng = np.random.default_rng(n)
+    rho = (1.0 + 0.5 * rng.standard_normal((n, n, n))).astype(np.float32)
+    c = ctx(n, n // 2)
+    acc, amax = c.force(torch.from_numpy(rho).cuda())
+    a = acc.cpu().numpy()
+    ref = mesh.force_mesh(rho.astype(np.float64))
+    for ax in range(3):
+        assert rel_rms(a[ax], ref[ax]) <= 1e-4, (ax, rel_rms(a[ax], ref[ax]))
+    assert abs(float(amax.item()) / np.max(np.abs(ref)) - 1) < 1e-4
+
+
+def test_force_in_place_alias():
+    n = 32
+    rng = np.random.default_rng(1)
+    rho = rng.random((n, n, n)).astype(np.float32)
+    c = ctx(n, 16)
+    buf = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+    buf[0].copy_(torch.from_numpy(rho))
+    acc, _ = c.force(buf[0], acc=buf)
+    ref = mesh.force_mesh(rho.astype(np.float64))
+    for ax in range(3):
+        assert rel_rms(acc[ax].cpu().numpy(), ref[ax]) <= 1e-4
+
+
+def test_float_step_plain():
+    wl = make_plain()
+    c = ctx(wl.n_mesh, wl.n_cell)
+    sp = wl.species[0]
+    fs = c.float_species(sp.x, sp.v, sp.mass)
+    (out,) = c.step([fs], wl.dt)
+    c.sync()
+    (ref,), diag = step.step_float([(sp.x, sp.v, sp.mass)], wl.n_mesh, wl.dt, wl.dt)
+    dx = np.abs(out.x.cpu().numpy().astype(np.float64) - ref[0])
+    dx = np.minimum(dx, 1 - dx)
+    assert dx.max() <= 1e-6
+    # particle accelerations through the kick: a = (v' - v) / dt
+    a_gpu = (out.v.cpu().numpy().astype(np.float64) - sp.v) / wl.dt
+    assert rel_rms(a_gpu, diag["acc"][0]) <= 1e-4
+
+
+def _codes_old_order(host_state, perm):
+    """Integer position codes u and velocity codes j of a state, in old stream order."""
+    u, j = codec.decode_codes(host_state)
+    uo = np.empty_like(u)
+    jo = np.empty_like(j)
+    uo[perm] = u
+    jo[perm] = j
+    return uo, jo
+
+
+@pytest.mark.parametrize("n_p_c,n_mesh,seed", [(16, 32, 0), (32, 64, 1)])
+def test_compressed_step_tie_zone(n_p_c, n_mesh, seed):
+    wl = small_two_species(n_p_c, n_mesh, seed_offset=seed)
+    c = ctx(n_mesh, wl.n_cell)
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    rho = c.deposit(dev)
+    acc, amax = c.force(rho)
+    dt = wl.dt
+    out, perms = c.kick_drift_perm(dev, acc, amax, dt, dt)
+    c.sync()
+    states = [c.to_host(d) for d in dev]
+    masses = [sp.mass for sp in wl.species]
+    new, diag = step.step_compressed(states, masses, n_mesh, dt, dt)
+    S = 256 * wl.n_cell
+    a_scale = np.sqrt(np.mean(diag["a_mesh"] ** 2))
+    for o, ns, d, perm in zip(out, new, diag["species"], perms):
+        h = c.to_host(o)
+        pm = perm.cpu().numpy()
+        assert np.array_equal(np.sort(pm), np.arange(pm.size))
+        ug, jg = _codes_old_order(h, pm)
+        # position codes: equal unless the oracle's pre-floor value is within the
+        # propagated tolerance of an integer (force tolerance 1e-4 of the mesh scale
+        # plus float32 rounding of v')
+        dv = abs(dt) * 1e-4 * a_scale * 10 + 2.0 ** -22 * np.abs(d["v_new"])
+        tau_x = dt * S * dv + 1e-6
+        du = (ug - d["u_new"] + S // 2) % S - S // 2
+        bad = du != 0
+        assert np.all(np.abs(du[bad]) <= 1)
+        assert np.all(frac_dist(d["pos_pre"][bad]) <= tau_x[bad])
+        assert bad.mean() < 1e-3
+        # velocity codes (same v_max' on both sides in these cases)
+        assert float(h["v_max"]) == float(d["v_max_new"])
+        C = 32768.0 / float(d["v_max_new"])
+        tau_v = C * dv + 1e-6
+        dj = jg - d["j_new"]
+        badv = dj != 0
+        assert np.all(np.abs(dj[badv]) <= 1)
+        assert np.all(frac_dist(d["vel_pre"][badv]) <= tau_v[badv])
+        assert badv.mean() < 1e-3
+        # the stream is the stable cell sort of the GPU's own new codes
+        keys = codec.cell_keys(ug >> 8, wl.n_cell, c.brick)
+        order = np.argsort(keys, kind="stable")
+        assert np.array_equal(order, pm)
+        assert np.array_equal(codec.full_counts(h),
+                              np.bincount(keys, minlength=wl.n_cell ** 3))
+
+
+def test_step_equals_pieces_and_is_deterministic():
+    wl = small_two_species(16, 32, seed_offset=5)
+    c = ctx(32, wl.n_cell)
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    out1 = c.step(dev, wl.dt)
+    out2 = c.step(dev, wl.dt)
+    rho = c.deposit(dev)
+    acc, amax = c.force(rho)
+    out3 = c.kick_drift(dev, acc, amax, wl.dt, wl.dt)
+    c.sync()
+    for a, b, d in zip(out1, out2, out3):
+        ha, hb, hd = c.to_host(a), c.to_host(b), c.to_host(d)
+        assert_state_equal(ha, hb)
+        assert_state_equal(ha, hd)
+
+
+def test_multi_step_chain_conserves_particles():
+    wl = small_two_species(16, 32, seed_offset=6)
+    c = ctx(32, wl.n_cell)
+    cur = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    for _ in range(5):
+        cur = c.step(cur, wl.dt * 5)
+    c.sync()
+    for cs, sp in zip(cur, wl.species):
+        h = c.to_host(cs)
+        assert codec.full_counts(h).sum() == sp.x.shape[0]
+
+
+def test_pack_unpack_bytes():
+    wl = small_two_species(16, 32, seed_offset=2)
+    c = ctx(32, wl.n_cell)
+    for sid, sp in enumerate(wl.species):
+        cs = c.encode(c.float_species(sp.x, sp.v, sp.mass))
+        buf = c.pack(cs, sid)
+        st = c.to_host(cs)
+        ref = codec.pack(st, sp.mass, sid)
+        assert buf == ref
+        back, sid2 = c.unpack(buf, cs.n)
+        assert sid2 == sid and back.mass == sp.mass
+        assert_state_equal(c.to_host(back), st)
+
+
+def test_pack_escape_and_corruption():
+    from paper_1611_01545_amd._lib import PMError
+    n_c = 4
+    rng = np.random.default_rng(4)
+    x = rng.random((2000, 3)).astype(np.float32)
+    x[:400] = np.float32(0.6)
+    v = rng.standard_normal((2000, 3)).astype(np.float32)
+    c = ctx(16, n_c, 2)
+    cs = c.encode(c.float_species(x, v, 0.5))
+    buf = c.pack(cs, 1)
+    st = c.to_host(cs)
+    assert buf == codec.pack(st, 0.5, 1)
+    bad = bytearray(buf)
+    bad[100] ^= 0x10
+    with pytest.raises(PMError):
+        c.unpack(bytes(bad), cs.n)
+    with pytest.raises(PMError):
+        c.unpack(buf[:-3], cs.n)
+
+
+def test_reduce_mass_momentum():
+    wl = small_two_species(16, 32, seed_offset=3)
+    c = ctx(32, wl.n_cell)
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    rho = c.deposit(dev)
+    out = c.reduce(dev, rho)
+    mtot = sum(sp.mass * sp.x.shape[0] for sp in wl.species)
+    assert abs(out[1] - mtot) <= 1e-14 * mtot
+    assert abs(out[0] - mtot) <= 1e-6 * mtot  # float32 mesh summed in float64
+    p = np.zeros(3)
+    for d, sp in zip(dev, wl.species):
+        _, v = codec.decode(c.to_host(d))
+        p += sp.mass * v.astype(np.float64).sum(0)
+    assert np.allclose(out[2:5], p, rtol=1e-12, atol=1e-15)
+
+
+def test_bad_shapes_rejected():
+    from paper_1611_01545_amd._lib import PMError
+    for args in [(48, 16), (64, 128), (4096, 256), (64, 2)]:
+        with pytest.raises(PMError):
+            ctx(*args)
