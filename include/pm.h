@@ -221,6 +221,16 @@ pm_status pm_pack_size(pm_ctx ctx, const pm_species* sp, int64_t* bytes);
 pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species* out,
                     double* mass, int32_t* species_id);
 
+/* Per-stage timing with HIP events recorded on the context's stream around each
+ * kernel group. pm_profile(ctx, 1) clears the totals and starts recording, 0 stops.
+ * pm_profile_read synchronises and returns, for stage ids 0..cap-1, the summed
+ * milliseconds and the number of timed launches:
+ *   0 cell offsets   1 deposit          2 FFT x r2c     3 FFT y forward
+ *   4 FFT z fused    5 FFT y inverse    6 FFT x c2r     7 interpolate-kick-drift
+ *   8 re-sort        9 encode/decode   10 adjoint scatter/gather */
+pm_status pm_profile(pm_ctx ctx, int enable);
+pm_status pm_profile_read(pm_ctx ctx, double* ms, int64_t* launches, int cap);
+
 /* Diagnostics: copy the float32 kernel table G(|n|^2)/n_mesh^3 (device float
  * [3 (n_mesh/2)^2 + 1], indexed by the integer |n|^2). */
 pm_status pm_kernel_table(pm_ctx ctx, float* out, int64_t cap);

@@ -84,6 +84,8 @@ EXPORTS = [
     ("pm_pack_size", [P, PS, ctypes.POINTER(I64)]),
     ("pm_unpack", [P, P, I64, PS, ctypes.POINTER(ctypes.c_double),
                    ctypes.POINTER(ctypes.c_int32)]),
+    ("pm_profile", [P, ctypes.c_int]),
+    ("pm_profile_read", [P, P, P, ctypes.c_int]),
     ("pm_kernel_table", [P, P, I64]),
 ]
 

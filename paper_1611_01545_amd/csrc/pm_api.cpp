@@ -67,10 +67,34 @@ void* scratch(pm_context* c, int id, size_t bytes) {
   return b.p;
 }
 
+void prof_begin(pm_context* c, int stage) {
+  if (!c->prof) return;
+  size_t i = c->prof_used;
+  if (2 * i + 2 > c->prof_pool.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->prof_pool.push_back(e);
+    }
+    c->prof_stage.push_back(0);
+  }
+  c->prof_stage[i] = stage;
+  hipEventRecord(c->prof_pool[2 * i], c->stream);
+  c->prof_open = (int)i;
+  c->prof_used = i + 1;
+}
+
+void prof_end(pm_context* c) {
+  if (!c->prof || c->prof_open < 0) return;
+  hipEventRecord(c->prof_pool[2 * c->prof_open + 1], c->stream);
+  c->prof_open = -1;
+}
+
 // pm_kick.hip
-pm_status run_kick_compressed_off(pm_context* c, const pm_species* in, pm_species* out,
-                                  const int64_t* off_in, const float* acc, const float* amax,
-                                  double ck, double cd, int64_t* perm);
+pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
+                                  int n_sp, int64_t* const* offs, const float* acc,
+                                  const float* amax, double ck, double cd,
+                                  int64_t* const* perm);
 int deposit_tile_cells(const Geom& g);
 
 extern "C" {
@@ -146,6 +170,7 @@ pm_status pm_destroy(pm_ctx c) {
   hipFree(c->amax);
   for (auto& b : c->scratch)
     if (b.p) hipFree(b.p);
+  for (auto e : c->prof_pool) hipEventDestroy(e);
   delete c;
   return PM_OK;
 }
@@ -207,24 +232,24 @@ pm_status pm_force(pm_ctx c, const float* rho, float* acc, float* a_max) {
 static pm_status kick_all(pm_context* c, const pm_species* in, pm_species* out, int n_sp,
                           const float* acc, const float* a_max, double ck, double cd,
                           int64_t* const* offs, int64_t* const* perm = nullptr) {
-  for (int i = 0; i < n_sp; ++i) {
-    pm_status s;
-    if (in[i].layout == PM_FLOAT) {
-      s = run_kick_float(c, &in[i], &out[i], acc, ck, cd);
-      if (s == PM_OK && perm && perm[i]) s = run_iota(c, perm[i], in[i].n);
-    } else {
-      int64_t* off = offs ? offs[i] : nullptr;
-      if (!off) {
-        off = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
-        if (!off) return PM_ERR_NOMEM;
-        if ((s = run_cell_offsets(c, &in[i], off)) != PM_OK) return s;
-      }
-      s = run_kick_compressed_off(c, &in[i], &out[i], off, acc, a_max, ck, cd,
-                                  perm ? perm[i] : nullptr);
+  pm_status s;
+  if (in[0].layout == PM_FLOAT) {
+    for (int i = 0; i < n_sp; ++i) {
+      if ((s = run_kick_float(c, &in[i], &out[i], acc, ck, cd)) != PM_OK) return s;
+      if (perm && perm[i] && (s = run_iota(c, perm[i], in[i].n)) != PM_OK) return s;
     }
-    if (s != PM_OK) return s;
+    return PM_OK;
   }
-  return PM_OK;
+  int64_t* own[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (!offs) {
+    for (int i = 0; i < n_sp; ++i) {
+      own[i] = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+      if (!own[i]) return PM_ERR_NOMEM;
+      if ((s = run_cell_offsets(c, &in[i], own[i])) != PM_OK) return s;
+    }
+    offs = own;
+  }
+  return run_kick_compressed_all(c, in, out, n_sp, offs, acc, a_max, ck, cd, perm);
 }
 
 static pm_status check_kick_args(pm_context* c, const pm_species* in, pm_species* out,
@@ -424,6 +449,35 @@ pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, 
   PM_HIP_CHECK(hipMemcpy(out->hdr, &h, sizeof(h), hipMemcpyHostToDevice));
   if (mass) *mass = m;
   if (species_id) *species_id = (int32_t)sid;
+  return PM_OK;
+}
+
+pm_status pm_profile(pm_ctx c, int enable) {
+  if (!c) return PM_ERR_ARG;
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  c->prof = enable ? 1 : 0;
+  c->prof_used = 0;
+  c->prof_open = -1;
+  return PM_OK;
+}
+
+pm_status pm_profile_read(pm_ctx c, double* ms, int64_t* launches, int cap) {
+  if (!c || !ms || !launches || cap < 0) return PM_ERR_ARG;
+  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < cap; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (size_t i = 0; i < c->prof_used; ++i) {
+    int st = c->prof_stage[i];
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->prof_pool[2 * i], c->prof_pool[2 * i + 1]) != hipSuccess)
+      continue;
+    if (st < cap) {
+      ms[st] += t;
+      launches[st] += 1;
+    }
+  }
   return PM_OK;
 }
 

@@ -52,21 +52,32 @@ __global__ __launch_bounds__(T256) void k_encode_keys(const float* x, int64_t n,
   vals[p] = (uint32_t)p;
 }
 
-__device__ inline void wave_minmax_to_hdr(int jmin, int jmax, pm_shdr* h) {
+// Block min/max of the velocity codes, stored at the block's index (no atomics).
+__device__ inline void block_minmax_store(int jmin, int jmax, int32_t* pmn, int32_t* pmx) {
+  __shared__ int smn[T256 / 64], smx[T256 / 64];
   for (int d = 32; d >= 1; d >>= 1) {
     jmin = min(jmin, __shfl_xor(jmin, d, 64));
     jmax = max(jmax, __shfl_xor(jmax, d, 64));
   }
   if ((threadIdx.x & 63) == 0) {
-    if (jmin < 65536) atomicMin(&h->j_min, jmin);
-    if (jmax >= 0) atomicMax(&h->j_max, jmax);
+    smn[threadIdx.x >> 6] = jmin;
+    smx[threadIdx.x >> 6] = jmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < T256 / 64; ++q) {
+      jmin = min(jmin, smn[q]);
+      jmax = max(jmax, smx[q]);
+    }
+    pmn[blockIdx.x] = jmin;
+    pmx[blockIdx.x] = jmax;
   }
 }
 
 __global__ __launch_bounds__(T256) void k_encode_gather(
     const float* x, const float* v, int64_t n, Geom g, const uint32_t* keys_sorted,
     const uint32_t* idx_sorted, uint8_t* pos, uint16_t* vel, int64_t* perm,
-    uint32_t* count32, pm_shdr* h) {
+    uint32_t* run_start, pm_shdr* h, int32_t* pmn, int32_t* pmx) {
   int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
   int jmin = 65536, jmax = -1;
   if (j < n) {
@@ -83,9 +94,21 @@ __global__ __launch_bounds__(T256) void k_encode_gather(
       jmax = max(jmax, c);
     }
     if (perm) perm[j] = (int64_t)p;
-    atomicAdd(&count32[keys_sorted[j]], 1u);
+    const uint32_t k = keys_sorted[j];
+    if (j == 0 || keys_sorted[j - 1] != k) run_start[k] = (uint32_t)j;  // first of its cell
   }
-  wave_minmax_to_hdr(jmin, jmax, h);
+  block_minmax_store(jmin, jmax, pmn, pmx);
+}
+
+// Particle count of each occupied cell, from the sorted keys: stored by the last
+// particle of the cell's run (runs are contiguous after the sort).
+__global__ __launch_bounds__(T256) void k_run_counts(const uint32_t* keys_sorted, int64_t n,
+                                                    const uint32_t* run_start,
+                                                    uint32_t* count32) {
+  int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t k = keys_sorted[j];
+  if (j == n - 1 || keys_sorted[j + 1] != k) count32[k] = (uint32_t)(j + 1 - run_start[k]);
 }
 
 // Full count -> u8 byte and escape flag (count >= 255).
@@ -157,6 +180,18 @@ __global__ __launch_bounds__(T256) void k_decode(const uint8_t* pos, const uint1
 }
 
 // ---------------------------------------------------------------- byte stream --
+// Block sum of the checksum terms, stored at the block's index (integer: exact).
+__device__ inline void block_sum_store(uint64_t s, uint64_t* part) {
+  __shared__ uint64_t sm[T256 / 64];
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < T256 / 64; ++q) s += sm[q];
+    part[blockIdx.x] = s;
+  }
+}
+
 struct GetPackBytes {
   const int64_t* off;
   __device__ int64_t operator()(int64_t c) const {
@@ -185,8 +220,7 @@ __global__ __launch_bounds__(T256) void k_pack_cells(const int64_t* off, const i
       s += (2ull * (uint64_t)o + 1ull) * (uint64_t)k;
     }
   }
-  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)csum, (unsigned long long)s);
+  block_sum_store(s, csum);
 }
 
 __global__ __launch_bounds__(T256) void k_pack_records(const uint8_t* pos, const uint16_t* vel,
@@ -199,7 +233,8 @@ __global__ __launch_bounds__(T256) void k_pack_records(const uint8_t* pos, const
     int64_t c = find_cell(off, ncell, j);
     int64_t k = off[c + 1] - off[c];
     int64_t o = boff[c] + (k >= 255 ? 5 : 1) + 9 * (j - off[c]);
-    if (o + 9 > boff[ncell]) return;  // counts inconsistent with n (latched elsewhere)
+    // counts inconsistent with n (latched by the offset check): write nothing
+    if (o + 9 > boff[ncell]) o = -1;
     uint8_t b[9];
     b[0] = pos[3 * j];
     b[1] = pos[3 * j + 1];
@@ -212,12 +247,26 @@ __global__ __launch_bounds__(T256) void k_pack_records(const uint8_t* pos, const
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
+      if (o < 0) break;
       body[o + q] = b[q];
       s += (2ull * (uint64_t)(o + q) + 1ull) * b[q];
     }
   }
-  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)csum, (unsigned long long)s);
+  block_sum_store(s, csum);
+}
+
+// csum[0..nparts) -> csum[nparts] (sum mod 2^64, fixed order per thread, exact anyway)
+__global__ __launch_bounds__(1024) void k_fold_sum(uint64_t* csum, int64_t nparts) {
+  __shared__ uint64_t sm[16];
+  uint64_t a = 0;
+  for (int64_t i = threadIdx.x; i < nparts; i += 1024) a += csum[i];
+  for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 16; ++q) a += sm[q];
+    csum[nparts] = a;
+  }
 }
 
 __global__ void k_pack_header(uint8_t* buf, int64_t cap, const int64_t* boff, int64_t ncell,
@@ -239,7 +288,8 @@ __global__ void k_pack_header(uint8_t* buf, int64_t cap, const int64_t* boff, in
   };
   const char magic[4] = {'P', 'M', 'C', '1'};
   uint32_t ver = 1, usid = (uint32_t)sid, ub = (uint32_t)B, zero = 0;
-  uint64_t un = (uint64_t)n, unc = (uint64_t)nc, cs = *csum, ubl = (uint64_t)body;
+  const uint64_t cs = *csum;
+  uint64_t un = (uint64_t)n, unc = (uint64_t)nc, ubl = (uint64_t)body;
   float vmax = h->v_max;
   put(0, magic, 4);
   put(4, &ver, 4);
@@ -326,6 +376,7 @@ __global__ void k_reduce_final(const double* pmesh, int nmesh_part, double cell_
 }  // namespace
 
 pm_status run_cell_offsets(pm_context* c, const pm_species* sp, int64_t* off) {
+  ProfScope ps(c, ST_OFFSETS);
   pm_status s = scan_counts(c, sp->count, sp->esc, sp->hdr, c->g.ncell3, off);
   if (s != PM_OK) return s;
   hipLaunchKernelGGL(k_check_total, dim3(1), dim3(1), 0, c->stream, off, c->g.ncell3, sp->n,
@@ -354,6 +405,7 @@ pm_status run_finalize_counts(pm_context* c, const uint32_t* cnt32, const uint64
 }
 
 pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64_t* perm) {
+  ProfScope ps(c, ST_CODEC);
   const int64_t n = in->n;
   const Geom& g = c->g;
   hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(1), 0, c->stream, out->hdr);
@@ -379,9 +431,16 @@ pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64
     int bits = 3 * (g.lgB + g.lgnb);
     s = radix_sort_pairs(c, &ka, &va, &kb, &vb, n, bits);
     if (s != PM_OK) return s;
+    const int64_t nb = (int64_t)nbk;
+    int32_t* part = (int32_t*)scratch(c, SC_PARTS, (size_t)nb * 8);
+    uint32_t* rstart = (uint32_t*)scratch(c, SC_FLAG, (size_t)g.ncell3 * 4);
+    if (!part || !rstart) return PM_ERR_NOMEM;
     hipLaunchKernelGGL(k_encode_gather, dim3(nbk), dim3(T256), 0, c->stream, in->x, in->v, n,
-                       g, ka, va, out->pos, out->vel, perm, cnt32, out->hdr);
+                       g, ka, va, out->pos, out->vel, perm, rstart, out->hdr, part, part + nb);
     PM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_run_counts, dim3(nbk), dim3(T256), 0, c->stream, ka, n, rstart, cnt32);
+    PM_LAUNCH_CHECK();
+    if ((s = fold_minmax_to_header(c, part, part + nb, nb, out->hdr)) != PM_OK) return s;
   }
   return run_finalize_counts(c, cnt32, nullptr, out);
 }
@@ -403,24 +462,25 @@ pm_status run_pack(pm_context* c, const pm_species* sp, int32_t sid, uint8_t* bu
   const int64_t nc3 = c->g.ncell3;
   int64_t* off = (int64_t*)scratch(c, SC_OFF, (size_t)(nc3 + 1) * 8);
   int64_t* boff = (int64_t*)scratch(c, SC_FOFF, (size_t)(nc3 + 1) * 8);
-  uint64_t* csum = (uint64_t*)scratch(c, SC_MISC, 64);
+  const int64_t nbc = cdiv(nc3, T256), nbr = cdiv(sp->n, T256);
+  uint64_t* csum = (uint64_t*)scratch(c, SC_PARTS, (size_t)(nbc + nbr + 1) * 8);
   if (!off || !boff || !csum) return PM_ERR_NOMEM;
   pm_status s = run_cell_offsets(c, sp, off);
   if (s != PM_OK) return s;
   s = scan_generic_pack(c, off, nc3, boff);
   if (s != PM_OK) return s;
-  s = launch_fill_u64(c, csum, 1, 0ull);
-  if (s != PM_OK) return s;
   int64_t cap_body = cap - PM_STREAM_HEADER;
   uint8_t* body = buf + PM_STREAM_HEADER;
-  hipLaunchKernelGGL(k_pack_cells, dim3((unsigned)cdiv(nc3, T256)), dim3(T256), 0, c->stream,
+  hipLaunchKernelGGL(k_pack_cells, dim3((unsigned)nbc), dim3(T256), 0, c->stream,
                      off, boff, nc3, body, cap_body, csum);
-  if (sp->n > 0)
-    hipLaunchKernelGGL(k_pack_records, dim3((unsigned)cdiv(sp->n, T256)), dim3(T256), 0,
+  if (nbr > 0)
+    hipLaunchKernelGGL(k_pack_records, dim3((unsigned)nbr), dim3(T256), 0,
                        c->stream, sp->pos, sp->vel, off, boff, sp->n, nc3, body, cap_body,
-                       csum);
-  hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, c->stream, buf, cap, boff, nc3, csum,
-                     sp->hdr, sid, c->g.B, sp->n, c->g.nc, sp->mass, used, c->err);
+                       csum + nbc);
+  hipLaunchKernelGGL(k_fold_sum, dim3(1), dim3(1024), 0, c->stream, csum, nbc + nbr);
+  hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, c->stream, buf, cap, boff, nc3,
+                     csum + nbc + nbr, sp->hdr, sid, c->g.B, sp->n, c->g.nc, sp->mass, used,
+                     c->err);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "pm.h"
 
 // ---------------------------------------------------------------- error latch --
@@ -26,6 +28,22 @@ __device__ inline void latch_error(DevErr* e, int32_t bit, int64_t detail = 0) {
   atomicOr(&e->bits, bit);
   if (detail) atomicMax((unsigned long long*)&e->detail, (unsigned long long)detail);
 }
+
+// ------------------------------------------------------------ XCD mapping --
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its own L2.
+// Giving every XCD a contiguous range of tiles keeps neighbouring tiles (which share
+// halo cache lines) on the same L2.
+__device__ inline int64_t xcd_tile(int64_t bid, int64_t ntiles) {
+  if (ntiles % 8) return bid;
+  return (bid & 7) * (ntiles >> 3) + (bid >> 3);
+}
+
+// ------------------------------------------------------- partial reductions --
+// Whole-grid min/max without atomics: every workgroup stores its partial result at
+// its own index, and a one-block kernel folds the partials.
+pm_status fold_minmax_to_header(pm_context* c, const int32_t* mn, const int32_t* mx,
+                                int64_t n, pm_shdr* hdr);   // hdr->j_min / j_max
+pm_status fold_max_u32(pm_context* c, const uint32_t* part, int64_t n, uint32_t* out);
 
 // ----------------------------------------------------------------- geometry --
 // Cell keys: bricks of B^3 cells in x-fastest order, cells x-fastest inside a brick.
@@ -83,6 +101,25 @@ struct pm_context {
   // grow-on-demand scratch
   DevBuf scratch[32];
   int64_t last_detail = 0;
+  // stage profiler (pm_profile)
+  int prof = 0;
+  std::vector<hipEvent_t> prof_pool;
+  std::vector<int> prof_stage;   // stage of pair i (events 2i, 2i+1)
+  size_t prof_used = 0;          // pairs in use
+  int prof_open = -1;            // pair index currently open
+};
+
+enum ProfStage {
+  ST_OFFSETS = 0, ST_DEPOSIT, ST_FFT_R2C, ST_FFT_YF, ST_FFT_Z, ST_FFT_YI, ST_FFT_C2R,
+  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_N
+};
+// Record a begin/end event pair around a group of launches (no-op unless profiling).
+void prof_begin(pm_context* c, int stage);
+void prof_end(pm_context* c);
+struct ProfScope {
+  pm_context* c;
+  ProfScope(pm_context* cc, int stage) : c(cc) { prof_begin(c, stage); }
+  ~ProfScope() { prof_end(c); }
 };
 
 enum ScratchId {
@@ -112,6 +149,7 @@ enum ScratchId {
   SC_SPOFF1,
   SC_SPOFF2,
   SC_SPOFF3,
+  SC_PARTS,        // per-workgroup partial results of grid reductions
   SC_N
 };
 

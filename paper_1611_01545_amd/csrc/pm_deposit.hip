@@ -41,9 +41,10 @@ struct DepArgs {
 
 __device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
+template <int TT>  // tile side in cells (compile time, 0: runtime A.T)
 __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g, float* rho) {
   extern __shared__ unsigned char smem[];
-  const int T = A.T, R = A.R, r = A.r;
+  const int T = TT ? TT : A.T, R = A.R, r = A.r;
   const int E = T + 1;              // extended cells per side
   const int NE = E * E * E;
   const int R3 = R * R * R;
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
   unsigned long long* acc = (unsigned long long*)smem;
   int* pre = (int*)(acc + R3);      // [NE + 1] particle prefix over extended cells
   const int nt = (int)(g.nc / T);
-  const int tx = blockIdx.x % nt, ty = (blockIdx.x / nt) % nt, tz = blockIdx.x / (nt * nt);
+  const int64_t tile = xcd_tile(blockIdx.x, (int64_t)nt * nt * nt);
+  const int tx = (int)(tile % nt), ty = (int)((tile / nt) % nt), tz = (int)(tile / ((int64_t)nt * nt));
   const int ncs = (int)g.nc;
 
   for (int i = threadIdx.x; i < R3; i += DEP_THREADS) acc[i] = 0ull;
@@ -209,8 +211,14 @@ pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
   A.unit = mmax > 0 ? mmax * 0x1p-32 * ng3 : 0.0;
   int nt = (int)(g.nc / A.T);
   size_t lds = (size_t)A.R * A.R * A.R * 8 + ((size_t)(A.T + 1) * (A.T + 1) * (A.T + 1) + 1) * 4;
-  hipLaunchKernelGGL(k_deposit_tile, dim3((unsigned)((int64_t)nt * nt * nt)), dim3(DEP_THREADS),
-                     lds, c->stream, A, g, rho);
+  ProfScope ps(c, ST_DEPOSIT);
+  const dim3 grid((unsigned)((int64_t)nt * nt * nt));
+  if (A.T == 4)
+    hipLaunchKernelGGL(k_deposit_tile<4>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
+  else if (A.T == 8)
+    hipLaunchKernelGGL(k_deposit_tile<8>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
+  else
+    hipLaunchKernelGGL(k_deposit_tile<0>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -232,6 +240,7 @@ pm_status run_deposit(pm_context* c, const pm_species* sp, int n_sp, float* rho)
     return run_deposit_tile(c, sp, n_sp, offs, rho);
   }
   // float layout
+  ProfScope ps(c, ST_DEPOSIT);
   const int64_t n3 = g.ng * g.ng * g.ng;
   unsigned long long* acc = (unsigned long long*)scratch(c, SC_ACC64, (size_t)n3 * 8);
   if (!acc) return PM_ERR_NOMEM;

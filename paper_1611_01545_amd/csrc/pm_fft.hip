@@ -3,13 +3,14 @@
 // The paper transforms each tile with three threaded 1-D FFTW calls, one per
 // dimension (Sec. 2.3). Here every axis pass is one HBM pass over the mesh, and the
 // passes are fused so that the four transforms of a step (one forward, three
-// inverse) cost 5 sweeps instead of 12:
+// inverse) cost 10 launches moving 88 n^3 bytes instead of 12 passes moving 96 n^3:
 //   X  r2c      rho(x) -> rho~(kx)                     rows, in place, Nyquist column
 //                                                      kx = n/2 kept in a side plane
 //   Y  fwd      -> rho~(kx, ky)                        columns, in place
-//   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table), inverse
-//               z FFT twice: T1 = IFFT_z(G rho~), T2 = IFFT_z(-i k_z G rho~)
-//   Y  inv      U1 = IFFT_y(T1), U2 = IFFT_y(-i k_y T1), U3 = IFFT_y(T2)
+//   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table) and the
+//               gradient factor, inverse z FFT: T2 = IFFT_z(-i k_z G rho~), then in
+//               place T1 = IFFT_z(G rho~) (one output per launch: two launches)
+//   Y  inv      U2 = IFFT_y(-i k_y T1), then in place U1 = IFFT_y(T1), U3 = IFFT_y(T2)
 //   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
 //               max |a| for the velocity bound of the re-encode
 // The gradient factor -i k_a follows eq. (3) and is zero on the Nyquist index; the
@@ -240,7 +241,7 @@ __device__ __forceinline__ float grad_k(int k, int n) {
 
 // Generic c2c column FFT: out0 = FFT_SIGN(in); if out1, out1 = FFT_SIGN(-i k(e) in)
 // where k(e) is the line's own wave number (used for -i k_y in the inverse y pass).
-template <int N, int W, int SIGN>
+template <int N, int W, int SIGN, bool TWO>
 __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, float2* out0,
                                                             float2* out1, Lines d,
                                                             const float2* __restrict__ tw,
@@ -257,13 +258,15 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
 #pragma unroll
   for (int n1 = 0; n1 < P::E; ++n1)
     a[n1] = ok ? in[base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
-  float2 g[P::E];
-  if (out1) {
+  if constexpr (TWO) {
+    // the second output transforms -i k (x + i y) = k y - i k x; k is the line's own
+    // wave number
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) {
       float k = grad_k(t + P::T * n1, n);
-      g[n1] = make_float2(k * a[n1].y, -k * a[n1].x);  // -i k (x + i y) = k y - i k x
+      a[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
     }
+    out0 = out1;
   }
   nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
   if (ok) {
@@ -273,20 +276,11 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
       for (int k2 = 0; k2 < P::T; ++k2)
         out0[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = a[v * P::T + k2];
   }
-  if (out1) {  // uniform branch
-    nat_to_tr<N, SIGN>(g, t, my, tw, tws, twmask);
-    if (ok) {
-#pragma unroll
-      for (int v = 0; v < P::V; ++v)
-#pragma unroll
-        for (int k2 = 0; k2 < P::T; ++k2)
-          out1[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = g[v * P::T + k2];
-    }
-  }
 }
 
-// Fused z pass. MODE 0 (force): in0 -> out0 = IFFT(G F), out1 = IFFT(-i k_z G F) with
-// F = FFT(in0). MODE 1 (adjoint): out0 = IFFT(G sum_a (+i k_a) FFT(in_a)).
+// Fused z pass, F = FFT(in0): MODE 0: out0 = IFFT(G F); MODE 2: out0 = IFFT(-i k_z G F);
+// MODE 1 (adjoint): out0 = IFFT(G sum_a (+i k_a) FFT(in_a)). One output per launch keeps
+// a single line array in registers.
 template <int N, int W, int MODE>
 __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
     const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
@@ -305,34 +299,31 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
   const int sx = signed_k(kx, n), sy = signed_k(ky, n);
   const int nxy2 = sx * sx + sy * sy;
   float2 acc[P::E];
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 || MODE == 2) {
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1)
       acc[n1] = ok ? in0[base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
     nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
-    float2 g[P::E];
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
       for (int k2 = 0; k2 < P::T; ++k2) {
         const int kz = (t + P::T * v) + P::E * k2;
         const int sz = signed_k(kz, n);
-        const float G = ktab[nxy2 + sz * sz];
+        float G = ktab[nxy2 + sz * sz];
         float2 f = acc[v * P::T + k2];
-        f = make_float2(G * f.x, G * f.y);
-        acc[v * P::T + k2] = f;
-        const float kk = grad_k(kz, n);
-        g[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
+        if constexpr (MODE == 2) {
+          // -i k_z G (x + i y) = k_z G y - i k_z G x
+          const float kk = grad_k(kz, n) * G;
+          acc[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
+        } else {
+          acc[v * P::T + k2] = make_float2(G * f.x, G * f.y);
+        }
       }
     tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
     if (ok) {
 #pragma unroll
       for (int n1 = 0; n1 < P::E; ++n1) out0[base + (int64_t)(t + P::T * n1) * d.es] = acc[n1];
-    }
-    tr_to_nat<N, +1>(g, t, my, tw, tws, twmask);
-    if (ok) {
-#pragma unroll
-      for (int n1 = 0; n1 < P::E; ++n1) out1[base + (int64_t)(t + P::T * n1) * d.es] = g[n1];
     }
   } else {
     const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
@@ -497,8 +488,14 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
       m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
     }
   if (amax) {
+    __shared__ float wmax[16];
     for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmaxf(m, wmax[q]);
+      amax[blockIdx.x] = __float_as_uint(m);  // per-block partial, folded afterwards
+    }
   }
 }
 
@@ -555,12 +552,21 @@ pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, con
   constexpr int W = col_w<N>();
   dim3 grid((unsigned)cdiv(d.L1, W), (unsigned)L2);
   dim3 block(W * Plan<N>::T);
-  if (sign < 0)
-    hipLaunchKernelGGL((k_col_fft<N, W, -1>), grid, block, 0, f.c->stream, in, o0, o1, d,
-                       f.c->tw, 1, f.twmask, f.n);
-  else
-    hipLaunchKernelGGL((k_col_fft<N, W, 1>), grid, block, 0, f.c->stream, in, o0, o1, d,
-                       f.c->tw, 1, f.twmask, f.n);
+  if (sign < 0) {
+    if (o1)
+      hipLaunchKernelGGL((k_col_fft<N, W, -1, true>), grid, block, 0, f.c->stream, in, o0, o1,
+                         d, f.c->tw, 1, f.twmask, f.n);
+    else
+      hipLaunchKernelGGL((k_col_fft<N, W, -1, false>), grid, block, 0, f.c->stream, in, o0, o1,
+                         d, f.c->tw, 1, f.twmask, f.n);
+  } else {
+    if (o1)
+      hipLaunchKernelGGL((k_col_fft<N, W, 1, true>), grid, block, 0, f.c->stream, in, o0, o1, d,
+                         f.c->tw, 1, f.twmask, f.n);
+    else
+      hipLaunchKernelGGL((k_col_fft<N, W, 1, false>), grid, block, 0, f.c->stream, in, o0, o1,
+                         d, f.c->tw, 1, f.twmask, f.n);
+  }
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -573,6 +579,9 @@ pm_status col_zconv(const FftCtx& f, int mode, const float2* i0, const float2* i
   dim3 block(W * Plan<N>::T);
   if (mode == 0)
     hipLaunchKernelGGL((k_col_zconv<N, W, 0>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
+                       o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_col_zconv<N, W, 2>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
                        o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
   else
     hipLaunchKernelGGL((k_col_zconv<N, W, 1>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
@@ -645,6 +654,16 @@ pm_status d_row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float*
   return PM_ERR_SHAPE;
 }
 
+int64_t d_row_blocks(int n) {
+  switch (n) {
+#define CASE(N) \
+  case N: return cdiv((int64_t)N * N, rows_per_wg<N / 2>());
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return 0;
+}
+
 // Line descriptors of the half-spectrum layout: main [z][y][kx < n/2] and the Nyquist
 // plane nyq[z][y] (kx = n/2).
 Lines lines_y_main(int n) {  // l1 = kx, l2 = z, element = y
@@ -695,30 +714,63 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
   float2* A2 = (float2*)(acc + 2 * n3);
   float2 *N0 = nyq, *N1 = nyq + n2, *N2 = nyq + 2 * n2;
   pm_status s;
+  // per-block partial maxima of |a| of the three c2r launches
+  const int64_t nrow_blocks = d_row_blocks(n);
+  unsigned int* part = nullptr;
   if (amax) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, (unsigned int*)amax);
-    PM_LAUNCH_CHECK();
+    part = (unsigned int*)scratch(c, SC_PARTS, (size_t)3 * nrow_blocks * 4);
+    if (!part) return PM_ERR_NOMEM;
   }
   // X r2c (out of place allowed: rho -> acc x component)
-  if ((s = d_row_r2c(f, rho, A0, N0)) != PM_OK) return s;
+  {
+    ProfScope ps(c, ST_FFT_R2C);
+    if ((s = d_row_r2c(f, rho, A0, N0)) != PM_OK) return s;
+  }
   // Y forward
   Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
-  if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, -1)) != PM_OK) return s;
+  {
+    ProfScope ps(c, ST_FFT_YF);
+    if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, -1)) != PM_OK) return s;
+  }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
-  // Z fused: T1 -> A0, T2 -> A2
+  // Z fused: T2 = IFFT_z(-i k_z G F) -> A2 first (reads A0), then T1 = IFFT_z(G F) in place
   Lines zm = lines_z_main(n), zn = lines_z_nyq(n);
-  if ((s = d_col_zconv(f, 0, A0, nullptr, nullptr, A0, A2, zm, n)) != PM_OK) return s;
-  if ((s = d_col_zconv(f, 0, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
-  // Y inverse: U1 -> A0, U2 (-i k_y) -> A1, U3 -> A2
-  if ((s = d_col_fft(f, A0, A0, A1, ym, n, +1)) != PM_OK) return s;
-  if ((s = d_col_fft(f, N0, N0, N1, yn, 1, +1)) != PM_OK) return s;
-  if ((s = d_col_fft(f, A2, A2, nullptr, ym, n, +1)) != PM_OK) return s;
+  {
+    ProfScope ps(c, ST_FFT_Z);
+    if ((s = d_col_zconv(f, 2, A0, nullptr, nullptr, A2, nullptr, zm, n)) != PM_OK) return s;
+  }
+  {
+    ProfScope ps(c, ST_FFT_Z);
+    if ((s = d_col_zconv(f, 0, A0, nullptr, nullptr, A0, nullptr, zm, n)) != PM_OK) return s;
+  }
+  if ((s = d_col_zconv(f, 2, N0, nullptr, nullptr, N2, nullptr, zn, 1)) != PM_OK) return s;
+  if ((s = d_col_zconv(f, 0, N0, nullptr, nullptr, N0, nullptr, zn, 1)) != PM_OK) return s;
+  // Y inverse: U2 = IFFT_y(-i k_y T1) -> A1 first (reads A0), then U1 in place, U3 in place
+  {
+    ProfScope ps(c, ST_FFT_YI);
+    if ((s = d_col_fft(f, A0, nullptr, A1, ym, n, +1)) != PM_OK) return s;
+  }
+  {
+    ProfScope ps(c, ST_FFT_YI);
+    if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, +1)) != PM_OK) return s;
+  }
+  if ((s = d_col_fft(f, N0, nullptr, N1, yn, 1, +1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, +1)) != PM_OK) return s;
+  {
+    ProfScope ps(c, ST_FFT_YI);
+    if ((s = d_col_fft(f, A2, A2, nullptr, ym, n, +1)) != PM_OK) return s;
+  }
   if ((s = d_col_fft(f, N2, N2, nullptr, yn, 1, +1)) != PM_OK) return s;
   // X c2r
-  unsigned int* am = (unsigned int*)amax;
-  if ((s = d_row_c2r(f, A0, N0, (float*)A0, 1, am)) != PM_OK) return s;
-  if ((s = d_row_c2r(f, A1, N1, (float*)A1, 0, am)) != PM_OK) return s;
-  if ((s = d_row_c2r(f, A2, N2, (float*)A2, 0, am)) != PM_OK) return s;
+  float2* outs[3] = {A0, A1, A2};
+  float2* nqs[3] = {N0, N1, N2};
+  for (int ax = 0; ax < 3; ++ax) {
+    ProfScope ps(c, ST_FFT_C2R);
+    if ((s = d_row_c2r(f, outs[ax], nqs[ax], (float*)outs[ax], ax == 0 ? 1 : 0,
+                       part ? part + ax * nrow_blocks : nullptr)) != PM_OK)
+      return s;
+  }
+  if (amax) return fold_max_u32(c, part, 3 * nrow_blocks, (uint32_t*)amax);
   return PM_OK;
 }
 

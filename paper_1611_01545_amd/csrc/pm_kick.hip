@@ -94,16 +94,16 @@ __global__ void k_vmax_next(const pm_shdr* hin, pm_shdr* hout, const float* amax
   hout->reserved = 0;
 }
 
-struct KickArgs {
+constexpr int KB = 512;       // threads per workgroup of the brick kick
+constexpr int MAXSP = 4;
+
+struct KickSpecies {
   int64_t n;
   const uint8_t* pos;
   const uint16_t* vel;
   const pm_shdr* hin;
   pm_shdr* hout;
   const int64_t* off;   // input cell offsets [ncell3 + 1]
-  const float* acc;     // [3][ng^3]
-  float ck;
-  double cdS;           // c_d * S (position codes per unit velocity)
   uint8_t* tpos;        // new codes, old stream order
   uint16_t* tvel;
   uint32_t* tdst;       // (new local cell << 23) | rank, or MOVER
@@ -111,135 +111,210 @@ struct KickArgs {
   uint32_t* mkey;       // movers: new cell key, at [brick start + mover rank]
   uint32_t* midx;       // movers: old stream index
   uint32_t* mcnt;       // movers per brick
+  int32_t* pmn;         // per-brick extreme new velocity codes, folded into hout
+  int32_t* pmx;
+};
+struct KickArgs {
+  KickSpecies sp[MAXSP];
+  int n_sp;
+  const float* acc;     // [3][ng^3]
+  float ck;
+  double cdS;           // c_d * S (position codes per unit velocity)
 };
 
-__global__ __launch_bounds__(KT) void k_kick_brick(KickArgs A, Geom g, DevErr* err) {
+// One workgroup per brick, all species. With STAGE the brick's force nodes
+// [b R, b R + R]^3 (R = B r) are first copied to LDS with coalesced loads and every
+// particle gathers its 8 CIC nodes from there; the mesh is then read once per step
+// for all species.
+template <int RS>  // staged tile side in nodes (compile time), or 0: gather from HBM
+__global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* err) {
+  constexpr bool STAGE = RS > 0;
   const int B = g.B, B3 = B * B * B;
+  const int R = STAGE ? RS : B * g.r;
+  constexpr int R1 = RS + 1;
+  const int r = g.r;
   extern __shared__ unsigned char smem[];
-  int64_t* loff = (int64_t*)smem;                  // [B3 + 1] input offsets of the brick
-  uint32_t* run = (uint32_t*)(loff + B3 + 1);      // [B3 + 1] running counts (B3 = movers)
-  uint32_t* wcnt = run + (B3 + 1);                 // [4][B3 + 1] per-wave counts
+  float* F = (float*)smem;                                   // [3][R1^3] when STAGE
+  const int fsz = STAGE ? 3 * R1 * R1 * R1 : 0;
+  int64_t* loff = (int64_t*)(smem + ((fsz * 4 + 7) / 8) * 8);  // [B3 + 1]
+  uint32_t* run = (uint32_t*)(loff + B3 + 1);                // [B3 + 1] (B3 = movers)
+  uint32_t* wcnt = run + (B3 + 1);                           // [KB/64][B3 + 1]
+  constexpr int NW = KB / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_tile(blockIdx.x, g.nbrick);
   const uint32_t kbase = (uint32_t)(b * B3);
-  for (int i = threadIdx.x; i <= B3; i += KT) {
-    loff[i] = A.off[kbase + i];
-    run[i] = 0;
-  }
-  __syncthreads();
-  const int64_t j0 = min(loff[0], A.n), j1 = min(loff[B3], A.n);
-  const float vmax_in = A.hin->v_max;
-  const float vmax_out = A.hout->v_max;
   const int64_t ng = g.ng, n3 = ng * ng * ng;
-  const int r = g.r;
+  uint32_t bcx, bcy, bcz;  // first cell of the brick
+  key_cell(g, kbase, bcx, bcy, bcz);
+  const int64_t ox = (int64_t)bcx * r, oy = (int64_t)bcy * r, oz = (int64_t)bcz * r;
+  if constexpr (STAGE) {
+    // rows of RS nodes (x) as float4 loads, then the x = RS halo column; node (lz, ly)
+    // of component c is row (c R1 + lz) R1 + ly
+    static_assert(RS % 4 == 0, "staged tile side must be a multiple of 4");
+    constexpr int ROWS = 3 * R1 * R1;
+    constexpr int Q = RS / 4;  // float4 per row
+    const bool wrapx = ox + RS >= ng;
+    for (int i = threadIdx.x; i < ROWS * Q; i += KB) {
+      const int row = i / Q, q = i - row * Q;
+      const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
+      const int lz = rem / R1, ly = rem - lz * R1;
+      int64_t gz = oz + lz, gy = oy + ly;
+      gz -= gz >= ng ? ng : 0;
+      gy -= gy >= ng ? ng : 0;
+      const float4 v = *(const float4*)(A.acc + (int64_t)c * n3 + (gz * ng + gy) * ng + ox + 4 * q);
+      float* d = F + row * R1 + 4 * q;
+      d[0] = v.x;
+      d[1] = v.y;
+      d[2] = v.z;
+      d[3] = v.w;
+    }
+    for (int row = threadIdx.x; row < ROWS; row += KB) {
+      const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
+      const int lz = rem / R1, ly = rem - lz * R1;
+      int64_t gz = oz + lz, gy = oy + ly, gx = wrapx ? 0 : ox + RS;
+      gz -= gz >= ng ? ng : 0;
+      gy -= gy >= ng ? ng : 0;
+      F[row * R1 + RS] = A.acc[(int64_t)c * n3 + (gz * ng + gy) * ng + gx];
+    }
+  }
   const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
-  int jmin = 65536, jmax = -1;
   bool bad = false;
-  for (int64_t base = j0; base < j1; base += KT) {
-    for (int i = threadIdx.x; i < 4 * (B3 + 1); i += KT) wcnt[i] = 0;
-    __syncthreads();
-    const int64_t j = base + threadIdx.x;
-    const bool valid = j < j1;
-    uint32_t digit = 0;
-    uint32_t newkey = 0;
-    if (valid) {
-      // local cell of j: largest l with loff[l] <= j
-      int lo = 0, hi = B3;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (loff[mid] <= j) lo = mid; else hi = mid;
-      }
-      uint32_t cx, cy, cz;
-      key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
-      const uint32_t cell[3] = {cx, cy, cz};
-      uint32_t u[3];
-      int li[3];
-      float f[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        u[a] = (cell[a] << 8) | A.pos[3 * j + a];
-        const int64_t gg = (2 * (int64_t)u[a] + 1) * r;  // 1/512 mesh cells
-        li[a] = (int)(gg >> 9);
-        f[a] = (float)(gg & 511) * (1.0f / 512.0f);
-      }
-      float acc3[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-          for (int dx = 0; dx < 2; ++dx) {
-            float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
-                        (dz ? f[2] : 1.f - f[2]);
-            int64_t nz = li[2] + dz, ny = li[1] + dy, nx = li[0] + dx;
-            nz -= nz >= ng ? ng : 0;
-            ny -= ny >= ng ? ng : 0;
-            nx -= nx >= ng ? ng : 0;
-            const int64_t node = (nz * ng + ny) * ng + nx;
-            acc3[0] += wgt * A.acc[node];
-            acc3[1] += wgt * A.acc[n3 + node];
-            acc3[2] += wgt * A.acc[2 * n3 + node];
-          }
-      uint32_t un[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float v0 = vel_decode(A.vel[3 * j + a], vmax_in);
-        const float v1 = v0 + A.ck * acc3[a];
-        const double d = floor((double)v1 * A.cdS + 0.5);
-        if (!(fabs(d) < 4.0e15)) bad = true;
-        int64_t q = ((int64_t)u[a] + (int64_t)(bad ? 0.0 : d)) % g.S;
-        un[a] = (uint32_t)(q < 0 ? q + g.S : q);
-        const int jc = vel_code(v1, vmax_out);
-        A.tpos[3 * j + a] = (uint8_t)(un[a] & 255u);
-        A.tvel[3 * j + a] = (uint16_t)jc;
-        jmin = min(jmin, jc);
-        jmax = max(jmax, jc);
-      }
-      newkey = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
-      digit = (newkey >= kbase && newkey < kbase + (uint32_t)B3) ? newkey - kbase : (uint32_t)B3;
-    }
-    // stable multi-split of this chunk by digit (new local cell, or B3 for movers)
-    uint64_t match = __ballot(valid);
-    for (int bit = 0; bit < nbits; ++bit) {
-      uint64_t m = __ballot(valid && ((digit >> bit) & 1u));
-      match &= ((digit >> bit) & 1u) ? m : ~m;
-    }
-    const uint32_t rk = (uint32_t)__popcll(match & lt);
-    if (valid && rk == 0) wcnt[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
-    __syncthreads();
-    if (valid) {
-      uint32_t pre = run[digit];
-      for (int q = 0; q < w; ++q) pre += wcnt[q * (B3 + 1) + digit];
-      const uint32_t rank = pre + rk;
-      if (digit < (uint32_t)B3) {
-        if (rank >= RANK_LIMIT) bad = true;
-        A.tdst[j] = (digit << RANK_BITS) | (rank & RANK_LIMIT);
-      } else {
-        A.tdst[j] = MOVER;
-        A.mkey[j0 + rank] = newkey;
-        A.midx[j0 + rank] = (uint32_t)j;
-      }
+  for (int s = 0; s < A.n_sp; ++s) {
+    const KickSpecies& S = A.sp[s];
+    __syncthreads();  // F loaded / previous species done with loff, run
+    for (int i = threadIdx.x; i <= B3; i += KB) {
+      loff[i] = S.off[kbase + i];
+      run[i] = 0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= B3; i += KT) {
-      uint32_t add = 0;
-      for (int q = 0; q < 4; ++q) add += wcnt[q * (B3 + 1) + i];
-      run[i] += add;
+    const int64_t j0 = min(loff[0], S.n), j1 = min(loff[B3], S.n);
+    const float vmax_in = S.hin->v_max;
+    const float vmax_out = S.hout->v_max;
+    int jmin = 65536, jmax = -1;
+    for (int64_t base = j0; base < j1; base += KB) {
+      for (int i = threadIdx.x; i < NW * (B3 + 1); i += KB) wcnt[i] = 0;
+      __syncthreads();
+      const int64_t j = base + threadIdx.x;
+      const bool valid = j < j1;
+      uint32_t digit = 0, newkey = 0;
+      if (valid) {
+        int lo = 0, hi = B3;  // local cell: largest l with loff[l] <= j
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (loff[mid] <= j) lo = mid; else hi = mid;
+        }
+        uint32_t cx, cy, cz;
+        key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
+        const uint32_t cell[3] = {cx, cy, cz};
+        const int64_t org[3] = {ox, oy, oz};
+        uint32_t u[3];
+        int li[3];
+        float f[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          u[a] = (cell[a] << 8) | S.pos[3 * j + a];
+          const int64_t gg = (2 * (int64_t)u[a] + 1) * r;  // 1/512 mesh cells
+          li[a] = (int)((gg >> 9) - org[a]);               // node index inside the brick
+          f[a] = (float)(gg & 511) * (1.0f / 512.0f);
+        }
+        float acc3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+              const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
+                                (dz ? f[2] : 1.f - f[2]);
+              if constexpr (STAGE) {
+                const int node = ((li[2] + dz) * R1 + (li[1] + dy)) * R1 + (li[0] + dx);
+                acc3[0] += wgt * F[node];
+                acc3[1] += wgt * F[R1 * R1 * R1 + node];
+                acc3[2] += wgt * F[2 * R1 * R1 * R1 + node];
+              } else {
+                int64_t nz = oz + li[2] + dz, ny = oy + li[1] + dy, nx = ox + li[0] + dx;
+                nz -= nz >= ng ? ng : 0;
+                ny -= ny >= ng ? ng : 0;
+                nx -= nx >= ng ? ng : 0;
+                const int64_t node = (nz * ng + ny) * ng + nx;
+                acc3[0] += wgt * A.acc[node];
+                acc3[1] += wgt * A.acc[n3 + node];
+                acc3[2] += wgt * A.acc[2 * n3 + node];
+              }
+            }
+        uint32_t un[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float v0 = vel_decode(S.vel[3 * j + a], vmax_in);
+          const float v1 = v0 + A.ck * acc3[a];
+          const double d = floor((double)v1 * A.cdS + 0.5);
+          const bool okd = fabs(d) < 4.0e15;
+          bad |= !okd;
+          int64_t q = ((int64_t)u[a] + (okd ? (int64_t)d : 0)) & (g.S - 1);  // S = 2^k
+          un[a] = (uint32_t)q;
+          const int jc = vel_code(v1, vmax_out);
+          S.tpos[3 * j + a] = (uint8_t)(un[a] & 255u);
+          S.tvel[3 * j + a] = (uint16_t)jc;
+          jmin = min(jmin, jc);
+          jmax = max(jmax, jc);
+        }
+        newkey = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
+        digit = (newkey >= kbase && newkey < kbase + (uint32_t)B3) ? newkey - kbase
+                                                                  : (uint32_t)B3;
+      }
+      // stable multi-split of this chunk by digit (new local cell, or B3 for movers)
+      uint64_t match = __ballot(valid);
+      for (int bit = 0; bit < nbits; ++bit) {
+        uint64_t m = __ballot(valid && ((digit >> bit) & 1u));
+        match &= ((digit >> bit) & 1u) ? m : ~m;
+      }
+      const uint32_t rk = (uint32_t)__popcll(match & lt);
+      if (valid && rk == 0) wcnt[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
+      __syncthreads();
+      if (valid) {
+        uint32_t pre = run[digit];
+        for (int q = 0; q < w; ++q) pre += wcnt[q * (B3 + 1) + digit];
+        const uint32_t rank = pre + rk;
+        if (digit < (uint32_t)B3) {
+          if (rank >= RANK_LIMIT) bad = true;
+          S.tdst[j] = (digit << RANK_BITS) | (rank & RANK_LIMIT);
+        } else {
+          S.tdst[j] = MOVER;
+          S.mkey[j0 + rank] = newkey;
+          S.midx[j0 + rank] = (uint32_t)j;
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i <= B3; i += KB) {
+        uint32_t add = 0;
+        for (int q = 0; q < NW; ++q) add += wcnt[q * (B3 + 1) + i];
+        run[i] += add;
+      }
+      __syncthreads();
+    }
+    for (int i = threadIdx.x; i < B3; i += KB) S.cnt[kbase + i] = (uint64_t)run[i];
+    if (threadIdx.x == 0) S.mcnt[b] = run[B3];
+    // block min / max of the new velocity codes, stored per brick (no atomics)
+    for (int d = 32; d >= 1; d >>= 1) {
+      jmin = min(jmin, __shfl_xor(jmin, d, 64));
+      jmax = max(jmax, __shfl_xor(jmax, d, 64));
+    }
+    if (lane == 0) {
+      wcnt[2 * w] = (uint32_t)jmin;
+      wcnt[2 * w + 1] = (uint32_t)jmax;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < NW; ++q) {
+        jmin = min(jmin, (int)wcnt[2 * q]);
+        jmax = max(jmax, (int)wcnt[2 * q + 1]);
+      }
+      S.pmn[b] = jmin;
+      S.pmx[b] = jmax;
+    }
   }
-  for (int i = threadIdx.x; i < B3; i += KT) A.cnt[kbase + i] = (uint64_t)run[i];
-  if (threadIdx.x == 0) A.mcnt[b] = run[B3];
   if (bad) latch_error(err, ERRBIT_RANGE);
-  for (int d = 32; d >= 1; d >>= 1) {
-    jmin = min(jmin, __shfl_xor(jmin, d, 64));
-    jmax = max(jmax, __shfl_xor(jmax, d, 64));
-  }
-  if (lane == 0) {
-    if (jmin < 65536) atomicMin(&A.hout->j_min, jmin);
-    if (jmax >= 0) atomicMax(&A.hout->j_max, jmax);
-  }
 }
 
 // movers of brick b sit at [off[b B^3], off[b B^3] + mcnt[b]); gather them in old order
@@ -343,25 +418,32 @@ __global__ void k_read_total(const int64_t* moff, int64_t nb, int64_t* out) { *o
 pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
                          const float* acc, double ck, double cd) {
   if (in->n == 0) return PM_OK;
+  ProfScope ps(c, ST_KICK);
   hipLaunchKernelGGL(k_kick_float, dim3((unsigned)cdiv(in->n, KT)), dim3(KT), 0, c->stream,
                      in->x, in->v, out->x, out->v, in->n, acc, c->g.ng, (float)ck, (float)cd);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
 
-// perm (device int64 [n], nullable): new stream position -> old stream position.
-pm_status run_kick_compressed_off(pm_context* c, const pm_species* in, pm_species* out,
-                                  const int64_t* off_in, const float* acc, const float* amax,
-                                  double ck, double cd, int64_t* perm) {
+// All species of a compressed state: one brick kernel launch, then the re-sort of each
+// species. offs[s]: input cell offsets; perm[s] (device int64 [n], nullable): new stream
+// position -> old stream position.
+pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
+                                  int n_sp, int64_t* const* offs, const float* acc,
+                                  const float* amax, double ck, double cd,
+                                  int64_t* const* perm) {
   const Geom& g = c->g;
-  const int64_t n = in->n;
+  if (n_sp <= 0 || n_sp > MAXSP) return PM_ERR_ARG;
   const int B3 = g.B * g.B * g.B;
-  hipLaunchKernelGGL(k_vmax_next, dim3(1), dim3(1), 0, c->stream, in->hdr, out->hdr, amax, ck,
-                     n);
-  PM_LAUNCH_CHECK();
-  uint64_t* cnt = (uint64_t*)scratch(c, SC_CNT, (size_t)g.ncell3 * 8);
+  int64_t ntot = 0, nbase[MAXSP + 1];
+  for (int s = 0; s < n_sp; ++s) {
+    nbase[s] = ntot;
+    ntot += in[s].n;
+  }
+  nbase[n_sp] = ntot;
+  const size_t nn = (size_t)(ntot > 0 ? ntot : 1);
+  uint64_t* cnt = (uint64_t*)scratch(c, SC_CNT, (size_t)g.ncell3 * 8 * n_sp);
   int64_t* off_new = (int64_t*)scratch(c, SC_OFF2, (size_t)(g.ncell3 + 1) * 8);
-  const size_t nn = (size_t)(n > 0 ? n : 1);
   uint8_t* tpos = (uint8_t*)scratch(c, SC_TPOS, nn * 3);
   uint16_t* tvel = (uint16_t*)scratch(c, SC_TVEL, nn * 6);
   uint32_t* tdst = (uint32_t*)scratch(c, SC_TDST, nn * 4);
@@ -369,58 +451,112 @@ pm_status run_kick_compressed_off(pm_context* c, const pm_species* in, pm_specie
   uint32_t* midx = (uint32_t*)scratch(c, SC_VALA, nn * 4);
   uint32_t* skey = (uint32_t*)scratch(c, SC_KEYB, nn * 4);
   uint32_t* sidx = (uint32_t*)scratch(c, SC_VALB, nn * 4);
-  uint32_t* mcnt = (uint32_t*)scratch(c, SC_MCNT, (size_t)g.nbrick * 4);
+  uint32_t* mcnt = (uint32_t*)scratch(c, SC_MCNT, (size_t)g.nbrick * 4 * n_sp);
   int64_t* moff = (int64_t*)scratch(c, SC_MOFF, (size_t)(g.nbrick + 1) * 8);
-  int64_t* nmv = (int64_t*)scratch(c, SC_MISC, 64);
+  int32_t* part = (int32_t*)scratch(c, SC_PARTS, (size_t)g.nbrick * 8 * n_sp);
   if (!cnt || !off_new || !tpos || !tvel || !tdst || !mkey || !midx || !skey || !sidx ||
-      !mcnt || !moff || !nmv)
+      !mcnt || !moff || !part)
     return PM_ERR_NOMEM;
-  KickArgs A{n, in->pos, in->vel, in->hdr, out->hdr, off_in, acc, (float)ck,
-             cd * (double)g.S, tpos, tvel, tdst, cnt, mkey, midx, mcnt};
-  size_t lds = (size_t)(B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * 5;
-  hipLaunchKernelGGL(k_kick_brick, dim3((unsigned)g.nbrick), dim3(KT), lds, c->stream, A, g,
-                     c->err);
-  PM_LAUNCH_CHECK();
-  pm_status s = scan_u32(c, mcnt, g.nbrick, moff);
-  if (s != PM_OK) return s;
-  // the mover count is data dependent: read it back (one small synchronisation)
-  int64_t nm = 0;
-  PM_HIP_CHECK(hipMemcpyAsync(&nm, moff + g.nbrick, 8, hipMemcpyDeviceToHost, c->stream));
-  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
-  if (nm > 0) {
-    hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
-                       off_in, mcnt, moff, B3, mkey, midx, skey, sidx);
-    PM_LAUNCH_CHECK();
-    // stable sort (old order preserved inside each new cell)
-    uint32_t *k1 = skey, *v1 = sidx, *k2 = mkey, *v2 = midx;
-    s = radix_sort_pairs(c, &k1, &v1, &k2, &v2, nm, 3 * (g.lgB + g.lgnb));
-    if (s != PM_OK) return s;
-    skey = k1;
-    sidx = v1;
-    hipLaunchKernelGGL(k_arrivals, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream, skey,
-                       sidx, nm, off_in, B3, cnt);
-    PM_LAUNCH_CHECK();
+  KickArgs A{};
+  A.n_sp = n_sp;
+  A.acc = acc;
+  A.ck = (float)ck;
+  A.cdS = cd * (double)g.S;
+  for (int s = 0; s < n_sp; ++s) {
+    KickSpecies& S = A.sp[s];
+    S.n = in[s].n;
+    S.pos = in[s].pos;
+    S.vel = in[s].vel;
+    S.hin = in[s].hdr;
+    S.hout = out[s].hdr;
+    S.off = offs[s];
+    S.tpos = tpos + 3 * nbase[s];
+    S.tvel = tvel + 3 * nbase[s];
+    S.tdst = tdst + nbase[s];
+    S.cnt = cnt + (int64_t)s * g.ncell3;
+    S.mkey = mkey + nbase[s];
+    S.midx = midx + nbase[s];
+    S.mcnt = mcnt + (int64_t)s * g.nbrick;
+    S.pmn = part + (int64_t)2 * s * g.nbrick;
+    S.pmx = S.pmn + g.nbrick;
   }
-  s = scan_u64lo(c, cnt, g.ncell3, off_new);
-  if (s != PM_OK) return s;
-  hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream, off_in,
-                     tdst, tpos, tvel, cnt, off_new, B3, out->pos, out->vel, perm, n, c->err);
-  PM_LAUNCH_CHECK();
-  if (nm > 0) {
-    hipLaunchKernelGGL(k_place_movers, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream,
-                       skey, sidx, nm, tpos, tvel, cnt, off_new, out->pos, out->vel, perm, n,
-                       c->err);
+  {
+    ProfScope ps(c, ST_KICK);
+    pm_status st0;
+    for (int s = 0; s < n_sp; ++s)
+      hipLaunchKernelGGL(k_vmax_next, dim3(1), dim3(1), 0, c->stream, in[s].hdr, out[s].hdr,
+                         amax, ck, in[s].n);
+    const int R1 = g.B * g.r + 1;
+    const size_t fbytes = (size_t)3 * R1 * R1 * R1 * 4;
+    const size_t tail = (size_t)(B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + KB / 64);
+    const int R = g.B * g.r;
+    if (R == 16 && fbytes + tail <= 96 * 1024)
+      hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB),
+                         ((fbytes + 7) / 8) * 8 + tail, c->stream, A, g, c->err);
+    else if (R == 8)
+      hipLaunchKernelGGL(k_kick_brick<8>, dim3((unsigned)g.nbrick), dim3(KB),
+                         ((fbytes + 7) / 8) * 8 + tail, c->stream, A, g, c->err);
+    else
+      hipLaunchKernelGGL(k_kick_brick<0>, dim3((unsigned)g.nbrick), dim3(KB), tail,
+                         c->stream, A, g, c->err);
     PM_LAUNCH_CHECK();
+    for (int s = 0; s < n_sp; ++s)
+      if ((st0 = fold_minmax_to_header(c, A.sp[s].pmn, A.sp[s].pmx, g.nbrick, out[s].hdr)) !=
+          PM_OK)
+        return st0;
   }
-  return run_finalize_counts(c, nullptr, cnt, out);
+  for (int s = 0; s < n_sp; ++s) {
+    const int64_t n = in[s].n;
+    const KickSpecies& S = A.sp[s];
+    ProfScope ps(c, ST_RESORT);
+    pm_status st = scan_u32(c, S.mcnt, g.nbrick, moff);
+    if (st != PM_OK) return st;
+    // the mover count is data dependent: read it back (one small synchronisation)
+    int64_t nm = 0;
+    PM_HIP_CHECK(hipMemcpyAsync(&nm, moff + g.nbrick, 8, hipMemcpyDeviceToHost, c->stream));
+    PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    uint32_t* sk = skey + nbase[s];
+    uint32_t* si = sidx + nbase[s];
+    if (nm > 0) {
+      hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
+                         S.off, S.mcnt, moff, B3, S.mkey, S.midx, sk, si);
+      PM_LAUNCH_CHECK();
+      // stable sort (old order preserved inside each new cell)
+      uint32_t *k1 = sk, *v1 = si, *k2 = S.mkey, *v2 = S.midx;
+      st = radix_sort_pairs(c, &k1, &v1, &k2, &v2, nm, 3 * (g.lgB + g.lgnb));
+      if (st != PM_OK) return st;
+      sk = k1;
+      si = v1;
+      hipLaunchKernelGGL(k_arrivals, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream, sk,
+                         si, nm, S.off, B3, S.cnt);
+      PM_LAUNCH_CHECK();
+    }
+    st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
+    if (st != PM_OK) return st;
+    int64_t* pm = perm ? perm[s] : nullptr;
+    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
+                       S.off, S.tdst, S.tpos, S.tvel, S.cnt, off_new, B3, out[s].pos,
+                       out[s].vel, pm, n, c->err);
+    PM_LAUNCH_CHECK();
+    if (nm > 0) {
+      hipLaunchKernelGGL(k_place_movers, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream,
+                         sk, si, nm, S.tpos, S.tvel, S.cnt, off_new, out[s].pos, out[s].vel,
+                         pm, n, c->err);
+      PM_LAUNCH_CHECK();
+    }
+    st = run_finalize_counts(c, nullptr, S.cnt, &out[s]);
+    if (st != PM_OK) return st;
+  }
+  return PM_OK;
 }
 
 pm_status run_kick_compressed(pm_context* c, const pm_species* in, pm_species* out,
                               const float* acc, const float* amax, double ck, double cd,
                               uint32_t* /*unused*/) {
-  int64_t* off = (int64_t*)scratch(c, SC_OFF, (size_t)(c->g.ncell3 + 1) * 8);
+  int64_t* off = (int64_t*)scratch(c, SC_SPOFF0, (size_t)(c->g.ncell3 + 1) * 8);
   if (!off) return PM_ERR_NOMEM;
   pm_status s = run_cell_offsets(c, in, off);
   if (s != PM_OK) return s;
-  return run_kick_compressed_off(c, in, out, off, acc, amax, ck, cd, nullptr);
+  int64_t* offs[1] = {off};
+  return run_kick_compressed_all(c, in, out, 1, offs, acc, amax, ck, cd, nullptr);
 }

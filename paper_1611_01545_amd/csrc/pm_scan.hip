@@ -81,7 +81,61 @@ __global__ void k_iota(int64_t* p, int64_t n) {
   if (i < n) p[i] = i;
 }
 
+__global__ __launch_bounds__(1024) void k_fold_minmax(const int32_t* mn, const int32_t* mx,
+                                                      int64_t n, pm_shdr* h) {
+  __shared__ int smn[16], smx[16];
+  int a = 65536, b = -1;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    a = min(a, mn[i]);
+    b = max(b, mx[i]);
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    a = min(a, __shfl_xor(a, d, 64));
+    b = max(b, __shfl_xor(b, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smn[threadIdx.x >> 6] = a;
+    smx[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 16; ++q) {
+      a = min(a, smn[q]);
+      b = max(b, smx[q]);
+    }
+    h->j_min = a;
+    h->j_max = b;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_fold_max(const uint32_t* part, int64_t n,
+                                                   uint32_t* out) {
+  __shared__ uint32_t sm[16];
+  uint32_t a = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) a = max(a, part[i]);
+  for (int d = 32; d >= 1; d >>= 1) a = max(a, (uint32_t)__shfl_xor((int)a, d, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 16; ++q) a = max(a, sm[q]);
+    *out = a;
+  }
+}
+
 }  // namespace
+
+pm_status fold_minmax_to_header(pm_context* c, const int32_t* mn, const int32_t* mx,
+                                int64_t n, pm_shdr* hdr) {
+  hipLaunchKernelGGL(k_fold_minmax, dim3(1), dim3(1024), 0, c->stream, mn, mx, n, hdr);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+pm_status fold_max_u32(pm_context* c, const uint32_t* part, int64_t n, uint32_t* out) {
+  hipLaunchKernelGGL(k_fold_max, dim3(1), dim3(1024), 0, c->stream, part, n, out);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
 
 pm_status run_iota(pm_context* c, int64_t* p, int64_t n) {
   if (n <= 0) return PM_OK;

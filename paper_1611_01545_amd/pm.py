@@ -275,6 +275,19 @@ class PMContext:
         out.mass = mass.value
         return out, sid.value
 
+    STAGES = ["cell_offsets", "deposit", "fft_x_r2c", "fft_y_fwd", "fft_z_fused",
+              "fft_y_inv", "fft_x_c2r", "interp_kick_drift", "resort", "codec", "adjoint"]
+
+    def profile(self, enable: bool = True):
+        check(self.lib.pm_profile(self.h, 1 if enable else 0), "pm_profile")
+
+    def profile_read(self) -> dict:
+        k = len(self.STAGES)
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int64 * k)()
+        check(self.lib.pm_profile_read(self.h, ms, cnt, k), "pm_profile_read")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(self.STAGES)}
+
     def kernel_table(self) -> torch.Tensor:
         m = self.n_mesh // 2
         t = torch.empty(3 * m * m + 1, dtype=torch.float32, device=self.device)
