@@ -189,7 +189,9 @@ def test_inverse_square_far_from_softening():
     n = 64
     rng = np.random.default_rng(7)
     src = rng.random(3)
-    for rc in (8.0, 12.0, 16.0):
+    # the CIC mesh force is anisotropic at ~1% eight cells from the source, and the
+    # error falls with distance (tolerances per distance)
+    for rc, tol in ((8.0, 0.02), (12.0, 0.01), (16.0, 0.005)):
         dirs = rng.standard_normal((12, 3))
         dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
         xt = np.mod(src + dirs * rc / n, 1.0)
@@ -207,7 +209,7 @@ def test_inverse_square_far_from_softening():
             ref = ref * rr ** 3 / (rr * rr + eps * eps) ** 1.5
             errs.append(np.linalg.norm(ai[p] - ref) / np.linalg.norm(ref))
         rms = np.sqrt(np.mean(np.square(errs)))
-        assert rms < 0.01, (rc, rms)
+        assert rms < tol, (rc, rms)
 
 
 # -------------------------------------------------------- Zel'dovich plane wave --
