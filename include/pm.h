@@ -226,7 +226,7 @@ pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species
  * pm_profile_read synchronises and returns, for stage ids 0..cap-1, the summed
  * milliseconds and the number of timed launches:
  *   0 cell offsets   1 deposit          2 FFT x r2c     3 FFT y forward
- *   4 FFT z fused    5 FFT y inverse    6 FFT x c2r     7 interpolate-kick-drift
+ *   4 FFT z sweeps   5 FFT y inverse    6 FFT x c2r     7 interpolate-kick-drift
  *   8 re-sort        9 encode/decode   10 adjoint scatter/gather */
 pm_status pm_profile(pm_ctx ctx, int enable);
 pm_status pm_profile_read(pm_ctx ctx, double* ms, int64_t* launches, int cap);

@@ -2,14 +2,14 @@
 //
 // The paper transforms each tile with three threaded 1-D FFTW calls, one per
 // dimension (Sec. 2.3). Here every axis pass is one HBM pass over the mesh, and the
-// passes are fused so that the four transforms of a step (one forward, three
-// inverse) cost 10 launches moving 88 n^3 bytes instead of 12 passes moving 96 n^3:
-//   X  r2c      rho(x) -> rho~(kx)                     rows, in place, Nyquist column
-//                                                      kx = n/2 kept in a side plane
+// kernel multiply and gradient factors are fused into the passes; the four transforms
+// of a step (one forward, three inverse) take these sweeps:
+//   X  r2c      rho(x) -> rho~(kx)                     rows, Nyquist column kx = n/2
+//                                                      kept in a side plane
 //   Y  fwd      -> rho~(kx, ky)                        columns, in place
-//   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table) and the
-//               gradient factor, inverse z FFT: T2 = IFFT_z(-i k_z G rho~), then in
-//               place T1 = IFFT_z(G rho~) (one output per launch: two launches)
+//   Z           two-level z transform (N = N1 N2): outer DFT; inner DFT, multiply by
+//               G(|k|^2) (softened kernel table), inverse inner DFT with two outputs
+//               T1 = G rho~ and T2 = -i k_z G rho~; outer inverse DFT of T1 and T2
 //   Y  inv      U2 = IFFT_y(-i k_y T1), then in place U1 = IFFT_y(T1), U3 = IFFT_y(T2)
 //   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
 //               max |a| for the velocity bound of the re-encode
@@ -147,14 +147,18 @@ __device__ __forceinline__ void nat_to_tr(float2 (&a)[Plan<N>::E], int t, float*
                                           const float2* __restrict__ tw, int tws,
                                           int twmask) {
   using P = Plan<N>;
+  // scheduling fences: without them the fully unrolled passes hoist every twiddle load
+  // of the kernel to its start and run out of registers
+  __builtin_amdgcn_sched_barrier(0);
   dft_reg<P::E, SIGN>(a);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k1 = 1; k1 < P::E; ++k1) {
     float2 w = tw[((t * k1) * tws) & twmask];
     a[k1] = (SIGN < 0) ? cmul(a[k1], w) : cmulc(a[k1], w);
   }
-  // exchange real parts, then imaginary parts (halves the LDS footprint)
-  float2 b[P::E];
+  // exchange real parts, then imaginary parts (halves the LDS footprint); the array is
+  // reused in place: a part is dead once it is in LDS
 #pragma unroll
   for (int part = 0; part < 2; ++part) {
 #pragma unroll
@@ -165,14 +169,12 @@ __device__ __forceinline__ void nat_to_tr(float2 (&a)[Plan<N>::E], int t, float*
 #pragma unroll
       for (int k2 = 0; k2 < P::T; ++k2) {
         float q = lds[(t + P::T * v) * P::TP + k2];
-        if (part) b[v * P::T + k2].y = q; else b[v * P::T + k2].x = q;
+        if (part) a[v * P::T + k2].y = q; else a[v * P::T + k2].x = q;
       }
     __syncthreads();
   }
 #pragma unroll
-  for (int v = 0; v < P::V; ++v) dft_reg<P::T, SIGN>(&b[v * P::T]);
-#pragma unroll
-  for (int i = 0; i < P::E; ++i) a[i] = b[i];
+  for (int v = 0; v < P::V; ++v) dft_reg<P::T, SIGN>(&a[v * P::T]);
 }
 
 // tr_to_nat: N-point DFT (SIGN) of a line held in transposed layout, result in natural
@@ -182,9 +184,11 @@ __device__ __forceinline__ void tr_to_nat(float2 (&b)[Plan<N>::E], int t, float*
                                           const float2* __restrict__ tw, int tws,
                                           int twmask) {
   using P = Plan<N>;
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int v = 0; v < P::V; ++v) {
     dft_reg<P::T, SIGN>(&b[v * P::T]);
+    __builtin_amdgcn_sched_barrier(0);
     const int k1 = t + P::T * v;
 #pragma unroll
     for (int n1 = 1; n1 < P::T; ++n1) {
@@ -192,7 +196,6 @@ __device__ __forceinline__ void tr_to_nat(float2 (&b)[Plan<N>::E], int t, float*
       b[v * P::T + n1] = (SIGN < 0) ? cmul(b[v * P::T + n1], w) : cmulc(b[v * P::T + n1], w);
     }
   }
-  float2 a[P::E];
 #pragma unroll
   for (int part = 0; part < 2; ++part) {
 #pragma unroll
@@ -206,13 +209,11 @@ __device__ __forceinline__ void tr_to_nat(float2 (&b)[Plan<N>::E], int t, float*
 #pragma unroll
     for (int k1 = 0; k1 < P::E; ++k1) {
       float q = lds[k1 * P::TP + t];
-      if (part) a[k1].y = q; else a[k1].x = q;
+      if (part) b[k1].y = q; else b[k1].x = q;
     }
     __syncthreads();
   }
-  dft_reg<P::E, SIGN>(a);
-#pragma unroll
-  for (int i = 0; i < P::E; ++i) b[i] = a[i];
+  dft_reg<P::E, SIGN>(b);
 }
 
 // ------------------------------------------------------------- column passes --
@@ -249,15 +250,14 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
   using P = Plan<N>;
   constexpr int CS = col_cs<W>(P::E * P::TP);
   __shared__ float lds[W * CS];
+  // the grid covers the lines exactly (W divides the line count; checked on the host)
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int64_t l1 = (int64_t)blockIdx.x * W + c;
-  const bool ok = l1 < d.L1;
   const int64_t base = l1 * d.s1 + (int64_t)blockIdx.y * d.s2;
   float* my = lds + c * CS;
   float2 a[P::E];
 #pragma unroll
-  for (int n1 = 0; n1 < P::E; ++n1)
-    a[n1] = ok ? in[base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
+  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = in[base + (int64_t)(t + P::T * n1) * d.es];
   if constexpr (TWO) {
     // the second output transforms -i k (x + i y) = k y - i k x; k is the line's own
     // wave number
@@ -269,101 +269,141 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
     out0 = out1;
   }
   nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
-  if (ok) {
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+  for (int v = 0; v < P::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2)
-        out0[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = a[v * P::T + k2];
-  }
+    for (int k2 = 0; k2 < P::T; ++k2)
+      out0[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = a[v * P::T + k2];
 }
 
-// Fused z pass, F = FFT(in0): MODE 0: out0 = IFFT(G F); MODE 2: out0 = IFFT(-i k_z G F);
-// MODE 1 (adjoint): out0 = IFFT(G sum_a (+i k_a) FFT(in_a)). One output per launch keeps
-// a single line array in registers.
-template <int N, int W, int MODE>
-__global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
-    const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
-    Lines d, const float2* __restrict__ tw, int tws, int twmask, int n,
-    const float* __restrict__ ktab) {
-  using P = Plan<N>;
-  constexpr int CS = col_cs<W>(P::E * P::TP);
-  __shared__ float lds[W * CS];
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int64_t l1 = (int64_t)blockIdx.x * W + c;
-  const bool ok = l1 < d.L1;
-  const int64_t base = l1 * d.s1 + (int64_t)blockIdx.y * d.s2;
-  float* my = lds + c * CS;
-  const int kx = d.kx_mode ? d.kx_fixed : (int)l1;
-  const int ky = d.ky_mode ? (int)l1 : (int)blockIdx.y;
+// ------------------------------------------------------------- z passes --
+// The z transform (stride n * n/2 complex between z points) is split N = N1 N2 so that a
+// workgroup touches only N1 or N2 z-planes (a handful of address translations instead
+// of one per point) and every access is a run of consecutive kx:
+//   ZA  fixed slot s < N2: the N1 points z = N2 m + s, DFT over m, twiddle
+//       exp(-2 pi i s k1 / N), stored back at z = N2 k1 + s                (in place)
+//   ZB  fixed k1 < N1: the N2 consecutive points z = N2 k1 + s, DFT over s gives
+//       X[k1 + N1 j]; multiply by the kernel (and the gradient factor), inverse DFT over
+//       j, twiddle exp(+2 pi i s' k1 / N), store at z = N2 k1 + s'
+//   ZC  fixed slot s' < N2: inverse DFT over k1 of the N1 points z = N2 k1 + s', stored
+//       at z = N2 m' + s' (natural order)                                  (in place)
+// Each thread owns one (kx, y) position and keeps its N1 or N2 points in registers.
+template <int N>
+struct ZPlan {
+  static constexpr int LG = ilog2(N);
+  static constexpr int N2 = 1 << (LG / 2);  // consecutive planes (inner length)
+  static constexpr int N1 = N / N2;         // strided planes (outer length)
+};
+
+// Geometry of one z sweep: lanes (unit stride: kx, or y on the Nyquist plane) and rows
+// (y, or a single row on the Nyquist plane).
+struct ZGeom {
+  int64_t s_row, s_plane;  // complex strides between rows and between z planes
+  int nyq;                 // 1: the Nyquist plane kx = n/2, lanes are y
+};
+
+__device__ __forceinline__ int64_t zpos(const ZGeom& g, int& kx, int& ky, int n) {
+  const int lane = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y * blockDim.y + threadIdx.y;
+  kx = g.nyq ? n / 2 : lane;
+  ky = g.nyq ? lane : row;
+  return lane + (int64_t)row * g.s_row;
+}
+
+// ZA (SIGN -1, with the twiddle) and ZC (SIGN +1, no twiddle). blockIdx.z is the slot.
+template <int N, int SIGN>
+__global__ __launch_bounds__(256) void k_zouter(const float2* in, float2* out, ZGeom g,
+                                                const float2* __restrict__ tw, int n) {
+  using Z = ZPlan<N>;
+  int kx, ky;
+  const int s = blockIdx.z;
+  const int64_t off = zpos(g, kx, ky, n) + (int64_t)s * g.s_plane;
+  float2 a[Z::N1];
+#pragma unroll
+  for (int m = 0; m < Z::N1; ++m) a[m] = in[off + (int64_t)(Z::N2 * m) * g.s_plane];
+  dft_reg<Z::N1, SIGN>(a);
+  if constexpr (SIGN < 0) {
+#pragma unroll
+    for (int k = 1; k < Z::N1; ++k) a[k] = cmul(a[k], tw[s * k]);
+  }
+#pragma unroll
+  for (int m = 0; m < Z::N1; ++m) out[off + (int64_t)(Z::N2 * m) * g.s_plane] = a[m];
+}
+
+// ZB. MODE 0 (force): out0 = G X, out1 = -i k_z G X (out0 may alias in0).
+// MODE 1 (transpose of the force): out0 = G sum_a (+i k_a) X_a over in0..in2.
+// blockIdx.z is the outer frequency k1.
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_zinner(const float2* in0, const float2* in1,
+                                                const float2* in2, float2* out0,
+                                                float2* out1, ZGeom g,
+                                                const float2* __restrict__ tw, int n,
+                                                const float* __restrict__ ktab) {
+  using Z = ZPlan<N>;
+  int kx, ky;
+  const int k1 = blockIdx.z;
+  const int64_t off = zpos(g, kx, ky, n) + (int64_t)(Z::N2 * k1) * g.s_plane;
   const int sx = signed_k(kx, n), sy = signed_k(ky, n);
   const int nxy2 = sx * sx + sy * sy;
-  float2 acc[P::E];
-  if constexpr (MODE == 0 || MODE == 2) {
+  float2 acc[Z::N2];
+  if constexpr (MODE == 0) {
+    float2 gz[Z::N2];
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1)
-      acc[n1] = ok ? in0[base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
-    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+    for (int j = 0; j < Z::N2; ++j) acc[j] = in0[off + (int64_t)j * g.s_plane];
+    dft_reg<Z::N2, -1>(acc);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int j = 0; j < Z::N2; ++j) {
+      const int kz = k1 + Z::N1 * j;
+      const int sz = signed_k(kz, n);
+      const float G = ktab[nxy2 + sz * sz];
+      const float2 f = make_float2(G * acc[j].x, G * acc[j].y);
+      const float kk = grad_k(kz, n);
+      acc[j] = f;
+      gz[j] = make_float2(kk * f.y, -kk * f.x);  // -i k_z (x + i y) = k_z y - i k_z x
+    }
+    dft_reg<Z::N2, +1>(acc);
+    dft_reg<Z::N2, +1>(gz);
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const int kz = (t + P::T * v) + P::E * k2;
-        const int sz = signed_k(kz, n);
-        float G = ktab[nxy2 + sz * sz];
-        float2 f = acc[v * P::T + k2];
-        if constexpr (MODE == 2) {
-          // -i k_z G (x + i y) = k_z G y - i k_z G x
-          const float kk = grad_k(kz, n) * G;
-          acc[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
-        } else {
-          acc[v * P::T + k2] = make_float2(G * f.x, G * f.y);
-        }
-      }
-    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
-    if (ok) {
+    for (int j = 1; j < Z::N2; ++j) {
+      const float2 w = tw[j * k1];
+      acc[j] = cmulc(acc[j], w);
+      gz[j] = cmulc(gz[j], w);
+    }
 #pragma unroll
-      for (int n1 = 0; n1 < P::E; ++n1) out0[base + (int64_t)(t + P::T * n1) * d.es] = acc[n1];
+    for (int j = 0; j < Z::N2; ++j) {
+      out0[off + (int64_t)j * g.s_plane] = acc[j];
+      out1[off + (int64_t)j * g.s_plane] = gz[j];
     }
   } else {
     const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
 #pragma unroll
-    for (int i = 0; i < P::E; ++i) acc[i] = make_float2(0.f, 0.f);
+    for (int j = 0; j < Z::N2; ++j) acc[j] = make_float2(0.f, 0.f);
     const float2* ins[3] = {in0, in1, in2};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      float2 f[P::E];
+      float2 f[Z::N2];
 #pragma unroll
-      for (int n1 = 0; n1 < P::E; ++n1)
-        f[n1] = ok ? ins[ax][base + (int64_t)(t + P::T * n1) * d.es] : make_float2(0.f, 0.f);
-      nat_to_tr<N, -1>(f, t, my, tw, tws, twmask);
+      for (int j = 0; j < Z::N2; ++j) f[j] = ins[ax][off + (int64_t)j * g.s_plane];
+      dft_reg<Z::N2, -1>(f);
 #pragma unroll
-      for (int v = 0; v < P::V; ++v)
-#pragma unroll
-        for (int k2 = 0; k2 < P::T; ++k2) {
-          const int kz = (t + P::T * v) + P::E * k2;
-          const float k = ax == 0 ? kxg : ax == 1 ? kyg : grad_k(kz, n);
-          float2 q = f[v * P::T + k2];
-          // + i k (x + i y) = -k y + i k x
-          acc[v * P::T + k2].x += -k * q.y;
-          acc[v * P::T + k2].y += k * q.x;
-        }
-    }
-#pragma unroll
-    for (int v = 0; v < P::V; ++v)
-#pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const int kz = (t + P::T * v) + P::E * k2;
-        const int sz = signed_k(kz, n);
-        const float G = ktab[nxy2 + sz * sz];
-        acc[v * P::T + k2].x *= G;
-        acc[v * P::T + k2].y *= G;
+      for (int j = 0; j < Z::N2; ++j) {
+        const float k = ax == 0 ? kxg : ax == 1 ? kyg : grad_k(k1 + Z::N1 * j, n);
+        acc[j].x += -k * f[j].y;  // + i k (x + i y) = -k y + i k x
+        acc[j].y += k * f[j].x;
       }
-    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
-    if (ok) {
-#pragma unroll
-      for (int n1 = 0; n1 < P::E; ++n1) out0[base + (int64_t)(t + P::T * n1) * d.es] = acc[n1];
     }
+#pragma unroll
+    for (int j = 0; j < Z::N2; ++j) {
+      const int sz = signed_k(k1 + Z::N1 * j, n);
+      const float G = ktab[nxy2 + sz * sz];
+      acc[j].x *= G;
+      acc[j].y *= G;
+    }
+    dft_reg<Z::N2, +1>(acc);
+#pragma unroll
+    for (int j = 1; j < Z::N2; ++j) acc[j] = cmulc(acc[j], tw[j * k1]);
+#pragma unroll
+    for (int j = 0; j < Z::N2; ++j) out0[off + (int64_t)j * g.s_plane] = acc[j];
   }
 }
 
@@ -397,14 +437,14 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
   constexpr int R = rows_per_wg<M>();
   constexpr int LF = row_lds_floats<M>();
   __shared__ float lds[R * LF];
+  // R divides the row count (checked on the host): no bounds guards
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
   const int64_t row = (int64_t)blockIdx.x * R + rr;
-  const bool ok = row < nrows;
   float* my = lds + rr * LF;
   const float2* zin = (const float2*)(in + row * 2 * M);
   float2 a[P::E];
 #pragma unroll
-  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = ok ? zin[t + P::T * n1] : make_float2(0.f, 0.f);
+  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = zin[t + P::T * n1];
   // M-point DFT: tw table is for n = 2M points, stride 2
   nat_to_tr<M, -1>(a, t, my, tw, 2, twmask);
   // stage Z in natural order
@@ -427,9 +467,9 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
     float2 wb = cmul(w, B);
     float2 X = make_float2(A.x + wb.x, A.y + wb.y);
     if (k == 0) X = make_float2(zk.x + zk.y, 0.f);
-    if (ok) o[k] = X;
+    o[k] = X;
   }
-  if (ok && t == 0) nyq[row] = make_float2(zs[0].x - zs[0].y, 0.f);
+  if (t == 0) nyq[row] = make_float2(zs[0].x - zs[0].y, 0.f);
 }
 
 // X c2r: in main rows (M complex) + nyq[row] -> out real rows; optional -i k_x factor;
@@ -444,7 +484,6 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   __shared__ float lds[R * LF];
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
   const int64_t row = (int64_t)blockIdx.x * R + rr;
-  const bool ok = row < nrows;
   float* my = lds + rr * LF;
   float2* xs = (float2*)my;
   const float2* xi = in + row * M;
@@ -452,7 +491,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
 #pragma unroll
   for (int j = 0; j < P::E; ++j) {
     const int k = t + P::T * j;
-    float2 X = ok ? xi[k] : make_float2(0.f, 0.f);
+    float2 X = xi[k];
     if (grad) {
       float kk = grad_k(k, n);
       X = make_float2(kk * X.y, -kk * X.x);
@@ -460,7 +499,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
     xs[k] = X;
   }
   if (t == 0) {
-    float2 X = ok ? nyq[row] : make_float2(0.f, 0.f);
+    const float2 X = nyq[row];
     xs[M] = grad ? make_float2(0.f, 0.f) : X;  // -i k_x is zero on the Nyquist index
   }
   __syncthreads();
@@ -484,7 +523,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
 #pragma unroll
     for (int k2 = 0; k2 < P::T; ++k2) {
       float2 z = a[v * P::T + k2];
-      if (ok) zo[(t + P::T * v) + P::E * k2] = z;
+      zo[(t + P::T * v) + P::E * k2] = z;
       m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
     }
   if (amax) {
@@ -532,10 +571,13 @@ __global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, dou
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 // ------------------------------------------------------------------ dispatch --
+// columns per workgroup: at most 16, at most half the line length (the number of kx
+// lines is N/2, so W always divides the line count), and the LDS exchange <= 64 KB
 template <int N>
 constexpr int col_w() {
   int w = 16384 / N;
   if (w > 16) w = 16;
+  if (w > N / 2) w = N / 2;
   if (w < 1) w = 1;
   return w;
 }
@@ -550,7 +592,8 @@ template <int N>
 pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, const Lines& d,
                   int64_t L2, int sign) {
   constexpr int W = col_w<N>();
-  dim3 grid((unsigned)cdiv(d.L1, W), (unsigned)L2);
+  if (d.L1 % W) return PM_ERR_SHAPE;
+  dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
   dim3 block(W * Plan<N>::T);
   if (sign < 0) {
     if (o1)
@@ -571,21 +614,45 @@ pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, con
   return PM_OK;
 }
 
+// z sweep launch shape: 64 consecutive lanes per wave (a 512-byte run per plane), the
+// rest of the 256 threads on adjacent rows; lanes and rows are powers of two, so the
+// grid covers them exactly.
+struct ZLaunch {
+  dim3 block, grid;
+};
+ZLaunch zlaunch(int64_t lanes, int64_t rows, int slots) {
+  int lx = (int)(lanes < 64 ? lanes : 64);
+  int64_t ly = 256 / lx;
+  if (ly > rows) ly = rows;
+  return ZLaunch{dim3(lx, (unsigned)ly), dim3((unsigned)(lanes / lx), (unsigned)(rows / ly),
+                                             (unsigned)slots)};
+}
+
 template <int N>
-pm_status col_zconv(const FftCtx& f, int mode, const float2* i0, const float2* i1,
-                    const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
-  constexpr int W = col_w<N>();
-  dim3 grid((unsigned)cdiv(d.L1, W), (unsigned)L2);
-  dim3 block(W * Plan<N>::T);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_col_zconv<N, W, 0>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
-                       o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
-  else if (mode == 2)
-    hipLaunchKernelGGL((k_col_zconv<N, W, 2>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
-                       o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
+pm_status z_outer(const FftCtx& f, int sign, const float2* in, float2* out, const ZGeom& g,
+                  int64_t lanes, int64_t rows) {
+  ZLaunch L = zlaunch(lanes, rows, ZPlan<N>::N2);
+  if (sign < 0)
+    hipLaunchKernelGGL((k_zouter<N, -1>), L.grid, L.block, 0, f.c->stream, in, out, g,
+                       f.c->tw, f.n);
   else
-    hipLaunchKernelGGL((k_col_zconv<N, W, 1>), grid, block, 0, f.c->stream, i0, i1, i2, o0,
-                       o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab);
+    hipLaunchKernelGGL((k_zouter<N, 1>), L.grid, L.block, 0, f.c->stream, in, out, g, f.c->tw,
+                       f.n);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+template <int N>
+pm_status z_inner(const FftCtx& f, int mode, const float2* i0, const float2* i1,
+                  const float2* i2, float2* o0, float2* o1, const ZGeom& g, int64_t lanes,
+                  int64_t rows) {
+  ZLaunch L = zlaunch(lanes, rows, ZPlan<N>::N1);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_zinner<N, 0>), L.grid, L.block, 0, f.c->stream, i0, i1, i2, o0, o1,
+                       g, f.c->tw, f.n, f.c->ktab);
+  else
+    hipLaunchKernelGGL((k_zinner<N, 1>), L.grid, L.block, 0, f.c->stream, i0, i1, i2, o0, o1,
+                       g, f.c->tw, f.n, f.c->ktab);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -594,6 +661,7 @@ template <int M>
 pm_status row_r2c(const FftCtx& f, const float* in, float2* out, float2* nyq) {
   constexpr int R = rows_per_wg<M>();
   int64_t nrows = (int64_t)f.n * f.n;
+  if (nrows % R) return PM_ERR_SHAPE;
   hipLaunchKernelGGL(k_row_r2c<M>, dim3((unsigned)cdiv(nrows, R)), dim3(R * Plan<M>::T), 0,
                      f.c->stream, in, out, nyq, nrows, f.c->tw, f.twmask);
   PM_LAUNCH_CHECK();
@@ -605,6 +673,7 @@ pm_status row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* o
                   unsigned int* amax) {
   constexpr int R = rows_per_wg<M>();
   int64_t nrows = (int64_t)f.n * f.n;
+  if (nrows % R) return PM_ERR_SHAPE;
   hipLaunchKernelGGL(k_row_c2r<M>, dim3((unsigned)cdiv(nrows, R)), dim3(R * Plan<M>::T), 0,
                      f.c->stream, in, nyq, out, nrows, grad, f.c->tw, f.twmask, amax);
   PM_LAUNCH_CHECK();
@@ -624,11 +693,22 @@ pm_status d_col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, c
   }
   return PM_ERR_SHAPE;
 }
-pm_status d_col_zconv(const FftCtx& f, int mode, const float2* i0, const float2* i1,
-                      const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
+pm_status d_z_outer(const FftCtx& f, int sign, const float2* in, float2* out, const ZGeom& g,
+                    int64_t lanes, int64_t rows) {
   switch (f.n) {
 #define CASE(N) \
-  case N: return col_zconv<N>(f, mode, i0, i1, i2, o0, o1, d, L2);
+  case N: return z_outer<N>(f, sign, in, out, g, lanes, rows);
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return PM_ERR_SHAPE;
+}
+pm_status d_z_inner(const FftCtx& f, int mode, const float2* i0, const float2* i1,
+                    const float2* i2, float2* o0, float2* o1, const ZGeom& g, int64_t lanes,
+                    int64_t rows) {
+  switch (f.n) {
+#define CASE(N) \
+  case N: return z_inner<N>(f, mode, i0, i1, i2, o0, o1, g, lanes, rows);
     PM_FFT_SIZES(CASE)
 #undef CASE
   }
@@ -673,13 +753,17 @@ Lines lines_y_main(int n) {  // l1 = kx, l2 = z, element = y
 Lines lines_y_nyq(int n) {  // l1 = z, element = y
   return Lines{n, 0, 1, n, 1, 1, n / 2};
 }
-Lines lines_z_main(int n) {  // l1 = kx, l2 = y, element = z
+// z sweeps over the main half spectrum (lanes kx < n/2, rows y) and the Nyquist plane
+// (lanes y).
+struct ZSweep {
+  ZGeom g;
+  int64_t lanes, rows;
+};
+ZSweep z_main(int n) {
   int64_t M = n / 2;
-  return Lines{1, M, (int64_t)n * M, M, 0, 0, 0};
+  return ZSweep{ZGeom{M, (int64_t)n * M, 0}, M, n};
 }
-Lines lines_z_nyq(int n) {  // l1 = y, element = z
-  return Lines{1, 0, n, n, 1, 1, n / 2};
-}
+ZSweep z_nyq(int n) { return ZSweep{ZGeom{0, n, 1}, n, 1}; }
 
 }  // namespace
 
@@ -733,18 +817,31 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
     if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, -1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
-  // Z fused: T2 = IFFT_z(-i k_z G F) -> A2 first (reads A0), then T1 = IFFT_z(G F) in place
-  Lines zm = lines_z_main(n), zn = lines_z_nyq(n);
+  // Z: outer forward DFT, inner forward DFT x kernel x inverse inner DFT with the two
+  // outputs T1 = G F (in place) and T2 = -i k_z G F (into A2), outer inverse DFT of both
+  const ZSweep zm = z_main(n), zn = z_nyq(n);
   {
     ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_col_zconv(f, 2, A0, nullptr, nullptr, A2, nullptr, zm, n)) != PM_OK) return s;
+    if ((s = d_z_outer(f, -1, A0, A0, zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
   }
   {
     ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_col_zconv(f, 0, A0, nullptr, nullptr, A0, nullptr, zm, n)) != PM_OK) return s;
+    if ((s = d_z_inner(f, 0, A0, nullptr, nullptr, A0, A2, zm.g, zm.lanes, zm.rows)) != PM_OK)
+      return s;
   }
-  if ((s = d_col_zconv(f, 2, N0, nullptr, nullptr, N2, nullptr, zn, 1)) != PM_OK) return s;
-  if ((s = d_col_zconv(f, 0, N0, nullptr, nullptr, N0, nullptr, zn, 1)) != PM_OK) return s;
+  {
+    ProfScope ps(c, ST_FFT_Z);
+    if ((s = d_z_outer(f, +1, A0, A0, zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
+  }
+  {
+    ProfScope ps(c, ST_FFT_Z);
+    if ((s = d_z_outer(f, +1, A2, A2, zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
+  }
+  if ((s = d_z_outer(f, -1, N0, N0, zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
+  if ((s = d_z_inner(f, 0, N0, nullptr, nullptr, N0, N2, zn.g, zn.lanes, zn.rows)) != PM_OK)
+    return s;
+  if ((s = d_z_outer(f, +1, N0, N0, zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
+  if ((s = d_z_outer(f, +1, N2, N2, zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
   // Y inverse: U2 = IFFT_y(-i k_y T1) -> A1 first (reads A0), then U1 in place, U3 in place
   {
     ProfScope ps(c, ST_FFT_YI);
@@ -781,14 +878,22 @@ pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
   float2* A[3] = {(float2*)acc, (float2*)(acc + n3), (float2*)(acc + 2 * n3)};
   float2* Nq[3] = {nyq, nyq + n2, nyq + 2 * n2};
   pm_status s;
-  Lines ym = lines_y_main(n), yn = lines_y_nyq(n), zm = lines_z_main(n), zn = lines_z_nyq(n);
+  Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
+  const ZSweep zm = z_main(n), zn = z_nyq(n);
   for (int ax = 0; ax < 3; ++ax) {
     if ((s = d_row_r2c(f, (const float*)A[ax], A[ax], Nq[ax])) != PM_OK) return s;
     if ((s = d_col_fft(f, A[ax], A[ax], nullptr, ym, n, -1)) != PM_OK) return s;
     if ((s = d_col_fft(f, Nq[ax], Nq[ax], nullptr, yn, 1, -1)) != PM_OK) return s;
+    if ((s = d_z_outer(f, -1, A[ax], A[ax], zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
+    if ((s = d_z_outer(f, -1, Nq[ax], Nq[ax], zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
   }
-  if ((s = d_col_zconv(f, 1, A[0], A[1], A[2], A[0], nullptr, zm, n)) != PM_OK) return s;
-  if ((s = d_col_zconv(f, 1, Nq[0], Nq[1], Nq[2], Nq[0], nullptr, zn, 1)) != PM_OK) return s;
+  if ((s = d_z_inner(f, 1, A[0], A[1], A[2], A[0], nullptr, zm.g, zm.lanes, zm.rows)) != PM_OK)
+    return s;
+  if ((s = d_z_inner(f, 1, Nq[0], Nq[1], Nq[2], Nq[0], nullptr, zn.g, zn.lanes, zn.rows)) !=
+      PM_OK)
+    return s;
+  if ((s = d_z_outer(f, +1, A[0], A[0], zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
+  if ((s = d_z_outer(f, +1, Nq[0], Nq[0], zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
   if ((s = d_col_fft(f, A[0], A[0], nullptr, ym, n, +1)) != PM_OK) return s;
   if ((s = d_col_fft(f, Nq[0], Nq[0], nullptr, yn, 1, +1)) != PM_OK) return s;
   if ((s = d_row_c2r(f, A[0], Nq[0], (float*)A[0], 0, nullptr)) != PM_OK) return s;

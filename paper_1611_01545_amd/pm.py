@@ -275,7 +275,7 @@ class PMContext:
         out.mass = mass.value
         return out, sid.value
 
-    STAGES = ["cell_offsets", "deposit", "fft_x_r2c", "fft_y_fwd", "fft_z_fused",
+    STAGES = ["cell_offsets", "deposit", "fft_x_r2c", "fft_y_fwd", "fft_z",
               "fft_y_inv", "fft_x_c2r", "interp_kick_drift", "resort", "codec", "adjoint"]
 
     def profile(self, enable: bool = True):
