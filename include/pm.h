@@ -183,8 +183,14 @@ pm_status pm_step(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp, d
 /* Adjoint of pm_step at state `in` (straight-through for the quantisation of
  * compressed states). lam_x1, lam_v1: per species device float [n][3] cotangents of
  * the step's outputs, in the output's particle order; lam_x0, lam_v0: results, in
- * the input's particle order. Arrays are passed as arrays of n_sp device pointers
- * (host arrays of pointers). */
+ * the input's particle order (no result array may be one of the cotangent arrays:
+ * PM_ERR_ARG). Arrays are passed as arrays of n_sp device pointers (host arrays of
+ * pointers). The step is recomputed (deposit, force and, for compressed states, the
+ * re-sort that maps output order to input order); the cotangent of the interpolated
+ * force is scattered to three meshes, taken through the transposed force operator
+ * (eqs. (1)-(3): the conjugate spectral multiplier +i k G) and gathered with the
+ * gradient of the CIC weights. The scatter uses float atomics, so results may differ
+ * between calls in the last bits. */
 pm_status pm_step_vjp(pm_ctx ctx, const pm_species* in, int n_sp, double dt,
                       float* const* lam_x1, float* const* lam_v1, float* const* lam_x0,
                       float* const* lam_v0);

@@ -322,6 +322,12 @@ pm_status pm_step_vjp(pm_ctx c, const pm_species* in, int n_sp, double dt,
       return PM_ERR_ARG;
     if (in[i].n > 0 && (!lam_x1[i] || !lam_v1[i] || !lam_x0[i] || !lam_v0[i]))
       return PM_ERR_ARG;
+    // results are written in another particle order than the cotangents are read
+    for (int j = 0; j < n_sp; ++j)
+      if (in[i].n > 0 && in[j].n > 0 &&
+          (lam_x0[i] == lam_x1[j] || lam_x0[i] == lam_v1[j] || lam_v0[i] == lam_x1[j] ||
+           lam_v0[i] == lam_v1[j]))
+        return PM_ERR_ARG;
   }
   if (!std::isfinite(dt)) return PM_ERR_ARG;
   pm_status s = ensure_step_meshes(c);

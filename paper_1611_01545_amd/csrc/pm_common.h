@@ -142,8 +142,9 @@ enum ScratchId {
   SC_FLAG,         // uint32 [ncell3] escape flags / misc
   SC_FOFF,         // int64 [ncell3+1] flag offsets
   SC_MISC,         // small
-  SC_VJP,          // float scratch for the adjoint
-  SC_VJP2,
+  SC_VJP,          // float [3][ng^3] adjoint meshes
+  SC_VJP2,         // decoded positions of compressed species (adjoint)
+  SC_VJP3,         // recomputed re-sort of the adjoint: permutations and stream copies
   SC_COUNT32,      // uint32 [ncell3]
   SC_SPOFF0,       // int64 [ncell3+1] cell offsets of species 0..3
   SC_SPOFF1,
