@@ -37,6 +37,39 @@ WORKLOAD_TEXT = {
 }
 
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch; commands and calibration in
+# profiles/hbm_traffic_<workload>.md), each scaled by what the counter reads for a kernel
+# that reads and writes exactly 1 GiB. A record holds only for the kernel sources it was
+# taken on (sha256 over `sources`); otherwise the traffic is reported as null.
+MEASURED_TRAFFIC = {
+    ("interp_kick_drift", "tile_1024"): {
+        "kernel": "k_kick_brick<16>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h",
+                    "paper_1611_01545_amd/csrc/pm_codec.h"],
+        "sha256": "d45e232403e67d09d0341521d81ee3d93a3791ec074597979d00bee927bcec0c",
+        "fetch_kib": 8016644.25, "fetch_factor": 1.99991,
+        "write_kib": 2216278.41, "write_factor": 1.0,
+    },
+}
+
+
+def measured_traffic(stage: str, workload: str):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((stage, workload))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sha256"]:
+        return None  # the kernel changed since the counters were taken
+    return (rec["fetch_kib"] * 1024 * rec["fetch_factor"] +
+            rec["write_kib"] * 1024 * rec["write_factor"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -57,28 +90,34 @@ def stage_bytes(name: str, n: int, wl) -> float:
         "fft_y_inv": 8 * n3,                    # one in, one out per launch
         "fft_x_c2r": 8 * n3 + 8 * n2,           # half spectrum + Nyquist in, real out
         "deposit": 3 * N + ns * nc3 + 4 * n3,   # positions, counts, density
-        "interp_kick_drift": (9 * N + 9 * N + 2 * ns * nc3 + 12 * n3) / ns,
+        # one launch moves every species: codes in and out, counts, the 3 force meshes
+        "interp_kick_drift": 9 * N + 9 * N + 2 * ns * nc3 + 12 * n3,
         "resort": (18 * N + 2 * ns * nc3) / ns,
         "cell_offsets": nc3 + 8 * nc3,          # counts in, offsets out (per species)
     }.get(name, 0.0)
 
 
 def cpu_baseline_and_error(ctx_cls, make_workload, base: str):
-    """Oracle step (FP64, numpy) on a 1/8-linear sample of the workload, timed on the
-    host; the GPU step on the same sample, compared with it."""
+    """The oracle (FP64, numpy, one thread) timed on a bounded sample of the workload:
+    the same recipe at 1/4 of the linear size, five compressed steps. The GPU step on
+    the same sample is compared with the oracle's first step."""
     import numpy as np
 
     from oracle import codec, step
 
-    c = {"tile_1024": dict(n_p_c=32, n_p_nu=64, n_mesh=128, n_cell=32),
+    c = {"tile_1024": dict(n_p_c=64, n_p_nu=128, n_mesh=256, n_cell=64),
          "two_species_256": dict(n_p_c=32, n_p_nu=64, n_mesh=64, n_cell=32)}[base]
     wl = make_workload(base, **c)
     ctx = ctx_cls(wl.n_mesh, wl.n_cell)
     dev = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
     states = [ctx.to_host(d) for d in dev]
     masses = [sp.mass for sp in wl.species]
+    n_steps = 5
     t0 = time.perf_counter()
     new, diag = step.step_compressed(states, masses, wl.n_mesh, wl.dt, wl.dt)
+    cur = new
+    for _ in range(n_steps - 1):
+        cur, _ = step.step_compressed(cur, masses, wl.n_mesh, wl.dt, wl.dt)
     t_cpu = time.perf_counter() - t0
     # GPU on the same sample
     rho = ctx.deposit(dev)
@@ -103,14 +142,53 @@ def cpu_baseline_and_error(ctx_cls, make_workload, base: str):
         tot += u.size
     ctx.close()
     n = wl.n_particles
-    return ({"value": n / t_cpu, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
-             "sample": f"{base} recipe at 1/8 linear size ({c['n_p_c']}^3 CDM + "
+    return ({"value": n * n_steps / t_cpu, "unit": "particle-updates/s", "cores": 1,
+             "kind": "oracle",
+             "sample": f"{base} recipe at 1/4 linear size ({c['n_p_c']}^3 CDM + "
                        f"{c['n_p_nu']}^3 nu, {c['n_mesh']}^3 mesh, n_cell {c['n_cell']}), "
-                       f"one compressed step, numpy float64, single thread",
+                       f"{n_steps} compressed steps, numpy float64, one thread",
              "seconds": t_cpu},
-            {"sample": f"{c['n_mesh']}^3 mesh, {n} particles",
+            {"sample": f"{c['n_mesh']}^3 mesh, {n} particles, first step",
              "density_max_rel": rho_err, "force_rel_rms": f_err,
              "position_code_mismatch_frac": mism / max(1, tot)})
+
+
+def adjoint_rates(ctx_cls, make_workload, torch, name: str, reps: int = 3):
+    """Forward K compressed steps (keeping every state as a checkpoint), then the density
+    loss and K step adjoints backward. Returns the median forward and backward times."""
+    wl = make_workload(name)
+    tg = make_workload(name, seed_offset=1)
+    K = wl.steps
+    ctx = ctx_cls(wl.n_mesh, wl.n_cell)
+    tgt = [ctx.float_species(sp.x, sp.v, sp.mass) for sp in tg.species]
+    rho_t = ctx.deposit(tgt)
+    st0 = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    traj = [st0] + [[ctx.empty_like(s) for s in st0] for _ in range(K)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_f, t_b = [], []
+    for r in range(reps + 1):
+        ctx.sync()
+        ev[0].record()
+        for k in range(K):
+            ctx.step(traj[k], wl.dt, out=traj[k + 1])
+        ev[1].record()
+        _, lx = ctx.loss_density_vjp(traj[K], rho_t)
+        lv = [torch.zeros_like(t) for t in lx]
+        for k in range(K - 1, -1, -1):
+            lx, lv = ctx.step_vjp(traj[k], wl.dt, lx, lv)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if r > 0:  # the first repetition warms up
+            t_f.append(ev[0].elapsed_time(ev[1]))
+            t_b.append(ev[1].elapsed_time(ev[2]))
+    ctx.close()
+    t_f = sorted(t_f)[len(t_f) // 2]
+    t_b = sorted(t_b)[len(t_b) // 2]
+    N = wl.n_particles
+    return {"workload": name, "particles": N, "n_mesh": wl.n_mesh, "steps": K,
+            "fwd_ms": t_f, "bwd_ms": t_b, "bwd_over_fwd": t_b / t_f,
+            "fwd_updates_per_s": N * K / (t_f * 1e-3),
+            "fwd_adjoint_updates_per_s": N * K / ((t_f + t_b) * 1e-3)}
 
 
 def main():
@@ -120,6 +198,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="tile_1024", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the step-adjoint timings (fwd+adjoint rates)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run one elementwise kernel that reads and "
                          "writes exactly 1 GiB (reference for HBM byte counters)")
@@ -179,12 +259,37 @@ def main():
               key=lambda k: stages[k]["ms_per_step"])
     ach = stages[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": measured_traffic(dom, args.config),
                 "bytes_per_launch": stage_bytes(dom, wl.n_mesh, wl),
                 "ms_per_launch": stages[dom]["ms_per_launch"]}
     total_model = sum(stage_bytes(k, wl.n_mesh, wl) * stages[k]["launches_per_step"]
                       for k in stages)
     step_frac = total_model / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    adj = None
+    if not args.no_adjoint:
+        log("[bench] step adjoint at the same workload")
+        lx = [torch.ones((sp.n, 3), dtype=torch.float32, device=ctx.device) for sp in cur]
+        lv = [torch.ones_like(t) for t in lx]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        t_vjp = []
+        for r in range(3):
+            ev[0].record()
+            gx, gv = ctx.step_vjp(cur, wl.dt, lx, lv)
+            ev[1].record()
+            torch.cuda.synchronize()
+            if r > 0:
+                t_vjp.append(ev[0].elapsed_time(ev[1]))
+        del gx, gv, lx, lv
+        t_vjp = min(t_vjp)
+        adj = {"step_vjp_ms": t_vjp, "vjp_over_step": t_vjp / ms_step,
+               "fwd_adjoint_updates_per_s": wl.n_particles / ((ms_step + t_vjp) * 1e-3)}
+        log(f"[bench] step adjoint {t_vjp:.3f} ms ({t_vjp / ms_step:.2f}x the step)")
+        a128 = adjoint_rates(PMContext, make_workload, torch, "adjoint_128")
+        adj["adjoint_128"] = a128
+        log(f"[bench] adjoint_128: fwd {a128['fwd_ms']:.2f} ms, bwd {a128['bwd_ms']:.2f} ms "
+            f"for {a128['steps']} steps")
 
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device=ctx.device)
@@ -209,6 +314,7 @@ def main():
         "roofline": roofline,
         "step_hbm_frac_model": step_frac,
         "stages": stages,
+        "adjoint": adj,
         "err_vs_fp64": err,
         "cpu_baseline": cpu,
     }

@@ -481,11 +481,11 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     S.pmx = S.pmn + g.nbrick;
   }
   {
-    ProfScope ps(c, ST_KICK);
     pm_status st0;
     for (int s = 0; s < n_sp; ++s)
       hipLaunchKernelGGL(k_vmax_next, dim3(1), dim3(1), 0, c->stream, in[s].hdr, out[s].hdr,
                          amax, ck, in[s].n);
+    ProfScope ps(c, ST_KICK);
     const int R1 = g.B * g.r + 1;
     const size_t fbytes = (size_t)3 * R1 * R1 * R1 * 4;
     const size_t tail = (size_t)(B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + KB / 64);
@@ -500,6 +500,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
       hipLaunchKernelGGL(k_kick_brick<0>, dim3((unsigned)g.nbrick), dim3(KB), tail,
                          c->stream, A, g, c->err);
     PM_LAUNCH_CHECK();
+    prof_end(c);  // the scope covers the brick kernel only
     for (int s = 0; s < n_sp; ++s)
       if ((st0 = fold_minmax_to_header(c, A.sp[s].pmn, A.sp[s].pmx, g.nbrick, out[s].hdr)) !=
           PM_OK)
