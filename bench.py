@@ -84,9 +84,7 @@ def stage_bytes(name: str, n: int, wl) -> float:
     return {
         "fft_x_r2c": 8 * n3 + 8 * n2,          # real mesh in, half spectrum + Nyquist out
         "fft_y_fwd": 8 * n3,                    # half spectrum in and out
-        # four sweeps per step: outer DFT 8, inner DFT x kernel x inverse (one in, two
-        # out) 12, outer inverse of both outputs 8 + 8: 36 n^3 over 4 launches
-        "fft_z": 9 * n3,
+        "fft_z": 12 * n3,                       # fused z pass, one in, two out
         "fft_y_inv": 8 * n3,                    # one in, one out per launch
         "fft_x_c2r": 8 * n3 + 8 * n2,           # half spectrum + Nyquist in, real out
         "deposit": 3 * N + ns * nc3 + 4 * n3,   # positions, counts, density

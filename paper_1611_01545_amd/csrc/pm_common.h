@@ -151,6 +151,7 @@ enum ScratchId {
   SC_SPOFF2,
   SC_SPOFF3,
   SC_PARTS,        // per-workgroup partial results of grid reductions
+  SC_SPEC,         // float [ng^3] spectrum scratch of the force transforms
   SC_N
 };
 

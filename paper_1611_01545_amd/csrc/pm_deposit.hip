@@ -12,9 +12,10 @@
 //
 // Weights are exact: a compressed position sits at the bin centre (2u+1)/(512 n_c),
 // i.e. at (2u+1) r / 512 mesh cells, so each axis weight is an integer multiple of
-// 1/512 and their product an integer multiple of 2^-27. Contributions are summed as
-// 64-bit fixed point (units of m_max 2^-32), which makes the deposit independent of
-// the order of the atomics: every run, and the recomputation in the adjoint, gives
+// 1/512 and their product an integer multiple of 2^-27. Each species' weights are
+// summed as 64-bit integers in LDS (exact, so independent of the order of the
+// atomics), then scaled by the species' mass into per-thread FP64 node densities in a
+// fixed species order: every run, and the recomputation in the adjoint, gives
 // bit-identical densities.
 #include "pm_codec.h"
 #include "pm_scan.h"
@@ -28,7 +29,7 @@ struct DepSpecies {
   int64_t n;           // particles (bounds guard against inconsistent counts)
   const uint8_t* pos;
   const int64_t* off;  // [ncell3 + 1]
-  double scale;        // 32 m_s / m_max: fixed-point units per exact 2^-27 weight
+  double unit;         // density per weight unit 2^-27: m_s n_g^3 2^-27
 };
 struct DepArgs {
   DepSpecies sp[MAX_SP];
@@ -36,7 +37,6 @@ struct DepArgs {
   int T;   // tile side in cells
   int r;   // mesh cells per compression cell
   int R;   // tile side in nodes
-  double unit;  // density per fixed-point unit: m_max 2^-32 n_g^3
 };
 
 __device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
@@ -44,19 +44,27 @@ __device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c -
 template <int TT>  // tile side in cells (compile time, 0: runtime A.T)
 __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g, float* rho) {
   extern __shared__ unsigned char smem[];
-  const int T = TT ? TT : A.T, R = A.R, r = A.r;
+  // compile-time tiles have T r = 16 nodes per side (T = 16 / r)
+  const int T = TT ? TT : A.T, R = TT ? 16 : A.R, r = TT ? 16 / TT : A.r;
   const int E = T + 1;              // extended cells per side
   const int NE = E * E * E;
   const int R3 = R * R * R;
   __shared__ int64_t lw[DEP_THREADS / 64 + 1];
   unsigned long long* acc = (unsigned long long*)smem;
-  int* pre = (int*)(acc + R3);      // [NE + 1] particle prefix over extended cells
+  int64_t* cst = (int64_t*)(acc + R3);  // [NE] stream start of each extended cell
+  int* pre = (int*)(cst + NE);          // [NE + 1] particle prefix over extended cells
   const int nt = (int)(g.nc / T);
   const int64_t tile = xcd_tile(blockIdx.x, (int64_t)nt * nt * nt);
   const int tx = (int)(tile % nt), ty = (int)((tile / nt) % nt), tz = (int)(tile / ((int64_t)nt * nt));
   const int ncs = (int)g.nc;
 
   for (int i = threadIdx.x; i < R3; i += DEP_THREADS) acc[i] = 0ull;
+  // per-thread density of its nodes i = threadIdx.x + k DEP_THREADS (R <= 16, so at most
+  // 16 nodes), summed over species in a fixed order
+  constexpr int NPT = 4096 / DEP_THREADS;
+  double racc[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) racc[k] = 0.0;
 
   for (int s = 0; s < A.n_sp; ++s) {
     const DepSpecies sp = A.sp[s];
@@ -67,7 +75,9 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
       int cx = wrapc(tx * T + ex - 1, ncs), cy = wrapc(ty * T + ey - 1, ncs),
           cz = wrapc(tz * T + ez - 1, ncs);
       uint32_t key = cell_key(g, cx, cy, cz);
-      pre[e + 1] = (int)(sp.off[key + 1] - sp.off[key]);
+      const int64_t o0 = sp.off[key], o1 = sp.off[key + 1];
+      cst[e] = o0;
+      pre[e + 1] = (int)(o1 - o0);
     }
     __syncthreads();
     {
@@ -87,57 +97,99 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
     }
     __syncthreads();
     const int P = pre[NE];
-    for (int q = threadIdx.x; q < P; q += DEP_THREADS) {
-      // extended cell of flat particle q: largest e with pre[e] <= q
-      int lo = 0, hi = NE;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (pre[mid] <= q) lo = mid; else hi = mid;
+    // U particles per thread per round: their code loads are issued together
+    constexpr int U = 4;
+    for (int q0 = threadIdx.x; q0 < P; q0 += DEP_THREADS * U) {
+      int eu[U];
+      int64_t ju[U];
+      uint32_t pb[U][3];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * DEP_THREADS;
+        // extended cell of flat particle q: largest e with pre[e] <= q
+        int lo = 0, hi = NE;
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (pre[mid] <= q) lo = mid; else hi = mid;
+        }
+        eu[u] = lo;
+        const int64_t j = cst[lo] + (q - pre[lo]);
+        // counts inconsistent with n are latched by the offset check; q >= P is padding
+        ok[u] = q < P && j < sp.n;
+        ju[u] = ok[u] ? j : 0;  // n > 0 whenever P > 0
       }
-      const int e = lo;
-      const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
-      const int cx = wrapc(tx * T + ex - 1, ncs), cy = wrapc(ty * T + ey - 1, ncs),
-                cz = wrapc(tz * T + ez - 1, ncs);
-      const uint32_t key = cell_key(g, cx, cy, cz);
-      const int64_t j = sp.off[key] + (q - pre[e]);
-      if (j >= sp.n) continue;  // counts inconsistent with n (latched by the offset check)
-      int li[3], f[3];
-      const int le[3] = {ex - 1, ey - 1, ez - 1};
+      // all code loads of the round, then the arithmetic
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        int gl = (2 * (int)sp.pos[3 * j + a] + 1) * r;  // position inside the cell, 1/512 mesh cell
-        li[a] = le[a] * r + (gl >> 9);
-        f[a] = gl & 511;
-      }
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int dz = 0; dz < 2; ++dz) {
-        int nz = li[2] + dz;
-        int wz = dz ? f[2] : 512 - f[2];
-        if (nz < 0 || nz >= R || wz == 0) continue;
+        for (int a = 0; a < 3; ++a) pb[u][a] = sp.pos[3 * ju[u] + a];
 #pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
-          int ny = li[1] + dy;
-          int wy = dy ? f[1] : 512 - f[1];
-          if (ny < 0 || ny >= R || wy == 0) continue;
+      for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        const int e = eu[u];
+        const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+        int li[3], f[3];
+        const int le[3] = {ex - 1, ey - 1, ez - 1};
 #pragma unroll
-          for (int dx = 0; dx < 2; ++dx) {
-            int nx = li[0] + dx;
-            int wx = dx ? f[0] : 512 - f[0];
-            if (nx < 0 || nx >= R || wx == 0) continue;
-            int64_t W = (int64_t)wx * wy * wz;  // exact, units of 2^-27
-            unsigned long long qv = (unsigned long long)__double2ll_rn((double)W * sp.scale);
-            atomicAdd(&acc[(nz * R + ny) * R + nx], qv);
+        for (int a = 0; a < 3; ++a) {
+          int gl = (2 * (int)pb[u][a] + 1) * r;  // position inside the cell, 1/512 mesh cell
+          li[a] = le[a] * r + (gl >> 9);
+          f[a] = gl & 511;
+        }
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+          int nz = li[2] + dz;
+          int wz = dz ? f[2] : 512 - f[2];
+          if (nz < 0 || nz >= R || wz == 0) continue;
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            int ny = li[1] + dy;
+            int wy = dy ? f[1] : 512 - f[1];
+            if (ny < 0 || ny >= R || wy == 0) continue;
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+              int nx = li[0] + dx;
+              int wx = dx ? f[0] : 512 - f[0];
+              if (nx < 0 || nx >= R || wx == 0) continue;
+              const uint32_t W = (uint32_t)(wx * wy) * (uint32_t)wz;  // exact, 2^-27
+              atomicAdd(&acc[(nz * R + ny) * R + nx], (unsigned long long)W);
+            }
           }
         }
       }
     }
+    // this species' integer weight sums into the thread's FP64 node densities
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int i = threadIdx.x + k * DEP_THREADS;
+      if (i < R3) {
+        racc[k] += (double)acc[i] * sp.unit;
+        acc[i] = 0ull;
+      }
+    }
   }
-  __syncthreads();
   const int64_t ng = g.ng;
-  for (int i = threadIdx.x; i < R3; i += DEP_THREADS) {
-    int lx = i % R, ly = (i / R) % R, lz = i / (R * R);
-    int64_t gx = (int64_t)tx * R + lx, gy = (int64_t)ty * R + ly, gz = (int64_t)tz * R + lz;
-    rho[(gz * ng + gy) * ng + gx] = (float)((double)acc[i] * A.unit);
+  if (TT) {
+    // R = 16: node i = threadIdx.x + 256 k has lx = i & 15, ly = (i >> 4) & 15, lz = k
+    const int64_t ng2 = ng * ng;
+    float* dst = rho + (int64_t)tz * 16 * ng2 +
+                 ((int64_t)ty * 16 + ((threadIdx.x >> 4) & 15)) * ng + (int64_t)tx * 16 +
+                 (threadIdx.x & 15);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) dst[k * ng2] = (float)racc[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int i = threadIdx.x + k * DEP_THREADS;
+      if (i < R3) {
+        int lx = i % R, ly = (i / R) % R, lz = i / (R * R);
+        int64_t gx = (int64_t)tx * R + lx, gy = (int64_t)ty * R + ly,
+                gz = (int64_t)tz * R + lz;
+        rho[(gz * ng + gy) * ng + gx] = (float)racc[k];
+      }
+    }
   }
 }
 
@@ -192,8 +244,7 @@ pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
                            int64_t* const* offs, float* rho) {
   const Geom& g = c->g;
   if (n_sp > MAX_SP) return PM_ERR_ARG;
-  double mmax = 0.0;
-  for (int s = 0; s < n_sp; ++s) mmax = fmax(mmax, sp[s].mass);
+  const double ng3 = (double)g.ng * g.ng * g.ng;
   DepArgs A{};
   A.n_sp = 0;
   for (int s = 0; s < n_sp; ++s) {
@@ -201,21 +252,22 @@ pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
     A.sp[A.n_sp].n = sp[s].n;
     A.sp[A.n_sp].pos = sp[s].pos;
     A.sp[A.n_sp].off = offs[s];
-    A.sp[A.n_sp].scale = 32.0 * (sp[s].mass / mmax);
+    A.sp[A.n_sp].unit = sp[s].mass * ng3 * 0x1p-27;
     A.n_sp++;
   }
   A.r = g.r;
   A.T = deposit_tile_cells(g);
   A.R = A.T * g.r;
-  double ng3 = (double)g.ng * g.ng * g.ng;
-  A.unit = mmax > 0 ? mmax * 0x1p-32 * ng3 : 0.0;
+  if (A.R > 16) return PM_ERR_SHAPE;  // at most 16 nodes per thread
   int nt = (int)(g.nc / A.T);
-  size_t lds = (size_t)A.R * A.R * A.R * 8 + ((size_t)(A.T + 1) * (A.T + 1) * (A.T + 1) + 1) * 4;
+  const size_t ne = (size_t)(A.T + 1) * (A.T + 1) * (A.T + 1);
+  size_t lds = (size_t)A.R * A.R * A.R * 8 + ne * 8 + (ne + 1) * 4;
   ProfScope ps(c, ST_DEPOSIT);
   const dim3 grid((unsigned)((int64_t)nt * nt * nt));
-  if (A.T == 4)
+  // the compile-time variants assume T r = 16
+  if (A.T == 4 && A.r == 4)
     hipLaunchKernelGGL(k_deposit_tile<4>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
-  else if (A.T == 8)
+  else if (A.T == 8 && A.r == 2)
     hipLaunchKernelGGL(k_deposit_tile<8>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
   else
     hipLaunchKernelGGL(k_deposit_tile<0>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);

@@ -4,15 +4,15 @@
 // dimension (Sec. 2.3). Here every axis pass is one HBM pass over the mesh, and the
 // kernel multiply and gradient factors are fused into the passes; the four transforms
 // of a step (one forward, three inverse) take these sweeps:
-//   X  r2c      rho(x) -> rho~(kx)                     rows, Nyquist column kx = n/2
+//   X  r2c      rho(x) -> rho~(kx)                     rows; Nyquist column kx = n/2
 //                                                      kept in a side plane
 //   Y  fwd      -> rho~(kx, ky)                        columns, in place
-//   Z           two-level z transform (N = N1 N2): outer DFT; inner DFT, multiply by
-//               G(|k|^2) (softened kernel table), inverse inner DFT with two outputs
-//               T1 = G rho~ and T2 = -i k_z G rho~; outer inverse DFT of T1 and T2
-//   Y  inv      U2 = IFFT_y(-i k_y T1), then in place U1 = IFFT_y(T1), U3 = IFFT_y(T2)
+//   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table), inverse z
+//               FFT: T1 = IFFT_z(G rho~) and T2 = IFFT_z(-i k_z G rho~) from one read
+//   Y  inv      U2 = IFFT_y(-i k_y T1), U1 = IFFT_y(T1), U3 = IFFT_y(T2)
 //   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
 //               max |a| for the velocity bound of the re-encode
+// 9 launches moving 76 n^3 bytes, against 12 plain passes and separate multiplies.
 // The gradient factor -i k_a follows eq. (3) and is zero on the Nyquist index; the
 // 1/n^3 of the inverse transform is folded into the kernel table.
 //
@@ -216,16 +216,37 @@ __device__ __forceinline__ void tr_to_nat(float2 (&b)[Plan<N>::E], int t, float*
   dft_reg<P::E, SIGN>(b);
 }
 
+// ------------------------------------------------------------ spectrum layout --
+// The half spectrum (kx < n/2, M = n/2 complex per row) is stored z-blocked:
+//   index(kx, y, z) = ((z / ZB) n + y) ZB M + (z % ZB) M + kx,   ZB = min(16, T(n)),
+// so that a z line visits n / ZB address blocks of ZB consecutive rows instead of n
+// blocks 4 n M bytes apart (one address translation per ZB points), while y lines keep
+// runs of W kx at a stride of ZB M. The Nyquist plane kx = n/2 is a separate [z][y]
+// array. T(n) is the four-step split of an n-point line, so ZB divides T and E.
+__host__ __device__ constexpr int zblk(int n) {
+  int t = 1 << (ilog2(n) / 2);
+  return t < 16 ? t : 16;
+}
+
 // ------------------------------------------------------------- column passes --
-// Lines l = (l1, l2): element e of line l at base + l1*s1 + l2*s2 + e*es (complex
-// units). A workgroup takes W consecutive l1 (s1 = 1 gives W*8-byte runs) and one l2.
+// Lines l = (l1, l2): element e of line l at
+//   base = l1 s1 + (l2 >> sh2) s2h + (l2 & (2^sh2 - 1)) s2l
+//   element e: e es, or for z-blocked lines (e / ZB) es + (e % ZB) esl
+// (complex units). A workgroup takes W consecutive l1 (s1 = 1 gives W*8-byte runs) and
+// one l2.
 struct Lines {
-  int64_t s1, s2, es;
+  int64_t s1, s2h, s2l;
+  int sh2;
+  int64_t es, esl;
   int64_t L1;      // number of l1 values
   int kx_mode;     // 0: kx = l1; 1: kx = kx_fixed
   int ky_mode;     // 0: ky = l2; 1: ky = l1
   int kx_fixed;
 };
+
+__device__ __forceinline__ int64_t line_base(const Lines& d, int64_t l1, int64_t l2) {
+  return l1 * d.s1 + (l2 >> d.sh2) * d.s2h + (l2 & ((1 << d.sh2) - 1)) * d.s2l;
+}
 
 template <int W>
 constexpr int col_cs(int per_col) {  // padded per-column stride, spreads LDS banks
@@ -253,7 +274,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
   // the grid covers the lines exactly (W divides the line count; checked on the host)
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int64_t l1 = (int64_t)blockIdx.x * W + c;
-  const int64_t base = l1 * d.s1 + (int64_t)blockIdx.y * d.s2;
+  const int64_t base = line_base(d, l1, blockIdx.y);
   float* my = lds + c * CS;
   float2 a[P::E];
 #pragma unroll
@@ -276,140 +297,131 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
       out0[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = a[v * P::T + k2];
 }
 
-// ------------------------------------------------------------- z passes --
-// The z transform (stride n * n/2 complex between z points) is split N = N1 N2 so that a
-// workgroup touches only N1 or N2 z-planes (a handful of address translations instead
-// of one per point) and every access is a run of consecutive kx:
-//   ZA  fixed slot s < N2: the N1 points z = N2 m + s, DFT over m, twiddle
-//       exp(-2 pi i s k1 / N), stored back at z = N2 k1 + s                (in place)
-//   ZB  fixed k1 < N1: the N2 consecutive points z = N2 k1 + s, DFT over s gives
-//       X[k1 + N1 j]; multiply by the kernel (and the gradient factor), inverse DFT over
-//       j, twiddle exp(+2 pi i s' k1 / N), store at z = N2 k1 + s'
-//   ZC  fixed slot s' < N2: inverse DFT over k1 of the N1 points z = N2 k1 + s', stored
-//       at z = N2 m' + s' (natural order)                                  (in place)
-// Each thread owns one (kx, y) position and keeps its N1 or N2 points in registers.
-template <int N>
-struct ZPlan {
-  static constexpr int LG = ilog2(N);
-  static constexpr int N2 = 1 << (LG / 2);  // consecutive planes (inner length)
-  static constexpr int N1 = N / N2;         // strided planes (outer length)
-};
-
-// Geometry of one z sweep: lanes (unit stride: kx, or y on the Nyquist plane) and rows
-// (y, or a single row on the Nyquist plane).
-struct ZGeom {
-  int64_t s_row, s_plane;  // complex strides between rows and between z planes
-  int nyq;                 // 1: the Nyquist plane kx = n/2, lanes are y
-};
-
-__device__ __forceinline__ int64_t zpos(const ZGeom& g, int& kx, int& ky, int n) {
-  const int lane = blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = blockIdx.y * blockDim.y + threadIdx.y;
-  kx = g.nyq ? n / 2 : lane;
-  ky = g.nyq ? lane : row;
-  return lane + (int64_t)row * g.s_row;
-}
-
-// ZA (SIGN -1, with the twiddle) and ZC (SIGN +1, no twiddle). blockIdx.z is the slot.
-template <int N, int SIGN>
-__global__ __launch_bounds__(256) void k_zouter(const float2* in, float2* out, ZGeom g,
-                                                const float2* __restrict__ tw, int n) {
-  using Z = ZPlan<N>;
-  int kx, ky;
-  const int s = blockIdx.z;
-  const int64_t off = zpos(g, kx, ky, n) + (int64_t)s * g.s_plane;
-  float2 a[Z::N1];
-#pragma unroll
-  for (int m = 0; m < Z::N1; ++m) a[m] = in[off + (int64_t)(Z::N2 * m) * g.s_plane];
-  dft_reg<Z::N1, SIGN>(a);
-  if constexpr (SIGN < 0) {
-#pragma unroll
-    for (int k = 1; k < Z::N1; ++k) a[k] = cmul(a[k], tw[s * k]);
-  }
-#pragma unroll
-  for (int m = 0; m < Z::N1; ++m) out[off + (int64_t)(Z::N2 * m) * g.s_plane] = a[m];
-}
-
-// ZB. MODE 0 (force): out0 = G X, out1 = -i k_z G X (out0 may alias in0).
-// MODE 1 (transpose of the force): out0 = G sum_a (+i k_a) X_a over in0..in2.
-// blockIdx.z is the outer frequency k1.
-template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_zinner(const float2* in0, const float2* in1,
-                                                const float2* in2, float2* out0,
-                                                float2* out1, ZGeom g,
-                                                const float2* __restrict__ tw, int n,
-                                                const float* __restrict__ ktab) {
-  using Z = ZPlan<N>;
-  int kx, ky;
-  const int k1 = blockIdx.z;
-  const int64_t off = zpos(g, kx, ky, n) + (int64_t)(Z::N2 * k1) * g.s_plane;
+// ---------------------------------------------------------------- fused z pass --
+// F = FFT_z(in0) per line, then MODE 0: out0 = IFFT_z(G F); MODE 2: out0 =
+// IFFT_z(-i k_z G F); MODE 3: both, out0 = IFFT_z(G F) and out1 = IFFT_z(-i k_z G F)
+// from one read (the two inverse transforms run one after the other); MODE 1
+// (transpose of the force): out0 = IFFT_z(G sum_a (+i k_a) FFT_z(in_a)). BLK: the lines
+// are z-blocked (main spectrum) or plain strided (Nyquist plane).
+template <int N, int W, int MODE, bool BLK>
+__global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
+    const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
+    Lines d,
+    const float2* __restrict__ tw, int tws, int twmask, int n,
+    const float* __restrict__ ktab) {
+  using P = Plan<N>;
+  constexpr int ZB = zblk(N), LZB = ilog2(ZB);
+  static_assert(P::T % ZB == 0, "z blocks must divide the thread stride");
+  constexpr int CS = col_cs<W>(P::E * P::TP);
+  __shared__ float lds[W * CS];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int64_t l1 = (int64_t)blockIdx.x * W + c;
+  // element t + T n1 of the line: z-blocked lines split it as (block, row in block)
+  const int64_t base = line_base(d, l1, blockIdx.y) +
+                       (BLK ? (int64_t)(t >> LZB) * d.es + (int64_t)(t & (ZB - 1)) * d.esl
+                            : (int64_t)t * d.es);
+  const int64_t step = BLK ? (int64_t)(P::T >> LZB) * d.es : (int64_t)P::T * d.es;
+  float* my = lds + c * CS;
+  const int kx = d.kx_mode ? d.kx_fixed : (int)l1;
+  const int ky = d.ky_mode ? (int)l1 : (int)blockIdx.y;
   const int sx = signed_k(kx, n), sy = signed_k(ky, n);
   const int nxy2 = sx * sx + sy * sy;
-  float2 acc[Z::N2];
-  if constexpr (MODE == 0) {
-    float2 gz[Z::N2];
+  float2 acc[P::E];
+  if constexpr (MODE == 3) {
 #pragma unroll
-    for (int j = 0; j < Z::N2; ++j) acc[j] = in0[off + (int64_t)j * g.s_plane];
-    dft_reg<Z::N2, -1>(acc);
+    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = in0[base + n1 * step];
+    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+    float2 gz[P::E];
 #pragma unroll
-    for (int j = 0; j < Z::N2; ++j) {
-      const int kz = k1 + Z::N1 * j;
-      const int sz = signed_k(kz, n);
-      const float G = ktab[nxy2 + sz * sz];
-      const float2 f = make_float2(G * acc[j].x, G * acc[j].y);
-      const float kk = grad_k(kz, n);
-      acc[j] = f;
-      gz[j] = make_float2(kk * f.y, -kk * f.x);  // -i k_z (x + i y) = k_z y - i k_z x
-    }
-    dft_reg<Z::N2, +1>(acc);
-    dft_reg<Z::N2, +1>(gz);
+    for (int v = 0; v < P::V; ++v)
 #pragma unroll
-    for (int j = 1; j < Z::N2; ++j) {
-      const float2 w = tw[j * k1];
-      acc[j] = cmulc(acc[j], w);
-      gz[j] = cmulc(gz[j], w);
-    }
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const int kz = (t + P::T * v) + P::E * k2;
+        const int sz = signed_k(kz, n);
+        const float G = ktab[nxy2 + sz * sz];
+        const float2 f = make_float2(G * acc[v * P::T + k2].x, G * acc[v * P::T + k2].y);
+        const float kk = grad_k(kz, n);
+        acc[v * P::T + k2] = f;
+        gz[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
+      }
+    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
 #pragma unroll
-    for (int j = 0; j < Z::N2; ++j) {
-      out0[off + (int64_t)j * g.s_plane] = acc[j];
-      out1[off + (int64_t)j * g.s_plane] = gz[j];
-    }
+    for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
+    tr_to_nat<N, +1>(gz, t, my, tw, tws, twmask);
+#pragma unroll
+    for (int n1 = 0; n1 < P::E; ++n1) out1[base + n1 * step] = gz[n1];
+  } else if constexpr (MODE == 0 || MODE == 2) {
+#pragma unroll
+    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = in0[base + n1 * step];
+    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const int kz = (t + P::T * v) + P::E * k2;
+        const int sz = signed_k(kz, n);
+        const float G = ktab[nxy2 + sz * sz];
+        const float2 f = acc[v * P::T + k2];
+        if constexpr (MODE == 2) {
+          // -i k_z G (x + i y) = k_z G y - i k_z G x
+          const float kk = grad_k(kz, n) * G;
+          acc[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
+        } else {
+          acc[v * P::T + k2] = make_float2(G * f.x, G * f.y);
+        }
+      }
+    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
+#pragma unroll
+    for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
   } else {
     const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
 #pragma unroll
-    for (int j = 0; j < Z::N2; ++j) acc[j] = make_float2(0.f, 0.f);
+    for (int i = 0; i < P::E; ++i) acc[i] = make_float2(0.f, 0.f);
     const float2* ins[3] = {in0, in1, in2};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      float2 f[Z::N2];
+      float2 f[P::E];
 #pragma unroll
-      for (int j = 0; j < Z::N2; ++j) f[j] = ins[ax][off + (int64_t)j * g.s_plane];
-      dft_reg<Z::N2, -1>(f);
+      for (int n1 = 0; n1 < P::E; ++n1) f[n1] = ins[ax][base + n1 * step];
+      nat_to_tr<N, -1>(f, t, my, tw, tws, twmask);
 #pragma unroll
-      for (int j = 0; j < Z::N2; ++j) {
-        const float k = ax == 0 ? kxg : ax == 1 ? kyg : grad_k(k1 + Z::N1 * j, n);
-        acc[j].x += -k * f[j].y;  // + i k (x + i y) = -k y + i k x
-        acc[j].y += k * f[j].x;
+      for (int v = 0; v < P::V; ++v)
+#pragma unroll
+        for (int k2 = 0; k2 < P::T; ++k2) {
+          const int kz = (t + P::T * v) + P::E * k2;
+          const float k = ax == 0 ? kxg : ax == 1 ? kyg : grad_k(kz, n);
+          const float2 q = f[v * P::T + k2];
+          // + i k (x + i y) = -k y + i k x
+          acc[v * P::T + k2].x += -k * q.y;
+          acc[v * P::T + k2].y += k * q.x;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const int kz = (t + P::T * v) + P::E * k2;
+        const int sz = signed_k(kz, n);
+        const float G = ktab[nxy2 + sz * sz];
+        acc[v * P::T + k2].x *= G;
+        acc[v * P::T + k2].y *= G;
       }
-    }
+    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
 #pragma unroll
-    for (int j = 0; j < Z::N2; ++j) {
-      const int sz = signed_k(k1 + Z::N1 * j, n);
-      const float G = ktab[nxy2 + sz * sz];
-      acc[j].x *= G;
-      acc[j].y *= G;
-    }
-    dft_reg<Z::N2, +1>(acc);
-#pragma unroll
-    for (int j = 1; j < Z::N2; ++j) acc[j] = cmulc(acc[j], tw[j * k1]);
-#pragma unroll
-    for (int j = 0; j < Z::N2; ++j) out0[off + (int64_t)j * g.s_plane] = acc[j];
+    for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
   }
 }
 
 // ----------------------------------------------------------------- row passes --
 // A real row of n = 2M floats is the complex row z[m] = x[2m] + i x[2m+1] of M points.
-// Workgroup: R rows x T threads, threads of a row consecutive (coalesced rows).
+// Workgroup: R rows x T threads, threads of a row consecutive (coalesced rows). Real
+// rows are in natural order (row = z n + y); spectrum rows are z-blocked.
+template <int M>
+__device__ __forceinline__ int64_t spec_row(int64_t row) {
+  constexpr int n = 2 * M, ZB = zblk(n), LZB = ilog2(ZB), LN = ilog2(n);
+  const int64_t z = row >> LN, y = row & (n - 1);
+  return (((z >> LZB) << LN) + y) * ((int64_t)ZB * M) + (z & (ZB - 1)) * M;
+}
 template <int M>
 constexpr int row_lds_floats() {
   using P = Plan<M>;
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
 #pragma unroll
     for (int k2 = 0; k2 < P::T; ++k2) zs[(t + P::T * v) + P::E * k2] = a[v * P::T + k2];
   __syncthreads();
-  float2* o = out + row * M;
+  float2* o = out + spec_row<M>(row);
 #pragma unroll
   for (int j = 0; j < P::E; ++j) {
     const int k = t + P::T * j;
@@ -486,7 +498,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   const int64_t row = (int64_t)blockIdx.x * R + rr;
   float* my = lds + rr * LF;
   float2* xs = (float2*)my;
-  const float2* xi = in + row * M;
+  const float2* xi = in + spec_row<M>(row);
   const int n = 2 * M;
 #pragma unroll
   for (int j = 0; j < P::E; ++j) {
@@ -614,45 +626,28 @@ pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, con
   return PM_OK;
 }
 
-// z sweep launch shape: 64 consecutive lanes per wave (a 512-byte run per plane), the
-// rest of the 256 threads on adjacent rows; lanes and rows are powers of two, so the
-// grid covers them exactly.
-struct ZLaunch {
-  dim3 block, grid;
-};
-ZLaunch zlaunch(int64_t lanes, int64_t rows, int slots) {
-  int lx = (int)(lanes < 64 ? lanes : 64);
-  int64_t ly = 256 / lx;
-  if (ly > rows) ly = rows;
-  return ZLaunch{dim3(lx, (unsigned)ly), dim3((unsigned)(lanes / lx), (unsigned)(rows / ly),
-                                             (unsigned)slots)};
-}
-
 template <int N>
-pm_status z_outer(const FftCtx& f, int sign, const float2* in, float2* out, const ZGeom& g,
-                  int64_t lanes, int64_t rows) {
-  ZLaunch L = zlaunch(lanes, rows, ZPlan<N>::N2);
-  if (sign < 0)
-    hipLaunchKernelGGL((k_zouter<N, -1>), L.grid, L.block, 0, f.c->stream, in, out, g,
-                       f.c->tw, f.n);
-  else
-    hipLaunchKernelGGL((k_zouter<N, 1>), L.grid, L.block, 0, f.c->stream, in, out, g, f.c->tw,
-                       f.n);
-  PM_LAUNCH_CHECK();
-  return PM_OK;
-}
-
-template <int N>
-pm_status z_inner(const FftCtx& f, int mode, const float2* i0, const float2* i1,
-                  const float2* i2, float2* o0, float2* o1, const ZGeom& g, int64_t lanes,
-                  int64_t rows) {
-  ZLaunch L = zlaunch(lanes, rows, ZPlan<N>::N1);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_zinner<N, 0>), L.grid, L.block, 0, f.c->stream, i0, i1, i2, o0, o1,
-                       g, f.c->tw, f.n, f.c->ktab);
-  else
-    hipLaunchKernelGGL((k_zinner<N, 1>), L.grid, L.block, 0, f.c->stream, i0, i1, i2, o0, o1,
-                       g, f.c->tw, f.n, f.c->ktab);
+pm_status col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0, const float2* i1,
+                    const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
+  constexpr int W = col_w<N>();
+  if (d.L1 % W) return PM_ERR_SHAPE;
+  dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
+  dim3 block(W * Plan<N>::T);
+#define ZLAUNCH(MODE, BLK)                                                                 \
+  hipLaunchKernelGGL((k_col_zconv<N, W, MODE, BLK>), grid, block, 0, f.c->stream, i0, i1, \
+                     i2, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab)
+  if (blk) {
+    if (mode == 0) ZLAUNCH(0, true);
+    else if (mode == 2) ZLAUNCH(2, true);
+    else if (mode == 3) ZLAUNCH(3, true);
+    else ZLAUNCH(1, true);
+  } else {
+    if (mode == 0) ZLAUNCH(0, false);
+    else if (mode == 2) ZLAUNCH(2, false);
+    else if (mode == 3) ZLAUNCH(3, false);
+    else ZLAUNCH(1, false);
+  }
+#undef ZLAUNCH
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -693,22 +688,12 @@ pm_status d_col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, c
   }
   return PM_ERR_SHAPE;
 }
-pm_status d_z_outer(const FftCtx& f, int sign, const float2* in, float2* out, const ZGeom& g,
-                    int64_t lanes, int64_t rows) {
+pm_status d_col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0,
+                      const float2* i1, const float2* i2, float2* o0, float2* o1,
+                      const Lines& d, int64_t L2) {
   switch (f.n) {
 #define CASE(N) \
-  case N: return z_outer<N>(f, sign, in, out, g, lanes, rows);
-    PM_FFT_SIZES(CASE)
-#undef CASE
-  }
-  return PM_ERR_SHAPE;
-}
-pm_status d_z_inner(const FftCtx& f, int mode, const float2* i0, const float2* i1,
-                    const float2* i2, float2* o0, float2* o1, const ZGeom& g, int64_t lanes,
-                    int64_t rows) {
-  switch (f.n) {
-#define CASE(N) \
-  case N: return z_inner<N>(f, mode, i0, i1, i2, o0, o1, g, lanes, rows);
+  case N: return col_zconv<N>(f, mode, blk, i0, i1, i2, o0, o1, d, L2);
     PM_FFT_SIZES(CASE)
 #undef CASE
   }
@@ -744,26 +729,22 @@ int64_t d_row_blocks(int n) {
   return 0;
 }
 
-// Line descriptors of the half-spectrum layout: main [z][y][kx < n/2] and the Nyquist
-// plane nyq[z][y] (kx = n/2).
+// Line descriptors of the z-blocked half spectrum (main, [z/ZB][y][z%ZB][kx < n/2]) and
+// of the Nyquist plane nyq[z][y] (kx = n/2).
 Lines lines_y_main(int n) {  // l1 = kx, l2 = z, element = y
-  int64_t M = n / 2;
-  return Lines{1, (int64_t)n * M, M, M, 0, 1, 0};
+  const int64_t M = n / 2, ZB = zblk(n);
+  return Lines{1, (int64_t)n * ZB * M, M, ilog2(ZB), ZB * M, 0, M, 0, 1, 0};
 }
 Lines lines_y_nyq(int n) {  // l1 = z, element = y
-  return Lines{n, 0, 1, n, 1, 1, n / 2};
+  return Lines{n, 0, 0, 0, 1, 0, n, 1, 1, n / 2};
 }
-// z sweeps over the main half spectrum (lanes kx < n/2, rows y) and the Nyquist plane
-// (lanes y).
-struct ZSweep {
-  ZGeom g;
-  int64_t lanes, rows;
-};
-ZSweep z_main(int n) {
-  int64_t M = n / 2;
-  return ZSweep{ZGeom{M, (int64_t)n * M, 0}, M, n};
+Lines lines_z_main(int n) {  // l1 = kx, l2 = y, element = z (blocked)
+  const int64_t M = n / 2, ZB = zblk(n);
+  return Lines{1, ZB * M, 0, 0, (int64_t)n * ZB * M, M, M, 0, 0, 0};
 }
-ZSweep z_nyq(int n) { return ZSweep{ZGeom{0, n, 1}, n, 1}; }
+Lines lines_z_nyq(int n) {  // l1 = y, element = z
+  return Lines{1, 0, 0, 0, n, 0, n, 1, 1, n / 2};
+}
 
 }  // namespace
 
@@ -789,6 +770,14 @@ pm_status build_kernel_table(pm_context* c) {
   return PM_OK;
 }
 
+// Buffers: A0, A1, A2 are the three force meshes (acc), S one scratch mesh; N0..N2 the
+// Nyquist planes. Spectra are z-blocked, real meshes natural, so the x passes are out of
+// place:
+//   r2c   rho -> A1                        (rho may be A0)
+//   Y     A1 in place
+//   Z     T1 = G F: A1 in place and T2 = -i k_z G F: A1 -> S, one launch
+//   Y^-1  U2 = IFFT_y(-i k_y T1): A1 -> A2;  U1 = IFFT_y(T1): A1;  U3 = IFFT_y(T2): S
+//   c2r   a_x = IFFT_x(-i k_x U1): A1 -> A0;  a_y: A2 -> A1;  a_z: S -> A2
 pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, float* amax) {
   const int n = (int)c->g.ng;
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
@@ -796,6 +785,8 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
   float2* A0 = (float2*)acc;
   float2* A1 = (float2*)(acc + n3);
   float2* A2 = (float2*)(acc + 2 * n3);
+  float2* S = (float2*)scratch(c, SC_SPEC, (size_t)n3 * sizeof(float));
+  if (!S) return PM_ERR_NOMEM;
   float2 *N0 = nyq, *N1 = nyq + n2, *N2 = nyq + 2 * n2;
   pm_status s;
   // per-block partial maxima of |a| of the three c2r launches
@@ -805,65 +796,43 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
     part = (unsigned int*)scratch(c, SC_PARTS, (size_t)3 * nrow_blocks * 4);
     if (!part) return PM_ERR_NOMEM;
   }
-  // X r2c (out of place allowed: rho -> acc x component)
   {
     ProfScope ps(c, ST_FFT_R2C);
-    if ((s = d_row_r2c(f, rho, A0, N0)) != PM_OK) return s;
+    if ((s = d_row_r2c(f, rho, A1, N0)) != PM_OK) return s;
   }
-  // Y forward
-  Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
+  const Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
+  const Lines zm = lines_z_main(n), zn = lines_z_nyq(n);
   {
     ProfScope ps(c, ST_FFT_YF);
-    if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, -1)) != PM_OK) return s;
+    if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, -1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
-  // Z: outer forward DFT, inner forward DFT x kernel x inverse inner DFT with the two
-  // outputs T1 = G F (in place) and T2 = -i k_z G F (into A2), outer inverse DFT of both
-  const ZSweep zm = z_main(n), zn = z_nyq(n);
   {
     ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_z_outer(f, -1, A0, A0, zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
+    if ((s = d_col_zconv(f, 3, true, A1, nullptr, nullptr, A1, S, zm, n)) != PM_OK) return s;
   }
-  {
-    ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_z_inner(f, 0, A0, nullptr, nullptr, A0, A2, zm.g, zm.lanes, zm.rows)) != PM_OK)
-      return s;
-  }
-  {
-    ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_z_outer(f, +1, A0, A0, zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
-  }
-  {
-    ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_z_outer(f, +1, A2, A2, zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
-  }
-  if ((s = d_z_outer(f, -1, N0, N0, zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
-  if ((s = d_z_inner(f, 0, N0, nullptr, nullptr, N0, N2, zn.g, zn.lanes, zn.rows)) != PM_OK)
-    return s;
-  if ((s = d_z_outer(f, +1, N0, N0, zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
-  if ((s = d_z_outer(f, +1, N2, N2, zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
-  // Y inverse: U2 = IFFT_y(-i k_y T1) -> A1 first (reads A0), then U1 in place, U3 in place
+  if ((s = d_col_zconv(f, 3, false, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
   {
     ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, A0, nullptr, A1, ym, n, +1)) != PM_OK) return s;
+    if ((s = d_col_fft(f, A1, nullptr, A2, ym, n, +1)) != PM_OK) return s;
   }
   {
     ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, A0, A0, nullptr, ym, n, +1)) != PM_OK) return s;
+    if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, +1)) != PM_OK) return s;
+  }
+  {
+    ProfScope ps(c, ST_FFT_YI);
+    if ((s = d_col_fft(f, S, S, nullptr, ym, n, +1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, nullptr, N1, yn, 1, +1)) != PM_OK) return s;
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, +1)) != PM_OK) return s;
-  {
-    ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, A2, A2, nullptr, ym, n, +1)) != PM_OK) return s;
-  }
   if ((s = d_col_fft(f, N2, N2, nullptr, yn, 1, +1)) != PM_OK) return s;
-  // X c2r
-  float2* outs[3] = {A0, A1, A2};
-  float2* nqs[3] = {N0, N1, N2};
+  const float2* ins[3] = {A1, A2, S};
+  float* outs[3] = {(float*)A0, (float*)A1, (float*)A2};
+  const float2* nqs[3] = {N0, N1, N2};
   for (int ax = 0; ax < 3; ++ax) {
     ProfScope ps(c, ST_FFT_C2R);
-    if ((s = d_row_c2r(f, outs[ax], nqs[ax], (float*)outs[ax], ax == 0 ? 1 : 0,
+    if ((s = d_row_c2r(f, ins[ax], nqs[ax], outs[ax], ax == 0 ? 1 : 0,
                        part ? part + ax * nrow_blocks : nullptr)) != PM_OK)
       return s;
   }
@@ -871,31 +840,32 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
   return PM_OK;
 }
 
+// nu = sum_a IDFT(+i k_a G DFT(mu_a)) with mu_a in A0..A2 (destroyed); nu lands in A0.
+//   r2c   mu_z: A2 -> S;  mu_y: A1 -> A2;  mu_x: A0 -> A1   (each followed by Y)
+//   Z     (A1, A2, S) -> A1;   Y^-1 A1;   c2r A1 -> A0
 pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
   const int n = (int)c->g.ng;
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
   FftCtx f{c, n, n - 1};
   float2* A[3] = {(float2*)acc, (float2*)(acc + n3), (float2*)(acc + 2 * n3)};
+  float2* S = (float2*)scratch(c, SC_SPEC, (size_t)n3 * sizeof(float));
+  if (!S) return PM_ERR_NOMEM;
   float2* Nq[3] = {nyq, nyq + n2, nyq + 2 * n2};
   pm_status s;
-  Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
-  const ZSweep zm = z_main(n), zn = z_nyq(n);
-  for (int ax = 0; ax < 3; ++ax) {
-    if ((s = d_row_r2c(f, (const float*)A[ax], A[ax], Nq[ax])) != PM_OK) return s;
-    if ((s = d_col_fft(f, A[ax], A[ax], nullptr, ym, n, -1)) != PM_OK) return s;
+  const Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
+  const Lines zm = lines_z_main(n), zn = lines_z_nyq(n);
+  float2* spec[3] = {A[1], A[2], S};  // spectrum of mu_x, mu_y, mu_z
+  for (int ax = 2; ax >= 0; --ax) {
+    if ((s = d_row_r2c(f, (const float*)A[ax], spec[ax], Nq[ax])) != PM_OK) return s;
+    if ((s = d_col_fft(f, spec[ax], spec[ax], nullptr, ym, n, -1)) != PM_OK) return s;
     if ((s = d_col_fft(f, Nq[ax], Nq[ax], nullptr, yn, 1, -1)) != PM_OK) return s;
-    if ((s = d_z_outer(f, -1, A[ax], A[ax], zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
-    if ((s = d_z_outer(f, -1, Nq[ax], Nq[ax], zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
   }
-  if ((s = d_z_inner(f, 1, A[0], A[1], A[2], A[0], nullptr, zm.g, zm.lanes, zm.rows)) != PM_OK)
-    return s;
-  if ((s = d_z_inner(f, 1, Nq[0], Nq[1], Nq[2], Nq[0], nullptr, zn.g, zn.lanes, zn.rows)) !=
+  if ((s = d_col_zconv(f, 1, true, spec[0], spec[1], spec[2], spec[0], nullptr, zm, n)) !=
       PM_OK)
     return s;
-  if ((s = d_z_outer(f, +1, A[0], A[0], zm.g, zm.lanes, zm.rows)) != PM_OK) return s;
-  if ((s = d_z_outer(f, +1, Nq[0], Nq[0], zn.g, zn.lanes, zn.rows)) != PM_OK) return s;
-  if ((s = d_col_fft(f, A[0], A[0], nullptr, ym, n, +1)) != PM_OK) return s;
+  if ((s = d_col_zconv(f, 1, false, Nq[0], Nq[1], Nq[2], Nq[0], nullptr, zn, 1)) != PM_OK)
+    return s;
+  if ((s = d_col_fft(f, spec[0], spec[0], nullptr, ym, n, +1)) != PM_OK) return s;
   if ((s = d_col_fft(f, Nq[0], Nq[0], nullptr, yn, 1, +1)) != PM_OK) return s;
-  if ((s = d_row_c2r(f, A[0], Nq[0], (float*)A[0], 0, nullptr)) != PM_OK) return s;
-  return PM_OK;
+  return d_row_c2r(f, spec[0], Nq[0], (float*)A[0], 0, nullptr);
 }

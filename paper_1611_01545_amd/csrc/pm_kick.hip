@@ -150,32 +150,56 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   const int64_t ox = (int64_t)bcx * r, oy = (int64_t)bcy * r, oz = (int64_t)bcz * r;
   if constexpr (STAGE) {
     // rows of RS nodes (x) as float4 loads, then the x = RS halo column; node (lz, ly)
-    // of component c is row (c R1 + lz) R1 + ly
+    // of component c is row (c R1 + lz) R1 + ly. Every load of a thread is issued
+    // before the first LDS write, so the loads of the tile are in flight together.
     static_assert(RS % 4 == 0, "staged tile side must be a multiple of 4");
     constexpr int ROWS = 3 * R1 * R1;
     constexpr int Q = RS / 4;  // float4 per row
+    constexpr int NQ = ROWS * Q;
+    constexpr int PQ = (NQ + KB - 1) / KB;    // float4 loads per thread
+    constexpr int PH = (ROWS + KB - 1) / KB;  // halo loads per thread
     const bool wrapx = ox + RS >= ng;
-    for (int i = threadIdx.x; i < ROWS * Q; i += KB) {
+    float4 vq[PQ];
+    float vh[PH];
+    // indexes past the end are clamped to the last element (a duplicate load, not
+    // stored), so no load sits behind a branch
+#pragma unroll
+    for (int k = 0; k < PQ; ++k) {
+      const int i = min((int)threadIdx.x + k * KB, NQ - 1);
       const int row = i / Q, q = i - row * Q;
       const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
       const int lz = rem / R1, ly = rem - lz * R1;
       int64_t gz = oz + lz, gy = oy + ly;
       gz -= gz >= ng ? ng : 0;
       gy -= gy >= ng ? ng : 0;
-      const float4 v = *(const float4*)(A.acc + (int64_t)c * n3 + (gz * ng + gy) * ng + ox + 4 * q);
-      float* d = F + row * R1 + 4 * q;
-      d[0] = v.x;
-      d[1] = v.y;
-      d[2] = v.z;
-      d[3] = v.w;
+      vq[k] = *(const float4*)(A.acc + (int64_t)c * n3 + (gz * ng + gy) * ng + ox + 4 * q);
     }
-    for (int row = threadIdx.x; row < ROWS; row += KB) {
+#pragma unroll
+    for (int k = 0; k < PH; ++k) {
+      const int row = min((int)threadIdx.x + k * KB, ROWS - 1);
       const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
       const int lz = rem / R1, ly = rem - lz * R1;
       int64_t gz = oz + lz, gy = oy + ly, gx = wrapx ? 0 : ox + RS;
       gz -= gz >= ng ? ng : 0;
       gy -= gy >= ng ? ng : 0;
-      F[row * R1 + RS] = A.acc[(int64_t)c * n3 + (gz * ng + gy) * ng + gx];
+      vh[k] = A.acc[(int64_t)c * n3 + (gz * ng + gy) * ng + gx];
+    }
+#pragma unroll
+    for (int k = 0; k < PQ; ++k) {
+      const int i = threadIdx.x + k * KB;
+      if (i < NQ) {
+        const int row = i / Q, q = i - row * Q;
+        float* d = F + row * R1 + 4 * q;
+        d[0] = vq[k].x;
+        d[1] = vq[k].y;
+        d[2] = vq[k].z;
+        d[3] = vq[k].w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PH; ++k) {
+      const int row = threadIdx.x + k * KB;
+      if (row < ROWS) F[row * R1 + RS] = vh[k];
     }
   }
   const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
@@ -204,6 +228,13 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
           int mid = (lo + hi) >> 1;
           if (loff[mid] <= j) lo = mid; else hi = mid;
         }
+        // the particle's codes, loaded before any store of this thread
+        uint32_t pb[3], vc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          pb[a] = S.pos[3 * j + a];
+          vc[a] = S.vel[3 * j + a];
+        }
         uint32_t cx, cy, cz;
         key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
         const uint32_t cell[3] = {cx, cy, cz};
@@ -213,7 +244,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
         float f[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          u[a] = (cell[a] << 8) | S.pos[3 * j + a];
+          u[a] = (cell[a] << 8) | pb[a];
           const int64_t gg = (2 * (int64_t)u[a] + 1) * r;  // 1/512 mesh cells
           li[a] = (int)((gg >> 9) - org[a]);               // node index inside the brick
           f[a] = (float)(gg & 511) * (1.0f / 512.0f);
@@ -246,7 +277,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
         uint32_t un[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const float v0 = vel_decode(S.vel[3 * j + a], vmax_in);
+          const float v0 = vel_decode(vc[a], vmax_in);
           const float v1 = v0 + A.ck * acc3[a];
           const double d = floor((double)v1 * A.cdS + 0.5);
           const bool okd = fabs(d) < 4.0e15;
