@@ -15,9 +15,11 @@
 //
 // Compressed states are differentiated straight-through at the decoded bin centres;
 // the forward re-sort is recomputed to map the new stream order of the cotangents back
-// to the old order. The scatter uses float atomics (summation order not fixed).
+// to the old order. The scatter sums with float atomics (summation order not fixed).
 #include "pm_codec.h"
+#include "pm_scan.h"
 
+int deposit_tile_cells(const Geom& g);
 pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
                                   int n_sp, int64_t* const* offs, const float* acc,
                                   const float* amax, double ck, double cd,
@@ -168,6 +170,272 @@ __global__ void k_zero_f32(float* p, int64_t n) {
   if (i < n) p[i] = 0.f;
 }
 
+// ------------------------------------------------ compressed layout, tiled --
+// The scatter mu_a(c) = c_k sum_j W(x_j - x_c) g_v,ja and the gradient gather read the
+// particles' compressed codes directly (cell-sorted streams), like the deposit and the
+// kick: exact CIC weights from the codes, no decoded positions in HBM.
+constexpr int MAXSP = 4;
+constexpr int ST = 256;  // scatter threads per workgroup
+
+struct AdjSpecies {
+  int64_t n;
+  const uint8_t* pos;
+  const int64_t* off;  // cell offsets [ncell3 + 1]
+  const float* gv;     // g_v = dL/dv per particle, stream order
+  float* lx;           // dL/dx per particle, stream order (gather adds to it)
+  float sscale;        // m n^3 (density per unit weight)
+};
+struct AdjArgs {
+  AdjSpecies sp[MAXSP];
+  int n_sp;
+  float ck;
+};
+
+__device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// One workgroup per tile of TT^3 cells = 16^3 mesh nodes (r = 16 / TT), the three mu
+// components summed in LDS (float atomics) and written with plain stores: every node
+// has one owner. Particles of the one-cell shell on the -x/-y/-z faces reach the tile's
+// lowest node plane and are included, as in the deposit.
+template <int TT>
+__global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* mu) {
+  constexpr int T = TT, R = 16, r = 16 / TT, E = T + 1, NE = E * E * E, R3 = R * R * R;
+  __shared__ float F[3 * R3];
+  __shared__ int64_t cst[NE];
+  __shared__ int pre[NE + 1];
+  __shared__ int64_t lw[ST / 64 + 1];
+  const int nt = (int)(g.nc / T);
+  const int64_t tile = xcd_tile(blockIdx.x, (int64_t)nt * nt * nt);
+  const int tx = (int)(tile % nt), ty = (int)((tile / nt) % nt),
+            tz = (int)(tile / ((int64_t)nt * nt));
+  const int ncs = (int)g.nc;
+  for (int i = threadIdx.x; i < 3 * R3; i += ST) F[i] = 0.f;
+  for (int s = 0; s < A.n_sp; ++s) {
+    const AdjSpecies sp = A.sp[s];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += ST) {
+      const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+      const int cx = wrapc(tx * T + ex - 1, ncs), cy = wrapc(ty * T + ey - 1, ncs),
+                cz = wrapc(tz * T + ez - 1, ncs);
+      const uint32_t key = cell_key(g, cx, cy, cz);
+      const int64_t o0 = sp.off[key], o1 = sp.off[key + 1];
+      cst[e] = o0;
+      pre[e + 1] = (int)(o1 - o0);
+    }
+    __syncthreads();
+    {
+      constexpr int K = (NE + ST - 1) / ST;
+      const int e0 = 1 + threadIdx.x * K;
+      int loc = 0;
+      for (int k = 0; k < K; ++k)
+        if (e0 + k <= NE) loc += pre[e0 + k];
+      int base = (int)pmscan::block_excl_scan(loc, lw, nullptr);
+      for (int k = 0; k < K; ++k)
+        if (e0 + k <= NE) {
+          base += pre[e0 + k];
+          pre[e0 + k] = base;
+        }
+      if (threadIdx.x == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    const int P = pre[NE];
+    constexpr int U = 4;
+    for (int q0 = threadIdx.x; q0 < P; q0 += ST * U) {
+      int eu[U];
+      int64_t ju[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * ST;
+        int lo = 0, hi = NE;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (pre[mid] <= q) lo = mid; else hi = mid;
+        }
+        eu[u] = lo;
+        const int64_t j = cst[lo] + (q - pre[lo]);
+        ok[u] = q < P && j < sp.n;
+        ju[u] = ok[u] ? j : 0;  // n > 0 whenever P > 0
+      }
+      uint32_t pb[U][3];
+      float gg[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          pb[u][a] = sp.pos[3 * ju[u] + a];
+          gg[u][a] = sp.gv[3 * ju[u] + a];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        const int e = eu[u];
+        const int le[3] = {e % E - 1, (e / E) % E - 1, e / (E * E) - 1};
+        int li[3], f[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int gl = (2 * (int)pb[u][a] + 1) * r;  // 1/512 mesh cells
+          li[a] = le[a] * r + (gl >> 9);
+          f[a] = gl & 511;
+        }
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+          const int nz = li[2] + dz, wz = dz ? f[2] : 512 - f[2];
+          if (nz < 0 || nz >= R || wz == 0) continue;
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            const int ny = li[1] + dy, wy = dy ? f[1] : 512 - f[1];
+            if (ny < 0 || ny >= R || wy == 0) continue;
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+              const int nx = li[0] + dx, wx = dx ? f[0] : 512 - f[0];
+              if (nx < 0 || nx >= R || wx == 0) continue;
+              const float w = (float)((uint32_t)(wx * wy) * (uint32_t)wz) * 0x1p-27f;
+              const int node = (nz * R + ny) * R + nx;
+              atomicAdd(&F[node], w * gg[u][0]);
+              atomicAdd(&F[R3 + node], w * gg[u][1]);
+              atomicAdd(&F[2 * R3 + node], w * gg[u][2]);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // node i = threadIdx.x + 256 k: lx = i & 15, ly = (i >> 4) & 15, lz = k
+  const int64_t ng = g.ng, ng2 = ng * ng, n3 = ng2 * ng;
+  float* dst = mu + (int64_t)tz * 16 * ng2 + ((int64_t)ty * 16 + ((threadIdx.x >> 4) & 15)) * ng +
+               (int64_t)tx * 16 + (threadIdx.x & 15);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < R3 / ST; ++k)
+      dst[c * n3 + k * ng2] = A.ck * F[c * R3 + threadIdx.x + k * ST];
+}
+
+// Gradient gather on bricks of B^3 cells = 16^3 nodes: the four meshes a_x, a_y, a_z
+// and nu are staged for the nodes [0, 16]^3 of the brick, then for every particle of the
+// brick's cells lx += sum_c grad W(x - x_c) [c_k g_v . a(c) + m n^3 nu(c)].
+constexpr int GT = 512;  // gather threads per workgroup
+constexpr int GR = 16, GR1 = GR + 1;
+
+__global__ __launch_bounds__(GT) void k_gather_brick(AdjArgs A, Geom g, const float* acc,
+                                                     const float* nu) {
+  constexpr int FS = GR1 * GR1 * GR1;
+  __shared__ float Fm[4 * FS];  // a_x, a_y, a_z, nu on the brick's nodes
+  __shared__ int64_t loff[8 * 8 * 8 + 1];
+  const int B = g.B, B3 = B * B * B, r = g.r;
+  const int64_t b = xcd_tile(blockIdx.x, g.nbrick);
+  const uint32_t kbase = (uint32_t)(b * B3);
+  const int64_t ng = g.ng, n3 = ng * ng * ng;
+  uint32_t bcx, bcy, bcz;
+  key_cell(g, kbase, bcx, bcy, bcz);
+  const int64_t ox = (int64_t)bcx * r, oy = (int64_t)bcy * r, oz = (int64_t)bcz * r;
+  {
+    // rows of 16 nodes as float4 loads plus the x = 16 halo column; all loads of a
+    // thread are issued before its LDS writes
+    constexpr int ROWS = 4 * GR1 * GR1, NQ = ROWS * 4;
+    constexpr int PQ = (NQ + GT - 1) / GT, PH = (ROWS + GT - 1) / GT;
+    const bool wrapx = ox + GR >= ng;
+    float4 vq[PQ];
+    float vh[PH];
+#pragma unroll
+    for (int k = 0; k < PQ; ++k) {
+      const int i = min((int)threadIdx.x + k * GT, NQ - 1);
+      const int row = i >> 2, q = i & 3;
+      const int c = row / (GR1 * GR1), rem = row - c * (GR1 * GR1);
+      const int lz = rem / GR1, ly = rem - lz * GR1;
+      int64_t gz = oz + lz, gy = oy + ly;
+      gz -= gz >= ng ? ng : 0;
+      gy -= gy >= ng ? ng : 0;
+      const float* src = c < 3 ? acc + (int64_t)c * n3 : nu;
+      vq[k] = *(const float4*)(src + (gz * ng + gy) * ng + ox + 4 * q);
+    }
+#pragma unroll
+    for (int k = 0; k < PH; ++k) {
+      const int row = min((int)threadIdx.x + k * GT, ROWS - 1);
+      const int c = row / (GR1 * GR1), rem = row - c * (GR1 * GR1);
+      const int lz = rem / GR1, ly = rem - lz * GR1;
+      int64_t gz = oz + lz, gy = oy + ly;
+      gz -= gz >= ng ? ng : 0;
+      gy -= gy >= ng ? ng : 0;
+      const float* src = c < 3 ? acc + (int64_t)c * n3 : nu;
+      vh[k] = src[(gz * ng + gy) * ng + (wrapx ? 0 : ox + GR)];
+    }
+#pragma unroll
+    for (int k = 0; k < PQ; ++k) {
+      const int i = threadIdx.x + k * GT;
+      if (i < NQ) {
+        float* d = Fm + (i >> 2) * GR1 + 4 * (i & 3);
+        d[0] = vq[k].x;
+        d[1] = vq[k].y;
+        d[2] = vq[k].z;
+        d[3] = vq[k].w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PH; ++k) {
+      const int row = threadIdx.x + k * GT;
+      if (row < ROWS) Fm[row * GR1 + GR] = vh[k];
+    }
+  }
+  const float fn = (float)ng;
+  for (int s = 0; s < A.n_sp; ++s) {
+    const AdjSpecies sp = A.sp[s];
+    __syncthreads();  // staged meshes ready / previous species done with loff
+    for (int i = threadIdx.x; i <= B3; i += GT) loff[i] = sp.off[kbase + i];
+    __syncthreads();
+    const int64_t j0 = min(loff[0], sp.n), j1 = min(loff[B3], sp.n);
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += GT) {
+      uint32_t pb[3];
+      float gvv[3], lxx[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pb[a] = sp.pos[3 * j + a];
+        gvv[a] = sp.gv[3 * j + a];
+        lxx[a] = sp.lx[3 * j + a];
+      }
+      int lo = 0, hi = B3;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (loff[mid] <= j) lo = mid; else hi = mid;
+      }
+      uint32_t cx, cy, cz;
+      key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
+      const uint32_t cell[3] = {cx, cy, cz};
+      const int64_t org[3] = {ox, oy, oz};
+      int li[3];
+      float f[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t gg = (2 * (int64_t)((cell[a] << 8) | pb[a]) + 1) * r;  // 1/512 cells
+        li[a] = (int)((gg >> 9) - org[a]);
+        f[a] = (float)(gg & 511) * (1.0f / 512.0f);
+      }
+      const float g0 = A.ck * gvv[0], g1 = A.ck * gvv[1], g2 = A.ck * gvv[2];
+      float gr[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int node = ((li[2] + dz) * GR1 + (li[1] + dy)) * GR1 + (li[0] + dx);
+            const float val = g0 * Fm[node] + g1 * Fm[FS + node] + g2 * Fm[2 * FS + node] +
+                              sp.sscale * Fm[3 * FS + node];
+            const float wx = dx ? f[0] : 1.f - f[0];
+            const float wy = dy ? f[1] : 1.f - f[1];
+            const float wz = dz ? f[2] : 1.f - f[2];
+            gr[0] += (dx ? fn : -fn) * wy * wz * val;
+            gr[1] += (dy ? fn : -fn) * wx * wz * val;
+            gr[2] += (dz ? fn : -fn) * wx * wy * val;
+          }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sp.lx[3 * j + a] = lxx[a] + gr[a];
+    }
+  }
+}
+
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Float positions of every species (decoded bin centres for compressed states) and,
@@ -178,13 +446,22 @@ struct Positions {
 };
 
 pm_status positions(pm_context* c, const pm_species* sp, int n_sp, int scratch_id,
-                    Positions& P) {
+                    Positions& P, bool decode = true) {
   pm_status s;
   for (int i = 0; i < n_sp; ++i) {
     P.x[i] = sp[i].x;
     P.offs[i] = nullptr;
   }
   if (sp[0].layout != PM_COMPRESSED) return PM_OK;
+  if (!decode) {
+    for (int i = 0; i < n_sp; ++i) {
+      P.x[i] = nullptr;
+      P.offs[i] = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+      if (!P.offs[i]) return PM_ERR_NOMEM;
+      if ((s = run_cell_offsets(c, &sp[i], P.offs[i])) != PM_OK) return s;
+    }
+    return PM_OK;
+  }
   size_t bytes = 0;
   for (int i = 0; i < n_sp; ++i) bytes += 2 * align256((size_t)sp[i].n * 12);
   char* pool = (char*)scratch(c, scratch_id, bytes);
@@ -222,8 +499,14 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
   const int64_t ng = c->g.ng, n3 = ng * ng * ng;
   const float ck = (float)dt, cd = (float)dt;
   pm_status s;
+  // compressed states with 16-node tiles and bricks use the tiled scatter and gather on
+  // the codes; other shapes and float states decode and use the per-particle kernels
+  const Geom& g = c->g;
+  const bool comp = in[0].layout == PM_COMPRESSED;
+  const int tt = comp ? deposit_tile_cells(g) : 0;
+  const bool tiled = comp && tt * g.r == 16 && (tt == 4 || tt == 8) && g.B * g.r == 16;
   Positions P;
-  if ((s = positions(c, in, n_sp, SC_VJP2, P)) != PM_OK) return s;
+  if ((s = positions(c, in, n_sp, SC_VJP2, P, !tiled)) != PM_OK) return s;
   // forward recomputation: density, acceleration mesh (in the context mesh)
   float* acc = c->mesh;
   if ((s = deposit_all(c, in, n_sp, P, acc)) != PM_OK) return s;
@@ -267,17 +550,42 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
   // cotangents into old order; g_v lands in lv0
   float* mu = (float*)scratch(c, SC_VJP, (size_t)3 * n3 * sizeof(float));
   if (!mu) return PM_ERR_NOMEM;
+  AdjArgs T{};
+  T.ck = ck;
+  for (int i = 0; i < n_sp; ++i) {
+    if (in[i].n == 0) continue;
+    AdjSpecies& a = T.sp[T.n_sp++];
+    a.n = in[i].n;
+    a.pos = in[i].pos;
+    a.off = P.offs[i];
+    a.gv = lv0[i];
+    a.lx = lx0[i];
+    a.sscale = (float)(in[i].mass * (double)n3);
+  }
   {
     ProfScope ps(c, ST_ADJOINT);
-    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)cdiv(3 * n3, AT)), dim3(AT), 0, c->stream,
-                       mu, 3 * n3);
+    if (!tiled)
+      hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)cdiv(3 * n3, AT)), dim3(AT), 0,
+                         c->stream, mu, 3 * n3);
     for (int i = 0; i < n_sp; ++i) {
       if (in[i].n == 0) continue;
       const unsigned nb = (unsigned)cdiv(in[i].n, AT);
       hipLaunchKernelGGL(k_vjp_init, dim3(nb), dim3(AT), 0, c->stream, lx1[i], lv1[i],
                          perm[i], in[i].n, cd, lx0[i], lv0[i]);
-      hipLaunchKernelGGL(k_scatter_vec, dim3(nb), dim3(AT), 0, c->stream, P.x[i], lv0[i],
-                         in[i].n, ng, ck, mu);
+      if (!tiled)
+        hipLaunchKernelGGL(k_scatter_vec, dim3(nb), dim3(AT), 0, c->stream, P.x[i], lv0[i],
+                           in[i].n, ng, ck, mu);
+    }
+    if (tiled && T.n_sp > 0) {
+      const int64_t nt = g.nc / tt;
+      const dim3 grid((unsigned)(nt * nt * nt));
+      if (tt == 4)
+        hipLaunchKernelGGL(k_scatter_tile<4>, grid, dim3(ST), 0, c->stream, T, g, mu);
+      else
+        hipLaunchKernelGGL(k_scatter_tile<8>, grid, dim3(ST), 0, c->stream, T, g, mu);
+    } else if (tiled) {
+      hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)cdiv(3 * n3, AT)), dim3(AT), 0,
+                         c->stream, mu, 3 * n3);
     }
     PM_LAUNCH_CHECK();
   }
@@ -287,12 +595,18 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
   }
   {
     ProfScope ps(c, ST_ADJOINT);
-    for (int i = 0; i < n_sp; ++i) {
-      if (in[i].n == 0) continue;
-      const float sscale = (float)(in[i].mass * (double)n3);
-      hipLaunchKernelGGL(k_gather_grad, dim3((unsigned)cdiv(in[i].n, AT)), dim3(AT), 0,
-                         c->stream, P.x[i], in[i].n, ng, mu, sscale, acc, lv0[i], ck, lx0[i],
-                         1);
+    if (tiled) {
+      if (T.n_sp > 0)
+        hipLaunchKernelGGL(k_gather_brick, dim3((unsigned)g.nbrick), dim3(GT), 0, c->stream,
+                           T, g, acc, mu);
+    } else {
+      for (int i = 0; i < n_sp; ++i) {
+        if (in[i].n == 0) continue;
+        const float sscale = (float)(in[i].mass * (double)n3);
+        hipLaunchKernelGGL(k_gather_grad, dim3((unsigned)cdiv(in[i].n, AT)), dim3(AT), 0,
+                           c->stream, P.x[i], in[i].n, ng, mu, sscale, acc, lv0[i], ck,
+                           lx0[i], 1);
+      }
     }
     PM_LAUNCH_CHECK();
   }

@@ -374,28 +374,27 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
   } else {
+    // sum_a (+i k_a) FFT_z(in_a): k_x and k_y are constant along a z line, so their two
+    // terms are one transform of +i (k_x in0 + k_y in1); k_z multiplies after FFT_z(in2)
     const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
 #pragma unroll
-    for (int i = 0; i < P::E; ++i) acc[i] = make_float2(0.f, 0.f);
-    const float2* ins[3] = {in0, in1, in2};
+    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = in2[base + n1 * step];
+    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      float2 f[P::E];
+    for (int v = 0; v < P::V; ++v)
 #pragma unroll
-      for (int n1 = 0; n1 < P::E; ++n1) f[n1] = ins[ax][base + n1 * step];
-      nat_to_tr<N, -1>(f, t, my, tw, tws, twmask);
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const float k = grad_k((t + P::T * v) + P::E * k2, n);
+        const float2 q = acc[v * P::T + k2];
+        acc[v * P::T + k2] = make_float2(-k * q.y, k * q.x);  // + i k (x + i y)
+      }
+    float2 f[P::E];
 #pragma unroll
-      for (int v = 0; v < P::V; ++v)
-#pragma unroll
-        for (int k2 = 0; k2 < P::T; ++k2) {
-          const int kz = (t + P::T * v) + P::E * k2;
-          const float k = ax == 0 ? kxg : ax == 1 ? kyg : grad_k(kz, n);
-          const float2 q = f[v * P::T + k2];
-          // + i k (x + i y) = -k y + i k x
-          acc[v * P::T + k2].x += -k * q.y;
-          acc[v * P::T + k2].y += k * q.x;
-        }
+    for (int n1 = 0; n1 < P::E; ++n1) {
+      const float2 a = in0[base + n1 * step], b2 = in1[base + n1 * step];
+      f[n1] = make_float2(-(kxg * a.y + kyg * b2.y), kxg * a.x + kyg * b2.x);
     }
+    nat_to_tr<N, -1>(f, t, my, tw, tws, twmask);
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
@@ -403,8 +402,8 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
         const int kz = (t + P::T * v) + P::E * k2;
         const int sz = signed_k(kz, n);
         const float G = ktab[nxy2 + sz * sz];
-        acc[v * P::T + k2].x *= G;
-        acc[v * P::T + k2].y *= G;
+        const float2 q = acc[v * P::T + k2], p = f[v * P::T + k2];
+        acc[v * P::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
       }
     tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
 #pragma unroll

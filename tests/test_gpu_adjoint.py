@@ -49,8 +49,11 @@ def test_step_vjp_float_matches_oracle(n_mesh, n_p):
     c.close()
 
 
-def test_step_vjp_compressed_two_species_matches_oracle():
-    wl = small_two_species(n_p_c=16, n_mesh=32)
+# (n_mesh, n_cell): 16-node tiles of 8 cells (r = 2), of 4 cells (r = 4), and a shape
+# that takes the per-particle fallback (r = 1)
+@pytest.mark.parametrize("n_mesh,n_cell", [(32, 16), (64, 16), (32, 32)])
+def test_step_vjp_compressed_two_species_matches_oracle(n_mesh, n_cell):
+    wl = small_two_species(n_p_c=16, n_mesh=n_mesh, n_cell=n_cell)
     c = ctx(wl.n_mesh, wl.n_cell)
     st = [c.encode(c.float_species(s.x, s.v, s.mass)) for s in wl.species]
     host = [c.to_host(s) for s in st]
