@@ -125,20 +125,22 @@ struct KickArgs {
 // One workgroup per brick, all species. With STAGE the brick's force nodes
 // [b R, b R + R]^3 (R = B r) are first copied to LDS with coalesced loads and every
 // particle gathers its 8 CIC nodes from there; the mesh is then read once per step
-// for all species.
+// for all species. The global reads of a workgroup form two rounds: (1) the force
+// tile, every species' cell offsets and velocity headers; (2) the codes of the first
+// chunk of every species. Only species with more than KB particles in the brick load
+// later chunks on the way.
 template <int RS>  // staged tile side in nodes (compile time), or 0: gather from HBM
 __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* err) {
   constexpr bool STAGE = RS > 0;
   const int B = g.B, B3 = B * B * B;
-  const int R = STAGE ? RS : B * g.r;
   constexpr int R1 = RS + 1;
   const int r = g.r;
   extern __shared__ unsigned char smem[];
-  float* F = (float*)smem;                                   // [3][R1^3] when STAGE
+  float* F = (float*)smem;                                     // [3][R1^3] when STAGE
   const int fsz = STAGE ? 3 * R1 * R1 * R1 : 0;
-  int64_t* loff = (int64_t*)(smem + ((fsz * 4 + 7) / 8) * 8);  // [B3 + 1]
-  uint32_t* run = (uint32_t*)(loff + B3 + 1);                // [B3 + 1] (B3 = movers)
-  uint32_t* wcnt = run + (B3 + 1);                           // [KB/64][B3 + 1]
+  int64_t* loffs = (int64_t*)(smem + ((fsz * 4 + 7) / 8) * 8);  // [MAXSP][B3 + 1]
+  uint32_t* run = (uint32_t*)(loffs + MAXSP * (B3 + 1));       // [B3 + 1] (B3 = movers)
+  uint32_t* wcnt = run + (B3 + 1);                             // [KB/64][B3 + 1]
   constexpr int NW = KB / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
@@ -148,41 +150,59 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   uint32_t bcx, bcy, bcz;  // first cell of the brick
   key_cell(g, kbase, bcx, bcy, bcz);
   const int64_t ox = (int64_t)bcx * r, oy = (int64_t)bcy * r, oz = (int64_t)bcz * r;
+  const int n_sp = A.n_sp;
+
+  // ---- round 1: cell offsets of every species, velocity headers, force tile
+  const int NL = n_sp * (B3 + 1);
+  int64_t lof[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int i = threadIdx.x + k * KB;
+    if (i < NL) {
+      const int s = i / (B3 + 1);
+      lof[k] = A.sp[s].off[kbase + (i - s * (B3 + 1))];
+    }
+  }
+  for (int i = threadIdx.x + 2 * KB; i < NL; i += KB) {  // more than 2 KB entries
+    const int s = i / (B3 + 1);
+    loffs[i] = A.sp[s].off[kbase + (i - s * (B3 + 1))];
+  }
+  float vin[MAXSP], vout[MAXSP];
+#pragma unroll
+  for (int s = 0; s < MAXSP; ++s) {
+    vin[s] = s < n_sp ? A.sp[s].hin->v_max : 0.f;
+    vout[s] = s < n_sp ? A.sp[s].hout->v_max : 0.f;
+  }
   if constexpr (STAGE) {
     // rows of RS nodes (x) as float4 loads, then the x = RS halo column; node (lz, ly)
-    // of component c is row (c R1 + lz) R1 + ly. Every load of a thread is issued
-    // before the first LDS write, so the loads of the tile are in flight together.
+    // of component c is row (c R1 + lz) R1 + ly. Indexes past the end are clamped to
+    // the last element (a duplicate load, not stored), so no load sits behind a branch.
     static_assert(RS % 4 == 0, "staged tile side must be a multiple of 4");
     constexpr int ROWS = 3 * R1 * R1;
     constexpr int Q = RS / 4;  // float4 per row
     constexpr int NQ = ROWS * Q;
     constexpr int PQ = (NQ + KB - 1) / KB;    // float4 loads per thread
     constexpr int PH = (ROWS + KB - 1) / KB;  // halo loads per thread
-    const bool wrapx = ox + RS >= ng;
+    const int64_t m = ng - 1;                 // ng is a power of two
+    const int64_t hx = (ox + RS) & m;
     float4 vq[PQ];
     float vh[PH];
-    // indexes past the end are clamped to the last element (a duplicate load, not
-    // stored), so no load sits behind a branch
 #pragma unroll
     for (int k = 0; k < PQ; ++k) {
       const int i = min((int)threadIdx.x + k * KB, NQ - 1);
       const int row = i / Q, q = i - row * Q;
       const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
       const int lz = rem / R1, ly = rem - lz * R1;
-      int64_t gz = oz + lz, gy = oy + ly;
-      gz -= gz >= ng ? ng : 0;
-      gy -= gy >= ng ? ng : 0;
-      vq[k] = *(const float4*)(A.acc + (int64_t)c * n3 + (gz * ng + gy) * ng + ox + 4 * q);
+      const int64_t gz = (oz + lz) & m, gy = (oy + ly) & m;
+      vq[k] = *(const float4*)(A.acc + c * n3 + (gz * ng + gy) * ng + ox + 4 * q);
     }
 #pragma unroll
     for (int k = 0; k < PH; ++k) {
       const int row = min((int)threadIdx.x + k * KB, ROWS - 1);
       const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
       const int lz = rem / R1, ly = rem - lz * R1;
-      int64_t gz = oz + lz, gy = oy + ly, gx = wrapx ? 0 : ox + RS;
-      gz -= gz >= ng ? ng : 0;
-      gy -= gy >= ng ? ng : 0;
-      vh[k] = A.acc[(int64_t)c * n3 + (gz * ng + gy) * ng + gx];
+      const int64_t gz = (oz + lz) & m, gy = (oy + ly) & m;
+      vh[k] = A.acc[c * n3 + (gz * ng + gy) * ng + hx];
     }
 #pragma unroll
     for (int k = 0; k < PQ; ++k) {
@@ -202,19 +222,42 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       if (row < ROWS) F[row * R1 + RS] = vh[k];
     }
   }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int i = threadIdx.x + k * KB;
+    if (i < NL) loffs[i] = lof[k];
+  }
+  __syncthreads();
+
+  // ---- round 2: codes of the first chunk of every species
+  uint32_t pre_pb[MAXSP][3], pre_vc[MAXSP][3];
+#pragma unroll
+  for (int s = 0; s < MAXSP; ++s) {
+    const int64_t* lo = loffs + s * (B3 + 1);
+    const bool have = s < n_sp;
+    const int64_t n = have ? A.sp[s].n : 0;
+    const int64_t j0 = have ? min(lo[0], n) : 0, j1 = have ? min(lo[B3], n) : 0;
+    const int64_t j = j0 + threadIdx.x;
+    const int64_t jj = j < j1 ? j : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pre_pb[s][a] = j < j1 ? A.sp[s].pos[3 * jj + a] : 0u;
+      pre_vc[s][a] = j < j1 ? A.sp[s].vel[3 * jj + a] : 0u;
+    }
+  }
+
   const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
   bool bad = false;
-  for (int s = 0; s < A.n_sp; ++s) {
+#pragma unroll
+  for (int s = 0; s < MAXSP; ++s) {
+    if (s >= n_sp) break;
     const KickSpecies& S = A.sp[s];
-    __syncthreads();  // F loaded / previous species done with loff, run
-    for (int i = threadIdx.x; i <= B3; i += KB) {
-      loff[i] = S.off[kbase + i];
-      run[i] = 0;
-    }
-    __syncthreads();
+    const int64_t* loff = loffs + s * (B3 + 1);
+    __syncthreads();  // previous species done with run
+    for (int i = threadIdx.x; i <= B3; i += KB) run[i] = 0;
     const int64_t j0 = min(loff[0], S.n), j1 = min(loff[B3], S.n);
-    const float vmax_in = S.hin->v_max;
-    const float vmax_out = S.hout->v_max;
+    const float vmax_in = vin[s];
+    const float vmax_out = vout[s];
     int jmin = 65536, jmax = -1;
     for (int64_t base = j0; base < j1; base += KB) {
       for (int i = threadIdx.x; i < NW * (B3 + 1); i += KB) wcnt[i] = 0;
@@ -223,17 +266,25 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       const bool valid = j < j1;
       uint32_t digit = 0, newkey = 0;
       if (valid) {
+        // the particle's codes: prefetched for the first chunk
+        uint32_t pb[3], vc[3];
+        if (base == j0) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            pb[a] = pre_pb[s][a];
+            vc[a] = pre_vc[s][a];
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            pb[a] = S.pos[3 * j + a];
+            vc[a] = S.vel[3 * j + a];
+          }
+        }
         int lo = 0, hi = B3;  // local cell: largest l with loff[l] <= j
         while (hi - lo > 1) {
           int mid = (lo + hi) >> 1;
           if (loff[mid] <= j) lo = mid; else hi = mid;
-        }
-        // the particle's codes, loaded before any store of this thread
-        uint32_t pb[3], vc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          pb[a] = S.pos[3 * j + a];
-          vc[a] = S.vel[3 * j + a];
         }
         uint32_t cx, cy, cz;
         key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
@@ -264,10 +315,9 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
                 acc3[1] += wgt * F[R1 * R1 * R1 + node];
                 acc3[2] += wgt * F[2 * R1 * R1 * R1 + node];
               } else {
-                int64_t nz = oz + li[2] + dz, ny = oy + li[1] + dy, nx = ox + li[0] + dx;
-                nz -= nz >= ng ? ng : 0;
-                ny -= ny >= ng ? ng : 0;
-                nx -= nx >= ng ? ng : 0;
+                const int64_t m = ng - 1;
+                const int64_t nz = (oz + li[2] + dz) & m, ny = (oy + li[1] + dy) & m,
+                              nx = (ox + li[0] + dx) & m;
                 const int64_t node = (nz * ng + ny) * ng + nx;
                 acc3[0] += wgt * A.acc[node];
                 acc3[1] += wgt * A.acc[n3 + node];
@@ -297,8 +347,8 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       // stable multi-split of this chunk by digit (new local cell, or B3 for movers)
       uint64_t match = __ballot(valid);
       for (int bit = 0; bit < nbits; ++bit) {
-        uint64_t m = __ballot(valid && ((digit >> bit) & 1u));
-        match &= ((digit >> bit) & 1u) ? m : ~m;
+        uint64_t mm = __ballot(valid && ((digit >> bit) & 1u));
+        match &= ((digit >> bit) & 1u) ? mm : ~mm;
       }
       const uint32_t rk = (uint32_t)__popcll(match & lt);
       if (valid && rk == 0) wcnt[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
@@ -519,7 +569,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     ProfScope ps(c, ST_KICK);
     const int R1 = g.B * g.r + 1;
     const size_t fbytes = (size_t)3 * R1 * R1 * R1 * 4;
-    const size_t tail = (size_t)(B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + KB / 64);
+    const size_t tail = (size_t)MAXSP * (B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + KB / 64);
     const int R = g.B * g.r;
     if (R == 16 && fbytes + tail <= 96 * 1024)
       hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB),
