@@ -159,6 +159,31 @@ def decode(state):
     return x, v
 
 
+def cell_offsets(state) -> np.ndarray:
+    """Stream offset of every cell key (int64 [n_c^3 + 1]): exclusive prefix of counts."""
+    full = full_counts(state)
+    off = np.zeros(full.size + 1, dtype=np.int64)
+    np.cumsum(full, out=off[1:])
+    return off
+
+
+def decode_cells(state, keys, offsets=None):
+    """Decoded (x, v) float32 and stream indices of the particles of the given cell keys
+    only, with the same definitions as decode()."""
+    off = cell_offsets(state) if offsets is None else offsets
+    n_c, brick = state["n_c"], state["brick"]
+    keys = np.asarray(keys, dtype=np.int64).reshape(-1)
+    idx = np.concatenate([np.arange(off[k], off[k + 1]) for k in keys]) if keys.size else \
+        np.zeros(0, dtype=np.int64)
+    kk = np.repeat(keys, off[keys + 1] - off[keys])
+    cell = key_to_cell(kk, n_c, brick)
+    u = cell * 256 + state["pos"][idx].astype(np.int64)
+    S = 256 * n_c
+    x = ((u.astype(np.float64) + 0.5) / S).astype(np.float32)
+    v = decode_velocity(state["vel"][idx].astype(np.int64), np.float32(state["v_max"]))
+    return x, v, idx
+
+
 def decoded_vmax(state) -> float:
     """Largest |decoded velocity component| (exact, float64)."""
     if state["vel"].size == 0:

@@ -57,6 +57,26 @@ def deposit(x: np.ndarray, mass, n_g: int) -> np.ndarray:
     return rho.reshape(n_g, n_g, n_g) * float(n_g) ** 3
 
 
+def density_at(x: np.ndarray, mass, n_g: int, nodes: np.ndarray) -> np.ndarray:
+    """CIC density at the given nodes [k][3] (integer x, y, z) only.
+
+    By the definition of the weight: W is the product over axes of the tent
+    max(0, 1 - |u - c|) in mesh units (u = x n_g, c the node), with the periodic
+    (nearest image) distance; rho(c) = n_g^3 sum_i m_i W. For particles far from the
+    nodes this never forms the mesh, so it serves single nodes of large meshes.
+    """
+    u = np.asarray(x, dtype=np.float64) * n_g
+    m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (u.shape[0],))
+    nodes = np.asarray(nodes, dtype=np.int64).reshape(-1, 3)
+    out = np.zeros(nodes.shape[0], dtype=np.float64)
+    for k, c in enumerate(nodes):
+        d = u - c
+        d -= n_g * np.round(d / n_g)  # nearest periodic image
+        w = np.prod(np.clip(1.0 - np.abs(d), 0.0, None), axis=1)
+        out[k] = float(np.sum(m * w)) * float(n_g) ** 3
+    return out
+
+
 def deposit_species(species, n_g: int) -> np.ndarray:
     """Both species onto the same mesh (Sec. 2.1 footnote): list of (x, mass)."""
     rho = np.zeros((n_g, n_g, n_g), dtype=np.float64)

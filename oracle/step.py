@@ -55,6 +55,28 @@ def step_float(species, n_g: int, c_k: float, c_d: float, soft_cells: float = 1.
     return out, {"acc": acc, "a_mesh": a_mesh, "rho": rho}
 
 
+def kick_codes(u: np.ndarray, v_dec: np.ndarray, a_i: np.ndarray, v_max_new, S: int,
+               c_k: float, c_d: float):
+    """Kick, fixed-point drift and velocity re-binning of decoded particles.
+
+    u: position codes [n][3]; v_dec: decoded velocities; a_i: interpolated accelerations;
+    v_max_new: the new bin range. Returns (u_new, j_new, v_new, pos_pre, vel_pre) with
+    the pre-floor values d + 1/2 and v' C + 32768.
+    """
+    v1 = np.asarray(v_dec, dtype=np.float64) + c_k * np.asarray(a_i, dtype=np.float64)
+    d = v1 * (c_d * S)
+    pos_pre = d + 0.5
+    u1 = np.mod(np.asarray(u, dtype=np.int64) + np.floor(pos_pre).astype(np.int64), S)
+    if float(v_max_new) > 0:
+        C = 32768.0 / np.float64(v_max_new)
+        vel_pre = v1 * C + 32768.0
+        j1 = np.clip(np.floor(vel_pre), 0, 65535).astype(np.int64)
+    else:
+        vel_pre = np.full(v1.shape, 32768.0)
+        j1 = np.full(v1.shape, 32768, dtype=np.int64)
+    return u1, j1, v1, pos_pre, vel_pre
+
+
 def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
                     soft_cells: float = 1.0, G: float = 1.0 / mesh.FOUR_PI):
     """states: list of codec state dicts (same n_c, brick) -> new states + diagnostics.
@@ -77,17 +99,7 @@ def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
         v_dec = v.astype(np.float64)
         V = float(np.max(np.abs(v_dec))) if v_dec.size else 0.0
         v_max_new = np.float32(pow2_ceil(V + abs(c_k) * a_max))
-        v1 = v_dec + c_k * ai
-        d = v1 * (c_d * S)
-        pos_pre = d + 0.5
-        u1 = np.mod(u + np.floor(pos_pre).astype(np.int64), S)
-        if float(v_max_new) > 0:
-            C = 32768.0 / np.float64(v_max_new)
-            vel_pre = v1 * C + 32768.0
-            j1 = np.clip(np.floor(vel_pre), 0, 65535).astype(np.int64)
-        else:
-            vel_pre = np.full(v1.shape, 32768.0)
-            j1 = np.full(v1.shape, 32768, dtype=np.int64)
+        u1, j1, v1, pos_pre, vel_pre = kick_codes(u, v_dec, ai, v_max_new, S, c_k, c_d)
         keys = codec.cell_keys(u1 >> 8, n_c, brick)
         perm = np.argsort(keys, kind="stable")
         ns = codec.assemble(u1[perm], j1[perm], keys[perm], v_max_new, n_c, brick)

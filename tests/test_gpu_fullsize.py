@@ -1,0 +1,163 @@
+"""GPU parity at the headline workload's full size (256^3 CDM + 512^3 neutrinos, 1024^3
+mesh, n_cell 256), in the launch configuration the benchmark times.
+
+The oracle cannot form 1024^3 meshes and 151 M particles at once, so it checks what it
+can compute piece by piece, or what holds at any size:
+  * density at sampled nodes, from the particles of the neighbouring cells only
+    (oracle.mesh.density_at), tolerance 1e-5 max(|rho|, mean rho);
+  * the force of a full-size plane-wave density against the oracle's kernel value:
+    a_a = k_a G(|k|) sin(k.x), relative RMS over sampled nodes <= 1e-4;
+  * the kick-drift-re-encode of every particle of sampled cells from the GPU's own force
+    mesh, against oracle.step.kick_codes in float64 (equal codes outside the tie zone);
+  * the fused pm_step equals the separate calls bit for bit; mass is conserved.
+"""
+
+import types
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import ctx, frac_dist
+from oracle import codec, mesh, step
+from pmsynth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    print("[fullsize] generating tile_1024", flush=True)
+    wl = make_workload("tile_1024")
+    c = ctx(wl.n_mesh, wl.n_cell)
+    st = [c.encode(c.float_species(s.x, s.v, s.mass)) for s in wl.species]
+    rho = c.deposit(st)
+    acc, amax = c.force(rho)
+    out, perms = c.kick_drift_perm(st, acc, amax, wl.dt, wl.dt)
+    stepped = c.step(st, wl.dt)
+    c.sync()
+    print("[fullsize] GPU step done", flush=True)
+    yield types.SimpleNamespace(wl=wl, c=c, st=st, rho=rho, acc=acc, amax=amax, out=out,
+                                perms=perms, stepped=stepped)
+    c.close()
+
+
+def test_fullsize_step_equals_pieces(full):
+    for a, b in zip(full.stepped, full.out):
+        assert torch.equal(a.count, b.count)
+        assert torch.equal(a.pos, b.pos)
+        assert torch.equal(a.vel, b.vel)
+        assert torch.equal(a.hdr, b.hdr)
+        n_esc = int(np.frombuffer(a.hdr.cpu().numpy().tobytes()[16:24], dtype=np.int64)[0])
+        assert torch.equal(a.esc[:n_esc], b.esc[:n_esc])
+
+
+def test_fullsize_mass(full):
+    red = full.c.reduce(full.st, full.rho)
+    assert abs(red[0] - red[1]) <= 1e-6 * red[1]
+
+
+def _node_cells(node, n_g, n_c, brick):
+    """Cell keys whose particles can reach a mesh node (mesh cells node-1 and node)."""
+    r = n_g // n_c
+    per_axis = [sorted({((c - 1) % n_g) // r, c // r}) for c in node]
+    cells = np.array([(x, y, z) for z in per_axis[2] for y in per_axis[1]
+                      for x in per_axis[0]], dtype=np.int64)
+    return codec.cell_keys(cells, n_c, brick)
+
+
+def test_fullsize_density_sampled(full):
+    wl, c = full.wl, full.c
+    n = wl.n_mesh
+    rng = np.random.default_rng(11)
+    nodes = rng.integers(0, n, size=(48, 3))
+    nodes = np.concatenate([nodes, [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 3]]])
+    hosts = [c.to_host(s) for s in full.st]
+    offs = [codec.cell_offsets(h) for h in hosts]
+    rho = full.rho
+    got = np.array([float(rho[z, y, x]) for x, y, z in nodes])
+    want = np.zeros(len(nodes))
+    for k, node in enumerate(nodes):
+        keys = _node_cells(node, n, wl.n_cell, c.brick)
+        for h, off, sp in zip(hosts, offs, wl.species):
+            x, _, _ = codec.decode_cells(h, keys, off)
+            want[k] += mesh.density_at(x, sp.mass, n, node[None, :])[0]
+    mean = sum(sp.mass for sp in wl.species)
+    err = np.abs(got - want) / np.maximum(np.abs(want), mean)
+    assert err.max() <= 1e-5, err.max()
+
+
+def test_fullsize_plane_wave_force(full):
+    wl, c = full.wl, full.c
+    n = wl.n_mesh
+    nv = np.array([3, -5, 7])  # wave numbers along x, y, z
+    dev = c.device
+    i = torch.arange(n, device=dev, dtype=torch.int32)
+    ph = (int(nv[2]) * i[:, None, None] + int(nv[1]) * i[None, :, None] +
+          int(nv[0]) * i[None, None, :]) % n
+    rho_pw = torch.cos(ph.to(torch.float64) * (2 * np.pi / n)).to(torch.float32)
+    del ph
+    acc_pw, _ = c.force(rho_pw)
+    del rho_pw
+    rng = np.random.default_rng(3)
+    nodes = rng.integers(0, n, size=(4096, 3))
+    idx = torch.from_numpy(nodes[:, 2] * n * n + nodes[:, 1] * n + nodes[:, 0]).to(dev)
+    got = acc_pw.reshape(3, -1)[:, idx].cpu().numpy().astype(np.float64)
+    del acc_pw
+    k = 2 * np.pi * nv.astype(np.float64)
+    G = mesh.plummer_kernel_k(np.array([np.linalg.norm(k)]), c.soft_cells / n, c.G)[0]
+    theta = 2 * np.pi * ((nodes @ nv) % n) / n
+    want = k[:, None] * G * np.sin(theta)[None, :]
+    err = np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
+    assert err <= 1e-4, err
+
+
+def test_fullsize_kick_sampled(full):
+    wl, c = full.wl, full.c
+    n, n_c = wl.n_mesh, wl.n_cell
+    S = 256 * n_c
+    dt = wl.dt
+    acc_h = full.acc.cpu().numpy()
+    a_max = float(np.max(np.abs(acc_h)))
+    assert a_max == float(full.amax.item())
+    a_scale = float(np.sqrt(np.mean(acc_h[:, ::8, ::8, ::8].astype(np.float64) ** 2)))
+    rng = np.random.default_rng(5)
+    for st, o, perm in zip(full.st, full.out, full.perms):
+        h = c.to_host(st)
+        ho = c.to_host(o)
+        keys = rng.choice(n_c ** 3, size=4000, replace=False)
+        x, v, idx = codec.decode_cells(h, keys)
+        ai = mesh.interpolate(acc_h, x.astype(np.float64))
+        jv = h["vel"]
+        ext = codec.decode_velocity(np.array([jv.min(), jv.max()]), np.float32(h["v_max"]))
+        V = float(np.max(np.abs(ext.astype(np.float64))))
+        v_max_new = np.float32(step.pow2_ceil(V + abs(dt) * a_max))
+        assert float(ho["v_max"]) == float(v_max_new)
+        u = codec.position_codes(x, n_c)
+        u1, j1, v1, pos_pre, vel_pre = step.kick_codes(u, v, ai, v_max_new, S, dt, dt)
+        # where the particles went: new stream index of each sampled old index
+        pm = perm.cpu().numpy()
+        inv = np.empty_like(pm)
+        inv[pm] = np.arange(pm.size)
+        ni = inv[idx]
+        off_new = codec.cell_offsets(ho)
+        nkey = np.searchsorted(off_new, ni, side="right") - 1
+        ug = codec.key_to_cell(nkey, n_c, c.brick) * 256 + ho["pos"][ni].astype(np.int64)
+        jg = ho["vel"][ni].astype(np.int64)
+        # the interpolation differs from the oracle's only by float32 rounding
+        dv = abs(dt) * 1e-6 * (np.abs(ai) + a_scale) + 2.0 ** -22 * np.abs(v1)
+        tau_x = dt * S * dv + 1e-6
+        du = (ug - u1 + S // 2) % S - S // 2
+        bad = du != 0
+        assert np.all(np.abs(du[bad]) <= 1)
+        assert np.all(frac_dist(pos_pre[bad]) <= tau_x[bad])
+        assert bad.mean() < 1e-3
+        C = 32768.0 / float(v_max_new)
+        tau_v = C * dv + 1e-6
+        dj = jg - j1
+        badv = dj != 0
+        assert np.all(np.abs(dj[badv]) <= 1)
+        assert np.all(frac_dist(vel_pre[badv]) <= tau_v[badv])
+        assert badv.mean() < 1e-3
+        print(f"[fullsize] kick sample {idx.size}: {int(bad.sum())} position and "
+              f"{int(badv.sum())} velocity codes in the tie zone", flush=True)

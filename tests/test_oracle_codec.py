@@ -185,3 +185,15 @@ def test_float_step_single_particle_free_drift():
     (out,), _ = step.step_float([(x, v, 0.0)], 8, 0.01, 0.01)
     assert np.allclose(out[0], np.mod(x + 0.01 * v, 1.0), atol=1e-15)
     assert np.allclose(out[1], v)
+
+
+def test_decode_cells_matches_full_decode():
+    rng = np.random.default_rng(9)
+    x0, v0 = _random_state(rng, 2000, 8, 4, clump=300)
+    st = codec.encode(x0, v0, 8, 4)
+    x, v = codec.decode(st)
+    keys = rng.choice(8 ** 3, size=40, replace=False)
+    xs, vs, idx = codec.decode_cells(st, keys)
+    assert np.array_equal(xs, x[idx]) and np.array_equal(vs, v[idx])
+    sk = codec.stream_keys(st)
+    assert np.array_equal(np.sort(idx), np.flatnonzero(np.isin(sk, keys)))

@@ -269,3 +269,19 @@ def test_zeldovich_plane_wave_growth():
     sT = np.sqrt(T)
     cont = A * np.cosh(sT * (K * h + h / 2)) / np.cosh(sT * h / 2)
     assert abs(cur / cont - 1.0) < 1e-4
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_density_at_nodes_equals_full_deposit(n):
+    """The per-node tent-function form equals the corner-weight deposit everywhere,
+    including particles within a cell of the periodic boundary."""
+    rng = np.random.default_rng(n)
+    x = rng.random((300, 3))
+    x[:20] = rng.choice([0.0, 1.0 - 1e-9, 0.5 / n], size=(20, 3))
+    m = rng.random(300)
+    full = mesh.deposit(x, m, n)
+    nodes = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n),
+                                 indexing="ij"), axis=-1).reshape(-1, 3)[:, ::-1]
+    got = mesh.density_at(x, m, n, nodes)
+    want = full[nodes[:, 2], nodes[:, 1], nodes[:, 0]]
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * full.max())
