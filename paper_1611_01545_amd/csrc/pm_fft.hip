@@ -314,12 +314,21 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
   static_assert(P::T % ZB == 0, "z blocks must divide the thread stride");
   constexpr int CS = col_cs<W>(P::E * P::TP);
   __shared__ float lds[W * CS];
+  // the line's twiddles exp(-2 pi i j / N) in LDS: 32-bit LDS addresses instead of
+  // 64-bit global pointers per twiddle, which the two inverse transforms of MODE 3
+  // would otherwise keep live together
+  __shared__ float2 stw[N];
+  for (int i = threadIdx.x; i < N; i += W * P::T) stw[i] = tw[(i * tws) & twmask];
+  __syncthreads();
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int64_t l1 = (int64_t)blockIdx.x * W + c;
-  // element t + T n1 of the line: z-blocked lines split it as (block, row in block)
-  const int64_t base = line_base(d, l1, blockIdx.y) +
-                       (BLK ? (int64_t)(t >> LZB) * d.es + (int64_t)(t & (ZB - 1)) * d.esl
-                            : (int64_t)t * d.es);
+  // element t + T n1 of the line: z-blocked lines split it as (block, row in block).
+  // Addresses are a workgroup-uniform 64-bit part (scalar registers) plus a 32-bit
+  // per-thread offset, so that no 64-bit address per point stays live in VGPRs.
+  const int64_t ubase = line_base(d, (int64_t)blockIdx.x * W, blockIdx.y);
+  const uint32_t toff =
+      (uint32_t)(c * d.s1 + (BLK ? (int64_t)(t >> LZB) * d.es + (int64_t)(t & (ZB - 1)) * d.esl
+                                 : (int64_t)t * d.es));
   const int64_t step = BLK ? (int64_t)(P::T >> LZB) * d.es : (int64_t)P::T * d.es;
   float* my = lds + c * CS;
   const int kx = d.kx_mode ? d.kx_fixed : (int)l1;
@@ -329,8 +338,8 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
   float2 acc[P::E];
   if constexpr (MODE == 3) {
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = in0[base + n1 * step];
-    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
+    nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
     float2 gz[P::E];
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
@@ -344,16 +353,16 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
         acc[v * P::T + k2] = f;
         gz[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
       }
-    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
+    tr_to_nat<N, +1>(acc, t, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
-    tr_to_nat<N, +1>(gz, t, my, tw, tws, twmask);
+    for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
+    tr_to_nat<N, +1>(gz, t, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) out1[base + n1 * step] = gz[n1];
+    for (int n1 = 0; n1 < P::E; ++n1) (out1 + (ubase + n1 * step))[toff] = gz[n1];
   } else if constexpr (MODE == 0 || MODE == 2) {
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = in0[base + n1 * step];
-    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
+    nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
@@ -370,16 +379,16 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
           acc[v * P::T + k2] = make_float2(G * f.x, G * f.y);
         }
       }
-    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
+    tr_to_nat<N, +1>(acc, t, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
+    for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   } else {
     // sum_a (+i k_a) FFT_z(in_a): k_x and k_y are constant along a z line, so their two
     // terms are one transform of +i (k_x in0 + k_y in1); k_z multiplies after FFT_z(in2)
     const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = in2[base + n1 * step];
-    nat_to_tr<N, -1>(acc, t, my, tw, tws, twmask);
+    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in2 + (ubase + n1 * step))[toff];
+    nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
@@ -391,10 +400,10 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
     float2 f[P::E];
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) {
-      const float2 a = in0[base + n1 * step], b2 = in1[base + n1 * step];
+      const float2 a = (in0 + (ubase + n1 * step))[toff], b2 = (in1 + (ubase + n1 * step))[toff];
       f[n1] = make_float2(-(kxg * a.y + kyg * b2.y), kxg * a.x + kyg * b2.x);
     }
-    nat_to_tr<N, -1>(f, t, my, tw, tws, twmask);
+    nat_to_tr<N, -1>(f, t, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
@@ -405,9 +414,9 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
         const float2 q = acc[v * P::T + k2], p = f[v * P::T + k2];
         acc[v * P::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
       }
-    tr_to_nat<N, +1>(acc, t, my, tw, tws, twmask);
+    tr_to_nat<N, +1>(acc, t, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) out0[base + n1 * step] = acc[n1];
+    for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   }
 }
 
