@@ -163,6 +163,7 @@ pm_status pm_destroy(pm_ctx c) {
   if (!c) return PM_ERR_ARG;
   hipStreamSynchronize(c->stream);
   hipFree(c->ktab);
+  hipFree(c->gtab);
   hipFree(c->tw);
   hipFree(c->mesh);
   hipFree(c->nyq);

@@ -92,6 +92,7 @@ struct pm_context {
   // gravity kernel table G(|n|^2)/n^3 (float) and twiddles exp(-2 pi i k/n), k<n
   float* ktab = nullptr;
   int64_t ktab_n = 0;
+  float* gtab = nullptr;  // the same kernel values on the octant [kx][|ky|][|kz|] <= n/2
   float2* tw = nullptr;
   // owned meshes for pm_step: 3 x ng^3 floats + 3 Nyquist planes (complex ng^2)
   float* mesh = nullptr;

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
     const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
     Lines d,
     const float2* __restrict__ tw, int tws, int twmask, int n,
-    const float* __restrict__ ktab) {
+    const float* __restrict__ gtab) {
   using P = Plan<N>;
   constexpr int ZB = zblk(N), LZB = ilog2(ZB);
   static_assert(P::T % ZB == 0, "z blocks must divide the thread stride");
@@ -334,7 +334,10 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
   const int kx = d.kx_mode ? d.kx_fixed : (int)l1;
   const int ky = d.ky_mode ? (int)l1 : (int)blockIdx.y;
   const int sx = signed_k(kx, n), sy = signed_k(ky, n);
-  const int nxy2 = sx * sx + sy * sy;
+  // kernel values of this line: gtab row (|kx|, |ky|), indexed by |kz|
+  const int h1 = n / 2 + 1;
+  const float* __restrict__ grow =
+      gtab + ((int64_t)(sx < 0 ? -sx : sx) * h1 + (sy < 0 ? -sy : sy)) * h1;
   float2 acc[P::E];
   if constexpr (MODE == 3) {
 #pragma unroll
@@ -347,7 +350,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
       for (int k2 = 0; k2 < P::T; ++k2) {
         const int kz = (t + P::T * v) + P::E * k2;
         const int sz = signed_k(kz, n);
-        const float G = ktab[nxy2 + sz * sz];
+        const float G = grow[sz < 0 ? -sz : sz];
         const float2 f = make_float2(G * acc[v * P::T + k2].x, G * acc[v * P::T + k2].y);
         const float kk = grad_k(kz, n);
         acc[v * P::T + k2] = f;
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
       for (int k2 = 0; k2 < P::T; ++k2) {
         const int kz = (t + P::T * v) + P::E * k2;
         const int sz = signed_k(kz, n);
-        const float G = ktab[nxy2 + sz * sz];
+        const float G = grow[sz < 0 ? -sz : sz];
         const float2 f = acc[v * P::T + k2];
         if constexpr (MODE == 2) {
           // -i k_z G (x + i y) = k_z G y - i k_z G x
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
       for (int k2 = 0; k2 < P::T; ++k2) {
         const int kz = (t + P::T * v) + P::E * k2;
         const int sz = signed_k(kz, n);
-        const float G = ktab[nxy2 + sz * sz];
+        const float G = grow[sz < 0 ? -sz : sz];
         const float2 q = acc[v * P::T + k2], p = f[v * P::T + k2];
         acc[v * P::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
       }
@@ -588,6 +591,17 @@ __global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, dou
   ktab[q] = (float)val;
 }
 
+// Octant copy of the kernel table: gtab[(kx (h+1) + ay) (h+1) + az] = ktab[kx^2 + ay^2 +
+// az^2] for kx, ay, az in [0, h], h = n/2 (the kernel depends on |k| only). A z line at
+// fixed (kx, ky) then reads its kernel values as one contiguous run.
+__global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h) {
+  const int64_t h1 = h + 1, tot = h1 * h1 * h1;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= tot) return;
+  const int64_t az = q % h1, ay = (q / h1) % h1, kx = q / (h1 * h1);
+  gtab[q] = ktab[kx * kx + ay * ay + az * az];
+}
+
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 // ------------------------------------------------------------------ dispatch --
@@ -643,7 +657,7 @@ pm_status col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0, const
   dim3 block(W * Plan<N>::T);
 #define ZLAUNCH(MODE, BLK)                                                                 \
   hipLaunchKernelGGL((k_col_zconv<N, W, MODE, BLK>), grid, block, 0, f.c->stream, i0, i1, \
-                     i2, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->ktab)
+                     i2, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gtab)
   if (blk) {
     if (mode == 0) ZLAUNCH(0, true);
     else if (mode == 2) ZLAUNCH(2, true);
@@ -763,6 +777,11 @@ pm_status build_kernel_table(pm_context* c) {
   double eps = c->cfg.soft_cells / (double)n;
   hipLaunchKernelGGL(k_build_ktab, dim3((unsigned)cdiv(c->ktab_n, 256)), dim3(256), 0,
                      c->stream, c->ktab, c->ktab_n, n, c->cfg.G, eps);
+  PM_LAUNCH_CHECK();
+  const int64_t h1 = n / 2 + 1, ng3 = h1 * h1 * h1;
+  PM_HIP_CHECK(hipMalloc(&c->gtab, (size_t)ng3 * sizeof(float)));
+  hipLaunchKernelGGL(k_build_gtab, dim3((unsigned)cdiv(ng3, 256)), dim3(256), 0, c->stream,
+                     c->ktab, c->gtab, n / 2);
   PM_LAUNCH_CHECK();
   // twiddles exp(-2 pi i k / n), k < n, built in float64 on the host
   float2* h = (float2*)malloc(sizeof(float2) * n);
