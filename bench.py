@@ -85,7 +85,7 @@ def stage_bytes(name: str, n: int, wl) -> float:
         "fft_x_r2c": 8 * n3 + 8 * n2,          # real mesh in, half spectrum + Nyquist out
         "fft_y_fwd": 8 * n3,                    # half spectrum in and out
         "fft_z": 12 * n3,                       # fused z pass, one in, two out
-        "fft_y_inv": 8 * n3,                    # one in, one out per launch
+        "fft_y_inv": 10 * n3,                   # 2 launches: one in two out, one in one out
         "fft_x_c2r": 8 * n3 + 8 * n2,           # half spectrum + Nyquist in, real out
         "deposit": 3 * N + ns * nc3 + 4 * n3,   # positions, counts, density
         # one launch moves every species: codes in and out, counts, the 3 force meshes

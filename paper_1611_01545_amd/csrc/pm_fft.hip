@@ -9,10 +9,10 @@
 //   Y  fwd      -> rho~(kx, ky)                        columns, in place
 //   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table), inverse z
 //               FFT: T1 = IFFT_z(G rho~) and T2 = IFFT_z(-i k_z G rho~) from one read
-//   Y  inv      U2 = IFFT_y(-i k_y T1), U1 = IFFT_y(T1), U3 = IFFT_y(T2)
+//   Y  inv      U1 = IFFT_y(T1) and U2 = IFFT_y(-i k_y T1) from one read, U3 = IFFT_y(T2)
 //   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
 //               max |a| for the velocity bound of the re-encode
-// 9 launches moving 76 n^3 bytes, against 12 plain passes and separate multiplies.
+// 8 launches moving 72 n^3 bytes, against 12 plain passes and separate multiplies.
 // The gradient factor -i k_a follows eq. (3) and is zero on the Nyquist index; the
 // 1/n^3 of the inverse transform is folded into the kernel table.
 //
@@ -261,9 +261,11 @@ __device__ __forceinline__ float grad_k(int k, int n) {
   return (k == n / 2) ? 0.f : 6.283185307179586f * (float)signed_k(k, n);
 }
 
-// Generic c2c column FFT: out0 = FFT_SIGN(in); if out1, out1 = FFT_SIGN(-i k(e) in)
-// where k(e) is the line's own wave number (used for -i k_y in the inverse y pass).
-template <int N, int W, int SIGN, bool TWO>
+// Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
+// only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
+// inverse y pass). With two outputs the twiddles are staged in LDS (32-bit addresses),
+// which keeps both line arrays in registers without spilling.
+template <int N, int W, int SIGN, int OUT>
 __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, float2* out0,
                                                             float2* out1, Lines d,
                                                             const float2* __restrict__ tw,
@@ -271,17 +273,22 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
   using P = Plan<N>;
   constexpr int CS = col_cs<W>(P::E * P::TP);
   __shared__ float lds[W * CS];
+  __shared__ float2 stw[OUT == 2 ? N : 1];
+  if constexpr (OUT == 2) {
+    for (int i = threadIdx.x; i < N; i += W * P::T) stw[i] = tw[(i * tws) & twmask];
+    __syncthreads();
+  }
   // the grid covers the lines exactly (W divides the line count; checked on the host)
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int64_t l1 = (int64_t)blockIdx.x * W + c;
-  const int64_t base = line_base(d, l1, blockIdx.y);
+  // addresses: a workgroup-uniform 64-bit part plus a 32-bit per-thread offset
+  const int64_t ubase = line_base(d, (int64_t)blockIdx.x * W, blockIdx.y);
+  const uint32_t lo_in = (uint32_t)(c * d.s1 + (int64_t)t * d.es);
   float* my = lds + c * CS;
   float2 a[P::E];
 #pragma unroll
-  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = in[base + (int64_t)(t + P::T * n1) * d.es];
-  if constexpr (TWO) {
-    // the second output transforms -i k (x + i y) = k y - i k x; k is the line's own
-    // wave number
+  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = (in + (ubase + (int64_t)P::T * n1 * d.es))[lo_in];
+  if constexpr (OUT == 1) {
+    // -i k (x + i y) = k y - i k x; k is the line's own wave number
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) {
       float k = grad_k(t + P::T * n1, n);
@@ -289,12 +296,36 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
     }
     out0 = out1;
   }
-  nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
+  if constexpr (OUT == 2) {
+    float2 b[P::E];
 #pragma unroll
-  for (int v = 0; v < P::V; ++v)
+    for (int n1 = 0; n1 < P::E; ++n1) {
+      float k = grad_k(t + P::T * n1, n);
+      b[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
+    }
+    nat_to_tr<N, SIGN>(a, t, my, stw, 1, N - 1);
 #pragma unroll
-    for (int k2 = 0; k2 < P::T; ++k2)
-      out0[base + (int64_t)((t + P::T * v) + P::E * k2) * d.es] = a[v * P::T + k2];
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2)
+        (out0 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
+            a[v * P::T + k2];
+    nat_to_tr<N, SIGN>(b, t, my, stw, 1, N - 1);
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2)
+        (out1 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
+            b[v * P::T + k2];
+  } else {
+    nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2)
+        (out0 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
+            a[v * P::T + k2];
+  }
 }
 
 // ---------------------------------------------------------------- fused z pass --
@@ -622,6 +653,7 @@ struct FftCtx {
   int twmask;
 };
 
+// out: 0 plain (o0), 1 only the -i k output (o1), 2 both
 template <int N>
 pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, const Lines& d,
                   int64_t L2, int sign) {
@@ -629,21 +661,20 @@ pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, con
   if (d.L1 % W) return PM_ERR_SHAPE;
   dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
   dim3 block(W * Plan<N>::T);
+  const int out = o1 ? (o0 ? 2 : 1) : 0;
+#define CLAUNCH(S, O)                                                                     \
+  hipLaunchKernelGGL((k_col_fft<N, W, S, O>), grid, block, 0, f.c->stream, in, o0, o1, d, \
+                     f.c->tw, 1, f.twmask, f.n)
   if (sign < 0) {
-    if (o1)
-      hipLaunchKernelGGL((k_col_fft<N, W, -1, true>), grid, block, 0, f.c->stream, in, o0, o1,
-                         d, f.c->tw, 1, f.twmask, f.n);
-    else
-      hipLaunchKernelGGL((k_col_fft<N, W, -1, false>), grid, block, 0, f.c->stream, in, o0, o1,
-                         d, f.c->tw, 1, f.twmask, f.n);
+    if (out == 0) CLAUNCH(-1, 0);
+    else if (out == 1) CLAUNCH(-1, 1);
+    else CLAUNCH(-1, 2);
   } else {
-    if (o1)
-      hipLaunchKernelGGL((k_col_fft<N, W, 1, true>), grid, block, 0, f.c->stream, in, o0, o1, d,
-                         f.c->tw, 1, f.twmask, f.n);
-    else
-      hipLaunchKernelGGL((k_col_fft<N, W, 1, false>), grid, block, 0, f.c->stream, in, o0, o1,
-                         d, f.c->tw, 1, f.twmask, f.n);
+    if (out == 0) CLAUNCH(1, 0);
+    else if (out == 1) CLAUNCH(1, 1);
+    else CLAUNCH(1, 2);
   }
+#undef CLAUNCH
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -803,7 +834,8 @@ pm_status build_kernel_table(pm_context* c) {
 //   r2c   rho -> A1                        (rho may be A0)
 //   Y     A1 in place
 //   Z     T1 = G F: A1 in place and T2 = -i k_z G F: A1 -> S, one launch
-//   Y^-1  U2 = IFFT_y(-i k_y T1): A1 -> A2;  U1 = IFFT_y(T1): A1;  U3 = IFFT_y(T2): S
+//   Y^-1  U1 = IFFT_y(T1): A1 and U2 = IFFT_y(-i k_y T1): A1 -> A2 (one read);
+//         U3 = IFFT_y(T2): S
 //   c2r   a_x = IFFT_x(-i k_x U1): A1 -> A0;  a_y: A2 -> A1;  a_z: S -> A2
 pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, float* amax) {
   const int n = (int)c->g.ng;
@@ -841,18 +873,13 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
   if ((s = d_col_zconv(f, 3, false, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
   {
     ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, A1, nullptr, A2, ym, n, +1)) != PM_OK) return s;
-  }
-  {
-    ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, +1)) != PM_OK) return s;
+    if ((s = d_col_fft(f, A1, A1, A2, ym, n, +1)) != PM_OK) return s;
   }
   {
     ProfScope ps(c, ST_FFT_YI);
     if ((s = d_col_fft(f, S, S, nullptr, ym, n, +1)) != PM_OK) return s;
   }
-  if ((s = d_col_fft(f, N0, nullptr, N1, yn, 1, +1)) != PM_OK) return s;
-  if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, +1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, N0, N0, N1, yn, 1, +1)) != PM_OK) return s;
   if ((s = d_col_fft(f, N2, N2, nullptr, yn, 1, +1)) != PM_OK) return s;
   const float2* ins[3] = {A1, A2, S};
   float* outs[3] = {(float*)A0, (float*)A1, (float*)A2};
