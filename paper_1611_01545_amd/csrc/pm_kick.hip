@@ -140,7 +140,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   const int fsz = STAGE ? 3 * R1 * R1 * R1 : 0;
   int64_t* loffs = (int64_t*)(smem + ((fsz * 4 + 7) / 8) * 8);  // [MAXSP][B3 + 1]
   uint32_t* run = (uint32_t*)(loffs + MAXSP * (B3 + 1));       // [B3 + 1] (B3 = movers)
-  uint32_t* wcnt = run + (B3 + 1);                             // [KB/64][B3 + 1]
+  uint32_t* wcnt = run + (B3 + 1);                             // [2][KB/64][B3 + 1]
   constexpr int NW = KB / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
@@ -248,25 +248,35 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
 
   const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
   bool bad = false;
+  __shared__ int mm[2 * NW];  // per-wave extreme velocity codes
+  // Rounds of KB particles in stream order. Per round: (1) new codes and digits, stable
+  // multi-split inside each wave, per-wave digit counts into wcnt[round & 1]; barrier;
+  // (2) rank = running count + counts of earlier waves + rank in the wave, outputs,
+  // and the other count buffer cleared for the next round; barrier; (3) running counts
+  // advanced (overlaps the next round's step 1, which uses the other buffer).
+  const int WS = NW * (B3 + 1);
 #pragma unroll
   for (int s = 0; s < MAXSP; ++s) {
     if (s >= n_sp) break;
     const KickSpecies& S = A.sp[s];
     const int64_t* loff = loffs + s * (B3 + 1);
-    __syncthreads();  // previous species done with run
+    __syncthreads();  // previous species done with run and wcnt
     for (int i = threadIdx.x; i <= B3; i += KB) run[i] = 0;
+    for (int i = threadIdx.x; i < 2 * WS; i += KB) wcnt[i] = 0;
+    __syncthreads();
     const int64_t j0 = min(loff[0], S.n), j1 = min(loff[B3], S.n);
     const float vmax_in = vin[s];
     const float vmax_out = vout[s];
     int jmin = 65536, jmax = -1;
-    for (int64_t base = j0; base < j1; base += KB) {
-      for (int i = threadIdx.x; i < NW * (B3 + 1); i += KB) wcnt[i] = 0;
-      __syncthreads();
+    int rnd = 0;
+    for (int64_t base = j0; base < j1; base += KB, ++rnd) {
+      uint32_t* wc = wcnt + (rnd & 1) * WS;
+      uint32_t* wo = wcnt + ((rnd & 1) ^ 1) * WS;
       const int64_t j = base + threadIdx.x;
       const bool valid = j < j1;
       uint32_t digit = 0, newkey = 0;
       if (valid) {
-        // the particle's codes: prefetched for the first chunk
+        // the particle's codes: prefetched for the first round
         uint32_t pb[3], vc[3];
         if (base == j0) {
 #pragma unroll
@@ -344,18 +354,18 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
         digit = (newkey >= kbase && newkey < kbase + (uint32_t)B3) ? newkey - kbase
                                                                   : (uint32_t)B3;
       }
-      // stable multi-split of this chunk by digit (new local cell, or B3 for movers)
+      // stable multi-split of this round by digit (new local cell, or B3 for movers)
       uint64_t match = __ballot(valid);
       for (int bit = 0; bit < nbits; ++bit) {
-        uint64_t mm = __ballot(valid && ((digit >> bit) & 1u));
-        match &= ((digit >> bit) & 1u) ? mm : ~mm;
+        uint64_t mbit = __ballot(valid && ((digit >> bit) & 1u));
+        match &= ((digit >> bit) & 1u) ? mbit : ~mbit;
       }
       const uint32_t rk = (uint32_t)__popcll(match & lt);
-      if (valid && rk == 0) wcnt[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
+      if (valid && rk == 0) wc[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
       __syncthreads();
       if (valid) {
         uint32_t pre = run[digit];
-        for (int q = 0; q < w; ++q) pre += wcnt[q * (B3 + 1) + digit];
+        for (int q = 0; q < w; ++q) pre += wc[q * (B3 + 1) + digit];
         const uint32_t rank = pre + rk;
         if (digit < (uint32_t)B3) {
           if (rank >= RANK_LIMIT) bad = true;
@@ -366,30 +376,33 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
           S.midx[j0 + rank] = (uint32_t)j;
         }
       }
+      for (int i = threadIdx.x; i < WS; i += KB) wo[i] = 0;
       __syncthreads();
       for (int i = threadIdx.x; i <= B3; i += KB) {
         uint32_t add = 0;
-        for (int q = 0; q < NW; ++q) add += wcnt[q * (B3 + 1) + i];
+        for (int q = 0; q < NW; ++q) add += wc[q * (B3 + 1) + i];
         run[i] += add;
       }
-      __syncthreads();
     }
-    for (int i = threadIdx.x; i < B3; i += KB) S.cnt[kbase + i] = (uint64_t)run[i];
-    if (threadIdx.x == 0) S.mcnt[b] = run[B3];
+    // the thread that advanced run[i] writes it out
+    for (int i = threadIdx.x; i <= B3; i += KB) {
+      if (i < B3) S.cnt[kbase + i] = (uint64_t)run[i];
+      else S.mcnt[b] = run[B3];
+    }
     // block min / max of the new velocity codes, stored per brick (no atomics)
     for (int d = 32; d >= 1; d >>= 1) {
       jmin = min(jmin, __shfl_xor(jmin, d, 64));
       jmax = max(jmax, __shfl_xor(jmax, d, 64));
     }
     if (lane == 0) {
-      wcnt[2 * w] = (uint32_t)jmin;
-      wcnt[2 * w + 1] = (uint32_t)jmax;
+      mm[2 * w] = jmin;
+      mm[2 * w + 1] = jmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       for (int q = 1; q < NW; ++q) {
-        jmin = min(jmin, (int)wcnt[2 * q]);
-        jmax = max(jmax, (int)wcnt[2 * q + 1]);
+        jmin = min(jmin, mm[2 * q]);
+        jmax = max(jmax, mm[2 * q + 1]);
       }
       S.pmn[b] = jmin;
       S.pmx[b] = jmax;
@@ -569,7 +582,8 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     ProfScope ps(c, ST_KICK);
     const int R1 = g.B * g.r + 1;
     const size_t fbytes = (size_t)3 * R1 * R1 * R1 * 4;
-    const size_t tail = (size_t)MAXSP * (B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + KB / 64);
+    const size_t tail =
+        (size_t)MAXSP * (B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + 2 * (KB / 64));
     const int R = g.B * g.r;
     if (R == 16 && fbytes + tail <= 96 * 1024)
       hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB),
