@@ -48,9 +48,9 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "d45e232403e67d09d0341521d81ee3d93a3791ec074597979d00bee927bcec0c",
-        "fetch_kib": 8016644.25, "fetch_factor": 1.99991,
-        "write_kib": 2216278.41, "write_factor": 1.0,
+        "sha256": "fb279a8e1c429f84d5d8b54f3e3044664668ac2121f49f8548413e8133df8716",
+        "fetch_kib": 7986915.31, "fetch_factor": 1.99992,
+        "write_kib": 2215845.50, "write_factor": 1.0,
     },
 }
 
