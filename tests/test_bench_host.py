@@ -1,0 +1,38 @@
+"""Host-side logic of bench.py: the byte model, the measured-traffic record, the
+single-GPU guard (no GPU needed)."""
+
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from pmsynth import make_workload  # noqa: E402
+
+
+def test_byte_model_headline_totals():
+    wl = make_workload("plain_cdm_64")  # shape only; the model is linear in N and n^3
+    n = 1024
+    n3 = float(n) ** 3
+    assert bench.stage_bytes("fft_z", n, wl) == 12 * n3
+    assert bench.stage_bytes("fft_y_fwd", n, wl) == 8 * n3
+    assert bench.stage_bytes("unknown", n, wl) == 0.0
+    N = wl.n_particles
+    assert bench.stage_bytes("interp_kick_drift", n, wl) == 18 * N + 2 * wl.n_cell ** 3 + 12 * n3
+
+
+def test_measured_traffic_is_tied_to_the_kernel_sources():
+    rec = bench.MEASURED_TRAFFIC[("interp_kick_drift", "tile_1024")]
+    t = bench.measured_traffic("interp_kick_drift", "tile_1024")
+    want = rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
+    assert t is None or abs(t - want) < 1.0
+    assert bench.measured_traffic("deposit", "tile_1024") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
