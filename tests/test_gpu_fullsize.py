@@ -161,3 +161,39 @@ def test_fullsize_kick_sampled(full):
         assert badv.mean() < 1e-3
         print(f"[fullsize] kick sample {idx.size}: {int(bad.sum())} position and "
               f"{int(badv.sum())} velocity codes in the tie zone", flush=True)
+
+
+def test_plane_wave_force_2048():
+    """The force path at the largest mesh (2048^3, the 1.2 G-particle workload's mesh):
+    every FFT kernel variant of that size on a plane-wave density, against the oracle's
+    kernel value at sampled nodes, and max |a| against its analytic value."""
+    n = 2048
+    c = ctx(n, 128)
+    dev = c.device
+    nv = np.array([3, -5, 7])
+    rho = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    i = torch.arange(n, device=dev, dtype=torch.int64)
+    xy = (int(nv[1]) * i[:, None] + int(nv[0]) * i[None, :])
+    for z0 in range(0, n, 64):  # slabs keep the float64 temporaries small
+        zz = torch.arange(z0, z0 + 64, device=dev, dtype=torch.int64)
+        ph = (int(nv[2]) * zz[:, None, None] + xy[None, :, :]) % n
+        rho[z0:z0 + 64] = torch.cos(ph.to(torch.float64) * (2 * np.pi / n)).to(torch.float32)
+        del ph
+    acc, amax = c.force(rho)
+    del rho
+    rng = np.random.default_rng(4)
+    nodes = rng.integers(0, n, size=(4096, 3))
+    idx = torch.from_numpy(nodes[:, 2] * n * n + nodes[:, 1] * n + nodes[:, 0]).to(dev)
+    got = acc.reshape(3, -1)[:, idx].cpu().numpy().astype(np.float64)
+    k = 2 * np.pi * nv.astype(np.float64)
+    G = mesh.plummer_kernel_k(np.array([np.linalg.norm(k)]), c.soft_cells / n, c.G)[0]
+    theta = 2 * np.pi * ((nodes @ nv) % n) / n
+    want = k[:, None] * G * np.sin(theta)[None, :]
+    err = np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
+    assert err <= 1e-4, err
+    # the phase takes every residue mod n, so |sin| reaches 1 on the mesh
+    amax_want = float(np.max(np.abs(k)) * abs(G))
+    assert abs(float(amax.item()) - amax_want) <= 1e-4 * amax_want
+    del acc
+    c.close()
+    torch.cuda.empty_cache()
