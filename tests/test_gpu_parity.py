@@ -180,10 +180,13 @@ def _codes_old_order(host_state, perm):
     return uo, jo
 
 
-@pytest.mark.parametrize("n_p_c,n_mesh,seed", [(16, 32, 0), (32, 64, 1)])
-def test_compressed_step_tie_zone(n_p_c, n_mesh, seed):
+# bricks: the default (16-node staged tiles), 2 (8-node tiles at r = 4) and 1 (the
+# per-particle gather from the mesh)
+@pytest.mark.parametrize("n_p_c,n_mesh,seed,brick", [(16, 32, 0, None), (32, 64, 1, None),
+                                                     (16, 64, 2, 2), (16, 32, 3, 1)])
+def test_compressed_step_tie_zone(n_p_c, n_mesh, seed, brick):
     wl = small_two_species(n_p_c, n_mesh, seed_offset=seed)
-    c = ctx(n_mesh, wl.n_cell)
+    c = ctx(n_mesh, wl.n_cell, brick=brick)
     dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
     rho = c.deposit(dev)
     acc, amax = c.force(rho)
