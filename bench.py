@@ -48,9 +48,9 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "fb279a8e1c429f84d5d8b54f3e3044664668ac2121f49f8548413e8133df8716",
-        "fetch_kib": 7986915.31, "fetch_factor": 1.99992,
-        "write_kib": 2215845.50, "write_factor": 1.0,
+        "sha256": "38a922faf21e541a71db0112392e9e08298e3bcbf350f7a5216b0c3d6b8ae023",
+        "fetch_kib": 8012033.06, "fetch_factor": 1.99992,
+        "write_kib": 2212771.09, "write_factor": 1.0,
     },
 }
 

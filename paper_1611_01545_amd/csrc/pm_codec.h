@@ -48,4 +48,27 @@ __device__ inline float vel_decode(uint32_t j, float vmax) {
   return (float)(((double)j - 32767.5) * w);
 }
 
+// vel_code for a power-of-two v_max in [2^-90, 2^90], in float32 with the same result
+// on every input. x = v C is exact (C a power of two; an overflow to +-inf or an
+// underflow of a value below 2^-126 cannot change the outcome), and x + 32768 is exact
+// in float64 except for |x| < 2^-15, where the float64 sum rounds up to 32768 exactly
+// when -2^-39 <= x < 0 (ties to even). C is passed in as 2^15 / v_max.
+__device__ inline int vel_code_p2(float v, float C) {
+#pragma clang fp contract(off)
+  const float x = v * C;
+  float fl = floorf(x);
+  if (x < 0.f && x >= -0x1p-39f) fl = 0.f;
+  if (!(fl >= -32768.f)) return 0;  // also NaN
+  if (fl >= 32767.f) return 65535;
+  return (int)fl + 32768;
+}
+
+// vel_decode for v_max in [2^-90, 2^90], in float32 with the same result: j - 32767.5
+// and w = v_max 2^-15 are exact in float32, so the one product is the same correctly
+// rounded value as the float64 product rounded to float32. w is passed in.
+__device__ inline float vel_decode_w(uint32_t j, float w) {
+#pragma clang fp contract(off)
+  return ((float)j - 32767.5f) * w;
+}
+
 pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_t* out);

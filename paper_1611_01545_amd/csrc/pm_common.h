@@ -153,6 +153,7 @@ enum ScratchId {
   SC_SPOFF3,
   SC_PARTS,        // per-workgroup partial results of grid reductions
   SC_SPEC,         // float [ng^3] spectrum scratch of the force transforms
+  SC_FOLD,         // first-stage results of the grid min / max folds
   SC_N
 };
 

@@ -16,7 +16,10 @@
 //   k_arrivals      per new cell: arrivals, and how many of them come from earlier
 //                   bricks (they precede the cell's stayers in stream order).
 //   scan            new cell offsets.
-//   k_place_*       stayers and movers written at their final stream positions.
+//   k_place_*       stayers and movers written at their final stream positions
+//                   (per brick, the stayers' per-cell destinations staged in LDS).
+#include <type_traits>
+
 #include "pm_codec.h"
 #include "pm_scan.h"
 
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   const int fsz = STAGE ? 3 * R1 * R1 * R1 : 0;
   int64_t* loffs = (int64_t*)(smem + ((fsz * 4 + 7) / 8) * 8);  // [MAXSP][B3 + 1]
   uint32_t* run = (uint32_t*)(loffs + MAXSP * (B3 + 1));       // [B3 + 1] (B3 = movers)
-  uint32_t* wcnt = run + (B3 + 1);                             // [2][KB/64][B3 + 1]
+  uint32_t* wcnt = run + (B3 + 1);  // [2][KB/64][B3 + 1], then rel [B3 + 1]
   constexpr int NW = KB / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
@@ -187,33 +190,71 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
     const int64_t hx = (ox + RS) & m;
     float4 vq[PQ];
     float vh[PH];
+    // row index (c R1 + lz) R1 + ly advanced by KB / Q rows per load without divisions
+    constexpr int RR = R1 * R1;
+    constexpr int DR = KB / Q;
+    constexpr int DC = DR / RR, DLZ = (DR % RR) / R1, DLY = DR % R1;
+    static_assert(KB % Q == 0, "a workgroup covers whole rows");
+    const float* pc0 = A.acc;
+    const float* pc1 = A.acc + n3;
+    const float* pc2 = A.acc + 2 * n3;
+    const uint32_t mu = (uint32_t)m, ngu = (uint32_t)ng;
+    const uint32_t oxq = (uint32_t)ox + 4 * (threadIdx.x % Q);
+    const int row0 = threadIdx.x / Q;
+    {
+      int c = row0 / RR, lz = (row0 % RR) / R1, ly = row0 % R1;
 #pragma unroll
-    for (int k = 0; k < PQ; ++k) {
-      const int i = min((int)threadIdx.x + k * KB, NQ - 1);
-      const int row = i / Q, q = i - row * Q;
-      const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
-      const int lz = rem / R1, ly = rem - lz * R1;
-      const int64_t gz = (oz + lz) & m, gy = (oy + ly) & m;
-      vq[k] = *(const float4*)(A.acc + c * n3 + (gz * ng + gy) * ng + ox + 4 * q);
+      for (int k = 0; k < PQ; ++k) {
+        const bool over = c >= 3;  // past the end: load the last row again (not stored)
+        const int cc = over ? 2 : c, zz = over ? R1 - 1 : lz, yy = over ? R1 - 1 : ly;
+        const float* pc = cc == 0 ? pc0 : (cc == 1 ? pc1 : pc2);
+        const uint32_t gz = ((uint32_t)oz + zz) & mu, gy = ((uint32_t)oy + yy) & mu;
+        vq[k] = *(const float4*)(pc + ((uint64_t)(gz * ngu + gy) * ngu + oxq));
+        ly += DLY;
+        lz += DLZ;
+        c += DC;
+        if (ly >= R1) {
+          ly -= R1;
+          ++lz;
+        }
+        if (lz >= R1) {
+          lz -= R1;
+          ++c;
+        }
+      }
     }
 #pragma unroll
     for (int k = 0; k < PH; ++k) {
       const int row = min((int)threadIdx.x + k * KB, ROWS - 1);
-      const int c = row / (R1 * R1), rem = row - c * (R1 * R1);
+      const int c = row / RR, rem = row - c * RR;
       const int lz = rem / R1, ly = rem - lz * R1;
-      const int64_t gz = (oz + lz) & m, gy = (oy + ly) & m;
-      vh[k] = A.acc[c * n3 + (gz * ng + gy) * ng + hx];
+      const float* pc = c == 0 ? pc0 : (c == 1 ? pc1 : pc2);
+      const uint32_t gz = ((uint32_t)oz + lz) & mu, gy = ((uint32_t)oy + ly) & mu;
+      vh[k] = pc[(uint64_t)(gz * ngu + gy) * ngu + (uint32_t)hx];
     }
+    {
+      int c = row0 / RR, lz = (row0 % RR) / R1, ly = row0 % R1;
+      const int q4 = 4 * (threadIdx.x % Q);
 #pragma unroll
-    for (int k = 0; k < PQ; ++k) {
-      const int i = threadIdx.x + k * KB;
-      if (i < NQ) {
-        const int row = i / Q, q = i - row * Q;
-        float* d = F + row * R1 + 4 * q;
-        d[0] = vq[k].x;
-        d[1] = vq[k].y;
-        d[2] = vq[k].z;
-        d[3] = vq[k].w;
+      for (int k = 0; k < PQ; ++k) {
+        if (c < 3) {
+          float* d = F + ((c * R1 + lz) * R1 + ly) * R1 + q4;
+          d[0] = vq[k].x;
+          d[1] = vq[k].y;
+          d[2] = vq[k].z;
+          d[3] = vq[k].w;
+        }
+        ly += DLY;
+        lz += DLZ;
+        c += DC;
+        if (ly >= R1) {
+          ly -= R1;
+          ++lz;
+        }
+        if (lz >= R1) {
+          lz -= R1;
+          ++c;
+        }
       }
     }
 #pragma unroll
@@ -247,6 +288,10 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   }
 
   const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
+  const uint32_t mB = (uint32_t)B - 1;
+  const uint32_t bc[3] = {bcx, bcy, bcz};
+  const uint32_t Sm = (uint32_t)g.S - 1;
+  const double Sd = (double)g.S, invS = 1.0 / Sd;  // powers of two
   bool bad = false;
   __shared__ int mm[2 * NW];  // per-wave extreme velocity codes
   // Rounds of KB particles in stream order. Per round: (1) new codes and digits, stable
@@ -255,135 +300,157 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   // and the other count buffer cleared for the next round; barrier; (3) running counts
   // advanced (overlaps the next round's step 1, which uses the other buffer).
   const int WS = NW * (B3 + 1);
+  uint32_t* rel = wcnt + 2 * WS;  // [B3 + 1]: cell offsets relative to the brick's first
 #pragma unroll
   for (int s = 0; s < MAXSP; ++s) {
     if (s >= n_sp) break;
     const KickSpecies& S = A.sp[s];
     const int64_t* loff = loffs + s * (B3 + 1);
-    __syncthreads();  // previous species done with run and wcnt
-    for (int i = threadIdx.x; i <= B3; i += KB) run[i] = 0;
+    __syncthreads();  // previous species done with run, rel and wcnt
+    const int64_t l0 = loff[0];
+    for (int i = threadIdx.x; i <= B3; i += KB) {
+      run[i] = 0;
+      rel[i] = (uint32_t)(loff[i] - l0);
+    }
     for (int i = threadIdx.x; i < 2 * WS; i += KB) wcnt[i] = 0;
     __syncthreads();
-    const int64_t j0 = min(loff[0], S.n), j1 = min(loff[B3], S.n);
+    const int64_t j0 = min(l0, S.n), j1 = min(loff[B3], S.n);
+    // float32 forms of the velocity codec where they give the same codes (uniform)
     const float vmax_in = vin[s];
     const float vmax_out = vout[s];
+    const bool fdec = vmax_in >= 0x1p-90f && vmax_in <= 0x1p90f;
+    const uint32_t ob = __float_as_uint(vmax_out);
+    const bool fenc = vmax_out >= 0x1p-90f && vmax_out <= 0x1p90f && (ob & 0x7fffffu) == 0;
+    const float wdec = vmax_in * 0x1p-15f;
+    const float cenc = __uint_as_float((269u - (ob >> 23)) << 23);  // 2^15 / v_max
     int jmin = 65536, jmax = -1;
-    int rnd = 0;
-    for (int64_t base = j0; base < j1; base += KB, ++rnd) {
-      uint32_t* wc = wcnt + (rnd & 1) * WS;
-      uint32_t* wo = wcnt + ((rnd & 1) ^ 1) * WS;
-      const int64_t j = base + threadIdx.x;
-      const bool valid = j < j1;
-      uint32_t digit = 0, newkey = 0;
-      if (valid) {
-        // the particle's codes: prefetched for the first round
-        uint32_t pb[3], vc[3];
-        if (base == j0) {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            pb[a] = pre_pb[s][a];
-            vc[a] = pre_vc[s][a];
-          }
-        } else {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            pb[a] = S.pos[3 * j + a];
-            vc[a] = S.vel[3 * j + a];
-          }
-        }
-        int lo = 0, hi = B3;  // local cell: largest l with loff[l] <= j
-        while (hi - lo > 1) {
-          int mid = (lo + hi) >> 1;
-          if (loff[mid] <= j) lo = mid; else hi = mid;
-        }
-        uint32_t cx, cy, cz;
-        key_cell(g, kbase + (uint32_t)lo, cx, cy, cz);
-        const uint32_t cell[3] = {cx, cy, cz};
-        const int64_t org[3] = {ox, oy, oz};
-        uint32_t u[3];
-        int li[3];
-        float f[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          u[a] = (cell[a] << 8) | pb[a];
-          const int64_t gg = (2 * (int64_t)u[a] + 1) * r;  // 1/512 mesh cells
-          li[a] = (int)((gg >> 9) - org[a]);               // node index inside the brick
-          f[a] = (float)(gg & 511) * (1.0f / 512.0f);
-        }
-        float acc3[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-              const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
-                                (dz ? f[2] : 1.f - f[2]);
-              if constexpr (STAGE) {
-                const int node = ((li[2] + dz) * R1 + (li[1] + dy)) * R1 + (li[0] + dx);
-                acc3[0] += wgt * F[node];
-                acc3[1] += wgt * F[R1 * R1 * R1 + node];
-                acc3[2] += wgt * F[2 * R1 * R1 * R1 + node];
-              } else {
-                const int64_t m = ng - 1;
-                const int64_t nz = (oz + li[2] + dz) & m, ny = (oy + li[1] + dy) & m,
-                              nx = (ox + li[0] + dx) & m;
-                const int64_t node = (nz * ng + ny) * ng + nx;
-                acc3[0] += wgt * A.acc[node];
-                acc3[1] += wgt * A.acc[n3 + node];
-                acc3[2] += wgt * A.acc[2 * n3 + node];
-              }
+    // the round loop, compiled once with the float32 codec forms and once without
+    auto rounds = [&](auto fast) {
+      constexpr bool FAST = decltype(fast)::value;
+      int rnd = 0;
+      for (int64_t base = j0; base < j1; base += KB, ++rnd) {
+        uint32_t* wc = wcnt + (rnd & 1) * WS;
+        uint32_t* wo = wcnt + ((rnd & 1) ^ 1) * WS;
+        const int64_t j = base + threadIdx.x;
+        const bool valid = j < j1;
+        const uint32_t t3 = 3 * threadIdx.x;
+        uint32_t digit = 0, un[3] = {0, 0, 0};
+        if (valid) {
+          // the particle's codes: prefetched for the first round
+          uint32_t pb[3], vc[3];
+          if (base == j0) {
+  #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              pb[a] = pre_pb[s][a];
+              vc[a] = pre_vc[s][a];
             }
-        uint32_t un[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const float v0 = vel_decode(vc[a], vmax_in);
-          const float v1 = v0 + A.ck * acc3[a];
-          const double d = floor((double)v1 * A.cdS + 0.5);
-          const bool okd = fabs(d) < 4.0e15;
-          bad |= !okd;
-          int64_t q = ((int64_t)u[a] + (okd ? (int64_t)d : 0)) & (g.S - 1);  // S = 2^k
-          un[a] = (uint32_t)q;
-          const int jc = vel_code(v1, vmax_out);
-          S.tpos[3 * j + a] = (uint8_t)(un[a] & 255u);
-          S.tvel[3 * j + a] = (uint16_t)jc;
-          jmin = min(jmin, jc);
-          jmax = max(jmax, jc);
+          } else {
+            const uint8_t* pp = S.pos + 3 * base;
+            const uint16_t* vp = S.vel + 3 * base;
+  #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              pb[a] = pp[t3 + a];
+              vc[a] = vp[t3 + a];
+            }
+          }
+          const uint32_t jr = (uint32_t)(base - l0) + threadIdx.x;
+          int lo = 0, hi = B3;  // local cell: largest l with rel[l] <= jr
+          while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (rel[mid] <= jr) lo = mid; else hi = mid;
+          }
+          const uint32_t lc[3] = {(uint32_t)lo & mB, ((uint32_t)lo >> g.lgB) & mB,
+                                  (uint32_t)lo >> (2 * g.lgB)};
+          int li[3];
+          float f[3];
+  #pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            // position in 1/512 mesh cells from the brick's corner node: (2 u + 1) r
+            const uint32_t gl = (2 * ((lc[a] << 8) | pb[a]) + 1) * (uint32_t)r;
+            li[a] = (int)(gl >> 9);
+            f[a] = (float)(gl & 511u) * (1.0f / 512.0f);
+          }
+          float acc3[3] = {0.f, 0.f, 0.f};
+  #pragma unroll
+          for (int dz = 0; dz < 2; ++dz)
+  #pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+  #pragma unroll
+              for (int dx = 0; dx < 2; ++dx) {
+                const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
+                                  (dz ? f[2] : 1.f - f[2]);
+                if constexpr (STAGE) {
+                  const int node = ((li[2] + dz) * R1 + (li[1] + dy)) * R1 + (li[0] + dx);
+                  acc3[0] += wgt * F[node];
+                  acc3[1] += wgt * F[R1 * R1 * R1 + node];
+                  acc3[2] += wgt * F[2 * R1 * R1 * R1 + node];
+                } else {
+                  const int64_t m = ng - 1;
+                  const int64_t nz = (oz + li[2] + dz) & m, ny = (oy + li[1] + dy) & m,
+                                nx = (ox + li[0] + dx) & m;
+                  const int64_t node = (nz * ng + ny) * ng + nx;
+                  acc3[0] += wgt * A.acc[node];
+                  acc3[1] += wgt * A.acc[n3 + node];
+                  acc3[2] += wgt * A.acc[2 * n3 + node];
+                }
+              }
+          uint8_t* tp = S.tpos + 3 * base;
+          uint16_t* tv = S.tvel + 3 * base;
+          uint32_t nl[3];
+  #pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float v0 = FAST ? vel_decode_w(vc[a], wdec) : vel_decode(vc[a], vmax_in);
+            const float v1 = v0 + A.ck * acc3[a];
+            const double d = floor((double)v1 * A.cdS + 0.5);
+            const bool okd = fabs(d) < 4.0e15;
+            bad |= !okd;
+            // d mod S, exact in float64 (d is an integer below 2^52, S a power of two)
+            const double dm = okd ? d - Sd * floor(d * invS) : 0.0;
+            un[a] = ((((bc[a] + lc[a]) << 8) | pb[a]) + (uint32_t)dm) & Sm;
+            nl[a] = (un[a] >> 8) - bc[a];  // new local cell (wraps above B when outside)
+            const int jc = FAST ? vel_code_p2(v1, cenc) : vel_code(v1, vmax_out);
+            tp[t3 + a] = (uint8_t)(un[a] & 255u);
+            tv[t3 + a] = (uint16_t)jc;
+            jmin = min(jmin, jc);
+            jmax = max(jmax, jc);
+          }
+          digit = (nl[0] <= mB && nl[1] <= mB && nl[2] <= mB)
+                      ? (((nl[2] << g.lgB) | nl[1]) << g.lgB) | nl[0]
+                      : (uint32_t)B3;
         }
-        newkey = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
-        digit = (newkey >= kbase && newkey < kbase + (uint32_t)B3) ? newkey - kbase
-                                                                  : (uint32_t)B3;
-      }
-      // stable multi-split of this round by digit (new local cell, or B3 for movers)
-      uint64_t match = __ballot(valid);
-      for (int bit = 0; bit < nbits; ++bit) {
-        uint64_t mbit = __ballot(valid && ((digit >> bit) & 1u));
-        match &= ((digit >> bit) & 1u) ? mbit : ~mbit;
-      }
-      const uint32_t rk = (uint32_t)__popcll(match & lt);
-      if (valid && rk == 0) wc[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
-      __syncthreads();
-      if (valid) {
-        uint32_t pre = run[digit];
-        for (int q = 0; q < w; ++q) pre += wc[q * (B3 + 1) + digit];
-        const uint32_t rank = pre + rk;
-        if (digit < (uint32_t)B3) {
-          if (rank >= RANK_LIMIT) bad = true;
-          S.tdst[j] = (digit << RANK_BITS) | (rank & RANK_LIMIT);
-        } else {
-          S.tdst[j] = MOVER;
-          S.mkey[j0 + rank] = newkey;
-          S.midx[j0 + rank] = (uint32_t)j;
+        // stable multi-split of this round by digit (new local cell, or B3 for movers)
+        uint64_t match = __ballot(valid);
+        for (int bit = 0; bit < nbits; ++bit) {
+          uint64_t mbit = __ballot(valid && ((digit >> bit) & 1u));
+          match &= ((digit >> bit) & 1u) ? mbit : ~mbit;
+        }
+        const uint32_t rk = (uint32_t)__popcll(match & lt);
+        if (valid && rk == 0) wc[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (valid) {
+          uint32_t pre = run[digit];
+          for (int q = 0; q < w; ++q) pre += wc[q * (B3 + 1) + digit];
+          const uint32_t rank = pre + rk;
+          if (digit < (uint32_t)B3) {
+            if (rank >= RANK_LIMIT) bad = true;
+            S.tdst[j] = (digit << RANK_BITS) | (rank & RANK_LIMIT);
+          } else {
+            S.tdst[j] = MOVER;
+            S.mkey[j0 + rank] = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
+            S.midx[j0 + rank] = (uint32_t)j;
+          }
+        }
+        for (int i = threadIdx.x; i < WS; i += KB) wo[i] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i <= B3; i += KB) {
+          uint32_t add = 0;
+          for (int q = 0; q < NW; ++q) add += wc[q * (B3 + 1) + i];
+          run[i] += add;
         }
       }
-      for (int i = threadIdx.x; i < WS; i += KB) wo[i] = 0;
-      __syncthreads();
-      for (int i = threadIdx.x; i <= B3; i += KB) {
-        uint32_t add = 0;
-        for (int q = 0; q < NW; ++q) add += wc[q * (B3 + 1) + i];
-        run[i] += add;
-      }
-    }
+    };
+    if (fdec && fenc) rounds(std::true_type{});
+    else rounds(std::false_type{});
     // the thread that advanced run[i] writes it out
     for (int i = threadIdx.x; i <= B3; i += KB) {
       if (i < B3) S.cnt[kbase + i] = (uint64_t)run[i];
@@ -448,30 +515,52 @@ __global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uin
   atomicAdd((unsigned long long*)&cnt[k], (unsigned long long)(((uint64_t)nb << 32) | (uint64_t)(ge - s)));
 }
 
+// One workgroup per brick. The first stream position of the brick's stayers in each
+// new cell (cell offset + arrivals from earlier bricks) is staged in LDS, so a stayer
+// needs its own coalesced loads only; each thread takes U particles per pass with all
+// their loads issued before any store.
 __global__ __launch_bounds__(KT) void k_place_stayers(const int64_t* off_in, const uint32_t* tdst,
                                                      const uint8_t* tpos, const uint16_t* tvel,
                                                      const uint64_t* cnt, const int64_t* off_new,
                                                      int B3, uint8_t* pos, uint16_t* vel,
                                                      int64_t* perm, int64_t n, DevErr* err) {
+  extern __shared__ int64_t dbase[];  // [B3]
+  constexpr int U = 2;
   const int64_t b = blockIdx.x;
   const int64_t kbase = b * B3;
+  for (int l = threadIdx.x; l < B3; l += KT)
+    dbase[l] = off_new[kbase + l] + (int64_t)(cnt[kbase + l] >> 32);
   const int64_t j0 = min(off_in[kbase], n), j1 = min(off_in[kbase + B3], n);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += KT) {
-    const uint32_t d = tdst[j];
-    if (d == MOVER) continue;
-    const int64_t key = kbase + (d >> RANK_BITS);
-    const int64_t dst = off_new[key] + (int64_t)(cnt[key] >> 32) + (d & RANK_LIMIT);
-    if (dst < 0 || dst >= n) {
-      latch_error(err, ERRBIT_CORRUPT);
-      continue;
+  __syncthreads();
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += U * KT) {
+    uint32_t d[U], p[U][3], v[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t ju = j + u * KT;
+      const bool h = ju < j1;
+      const int64_t jj = h ? ju : j;
+      d[u] = h ? tdst[jj] : MOVER;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        p[u][a] = tpos[3 * jj + a];
+        v[u][a] = tvel[3 * jj + a];
+      }
     }
-    pos[3 * dst] = tpos[3 * j];
-    pos[3 * dst + 1] = tpos[3 * j + 1];
-    pos[3 * dst + 2] = tpos[3 * j + 2];
-    vel[3 * dst] = tvel[3 * j];
-    vel[3 * dst + 1] = tvel[3 * j + 1];
-    vel[3 * dst + 2] = tvel[3 * j + 2];
-    if (perm) perm[dst] = j;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (d[u] == MOVER) continue;
+      const int64_t dst = dbase[d[u] >> RANK_BITS] + (int64_t)(d[u] & RANK_LIMIT);
+      if (dst < 0 || dst >= n) {
+        latch_error(err, ERRBIT_CORRUPT);
+        continue;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pos[3 * dst + a] = (uint8_t)p[u][a];
+        vel[3 * dst + a] = (uint16_t)v[u][a];
+      }
+      if (perm) perm[dst] = j + u * KT;
+    }
   }
 }
 
@@ -583,7 +672,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     const int R1 = g.B * g.r + 1;
     const size_t fbytes = (size_t)3 * R1 * R1 * R1 * 4;
     const size_t tail =
-        (size_t)MAXSP * (B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (1 + 2 * (KB / 64));
+        (size_t)MAXSP * (B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (2 + 2 * (KB / 64));
     const int R = g.B * g.r;
     if (R == 16 && fbytes + tail <= 96 * 1024)
       hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB),
@@ -630,7 +719,8 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
-    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
+    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT),
+                       (size_t)B3 * 8, c->stream,
                        S.off, S.tdst, S.tpos, S.tvel, S.cnt, off_new, B3, out[s].pos,
                        out[s].vel, pm, n, c->err);
     PM_LAUNCH_CHECK();

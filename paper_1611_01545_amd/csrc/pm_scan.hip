@@ -81,14 +81,13 @@ __global__ void k_iota(int64_t* p, int64_t n) {
   if (i < n) p[i] = i;
 }
 
-__global__ __launch_bounds__(1024) void k_fold_minmax(const int32_t* mn, const int32_t* mx,
-                                                      int64_t n, pm_shdr* h) {
-  __shared__ int smn[16], smx[16];
-  int a = 65536, b = -1;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    a = min(a, mn[i]);
-    b = max(b, mx[i]);
-  }
+// Grid folds in two launches: FOLD_G workgroups reduce strided slices of the partials
+// to one pair each, then one workgroup reduces those.
+constexpr int FOLD_T = 256;
+constexpr int FOLD_G = 256;
+
+__device__ inline void block_minmax(int& a, int& b) {
+  __shared__ int smn[FOLD_T / 64], smx[FOLD_T / 64];
   for (int d = 32; d >= 1; d >>= 1) {
     a = min(a, __shfl_xor(a, d, 64));
     b = max(b, __shfl_xor(b, d, 64));
@@ -98,41 +97,73 @@ __global__ __launch_bounds__(1024) void k_fold_minmax(const int32_t* mn, const i
     smx[threadIdx.x >> 6] = b;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < 16; ++q) {
+  if (threadIdx.x == 0)
+    for (int q = 1; q < FOLD_T / 64; ++q) {
       a = min(a, smn[q]);
       b = max(b, smx[q]);
     }
+}
+
+__global__ __launch_bounds__(FOLD_T) void k_fold_minmax_part(const int32_t* mn,
+                                                             const int32_t* mx, int64_t n,
+                                                             int32_t* part) {
+  int a = 65536, b = -1;
+  for (int64_t i = (int64_t)blockIdx.x * FOLD_T + threadIdx.x; i < n;
+       i += (int64_t)FOLD_T * gridDim.x) {
+    a = min(a, mn[i]);
+    b = max(b, mx[i]);
+  }
+  block_minmax(a, b);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ __launch_bounds__(FOLD_T) void k_fold_minmax(const int32_t* part, int g,
+                                                        pm_shdr* h) {
+  int a = 65536, b = -1;
+  for (int i = threadIdx.x; i < g; i += FOLD_T) {
+    a = min(a, part[2 * i]);
+    b = max(b, part[2 * i + 1]);
+  }
+  block_minmax(a, b);
+  if (threadIdx.x == 0) {
     h->j_min = a;
     h->j_max = b;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_fold_max(const uint32_t* part, int64_t n,
-                                                   uint32_t* out) {
-  __shared__ uint32_t sm[16];
-  uint32_t a = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) a = max(a, part[i]);
-  for (int d = 32; d >= 1; d >>= 1) a = max(a, (uint32_t)__shfl_xor((int)a, d, 64));
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < 16; ++q) a = max(a, sm[q]);
-    *out = a;
-  }
+__global__ __launch_bounds__(FOLD_T) void k_fold_max_part(const uint32_t* part, int64_t n,
+                                                          uint32_t* out) {
+  int a = 0, b = 0;  // values as non-negative float bit patterns fit int
+  for (int64_t i = (int64_t)blockIdx.x * FOLD_T + threadIdx.x; i < n;
+       i += (int64_t)FOLD_T * gridDim.x)
+    b = max(b, (int)part[i]);
+  block_minmax(a, b);
+  if (threadIdx.x == 0) out[blockIdx.x] = (uint32_t)b;
 }
 
 }  // namespace
 
 pm_status fold_minmax_to_header(pm_context* c, const int32_t* mn, const int32_t* mx,
                                 int64_t n, pm_shdr* hdr) {
-  hipLaunchKernelGGL(k_fold_minmax, dim3(1), dim3(1024), 0, c->stream, mn, mx, n, hdr);
+  const int g = (int)std::min<int64_t>(FOLD_G, std::max<int64_t>(1, (n + FOLD_T - 1) / FOLD_T));
+  int32_t* part = (int32_t*)scratch(c, SC_FOLD, (size_t)2 * FOLD_G * sizeof(int32_t));
+  if (!part) return PM_ERR_NOMEM;
+  hipLaunchKernelGGL(k_fold_minmax_part, dim3(g), dim3(FOLD_T), 0, c->stream, mn, mx, n, part);
+  hipLaunchKernelGGL(k_fold_minmax, dim3(1), dim3(FOLD_T), 0, c->stream, part, g, hdr);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
 
+// max of non-negative float bit patterns (or any values below 2^31)
 pm_status fold_max_u32(pm_context* c, const uint32_t* part, int64_t n, uint32_t* out) {
-  hipLaunchKernelGGL(k_fold_max, dim3(1), dim3(1024), 0, c->stream, part, n, out);
+  const int g = (int)std::min<int64_t>(FOLD_G, std::max<int64_t>(1, (n + FOLD_T - 1) / FOLD_T));
+  uint32_t* p2 = (uint32_t*)scratch(c, SC_FOLD, (size_t)2 * FOLD_G * sizeof(int32_t));
+  if (!p2) return PM_ERR_NOMEM;
+  hipLaunchKernelGGL(k_fold_max_part, dim3(g), dim3(FOLD_T), 0, c->stream, part, n, p2);
+  hipLaunchKernelGGL(k_fold_max_part, dim3(1), dim3(FOLD_T), 0, c->stream, p2, (int64_t)g, out);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
