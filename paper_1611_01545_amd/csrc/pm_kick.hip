@@ -7,17 +7,22 @@
 //                   decoded |v| of the input, from its extreme velocity codes; A_max:
 //                   largest |a| on the mesh). Interpolation is a convex combination of
 //                   mesh values, so no kicked component exceeds the bound.
-//   k_kick_brick    one workgroup per brick of B^3 cells, particles in stream order:
+//   k_kick_pair     two bricks adjacent along x per workgroup (R = 16 nodes per brick
+//   k_kick_brick    side), or one brick of any shape: the force nodes staged in LDS,
+//                   then waves take 64-particle chunks independently (no barrier):
 //                   decode, gather a from the 8 CIC nodes, v' = v + c_k a, fixed-point
-//                   drift u' = u + floor(v' c_d S + 1/2), new codes. Particles that
-//                   stay inside the brick get their stable rank inside their new cell;
-//                   the others ("movers") are listed with (new cell, old index).
-//   movers          compacted in old order, stably radix-sorted by new cell.
+//                   drift u' = u + floor(v' c_d S + 1/2), new codes, and the digit: the
+//                   new cell inside the brick, or B^3 for a particle that leaves it (a
+//                   "mover", whose new cell key is kept). Stayers are counted per new
+//                   cell and movers per brick with LDS atomics.
+//   movers          compacted in old order (block scan over the digits), stably
+//                   radix-sorted by new cell.
 //   k_arrivals      per new cell: arrivals, and how many of them come from earlier
 //                   bricks (they precede the cell's stayers in stream order).
 //   scan            new cell offsets.
-//   k_place_*       stayers and movers written at their final stream positions
-//                   (per brick, the stayers' per-cell destinations staged in LDS).
+//   k_place_*       stayers and movers written at their final stream positions: per
+//                   brick, the stayers' first position in each new cell staged in LDS and
+//                   their stable rank from a multi-split of the digits.
 #include <type_traits>
 
 #include "pm_codec.h"
@@ -26,9 +31,6 @@
 namespace {
 
 constexpr int KT = 256;  // threads per workgroup
-constexpr uint32_t MOVER = 0xffffffffu;
-constexpr uint32_t RANK_BITS = 23;
-constexpr uint32_t RANK_LIMIT = (1u << RANK_BITS) - 1;
 
 // ------------------------------------------------------------ float layout --
 __global__ __launch_bounds__(KT) void k_kick_float(const float* x, const float* v, float* xo,
@@ -97,7 +99,8 @@ __global__ void k_vmax_next(const pm_shdr* hin, pm_shdr* hout, const float* amax
   hout->reserved = 0;
 }
 
-constexpr int KB = 512;       // threads per workgroup of the brick kick
+constexpr int KB = 512;  // threads per workgroup of the brick kicks
+constexpr int NWK = KB / 64;
 constexpr int MAXSP = 4;
 
 struct KickSpecies {
@@ -106,106 +109,205 @@ struct KickSpecies {
   const uint16_t* vel;
   const pm_shdr* hin;
   pm_shdr* hout;
-  const int64_t* off;   // input cell offsets [ncell3 + 1]
-  uint8_t* tpos;        // new codes, old stream order
+  const int64_t* off;  // input cell offsets [ncell3 + 1]
+  uint8_t* tpos;       // new codes, old stream order
   uint16_t* tvel;
-  uint32_t* tdst;       // (new local cell << 23) | rank, or MOVER
-  uint64_t* cnt;        // per cell: stayers (low 32 bits)
-  uint32_t* mkey;       // movers: new cell key, at [brick start + mover rank]
-  uint32_t* midx;       // movers: old stream index
-  uint32_t* mcnt;       // movers per brick
-  int32_t* pmn;         // per-brick extreme new velocity codes, folded into hout
+  uint16_t* tdig;      // new local cell in the brick, or B^3 for movers
+  uint32_t* mkey;      // movers: new cell key, at the old stream index
+  uint64_t* cnt;       // per cell: stayers (low 32 bits)
+  uint32_t* mcnt;      // movers per brick
+  int32_t* pmn;        // per-brick extreme new velocity codes, folded into hout
   int32_t* pmx;
 };
 struct KickArgs {
   KickSpecies sp[MAXSP];
   int n_sp;
-  const float* acc;     // [3][ng^3]
+  const float* acc;  // [3][ng^3]
   float ck;
-  double cdS;           // c_d * S (position codes per unit velocity)
+  double cdS;        // c_d * S (position codes per unit velocity)
 };
 
-// One workgroup per brick, all species. With STAGE the brick's force nodes
-// [b R, b R + R]^3 (R = B r) are first copied to LDS with coalesced loads and every
-// particle gathers its 8 CIC nodes from there; the mesh is then read once per step
-// for all species. The global reads of a workgroup form two rounds: (1) the force
-// tile, every species' cell offsets and velocity headers; (2) the codes of the first
-// chunk of every species. Only species with more than KB particles in the brick load
-// later chunks on the way.
+// Codec constants of one species (uniform).
+struct Codec {
+  float vmi, vmo, wd, ce;
+};
+__device__ inline Codec codec_of(const KickSpecies& S) {
+  Codec k;
+  k.vmi = S.hin->v_max;
+  k.vmo = S.hout->v_max;
+  k.wd = k.vmi * 0x1p-15f;
+  k.ce = __uint_as_float((269u - (__float_as_uint(k.vmo) >> 23)) << 23);  // 2^15 / v_max'
+  return k;
+}
+// float32 codec forms valid for every species (see vel_code_p2, vel_decode_w)
+__device__ inline bool codec_fast(const KickArgs& A) {
+  bool fast = true;
+  for (int s = 0; s < A.n_sp; ++s) {
+    const float vi = A.sp[s].hin->v_max, vo = A.sp[s].hout->v_max;
+    fast = fast && vi >= 0x1p-90f && vi <= 0x1p90f && vo >= 0x1p-90f && vo <= 0x1p90f &&
+           (__float_as_uint(vo) & 0x7fffffu) == 0;
+  }
+  return fast;
+}
+
+// One wave kicks up to 64 consecutive particles [jc, min(jc + 64, jend)) of one species
+// in one brick: decode, gather a through `gather(li, f)` (node index inside the brick,
+// CIC fractions), kick, fixed-point drift, new codes. Writes the new codes and the
+// particle's digit (new local cell, or B^3 when it leaves the brick; movers also get
+// their new cell key), counts stayers per new cell and movers in LDS, and folds the
+// wave's extreme velocity codes into smm. No barrier: waves are independent.
+template <bool FAST, typename Gather>
+__device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const Geom& g,
+                                  const Codec& cd, int64_t jc, int64_t jend, int64_t l0,
+                                  const uint32_t* rel, int lo0, int hi0, const uint32_t bc[3],
+                                  uint32_t* run, uint32_t* mvc, int* smm, bool& bad,
+                                  Gather gather) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = jc + lane;
+  const int B3 = g.B * g.B * g.B;
+  const uint32_t mB = (uint32_t)g.B - 1;
+  int jmn = 65536, jmx = -1;
+  if (j < jend) {
+    const uint32_t t3 = 3 * (uint32_t)lane;
+    const uint8_t* pp = S.pos + 3 * jc;
+    const uint16_t* vp = S.vel + 3 * jc;
+    uint32_t pb[3], vc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pb[a] = pp[t3 + a];
+      vc[a] = vp[t3 + a];
+    }
+    const uint32_t jr = (uint32_t)(j - l0);
+    int lo = lo0, hi = hi0;  // local cell: largest l with rel[l] <= jr
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (rel[mid] <= jr) lo = mid; else hi = mid;
+    }
+    const uint32_t lc[3] = {(uint32_t)lo & mB, ((uint32_t)lo >> g.lgB) & mB,
+                            (uint32_t)lo >> (2 * g.lgB)};
+    int li[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      // position in 1/512 mesh cells from the brick's corner node: (2 u + 1) r
+      const uint32_t gl = (2 * ((lc[a] << 8) | pb[a]) + 1) * (uint32_t)g.r;
+      li[a] = (int)(gl >> 9);
+      f[a] = (float)(gl & 511u) * (1.0f / 512.0f);
+    }
+    float acc3[3];
+    gather(li, f, acc3);
+    const uint32_t Sm = (uint32_t)g.S - 1;
+    const double Sd = (double)g.S, invS = 1.0 / Sd;  // powers of two
+    uint8_t* tp = S.tpos + 3 * jc;
+    uint16_t* tv = S.tvel + 3 * jc;
+    uint32_t un[3], nl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float v0 = FAST ? vel_decode_w(vc[a], cd.wd) : vel_decode(vc[a], cd.vmi);
+      const float v1 = v0 + A.ck * acc3[a];
+      const double d = floor((double)v1 * A.cdS + 0.5);
+      const bool okd = fabs(d) < 4.0e15;
+      bad |= !okd;
+      // d mod S, exact in float64 (d is an integer below 2^52, S a power of two)
+      const double dm = okd ? d - Sd * floor(d * invS) : 0.0;
+      un[a] = ((((bc[a] + lc[a]) << 8) | pb[a]) + (uint32_t)dm) & Sm;
+      nl[a] = (un[a] >> 8) - bc[a];  // new local cell (wraps above B when outside)
+      const int jv = FAST ? vel_code_p2(v1, cd.ce) : vel_code(v1, cd.vmo);
+      tp[t3 + a] = (uint8_t)(un[a] & 255u);
+      tv[t3 + a] = (uint16_t)jv;
+      jmn = min(jmn, jv);
+      jmx = max(jmx, jv);
+    }
+    if (nl[0] <= mB && nl[1] <= mB && nl[2] <= mB) {
+      const uint32_t digit = (((nl[2] << g.lgB) | nl[1]) << g.lgB) | nl[0];
+      S.tdig[j] = (uint16_t)digit;
+      atomicAdd(&run[digit], 1u);
+    } else {
+      S.tdig[j] = (uint16_t)B3;
+      S.mkey[j] = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
+      atomicAdd(mvc, 1u);
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    jmn = min(jmn, __shfl_xor(jmn, d, 64));
+    jmx = max(jmx, __shfl_xor(jmx, d, 64));
+  }
+  if (lane == 0 && jmx >= 0) {
+    atomicMin(&smm[0], jmn);
+    atomicMax(&smm[1], jmx);
+  }
+}
+
+// Chunks of 64 particles over a list of segments (one species' particles in one brick,
+// or in one z half of it), dealt to the waves of the workgroup in turn. seg(i) gives
+// segment i's (species, brick slot, stream range, local cell search range).
+struct Seg {
+  int s, k;
+  int64_t j0, j1;
+  int lo, hi;
+};
+
+// ---- one brick per workgroup (any shape; R = B r nodes per side) ----
+// With STAGE the brick's force nodes [b R, b R + R]^3 are copied to LDS first and every
+// particle gathers its 8 CIC nodes from there.
 template <int RS>  // staged tile side in nodes (compile time), or 0: gather from HBM
 __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* err) {
   constexpr bool STAGE = RS > 0;
-  const int B = g.B, B3 = B * B * B;
+  const int B = g.B, B3 = B * B * B, L = B3 + 1;
   constexpr int R1 = RS + 1;
-  const int r = g.r;
   extern __shared__ unsigned char smem[];
-  float* F = (float*)smem;                                     // [3][R1^3] when STAGE
+  float* F = (float*)smem;  // [3][R1^3] when STAGE
   const int fsz = STAGE ? 3 * R1 * R1 * R1 : 0;
-  int64_t* loffs = (int64_t*)(smem + ((fsz * 4 + 7) / 8) * 8);  // [MAXSP][B3 + 1]
-  uint32_t* run = (uint32_t*)(loffs + MAXSP * (B3 + 1));       // [B3 + 1] (B3 = movers)
-  uint32_t* wcnt = run + (B3 + 1);  // [2][KB/64][B3 + 1], then rel [B3 + 1]
-  constexpr int NW = KB / 64;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+  uint32_t* rel = (uint32_t*)(smem + fsz * 4);  // [MAXSP][L]
+  uint32_t* run = rel + MAXSP * L;              // [MAXSP][L]
+  __shared__ int64_t l0s[MAXSP];
+  __shared__ uint32_t mvc[MAXSP];
+  __shared__ int smm[2 * MAXSP];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b = xcd_tile(blockIdx.x, g.nbrick);
   const uint32_t kbase = (uint32_t)(b * B3);
   const int64_t ng = g.ng, n3 = ng * ng * ng;
-  uint32_t bcx, bcy, bcz;  // first cell of the brick
-  key_cell(g, kbase, bcx, bcy, bcz);
-  const int64_t ox = (int64_t)bcx * r, oy = (int64_t)bcy * r, oz = (int64_t)bcz * r;
+  uint32_t bc[3];
+  key_cell(g, kbase, bc[0], bc[1], bc[2]);
+  const int64_t ox = (int64_t)bc[0] * g.r, oy = (int64_t)bc[1] * g.r, oz = (int64_t)bc[2] * g.r;
   const int n_sp = A.n_sp;
-
-  // ---- round 1: cell offsets of every species, velocity headers, force tile
-  const int NL = n_sp * (B3 + 1);
-  int64_t lof[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int i = threadIdx.x + k * KB;
-    if (i < NL) {
-      const int s = i / (B3 + 1);
-      lof[k] = A.sp[s].off[kbase + (i - s * (B3 + 1))];
-    }
+  for (int i = threadIdx.x; i < n_sp * L; i += KB) {
+    const int s = i / L, l = i - s * L;
+    const int64_t v0 = A.sp[s].off[kbase];
+    rel[i] = (uint32_t)(A.sp[s].off[kbase + l] - v0);
+    run[i] = 0;
+    if (l == 0) l0s[s] = v0;
   }
-  for (int i = threadIdx.x + 2 * KB; i < NL; i += KB) {  // more than 2 KB entries
-    const int s = i / (B3 + 1);
-    loffs[i] = A.sp[s].off[kbase + (i - s * (B3 + 1))];
-  }
-  float vin[MAXSP], vout[MAXSP];
-#pragma unroll
-  for (int s = 0; s < MAXSP; ++s) {
-    vin[s] = s < n_sp ? A.sp[s].hin->v_max : 0.f;
-    vout[s] = s < n_sp ? A.sp[s].hout->v_max : 0.f;
-  }
+  if (threadIdx.x < MAXSP) mvc[threadIdx.x] = 0;
+  if (threadIdx.x < 2 * MAXSP) smm[threadIdx.x] = (threadIdx.x & 1) ? -1 : 65536;
   if constexpr (STAGE) {
     // rows of RS nodes (x) as float4 loads, then the x = RS halo column; node (lz, ly)
-    // of component c is row (c R1 + lz) R1 + ly. Indexes past the end are clamped to
-    // the last element (a duplicate load, not stored), so no load sits behind a branch.
+    // of component c is row (c R1 + lz) R1 + ly. Rows past the end repeat the last row
+    // (a duplicate load, not stored), so no load sits behind a branch.
     static_assert(RS % 4 == 0, "staged tile side must be a multiple of 4");
+    constexpr int Q = RS / 4;
     constexpr int ROWS = 3 * R1 * R1;
-    constexpr int Q = RS / 4;  // float4 per row
     constexpr int NQ = ROWS * Q;
-    constexpr int PQ = (NQ + KB - 1) / KB;    // float4 loads per thread
-    constexpr int PH = (ROWS + KB - 1) / KB;  // halo loads per thread
-    const int64_t m = ng - 1;                 // ng is a power of two
-    const int64_t hx = (ox + RS) & m;
-    float4 vq[PQ];
-    float vh[PH];
-    // row index (c R1 + lz) R1 + ly advanced by KB / Q rows per load without divisions
+    constexpr int PQ = (NQ + KB - 1) / KB;
+    constexpr int PH = (ROWS + KB - 1) / KB;
     constexpr int RR = R1 * R1;
     constexpr int DR = KB / Q;
     constexpr int DC = DR / RR, DLZ = (DR % RR) / R1, DLY = DR % R1;
     static_assert(KB % Q == 0, "a workgroup covers whole rows");
+    const uint32_t mu = (uint32_t)(ng - 1), ngu = (uint32_t)ng;
+    const uint32_t oxq = (uint32_t)ox + 4 * (threadIdx.x % Q);
+    const uint32_t hx = ((uint32_t)ox + RS) & mu;
     const float* pc0 = A.acc;
     const float* pc1 = A.acc + n3;
     const float* pc2 = A.acc + 2 * n3;
-    const uint32_t mu = (uint32_t)m, ngu = (uint32_t)ng;
-    const uint32_t oxq = (uint32_t)ox + 4 * (threadIdx.x % Q);
     const int row0 = threadIdx.x / Q;
+    float4 vq[PQ];
+    float vh[PH];
     {
       int c = row0 / RR, lz = (row0 % RR) / R1, ly = row0 % R1;
 #pragma unroll
       for (int k = 0; k < PQ; ++k) {
-        const bool over = c >= 3;  // past the end: load the last row again (not stored)
+        const bool over = c >= 3;
         const int cc = over ? 2 : c, zz = over ? R1 - 1 : lz, yy = over ? R1 - 1 : ly;
         const float* pc = cc == 0 ? pc0 : (cc == 1 ? pc1 : pc2);
         const uint32_t gz = ((uint32_t)oz + zz) & mu, gy = ((uint32_t)oy + yy) & mu;
@@ -213,14 +315,8 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
         ly += DLY;
         lz += DLZ;
         c += DC;
-        if (ly >= R1) {
-          ly -= R1;
-          ++lz;
-        }
-        if (lz >= R1) {
-          lz -= R1;
-          ++c;
-        }
+        if (ly >= R1) { ly -= R1; ++lz; }
+        if (lz >= R1) { lz -= R1; ++c; }
       }
     }
 #pragma unroll
@@ -230,7 +326,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       const int lz = rem / R1, ly = rem - lz * R1;
       const float* pc = c == 0 ? pc0 : (c == 1 ? pc1 : pc2);
       const uint32_t gz = ((uint32_t)oz + lz) & mu, gy = ((uint32_t)oy + ly) & mu;
-      vh[k] = pc[(uint64_t)(gz * ngu + gy) * ngu + (uint32_t)hx];
+      vh[k] = pc[(uint64_t)(gz * ngu + gy) * ngu + hx];
     }
     {
       int c = row0 / RR, lz = (row0 % RR) / R1, ly = row0 % R1;
@@ -247,14 +343,8 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
         ly += DLY;
         lz += DLZ;
         c += DC;
-        if (ly >= R1) {
-          ly -= R1;
-          ++lz;
-        }
-        if (lz >= R1) {
-          lz -= R1;
-          ++c;
-        }
+        if (ly >= R1) { ly -= R1; ++lz; }
+        if (lz >= R1) { lz -= R1; ++c; }
       }
     }
 #pragma unroll
@@ -263,232 +353,282 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       if (row < ROWS) F[row * R1 + RS] = vh[k];
     }
   }
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int i = threadIdx.x + k * KB;
-    if (i < NL) loffs[i] = lof[k];
-  }
   __syncthreads();
 
-  // ---- round 2: codes of the first chunk of every species
-  uint32_t pre_pb[MAXSP][3], pre_vc[MAXSP][3];
+  auto gather = [&](const int li[3], const float f[3], float acc3[3]) {
+    acc3[0] = acc3[1] = acc3[2] = 0.f;
 #pragma unroll
-  for (int s = 0; s < MAXSP; ++s) {
-    const int64_t* lo = loffs + s * (B3 + 1);
-    const bool have = s < n_sp;
-    const int64_t n = have ? A.sp[s].n : 0;
-    const int64_t j0 = have ? min(lo[0], n) : 0, j1 = have ? min(lo[B3], n) : 0;
-    const int64_t j = j0 + threadIdx.x;
-    const int64_t jj = j < j1 ? j : 0;
+    for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      pre_pb[s][a] = j < j1 ? A.sp[s].pos[3 * jj + a] : 0u;
-      pre_vc[s][a] = j < j1 ? A.sp[s].vel[3 * jj + a] : 0u;
-    }
-  }
-
-  const int nbits = 3 * g.lgB + 1;  // local cell bits + mover flag
-  const uint32_t mB = (uint32_t)B - 1;
-  const uint32_t bc[3] = {bcx, bcy, bcz};
-  const uint32_t Sm = (uint32_t)g.S - 1;
-  const double Sd = (double)g.S, invS = 1.0 / Sd;  // powers of two
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
+                            (dz ? f[2] : 1.f - f[2]);
+          if constexpr (STAGE) {
+            const int node = ((li[2] + dz) * R1 + (li[1] + dy)) * R1 + (li[0] + dx);
+            acc3[0] += wgt * F[node];
+            acc3[1] += wgt * F[R1 * R1 * R1 + node];
+            acc3[2] += wgt * F[2 * R1 * R1 * R1 + node];
+          } else {
+            const int64_t m = ng - 1;
+            const int64_t nz = (oz + li[2] + dz) & m, ny = (oy + li[1] + dy) & m,
+                          nx = (ox + li[0] + dx) & m;
+            const int64_t node = (nz * ng + ny) * ng + nx;
+            acc3[0] += wgt * A.acc[node];
+            acc3[1] += wgt * A.acc[n3 + node];
+            acc3[2] += wgt * A.acc[2 * n3 + node];
+          }
+        }
+  };
   bool bad = false;
-  __shared__ int mm[2 * NW];  // per-wave extreme velocity codes
-  // Rounds of KB particles in stream order. Per round: (1) new codes and digits, stable
-  // multi-split inside each wave, per-wave digit counts into wcnt[round & 1]; barrier;
-  // (2) rank = running count + counts of earlier waves + rank in the wave, outputs,
-  // and the other count buffer cleared for the next round; barrier; (3) running counts
-  // advanced (overlaps the next round's step 1, which uses the other buffer).
-  const int WS = NW * (B3 + 1);
-  uint32_t* rel = wcnt + 2 * WS;  // [B3 + 1]: cell offsets relative to the brick's first
-#pragma unroll
-  for (int s = 0; s < MAXSP; ++s) {
-    if (s >= n_sp) break;
-    const KickSpecies& S = A.sp[s];
-    const int64_t* loff = loffs + s * (B3 + 1);
-    __syncthreads();  // previous species done with run, rel and wcnt
-    const int64_t l0 = loff[0];
-    for (int i = threadIdx.x; i <= B3; i += KB) {
-      run[i] = 0;
-      rel[i] = (uint32_t)(loff[i] - l0);
+  auto run_all = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    int64_t cbase = 0;  // chunks of the earlier species
+    for (int s = 0; s < n_sp; ++s) {
+      const KickSpecies& S = A.sp[s];
+      const int64_t l0 = l0s[s];
+      const int64_t j0 = min(l0, S.n), j1 = min(l0 + (int64_t)rel[s * L + B3], S.n);
+      const int64_t nch = j1 > j0 ? (j1 - j0 + 63) >> 6 : 0;
+      const Codec cd = codec_of(S);
+      // this wave's chunks of species s: global chunk index = cbase + c, dealt round-robin
+      int64_t c = ((int64_t)w - cbase) % NWK;
+      if (c < 0) c += NWK;
+      for (; c < nch; c += NWK)
+        kick_chunk<FAST>(S, A, g, cd, j0 + 64 * c, j1, l0, rel + s * L, 0, B3, bc,
+                         run + s * L, &mvc[s], &smm[2 * s], bad, gather);
+      cbase += nch;
     }
-    for (int i = threadIdx.x; i < 2 * WS; i += KB) wcnt[i] = 0;
-    __syncthreads();
-    const int64_t j0 = min(l0, S.n), j1 = min(loff[B3], S.n);
-    // float32 forms of the velocity codec where they give the same codes (uniform)
-    const float vmax_in = vin[s];
-    const float vmax_out = vout[s];
-    const bool fdec = vmax_in >= 0x1p-90f && vmax_in <= 0x1p90f;
-    const uint32_t ob = __float_as_uint(vmax_out);
-    const bool fenc = vmax_out >= 0x1p-90f && vmax_out <= 0x1p90f && (ob & 0x7fffffu) == 0;
-    const float wdec = vmax_in * 0x1p-15f;
-    const float cenc = __uint_as_float((269u - (ob >> 23)) << 23);  // 2^15 / v_max
-    int jmin = 65536, jmax = -1;
-    // the round loop, compiled once with the float32 codec forms and once without
-    auto rounds = [&](auto fast) {
-      constexpr bool FAST = decltype(fast)::value;
-      int rnd = 0;
-      for (int64_t base = j0; base < j1; base += KB, ++rnd) {
-        uint32_t* wc = wcnt + (rnd & 1) * WS;
-        uint32_t* wo = wcnt + ((rnd & 1) ^ 1) * WS;
-        const int64_t j = base + threadIdx.x;
-        const bool valid = j < j1;
-        const uint32_t t3 = 3 * threadIdx.x;
-        uint32_t digit = 0, un[3] = {0, 0, 0};
-        if (valid) {
-          // the particle's codes: prefetched for the first round
-          uint32_t pb[3], vc[3];
-          if (base == j0) {
-  #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              pb[a] = pre_pb[s][a];
-              vc[a] = pre_vc[s][a];
-            }
-          } else {
-            const uint8_t* pp = S.pos + 3 * base;
-            const uint16_t* vp = S.vel + 3 * base;
-  #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              pb[a] = pp[t3 + a];
-              vc[a] = vp[t3 + a];
-            }
-          }
-          const uint32_t jr = (uint32_t)(base - l0) + threadIdx.x;
-          int lo = 0, hi = B3;  // local cell: largest l with rel[l] <= jr
-          while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (rel[mid] <= jr) lo = mid; else hi = mid;
-          }
-          const uint32_t lc[3] = {(uint32_t)lo & mB, ((uint32_t)lo >> g.lgB) & mB,
-                                  (uint32_t)lo >> (2 * g.lgB)};
-          int li[3];
-          float f[3];
-  #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            // position in 1/512 mesh cells from the brick's corner node: (2 u + 1) r
-            const uint32_t gl = (2 * ((lc[a] << 8) | pb[a]) + 1) * (uint32_t)r;
-            li[a] = (int)(gl >> 9);
-            f[a] = (float)(gl & 511u) * (1.0f / 512.0f);
-          }
-          float acc3[3] = {0.f, 0.f, 0.f};
-  #pragma unroll
-          for (int dz = 0; dz < 2; ++dz)
-  #pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-  #pragma unroll
-              for (int dx = 0; dx < 2; ++dx) {
-                const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
-                                  (dz ? f[2] : 1.f - f[2]);
-                if constexpr (STAGE) {
-                  const int node = ((li[2] + dz) * R1 + (li[1] + dy)) * R1 + (li[0] + dx);
-                  acc3[0] += wgt * F[node];
-                  acc3[1] += wgt * F[R1 * R1 * R1 + node];
-                  acc3[2] += wgt * F[2 * R1 * R1 * R1 + node];
-                } else {
-                  const int64_t m = ng - 1;
-                  const int64_t nz = (oz + li[2] + dz) & m, ny = (oy + li[1] + dy) & m,
-                                nx = (ox + li[0] + dx) & m;
-                  const int64_t node = (nz * ng + ny) * ng + nx;
-                  acc3[0] += wgt * A.acc[node];
-                  acc3[1] += wgt * A.acc[n3 + node];
-                  acc3[2] += wgt * A.acc[2 * n3 + node];
-                }
-              }
-          uint8_t* tp = S.tpos + 3 * base;
-          uint16_t* tv = S.tvel + 3 * base;
-          uint32_t nl[3];
-  #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const float v0 = FAST ? vel_decode_w(vc[a], wdec) : vel_decode(vc[a], vmax_in);
-            const float v1 = v0 + A.ck * acc3[a];
-            const double d = floor((double)v1 * A.cdS + 0.5);
-            const bool okd = fabs(d) < 4.0e15;
-            bad |= !okd;
-            // d mod S, exact in float64 (d is an integer below 2^52, S a power of two)
-            const double dm = okd ? d - Sd * floor(d * invS) : 0.0;
-            un[a] = ((((bc[a] + lc[a]) << 8) | pb[a]) + (uint32_t)dm) & Sm;
-            nl[a] = (un[a] >> 8) - bc[a];  // new local cell (wraps above B when outside)
-            const int jc = FAST ? vel_code_p2(v1, cenc) : vel_code(v1, vmax_out);
-            tp[t3 + a] = (uint8_t)(un[a] & 255u);
-            tv[t3 + a] = (uint16_t)jc;
-            jmin = min(jmin, jc);
-            jmax = max(jmax, jc);
-          }
-          digit = (nl[0] <= mB && nl[1] <= mB && nl[2] <= mB)
-                      ? (((nl[2] << g.lgB) | nl[1]) << g.lgB) | nl[0]
-                      : (uint32_t)B3;
-        }
-        // stable multi-split of this round by digit (new local cell, or B3 for movers)
-        uint64_t match = __ballot(valid);
-        for (int bit = 0; bit < nbits; ++bit) {
-          uint64_t mbit = __ballot(valid && ((digit >> bit) & 1u));
-          match &= ((digit >> bit) & 1u) ? mbit : ~mbit;
-        }
-        const uint32_t rk = (uint32_t)__popcll(match & lt);
-        if (valid && rk == 0) wc[w * (B3 + 1) + digit] = (uint32_t)__popcll(match);
-        __syncthreads();
-        if (valid) {
-          uint32_t pre = run[digit];
-          for (int q = 0; q < w; ++q) pre += wc[q * (B3 + 1) + digit];
-          const uint32_t rank = pre + rk;
-          if (digit < (uint32_t)B3) {
-            if (rank >= RANK_LIMIT) bad = true;
-            S.tdst[j] = (digit << RANK_BITS) | (rank & RANK_LIMIT);
-          } else {
-            S.tdst[j] = MOVER;
-            S.mkey[j0 + rank] = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
-            S.midx[j0 + rank] = (uint32_t)j;
-          }
-        }
-        for (int i = threadIdx.x; i < WS; i += KB) wo[i] = 0;
-        __syncthreads();
-        for (int i = threadIdx.x; i <= B3; i += KB) {
-          uint32_t add = 0;
-          for (int q = 0; q < NW; ++q) add += wc[q * (B3 + 1) + i];
-          run[i] += add;
-        }
-      }
-    };
-    if (fdec && fenc) rounds(std::true_type{});
-    else rounds(std::false_type{});
-    // the thread that advanced run[i] writes it out
-    for (int i = threadIdx.x; i <= B3; i += KB) {
-      if (i < B3) S.cnt[kbase + i] = (uint64_t)run[i];
-      else S.mcnt[b] = run[B3];
-    }
-    // block min / max of the new velocity codes, stored per brick (no atomics)
-    for (int d = 32; d >= 1; d >>= 1) {
-      jmin = min(jmin, __shfl_xor(jmin, d, 64));
-      jmax = max(jmax, __shfl_xor(jmax, d, 64));
-    }
-    if (lane == 0) {
-      mm[2 * w] = jmin;
-      mm[2 * w + 1] = jmax;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int q = 1; q < NW; ++q) {
-        jmin = min(jmin, mm[2 * q]);
-        jmax = max(jmax, mm[2 * q + 1]);
-      }
-      S.pmn[b] = jmin;
-      S.pmx[b] = jmax;
-    }
+  };
+  if (codec_fast(A)) run_all(std::true_type{});
+  else run_all(std::false_type{});
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_sp * L; i += KB) {
+    const int s = i / L, l = i - s * L;
+    if (l < B3) A.sp[s].cnt[kbase + l] = (uint64_t)run[i];
+  }
+  if (threadIdx.x < n_sp) {
+    const int s = threadIdx.x;
+    A.sp[s].mcnt[b] = mvc[s];
+    A.sp[s].pmn[b] = smm[2 * s];
+    A.sp[s].pmx[b] = smm[2 * s + 1];
   }
   if (bad) latch_error(err, ERRBIT_RANGE);
 }
 
-// movers of brick b sit at [off[b B^3], off[b B^3] + mcnt[b]); gather them in old order
+// ---- two bricks adjacent along x per workgroup, R = 16, in two z-half passes ----
+// Pass h stages the force nodes x in [x0, x0 + 2R], y in [y0, y0 + R], z in
+// [z0 + h R/2, z0 + (h + 1) R/2] (33 x 17 x 9 nodes) and kicks the particles of both
+// bricks' cells in that z half. Rows of the staged tile are 2R nodes long, which the
+// memory system serves much faster than rows of R.
+constexpr int PR = 16;
+__global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
+  constexpr int X1 = 2 * PR + 1, Y1 = PR + 1, Z1 = PR / 2 + 1;
+  constexpr int TS = X1 * Y1 * Z1;  // nodes per component
+  const int B = g.B, B3 = B * B * B, L = B3 + 1, H = B3 / 2;  // H: cells per z half
+  extern __shared__ unsigned char smem[];
+  float* F = (float*)smem;                          // [3][Z1][Y1][X1]
+  uint32_t* rel = (uint32_t*)(smem + 3 * TS * 4);   // [2][MAXSP][L]
+  uint32_t* run = rel + 2 * MAXSP * L;              // [2][MAXSP][L]
+  __shared__ int64_t l0s[2 * MAXSP];
+  __shared__ uint32_t mvc[2 * MAXSP];
+  __shared__ int smm[2 * MAXSP];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t p = xcd_tile(blockIdx.x, g.nbrick / 2);
+  const int64_t b0 = 2 * p;  // bricks b0, b0 + 1 (x index even, same row)
+  const uint32_t kb0 = (uint32_t)(b0 * B3);
+  const int64_t ng = g.ng, n3 = ng * ng * ng;
+  uint32_t bc0[3];
+  key_cell(g, kb0, bc0[0], bc0[1], bc0[2]);
+  const int64_t ox = (int64_t)bc0[0] * g.r, oy = (int64_t)bc0[1] * g.r,
+                oz = (int64_t)bc0[2] * g.r;
+  const int n_sp = A.n_sp;
+  for (int i = threadIdx.x; i < 2 * MAXSP * L; i += KB) {
+    const int k = i / (MAXSP * L), rem = i - k * (MAXSP * L);
+    const int s = rem / L, l = rem - s * L;
+    uint32_t v = 0;
+    if (s < n_sp) {
+      const int64_t v0 = A.sp[s].off[kb0 + k * B3];
+      v = (uint32_t)(A.sp[s].off[kb0 + k * B3 + l] - v0);
+      if (l == 0) l0s[k * MAXSP + s] = v0;
+    }
+    rel[i] = v;
+    run[i] = 0;
+  }
+  if (threadIdx.x < 2 * MAXSP) {
+    mvc[threadIdx.x] = 0;
+    smm[threadIdx.x] = (threadIdx.x & 1) ? -1 : 65536;
+  }
+  const bool fast = codec_fast(A);
+  bool bad = false;
+
+  auto stage = [&](int h) {
+    constexpr int Q = 2 * PR / 4;
+    constexpr int ROWS = 3 * Z1 * Y1;
+    constexpr int NQ = ROWS * Q;
+    constexpr int PQ = (NQ + KB - 1) / KB;
+    constexpr int PH = (ROWS + KB - 1) / KB;
+    constexpr int RR = Z1 * Y1;
+    constexpr int DR = KB / Q;
+    constexpr int DC = DR / RR, DLZ = (DR % RR) / Y1, DLY = DR % Y1;
+    static_assert(KB % Q == 0, "a workgroup covers whole rows");
+    const uint32_t mu = (uint32_t)(ng - 1), ngu = (uint32_t)ng;
+    const uint32_t oz2 = (uint32_t)oz + h * (PR / 2);
+    const uint32_t oxq = (uint32_t)ox + 4 * (threadIdx.x % Q);
+    const uint32_t hx = ((uint32_t)ox + 2 * PR) & mu;
+    const float* pc0 = A.acc;
+    const float* pc1 = A.acc + n3;
+    const float* pc2 = A.acc + 2 * n3;
+    const int row0 = threadIdx.x / Q;
+    float4 vq[PQ];
+    float vh[PH];
+    {
+      int c = row0 / RR, lz = (row0 % RR) / Y1, ly = row0 % Y1;
+#pragma unroll
+      for (int k = 0; k < PQ; ++k) {
+        const bool over = c >= 3;
+        const int cc = over ? 2 : c, zz = over ? Z1 - 1 : lz, yy = over ? Y1 - 1 : ly;
+        const float* pc = cc == 0 ? pc0 : (cc == 1 ? pc1 : pc2);
+        const uint32_t gz = (oz2 + zz) & mu, gy = ((uint32_t)oy + yy) & mu;
+        vq[k] = *(const float4*)(pc + ((uint64_t)(gz * ngu + gy) * ngu + oxq));
+        ly += DLY;
+        lz += DLZ;
+        c += DC;
+        if (ly >= Y1) { ly -= Y1; ++lz; }
+        if (lz >= Z1) { lz -= Z1; ++c; }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PH; ++k) {
+      const int row = min((int)threadIdx.x + k * KB, ROWS - 1);
+      const int c = row / RR, rem = row - c * RR;
+      const int lz = rem / Y1, ly = rem - lz * Y1;
+      const float* pc = c == 0 ? pc0 : (c == 1 ? pc1 : pc2);
+      const uint32_t gz = (oz2 + lz) & mu, gy = ((uint32_t)oy + ly) & mu;
+      vh[k] = pc[(uint64_t)(gz * ngu + gy) * ngu + hx];
+    }
+    __syncthreads();  // the previous pass is done with F
+    {
+      int c = row0 / RR, lz = (row0 % RR) / Y1, ly = row0 % Y1;
+      const int q4 = 4 * (threadIdx.x % Q);
+#pragma unroll
+      for (int k = 0; k < PQ; ++k) {
+        if (c < 3) {
+          float* d = F + ((c * Z1 + lz) * Y1 + ly) * X1 + q4;
+          d[0] = vq[k].x;
+          d[1] = vq[k].y;
+          d[2] = vq[k].z;
+          d[3] = vq[k].w;
+        }
+        ly += DLY;
+        lz += DLZ;
+        c += DC;
+        if (ly >= Y1) { ly -= Y1; ++lz; }
+        if (lz >= Z1) { lz -= Z1; ++c; }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PH; ++k) {
+      const int row = threadIdx.x + k * KB;
+      if (row < ROWS) F[row * X1 + 2 * PR] = vh[k];
+    }
+    __syncthreads();
+  };
+
+  auto pass = [&](auto fast_tag, int h) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    int64_t cbase = 0;  // chunks of the earlier segments of this pass
+    for (int k = 0; k < 2; ++k) {
+      uint32_t bc[3];
+      key_cell(g, kb0 + (uint32_t)(k * B3), bc[0], bc[1], bc[2]);
+      auto gather = [&](const int li[3], const float f[3], float acc3[3]) {
+        const int tx = li[0] + k * PR, ty = li[1], tz = li[2] - h * (PR / 2);
+        acc3[0] = acc3[1] = acc3[2] = 0.f;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+              const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
+                                (dz ? f[2] : 1.f - f[2]);
+              const int node = ((tz + dz) * Y1 + (ty + dy)) * X1 + (tx + dx);
+              acc3[0] += wgt * F[node];
+              acc3[1] += wgt * F[TS + node];
+              acc3[2] += wgt * F[2 * TS + node];
+            }
+      };
+      for (int s = 0; s < n_sp; ++s) {
+        const KickSpecies& S = A.sp[s];
+        const uint32_t* rs = rel + (k * MAXSP + s) * L;
+        const int64_t l0 = l0s[k * MAXSP + s];
+        const int64_t j0 = min(l0 + (int64_t)rs[h * H], S.n);
+        const int64_t j1 = min(l0 + (int64_t)rs[(h + 1) * H], S.n);
+        const int64_t nch = j1 > j0 ? (j1 - j0 + 63) >> 6 : 0;
+        const Codec cd = codec_of(S);
+        int64_t c = ((int64_t)w - cbase) % NWK;
+        if (c < 0) c += NWK;
+        for (; c < nch; c += NWK)
+          kick_chunk<FAST>(S, A, g, cd, j0 + 64 * c, j1, l0, rs, h * H, (h + 1) * H, bc,
+                           run + (k * MAXSP + s) * L, &mvc[k * MAXSP + s], &smm[2 * s], bad,
+                           gather);
+        cbase += nch;
+      }
+    }
+  };
+  for (int h = 0; h < 2; ++h) {
+    stage(h);
+    if (fast) pass(std::true_type{}, h);
+    else pass(std::false_type{}, h);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * MAXSP * L; i += KB) {
+    const int k = i / (MAXSP * L), rem = i - k * (MAXSP * L);
+    const int s = rem / L, l = rem - s * L;
+    if (s < n_sp && l < B3) A.sp[s].cnt[kb0 + k * B3 + l] = (uint64_t)run[i];
+  }
+  if (threadIdx.x < 2 * n_sp) {
+    const int k = threadIdx.x / n_sp, s = threadIdx.x - k * n_sp;
+    A.sp[s].mcnt[b0 + k] = mvc[k * MAXSP + s];
+    A.sp[s].pmn[b0 + k] = smm[2 * s];
+    A.sp[s].pmx[b0 + k] = smm[2 * s + 1];
+  }
+  if (bad) latch_error(err, ERRBIT_RANGE);
+}
+
+// Movers of brick b, in old stream order, to [moff[b], moff[b] + mcnt[b]): a block scan
+// over the brick's digits.
 __global__ __launch_bounds__(KT) void k_compact_movers(const int64_t* off, const uint32_t* mcnt,
-                                                      const int64_t* moff, int B3,
-                                                      const uint32_t* mkey, const uint32_t* midx,
-                                                      uint32_t* okey, uint32_t* oidx) {
+                                                      const int64_t* moff, int B3, int64_t n,
+                                                      const uint16_t* tdig,
+                                                      const uint32_t* mkey, uint32_t* okey,
+                                                      uint32_t* oidx) {
+  constexpr int NW = KT / 64;
+  __shared__ uint32_t wsum[NW];
   const int64_t b = blockIdx.x;
-  const int64_t src = off[b * B3], dst = moff[b];
-  const uint32_t m = mcnt[b];
-  for (uint32_t i = threadIdx.x; i < m; i += KT) {
-    okey[dst + i] = mkey[src + i];
-    oidx[dst + i] = midx[src + i];
+  if (mcnt[b] == 0) return;
+  const int64_t j0 = min(off[b * B3], n), j1 = min(off[b * B3 + B3], n);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+  int64_t dst = moff[b];
+  for (int64_t base = j0; base < j1; base += KT) {
+    const int64_t j = base + threadIdx.x;
+    const bool m = j < j1 && tdig[j] == (uint16_t)B3;
+    const uint64_t bal = __ballot(m);
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int q = 0; q < NW; ++q) {
+      pre += q < w ? wsum[q] : 0u;
+      tot += wsum[q];
+    }
+    if (m) {
+      const int64_t o = dst + pre + (uint32_t)__popcll(bal & lt);
+      okey[o] = mkey[j];
+      oidx[o] = (uint32_t)j;
+    }
+    dst += tot;
+    __syncthreads();
   }
 }
 
@@ -515,52 +655,77 @@ __global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uin
   atomicAdd((unsigned long long*)&cnt[k], (unsigned long long)(((uint64_t)nb << 32) | (uint64_t)(ge - s)));
 }
 
-// One workgroup per brick. The first stream position of the brick's stayers in each
-// new cell (cell offset + arrivals from earlier bricks) is staged in LDS, so a stayer
-// needs its own coalesced loads only; each thread takes U particles per pass with all
-// their loads issued before any store.
-__global__ __launch_bounds__(KT) void k_place_stayers(const int64_t* off_in, const uint32_t* tdst,
+// One workgroup per brick: stayers to their final stream positions. The first position
+// of the brick's stayers in each new cell (cell offset + arrivals from earlier bricks)
+// is staged in LDS; the rank of a stayer among the brick's stayers of its new cell, in
+// old stream order, comes from a stable multi-split of each round by digit (ballots per
+// wave, per-wave digit counts, running counts per cell).
+__global__ __launch_bounds__(KT) void k_place_stayers(const int64_t* off_in, const uint16_t* tdig,
                                                      const uint8_t* tpos, const uint16_t* tvel,
                                                      const uint64_t* cnt, const int64_t* off_new,
-                                                     int B3, uint8_t* pos, uint16_t* vel,
-                                                     int64_t* perm, int64_t n, DevErr* err) {
-  extern __shared__ int64_t dbase[];  // [B3]
-  constexpr int U = 2;
+                                                     int B3, int nbits, uint8_t* pos,
+                                                     uint16_t* vel, int64_t* perm, int64_t n,
+                                                     DevErr* err) {
+  constexpr int NW = KT / 64;
+  extern __shared__ int64_t dbase[];  // [B3], then run [B3] and wc [NW][B3] (uint32)
+  uint32_t* run = (uint32_t*)(dbase + B3);
+  uint32_t* wc = run + B3;
   const int64_t b = blockIdx.x;
   const int64_t kbase = b * B3;
-  for (int l = threadIdx.x; l < B3; l += KT)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+  for (int l = threadIdx.x; l < B3; l += KT) {
     dbase[l] = off_new[kbase + l] + (int64_t)(cnt[kbase + l] >> 32);
+    run[l] = 0;
+  }
+  for (int i = threadIdx.x; i < NW * B3; i += KT) wc[i] = 0;
   const int64_t j0 = min(off_in[kbase], n), j1 = min(off_in[kbase + B3], n);
   __syncthreads();
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += U * KT) {
-    uint32_t d[U], p[U][3], v[U][3];
+  for (int64_t base = j0; base < j1; base += KT) {
+    const int64_t j = base + threadIdx.x;
+    const bool valid = j < j1;
+    const int64_t jj = valid ? j : j0;
+    const uint32_t d = tdig[jj];
+    uint32_t p[3], v[3];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t ju = j + u * KT;
-      const bool h = ju < j1;
-      const int64_t jj = h ? ju : j;
-      d[u] = h ? tdst[jj] : MOVER;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        p[u][a] = tpos[3 * jj + a];
-        v[u][a] = tvel[3 * jj + a];
-      }
+    for (int a = 0; a < 3; ++a) {
+      p[a] = tpos[3 * jj + a];
+      v[a] = tvel[3 * jj + a];
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (d[u] == MOVER) continue;
-      const int64_t dst = dbase[d[u] >> RANK_BITS] + (int64_t)(d[u] & RANK_LIMIT);
+    const bool stay = valid && d < (uint32_t)B3;
+    uint64_t match = __ballot(stay);
+    for (int bit = 0; bit < nbits; ++bit) {
+      const uint64_t mbit = __ballot(stay && ((d >> bit) & 1u));
+      match &= ((d >> bit) & 1u) ? mbit : ~mbit;
+    }
+    const uint32_t rk = (uint32_t)__popcll(match & lt);
+    if (stay && rk == 0) wc[w * B3 + d] = (uint32_t)__popcll(match);
+    __syncthreads();
+    if (stay) {
+      uint32_t rank = run[d] + rk;
+      for (int q = 0; q < w; ++q) rank += wc[q * B3 + d];
+      const int64_t dst = dbase[d] + (int64_t)rank;
       if (dst < 0 || dst >= n) {
         latch_error(err, ERRBIT_CORRUPT);
-        continue;
-      }
+      } else {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        pos[3 * dst + a] = (uint8_t)p[u][a];
-        vel[3 * dst + a] = (uint16_t)v[u][a];
+        for (int a = 0; a < 3; ++a) {
+          pos[3 * dst + a] = (uint8_t)p[a];
+          vel[3 * dst + a] = (uint16_t)v[a];
+        }
+        if (perm) perm[dst] = j;
       }
-      if (perm) perm[dst] = j + u * KT;
     }
+    __syncthreads();
+    for (int l = threadIdx.x; l < B3; l += KT) {
+      uint32_t add = 0;
+      for (int q = 0; q < NW; ++q) {
+        add += wc[q * B3 + l];
+        wc[q * B3 + l] = 0;
+      }
+      run[l] += add;
+    }
+    __syncthreads();
   }
 }
 
@@ -629,7 +794,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
   int64_t* off_new = (int64_t*)scratch(c, SC_OFF2, (size_t)(g.ncell3 + 1) * 8);
   uint8_t* tpos = (uint8_t*)scratch(c, SC_TPOS, nn * 3);
   uint16_t* tvel = (uint16_t*)scratch(c, SC_TVEL, nn * 6);
-  uint32_t* tdst = (uint32_t*)scratch(c, SC_TDST, nn * 4);
+  uint16_t* tdig = (uint16_t*)scratch(c, SC_TDST, nn * 2);
   uint32_t* mkey = (uint32_t*)scratch(c, SC_KEYA, nn * 4);
   uint32_t* midx = (uint32_t*)scratch(c, SC_VALA, nn * 4);
   uint32_t* skey = (uint32_t*)scratch(c, SC_KEYB, nn * 4);
@@ -637,7 +802,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
   uint32_t* mcnt = (uint32_t*)scratch(c, SC_MCNT, (size_t)g.nbrick * 4 * n_sp);
   int64_t* moff = (int64_t*)scratch(c, SC_MOFF, (size_t)(g.nbrick + 1) * 8);
   int32_t* part = (int32_t*)scratch(c, SC_PARTS, (size_t)g.nbrick * 8 * n_sp);
-  if (!cnt || !off_new || !tpos || !tvel || !tdst || !mkey || !midx || !skey || !sidx ||
+  if (!cnt || !off_new || !tpos || !tvel || !tdig || !mkey || !midx || !skey || !sidx ||
       !mcnt || !moff || !part)
     return PM_ERR_NOMEM;
   KickArgs A{};
@@ -655,10 +820,9 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     S.off = offs[s];
     S.tpos = tpos + 3 * nbase[s];
     S.tvel = tvel + 3 * nbase[s];
-    S.tdst = tdst + nbase[s];
+    S.tdig = tdig + nbase[s];
     S.cnt = cnt + (int64_t)s * g.ncell3;
     S.mkey = mkey + nbase[s];
-    S.midx = midx + nbase[s];
     S.mcnt = mcnt + (int64_t)s * g.nbrick;
     S.pmn = part + (int64_t)2 * s * g.nbrick;
     S.pmx = S.pmn + g.nbrick;
@@ -669,17 +833,21 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
       hipLaunchKernelGGL(k_vmax_next, dim3(1), dim3(1), 0, c->stream, in[s].hdr, out[s].hdr,
                          amax, ck, in[s].n);
     ProfScope ps(c, ST_KICK);
-    const int R1 = g.B * g.r + 1;
-    const size_t fbytes = (size_t)3 * R1 * R1 * R1 * 4;
-    const size_t tail =
-        (size_t)MAXSP * (B3 + 1) * 8 + (size_t)(B3 + 1) * 4 * (2 + 2 * (KB / 64));
     const int R = g.B * g.r;
-    if (R == 16 && fbytes + tail <= 96 * 1024)
-      hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB),
-                         ((fbytes + 7) / 8) * 8 + tail, c->stream, A, g, c->err);
+    const size_t tail = (size_t)MAXSP * (B3 + 1) * 4 * 2;
+    // two bricks per workgroup: R = 16, an even number of bricks per side, z halves of
+    // whole cells
+    const size_t pbytes = (size_t)3 * (2 * PR + 1) * (PR + 1) * (PR / 2 + 1) * 4 + 2 * tail;
+    const size_t fbytes = (size_t)3 * (R + 1) * (R + 1) * (R + 1) * 4;
+    if (R == PR && g.lgnb >= 1 && (g.B % 2) == 0 && pbytes <= 72 * 1024)
+      hipLaunchKernelGGL(k_kick_pair, dim3((unsigned)(g.nbrick / 2)), dim3(KB), pbytes,
+                         c->stream, A, g, c->err);
+    else if (R == 16 && fbytes + tail <= 96 * 1024)
+      hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB), fbytes + tail,
+                         c->stream, A, g, c->err);
     else if (R == 8)
-      hipLaunchKernelGGL(k_kick_brick<8>, dim3((unsigned)g.nbrick), dim3(KB),
-                         ((fbytes + 7) / 8) * 8 + tail, c->stream, A, g, c->err);
+      hipLaunchKernelGGL(k_kick_brick<8>, dim3((unsigned)g.nbrick), dim3(KB), fbytes + tail,
+                         c->stream, A, g, c->err);
     else
       hipLaunchKernelGGL(k_kick_brick<0>, dim3((unsigned)g.nbrick), dim3(KB), tail,
                          c->stream, A, g, c->err);
@@ -690,6 +858,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
           PM_OK)
         return st0;
   }
+  const size_t place_lds = (size_t)B3 * 8 + (size_t)B3 * 4 * (1 + KT / 64);
   for (int s = 0; s < n_sp; ++s) {
     const int64_t n = in[s].n;
     const KickSpecies& S = A.sp[s];
@@ -704,10 +873,10 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     uint32_t* si = sidx + nbase[s];
     if (nm > 0) {
       hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
-                         S.off, S.mcnt, moff, B3, S.mkey, S.midx, sk, si);
+                         S.off, S.mcnt, moff, B3, n, S.tdig, S.mkey, sk, si);
       PM_LAUNCH_CHECK();
       // stable sort (old order preserved inside each new cell)
-      uint32_t *k1 = sk, *v1 = si, *k2 = S.mkey, *v2 = S.midx;
+      uint32_t *k1 = sk, *v1 = si, *k2 = S.mkey, *v2 = midx + nbase[s];
       st = radix_sort_pairs(c, &k1, &v1, &k2, &v2, nm, 3 * (g.lgB + g.lgnb));
       if (st != PM_OK) return st;
       sk = k1;
@@ -719,10 +888,9 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
-    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT),
-                       (size_t)B3 * 8, c->stream,
-                       S.off, S.tdst, S.tpos, S.tvel, S.cnt, off_new, B3, out[s].pos,
-                       out[s].vel, pm, n, c->err);
+    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT), place_lds,
+                       c->stream, S.off, S.tdig, S.tpos, S.tvel, S.cnt, off_new, B3,
+                       3 * g.lgB, out[s].pos, out[s].vel, pm, n, c->err);
     PM_LAUNCH_CHECK();
     if (nm > 0) {
       hipLaunchKernelGGL(k_place_movers, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream,
