@@ -48,9 +48,9 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "b6b7297ac02bcd3edc1f70be959274960d090edaaac8c6413b395eac3d0ecb08",
-        "fetch_kib": 8069974.25, "fetch_factor": 1.99988,
-        "write_kib": 2091970.50, "write_factor": 1.0,
+        "sha256": "1b89b563c0ab3d35369e45bf4f580e1c0dc620ee2adac77cd6d06d5fcee9bd65",
+        "fetch_kib": 8071411.69, "fetch_factor": 1.99988,
+        "write_kib": 2091342.19, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
         "kernel": "k_row_c2r<512>",

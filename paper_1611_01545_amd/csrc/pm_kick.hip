@@ -15,14 +15,14 @@
 //                   new cell inside the brick, or B^3 for a particle that leaves it (a
 //                   "mover", whose new cell key is kept). Stayers are counted per new
 //                   cell and movers per brick with LDS atomics.
-//   movers          compacted in old order (block scan over the digits), stably
-//                   radix-sorted by new cell.
+//   movers          compacted in old order (ballots over the digits, one wave per
+//                   brick), stably radix-sorted by new cell.
 //   k_arrivals      per new cell: arrivals, and how many of them come from earlier
 //                   bricks (they precede the cell's stayers in stream order).
 //   scan            new cell offsets.
 //   k_place_*       stayers and movers written at their final stream positions: per
-//                   brick, the stayers' first position in each new cell staged in LDS and
-//                   their stable rank from a multi-split of the digits.
+//                   brick (one wave), the stayers' first position in each new cell staged
+//                   in LDS and their stable rank from a multi-split of the digits.
 #include <type_traits>
 
 #include "pm_codec.h"
@@ -596,42 +596,6 @@ __global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr*
   if (bad) latch_error(err, ERRBIT_RANGE);
 }
 
-// Movers of brick b, in old stream order, to [moff[b], moff[b] + mcnt[b]): a block scan
-// over the brick's digits.
-__global__ __launch_bounds__(KT) void k_compact_movers(const int64_t* off, const uint32_t* mcnt,
-                                                      const int64_t* moff, int B3, int64_t n,
-                                                      const uint16_t* tdig,
-                                                      const uint32_t* mkey, uint32_t* okey,
-                                                      uint32_t* oidx) {
-  constexpr int NW = KT / 64;
-  __shared__ uint32_t wsum[NW];
-  const int64_t b = blockIdx.x;
-  if (mcnt[b] == 0) return;
-  const int64_t j0 = min(off[b * B3], n), j1 = min(off[b * B3 + B3], n);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-  int64_t dst = moff[b];
-  for (int64_t base = j0; base < j1; base += KT) {
-    const int64_t j = base + threadIdx.x;
-    const bool m = j < j1 && tdig[j] == (uint16_t)B3;
-    const uint64_t bal = __ballot(m);
-    if (lane == 0) wsum[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int q = 0; q < NW; ++q) {
-      pre += q < w ? wsum[q] : 0u;
-      tot += wsum[q];
-    }
-    if (m) {
-      const int64_t o = dst + pre + (uint32_t)__popcll(bal & lt);
-      okey[o] = mkey[j];
-      oidx[o] = (uint32_t)j;
-    }
-    dst += tot;
-    __syncthreads();
-  }
-}
-
 __device__ inline int64_t lower_bound_u32(const uint32_t* a, int64_t lo, int64_t hi, uint32_t v) {
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
@@ -655,77 +619,116 @@ __global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uin
   atomicAdd((unsigned long long*)&cnt[k], (unsigned long long)(((uint64_t)nb << 32) | (uint64_t)(ge - s)));
 }
 
-// One workgroup per brick: stayers to their final stream positions. The first position
-// of the brick's stayers in each new cell (cell offset + arrivals from earlier bricks)
-// is staged in LDS; the rank of a stayer among the brick's stayers of its new cell, in
-// old stream order, comes from a stable multi-split of each round by digit (ballots per
-// wave, per-wave digit counts, running counts per cell).
-__global__ __launch_bounds__(KT) void k_place_stayers(const int64_t* off_in, const uint16_t* tdig,
-                                                     const uint8_t* tpos, const uint16_t* tvel,
-                                                     const uint64_t* cnt, const int64_t* off_new,
-                                                     int B3, int nbits, uint8_t* pos,
-                                                     uint16_t* vel, int64_t* perm, int64_t n,
-                                                     DevErr* err) {
-  constexpr int NW = KT / 64;
-  extern __shared__ int64_t dbase[];  // [B3], then run [B3] and wc [NW][B3] (uint32)
-  uint32_t* run = (uint32_t*)(dbase + B3);
-  uint32_t* wc = run + B3;
-  const int64_t b = blockIdx.x;
-  const int64_t kbase = b * B3;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// The two re-sort kernels below give each brick one wave (WB bricks per workgroup) and
+// take its particles in chunks of 64, PU chunks' loads issued together; ranks come from
+// ballots and a running count per wave, so no kernel has a barrier.
+constexpr int WB = 4;
+constexpr int PU = 8;
+
+// Movers of brick b, in old stream order, to [moff[b], moff[b] + mcnt[b]).
+__global__ __launch_bounds__(64 * WB) void k_compact_movers(
+    const int64_t* off, const uint32_t* mcnt, const int64_t* moff, int B3, int64_t nbrick,
+    int64_t n, const uint16_t* tdig, const uint32_t* mkey, uint32_t* okey, uint32_t* oidx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * WB + (threadIdx.x >> 6);
+  if (b >= nbrick || mcnt[b] == 0) return;  // the whole wave
   const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-  for (int l = threadIdx.x; l < B3; l += KT) {
+  const int64_t j0 = min(off[b * B3], n), j1 = min(off[b * B3 + B3], n);
+  int64_t dst = moff[b];
+  for (int64_t base = j0; base < j1; base += 64 * PU) {
+    uint32_t d[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int64_t j = base + 64 * u + lane;
+      d[u] = j < j1 ? tdig[j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int64_t j = base + 64 * u + lane;
+      const bool m = j < j1 && d[u] == (uint32_t)B3;
+      const uint64_t bal = __ballot(m);
+      if (m) {
+        const int64_t o = dst + __popcll(bal & lt);
+        okey[o] = mkey[j];
+        oidx[o] = (uint32_t)j;
+      }
+      dst += __popcll(bal);
+    }
+  }
+}
+
+// Stayers of brick b to their final stream positions: the first position of the
+// brick's stayers in each new cell (cell offset + arrivals from earlier bricks), plus
+// the stayer's rank among the brick's stayers of that cell in old stream order (a
+// stable multi-split of each chunk by digit and a running count per cell).
+__global__ __launch_bounds__(64 * WB) void k_place_stayers(
+    const int64_t* off_in, const uint16_t* tdig, const uint8_t* tpos, const uint16_t* tvel,
+    const uint64_t* cnt, const int64_t* off_new, int B3, int nbits, int64_t nbrick,
+    uint8_t* pos, uint16_t* vel, int64_t* perm, int64_t n, DevErr* err) {
+  extern __shared__ int64_t lds[];  // dbase [WB][B3], then run [WB][B3] (uint32)
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t* dbase = lds + (int64_t)wv * B3;
+  uint32_t* run = (uint32_t*)(lds + (int64_t)WB * B3) + (int64_t)wv * B3;
+  const int64_t b = (int64_t)blockIdx.x * WB + wv;
+  if (b >= nbrick) return;  // the whole wave
+  const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+  const int64_t kbase = b * B3;
+  for (int l = lane; l < B3; l += 64) {
     dbase[l] = off_new[kbase + l] + (int64_t)(cnt[kbase + l] >> 32);
     run[l] = 0;
   }
-  for (int i = threadIdx.x; i < NW * B3; i += KT) wc[i] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int64_t j0 = min(off_in[kbase], n), j1 = min(off_in[kbase + B3], n);
-  __syncthreads();
-  for (int64_t base = j0; base < j1; base += KT) {
-    const int64_t j = base + threadIdx.x;
-    const bool valid = j < j1;
-    const int64_t jj = valid ? j : j0;
-    const uint32_t d = tdig[jj];
-    uint32_t p[3], v[3];
+  for (int64_t base = j0; base < j1; base += 64 * PU) {
+    uint32_t d[PU], p[PU][3], v[PU][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      p[a] = tpos[3 * jj + a];
-      v[a] = tvel[3 * jj + a];
-    }
-    const bool stay = valid && d < (uint32_t)B3;
-    uint64_t match = __ballot(stay);
-    for (int bit = 0; bit < nbits; ++bit) {
-      const uint64_t mbit = __ballot(stay && ((d >> bit) & 1u));
-      match &= ((d >> bit) & 1u) ? mbit : ~mbit;
-    }
-    const uint32_t rk = (uint32_t)__popcll(match & lt);
-    if (stay && rk == 0) wc[w * B3 + d] = (uint32_t)__popcll(match);
-    __syncthreads();
-    if (stay) {
-      uint32_t rank = run[d] + rk;
-      for (int q = 0; q < w; ++q) rank += wc[q * B3 + d];
-      const int64_t dst = dbase[d] + (int64_t)rank;
-      if (dst < 0 || dst >= n) {
-        latch_error(err, ERRBIT_CORRUPT);
-      } else {
+    for (int u = 0; u < PU; ++u) {
+      const int64_t j = base + 64 * u + lane;
+      const bool h = j < j1;
+      const int64_t jj = h ? j : j0;
+      d[u] = h ? tdig[jj] : (uint32_t)B3;  // past the end: not a stayer
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          pos[3 * dst + a] = (uint8_t)p[a];
-          vel[3 * dst + a] = (uint16_t)v[a];
+      for (int a = 0; a < 3; ++a) {
+        p[u][a] = tpos[3 * jj + a];
+        v[u][a] = tvel[3 * jj + a];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const uint32_t du = d[u];
+      const bool stay = du < (uint32_t)B3;
+      uint64_t match = __ballot(stay);
+      for (int bit = 0; bit < nbits; ++bit) {
+        const uint64_t mbit = __ballot(stay && ((du >> bit) & 1u));
+        match &= ((du >> bit) & 1u) ? mbit : ~mbit;
+      }
+      const uint32_t rk = (uint32_t)__popcll(match & lt);
+      uint32_t before = 0;
+      if (stay) before = run[du];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (stay && rk == 0) run[du] = before + (uint32_t)__popcll(match);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (stay) {
+        const int64_t dst = dbase[du] + (int64_t)(before + rk);
+        const int64_t j = base + 64 * u + lane;
+        if (dst < 0 || dst >= n) {
+          latch_error(err, ERRBIT_CORRUPT);
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            pos[3 * dst + a] = (uint8_t)p[u][a];
+            vel[3 * dst + a] = (uint16_t)v[u][a];
+          }
+          if (perm) perm[dst] = j;
         }
-        if (perm) perm[dst] = j;
       }
     }
-    __syncthreads();
-    for (int l = threadIdx.x; l < B3; l += KT) {
-      uint32_t add = 0;
-      for (int q = 0; q < NW; ++q) {
-        add += wc[q * B3 + l];
-        wc[q * B3 + l] = 0;
-      }
-      run[l] += add;
-    }
-    __syncthreads();
   }
 }
 
@@ -858,7 +861,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
           PM_OK)
         return st0;
   }
-  const size_t place_lds = (size_t)B3 * 8 + (size_t)B3 * 4 * (1 + KT / 64);
+  const size_t place_lds = (size_t)WB * B3 * 12;
   for (int s = 0; s < n_sp; ++s) {
     const int64_t n = in[s].n;
     const KickSpecies& S = A.sp[s];
@@ -872,8 +875,9 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     uint32_t* sk = skey + nbase[s];
     uint32_t* si = sidx + nbase[s];
     if (nm > 0) {
-      hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)g.nbrick), dim3(KT), 0, c->stream,
-                         S.off, S.mcnt, moff, B3, n, S.tdig, S.mkey, sk, si);
+      hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)cdiv(g.nbrick, WB)), dim3(64 * WB),
+                         0, c->stream, S.off, S.mcnt, moff, B3, g.nbrick, n, S.tdig, S.mkey,
+                         sk, si);
       PM_LAUNCH_CHECK();
       // stable sort (old order preserved inside each new cell)
       uint32_t *k1 = sk, *v1 = si, *k2 = S.mkey, *v2 = midx + nbase[s];
@@ -888,9 +892,9 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
-    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)g.nbrick), dim3(KT), place_lds,
-                       c->stream, S.off, S.tdig, S.tpos, S.tvel, S.cnt, off_new, B3,
-                       3 * g.lgB, out[s].pos, out[s].vel, pm, n, c->err);
+    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)cdiv(g.nbrick, WB)), dim3(64 * WB),
+                       place_lds, c->stream, S.off, S.tdig, S.tpos, S.tvel, S.cnt, off_new,
+                       B3, 3 * g.lgB, g.nbrick, out[s].pos, out[s].vel, pm, n, c->err);
     PM_LAUNCH_CHECK();
     if (nm > 0) {
       hipLaunchKernelGGL(k_place_movers, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream,
