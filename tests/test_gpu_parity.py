@@ -180,9 +180,11 @@ def _codes_old_order(host_state, perm):
     return uo, jo
 
 
-# bricks: the default (16-node staged tiles), 2 (8-node tiles at r = 4) and 1 (the
-# per-particle gather from the mesh)
-@pytest.mark.parametrize("n_p_c,n_mesh,seed,brick", [(16, 32, 0, None), (32, 64, 1, None),
+# kick variants: two-brick z-half tiles (16 nodes per brick side: 4 cells at r = 4,
+# 2 cells at r = 8), one-brick 16-node tiles (8 cells at r = 2), 8-node tiles (2 cells
+# at r = 4) and the per-particle gather from the mesh (1 cell at r = 2)
+@pytest.mark.parametrize("n_p_c,n_mesh,seed,brick", [(16, 64, 4, None), (16, 128, 5, 2),
+                                                     (16, 32, 0, None), (32, 64, 1, None),
                                                      (16, 64, 2, 2), (16, 32, 3, 1)])
 def test_compressed_step_tie_zone(n_p_c, n_mesh, seed, brick):
     wl = small_two_species(n_p_c, n_mesh, seed_offset=seed)
