@@ -6,6 +6,8 @@ positions <= 1e-6 box units; compressed codes equal except in the tie zone where
 oracle's pre-floor value lies within the propagated force tolerance of an integer.
 """
 
+import types
+
 import numpy as np
 import pytest
 import torch
@@ -189,16 +191,35 @@ def _codes_old_order(host_state, perm):
 def test_compressed_step_tie_zone(n_p_c, n_mesh, seed, brick):
     wl = small_two_species(n_p_c, n_mesh, seed_offset=seed)
     c = ctx(n_mesh, wl.n_cell, brick=brick)
-    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    _step_against_oracle(c, wl.species, n_mesh, wl.n_cell, wl.dt)
+
+
+# one to four species (the most a step takes) through the two-brick kick tiles (r = 4)
+# and the one-brick 16-node tiles (r = 2)
+@pytest.mark.parametrize("n_sp,n_mesh", [(1, 64), (3, 64), (4, 64), (4, 32)])
+def test_compressed_step_species_count(n_sp, n_mesh):
+    a = small_two_species(16, n_mesh, seed_offset=6)
+    b = small_two_species(16, n_mesh, seed_offset=7)
+    species = [a.species[0], a.species[1], b.species[0], b.species[1]][:n_sp]
+    # distinct masses, so a species mix-up shows in the density and force
+    species = [types.SimpleNamespace(x=sp.x, v=sp.v, mass=sp.mass * (1.0 + 0.25 * i))
+               for i, sp in enumerate(species)]
+    c = ctx(n_mesh, a.n_cell)
+    _step_against_oracle(c, species, n_mesh, a.n_cell, a.dt)
+
+
+def _step_against_oracle(c, species, n_mesh, n_cell, dt):
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in species]
     rho = c.deposit(dev)
     acc, amax = c.force(rho)
-    dt = wl.dt
     out, perms = c.kick_drift_perm(dev, acc, amax, dt, dt)
     c.sync()
     states = [c.to_host(d) for d in dev]
-    masses = [sp.mass for sp in wl.species]
+    masses = [sp.mass for sp in species]
     new, diag = step.step_compressed(states, masses, n_mesh, dt, dt)
-    S = 256 * wl.n_cell
+    assert density_close(rho.cpu().numpy(), diag["rho"]) <= 1e-5
+    assert rel_rms(acc.cpu().numpy(), diag["a_mesh"]) <= 1e-4
+    S = 256 * n_cell
     a_scale = np.sqrt(np.mean(diag["a_mesh"] ** 2))
     for o, ns, d, perm in zip(out, new, diag["species"], perms):
         h = c.to_host(o)
@@ -225,11 +246,11 @@ def test_compressed_step_tie_zone(n_p_c, n_mesh, seed, brick):
         assert np.all(frac_dist(d["vel_pre"][badv]) <= tau_v[badv])
         assert badv.mean() < 1e-3
         # the stream is the stable cell sort of the GPU's own new codes
-        keys = codec.cell_keys(ug >> 8, wl.n_cell, c.brick)
+        keys = codec.cell_keys(ug >> 8, n_cell, c.brick)
         order = np.argsort(keys, kind="stable")
         assert np.array_equal(order, pm)
         assert np.array_equal(codec.full_counts(h),
-                              np.bincount(keys, minlength=wl.n_cell ** 3))
+                              np.bincount(keys, minlength=n_cell ** 3))
 
 
 def test_step_equals_pieces_and_is_deterministic():
