@@ -189,8 +189,11 @@ pm_status pm_step(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp, d
  * re-sort that maps output order to input order); the cotangent of the interpolated
  * force is scattered to three meshes, taken through the transposed force operator
  * (eqs. (1)-(3): the conjugate spectral multiplier +i k G) and gathered with the
- * gradient of the CIC weights. The scatter uses float atomics, so results may differ
- * between calls in the last bits. */
+ * gradient of the CIC weights. For compressed states on 16-node tiles (r = 2, 4 or 8
+ * mesh cells per compression cell) the scatter sums 32-bit fixed-point integers per
+ * tile and species, and the result is the same on every call; other shapes and float
+ * states sum with float atomics, and results may then differ between calls in the
+ * last bits. */
 pm_status pm_step_vjp(pm_ctx ctx, const pm_species* in, int n_sp, double dt,
                       float* const* lam_x1, float* const* lam_v1, float* const* lam_x0,
                       float* const* lam_v0);

@@ -15,7 +15,9 @@
 //
 // Compressed states are differentiated straight-through at the decoded bin centres;
 // the forward re-sort is recomputed to map the new stream order of the cotangents back
-// to the old order. The scatter sums with float atomics (summation order not fixed).
+// to the old order. The tiled scatter of compressed states sums fixed-point integers
+// (the result does not depend on the order of the atomics); the per-particle scatter of
+// the other shapes sums with float atomics (summation order not fixed).
 #include "pm_codec.h"
 #include "pm_scan.h"
 
@@ -193,23 +195,38 @@ struct AdjArgs {
 
 __device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-// One workgroup per tile of TT^3 cells = 16^3 mesh nodes (r = 16 / TT), the three mu
-// components summed in LDS (float atomics) and written with plain stores: every node
-// has one owner. Particles of the one-cell shell on the -x/-y/-z faces reach the tile's
-// lowest node plane and are included, as in the deposit.
+// One workgroup per tile of TT^3 cells = 16^3 mesh nodes (r = 16 / TT). Particles of the
+// one-cell shell on the -x/-y/-z faces reach the tile's lowest node plane and are
+// included, as in the deposit. Each species' contributions w g are summed in LDS as
+// 32-bit fixed-point integers (integer LDS atomics are several times faster than float
+// ones, and integer sums do not depend on the order of the atomics): the unit 2^-q is
+// chosen per tile and species from the largest |g| and the particle count so that no
+// sum can overflow. Each species is then converted into per-thread float sums of the
+// thread's nodes, in species order, and the tile is written with plain stores: every
+// node has one owner. A species whose cotangents in the tile are not all finite is
+// summed with float atomics instead, so that inf and NaN propagate.
 template <int TT>
 __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* mu) {
   constexpr int T = TT, R = 16, r = 16 / TT, E = T + 1, NE = E * E * E, R3 = R * R * R;
-  __shared__ float F[3 * R3];
+  constexpr int NW = ST / 64, NPT = R3 / ST;
+  __shared__ int F[3 * R3];  // one species' sums (fixed point, or float bits)
   __shared__ int64_t cst[NE];
   __shared__ int pre[NE + 1];
   __shared__ int64_t lw[ST / 64 + 1];
+  __shared__ float wgm[NW];
+  __shared__ int wnf[NW];
   const int nt = (int)(g.nc / T);
   const int64_t tile = xcd_tile(blockIdx.x, (int64_t)nt * nt * nt);
   const int tx = (int)(tile % nt), ty = (int)((tile / nt) % nt),
             tz = (int)(tile / ((int64_t)nt * nt));
   const int ncs = (int)g.nc;
-  for (int i = threadIdx.x; i < 3 * R3; i += ST) F[i] = 0.f;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 3 * R3; i += ST) F[i] = 0;
+  float racc[3][NPT];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) racc[c][k] = 0.f;
   for (int s = 0; s < A.n_sp; ++s) {
     const AdjSpecies sp = A.sp[s];
     __syncthreads();
@@ -240,10 +257,30 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
     __syncthreads();
     const int P = pre[NE];
     constexpr int U = 4;
-    for (int q0 = threadIdx.x; q0 < P; q0 += ST * U) {
-      int eu[U];
+    // the largest |g| of the species' particles in the tile: from the first batch's
+    // registers when one batch holds them all, otherwise from a pass of its own (one
+    // wave per extended cell)
+    const bool one = P <= ST * U;
+    float gm = 0.f;
+    int nf = 0;
+    if (!one)
+      for (int e = w; e < NE; e += NW)
+        for (int q = lane; q < pre[e + 1] - pre[e]; q += 64) {
+          const int64_t j = cst[e] + q;
+          if (j < sp.n)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const float v = fabsf(sp.gv[3 * j + a]);
+              nf |= !(v <= 3.4028234e38f);  // inf or NaN
+              gm = fmaxf(gm, v);
+            }
+        }
+    int eu[U];
+    bool ok[U];
+    uint32_t pb[U][3];
+    float gg[U][3];
+    auto load_batch = [&](int q0) {
       int64_t ju[U];
-      bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u * ST;
@@ -257,8 +294,6 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
         ok[u] = q < P && j < sp.n;
         ju[u] = ok[u] ? j : 0;  // n > 0 whenever P > 0
       }
-      uint32_t pb[U][3];
-      float gg[U][3];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -266,6 +301,37 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
           pb[u][a] = sp.pos[3 * ju[u] + a];
           gg[u][a] = sp.gv[3 * ju[u] + a];
         }
+    };
+    load_batch(threadIdx.x);
+    if (one)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float v = ok[u] ? fabsf(gg[u][a]) : 0.f;
+          nf |= !(v <= 3.4028234e38f);
+          gm = fmaxf(gm, v);
+        }
+    for (int d = 32; d >= 1; d >>= 1) {
+      gm = fmaxf(gm, __shfl_xor(gm, d, 64));
+      nf |= __shfl_xor(nf, d, 64);
+    }
+    if (lane == 0) {
+      wgm[w] = gm;
+      wnf[w] = nf;
+    }
+    __syncthreads();
+    for (int q = 0; q < NW; ++q) {
+      gm = fmaxf(gm, wgm[q]);
+      nf |= wnf[q];
+    }
+    // unit 2^-qs: P gm 2^qs < 2^30, so a node's sum of at most P rounded contributions
+    // stays below 2^30 + P / 2 < 2^31
+    const bool fixed = !nf;
+    const float t = (float)P * gm;
+    const int qs = t > 0.f ? 29 - ilogbf(t) : 0;
+    for (int q0 = threadIdx.x; q0 < P; q0 += ST * U) {
+      if (q0 != (int)threadIdx.x) load_batch(q0);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (!ok[u]) continue;
@@ -290,18 +356,33 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
             for (int dx = 0; dx < 2; ++dx) {
               const int nx = li[0] + dx, wx = dx ? f[0] : 512 - f[0];
               if (nx < 0 || nx >= R || wx == 0) continue;
-              const float w = (float)((uint32_t)(wx * wy) * (uint32_t)wz) * 0x1p-27f;
+              const float wt = (float)((uint32_t)(wx * wy) * (uint32_t)wz) * 0x1p-27f;
               const int node = (nz * R + ny) * R + nx;
-              atomicAdd(&F[node], w * gg[u][0]);
-              atomicAdd(&F[R3 + node], w * gg[u][1]);
-              atomicAdd(&F[2 * R3 + node], w * gg[u][2]);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const float cv = wt * gg[u][a];
+                if (fixed)
+                  atomicAdd(&F[a * R3 + node], __float2int_rn(ldexpf(cv, qs)));
+                else
+                  atomicAdd((float*)&F[a * R3 + node], cv);
+              }
             }
           }
         }
       }
     }
+    // this species' sums into the thread's float node sums, then cleared
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int i = c * R3 + threadIdx.x + k * ST;
+        const int v = F[i];
+        racc[c][k] += fixed ? ldexpf((float)v, -qs) : __int_as_float(v);
+        F[i] = 0;
+      }
   }
-  __syncthreads();
   // node i = threadIdx.x + 256 k: lx = i & 15, ly = (i >> 4) & 15, lz = k
   const int64_t ng = g.ng, ng2 = ng * ng, n3 = ng2 * ng;
   float* dst = mu + (int64_t)tz * 16 * ng2 + ((int64_t)ty * 16 + ((threadIdx.x >> 4) & 15)) * ng +
@@ -309,8 +390,7 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int k = 0; k < R3 / ST; ++k)
-      dst[c * n3 + k * ng2] = A.ck * F[c * R3 + threadIdx.x + k * ST];
+    for (int k = 0; k < NPT; ++k) dst[c * n3 + k * ng2] = A.ck * racc[c][k];
 }
 
 // Gradient gather on bricks of B^3 cells = 16^3 nodes: the four meshes a_x, a_y, a_z

@@ -80,6 +80,64 @@ def test_step_vjp_compressed_two_species_matches_oracle(n_mesh, n_cell):
     c.close()
 
 
+def test_step_vjp_compressed_dense_tile_matches_oracle():
+    """Half of the neutrinos in a ball of radius 0.02: one tile holds far more particles
+    than one batch of the tiled scatter, which then sizes its fixed-point unit from a
+    pass of its own over the tile's cotangents."""
+    import types
+    wl = small_two_species(n_p_c=16, n_mesh=64, n_cell=16, seed_offset=3)
+    rng = np.random.default_rng(21)
+    nu = wl.species[1]
+    x = nu.x.copy()
+    h = x.shape[0] // 2
+    x[:h] = (0.3 + 0.02 * rng.uniform(-1.0, 1.0, (h, 3))).astype(x.dtype)
+    species = [wl.species[0], types.SimpleNamespace(x=x, v=nu.v, mass=nu.mass)]
+    c = ctx(wl.n_mesh, wl.n_cell)
+    st = [c.encode(c.float_species(s.x, s.v, s.mass)) for s in species]
+    host = [c.to_host(s) for s in st]
+    masses = [s.mass for s in species]
+    _, diag = step.step_compressed(host, masses, wl.n_mesh, wl.dt, wl.dt)
+    perms = [d["perm"] for d in diag["species"]]
+    ns = [s.x.shape[0] for s in species]
+    lx1, lv1 = _cotangents(ns, 13)
+    gx, gv = c.step_vjp(st, wl.dt, _dev(lx1, c.device), _dev(lv1, c.device))
+    rx, rv = adjoint.vjp_step_compressed(host, masses, lx1, lv1, perms, wl.n_mesh,
+                                         wl.dt, wl.dt)
+    for a, b, l, p in zip(gx, rx, lx1, perms):
+        lo = np.empty_like(l)
+        lo[p] = l
+        e = rel_rms(a.cpu().numpy() - lo, b - lo)
+        assert e <= TOL, e
+    c.close()
+
+
+def test_step_vjp_compressed_repeatable():
+    """The tiled scatter sums fixed-point integers: two calls give the same bits."""
+    wl = small_two_species(n_p_c=16, n_mesh=64, n_cell=16, seed_offset=5)
+    c = ctx(wl.n_mesh, wl.n_cell)
+    st = [c.encode(c.float_species(s.x, s.v, s.mass)) for s in wl.species]
+    lx1, lv1 = _cotangents([s.n for s in wl.species], 19)
+    a = c.step_vjp(st, wl.dt, _dev(lx1, c.device), _dev(lv1, c.device))
+    b = c.step_vjp(st, wl.dt, _dev(lx1, c.device), _dev(lv1, c.device))
+    for p, q in zip(a[0] + a[1], b[0] + b[1]):
+        assert torch.equal(p, q)
+    c.close()
+
+
+def test_step_vjp_nan_cotangent_propagates():
+    """A NaN velocity cotangent must not vanish in the fixed-point scatter: its tile is
+    summed in float, so the position gradients come out NaN."""
+    wl = small_two_species(n_p_c=16, n_mesh=64, n_cell=16, seed_offset=4)
+    c = ctx(wl.n_mesh, wl.n_cell)
+    st = [c.encode(c.float_species(s.x, s.v, s.mass)) for s in wl.species]
+    ns = [s.n for s in wl.species]
+    lx1, lv1 = _cotangents(ns, 17)
+    lv1[1][5, 2] = np.nan
+    gx, _ = c.step_vjp(st, wl.dt, _dev(lx1, c.device), _dev(lv1, c.device))
+    assert np.isnan(gx[0].cpu().numpy()).any()
+    c.close()
+
+
 def test_step_vjp_rejects_aliased_results():
     wl = make_workload("plain_cdm_64", n_p_c=8, n_mesh=16, n_cell=8)
     c = ctx(wl.n_mesh, wl.n_cell)
