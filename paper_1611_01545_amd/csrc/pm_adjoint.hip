@@ -403,7 +403,8 @@ __global__ __launch_bounds__(GT) void k_gather_brick(AdjArgs A, Geom g, const fl
                                                      const float* nu) {
   constexpr int FS = GR1 * GR1 * GR1;
   __shared__ float Fm[4 * FS];  // a_x, a_y, a_z, nu on the brick's nodes
-  __shared__ int64_t loff[8 * 8 * 8 + 1];
+  extern __shared__ int64_t loff[];  // [B^3 + 1]: sized at launch, so that two
+                                     // workgroups fit one CU's LDS at B = 4
   const int B = g.B, B3 = B * B * B, r = g.r;
   const int64_t b = xcd_tile(blockIdx.x, g.nbrick);
   const uint32_t kbase = (uint32_t)(b * B3);
@@ -677,8 +678,8 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
     ProfScope ps(c, ST_ADJOINT);
     if (tiled) {
       if (T.n_sp > 0)
-        hipLaunchKernelGGL(k_gather_brick, dim3((unsigned)g.nbrick), dim3(GT), 0, c->stream,
-                           T, g, acc, mu);
+        hipLaunchKernelGGL(k_gather_brick, dim3((unsigned)g.nbrick), dim3(GT),
+                           (size_t)(g.B * g.B * g.B + 1) * 8, c->stream, T, g, acc, mu);
     } else {
       for (int i = 0; i < n_sp; ++i) {
         if (in[i].n == 0) continue;
