@@ -633,8 +633,6 @@ __global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h) {
   gtab[q] = ktab[kx * kx + ay * ay + az * az];
 }
 
-__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
-
 // ------------------------------------------------------------------ dispatch --
 // columns per workgroup: at most 16, at most half the line length (the number of kx
 // lines is N/2, so W always divides the line count), and the LDS exchange <= 64 KB

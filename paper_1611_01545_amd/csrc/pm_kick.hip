@@ -407,7 +407,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
     const int s = i / L, l = i - s * L;
     if (l < B3) A.sp[s].cnt[kbase + l] = (uint64_t)run[i];
   }
-  if (threadIdx.x < n_sp) {
+  if ((int)threadIdx.x < n_sp) {
     const int s = threadIdx.x;
     A.sp[s].mcnt[b] = mvc[s];
     A.sp[s].pmn[b] = smm[2 * s];
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr*
     const int s = rem / L, l = rem - s * L;
     if (s < n_sp && l < B3) A.sp[s].cnt[kb0 + k * B3 + l] = (uint64_t)run[i];
   }
-  if (threadIdx.x < 2 * n_sp) {
+  if ((int)threadIdx.x < 2 * n_sp) {
     const int k = threadIdx.x / n_sp, s = threadIdx.x - k * n_sp;
     A.sp[s].mcnt[b0 + k] = mvc[k * MAXSP + s];
     A.sp[s].pmn[b0 + k] = smm[2 * s];
