@@ -44,21 +44,21 @@ WORKLOAD_TEXT = {
 # taken on (sha256 over `sources`); otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
     ("interp_kick_drift", "tile_1024"): {
-        "kernel": "k_kick_pair",
+        "kernel": "k_kick_pair<256, 4>",
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "1b89b563c0ab3d35369e45bf4f580e1c0dc620ee2adac77cd6d06d5fcee9bd65",
-        "fetch_kib": 8071411.69, "fetch_factor": 1.99988,
-        "write_kib": 2091342.19, "write_factor": 1.0,
+        "sha256": "8bcbfa068df5b937d5de6a465f98c7a2c51f2666e916c09b1e895dd88794c43d",
+        "fetch_kib": 9098421.38, "fetch_factor": 1.99988,
+        "write_kib": 2166335.78, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
         "kernel": "k_row_c2r<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "6a69d53df7575f823890fad4cbb22772550a67bb7679662e6dbca7f53373e2e8",
-        "fetch_kib": 2102459.0, "fetch_factor": 1.99988,
-        "write_kib": 4196547.0, "write_factor": 1.0,
+        "sha256": "3e08642fdbbbff96ff4a9ad0657fa2aabbcc03d7e624f6102736969a330d806b",
+        "fetch_kib": 2102489.0, "fetch_factor": 1.99988,
+        "write_kib": 4196544.0, "write_factor": 1.0,
     },
 }
 

@@ -416,16 +416,20 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
   if (bad) latch_error(err, ERRBIT_RANGE);
 }
 
-// ---- two bricks adjacent along x per workgroup, R = 16, in two z-half passes ----
+// ---- two bricks adjacent along x per workgroup, R = 16, in NZ passes over z ----
 // Pass h stages the force nodes x in [x0, x0 + 2R], y in [y0, y0 + R], z in
-// [z0 + h R/2, z0 + (h + 1) R/2] (33 x 17 x 9 nodes) and kicks the particles of both
-// bricks' cells in that z half. Rows of the staged tile are 2R nodes long, which the
-// memory system serves much faster than rows of R.
+// [z0 + h R/NZ, z0 + (h + 1) R/NZ] (33 x 17 x 5 nodes for NZ = 4) and kicks the
+// particles of both bricks' cells in that z slice (whole cell layers). Rows of the
+// staged tile are 2R nodes long, which the memory system serves much faster than rows
+// of R; with NZ = 4 and 256 threads the tile is 34 KB and four workgroups share a CU,
+// each staging while the others compute.
 constexpr int PR = 16;
-__global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
-  constexpr int X1 = 2 * PR + 1, Y1 = PR + 1, Z1 = PR / 2 + 1;
+template <int NT, int NZ>  // threads per workgroup, z passes
+__global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
+  constexpr int KB = NT, NWK = NT / 64;
+  constexpr int X1 = 2 * PR + 1, Y1 = PR + 1, Z1 = PR / NZ + 1;
   constexpr int TS = X1 * Y1 * Z1;  // nodes per component
-  const int B = g.B, B3 = B * B * B, L = B3 + 1, H = B3 / 2;  // H: cells per z half
+  const int B = g.B, B3 = B * B * B, L = B3 + 1, H = B3 / NZ;  // H: cells per z pass
   extern __shared__ unsigned char smem[];
   float* F = (float*)smem;                          // [3][Z1][Y1][X1]
   uint32_t* rel = (uint32_t*)(smem + 3 * TS * 4);   // [2][MAXSP][L]
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr*
     constexpr int DC = DR / RR, DLZ = (DR % RR) / Y1, DLY = DR % Y1;
     static_assert(KB % Q == 0, "a workgroup covers whole rows");
     const uint32_t mu = (uint32_t)(ng - 1), ngu = (uint32_t)ng;
-    const uint32_t oz2 = (uint32_t)oz + h * (PR / 2);
+    const uint32_t oz2 = (uint32_t)oz + h * (PR / NZ);
     const uint32_t oxq = (uint32_t)ox + 4 * (threadIdx.x % Q);
     const uint32_t hx = ((uint32_t)ox + 2 * PR) & mu;
     const float* pc0 = A.acc;
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr*
       uint32_t bc[3];
       key_cell(g, kb0 + (uint32_t)(k * B3), bc[0], bc[1], bc[2]);
       auto gather = [&](const int li[3], const float f[3], float acc3[3]) {
-        const int tx = li[0] + k * PR, ty = li[1], tz = li[2] - h * (PR / 2);
+        const int tx = li[0] + k * PR, ty = li[1], tz = li[2] - h * (PR / NZ);
         acc3[0] = acc3[1] = acc3[2] = 0.f;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
@@ -576,7 +580,7 @@ __global__ __launch_bounds__(KB, 4) void k_kick_pair(KickArgs A, Geom g, DevErr*
       }
     }
   };
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NZ; ++h) {
     stage(h);
     if (fast) pass(std::true_type{}, h);
     else pass(std::false_type{}, h);
@@ -838,13 +842,13 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     ProfScope ps(c, ST_KICK);
     const int R = g.B * g.r;
     const size_t tail = (size_t)MAXSP * (B3 + 1) * 4 * 2;
-    // two bricks per workgroup: R = 16, an even number of bricks per side, z halves of
+    // two bricks per workgroup: R = 16, an even number of bricks per side, z quarters of
     // whole cells
-    const size_t pbytes = (size_t)3 * (2 * PR + 1) * (PR + 1) * (PR / 2 + 1) * 4 + 2 * tail;
+    const size_t pbytes = (size_t)3 * (2 * PR + 1) * (PR + 1) * (PR / 4 + 1) * 4 + 2 * tail;
     const size_t fbytes = (size_t)3 * (R + 1) * (R + 1) * (R + 1) * 4;
-    if (R == PR && g.lgnb >= 1 && (g.B % 2) == 0 && pbytes <= 72 * 1024)
-      hipLaunchKernelGGL(k_kick_pair, dim3((unsigned)(g.nbrick / 2)), dim3(KB), pbytes,
-                         c->stream, A, g, c->err);
+    if (R == PR && g.lgnb >= 1 && (g.B % 4) == 0 && pbytes <= 48 * 1024)
+      hipLaunchKernelGGL((k_kick_pair<256, 4>), dim3((unsigned)(g.nbrick / 2)), dim3(256),
+                         pbytes, c->stream, A, g, c->err);
     else if (R == 16 && fbytes + tail <= 96 * 1024)
       hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB), fbytes + tail,
                          c->stream, A, g, c->err);
