@@ -13,10 +13,15 @@
 // Weights are exact: a compressed position sits at the bin centre (2u+1)/(512 n_c),
 // i.e. at (2u+1) r / 512 mesh cells, so each axis weight is an integer multiple of
 // 1/512 and their product an integer multiple of 2^-27. Each species' weights are
-// summed as 64-bit integers in LDS (exact, so independent of the order of the
-// atomics), then scaled by the species' mass into per-thread FP64 node densities in a
-// fixed species order: every run, and the recomputation in the adjoint, gives
-// bit-identical densities.
+// summed as integers in LDS (exact, so independent of the order of the atomics): a
+// 32-bit word per node that wraps, plus a 16-bit count of its wraps, so 48 bits per
+// node in 6 bytes. Each species' sum is scaled by its mass in FP64, rounded once to
+// float and added to the thread's float node densities in a fixed species order: every
+// run, and the recomputation in the adjoint, gives bit-identical densities.
+//
+// The tile loop is bound by latency (cell offsets, then particle codes, per species),
+// so what pays is tiles in flight: the 26 KB of LDS and 79 VGPRs of a 16^3-node tile
+// let six workgroups share a CU (64-bit sums in LDS and FP64 densities held four).
 #include "pm_codec.h"
 #include "pm_scan.h"
 
@@ -39,6 +44,11 @@ struct DepArgs {
   int R;   // tile side in nodes
 };
 
+// byte offset of the cell starts after the weight sums (low words, then carries)
+__host__ __device__ inline size_t dep_cst_offset(int R3) {
+  return ((size_t)R3 * 4 + (size_t)((R3 + 1) / 2) * 4 + 7) & ~(size_t)7;
+}
+
 __device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 template <int TT>  // tile side in cells (compile time, 0: runtime A.T)
@@ -50,26 +60,30 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
   const int NE = E * E * E;
   const int R3 = R * R * R;
   __shared__ int64_t lw[DEP_THREADS / 64 + 1];
-  unsigned long long* acc = (unsigned long long*)smem;
-  int64_t* cst = (int64_t*)(acc + R3);  // [NE] stream start of each extended cell
-  int* pre = (int*)(cst + NE);          // [NE + 1] particle prefix over extended cells
+  // a node's weight sum is hi 2^32 + lo: lo wraps in the LDS atomics, and each wrap
+  // increments a 16-bit carry counter (two per word)
+  uint32_t* wlo = (uint32_t*)smem;                    // [R3]
+  uint32_t* whi = wlo + R3;                           // [(R3 + 1) / 2]
+  int64_t* cst = (int64_t*)(smem + dep_cst_offset(R3));  // [NE] stream start of each extended cell
+  int* pre = (int*)(cst + NE);                        // [NE + 1] particle prefix over extended cells
   const int nt = (int)(g.nc / T);
   const int64_t tile = xcd_tile(blockIdx.x, (int64_t)nt * nt * nt);
   const int tx = (int)(tile % nt), ty = (int)((tile / nt) % nt), tz = (int)(tile / ((int64_t)nt * nt));
   const int ncs = (int)g.nc;
 
-  for (int i = threadIdx.x; i < R3; i += DEP_THREADS) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < R3; i += DEP_THREADS) wlo[i] = 0u;
   // per-thread density of its nodes i = threadIdx.x + k DEP_THREADS (R <= 16, so at most
-  // 16 nodes), summed over species in a fixed order
+  // 16 nodes), summed over species (and segments) in a fixed order
   constexpr int NPT = 4096 / DEP_THREADS;
-  double racc[NPT];
+  float racc[NPT];
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) racc[k] = 0.0;
+  for (int k = 0; k < NPT; ++k) racc[k] = 0.0f;
 
   for (int s = 0; s < A.n_sp; ++s) {
     const DepSpecies sp = A.sp[s];
     // counts of the extended cells, then an exclusive prefix (single pass per wave)
     __syncthreads();
+    for (int i = threadIdx.x; i < (R3 + 1) / 2; i += DEP_THREADS) whi[i] = 0u;
     for (int e = threadIdx.x; e < NE; e += DEP_THREADS) {
       int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
       int cx = wrapc(tx * T + ex - 1, ncs), cy = wrapc(ty * T + ey - 1, ncs),
@@ -99,75 +113,90 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
     const int P = pre[NE];
     // U particles per thread per round: their code loads are issued together
     constexpr int U = 4;
-    for (int q0 = threadIdx.x; q0 < P; q0 += DEP_THREADS * U) {
-      int eu[U];
-      int64_t ju[U];
-      uint32_t pb[U][3];
-      bool ok[U];
+    // the carries count at most 2^16 wraps, i.e. 2^48 weight units per node: segments
+    // of 2^21 particles (each adds < 2^27 to a node) are flushed one by one; every
+    // tile of a realistic input has a single segment
+    constexpr int SEG = 1 << 21;
+    for (int s0 = 0;; s0 += SEG) {
+      const int s1 = P - s0 > SEG ? s0 + SEG : P;
+      for (int q0 = s0 + (int)threadIdx.x; q0 < s1; q0 += DEP_THREADS * U) {
+        int eu[U];
+        int64_t ju[U];
+        uint32_t pb[U][3];
+        bool ok[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int q = q0 + u * DEP_THREADS;
-        // extended cell of flat particle q: largest e with pre[e] <= q
-        int lo = 0, hi = NE;
-        while (hi - lo > 1) {
-          int mid = (lo + hi) >> 1;
-          if (pre[mid] <= q) lo = mid; else hi = mid;
+        for (int u = 0; u < U; ++u) {
+          const int q = q0 + u * DEP_THREADS;
+          // extended cell of flat particle q: largest e with pre[e] <= q
+          int lo = 0, hi = NE;
+          while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (pre[mid] <= q) lo = mid; else hi = mid;
+          }
+          eu[u] = lo;
+          const int64_t j = cst[lo] + (q - pre[lo]);
+          // counts inconsistent with n are latched by the offset check; q >= s1 is padding
+          ok[u] = q < s1 && j < sp.n;
+          ju[u] = ok[u] ? j : 0;  // n > 0 whenever P > 0
         }
-        eu[u] = lo;
-        const int64_t j = cst[lo] + (q - pre[lo]);
-        // counts inconsistent with n are latched by the offset check; q >= P is padding
-        ok[u] = q < P && j < sp.n;
-        ju[u] = ok[u] ? j : 0;  // n > 0 whenever P > 0
-      }
-      // all code loads of the round, then the arithmetic
+        // all code loads of the round, then the arithmetic
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) pb[u][a] = sp.pos[3 * ju[u] + a];
+          for (int a = 0; a < 3; ++a) pb[u][a] = sp.pos[3 * ju[u] + a];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (!ok[u]) continue;
-        const int e = eu[u];
-        const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
-        int li[3], f[3];
-        const int le[3] = {ex - 1, ey - 1, ez - 1};
+        for (int u = 0; u < U; ++u) {
+          if (!ok[u]) continue;
+          const int e = eu[u];
+          const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+          int li[3], f[3];
+          const int le[3] = {ex - 1, ey - 1, ez - 1};
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          int gl = (2 * (int)pb[u][a] + 1) * r;  // position inside the cell, 1/512 mesh cell
-          li[a] = le[a] * r + (gl >> 9);
-          f[a] = gl & 511;
-        }
+          for (int a = 0; a < 3; ++a) {
+            int gl = (2 * (int)pb[u][a] + 1) * r;  // position inside the cell, 1/512 mesh cell
+            li[a] = le[a] * r + (gl >> 9);
+            f[a] = gl & 511;
+          }
 #pragma unroll
-        for (int dz = 0; dz < 2; ++dz) {
-          int nz = li[2] + dz;
-          int wz = dz ? f[2] : 512 - f[2];
-          if (nz < 0 || nz >= R || wz == 0) continue;
+          for (int dz = 0; dz < 2; ++dz) {
+            int nz = li[2] + dz;
+            int wz = dz ? f[2] : 512 - f[2];
+            if (nz < 0 || nz >= R || wz == 0) continue;
 #pragma unroll
-          for (int dy = 0; dy < 2; ++dy) {
-            int ny = li[1] + dy;
-            int wy = dy ? f[1] : 512 - f[1];
-            if (ny < 0 || ny >= R || wy == 0) continue;
+            for (int dy = 0; dy < 2; ++dy) {
+              int ny = li[1] + dy;
+              int wy = dy ? f[1] : 512 - f[1];
+              if (ny < 0 || ny >= R || wy == 0) continue;
 #pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-              int nx = li[0] + dx;
-              int wx = dx ? f[0] : 512 - f[0];
-              if (nx < 0 || nx >= R || wx == 0) continue;
-              const uint32_t W = (uint32_t)(wx * wy) * (uint32_t)wz;  // exact, 2^-27
-              atomicAdd(&acc[(nz * R + ny) * R + nx], (unsigned long long)W);
+              for (int dx = 0; dx < 2; ++dx) {
+                int nx = li[0] + dx;
+                int wx = dx ? f[0] : 512 - f[0];
+                if (nx < 0 || nx >= R || wx == 0) continue;
+                const uint32_t W = (uint32_t)(wx * wy) * (uint32_t)wz;  // exact, 2^-27
+                const int i = (nz * R + ny) * R + nx;
+                const uint32_t old = atomicAdd(&wlo[i], W);
+                if (old > 0xffffffffu - W) atomicAdd(&whi[i >> 1], 1u << ((i & 1) * 16));
+              }
             }
           }
         }
       }
-    }
-    // this species' integer weight sums into the thread's FP64 node densities
-    __syncthreads();
+      // the segment's integer weight sums into the thread's node densities
+      __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int i = threadIdx.x + k * DEP_THREADS;
-      if (i < R3) {
-        racc[k] += (double)acc[i] * sp.unit;
-        acc[i] = 0ull;
+      for (int k = 0; k < NPT; ++k) {
+        const int i = threadIdx.x + k * DEP_THREADS;
+        if (i < R3) {
+          const uint64_t w =
+              ((uint64_t)((whi[i >> 1] >> ((i & 1) * 16)) & 0xffffu) << 32) | wlo[i];
+          racc[k] += (float)((double)w * sp.unit);
+          wlo[i] = 0u;
+        }
       }
+      if (s1 >= P) break;
+      __syncthreads();
+      for (int i = threadIdx.x; i < (R3 + 1) / 2; i += DEP_THREADS) whi[i] = 0u;
+      __syncthreads();
     }
   }
   const int64_t ng = g.ng;
@@ -178,7 +207,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
                  ((int64_t)ty * 16 + ((threadIdx.x >> 4) & 15)) * ng + (int64_t)tx * 16 +
                  (threadIdx.x & 15);
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) dst[k * ng2] = (float)racc[k];
+    for (int k = 0; k < NPT; ++k) dst[k * ng2] = racc[k];
   } else {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -187,7 +216,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
         int lx = i % R, ly = (i / R) % R, lz = i / (R * R);
         int64_t gx = (int64_t)tx * R + lx, gy = (int64_t)ty * R + ly,
                 gz = (int64_t)tz * R + lz;
-        rho[(gz * ng + gy) * ng + gx] = (float)racc[k];
+        rho[(gz * ng + gy) * ng + gx] = racc[k];
       }
     }
   }
@@ -261,7 +290,7 @@ pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
   if (A.R > 16) return PM_ERR_SHAPE;  // at most 16 nodes per thread
   int nt = (int)(g.nc / A.T);
   const size_t ne = (size_t)(A.T + 1) * (A.T + 1) * (A.T + 1);
-  size_t lds = (size_t)A.R * A.R * A.R * 8 + ne * 8 + (ne + 1) * 4;
+  size_t lds = dep_cst_offset(A.R * A.R * A.R) + ne * 8 + (ne + 1) * 4;
   ProfScope ps(c, ST_DEPOSIT);
   const dim3 grid((unsigned)((int64_t)nt * nt * nt));
   // the compile-time variants assume T r = 16

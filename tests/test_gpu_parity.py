@@ -116,6 +116,47 @@ def test_deposit_compressed(n_p_c, n_mesh):
     assert np.array_equal(rho, rho2)
 
 
+def test_deposit_compressed_dense_cell():
+    """15000 of 20000 particles inside one mesh cell: each of its eight nodes sums
+    thousands of CIC weights, far past 2^32 units of 2^-27 (the integer sums carry)."""
+    rng = np.random.default_rng(41)
+    n_mesh, n_c, n = 32, 8, 20000
+    x = rng.random((n, 3)).astype(np.float32)
+    x[:15000] = (0.3 + rng.uniform(0.0, 1.0 / n_mesh, (15000, 3))).astype(np.float32)
+    v = np.zeros((n, 3), np.float32)
+    x2 = rng.random((3000, 3)).astype(np.float32)
+    c = ctx(n_mesh, n_c)
+    dev = [c.encode(c.float_species(x, v, 1.0 / n)),
+           c.encode(c.float_species(x2, v[:3000], 0.25 / 3000))]
+    rho = c.deposit(dev).cpu().numpy()
+    c.sync()
+    sts = [c.to_host(d) for d in dev]
+    ref = mesh.deposit_species([(codec.decode(sts[0])[0].astype(np.float64), 1.0 / n),
+                                (codec.decode(sts[1])[0].astype(np.float64), 0.25 / 3000)],
+                               n_mesh)
+    assert ref.max() > 2000.0 * ref.mean()
+    assert density_close(rho, ref) <= 1e-5
+    assert np.array_equal(rho, c.deposit(dev).cpu().numpy())
+
+
+def test_deposit_compressed_tile_past_carry_range():
+    """2.2 M particles in one compression cell: more than 2^21 in one deposit tile, so
+    its per-node integer sums are flushed in several segments."""
+    rng = np.random.default_rng(43)
+    n_mesh, n_c, n = 16, 4, 2_300_000
+    x = rng.random((n, 3)).astype(np.float32)
+    x[:2_200_000] = (0.55 + rng.uniform(0.0, 0.2, (2_200_000, 3))).astype(np.float32)
+    v = np.zeros((n, 3), np.float32)
+    c = ctx(n_mesh, n_c)
+    dev = [c.encode(c.float_species(x, v, 1.0 / n))]
+    rho = c.deposit(dev).cpu().numpy()
+    c.sync()
+    h = c.to_host(dev[0])
+    assert int(codec.full_counts(h).max()) >= 2_200_000
+    ref = mesh.deposit_species([(codec.decode(h)[0].astype(np.float64), 1.0 / n)], n_mesh)
+    assert density_close(rho, ref) <= 1e-5
+
+
 def test_deposit_float():
     wl = make_plain()
     c = ctx(wl.n_mesh, wl.n_cell)
