@@ -212,7 +212,7 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
   __shared__ int F[3 * R3];  // one species' sums (fixed point, or float bits)
   __shared__ int64_t cst[NE];
   __shared__ int pre[NE + 1];
-  __shared__ int64_t lw[ST / 64 + 1];
+  __shared__ int wsum[NW];
   __shared__ float wgm[NW];
   __shared__ int wnf[NW];
   const int nt = (int)(g.nc / T);
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
       int loc = 0;
       for (int k = 0; k < K; ++k)
         if (e0 + k <= NE) loc += pre[e0 + k];
-      int base = (int)pmscan::block_excl_scan(loc, lw, nullptr);
+      int base = pmscan::block_excl_scan_i32(loc, wsum);
       for (int k = 0; k < K; ++k)
         if (e0 + k <= NE) {
           base += pre[e0 + k];

@@ -20,8 +20,9 @@
 // run, and the recomputation in the adjoint, gives bit-identical densities.
 //
 // The tile loop is bound by latency (cell offsets, then particle codes, per species),
-// so what pays is tiles in flight: the 26 KB of LDS and 79 VGPRs of a 16^3-node tile
-// let six workgroups share a CU (64-bit sums in LDS and FP64 densities held four).
+// so what pays is tiles in flight: the 26 KB of LDS and 74 VGPRs of a 16^3-node tile
+// let six workgroups share a CU (64-bit sums in LDS and FP64 densities held four), and
+// the prefix over the tile's cells is a DPP wave scan with a single barrier.
 #include "pm_codec.h"
 #include "pm_scan.h"
 
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
   const int E = T + 1;              // extended cells per side
   const int NE = E * E * E;
   const int R3 = R * R * R;
-  __shared__ int64_t lw[DEP_THREADS / 64 + 1];
+  __shared__ int wsum[DEP_THREADS / 64];
   // a node's weight sum is hi 2^32 + lo: lo wraps in the LDS atomics, and each wrap
   // increments a 16-bit carry counter (two per word)
   uint32_t* wlo = (uint32_t*)smem;                    // [R3]
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
       int loc = 0;
       for (int k = 0; k < K; ++k)
         if (e0 + k <= NE) loc += pre[e0 + k];
-      int base = (int)pmscan::block_excl_scan(loc, lw, nullptr);
+      int base = pmscan::block_excl_scan_i32(loc, wsum);
       for (int k = 0; k < K; ++k)
         if (e0 + k <= NE) {
           base += pre[e0 + k];

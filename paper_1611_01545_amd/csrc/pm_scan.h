@@ -53,6 +53,31 @@ __device__ inline int64_t wave_incl_scan(int64_t v) {
   return v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave by DPP: shifts by 1, 2, 4 and 8
+// within each row of 16 lanes, then the last lane of rows 0 and 2 added into rows 1 and
+// 3, then lane 31 added into rows 2 and 3; lanes with no source add 0. Unlike a scan by
+// shuffles it needs no lane-index registers.
+__device__ inline int wave_incl_scan_dpp(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
+// Exclusive scan of 32-bit values over the block's threads with one barrier. wsum:
+// blockDim.x / 64 ints of LDS that the caller leaves alone until its next barrier.
+__device__ inline int block_excl_scan_i32(int v, int* wsum) {
+  const int inc = wave_incl_scan_dpp(v);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  int base = inc - v;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) base += wsum[w];
+  return base;
+}
+
 // Exclusive scan over the block's threads (blockDim.x a multiple of 64, <= 1024).
 __device__ inline int64_t block_excl_scan(int64_t v, int64_t* lds_w, int64_t* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
