@@ -56,9 +56,9 @@ MEASURED_TRAFFIC = {
         "kernel": "k_row_c2r<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "3e08642fdbbbff96ff4a9ad0657fa2aabbcc03d7e624f6102736969a330d806b",
-        "fetch_kib": 2102489.0, "fetch_factor": 1.99988,
-        "write_kib": 4196544.0, "write_factor": 1.0,
+        "sha256": "198c838e56a3d58800c7305d5133ebc18365c777b8b899d995ebdaf5849b4484",
+        "fetch_kib": 2102463.0, "fetch_factor": 1.99988,
+        "write_kib": 4196542.0, "write_factor": 1.0,
     },
 }
 

@@ -263,18 +263,22 @@ __device__ __forceinline__ float grad_k(int k, int n) {
 
 // Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
 // only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
-// inverse y pass). With two outputs the twiddles are staged in LDS (32-bit addresses),
-// which keeps both line arrays in registers without spilling.
+// inverse y pass). OUT 3 (y lines of the transposed force): out0 = +i k_x FFT_SIGN(in) +
+// i k(e) FFT_SIGN(in1), k_x being constant along a y line. With two lines per thread
+// the twiddles are staged in LDS (32-bit addresses), which keeps both line arrays in
+// registers without spilling.
 template <int N, int W, int SIGN, int OUT>
-__global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, float2* out0,
+__global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
+                                                            const float2* in1, float2* out0,
                                                             float2* out1, Lines d,
                                                             const float2* __restrict__ tw,
                                                             int tws, int twmask, int n) {
   using P = Plan<N>;
   constexpr int CS = col_cs<W>(P::E * P::TP);
   __shared__ float lds[W * CS];
-  __shared__ float2 stw[OUT == 2 ? N : 1];
-  if constexpr (OUT == 2) {
+  constexpr bool TWO = OUT == 2 || OUT == 3;
+  __shared__ float2 stw[TWO ? N : 1];
+  if constexpr (TWO) {
     for (int i = threadIdx.x; i < N; i += W * P::T) stw[i] = tw[(i * tws) & twmask];
     __syncthreads();
   }
@@ -296,7 +300,29 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
     }
     out0 = out1;
   }
-  if constexpr (OUT == 2) {
+  if constexpr (OUT == 3) {
+    float2 b[P::E];
+#pragma unroll
+    for (int n1 = 0; n1 < P::E; ++n1) b[n1] = (in1 + (ubase + (int64_t)P::T * n1 * d.es))[lo_in];
+    nat_to_tr<N, SIGN>(a, t, my, stw, 1, N - 1);
+    nat_to_tr<N, SIGN>(b, t, my, stw, 1, N - 1);
+    const float kxg = grad_k(d.kx_mode ? d.kx_fixed : (int)(blockIdx.x * W) + c, n);
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2) {
+        const float kyg = grad_k((t + P::T * v) + P::E * k2, n);
+        const float2 q = a[v * P::T + k2], p = b[v * P::T + k2];
+        // + i (k_x q + k_y p)
+        a[v * P::T + k2] = make_float2(-(kxg * q.y + kyg * p.y), kxg * q.x + kyg * p.x);
+      }
+#pragma unroll
+    for (int v = 0; v < P::V; ++v)
+#pragma unroll
+      for (int k2 = 0; k2 < P::T; ++k2)
+        (out0 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
+            a[v * P::T + k2];
+  } else if constexpr (OUT == 2) {
     float2 b[P::E];
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) {
@@ -332,8 +358,9 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in, fl
 // F = FFT_z(in0) per line, then MODE 0: out0 = IFFT_z(G F); MODE 2: out0 =
 // IFFT_z(-i k_z G F); MODE 3: both, out0 = IFFT_z(G F) and out1 = IFFT_z(-i k_z G F)
 // from one read (the two inverse transforms run one after the other); MODE 1
-// (transpose of the force): out0 = IFFT_z(G sum_a (+i k_a) FFT_z(in_a)). BLK: the lines
-// are z-blocked (main spectrum) or plain strided (Nyquist plane).
+// (transpose of the force): out0 = IFFT_z(G (FFT_z(in0) + i k_z FFT_z(in2))), where in0
+// already holds the x and y terms +i (k_x mu_x + k_y mu_y) from the y pass. BLK: the
+// lines are z-blocked (main spectrum) or plain strided (Nyquist plane).
 template <int N, int W, int MODE, bool BLK>
 __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
     const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
@@ -417,9 +444,8 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   } else {
-    // sum_a (+i k_a) FFT_z(in_a): k_x and k_y are constant along a z line, so their two
-    // terms are one transform of +i (k_x in0 + k_y in1); k_z multiplies after FFT_z(in2)
-    const float kxg = grad_k(kx, n), kyg = grad_k(ky, n);
+    // sum_a (+i k_a) FFT_z(in_a): the x and y terms arrive summed in in0; k_z multiplies
+    // after FFT_z(in2)
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in2 + (ubase + n1 * step))[toff];
     nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
@@ -433,10 +459,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
       }
     float2 f[P::E];
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) {
-      const float2 a = (in0 + (ubase + n1 * step))[toff], b2 = (in1 + (ubase + n1 * step))[toff];
-      f[n1] = make_float2(-(kxg * a.y + kyg * b2.y), kxg * a.x + kyg * b2.x);
-    }
+    for (int n1 = 0; n1 < P::E; ++n1) f[n1] = (in0 + (ubase + n1 * step))[toff];
     nat_to_tr<N, -1>(f, t, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
@@ -652,19 +675,22 @@ struct FftCtx {
 };
 
 // out: 0 plain (o0), 1 only the -i k output (o1), 2 both
+// in1 (forward only): the two-input pass OUT 3 into o0
 template <int N>
-pm_status col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, const Lines& d,
-                  int64_t L2, int sign) {
+pm_status col_fft(const FftCtx& f, const float2* in, const float2* in1, float2* o0, float2* o1,
+                  const Lines& d, int64_t L2, int sign) {
   constexpr int W = col_w<N>();
   if (d.L1 % W) return PM_ERR_SHAPE;
   dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
   dim3 block(W * Plan<N>::T);
-  const int out = o1 ? (o0 ? 2 : 1) : 0;
-#define CLAUNCH(S, O)                                                                     \
-  hipLaunchKernelGGL((k_col_fft<N, W, S, O>), grid, block, 0, f.c->stream, in, o0, o1, d, \
-                     f.c->tw, 1, f.twmask, f.n)
+  const int out = in1 ? 3 : o1 ? (o0 ? 2 : 1) : 0;
+  if (out == 3 && (sign > 0 || o1)) return PM_ERR_ARG;
+#define CLAUNCH(S, O)                                                                 \
+  hipLaunchKernelGGL((k_col_fft<N, W, S, O>), grid, block, 0, f.c->stream, in, in1, o0, \
+                     o1, d, f.c->tw, 1, f.twmask, f.n)
   if (sign < 0) {
-    if (out == 0) CLAUNCH(-1, 0);
+    if (out == 3) CLAUNCH(-1, 3);
+    else if (out == 0) CLAUNCH(-1, 0);
     else if (out == 1) CLAUNCH(-1, 1);
     else CLAUNCH(-1, 2);
   } else {
@@ -733,7 +759,18 @@ pm_status d_col_fft(const FftCtx& f, const float2* in, float2* o0, float2* o1, c
                     int64_t L2, int sign) {
   switch (f.n) {
 #define CASE(N) \
-  case N: return col_fft<N>(f, in, o0, o1, d, L2, sign);
+  case N: return col_fft<N>(f, in, nullptr, o0, o1, d, L2, sign);
+    PM_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return PM_ERR_SHAPE;
+}
+// forward y transform of two spectra into one: o = +i k_x FFT_y(in0) + i k_y FFT_y(in1)
+pm_status d_col_fft_grad2(const FftCtx& f, const float2* in0, const float2* in1, float2* o,
+                          const Lines& d, int64_t L2) {
+  switch (f.n) {
+#define CASE(N) \
+  case N: return col_fft<N>(f, in0, in1, o, nullptr, d, L2, -1);
     PM_FFT_SIZES(CASE)
 #undef CASE
   }
@@ -893,8 +930,10 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
 }
 
 // nu = sum_a IDFT(+i k_a G DFT(mu_a)) with mu_a in A0..A2 (destroyed); nu lands in A0.
-//   r2c   mu_z: A2 -> S;  mu_y: A1 -> A2;  mu_x: A0 -> A1   (each followed by Y)
-//   Z     (A1, A2, S) -> A1;   Y^-1 A1;   c2r A1 -> A0
+//   r2c   mu_z: A2 -> S;  mu_y: A1 -> A2;  mu_x: A0 -> A1
+//   Y     S in place;  +i (k_x Y(A1) + k_y Y(A2)) -> A1 (one pass, k_x is constant along
+//         a y line, so the x and y terms need one stored spectrum instead of two)
+//   Z     (A1, S) -> A1;   Y^-1 A1;   c2r A1 -> A0
 pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
   const int n = (int)c->g.ng;
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
@@ -907,15 +946,16 @@ pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
   const Lines ym = lines_y_main(n), yn = lines_y_nyq(n);
   const Lines zm = lines_z_main(n), zn = lines_z_nyq(n);
   float2* spec[3] = {A[1], A[2], S};  // spectrum of mu_x, mu_y, mu_z
-  for (int ax = 2; ax >= 0; --ax) {
+  for (int ax = 2; ax >= 0; --ax)
     if ((s = d_row_r2c(f, (const float*)A[ax], spec[ax], Nq[ax])) != PM_OK) return s;
-    if ((s = d_col_fft(f, spec[ax], spec[ax], nullptr, ym, n, -1)) != PM_OK) return s;
-    if ((s = d_col_fft(f, Nq[ax], Nq[ax], nullptr, yn, 1, -1)) != PM_OK) return s;
-  }
-  if ((s = d_col_zconv(f, 1, true, spec[0], spec[1], spec[2], spec[0], nullptr, zm, n)) !=
+  if ((s = d_col_fft(f, spec[2], spec[2], nullptr, ym, n, -1)) != PM_OK) return s;
+  if ((s = d_col_fft(f, Nq[2], Nq[2], nullptr, yn, 1, -1)) != PM_OK) return s;
+  if ((s = d_col_fft_grad2(f, spec[0], spec[1], spec[0], ym, n)) != PM_OK) return s;
+  if ((s = d_col_fft_grad2(f, Nq[0], Nq[1], Nq[0], yn, 1)) != PM_OK) return s;
+  if ((s = d_col_zconv(f, 1, true, spec[0], nullptr, spec[2], spec[0], nullptr, zm, n)) !=
       PM_OK)
     return s;
-  if ((s = d_col_zconv(f, 1, false, Nq[0], Nq[1], Nq[2], Nq[0], nullptr, zn, 1)) != PM_OK)
+  if ((s = d_col_zconv(f, 1, false, Nq[0], nullptr, Nq[2], Nq[0], nullptr, zn, 1)) != PM_OK)
     return s;
   if ((s = d_col_fft(f, spec[0], spec[0], nullptr, ym, n, +1)) != PM_OK) return s;
   if ((s = d_col_fft(f, Nq[0], Nq[0], nullptr, yn, 1, +1)) != PM_OK) return s;
