@@ -56,9 +56,9 @@ MEASURED_TRAFFIC = {
         "kernel": "k_row_c2r<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "198c838e56a3d58800c7305d5133ebc18365c777b8b899d995ebdaf5849b4484",
-        "fetch_kib": 2102463.0, "fetch_factor": 1.99988,
-        "write_kib": 4196542.0, "write_factor": 1.0,
+        "sha256": "b4c65a62e4abf37a64be1ac3a81a194d3b65c53b2a438f4e666e0963fe4c84fc",
+        "fetch_kib": 2101697.0, "fetch_factor": 1.99988,
+        "write_kib": 4196763.0, "write_factor": 1.0,
     },
 }
 

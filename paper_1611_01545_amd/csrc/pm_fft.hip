@@ -487,32 +487,29 @@ __device__ __forceinline__ int64_t spec_row(int64_t row) {
   const int64_t z = row >> LN, y = row & (n - 1);
   return (((z >> LZB) << LN) + y) * ((int64_t)ZB * M) + (z & (ZB - 1)) * M;
 }
-template <int M>
-constexpr int row_lds_floats() {
-  using P = Plan<M>;
-  int ex = P::E * P::TP;    // exchange buffer (floats)
-  int st = 2 * (M + 1);     // complex staging of the row
-  return ex > st ? ex : st;
-}
-// rows per workgroup: up to 256 threads and about 80 KB of LDS (two groups per CU)
+// rows per workgroup of the row passes: up to 256 threads, and LDS for the FFT exchange
+// only (the pairing of k with M - k goes through lane shuffles)
 template <int M>
 constexpr int rows_per_wg() {
   constexpr int T = Plan<M>::T;
   int r = 256 / T;
   if (r > 16) r = 16;
-  int lim = 20480 / row_lds_floats<M>();
+  int lim = 20480 / (Plan<M>::E * Plan<M>::TP);
   if (r > lim) r = lim;
   return r < 1 ? 1 : r;
 }
 
-// X r2c: in real rows (nrows x n floats) -> out main rows (M complex) + nyq[row].
+// X r2c: in real rows (nrows x n floats) -> out main rows (M complex) + nyq[row]. The
+// spectrum is written in the transposed order the FFT leaves it in (runs of T complex),
+// and the post-process pairs Z[k] with Z[M - k] by lane shuffles, so that the LDS holds
+// only the FFT exchange.
 template <int M>
 __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
     const float* in, float2* out, float2* nyq, int64_t nrows, const float2* __restrict__ tw,
     int twmask) {
   using P = Plan<M>;
   constexpr int R = rows_per_wg<M>();
-  constexpr int LF = row_lds_floats<M>();
+  constexpr int LF = P::E * P::TP;
   __shared__ float lds[R * LF];
   // R divides the row count (checked on the host): no bounds guards
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
@@ -524,29 +521,32 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
   for (int n1 = 0; n1 < P::E; ++n1) a[n1] = zin[t + P::T * n1];
   // M-point DFT: tw table is for n = 2M points, stride 2
   nat_to_tr<M, -1>(a, t, my, tw, 2, twmask);
-  // stage Z in natural order
-  float2* zs = (float2*)my;
+  // a[v T + k2] = Z[k], k = (t + T v) + E k2. Z[M - k] is held by lane (T - t) of the
+  // row's lane group at index (V - 1 - v) T + (T - 1 - k2); lane t = 0 holds it itself,
+  // at index (V - v) T + (T - 1 - k2) for v >= 1 and (T - k2) mod T for v = 0 (Z[M] =
+  // Z[0]).
+  const int src = ((int)(threadIdx.x & 63) & ~(P::T - 1)) | ((P::T - t) & (P::T - 1));
+  float2* o = out + spec_row<M>(row);
+  const float2 z0 = a[0];
 #pragma unroll
   for (int v = 0; v < P::V; ++v)
 #pragma unroll
-    for (int k2 = 0; k2 < P::T; ++k2) zs[(t + P::T * v) + P::E * k2] = a[v * P::T + k2];
-  __syncthreads();
-  float2* o = out + spec_row<M>(row);
-#pragma unroll
-  for (int j = 0; j < P::E; ++j) {
-    const int k = t + P::T * j;
-    float2 zk = zs[k];
-    float2 zm = zs[(M - k) & (M - 1)];  // Z[M - k], Z[M] = Z[0]
-    // A = (Z[k] + conj Z[M-k]) / 2, B = -i (Z[k] - conj Z[M-k]) / 2, X = A + W^k B
-    float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    float2 w = tw[k];
-    float2 wb = cmul(w, B);
-    float2 X = make_float2(A.x + wb.x, A.y + wb.y);
-    if (k == 0) X = make_float2(zk.x + zk.y, 0.f);
-    o[k] = X;
-  }
-  if (t == 0) nyq[row] = make_float2(zs[0].x - zs[0].y, 0.f);
+    for (int k2 = 0; k2 < P::T; ++k2) {
+      const int k = (t + P::T * v) + P::E * k2;
+      const float2 zk = a[v * P::T + k2];
+      const int ip = (P::V - 1 - v) * P::T + (P::T - 1 - k2);
+      float2 zm = make_float2(__shfl(a[ip].x, src, 64), __shfl(a[ip].y, src, 64));
+      if (t == 0) zm = v == 0 ? a[(P::T - k2) % P::T] : a[(P::V - v) * P::T + (P::T - 1 - k2)];
+      // A = (Z[k] + conj Z[M-k]) / 2, B = -i (Z[k] - conj Z[M-k]) / 2, X = A + W^k B
+      float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+      float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+      float2 w = tw[k];
+      float2 wb = cmul(w, B);
+      float2 X = make_float2(A.x + wb.x, A.y + wb.y);
+      if (k == 0) X = make_float2(zk.x + zk.y, 0.f);
+      o[k] = X;
+    }
+  if (t == 0) nyq[row] = make_float2(z0.x - z0.y, 0.f);
 }
 
 // X c2r: in main rows (M complex) + nyq[row] -> out real rows; optional -i k_x factor;
@@ -557,14 +557,14 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
     const float2* __restrict__ tw, int twmask, unsigned int* amax) {
   using P = Plan<M>;
   constexpr int R = rows_per_wg<M>();
-  constexpr int LF = row_lds_floats<M>();
+  constexpr int LF = P::E * P::TP;
   __shared__ float lds[R * LF];
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
   const int64_t row = (int64_t)blockIdx.x * R + rr;
   float* my = lds + rr * LF;
-  float2* xs = (float2*)my;
   const float2* xi = in + spec_row<M>(row);
   const int n = 2 * M;
+  float2 xr[P::E];
 #pragma unroll
   for (int j = 0; j < P::E; ++j) {
     const int k = t + P::T * j;
@@ -573,25 +573,28 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
       float kk = grad_k(k, n);
       X = make_float2(kk * X.y, -kk * X.x);
     }
-    xs[k] = X;
+    xr[j] = X;
   }
-  if (t == 0) {
-    const float2 X = nyq[row];
-    xs[M] = grad ? make_float2(0.f, 0.f) : X;  // -i k_x is zero on the Nyquist index
-  }
-  __syncthreads();
+  float2 xn = make_float2(0.f, 0.f);  // X[M], held by lane t = 0
+  if (t == 0 && !grad) xn = nyq[row];  // -i k_x is zero on the Nyquist index
+  // X[M - k] for k = t + T j: lane (T - t) of the row's lane group holds it at index
+  // E - 1 - j; lane t = 0 holds it itself, at index E - j (X[M] for j = 0). The row's T
+  // lanes are consecutive and T divides 64, so the partner is in the same wave.
+  const int src = ((int)(threadIdx.x & 63) & ~(P::T - 1)) | ((P::T - t) & (P::T - 1));
   float2 a[P::E];
 #pragma unroll
   for (int n1 = 0; n1 < P::E; ++n1) {
     const int k = t + P::T * n1;
-    float2 xk = xs[k], xm = xs[M - k];
+    const float2 xk = xr[n1];
+    float2 xm = make_float2(__shfl(xr[P::E - 1 - n1].x, src, 64),
+                            __shfl(xr[P::E - 1 - n1].y, src, 64));
+    if (t == 0) xm = n1 == 0 ? xn : xr[(P::E - n1) % P::E];
     // Z = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k])
     float2 s = make_float2(xk.x + xm.x, xk.y - xm.y);
     float2 dd = make_float2(xk.x - xm.x, xk.y + xm.y);
     float2 wd = cmulc(dd, tw[k]);  // W^{-k} d
     a[n1] = make_float2(s.x - wd.y, s.y + wd.x);
   }
-  __syncthreads();
   nat_to_tr<M, +1>(a, t, my, tw, 2, twmask);
   float2* zo = (float2*)(out + row * 2 * M);
   float m = 0.f;
