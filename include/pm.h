@@ -145,8 +145,10 @@ pm_status pm_decode(pm_ctx ctx, const pm_species* in, pm_species* out);
 
 /* CIC mass density rho(c) = Delta^-3 sum_s m_s sum_i W(x_i - x_c) of all species
  * (Sec. 2.1 footnote: both species on the same mesh). rho: device float [n_mesh^3].
- * Species must all be PM_FLOAT or all PM_COMPRESSED. Deterministic: contributions are
- * summed in 64-bit fixed point. */
+ * Species must all be PM_FLOAT or all PM_COMPRESSED. Deterministic: PM_COMPRESSED
+ * sums each species' exact CIC weights as integers per node, scales each sum by the
+ * species' mass in FP64, rounds it to float and adds the species in a fixed order;
+ * PM_FLOAT sums all contributions in 64-bit fixed point. */
 pm_status pm_deposit(pm_ctx ctx, const pm_species* sp, int n_sp, float* rho);
 
 /* Accelerations a_a(c) from a density mesh, eqs. (2)-(3): a = IDFT(-i k G(k) DFT(rho))
