@@ -48,9 +48,9 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "8bcbfa068df5b937d5de6a465f98c7a2c51f2666e916c09b1e895dd88794c43d",
-        "fetch_kib": 9098421.38, "fetch_factor": 1.99988,
-        "write_kib": 2166335.78, "write_factor": 1.0,
+        "sha256": "226adfbfc05135631ee9a2065c35fcca6162e63a013f434ef30cf5d5221d291d",
+        "fetch_kib": 8189285.19, "fetch_factor": 1.99988,
+        "write_kib": 2200201.31, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
         "kernel": "k_row_c2r<512>",

@@ -419,10 +419,12 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
 // ---- two bricks adjacent along x per workgroup, R = 16, in NZ passes over z ----
 // Pass h stages the force nodes x in [x0, x0 + 2R], y in [y0, y0 + R], z in
 // [z0 + h R/NZ, z0 + (h + 1) R/NZ] (33 x 17 x 5 nodes for NZ = 4) and kicks the
-// particles of both bricks' cells in that z slice (whole cell layers). Rows of the
-// staged tile are 2R nodes long, which the memory system serves much faster than rows
-// of R; with NZ = 4 and 256 threads the tile is 34 KB and four workgroups share a CU,
-// each staging while the others compute.
+// particles of both bricks' cells in that z slice (whole cell layers). Consecutive
+// passes share a node layer, which stays in LDS: the layers form a ring, and passes
+// after the first stage only their R/NZ new layers. Rows of the staged tile are 2R
+// nodes long, which the memory system serves much faster than rows of R; with NZ = 4
+// and 256 threads the tile is 34 KB and four workgroups share a CU, each staging while
+// the others compute.
 constexpr int PR = 16;
 template <int NT, int NZ>  // threads per workgroup, z passes
 __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
@@ -466,18 +468,25 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
   const bool fast = codec_fast(A);
   bool bad = false;
 
-  auto stage = [&](int h) {
+  // The z passes share their boundary layer: pass h needs node layers 4h..4h+4 (for
+  // PR / NZ = 4), pass h + 1 starts at 4h + 4. F holds the Z1 layers as a ring, layer
+  // 4h + lz in slot (4h + lz) mod Z1, so that pass 0 stages Z1 layers and every later
+  // pass only the Z1 - 1 new ones.
+  auto stage = [&](int h, auto nl_tag) {
+    constexpr int NL = decltype(nl_tag)::value;  // layers loaded: Z1, or Z1 - 1
+    constexpr int LZ0 = Z1 - NL;                  // first local layer loaded
     constexpr int Q = 2 * PR / 4;
-    constexpr int ROWS = 3 * Z1 * Y1;
+    constexpr int ROWS = 3 * NL * Y1;
     constexpr int NQ = ROWS * Q;
     constexpr int PQ = (NQ + KB - 1) / KB;
     constexpr int PH = (ROWS + KB - 1) / KB;
-    constexpr int RR = Z1 * Y1;
+    constexpr int RR = NL * Y1;
     constexpr int DR = KB / Q;
     constexpr int DC = DR / RR, DLZ = (DR % RR) / Y1, DLY = DR % Y1;
     static_assert(KB % Q == 0, "a workgroup covers whole rows");
     const uint32_t mu = (uint32_t)(ng - 1), ngu = (uint32_t)ng;
-    const uint32_t oz2 = (uint32_t)oz + h * (PR / NZ);
+    const uint32_t oz2 = (uint32_t)oz + h * (PR / NZ) + LZ0;
+    const int hb = (h * (PR / NZ) + LZ0) % Z1;  // slot of the first loaded layer
     const uint32_t oxq = (uint32_t)ox + 4 * (threadIdx.x % Q);
     const uint32_t hx = ((uint32_t)ox + 2 * PR) & mu;
     const float* pc0 = A.acc;
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
 #pragma unroll
       for (int k = 0; k < PQ; ++k) {
         const bool over = c >= 3;
-        const int cc = over ? 2 : c, zz = over ? Z1 - 1 : lz, yy = over ? Y1 - 1 : ly;
+        const int cc = over ? 2 : c, zz = over ? NL - 1 : lz, yy = over ? Y1 - 1 : ly;
         const float* pc = cc == 0 ? pc0 : (cc == 1 ? pc1 : pc2);
         const uint32_t gz = (oz2 + zz) & mu, gy = ((uint32_t)oy + yy) & mu;
         vq[k] = *(const float4*)(pc + ((uint64_t)(gz * ngu + gy) * ngu + oxq));
@@ -499,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
         lz += DLZ;
         c += DC;
         if (ly >= Y1) { ly -= Y1; ++lz; }
-        if (lz >= Z1) { lz -= Z1; ++c; }
+        if (lz >= NL) { lz -= NL; ++c; }
       }
     }
 #pragma unroll
@@ -511,14 +520,16 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
       const uint32_t gz = (oz2 + lz) & mu, gy = ((uint32_t)oy + ly) & mu;
       vh[k] = pc[(uint64_t)(gz * ngu + gy) * ngu + hx];
     }
-    __syncthreads();  // the previous pass is done with F
+    __syncthreads();  // the previous pass is done with the slots rewritten here
     {
       int c = row0 / RR, lz = (row0 % RR) / Y1, ly = row0 % Y1;
       const int q4 = 4 * (threadIdx.x % Q);
 #pragma unroll
       for (int k = 0; k < PQ; ++k) {
         if (c < 3) {
-          float* d = F + ((c * Z1 + lz) * Y1 + ly) * X1 + q4;
+          int sl = hb + lz;
+          sl -= sl >= Z1 ? Z1 : 0;
+          float* d = F + ((c * Z1 + sl) * Y1 + ly) * X1 + q4;
           d[0] = vq[k].x;
           d[1] = vq[k].y;
           d[2] = vq[k].z;
@@ -528,13 +539,19 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
         lz += DLZ;
         c += DC;
         if (ly >= Y1) { ly -= Y1; ++lz; }
-        if (lz >= Z1) { lz -= Z1; ++c; }
+        if (lz >= NL) { lz -= NL; ++c; }
       }
     }
 #pragma unroll
     for (int k = 0; k < PH; ++k) {
       const int row = threadIdx.x + k * KB;
-      if (row < ROWS) F[row * X1 + 2 * PR] = vh[k];
+      if (row < ROWS) {
+        const int c = row / RR, rem = row - c * RR;
+        const int lz = rem / Y1, ly = rem - lz * Y1;
+        int sl = hb + lz;
+        sl -= sl >= Z1 ? Z1 : 0;
+        F[((c * Z1 + sl) * Y1 + ly) * X1 + 2 * PR] = vh[k];
+      }
     }
     __syncthreads();
   };
@@ -546,7 +563,11 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
       uint32_t bc[3];
       key_cell(g, kb0 + (uint32_t)(k * B3), bc[0], bc[1], bc[2]);
       auto gather = [&](const int li[3], const float f[3], float acc3[3]) {
-        const int tx = li[0] + k * PR, ty = li[1], tz = li[2] - h * (PR / NZ);
+        const int tx = li[0] + k * PR, ty = li[1];
+        // ring slots of the node layers tz and tz + 1 (local to this pass)
+        int z0 = li[2] - h * (PR / NZ) + (h * (PR / NZ)) % Z1;
+        z0 -= z0 >= Z1 ? Z1 : 0;
+        const int z1 = z0 + 1 == Z1 ? 0 : z0 + 1;
         acc3[0] = acc3[1] = acc3[2] = 0.f;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
@@ -556,7 +577,7 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
             for (int dx = 0; dx < 2; ++dx) {
               const float wgt = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
                                 (dz ? f[2] : 1.f - f[2]);
-              const int node = ((tz + dz) * Y1 + (ty + dy)) * X1 + (tx + dx);
+              const int node = ((dz ? z1 : z0) * Y1 + (ty + dy)) * X1 + (tx + dx);
               acc3[0] += wgt * F[node];
               acc3[1] += wgt * F[TS + node];
               acc3[2] += wgt * F[2 * TS + node];
@@ -580,8 +601,12 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
       }
     }
   };
-  for (int h = 0; h < NZ; ++h) {
-    stage(h);
+  stage(0, std::integral_constant<int, Z1>{});
+  if (fast) pass(std::true_type{}, 0);
+  else pass(std::false_type{}, 0);
+#pragma nounroll
+  for (int h = 1; h < NZ; ++h) {
+    stage(h, std::integral_constant<int, Z1 - 1>{});
     if (fast) pass(std::true_type{}, h);
     else pass(std::false_type{}, h);
   }
