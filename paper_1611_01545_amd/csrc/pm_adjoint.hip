@@ -54,18 +54,18 @@ __device__ __forceinline__ int64_t cic_node(const Cic& q, int dx, int dy, int dz
 }
 
 // g_v = lv1 + c_d lx1 into lv0 (old order), lx0 = lx1 (old order). perm: new -> old.
+// One thread per component, so that the loads are contiguous across the wave.
 __global__ __launch_bounds__(AT) void k_vjp_init(const float* lx1, const float* lv1,
                                                  const int64_t* perm, int64_t n, float cd,
                                                  float* lx0, float* lv0) {
-  const int64_t j = (int64_t)blockIdx.x * AT + threadIdx.x;
-  if (j >= n) return;
+  const int64_t i = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (i >= 3 * n) return;
+  const int64_t j = i / 3;
   const int64_t o = perm ? perm[j] : j;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float lx = lx1[3 * j + a];
-    lv0[3 * o + a] = lv1[3 * j + a] + cd * lx;
-    lx0[3 * o + a] = lx;
-  }
+  const int64_t d = 3 * o + (i - 3 * j);
+  const float lx = lx1[i];
+  lv0[d] = lv1[i] + cd * lx;
+  lx0[d] = lx;
 }
 
 // mu_a(c) += W(x_j - x_c) c_k g_v,ja for the three components.
@@ -651,8 +651,8 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
     for (int i = 0; i < n_sp; ++i) {
       if (in[i].n == 0) continue;
       const unsigned nb = (unsigned)cdiv(in[i].n, AT);
-      hipLaunchKernelGGL(k_vjp_init, dim3(nb), dim3(AT), 0, c->stream, lx1[i], lv1[i],
-                         perm[i], in[i].n, cd, lx0[i], lv0[i]);
+      hipLaunchKernelGGL(k_vjp_init, dim3((unsigned)cdiv(3 * in[i].n, AT)), dim3(AT), 0,
+                         c->stream, lx1[i], lv1[i], perm[i], in[i].n, cd, lx0[i], lv0[i]);
       if (!tiled)
         hipLaunchKernelGGL(k_scatter_vec, dim3(nb), dim3(AT), 0, c->stream, P.x[i], lv0[i],
                            in[i].n, ng, ck, mu);
