@@ -18,11 +18,14 @@
 //   movers          compacted in old order (ballots over the digits, one wave per
 //                   brick), stably radix-sorted by new cell.
 //   k_arrivals      per new cell: arrivals, and how many of them come from earlier
-//                   bricks (they precede the cell's stayers in stream order).
+//                   bricks (they precede the cell's stayers in stream order);
+//   k_brick_arrivals  per brick, its run of the sorted movers (its arrivals).
 //   scan            new cell offsets.
-//   k_place_*       stayers and movers written at their final stream positions: per
-//                   brick (one wave), the stayers' first position in each new cell staged
-//                   in LDS and their stable rank from a multi-split of the digits.
+//   k_place_stayers stayers and arrivals written at their final stream positions, per
+//                   brick by one wave: the stayers' first position in each new cell
+//                   staged in LDS and their stable rank from a multi-split of the
+//                   digits, then the brick's arrivals, so that one wave writes all of the
+//                   brick's output range.
 #include <type_traits>
 
 #include "pm_codec.h"
@@ -633,6 +636,15 @@ __device__ inline int64_t lower_bound_u32(const uint32_t* a, int64_t lo, int64_t
   return lo;
 }
 
+// astart[b] = first sorted mover whose new cell lies in brick b or later, b in [0, nbrick]:
+// the arrivals of brick b are the sorted movers [astart[b], astart[b + 1]).
+__global__ __launch_bounds__(KT) void k_brick_arrivals(const uint32_t* skey, int64_t nm, int B3,
+                                                      int64_t nbrick, int64_t* astart) {
+  const int64_t b = (int64_t)blockIdx.x * KT + threadIdx.x;
+  if (b > nbrick) return;
+  astart[b] = lower_bound_u32(skey, 0, nm, (uint32_t)(b * B3));
+}
+
 // per group of sorted movers with the same new cell: add arrivals (low 32 bits) and
 // arrivals from earlier bricks (high 32 bits) to the cell's count
 __global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uint32_t* sidx,
@@ -693,6 +705,7 @@ __global__ __launch_bounds__(64 * WB) void k_compact_movers(
 __global__ __launch_bounds__(64 * WB) void k_place_stayers(
     const int64_t* off_in, const uint16_t* tdig, const uint8_t* tpos, const uint16_t* tvel,
     const uint64_t* cnt, const int64_t* off_new, int B3, int nbits, int64_t nbrick,
+    const uint32_t* skey, const uint32_t* sidx, const int64_t* astart,
     uint8_t* pos, uint16_t* vel, int64_t* perm, int64_t n, DevErr* err) {
   extern __shared__ int64_t lds[];  // dbase [WB][B3], then run [WB][B3] (uint32)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -759,36 +772,33 @@ __global__ __launch_bounds__(64 * WB) void k_place_stayers(
       }
     }
   }
-}
-
-__global__ __launch_bounds__(KT) void k_place_movers(const uint32_t* skey, const uint32_t* sidx,
-                                                    int64_t nm, const uint8_t* tpos,
-                                                    const uint16_t* tvel, const uint64_t* cnt,
-                                                    const int64_t* off_new, uint8_t* pos,
-                                                    uint16_t* vel, int64_t* perm, int64_t n,
-                                                    DevErr* err) {
-  int64_t s = (int64_t)blockIdx.x * KT + threadIdx.x;
-  if (s >= nm) return;
-  const uint32_t k = skey[s];
-  const int64_t gs = lower_bound_u32(skey, 0, s, k);
-  const int64_t ge = lower_bound_u32(skey, s, nm, k + 1);
-  const uint64_t cv = cnt[k];
-  const int64_t before = (int64_t)(cv >> 32), total = (int64_t)(cv & 0xffffffffull);
-  const int64_t stay = total - (ge - gs);
-  const int64_t jg = s - gs;
-  const int64_t dst = off_new[k] + (jg < before ? jg : stay + jg);
-  const int64_t j = sidx[s];
-  if (dst < 0 || dst >= n || j >= n) {
-    latch_error(err, ERRBIT_CORRUPT);
-    return;
+  // the brick's arrivals, placed by the same wave so that every line of the brick's
+  // output range is written by one wave: arrivals from earlier bricks precede the
+  // stayers of their new cell, the others follow them
+  if (astart) {
+    const int64_t ms = astart[b], me = astart[b + 1];
+    for (int64_t s = ms + lane; s < me; s += 64) {
+      const uint32_t k = skey[s];
+      const int64_t gs = lower_bound_u32(skey, ms, s, k);
+      const int64_t ge = lower_bound_u32(skey, s, me, k + 1);
+      const uint64_t cv = cnt[k];
+      const int64_t before = (int64_t)(cv >> 32), total = (int64_t)(cv & 0xffffffffull);
+      const int64_t stay = total - (ge - gs);
+      const int64_t jg = s - gs;
+      const int64_t dst = off_new[k] + (jg < before ? jg : stay + jg);
+      const int64_t j = sidx[s];
+      if (dst < 0 || dst >= n || j < 0 || j >= n) {
+        latch_error(err, ERRBIT_CORRUPT);
+        continue;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pos[3 * dst + a] = tpos[3 * j + a];
+        vel[3 * dst + a] = tvel[3 * j + a];
+      }
+      if (perm) perm[dst] = j;
+    }
   }
-  pos[3 * dst] = tpos[3 * j];
-  pos[3 * dst + 1] = tpos[3 * j + 1];
-  pos[3 * dst + 2] = tpos[3 * j + 2];
-  vel[3 * dst] = tvel[3 * j];
-  vel[3 * dst + 1] = tvel[3 * j + 1];
-  vel[3 * dst + 2] = tvel[3 * j + 2];
-  if (perm) perm[dst] = j;
 }
 
 __global__ void k_read_total(const int64_t* moff, int64_t nb, int64_t* out) { *out = moff[nb]; }
@@ -917,20 +927,19 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
       hipLaunchKernelGGL(k_arrivals, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream, sk,
                          si, nm, S.off, B3, S.cnt);
       PM_LAUNCH_CHECK();
+      // the mover offsets are spent: moff now takes each brick's run of arrivals
+      hipLaunchKernelGGL(k_brick_arrivals, dim3((unsigned)cdiv(g.nbrick + 1, KT)), dim3(KT), 0,
+                         c->stream, sk, nm, B3, g.nbrick, moff);
+      PM_LAUNCH_CHECK();
     }
     st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
     hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)cdiv(g.nbrick, WB)), dim3(64 * WB),
                        place_lds, c->stream, S.off, S.tdig, S.tpos, S.tvel, S.cnt, off_new,
-                       B3, 3 * g.lgB, g.nbrick, out[s].pos, out[s].vel, pm, n, c->err);
+                       B3, 3 * g.lgB, g.nbrick, sk, si, nm > 0 ? moff : nullptr, out[s].pos,
+                       out[s].vel, pm, n, c->err);
     PM_LAUNCH_CHECK();
-    if (nm > 0) {
-      hipLaunchKernelGGL(k_place_movers, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream,
-                         sk, si, nm, S.tpos, S.tvel, S.cnt, off_new, out[s].pos, out[s].vel,
-                         pm, n, c->err);
-      PM_LAUNCH_CHECK();
-    }
     st = run_finalize_counts(c, nullptr, S.cnt, &out[s]);
     if (st != PM_OK) return st;
   }
