@@ -48,9 +48,9 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "3593042f4a9336ffc4faf6cf9e27d1ad12a209084cd106efd07549670b5f5853",
-        "fetch_kib": 8204505.69, "fetch_factor": 1.99988,
-        "write_kib": 2200204.28, "write_factor": 1.0,
+        "sha256": "1dc0117ead72af659fd28f6f6dc1cfa1f50eabd20de7c5455a87155bccba33e1",
+        "fetch_kib": 8164916.25, "fetch_factor": 1.99988,
+        "write_kib": 2200561.28, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
         "kernel": "k_row_c2r<512>",

@@ -664,7 +664,7 @@ __global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uin
 // take its particles in chunks of 64, PU chunks' loads issued together; ranks come from
 // ballots and a running count per wave, so no kernel has a barrier.
 constexpr int WB = 4;
-constexpr int PU = 8;
+constexpr int PU = 4;
 
 // Movers of brick b, in old stream order, to [moff[b], moff[b] + mcnt[b]).
 __global__ __launch_bounds__(64 * WB) void k_compact_movers(
