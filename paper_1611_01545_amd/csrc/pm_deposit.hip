@@ -113,7 +113,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
     __syncthreads();
     const int P = pre[NE];
     // U particles per thread per round: their code loads are issued together
-    constexpr int U = 4;
+    constexpr int U = 2;
     // the carries count at most 2^16 wraps, i.e. 2^48 weight units per node: segments
     // of 2^21 particles (each adds < 2^27 to a node) are flushed one by one; every
     // tile of a realistic input has a single segment
