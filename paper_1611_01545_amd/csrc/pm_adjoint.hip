@@ -177,7 +177,7 @@ __global__ void k_zero_f32(float* p, int64_t n) {
 // particles' compressed codes directly (cell-sorted streams), like the deposit and the
 // kick: exact CIC weights from the codes, no decoded positions in HBM.
 constexpr int MAXSP = 4;
-constexpr int ST = 256;  // scatter threads per workgroup
+constexpr int ST = 512;  // scatter threads per workgroup
 
 struct AdjSpecies {
   int64_t n;
@@ -383,14 +383,15 @@ __global__ __launch_bounds__(ST) void k_scatter_tile(AdjArgs A, Geom g, float* m
         F[i] = 0;
       }
   }
-  // node i = threadIdx.x + 256 k: lx = i & 15, ly = (i >> 4) & 15, lz = k
+  // node i = threadIdx.x + ST k: lx = i & 15, ly = (i >> 4) & 15, lz = i >> 8
   const int64_t ng = g.ng, ng2 = ng * ng, n3 = ng2 * ng;
-  float* dst = mu + (int64_t)tz * 16 * ng2 + ((int64_t)ty * 16 + ((threadIdx.x >> 4) & 15)) * ng +
-               (int64_t)tx * 16 + (threadIdx.x & 15);
+  float* dst = mu + ((int64_t)tz * 16 + (threadIdx.x >> 8)) * ng2 +
+               ((int64_t)ty * 16 + ((threadIdx.x >> 4) & 15)) * ng + (int64_t)tx * 16 +
+               (threadIdx.x & 15);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) dst[c * n3 + k * ng2] = A.ck * racc[c][k];
+    for (int k = 0; k < NPT; ++k) dst[c * n3 + k * (ST / 256) * ng2] = A.ck * racc[c][k];
 }
 
 // Gradient gather on bricks of B^3 cells = 16^3 nodes: the four meshes a_x, a_y, a_z
