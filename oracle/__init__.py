@@ -19,7 +19,8 @@ design notes):
     node-centred;
   * forward DFT unnormalised with exp(-2 pi i n.c / n), inverse with 1/n^3;
   * Poisson kernel with Plummer softening eps = soft_cells * Delta, zero at k = 0;
-  * spectral gradient -i k_a with k_a := 0 on the Nyquist index.
+  * gradient factor -i D(k_a), the fourth-order central-difference symbol (zero on
+    the Nyquist index).
 
 Parity status of each function is stated in its module docstring.
 """

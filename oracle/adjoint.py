@@ -8,9 +8,9 @@ lambda_v' = dL/dv' the adjoint returns dL/dx and dL/dv:
              + sum_c grad W(x_i - x_c) [sum_a a_a(c) g_a,ia]           (direct term)
              + m_i Delta^-3 sum_c grad W(x_i - x_c) nu(c)               (through rho)
 with mu_a(c) = sum_j W(x_j - x_c) g_a,ja (the transpose of the force interpolation is
-a scatter) and nu = sum_a IDFT(+i k_a G(k) DFT(mu_a)): the force operator a_a = K_a rho
+a scatter) and nu = sum_a IDFT(+i D(k_a) G(k) DFT(mu_a)): the force operator a_a = K_a rho
 is a real odd convolution, so its transpose is K_a^T = -K_a, i.e. the conjugate of
-the spectral multiplier (the Nyquist index stays zeroed). The transpose of the CIC
+the spectral multiplier (D is odd and zero on the Nyquist index). The transpose of the CIC
 deposit is the CIC gather scaled by Delta^-3 and the particle mass.
 
 For compressed particles the quantisation of positions and velocities is treated as
@@ -34,7 +34,7 @@ from . import codec, mesh
 
 def force_transpose(mu: np.ndarray, soft_cells: float = 1.0,
                     G: float = 1.0 / mesh.FOUR_PI) -> np.ndarray:
-    """nu = sum_a K_a^T mu_a with K_a^T = IDFT(conj(-i k_a G) DFT(.))."""
+    """nu = sum_a K_a^T mu_a with K_a^T = IDFT(conj(-i D(k_a) G) DFT(.))."""
     n_g = mu.shape[1]
     g = mesh.green(n_g, soft_cells, G)
     acc_k = np.zeros((n_g, n_g, n_g // 2 + 1), dtype=np.complex128)

@@ -144,3 +144,107 @@ def test_multistep_density_loss_gradient():
                     assert abs(fd - an) <= 1e-4 * (abs(an) + 1e-3 * abs(loss)), (fd, an)
                     checked += 1
     assert checked > 20
+
+
+# ------------------------------------------------ compressed adjoint: routing --
+
+def _brick_key(cell, n_c, brick):
+    """Stream key of a cell written out by hand: bricks x-fastest, cells x-fastest
+    inside a brick."""
+    nb = n_c // brick
+    cx, cy, cz = (int(c) for c in cell)
+    b = ((cz // brick) * nb + cy // brick) * nb + cx // brick
+    local = ((cz % brick) * brick + cy % brick) * brick + cx % brick
+    return b * brick ** 3 + local
+
+
+def _stable_order(keys):
+    """Pure-Python stable insertion sort: list of old indices in new order."""
+    order = []
+    for i, k in enumerate(keys):
+        j = len(order)
+        while j > 0 and keys[order[j - 1]] > k:
+            j -= 1
+        order.insert(j, i)
+    return order
+
+
+def _compressed_pair(seed, n_c=4, brick=2):
+    from oracle import codec
+    rng = np.random.default_rng(seed)
+    states, masses = [], []
+    for n, vs, m in ((40, 3.0, 1.0 / 40), (70, 9.0, 0.01 / 70)):
+        x = rng.random((n, 3)).astype(np.float32)
+        v = (rng.standard_normal((n, 3)) * vs).astype(np.float32)
+        states.append(codec.encode(x, v, n_c, brick))
+        masses.append(m)
+    return states, masses
+
+
+def _hand_routed_order(state, c_d, n_c, brick):
+    """New stream order of a drift without kick (c_k = 0), by hand: decoded velocity,
+    fixed-point displacement floor(v c_d S + 1/2), new cell, stable insertion sort."""
+    from oracle import codec
+    S = 256 * n_c
+    u, j = codec.decode_codes(state)
+    v = codec.decode_velocity(j, state["v_max"]).astype(np.float64)
+    keys = []
+    for p in range(u.shape[0]):
+        cell = [((int(u[p, a]) + int(np.floor(v[p, a] * c_d * S + 0.5))) % S) >> 8
+                for a in range(3)]
+        keys.append(_brick_key(cell, n_c, brick))
+    return np.array(_stable_order(keys), dtype=np.int64)
+
+
+def test_vjp_step_compressed_routes_cotangents_through_the_resort():
+    """With c_k = 0 the step is a pure drift: dL/dx = lambda_x' and dL/dv = lambda_v' +
+    c_d lambda_x', each carried from the particle's new stream position back to its old
+    one. The order is rebuilt here by hand; an inverted permutation fails."""
+    from oracle import step
+    n_c, brick, n_g, c_d = 4, 2, 8, 0.02
+    states, masses = _compressed_pair(31, n_c, brick)
+    rng = np.random.default_rng(32)
+    orders = [_hand_routed_order(st, c_d, n_c, brick) for st in states]
+    for o in orders:
+        # the routing is not its own inverse, so getting its direction wrong is visible
+        assert not np.array_equal(o[o], np.arange(o.size))
+    # the oracle's re-sort is the same order
+    _, diag = step.step_compressed(states, masses, n_g, 0.0, c_d)
+    for o, d in zip(orders, diag["species"]):
+        assert np.array_equal(d["perm"], o)
+    lx1 = [rng.standard_normal((o.size, 3)) for o in orders]
+    lv1 = [rng.standard_normal((o.size, 3)) for o in orders]
+    gx, gv = adjoint.vjp_step_compressed(states, masses, lx1, lv1, orders, n_g, 0.0, c_d)
+    for o, a, b, ex, ev in zip(orders, lx1, lv1, gx, gv):
+        for new_pos, old_pos in enumerate(o):
+            assert np.array_equal(ex[old_pos], a[new_pos])
+            assert np.allclose(ev[old_pos], b[new_pos] + c_d * a[new_pos], rtol=0, atol=1e-15)
+
+
+def test_vjp_step_compressed_equals_float_adjoint_on_routed_cotangents():
+    """With a force (c_k != 0): the float adjoint at the decoded state, fed the
+    cotangents routed to old order by the hand-built order."""
+    from oracle import codec
+    n_c, brick, n_g, dt = 4, 2, 8, 0.02
+    states, masses = _compressed_pair(33, n_c, brick)
+    rng = np.random.default_rng(34)
+    from oracle import step
+    _, diag = step.step_compressed(states, masses, n_g, dt, dt)
+    orders = [d["perm"] for d in diag["species"]]
+    lx1 = [rng.standard_normal((o.size, 3)) for o in orders]
+    lv1 = [rng.standard_normal((o.size, 3)) for o in orders]
+    gx, gv = adjoint.vjp_step_compressed(states, masses, lx1, lv1, orders, n_g, dt, dt)
+    species, lxo, lvo = [], [], []
+    for st, m, o, a, b in zip(states, masses, orders, lx1, lv1):
+        x, v = codec.decode(st)
+        species.append((x.astype(np.float64), v.astype(np.float64), m))
+        ra = np.zeros_like(a)
+        rb = np.zeros_like(b)
+        for new_pos, old_pos in enumerate(o):
+            ra[old_pos] = a[new_pos]
+            rb[old_pos] = b[new_pos]
+        lxo.append(ra)
+        lvo.append(rb)
+    fx, fv = adjoint.vjp_step_float(species, lxo, lvo, n_g, dt, dt)
+    for a, b in zip(gx + gv, fx + fv):
+        assert np.array_equal(a, b)
