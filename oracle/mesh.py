@@ -117,9 +117,13 @@ def green(n_g: int, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI) -> np.nda
 
 
 def gradient_symbol(nn, n_g: int):
-    """D(k) = (8 sin(k Delta) - sin(2 k Delta)) / (6 Delta) at k = 2 pi nn, Delta = 1/n_g."""
-    t = 2.0 * np.pi * np.asarray(nn, dtype=np.float64) / n_g
-    return (8.0 * np.sin(t) - np.sin(2.0 * t)) * (n_g / 6.0)
+    """D(k) = (8 sin(k Delta) - sin(2 k Delta)) / (6 Delta) at k = 2 pi nn, Delta = 1/n_g;
+    each sine is taken as exactly 0 where its angle is a multiple of pi."""
+    nn = np.asarray(nn, dtype=np.float64)
+    t = 2.0 * np.pi * nn / n_g
+    s1 = np.where(np.mod(2.0 * nn, n_g) == 0, 0.0, np.sin(t))
+    s2 = np.where(np.mod(4.0 * nn, n_g) == 0, 0.0, np.sin(2.0 * t))
+    return (8.0 * s1 - s2) * (n_g / 6.0)
 
 
 def gradient_factors(n_g: int):

@@ -165,6 +165,7 @@ pm_status pm_destroy(pm_ctx c) {
   hipFree(c->ktab);
   hipFree(c->gtab);
   hipFree(c->tw);
+  hipFree(c->gk);
   hipFree(c->mesh);
   hipFree(c->nyq);
   hipFree(c->err);

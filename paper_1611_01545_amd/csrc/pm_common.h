@@ -94,6 +94,7 @@ struct pm_context {
   int64_t ktab_n = 0;
   float* gtab = nullptr;  // the same kernel values on the octant [kx][|ky|][|kz|] <= n/2
   float2* tw = nullptr;
+  float* gk = nullptr;    // gradient symbol D(k), k < ng (fourth-order difference)
   // owned meshes for pm_step: 3 x ng^3 floats + 3 Nyquist planes (complex ng^2)
   float* mesh = nullptr;
   float2* nyq = nullptr;

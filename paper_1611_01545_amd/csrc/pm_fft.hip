@@ -13,8 +13,10 @@
 //   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
 //               max |a| for the velocity bound of the re-encode
 // 8 launches moving 72 n^3 bytes, against 12 plain passes and separate multiplies.
-// The gradient factor -i k_a follows eq. (3) and is zero on the Nyquist index; the
-// 1/n^3 of the inverse transform is folded into the kernel table.
+// The gradient factor of eq. (3) is -i D(k_a), D the symbol of the fourth-order central
+// difference (written k below; zero on the Nyquist index: the bare -i k truncated at the
+// Nyquist cube rings along the mesh axes); the 1/n^3 of the inverse transform is folded
+// into the kernel table.
 //
 // A line of N points is transformed as N = T x E (four-step): each of T threads holds
 // E points strided by T, does an E-point DFT in registers, multiplies by twiddles,
@@ -256,10 +258,10 @@ constexpr int col_cs(int per_col) {  // padded per-column stride, spreads LDS ba
 }
 
 __device__ __forceinline__ int signed_k(int k, int n) { return k < n / 2 ? k : k - n; }
-// 2 pi k_a for the gradient, zero on the Nyquist index
-__device__ __forceinline__ float grad_k(int k, int n) {
-  return (k == n / 2) ? 0.f : 6.283185307179586f * (float)signed_k(k, n);
-}
+// The gradient symbol of eq. (3) on the mesh: D(k) = (8 sin(k Delta) - sin(2 k Delta)) /
+// (6 Delta), the fourth-order central difference (zero on the Nyquist index), from the
+// context's table gk[k], k < n (built in float64 on the host).
+__device__ __forceinline__ float grad_k(const float* __restrict__ gk, int k) { return gk[k]; }
 
 // Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
 // only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
@@ -272,7 +274,8 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
                                                             const float2* in1, float2* out0,
                                                             float2* out1, Lines d,
                                                             const float2* __restrict__ tw,
-                                                            int tws, int twmask, int n) {
+                                                            int tws, int twmask, int n,
+                                                            const float* __restrict__ gk) {
   using P = Plan<N>;
   constexpr int CS = col_cs<W>(P::E * P::TP);
   __shared__ float lds[W * CS];
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
     // -i k (x + i y) = k y - i k x; k is the line's own wave number
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) {
-      float k = grad_k(t + P::T * n1, n);
+      float k = grad_k(gk, t + P::T * n1);
       a[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
     }
     out0 = out1;
@@ -306,12 +309,12 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
     for (int n1 = 0; n1 < P::E; ++n1) b[n1] = (in1 + (ubase + (int64_t)P::T * n1 * d.es))[lo_in];
     nat_to_tr<N, SIGN>(a, t, my, stw, 1, N - 1);
     nat_to_tr<N, SIGN>(b, t, my, stw, 1, N - 1);
-    const float kxg = grad_k(d.kx_mode ? d.kx_fixed : (int)(blockIdx.x * W) + c, n);
+    const float kxg = grad_k(gk, d.kx_mode ? d.kx_fixed : (int)(blockIdx.x * W) + c);
 #pragma unroll
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
       for (int k2 = 0; k2 < P::T; ++k2) {
-        const float kyg = grad_k((t + P::T * v) + P::E * k2, n);
+        const float kyg = grad_k(gk, (t + P::T * v) + P::E * k2);
         const float2 q = a[v * P::T + k2], p = b[v * P::T + k2];
         // + i (k_x q + k_y p)
         a[v * P::T + k2] = make_float2(-(kxg * q.y + kyg * p.y), kxg * q.x + kyg * p.x);
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
     float2 b[P::E];
 #pragma unroll
     for (int n1 = 0; n1 < P::E; ++n1) {
-      float k = grad_k(t + P::T * n1, n);
+      float k = grad_k(gk, t + P::T * n1);
       b[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
     }
     nat_to_tr<N, SIGN>(a, t, my, stw, 1, N - 1);
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
     const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
     Lines d,
     const float2* __restrict__ tw, int tws, int twmask, int n,
-    const float* __restrict__ gtab) {
+    const float* __restrict__ gtab, const float* __restrict__ gk) {
   using P = Plan<N>;
   constexpr int ZB = zblk(N), LZB = ilog2(ZB);
   static_assert(P::T % ZB == 0, "z blocks must divide the thread stride");
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
         const int sz = signed_k(kz, n);
         const float G = grow[sz < 0 ? -sz : sz];
         const float2 f = make_float2(G * acc[v * P::T + k2].x, G * acc[v * P::T + k2].y);
-        const float kk = grad_k(kz, n);
+        const float kk = grad_k(gk, kz);
         acc[v * P::T + k2] = f;
         gz[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
       }
@@ -434,7 +437,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
         const float2 f = acc[v * P::T + k2];
         if constexpr (MODE == 2) {
           // -i k_z G (x + i y) = k_z G y - i k_z G x
-          const float kk = grad_k(kz, n) * G;
+          const float kk = grad_k(gk, kz) * G;
           acc[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
         } else {
           acc[v * P::T + k2] = make_float2(G * f.x, G * f.y);
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
     for (int v = 0; v < P::V; ++v)
 #pragma unroll
       for (int k2 = 0; k2 < P::T; ++k2) {
-        const float k = grad_k((t + P::T * v) + P::E * k2, n);
+        const float k = grad_k(gk, (t + P::T * v) + P::E * k2);
         const float2 q = acc[v * P::T + k2];
         acc[v * P::T + k2] = make_float2(-k * q.y, k * q.x);  // + i k (x + i y)
       }
@@ -554,7 +557,8 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
 template <int M>
 __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
     const float2* in, const float2* nyq, float* out, int64_t nrows, int grad,
-    const float2* __restrict__ tw, int twmask, unsigned int* amax) {
+    const float2* __restrict__ tw, int twmask, unsigned int* amax,
+    const float* __restrict__ gk) {
   using P = Plan<M>;
   constexpr int R = rows_per_wg<M>();
   constexpr int LF = P::E * P::TP;
@@ -570,7 +574,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
     const int k = t + P::T * j;
     float2 X = xi[k];
     if (grad) {
-      float kk = grad_k(k, n);
+      float kk = grad_k(gk, k);
       X = make_float2(kk * X.y, -kk * X.x);
     }
     xr[j] = X;
@@ -690,7 +694,7 @@ pm_status col_fft(const FftCtx& f, const float2* in, const float2* in1, float2* 
   if (out == 3 && (sign > 0 || o1)) return PM_ERR_ARG;
 #define CLAUNCH(S, O)                                                                 \
   hipLaunchKernelGGL((k_col_fft<N, W, S, O>), grid, block, 0, f.c->stream, in, in1, o0, \
-                     o1, d, f.c->tw, 1, f.twmask, f.n)
+                     o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gk)
   if (sign < 0) {
     if (out == 3) CLAUNCH(-1, 3);
     else if (out == 0) CLAUNCH(-1, 0);
@@ -715,7 +719,7 @@ pm_status col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0, const
   dim3 block(W * Plan<N>::T);
 #define ZLAUNCH(MODE, BLK)                                                                 \
   hipLaunchKernelGGL((k_col_zconv<N, W, MODE, BLK>), grid, block, 0, f.c->stream, i0, i1, \
-                     i2, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gtab)
+                     i2, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gtab, f.c->gk)
   if (blk) {
     if (mode == 0) ZLAUNCH(0, true);
     else if (mode == 2) ZLAUNCH(2, true);
@@ -750,7 +754,7 @@ pm_status row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* o
   int64_t nrows = (int64_t)f.n * f.n;
   if (nrows % R) return PM_ERR_SHAPE;
   hipLaunchKernelGGL(k_row_c2r<M>, dim3((unsigned)cdiv(nrows, R)), dim3(R * Plan<M>::T), 0,
-                     f.c->stream, in, nyq, out, nrows, grad, f.c->tw, f.twmask, amax);
+                     f.c->stream, in, nyq, out, nrows, grad, f.c->tw, f.twmask, amax, f.c->gk);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -862,6 +866,19 @@ pm_status build_kernel_table(pm_context* c) {
   hipError_t e = hipMalloc(&c->tw, sizeof(float2) * n);
   if (e == hipSuccess) e = hipMemcpy(c->tw, h, sizeof(float2) * n, hipMemcpyHostToDevice);
   free(h);
+  if (e != hipSuccess) return PM_ERR_DEVICE;
+  // gradient symbol D(k) = n (8 sin(2 pi k/n) - sin(4 pi k/n)) / 6, k < n; both sines
+  // vanish exactly where 4 k is a multiple of n or 2 k is (sin(pi j) = 0)
+  std::vector<float> gk((size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    auto sin_turn = [](int64_t j, int64_t m) {  // sin(2 pi j / m)
+      j %= m;
+      return (2 * j) % m == 0 ? 0.0 : std::sin(2.0 * 3.141592653589793238462643 * (double)j / (double)m);
+    };
+    gk[(size_t)k] = (float)((double)n * (8.0 * sin_turn(k, n) - sin_turn(2 * k, n)) / 6.0);
+  }
+  e = hipMalloc(&c->gk, sizeof(float) * n);
+  if (e == hipSuccess) e = hipMemcpy(c->gk, gk.data(), sizeof(float) * n, hipMemcpyHostToDevice);
   if (e != hipSuccess) return PM_ERR_DEVICE;
   return PM_OK;
 }

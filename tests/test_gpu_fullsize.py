@@ -5,8 +5,10 @@ The oracle cannot form 1024^3 meshes and 151 M particles at once, so it checks w
 can compute piece by piece, or what holds at any size:
   * density at sampled nodes, from the particles of the neighbouring cells only
     (oracle.mesh.density_at), tolerance 1e-5 max(|rho|, mean rho);
-  * the force of a full-size plane-wave density against the oracle's kernel value:
-    a_a = k_a G(|k|) sin(k.x), relative RMS over sampled nodes <= 1e-4;
+  * the force of a full-size density made of 16 Fourier modes (the kx = 0 column and
+    the Nyquist planes of every axis among them) against its analytic value:
+    a_a = sum_m A_m D(k_m,a) G(|k_m|) sin(k_m.x + phi_m), relative RMS over sampled
+    nodes <= 1e-4;
   * the kick-drift-re-encode of every particle of sampled cells from the GPU's own force
     mesh, against oracle.step.kick_codes in float64 (equal codes outside the tie zone);
   * the fused pm_step equals the separate calls bit for bit; mass is conserved.
@@ -87,29 +89,63 @@ def test_fullsize_density_sampled(full):
     assert err.max() <= 1e-5, err.max()
 
 
-def test_fullsize_plane_wave_force(full):
-    wl, c = full.wl, full.c
-    n = wl.n_mesh
-    nv = np.array([3, -5, 7])  # wave numbers along x, y, z
+def _modes(n):
+    """16 Fourier modes (n_x, n_y, n_z) of an n^3 mesh: interior modes, the kx = 0
+    column, and modes on the Nyquist plane of each axis (alone and combined)."""
+    h = n // 2
+    return np.array([[3, -5, 7], [0, 4, -9], [h, 6, -2], [5, h, 1], [-7, 2, h],
+                     [0, 0, 11], [1, 0, 0], [h, h, 3], [17, -31, 29], [0, h, 0],
+                     [n // 4, -n // 8, 13], [2, 3, 1 - h], [h, 0, h], [-1, -1, -1],
+                     [0, -6, 0], [9, h, h]], dtype=np.int64)
+
+
+def _mode_density(n, modes, amps, phases, dev):
+    """rho(c) = sum_m A_m cos(2 pi (n_m . c mod n) / n + phi_m) in float32, built in
+    slabs of 32 planes (integer phases, float64 cosines)."""
+    rho = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    i = torch.arange(n, device=dev, dtype=torch.int64)
+    for z0 in range(0, n, 32):
+        zz = torch.arange(z0, z0 + 32, device=dev, dtype=torch.int64)
+        acc = torch.zeros((32, n, n), dtype=torch.float64, device=dev)
+        for (nx, ny, nz), a, ph in zip(modes.tolist(), amps, phases):
+            p = (nz * zz[:, None, None] + ny * i[None, :, None] + nx * i[None, None, :]) % n
+            acc += a * torch.cos(p.to(torch.float64) * (2 * np.pi / n) + ph)
+            del p
+        rho[z0:z0 + 32] = acc.to(torch.float32)
+        del acc
+    return rho
+
+
+def _mode_force_check(c, n, seed):
+    """Force of a 16-mode density at 4096 sampled nodes against the analytic value."""
+    rng = np.random.default_rng(seed)
+    modes = _modes(n)
+    amps = rng.uniform(0.5, 1.0, len(modes))
+    phases = rng.uniform(0.0, 2 * np.pi, len(modes))
     dev = c.device
-    i = torch.arange(n, device=dev, dtype=torch.int32)
-    ph = (int(nv[2]) * i[:, None, None] + int(nv[1]) * i[None, :, None] +
-          int(nv[0]) * i[None, None, :]) % n
-    rho_pw = torch.cos(ph.to(torch.float64) * (2 * np.pi / n)).to(torch.float32)
-    del ph
-    acc_pw, _ = c.force(rho_pw)
-    del rho_pw
-    rng = np.random.default_rng(3)
+    rho = _mode_density(n, modes, amps, phases, dev)
+    acc, _ = c.force(rho)
+    del rho
     nodes = rng.integers(0, n, size=(4096, 3))
     idx = torch.from_numpy(nodes[:, 2] * n * n + nodes[:, 1] * n + nodes[:, 0]).to(dev)
-    got = acc_pw.reshape(3, -1)[:, idx].cpu().numpy().astype(np.float64)
-    del acc_pw
-    k = 2 * np.pi * nv.astype(np.float64)
-    G = mesh.plummer_kernel_k(np.array([np.linalg.norm(k)]), c.soft_cells / n, c.G)[0]
-    theta = 2 * np.pi * ((nodes @ nv) % n) / n
-    want = k[:, None] * G * np.sin(theta)[None, :]
+    got = acc.reshape(3, -1)[:, idx].cpu().numpy().astype(np.float64)
+    del acc
+    kmag = 2 * np.pi * np.sqrt((modes.astype(np.float64) ** 2).sum(1))
+    G = mesh.plummer_kernel_k(kmag, c.soft_cells / n, c.G)
+    D = mesh.gradient_symbol(modes, n)  # [mode][axis]
+    theta = 2 * np.pi * ((nodes @ modes.T) % n) / n + phases[None, :]  # [node][mode]
+    want = ((amps * G)[None, :, None] * D[None, :, :] *
+            np.sin(theta)[:, :, None]).sum(1).T  # [axis][node]
     err = np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
     assert err <= 1e-4, err
+    # the Nyquist planes carry no x (resp. y, z) force: D vanishes there
+    assert np.all(D[modes == n // 2] == 0)
+    return err
+
+
+def test_fullsize_mode_sum_force(full):
+    err = _mode_force_check(full.c, full.wl.n_mesh, 3)
+    print(f"[fullsize] 16-mode force at 1024^3: relative RMS {err:.2e}", flush=True)
 
 
 def test_fullsize_kick_sampled(full):
@@ -163,37 +199,23 @@ def test_fullsize_kick_sampled(full):
               f"{int(badv.sum())} velocity codes in the tie zone", flush=True)
 
 
-def test_plane_wave_force_2048():
+def test_force_2048():
     """The force path at the largest mesh (2048^3, the 1.2 G-particle workload's mesh):
-    every FFT kernel variant of that size on a plane-wave density, against the oracle's
-    kernel value at sampled nodes, and max |a| against its analytic value."""
+    every FFT kernel variant of that size (8-column y and z passes) on a 16-mode density
+    at sampled nodes, and max |a| of a single plane wave against its analytic value."""
     n = 2048
+    print("[fullsize] 2048^3 force", flush=True)
     c = ctx(n, 128)
-    dev = c.device
-    nv = np.array([3, -5, 7])
-    rho = torch.empty((n, n, n), dtype=torch.float32, device=dev)
-    i = torch.arange(n, device=dev, dtype=torch.int64)
-    xy = (int(nv[1]) * i[:, None] + int(nv[0]) * i[None, :])
-    for z0 in range(0, n, 64):  # slabs keep the float64 temporaries small
-        zz = torch.arange(z0, z0 + 64, device=dev, dtype=torch.int64)
-        ph = (int(nv[2]) * zz[:, None, None] + xy[None, :, :]) % n
-        rho[z0:z0 + 64] = torch.cos(ph.to(torch.float64) * (2 * np.pi / n)).to(torch.float32)
-        del ph
+    err = _mode_force_check(c, n, 4)
+    print(f"[fullsize] 16-mode force at 2048^3: relative RMS {err:.2e}", flush=True)
+    nv = np.array([[3, -5, 7]], dtype=np.int64)
+    rho = _mode_density(n, nv, [1.0], [0.0], c.device)
     acc, amax = c.force(rho)
-    del rho
-    rng = np.random.default_rng(4)
-    nodes = rng.integers(0, n, size=(4096, 3))
-    idx = torch.from_numpy(nodes[:, 2] * n * n + nodes[:, 1] * n + nodes[:, 0]).to(dev)
-    got = acc.reshape(3, -1)[:, idx].cpu().numpy().astype(np.float64)
-    k = 2 * np.pi * nv.astype(np.float64)
-    G = mesh.plummer_kernel_k(np.array([np.linalg.norm(k)]), c.soft_cells / n, c.G)[0]
-    theta = 2 * np.pi * ((nodes @ nv) % n) / n
-    want = k[:, None] * G * np.sin(theta)[None, :]
-    err = np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
-    assert err <= 1e-4, err
+    del rho, acc
+    kmag = 2 * np.pi * np.sqrt(float((nv.astype(np.float64) ** 2).sum()))
+    G = mesh.plummer_kernel_k(np.array([kmag]), c.soft_cells / n, c.G)[0]
     # the phase takes every residue mod n, so |sin| reaches 1 on the mesh
-    amax_want = float(np.max(np.abs(k)) * abs(G))
+    amax_want = float(np.max(np.abs(mesh.gradient_symbol(nv[0], n))) * abs(G))
     assert abs(float(amax.item()) - amax_want) <= 1e-4 * amax_want
-    del acc
     c.close()
     torch.cuda.empty_cache()
