@@ -16,7 +16,8 @@
  * position offset inside the cell and a 2-byte velocity histogram index per axis.
  *
  * Conventions for every entry point:
- *   - box side 1; positions in [0, 1); mesh arrays are float [z][y][x] (x fastest);
+ *   - periodic box of side L (pm_config.box); positions in [0, L); mesh arrays are
+ *     float [z][y][x] (x fastest);
  *     particle float arrays are [n][3] with columns x, y, z;
  *   - all pointers documented "device" are device memory on the context's GPU; the
  *     caller owns them and keeps them alive until the work is done;
@@ -56,6 +57,11 @@ typedef enum pm_status {
 
 typedef struct pm_context* pm_ctx;
 
+/* Arithmetic of the mesh and particle kernels: float32 meshes, FFTs and kicks, with
+ * positions exact in the fixed-point codes of compressed species and float64 global
+ * reductions and kernel-table construction. No other precision is built. */
+enum { PM_PREC_F32 = 0 };
+
 /* Sizes and physics constants of a context.
  *   n_mesh     PM mesh side n_g: a power of two, 8 <= n_mesh <= 2048.
  *   n_cell     compression mesh side n_c (Sec. 2.4 uses (n_p/2)^3 cells): a power of
@@ -63,14 +69,18 @@ typedef struct pm_context* pm_ctx;
  *   brick      cells per brick side B of the stream order: a power of two dividing
  *              n_cell, B <= 8. Cells are ordered brick by brick (x fastest), and x
  *              fastest inside a brick; B = 1 is plain row-major order.
- *   flags      0.
+ *   prec       PM_PREC_F32 (anything else: PM_ERR_ARG).
+ *   box        box side L > 0: float positions lie in [0, L), the mesh spacing is
+ *              Delta = L / n_mesh and densities are mass per unit volume. A power of two
+ *              keeps every position conversion exact (L = 1 is the unit box).
  *   G          gravitational constant (1/(4 pi) makes 4 pi G = 1).
  *   soft_cells Plummer softening length in mesh cells (>= 0). */
 typedef struct pm_config {
   int64_t n_mesh;
   int64_t n_cell;
   int32_t brick;
-  int32_t flags;
+  int32_t prec;
+  double box;
   double G;
   double soft_cells;
 } pm_config;
@@ -123,6 +133,34 @@ typedef struct pm_species {
 /* Message for a status code (static string). */
 const char* pm_status_str(pm_status s);
 
+/* Device memory of a configuration, for planning (host only, no GPU call). Bytes:
+ *   context_bytes     what pm_create allocates (kernel tables, twiddles, gradient
+ *                     symbol, Nyquist planes), exact;
+ *   step_mesh_bytes   the context's force meshes (3 n_mesh^3 floats, allocated by the
+ *                     first pm_step, pm_step_vjp or pm_loss_density_vjp), exact;
+ *   step_scratch_bytes  upper bound of the scratch that pm_encode and pm_step grow for
+ *                     n_max particles in total over n_sp species (1 <= n_sp <= 4);
+ *   vjp_scratch_bytes   upper bound of what pm_step_vjp adds to that;
+ *   float_deposit_scratch_bytes  what a PM_FLOAT deposit adds (8 n_mesh^3);
+ *   compressed_species_bytes  one compressed species of n_max particles with
+ *                     cap_esc = n_max / 255 + 1 (caller-owned);
+ *   float_species_bytes  one float species of n_max particles (caller-owned).
+ * Scratch is grown on first use and kept until pm_destroy; pm_scratch_bytes reports
+ * what a context holds. */
+typedef struct pm_sizes {
+  int64_t context_bytes;
+  int64_t step_mesh_bytes;
+  int64_t step_scratch_bytes;
+  int64_t vjp_scratch_bytes;
+  int64_t float_deposit_scratch_bytes;
+  int64_t compressed_species_bytes;
+  int64_t float_species_bytes;
+} pm_sizes;
+
+pm_status pm_query_sizes(const pm_config* cfg, int64_t n_max, int n_sp, pm_sizes* out);
+/* Scratch bytes a context currently holds (host value). */
+pm_status pm_scratch_bytes(pm_ctx ctx, int64_t* bytes);
+
 /* Create a context on the current HIP device; `stream` is a hipStream_t (NULL for
  * the default stream). Builds the gravity-kernel table in float64 on the GPU. */
 pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out);
@@ -133,13 +171,15 @@ pm_status pm_sync(pm_ctx ctx);
 /* After PM_ERR_CAPACITY: the capacity (elements) that would have been needed. */
 pm_status pm_last_error_detail(pm_ctx ctx, int64_t* needed);
 
-/* Compress float particles (Sec. 2.4): v_max = largest |v_a| of the species; cells of
- * the n_cell^3 mesh in stream order; particles of a cell in input order.
+/* Compress float particles (Sec. 2.4): position code u = floor(x 256 n_cell / L) mod
+ * 256 n_cell per axis (cell u >> 8, byte u & 255); v_max = largest |v_a| of the species;
+ * cells of the n_cell^3 mesh in stream order; particles of a cell in input order.
  * in: PM_FLOAT; out: PM_COMPRESSED with out->n == in->n. perm (device int64 [n],
  * nullable) receives, for each stream position, the input index of that particle. */
 pm_status pm_encode(pm_ctx ctx, const pm_species* in, pm_species* out, int64_t* perm);
 
-/* Decompress to bin centres, in stream order (Sec. 2.4, used for restarts).
+/* Decompress to bin centres (u + 1/2) L / (256 n_cell), in stream order (Sec. 2.4,
+ * used for restarts).
  * in: PM_COMPRESSED; out: PM_FLOAT with out->n == in->n. */
 pm_status pm_decode(pm_ctx ctx, const pm_species* in, pm_species* out);
 
@@ -151,17 +191,19 @@ pm_status pm_decode(pm_ctx ctx, const pm_species* in, pm_species* out);
  * PM_FLOAT sums all contributions in 64-bit fixed point. */
 pm_status pm_deposit(pm_ctx ctx, const pm_species* sp, int n_sp, float* rho);
 
-/* Accelerations a_a(c) from a density mesh, eqs. (2)-(3): a = IDFT(-i k G(k) DFT(rho))
+/* Accelerations a_a(c) from a density mesh, eqs. (2)-(3): a = IDFT(-i D(k) G(k) DFT(rho))
  * with the softened kernel G(k) = -4 pi G eps K1(k eps)/k, G(0) = 0, eps =
- * soft_cells/n_mesh, and k_a = 0 on the Nyquist index. acc: device float
+ * soft_cells Delta, and for the gradient of eq. (3) the symbol of the fourth-order
+ * central difference, D(k_a) = (8 sin(k_a Delta) - sin(2 k_a Delta)) / (6 Delta) (zero on
+ * the Nyquist index). acc: device float
  * [3][n_mesh^3]; rho may alias acc (component x). a_max (device float, nullable)
  * receives max |a_a(c)| over the mesh. rho is not preserved when it aliases acc. */
 pm_status pm_force(pm_ctx ctx, const float* rho, float* acc, float* a_max);
 
 /* Interpolate acc to the particles (CIC), kick v' = v + c_kick a, drift
- * x' = x + c_drift v' (mod 1). PM_FLOAT: in and out may be the same arrays.
+ * x' = x + c_drift v' (mod L). PM_FLOAT: in and out may be the same arrays.
  * PM_COMPRESSED: in and out must be distinct; positions drift in fixed point
- * (u' = u + floor(v' c_drift 256 n_cell + 1/2)), velocities are re-binned with
+ * (u' = u + floor(v' c_drift 256 n_cell / L + 1/2)), velocities are re-binned with
  * v_max' = the smallest power of two >= max|v_decoded| + |c_kick| a_max, and the
  * stream is re-sorted stably into cell order. a_max: device float from pm_force
  * (required for PM_COMPRESSED). */
@@ -207,11 +249,20 @@ pm_status pm_loss_density_vjp(pm_ctx ctx, const pm_species* sp, int n_sp,
                               const float* rho_target, double* loss,
                               float* const* lam_x);
 
-/* Float64 global reductions (on the GPU): out[0] = sum_c rho(c) Delta^3 (rho may be
- * NULL, then 0), out[1] = sum_i m_i, out[2..4] = sum_i m_i v_i, out[5..7] = 0.
- * out: device double[8]. Compressed species use decoded velocities. */
+/* Float64 global reductions on the GPU: the conserved quantities that check the method
+ * (Sec. 2.1: the CIC deposit and interpolation with a real odd gradient conserve mass and
+ * momentum). out: device double [8 + 6 n_sp]:
+ *   out[0]        sum_c rho(c) Delta^3 (0 if rho is NULL),
+ *   out[1]        sum_s m_s N_s,
+ *   out[2..4]     sum_i m_i v_i over all species,
+ *   out[5..7]     sum_i m_i a_i over all species, a_i the CIC interpolation of acc at the
+ *                 particle (0 if acc is NULL; it vanishes up to rounding when acc is the
+ *                 force of the same particles' density),
+ *   out[8+6s..]   per species s: m_s sum_i v_i (3), then m_s sum_i a_i (3).
+ * Compressed species use decoded bin centres and velocities. acc: device float
+ * [3][n_mesh^3] or NULL. Asynchronous; 0 <= n_sp <= 4. */
 pm_status pm_reduce(pm_ctx ctx, const pm_species* sp, int n_sp, const float* rho,
-                    double* out);
+                    const float* acc, double* out);
 
 /* Byte stream of one compressed species (Sec. 2.4 layout): a 64-byte header
  * {"PMC1", version 1, species_id, brick, N, n_cell, v_max, 0, mass, checksum,
@@ -242,7 +293,7 @@ pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species
 pm_status pm_profile(pm_ctx ctx, int enable);
 pm_status pm_profile_read(pm_ctx ctx, double* ms, int64_t* launches, int cap);
 
-/* Diagnostics: copy the float32 kernel table G(|n|^2)/n_mesh^3 (device float
+/* Diagnostics: copy the float32 kernel table L G(|n|^2)/n_mesh^3 (device float
  * [3 (n_mesh/2)^2 + 1], indexed by the integer |n|^2). */
 pm_status pm_kernel_table(pm_ctx ctx, float* out, int64_t cap);
 

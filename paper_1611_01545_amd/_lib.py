@@ -36,10 +36,17 @@ class PmConfig(ctypes.Structure):
         ("n_mesh", ctypes.c_int64),
         ("n_cell", ctypes.c_int64),
         ("brick", ctypes.c_int32),
-        ("flags", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("box", ctypes.c_double),
         ("G", ctypes.c_double),
         ("soft_cells", ctypes.c_double),
     ]
+
+
+class PmSizes(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "context_bytes", "step_mesh_bytes", "step_scratch_bytes", "vjp_scratch_bytes",
+        "float_deposit_scratch_bytes", "compressed_species_bytes", "float_species_bytes")]
 
 
 class PmSpecies(ctypes.Structure):
@@ -66,6 +73,8 @@ PS = ctypes.POINTER(PmSpecies)
 EXPORTS = [
     ("pm_status_str", [ctypes.c_int]),
     ("pm_create", [ctypes.POINTER(PmConfig), P, ctypes.POINTER(P)]),
+    ("pm_query_sizes", [ctypes.POINTER(PmConfig), I64, ctypes.c_int, ctypes.POINTER(PmSizes)]),
+    ("pm_scratch_bytes", [P, ctypes.POINTER(I64)]),
     ("pm_destroy", [P]),
     ("pm_sync", [P]),
     ("pm_last_error_detail", [P, ctypes.POINTER(I64)]),
@@ -79,7 +88,7 @@ EXPORTS = [
     ("pm_step", [P, PS, PS, ctypes.c_int, ctypes.c_double]),
     ("pm_step_vjp", [P, PS, ctypes.c_int, ctypes.c_double, P, P, P, P]),
     ("pm_loss_density_vjp", [P, PS, ctypes.c_int, P, P, P]),
-    ("pm_reduce", [P, PS, ctypes.c_int, P, P]),
+    ("pm_reduce", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_pack", [P, PS, ctypes.c_int32, P, I64, P]),
     ("pm_pack_size", [P, PS, ctypes.POINTER(I64)]),
     ("pm_unpack", [P, P, I64, PS, ctypes.POINTER(ctypes.c_double),

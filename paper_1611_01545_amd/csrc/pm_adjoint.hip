@@ -36,11 +36,11 @@ struct Cic {
   float f[3];    // fractional offset per axis
 };
 
-__device__ __forceinline__ Cic cic_of(const float* x, int64_t ng) {
+__device__ __forceinline__ Cic cic_of(const float* x, int64_t ng, float ngL) {
   Cic r;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float u = x[a] * (float)ng;  // exact: ng is a power of two
+    float u = x[a] * ngL;  // mesh units (exact for a power-of-two box)
     float fl = floorf(u);
     r.f[a] = u - fl;
     int64_t k = (int64_t)fl % ng;
@@ -70,11 +70,11 @@ __global__ __launch_bounds__(AT) void k_vjp_init(const float* lx1, const float* 
 
 // mu_a(c) += W(x_j - x_c) c_k g_v,ja for the three components.
 __global__ __launch_bounds__(AT) void k_scatter_vec(const float* x, const float* gv, int64_t n,
-                                                    int64_t ng, float ck, float* mu) {
+                                                    int64_t ng, float ngL, float ck, float* mu) {
   const int64_t p = (int64_t)blockIdx.x * AT + threadIdx.x;
   if (p >= n) return;
   const int64_t n3 = ng * ng * ng;
-  const Cic q = cic_of(x + 3 * p, ng);
+  const Cic q = cic_of(x + 3 * p, ng, ngL);
   const float g0 = ck * gv[3 * p], g1 = ck * gv[3 * p + 1], g2 = ck * gv[3 * p + 2];
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -94,20 +94,20 @@ __global__ __launch_bounds__(AT) void k_scatter_vec(const float* x, const float*
 // out_i (+)= sum_c grad W(x_i - x_c) q(c) with
 //   q(c) = s_scale s(c) + c_k g_v,i . a(c)      (the second term only if acc is given).
 __global__ __launch_bounds__(AT) void k_gather_grad(const float* x, int64_t n, int64_t ng,
-                                                    const float* s, float s_scale,
+                                                    float ngL, const float* s, float s_scale,
                                                     const float* acc, const float* gv,
                                                     float ck, float* out, int accumulate) {
   const int64_t p = (int64_t)blockIdx.x * AT + threadIdx.x;
   if (p >= n) return;
   const int64_t n3 = ng * ng * ng;
-  const Cic q = cic_of(x + 3 * p, ng);
+  const Cic q = cic_of(x + 3 * p, ng, ngL);
   float g0 = 0.f, g1 = 0.f, g2 = 0.f;
   if (acc) {
     g0 = ck * gv[3 * p];
     g1 = ck * gv[3 * p + 1];
     g2 = ck * gv[3 * p + 2];
   }
-  const float fn = (float)ng;
+  const float fn = ngL;  // d W / d x per axis is +-n / L
   float gr[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -185,7 +185,7 @@ struct AdjSpecies {
   const int64_t* off;  // cell offsets [ncell3 + 1]
   const float* gv;     // g_v = dL/dv per particle, stream order
   float* lx;           // dL/dx per particle, stream order (gather adds to it)
-  float sscale;        // m n^3 (density per unit weight)
+  float sscale;        // m / Delta^3 (density per unit weight)
 };
 struct AdjArgs {
   AdjSpecies sp[MAXSP];
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(GT) void k_gather_brick(AdjArgs A, Geom g, const fl
       if (row < ROWS) Fm[row * GR1 + GR] = vh[k];
     }
   }
-  const float fn = (float)ng;
+  const float fn = g.ngL;  // d W / d x per axis is +-n / L
   for (int s = 0; s < A.n_sp; ++s) {
     const AdjSpecies sp = A.sp[s];
     __syncthreads();  // staged meshes ready / previous species done with loff
@@ -642,7 +642,7 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
     a.off = P.offs[i];
     a.gv = lv0[i];
     a.lx = lx0[i];
-    a.sscale = (float)(in[i].mass * (double)n3);
+    a.sscale = (float)(in[i].mass * (double)n3 / (c->g.box * c->g.box * c->g.box));
   }
   {
     ProfScope ps(c, ST_ADJOINT);
@@ -656,7 +656,7 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
                          c->stream, lx1[i], lv1[i], perm[i], in[i].n, cd, lx0[i], lv0[i]);
       if (!tiled)
         hipLaunchKernelGGL(k_scatter_vec, dim3(nb), dim3(AT), 0, c->stream, P.x[i], lv0[i],
-                           in[i].n, ng, ck, mu);
+                           in[i].n, ng, c->g.ngL, ck, mu);
     }
     if (tiled && T.n_sp > 0) {
       const int64_t nt = g.nc / tt;
@@ -684,9 +684,9 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
     } else {
       for (int i = 0; i < n_sp; ++i) {
         if (in[i].n == 0) continue;
-        const float sscale = (float)(in[i].mass * (double)n3);
+        const float sscale = (float)(in[i].mass * (double)n3 / (c->g.box * c->g.box * c->g.box));
         hipLaunchKernelGGL(k_gather_grad, dim3((unsigned)cdiv(in[i].n, AT)), dim3(AT), 0,
-                           c->stream, P.x[i], in[i].n, ng, mu, sscale, acc, lv0[i], ck,
+                           c->stream, P.x[i], in[i].n, ng, c->g.ngL, mu, sscale, acc, lv0[i], ck,
                            lx0[i], 1);
       }
     }
@@ -713,9 +713,9 @@ pm_status run_loss_vjp(pm_context* c, const pm_species* sp, int n_sp, const floa
     hipLaunchKernelGGL(k_fold_double, dim3(1), dim3(AT), 0, c->stream, part, nb, loss);
   for (int i = 0; i < n_sp; ++i) {
     if (sp[i].n == 0) continue;
-    const float sscale = (float)(2.0 * sp[i].mass * (double)n3);
+    const float sscale = (float)(2.0 * sp[i].mass * (double)n3 / (c->g.box * c->g.box * c->g.box));
     hipLaunchKernelGGL(k_gather_grad, dim3((unsigned)cdiv(sp[i].n, AT)), dim3(AT), 0,
-                       c->stream, P.x[i], sp[i].n, ng, r, sscale, nullptr, nullptr, 0.f,
+                       c->stream, P.x[i], sp[i].n, ng, c->g.ngL, r, sscale, nullptr, nullptr, 0.f,
                        lam_x[i], 0);
   }
   PM_LAUNCH_CHECK();

@@ -122,7 +122,8 @@ pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out) {
   if (!is_pow2(B) || B > 8 || B > nc) return PM_ERR_SHAPE;
   if (!(cfg->soft_cells >= 0.0) || !std::isfinite(cfg->soft_cells)) return PM_ERR_ARG;
   if (!std::isfinite(cfg->G)) return PM_ERR_ARG;
-  if (cfg->flags != 0) return PM_ERR_ARG;
+  if (!(cfg->box > 0.0) || !std::isfinite(cfg->box)) return PM_ERR_ARG;
+  if (cfg->prec != PM_PREC_F32) return PM_ERR_ARG;
   pm_context* c = new (std::nothrow) pm_context();
   if (!c) return PM_ERR_NOMEM;
   c->cfg = *cfg;
@@ -141,6 +142,10 @@ pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out) {
   g.ncell3 = nc * nc * nc;
   g.nbrick = (nc / B) * (nc / B) * (nc / B);
   g.S = 256 * nc;
+  g.box = cfg->box;
+  g.ngL = (float)((double)ng / cfg->box);
+  g.SL = (double)g.S / cfg->box;
+  g.LS = (float)(cfg->box / (double)g.S);
   pm_status s = PM_OK;
   if (hipMalloc(&c->err, sizeof(DevErr)) != hipSuccess ||
       hipMalloc(&c->amax, 64) != hipSuccess ||
@@ -156,6 +161,58 @@ pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out) {
     return s;
   }
   *out = c;
+  return PM_OK;
+}
+
+pm_status pm_query_sizes(const pm_config* cfg, int64_t n_max, int n_sp, pm_sizes* out) {
+  if (!cfg || !out || n_max < 0 || n_sp < 1 || n_sp > 4) return PM_ERR_ARG;
+  const int64_t ng = cfg->n_mesh, nc = cfg->n_cell, B = cfg->brick;
+  if (!is_pow2(ng) || ng < 8 || ng > 2048) return PM_ERR_SHAPE;
+  if (!is_pow2(nc) || nc > 1024 || nc > ng || ng / nc > 16) return PM_ERR_SHAPE;
+  if (!is_pow2(B) || B > 8 || B > nc) return PM_ERR_SHAPE;
+  const int64_t n3 = ng * ng * ng, n2 = ng * ng, h1 = ng / 2 + 1, nc3 = nc * nc * nc;
+  const int64_t nb = (nc / B) * (nc / B) * (nc / B), N = n_max;
+  // grown scratch buffers carry 1/8 headroom
+  auto grown = [](int64_t b) { return b + b / 8; };
+  *out = pm_sizes{};
+  // pm_create: kernel tables (by |n|^2 and the octant copy), twiddles, gradient symbol,
+  // three Nyquist planes, error word and max |a|
+  out->context_bytes = (3 * (ng / 2) * (ng / 2) + 1) * 4 + h1 * h1 * h1 * 4 + ng * 8 + ng * 4 +
+                       3 * n2 * 8 + (int64_t)sizeof(DevErr) + 64;
+  out->step_mesh_bytes = 3 * n3 * 4;
+  // pm_encode / pm_step of N particles in n_sp species
+  const int64_t rs_blocks = N / 4096 + 1;  // radix-sort workgroups (encode: uncapped)
+  int64_t st = 0;
+  st += grown(n3 * 4);                                  // spectrum scratch mesh
+  st += grown(3 * n2 * 4);                              // per-row max |a| partials (bound)
+  st += n_sp * grown((nc3 + 1) * 8);                    // cell offsets per species
+  st += grown((nc3 + 1) * 8) * 2;                       // new offsets, decode/pack offsets
+  st += grown(nc3 * 8 * n_sp);                          // new counts per cell
+  st += grown(nc3 * 4) * 2 + grown((nc3 + 1) * 8);      // escape flags, their scan, counts
+  st += grown(N * 3) + grown(N * 6) + grown(N * 2);     // new codes and digits, old order
+  st += 4 * grown(N * 4);                               // mover keys and indices, two copies
+  st += grown(nb * 4 * n_sp) + grown((nb + 1) * 8);     // movers per brick, their offsets
+  st += grown(std::max<int64_t>(nb * 8 * n_sp, (N / 256 + 1) * 8));  // grid partials
+  st += grown(rs_blocks * 256 * 4) + grown((rs_blocks * 256 + 1) * 8);  // radix histograms
+  st += grown((std::max<int64_t>(std::max<int64_t>(nc3, N), rs_blocks * 256) / 4096 + 1) * 8);
+  st += grown(4096) + grown(512 * 25 * 8) + grown(32);  // folds, reductions, mover counts
+  out->step_scratch_bytes = st;
+  // pm_step_vjp adds the three adjoint meshes, the decoded positions and the recomputed
+  // re-sort (permutations and a copy of the stream)
+  int64_t vj = grown(3 * n3 * 4) + grown(N * 24 + n_sp * 512);
+  vj += grown(N * 8 + N * 3 + N * 6 + n_sp * (nc3 + (N / 255 + 1) * 16 + 2048));
+  out->vjp_scratch_bytes = vj;
+  out->float_deposit_scratch_bytes = grown(n3 * 8);   // 64-bit fixed-point node sums
+  out->compressed_species_bytes = nc3 + 9 * N + (N / 255 + 1) * 16 + (int64_t)sizeof(pm_shdr);
+  out->float_species_bytes = 24 * N;
+  return PM_OK;
+}
+
+pm_status pm_scratch_bytes(pm_ctx c, int64_t* bytes) {
+  if (!c || !bytes) return PM_ERR_ARG;
+  int64_t t = 0;
+  for (const auto& b : c->scratch) t += (int64_t)b.bytes;
+  *bytes = t;
   return PM_OK;
 }
 
@@ -350,11 +407,12 @@ pm_status pm_loss_density_vjp(pm_ctx c, const pm_species* sp, int n_sp, const fl
   return run_loss_vjp(c, sp, n_sp, rho_t, loss, lam_x);
 }
 
-pm_status pm_reduce(pm_ctx c, const pm_species* sp, int n_sp, const float* rho, double* out) {
+pm_status pm_reduce(pm_ctx c, const pm_species* sp, int n_sp, const float* rho,
+                    const float* acc, double* out) {
   if (!c || !out || n_sp < 0 || n_sp > 4 || (n_sp > 0 && !sp)) return PM_ERR_ARG;
   for (int i = 0; i < n_sp; ++i)
     if (check_species(c, &sp[i], true) != PM_OK) return PM_ERR_ARG;
-  return run_reduce(c, sp, n_sp, rho, out);
+  return run_reduce(c, sp, n_sp, rho, acc, out);
 }
 
 pm_status pm_pack(pm_ctx c, const pm_species* sp, int32_t species_id, uint8_t* buf,

@@ -8,10 +8,11 @@
 
 #define PM_STREAM_HEADER 64
 
-// u = floor(x S) mod S (S = 256 n_c, a power of two). Returns false for non-finite
-// or absurdly large input (u is then 0).
-__device__ inline bool pos_code(float x, int64_t S, uint32_t& u) {
-  double t = (double)x * (double)S;
+// u = floor(x (S / L)) mod S (S = 256 n_c, a power of two; SL = S / L rounded once to
+// float64, exact when L is a power of two). Returns false for non-finite or absurdly
+// large input (u is then 0).
+__device__ inline bool pos_code(float x, double SL, int64_t S, uint32_t& u) {
+  double t = (double)x * SL;
   if (!(fabs(t) < 4.0e15)) {
     u = 0;
     return false;
@@ -23,9 +24,10 @@ __device__ inline bool pos_code(float x, int64_t S, uint32_t& u) {
   return true;
 }
 
-// Bin centre (u + 1/2) / S, exact in float32 (u < 2^19).
-__device__ inline float pos_decode(uint32_t u, int64_t S) {
-  return ((float)u + 0.5f) * (1.0f / (float)S);
+// Bin centre (u + 1/2) L / S with LS = L / S rounded to float32 (exact when L is a power
+// of two; u + 1/2 is exact, u < 2^19).
+__device__ inline float pos_decode(uint32_t u, float LS) {
+  return ((float)u + 0.5f) * LS;
 }
 
 // j = clamp(floor(v C + 32768), 0, 65535), C = 32768 / v_max, in float64 with the

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(T256) void k_encode_keys(const float* x, int64_t n,
   uint32_t u[3];
   bool ok = true;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ok &= pos_code(x[3 * p + a], g.S, u[a]);
+  for (int a = 0; a < 3; ++a) ok &= pos_code(x[3 * p + a], g.SL, g.S, u[a]);
   if (!ok) latch_error(err, ERRBIT_RANGE);
   keys[p] = cell_key(g, u[0] >> 8, u[1] >> 8, u[2] >> 8);
   vals[p] = (uint32_t)p;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(T256) void k_encode_gather(
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       uint32_t u;
-      pos_code(x[3 * (int64_t)p + a], g.S, u);
+      pos_code(x[3 * (int64_t)p + a], g.SL, g.S, u);
       pos[3 * j + a] = (uint8_t)(u & 255u);
       int c = vel_code(v[3 * (int64_t)p + a], vmax);
       vel[3 * j + a] = (uint16_t)c;
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(T256) void k_decode(const uint8_t* pos, const uint1
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     uint32_t u = (cell[a] << 8) | pos[3 * j + a];
-    x[3 * j + a] = pos_decode(u, g.S);
+    x[3 * j + a] = pos_decode(u, g.LS);
     v[3 * j + a] = vel_decode(vel[3 * j + a], vmax);
   }
 }
@@ -321,56 +321,111 @@ __global__ __launch_bounds__(T256) void k_reduce_mesh(const float* rho, int64_t 
   if (threadIdx.x == 0) part[blockIdx.x] = lw[0] + lw[1] + lw[2] + lw[3];
 }
 
-__global__ __launch_bounds__(T256) void k_reduce_particles(pm_species sp, double* part) {
-  double s[3] = {0.0, 0.0, 0.0};
+// Per block: sum of v and of the CIC-interpolated acceleration a_i over one species'
+// particles (decoded bin centres for compressed streams), in float64, stored at the
+// block's index. off: cell offsets of a compressed stream (finds each particle's cell).
+struct RedSpecies {
+  pm_species sp;
+  const int64_t* off;
+};
+
+__device__ inline void cic_accumulate(const float* acc, int64_t ng, const float xm[3],
+                                      double a[3]) {
+  int64_t i[3];
+  float f[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float fl = floorf(xm[q]);
+    f[q] = xm[q] - fl;
+    int64_t k = (int64_t)fl % ng;
+    i[q] = k < 0 ? k + ng : k;
+  }
+  const int64_t n3 = ng * ng * ng;
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const float w = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) *
+                        (dz ? f[2] : 1.f - f[2]);
+        const int64_t node = (((i[2] + dz) % ng) * ng + (i[1] + dy) % ng) * ng +
+                             (i[0] + dx) % ng;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[q] += (double)(w * acc[q * n3 + node]);
+      }
+}
+
+__global__ __launch_bounds__(T256) void k_reduce_particles(RedSpecies rs, const float* acc,
+                                                          Geom g, double* part) {
+  const pm_species& sp = rs.sp;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const float fng = g.ngL;
+  const float rs_cell = (float)g.r / 256.f;  // mesh cells per position quantum
   for (int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x; j < sp.n;
        j += (int64_t)gridDim.x * T256) {
+    float xm[3];
+    if (sp.layout == PM_FLOAT) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float vv = sp.layout == PM_FLOAT ? sp.v[3 * j + a]
-                                       : vel_decode(sp.vel[3 * j + a], sp.hdr->v_max);
-      s[a] += (double)vv;
+      for (int a = 0; a < 3; ++a) {
+        s[a] += (double)sp.v[3 * j + a];
+        xm[a] = sp.x[3 * j + a] * fng;  // mesh units (exact for a power-of-two box)
+      }
+    } else {
+      uint32_t cell[3];
+      key_cell(g, (uint32_t)find_cell(rs.off, g.ncell3, j), cell[0], cell[1], cell[2]);
+      const float vmax = sp.hdr->v_max;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        s[a] += (double)vel_decode(sp.vel[3 * j + a], vmax);
+        const uint32_t u = (cell[a] << 8) | sp.pos[3 * j + a];
+        xm[a] = ((float)u + 0.5f) * rs_cell;  // bin centre in mesh units, exact
+      }
     }
+    if (acc) cic_accumulate(acc, g.ng, xm, s + 3);
   }
-  __shared__ double lw[3][T256 / 64];
+  __shared__ double lw[6][T256 / 64];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 6; ++a) {
     for (int d = 32; d >= 1; d >>= 1) s[a] += __shfl_xor(s[a], d, 64);
     if ((threadIdx.x & 63) == 0) lw[a][threadIdx.x >> 6] = s[a];
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
-    int a = threadIdx.x;
-    part[3 * blockIdx.x + a] = lw[a][0] + lw[a][1] + lw[a][2] + lw[a][3];
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    part[6 * blockIdx.x + a] = lw[a][0] + lw[a][1] + lw[a][2] + lw[a][3];
   }
 }
 
+struct RedMeta {
+  int n_sp;
+  double mass[4];
+  int64_t count[4];
+};
+
+// Fixed-order final sums (deterministic). out[0] mesh mass, out[1] particle mass,
+// out[2..4] total momentum, out[5..7] total sum m a; per species s, out[8 + 6 s ..] =
+// m_s sum v (3) and m_s sum a (3).
 __global__ void k_reduce_final(const double* pmesh, int nmesh_part, double cell_vol,
-                               const double* ppart, int n_sp, const double* masses,
-                               const int64_t* counts, double* out) {
-  // fixed-order final sums (deterministic)
+                               const double* ppart, RedMeta meta, double* out) {
   double m = 0.0;
   for (int i = 0; i < nmesh_part; ++i) m += pmesh[i];
   out[0] = m * cell_vol;
-  double mt = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-  for (int s = 0; s < n_sp; ++s) {
-    mt += masses[s] * (double)counts[s];
-    double sx = 0, sy = 0, sz = 0;
+  double mt = 0.0, tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < meta.n_sp; ++s) {
+    mt += meta.mass[s] * (double)meta.count[s];
+    double sum[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = 0; b < RED_BLOCKS; ++b) {
-      const double* q = ppart + 3 * (int64_t)(s * RED_BLOCKS + b);
-      sx += q[0];
-      sy += q[1];
-      sz += q[2];
+      const double* q = ppart + 6 * (int64_t)(s * RED_BLOCKS + b);
+      for (int a = 0; a < 6; ++a) sum[a] += q[a];
     }
-    px += masses[s] * sx;
-    py += masses[s] * sy;
-    pz += masses[s] * sz;
+    for (int a = 0; a < 6; ++a) {
+      out[8 + 6 * s + a] = meta.mass[s] * sum[a];
+      tot[a] += meta.mass[s] * sum[a];
+    }
   }
   out[1] = mt;
-  out[2] = px;
-  out[3] = py;
-  out[4] = pz;
-  out[5] = out[6] = out[7] = 0.0;
+  for (int a = 0; a < 6; ++a) out[2 + a] = tot[a];
 }
 
 }  // namespace
@@ -490,34 +545,37 @@ pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_
 }
 
 pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
-                     double* out) {
-  if (n_sp < 0 || n_sp > 8) return PM_ERR_ARG;
-  double* part = (double*)scratch(c, SC_MISC, (size_t)(RED_BLOCKS * (3 * 8 + 1) + 32) * 8);
+                     const float* acc, double* out) {
+  if (n_sp < 0 || n_sp > 4) return PM_ERR_ARG;
+  double* part = (double*)scratch(c, SC_MISC, (size_t)(RED_BLOCKS * (6 * 4 + 1)) * 8);
   if (!part) return PM_ERR_NOMEM;
   double* pmesh = part;
   double* ppart = part + RED_BLOCKS;
-  double* meta = ppart + 3 * 8 * RED_BLOCKS;  // masses[8], counts[8] (as bits)
-  double hm[16];
-  for (int s = 0; s < 8; ++s) {
-    hm[s] = s < n_sp ? sp[s].mass : 0.0;
-    int64_t cnt = s < n_sp ? sp[s].n : 0;
-    std::memcpy(&hm[8 + s], &cnt, 8);
-  }
-  PM_HIP_CHECK(hipMemcpyAsync(meta, hm, sizeof(hm), hipMemcpyHostToDevice, c->stream));
+  RedMeta meta{};
+  meta.n_sp = n_sp;
   int nmp = 0;
   if (rho) {
     nmp = RED_BLOCKS;
     hipLaunchKernelGGL(k_reduce_mesh, dim3(RED_BLOCKS), dim3(T256), 0, c->stream, rho,
                        c->g.ng * c->g.ng * c->g.ng, pmesh);
   }
-  for (int s = 0; s < n_sp; ++s)
-    hipLaunchKernelGGL(k_reduce_particles, dim3(RED_BLOCKS), dim3(T256), 0, c->stream, sp[s],
-                       ppart + 3 * (int64_t)s * RED_BLOCKS);
-  double dv = 1.0 / ((double)c->g.ng * c->g.ng * c->g.ng);
+  for (int s = 0; s < n_sp; ++s) {
+    meta.mass[s] = sp[s].mass;
+    meta.count[s] = sp[s].n;
+    RedSpecies rs{sp[s], nullptr};
+    if (sp[s].layout == PM_COMPRESSED) {
+      int64_t* off = (int64_t*)scratch(c, SC_SPOFF0 + s, (size_t)(c->g.ncell3 + 1) * 8);
+      if (!off) return PM_ERR_NOMEM;
+      pm_status st = run_cell_offsets(c, &sp[s], off);
+      if (st != PM_OK) return st;
+      rs.off = off;
+    }
+    hipLaunchKernelGGL(k_reduce_particles, dim3(RED_BLOCKS), dim3(T256), 0, c->stream, rs,
+                       acc, c->g, ppart + 6 * (int64_t)s * RED_BLOCKS);
+  }
+  const double dv = c->g.box * c->g.box * c->g.box / ((double)c->g.ng * c->g.ng * c->g.ng);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1), 0, c->stream, pmesh, nmp, dv, ppart,
-                     n_sp, meta, (const int64_t*)(meta + 8), out);
+                     meta, out);
   PM_LAUNCH_CHECK();
-  // the host staging array must outlive the async copy
-  PM_HIP_CHECK(hipStreamSynchronize(c->stream));
   return PM_OK;
 }

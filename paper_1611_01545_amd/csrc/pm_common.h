@@ -57,6 +57,10 @@ struct Geom {
   int64_t ncell3;  // nc^3
   int64_t nbrick;  // (nc/B)^3
   int64_t S;       // 256 nc (position codes per box side)
+  double box;      // box side L (positions in [0, L))
+  float ngL;       // ng / L: mesh cells per unit length (float)
+  double SL;       // S / L: position codes per unit length
+  float LS;        // L / S: length of one position code (float)
 };
 
 __host__ __device__ inline uint32_t cell_key(const Geom& g, uint32_t cx, uint32_t cy,
@@ -155,6 +159,7 @@ enum ScratchId {
   SC_PARTS,        // per-workgroup partial results of grid reductions
   SC_SPEC,         // float [ng^3] spectrum scratch of the force transforms
   SC_FOLD,         // first-stage results of the grid min / max folds
+  SC_NMOV,         // int64 [4]: mover count of each species (device-side)
   SC_N
 };
 
@@ -189,6 +194,11 @@ pm_status scan_counts(pm_context* c, const uint8_t* count, const uint64_t* esc,
 pm_status radix_sort_pairs(pm_context* c, uint32_t** keys, uint32_t** vals,
                            uint32_t** keys_alt, uint32_t** vals_alt, int64_t n,
                            int bits);
+// the same with the pair count read on the device (*n_dev <= n_max): nothing waits on
+// the host for a count the device produced
+pm_status radix_sort_pairs_dev(pm_context* c, uint32_t** keys, uint32_t** vals,
+                               uint32_t** keys_alt, uint32_t** vals_alt, int64_t n_max,
+                               const int64_t* n_dev, int bits);
 
 // codec (pm_codec.hip)
 pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64_t* perm);
@@ -199,7 +209,7 @@ pm_status run_finalize_counts(pm_context* c, const uint32_t* cnt32, const uint64
 pm_status run_pack(pm_context* c, const pm_species* sp, int32_t sid, uint8_t* buf,
                    int64_t cap, int64_t* used);
 pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
-                     double* out);
+                     const float* acc, double* out);
 
 // deposit (pm_deposit.hip)
 pm_status run_deposit(pm_context* c, const pm_species* sp, int n_sp, float* rho);

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
 // Unsorted float particles: fixed-point weights accumulated with 64-bit global atomics
 // (still order independent), then converted.
 __global__ __launch_bounds__(256) void k_deposit_float(const float* x, int64_t n, int64_t ng,
-                                                      double scale,
+                                                      float ngL, double scale,
                                                       unsigned long long* acc) {
   int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_deposit_float(const float* x, int64_t n
   double f[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double u = (double)x[3 * p + a] * (double)ng;  // exact (ng a power of two)
+    double u = (double)(x[3 * p + a] * ngL);  // mesh units (exact for a power-of-two box)
     double fl = floor(u);
     f[a] = u - fl;
     int64_t k = (int64_t)fl % ng;
@@ -274,7 +274,7 @@ pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
                            int64_t* const* offs, float* rho) {
   const Geom& g = c->g;
   if (n_sp > MAX_SP) return PM_ERR_ARG;
-  const double ng3 = (double)g.ng * g.ng * g.ng;
+  const double ng3 = (double)g.ng * g.ng * g.ng / (g.box * g.box * g.box);  // 1 / Delta^3
   DepArgs A{};
   A.n_sp = 0;
   for (int s = 0; s < n_sp; ++s) {
@@ -334,9 +334,9 @@ pm_status run_deposit(pm_context* c, const pm_species* sp, int n_sp, float* rho)
     if (sp[s].n == 0 || sp[s].mass == 0.0) continue;
     double scale = 0x1p32 * (sp[s].mass / mmax);
     hipLaunchKernelGGL(k_deposit_float, dim3((unsigned)cdiv(sp[s].n, 256)), dim3(256), 0,
-                       c->stream, sp[s].x, sp[s].n, g.ng, scale, acc);
+                       c->stream, sp[s].x, sp[s].n, g.ng, g.ngL, scale, acc);
   }
-  double unit = mmax > 0 ? mmax * 0x1p-32 * (double)n3 : 0.0;
+  double unit = mmax > 0 ? mmax * 0x1p-32 * (double)n3 / (g.box * g.box * g.box) : 0.0;
   hipLaunchKernelGGL(k_fixed_to_float, dim3((unsigned)cdiv(n3, 256)), dim3(256), 0, c->stream,
                      acc, n3, unit, rho);
   PM_LAUNCH_CHECK();

@@ -638,7 +638,8 @@ __device__ double bessel_k1(double x) {
   return sum * h;
 }
 
-__global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, double eps) {
+__global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, double eps,
+                             double box) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nent) return;
   double val = 0.0;
@@ -647,7 +648,9 @@ __global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, dou
     double g;
     if (eps > 0) g = -4.0 * 3.141592653589793238462643 * G * eps * bessel_k1(k * eps) / k;
     else g = -4.0 * 3.141592653589793238462643 * G / (k * k);
-    val = g / ((double)n * (double)n * (double)n);
+    // the 1/n^3 of the inverse transform, and the box: a density in mass per unit volume
+    // of a box of side L has the force L a_1 of the same mesh values in the unit box
+    val = g * box / ((double)n * (double)n * (double)n);
   }
   ktab[q] = (float)val;
 }
@@ -849,7 +852,7 @@ pm_status build_kernel_table(pm_context* c) {
   PM_HIP_CHECK(hipMalloc(&c->ktab, (size_t)c->ktab_n * sizeof(float)));
   double eps = c->cfg.soft_cells / (double)n;
   hipLaunchKernelGGL(k_build_ktab, dim3((unsigned)cdiv(c->ktab_n, 256)), dim3(256), 0,
-                     c->stream, c->ktab, c->ktab_n, n, c->cfg.G, eps);
+                     c->stream, c->ktab, c->ktab_n, n, c->cfg.G, eps, c->cfg.box);
   PM_LAUNCH_CHECK();
   const int64_t h1 = n / 2 + 1, ng3 = h1 * h1 * h1;
   PM_HIP_CHECK(hipMalloc(&c->gtab, (size_t)ng3 * sizeof(float)));

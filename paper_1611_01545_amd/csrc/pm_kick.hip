@@ -38,7 +38,8 @@ constexpr int KT = 256;  // threads per workgroup
 // ------------------------------------------------------------ float layout --
 __global__ __launch_bounds__(KT) void k_kick_float(const float* x, const float* v, float* xo,
                                                   float* vo, int64_t n, const float* acc,
-                                                  int64_t ng, float ck, float cd) {
+                                                  int64_t ng, float ngL, float box, float ck,
+                                                  float cd) {
   int64_t p = (int64_t)blockIdx.x * KT + threadIdx.x;
   if (p >= n) return;
   const int64_t n3 = ng * ng * ng;
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(KT) void k_kick_float(const float* x, const float* 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     xv[a] = x[3 * p + a];
-    float u = xv[a] * (float)ng;  // exact (ng a power of two)
+    float u = xv[a] * ngL;  // mesh units (exact for a power-of-two box)
     float fl = floorf(u);
     f[a] = u - fl;
     int64_t k = (int64_t)fl % ng;
@@ -71,8 +72,8 @@ __global__ __launch_bounds__(KT) void k_kick_float(const float* x, const float* 
   for (int a = 0; a < 3; ++a) {
     float v1 = v[3 * p + a] + ck * a3[a];
     float x1 = xv[a] + cd * v1;
-    x1 -= floorf(x1);
-    if (x1 >= 1.f) x1 = 0.f;
+    x1 -= box * floorf(x1 / box);  // periodic wrap into [0, L)
+    if (x1 >= box || x1 < 0.f) x1 = 0.f;
     vo[3 * p + a] = v1;
     xo[3 * p + a] = x1;
   }
@@ -127,7 +128,7 @@ struct KickArgs {
   int n_sp;
   const float* acc;  // [3][ng^3]
   float ck;
-  double cdS;        // c_d * S (position codes per unit velocity)
+  double cdS;        // c_d S / L (position codes per unit velocity)
 };
 
 // Codec constants of one species (uniform).
@@ -638,26 +639,31 @@ __device__ inline int64_t lower_bound_u32(const uint32_t* a, int64_t lo, int64_t
 
 // astart[b] = first sorted mover whose new cell lies in brick b or later, b in [0, nbrick]:
 // the arrivals of brick b are the sorted movers [astart[b], astart[b + 1]).
-__global__ __launch_bounds__(KT) void k_brick_arrivals(const uint32_t* skey, int64_t nm, int B3,
-                                                      int64_t nbrick, int64_t* astart) {
+// The mover count nm is read on the device (*nmd): the host never waits for it.
+__global__ __launch_bounds__(KT) void k_brick_arrivals(const uint32_t* skey, const int64_t* nmd,
+                                                      int B3, int64_t nbrick, int64_t* astart) {
   const int64_t b = (int64_t)blockIdx.x * KT + threadIdx.x;
   if (b > nbrick) return;
-  astart[b] = lower_bound_u32(skey, 0, nm, (uint32_t)(b * B3));
+  astart[b] = lower_bound_u32(skey, 0, *nmd, (uint32_t)(b * B3));
 }
 
 // per group of sorted movers with the same new cell: add arrivals (low 32 bits) and
-// arrivals from earlier bricks (high 32 bits) to the cell's count
+// arrivals from earlier bricks (high 32 bits) to the cell's count. A fixed grid strides
+// over the nm sorted movers.
 __global__ __launch_bounds__(KT) void k_arrivals(const uint32_t* skey, const uint32_t* sidx,
-                                                int64_t nm, const int64_t* off_in, int B3,
-                                                uint64_t* cnt) {
-  int64_t s = (int64_t)blockIdx.x * KT + threadIdx.x;
-  if (s >= nm) return;
-  const uint32_t k = skey[s];
-  if (s > 0 && skey[s - 1] == k) return;  // group leader only
-  const int64_t ge = lower_bound_u32(skey, s, nm, k + 1);
-  const int64_t bstart = off_in[(int64_t)(k / (uint32_t)B3) * B3];  // first old index of the cell's brick
-  const int64_t nb = lower_bound_u32(sidx, s, ge, (uint32_t)bstart) - s;
-  atomicAdd((unsigned long long*)&cnt[k], (unsigned long long)(((uint64_t)nb << 32) | (uint64_t)(ge - s)));
+                                                const int64_t* nmd, const int64_t* off_in,
+                                                int B3, uint64_t* cnt) {
+  const int64_t nm = *nmd;
+  for (int64_t s = (int64_t)blockIdx.x * KT + threadIdx.x; s < nm;
+       s += (int64_t)gridDim.x * KT) {
+    const uint32_t k = skey[s];
+    if (s > 0 && skey[s - 1] == k) continue;  // group leader only
+    const int64_t ge = lower_bound_u32(skey, s, nm, k + 1);
+    const int64_t bstart = off_in[(int64_t)(k / (uint32_t)B3) * B3];  // first old index of the cell's brick
+    const int64_t nb = lower_bound_u32(sidx, s, ge, (uint32_t)bstart) - s;
+    atomicAdd((unsigned long long*)&cnt[k],
+              (unsigned long long)(((uint64_t)nb << 32) | (uint64_t)(ge - s)));
+  }
 }
 
 // The two re-sort kernels below give each brick one wave (WB bricks per workgroup) and
@@ -810,7 +816,8 @@ pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
   if (in->n == 0) return PM_OK;
   ProfScope ps(c, ST_KICK);
   hipLaunchKernelGGL(k_kick_float, dim3((unsigned)cdiv(in->n, KT)), dim3(KT), 0, c->stream,
-                     in->x, in->v, out->x, out->v, in->n, acc, c->g.ng, (float)ck, (float)cd);
+                     in->x, in->v, out->x, out->v, in->n, acc, c->g.ng, c->g.ngL,
+                     (float)c->g.box, (float)ck, (float)cd);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -851,7 +858,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
   A.n_sp = n_sp;
   A.acc = acc;
   A.ck = (float)ck;
-  A.cdS = cd * (double)g.S;
+  A.cdS = cd * g.SL;
   for (int s = 0; s < n_sp; ++s) {
     KickSpecies& S = A.sp[s];
     S.n = in[s].n;
@@ -901,44 +908,47 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
         return st0;
   }
   const size_t place_lds = (size_t)WB * B3 * 12;
+  int64_t* nmov = (int64_t*)scratch(c, SC_NMOV, (size_t)MAXSP * 8);
+  if (!nmov) return PM_ERR_NOMEM;
   for (int s = 0; s < n_sp; ++s) {
     const int64_t n = in[s].n;
     const KickSpecies& S = A.sp[s];
     ProfScope ps(c, ST_RESORT);
     pm_status st = scan_u32(c, S.mcnt, g.nbrick, moff);
     if (st != PM_OK) return st;
-    // the mover count is data dependent: read it back (one small synchronisation)
-    int64_t nm = 0;
-    PM_HIP_CHECK(hipMemcpyAsync(&nm, moff + g.nbrick, 8, hipMemcpyDeviceToHost, c->stream));
-    PM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    // the mover count stays on the device; the kernels below read it there and are
+    // launched for the worst case (every particle a mover), so nothing waits on the host
+    int64_t* nmd = nmov + s;
+    hipLaunchKernelGGL(k_read_total, dim3(1), dim3(1), 0, c->stream, moff, g.nbrick, nmd);
     uint32_t* sk = skey + nbase[s];
     uint32_t* si = sidx + nbase[s];
-    if (nm > 0) {
+    if (n > 0) {
       hipLaunchKernelGGL(k_compact_movers, dim3((unsigned)cdiv(g.nbrick, WB)), dim3(64 * WB),
                          0, c->stream, S.off, S.mcnt, moff, B3, g.nbrick, n, S.tdig, S.mkey,
                          sk, si);
       PM_LAUNCH_CHECK();
       // stable sort (old order preserved inside each new cell)
       uint32_t *k1 = sk, *v1 = si, *k2 = S.mkey, *v2 = midx + nbase[s];
-      st = radix_sort_pairs(c, &k1, &v1, &k2, &v2, nm, 3 * (g.lgB + g.lgnb));
+      st = radix_sort_pairs_dev(c, &k1, &v1, &k2, &v2, n, nmd, 3 * (g.lgB + g.lgnb));
       if (st != PM_OK) return st;
       sk = k1;
       si = v1;
-      hipLaunchKernelGGL(k_arrivals, dim3((unsigned)cdiv(nm, KT)), dim3(KT), 0, c->stream, sk,
-                         si, nm, S.off, B3, S.cnt);
-      PM_LAUNCH_CHECK();
-      // the mover offsets are spent: moff now takes each brick's run of arrivals
-      hipLaunchKernelGGL(k_brick_arrivals, dim3((unsigned)cdiv(g.nbrick + 1, KT)), dim3(KT), 0,
-                         c->stream, sk, nm, B3, g.nbrick, moff);
+      const int64_t ag = std::min<int64_t>(cdiv(n, KT), 2048);
+      hipLaunchKernelGGL(k_arrivals, dim3((unsigned)ag), dim3(KT), 0, c->stream, sk, si, nmd,
+                         S.off, B3, S.cnt);
       PM_LAUNCH_CHECK();
     }
+    // the mover offsets are spent: moff now takes each brick's run of arrivals
+    hipLaunchKernelGGL(k_brick_arrivals, dim3((unsigned)cdiv(g.nbrick + 1, KT)), dim3(KT), 0,
+                       c->stream, sk, nmd, B3, g.nbrick, moff);
+    PM_LAUNCH_CHECK();
     st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
     hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)cdiv(g.nbrick, WB)), dim3(64 * WB),
                        place_lds, c->stream, S.off, S.tdig, S.tpos, S.tvel, S.cnt, off_new,
-                       B3, 3 * g.lgB, g.nbrick, sk, si, nm > 0 ? moff : nullptr, out[s].pos,
-                       out[s].vel, pm, n, c->err);
+                       B3, 3 * g.lgB, g.nbrick, sk, si, moff, out[s].pos, out[s].vel, pm, n,
+                       c->err);
     PM_LAUNCH_CHECK();
     st = run_finalize_counts(c, nullptr, S.cnt, &out[s]);
     if (st != PM_OK) return st;

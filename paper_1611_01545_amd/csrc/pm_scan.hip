@@ -12,25 +12,38 @@ namespace {
 constexpr int RS_THREADS = 256;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
+constexpr int64_t RS_GMAX = 1024;  // workgroups of a sort whose length is on the device
+
+// The pair count is n_host, or *n_dev when given (a count produced on the device, so
+// that the host never waits for it). Workgroup b of nblk takes the contiguous range
+// [lo, hi) of whole rounds of RS_THREADS pairs; ranges follow the workgroup order, so the
+// digit histogram laid out [digit][workgroup] and scanned gives stable destinations.
+__device__ inline void rs_range(int64_t n_host, const int64_t* n_dev, int64_t nblk,
+                                int64_t b, int64_t& lo, int64_t& hi) {
+  const int64_t n = n_dev ? *n_dev : n_host;
+  const int64_t per = ((n + nblk - 1) / nblk + RS_THREADS - 1) / RS_THREADS * RS_THREADS;
+  lo = b * per < n ? b * per : n;
+  hi = lo + per < n ? lo + per : n;
+}
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
-                                                        int shift, int64_t nblk,
-                                                        uint32_t* hist) {
+                                                        const int64_t* n_dev, int shift,
+                                                        int64_t nblk, uint32_t* hist) {
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * RS_TILE;
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    int64_t i = base + r * RS_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
-  }
+  int64_t lo, hi;
+  rs_range(n, n_dev, nblk, blockIdx.x, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += RS_THREADS)
+    atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
                                                            const uint32_t* vin, int64_t n,
-                                                           int shift, int64_t nblk,
+                                                           const int64_t* n_dev, int shift,
+                                                           int64_t nblk,
                                                            const int64_t* hoff,
                                                            uint32_t* kout, uint32_t* vout) {
   __shared__ uint32_t run[256];
@@ -38,14 +51,14 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   run[threadIdx.x] = 0;
-  int64_t base = (int64_t)blockIdx.x * RS_TILE;
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    if (base + r * RS_THREADS >= n) break;  // uniform across the block
+  int64_t lo, hi;
+  rs_range(n, n_dev, nblk, blockIdx.x, lo, hi);
+  for (int64_t base = lo; base < hi; base += RS_THREADS) {  // uniform across the block
 #pragma unroll
     for (int q = 0; q < RS_THREADS / 64; ++q) wcnt[q][threadIdx.x] = 0;
     __syncthreads();
-    int64_t i = base + r * RS_THREADS + threadIdx.x;
-    bool valid = i < n;
+    int64_t i = base + threadIdx.x;
+    bool valid = i < hi;
     uint32_t key = valid ? kin[i] : 0u;
     uint32_t val = valid ? vin[i] : 0u;
     uint32_t d = (key >> shift) & 255u;
@@ -206,22 +219,21 @@ pm_status scan_counts(pm_context* c, const uint8_t* count, const uint64_t* esc,
   return scan_generic(c, GetCount{count, esc, hdr}, n, out);
 }
 
-pm_status radix_sort_pairs(pm_context* c, uint32_t** keys, uint32_t** vals,
-                           uint32_t** keys_alt, uint32_t** vals_alt, int64_t n,
-                           int bits) {
-  if (n <= 1 || bits <= 0) return PM_OK;
-  int64_t nblk = cdiv(n, RS_TILE);
+namespace {
+pm_status radix_sort_impl(pm_context* c, uint32_t** keys, uint32_t** vals,
+                          uint32_t** keys_alt, uint32_t** vals_alt, int64_t n,
+                          const int64_t* n_dev, int64_t nblk, int bits) {
   uint32_t* hist = (uint32_t*)scratch(c, SC_HIST, (size_t)nblk * 256 * sizeof(uint32_t));
   int64_t* hoff = (int64_t*)scratch(c, SC_HOFF, ((size_t)nblk * 256 + 1) * sizeof(int64_t));
   if (!hist || !hoff) return PM_ERR_NOMEM;
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, c->stream,
-                       *keys, n, shift, nblk, hist);
+                       *keys, n, n_dev, shift, nblk, hist);
     PM_LAUNCH_CHECK();
     pm_status s = scan_u32(c, hist, nblk * 256, hoff);
     if (s != PM_OK) return s;
     hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, c->stream,
-                       *keys, *vals, n, shift, nblk, hoff, *keys_alt, *vals_alt);
+                       *keys, *vals, n, n_dev, shift, nblk, hoff, *keys_alt, *vals_alt);
     PM_LAUNCH_CHECK();
     uint32_t* t = *keys;
     *keys = *keys_alt;
@@ -231,4 +243,22 @@ pm_status radix_sort_pairs(pm_context* c, uint32_t** keys, uint32_t** vals,
     *vals_alt = t;
   }
   return PM_OK;
+}
+}  // namespace
+
+pm_status radix_sort_pairs(pm_context* c, uint32_t** keys, uint32_t** vals,
+                           uint32_t** keys_alt, uint32_t** vals_alt, int64_t n,
+                           int bits) {
+  if (n <= 1 || bits <= 0) return PM_OK;
+  return radix_sort_impl(c, keys, vals, keys_alt, vals_alt, n, nullptr, cdiv(n, RS_TILE),
+                         bits);
+}
+
+pm_status radix_sort_pairs_dev(pm_context* c, uint32_t** keys, uint32_t** vals,
+                               uint32_t** keys_alt, uint32_t** vals_alt, int64_t n_max,
+                               const int64_t* n_dev, int bits) {
+  if (n_max <= 1 || bits <= 0) return PM_OK;
+  int64_t nblk = cdiv(n_max, RS_TILE);
+  if (nblk > RS_GMAX) nblk = RS_GMAX;
+  return radix_sort_impl(c, keys, vals, keys_alt, vals_alt, n_max, n_dev, nblk, bits);
 }

@@ -93,7 +93,8 @@ class PMContext:
     """A libpm context: one mesh size, one compression-cell size, one HIP stream."""
 
     def __init__(self, n_mesh: int, n_cell: int, brick: int | None = None,
-                 G: float = G_UNIT, soft_cells: float = 1.0, device: str = "cuda"):
+                 G: float = G_UNIT, soft_cells: float = 1.0, device: str = "cuda",
+                 box: float = 1.0):
         self.lib = _lib.lib()
         dev = torch.device(device)
         if dev.type != "cuda" or not torch.cuda.is_available():
@@ -105,8 +106,8 @@ class PMContext:
         if brick is None:
             brick = max(1, min(8, n_cell, 16 // max(1, n_mesh // n_cell)))
         self.n_mesh, self.n_cell, self.brick = n_mesh, n_cell, brick
-        self.G, self.soft_cells = G, soft_cells
-        cfg = PmConfig(n_mesh, n_cell, brick, 0, G, soft_cells)
+        self.G, self.soft_cells, self.box = G, soft_cells, float(box)
+        cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G, soft_cells)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         check(self.lib.pm_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -123,6 +124,22 @@ class PMContext:
             self.close()
         except Exception:
             pass
+
+    @staticmethod
+    def query_sizes(n_mesh: int, n_cell: int, brick: int, n_max: int, n_sp: int,
+                    box: float = 1.0) -> dict:
+        """pm_query_sizes: device bytes of a configuration (no GPU needed)."""
+        lib = _lib.lib()
+        cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G_UNIT, 1.0)
+        out = _lib.PmSizes()
+        check(lib.pm_query_sizes(ctypes.byref(cfg), int(n_max), int(n_sp), ctypes.byref(out)),
+              "pm_query_sizes")
+        return {name: getattr(out, name) for name, _ in _lib.PmSizes._fields_}
+
+    def scratch_bytes(self) -> int:
+        v = ctypes.c_int64()
+        check(self.lib.pm_scratch_bytes(self.h, ctypes.byref(v)), "pm_scratch_bytes")
+        return v.value
 
     # ----------------------------------------------------------- allocation --
     def float_species(self, x, v, mass: float) -> FloatSpecies:
@@ -241,10 +258,14 @@ class PMContext:
               "pm_loss_density_vjp")
         return loss, lam
 
-    def reduce(self, species, rho: torch.Tensor | None = None) -> np.ndarray:
-        out = torch.zeros(8, dtype=torch.float64, device=self.device)
+    def reduce(self, species, rho: torch.Tensor | None = None,
+               acc: torch.Tensor | None = None) -> np.ndarray:
+        """pm_reduce: [mesh mass, particle mass, sum m v (3), sum m a (3), then per
+        species m sum v (3), m sum a (3)] as float64."""
+        out = torch.zeros(8 + 6 * len(species), dtype=torch.float64, device=self.device)
         arr = _species_array(species) if species else None
-        check(self.lib.pm_reduce(self.h, arr, len(species), _ptr(rho), _ptr(out)), "pm_reduce")
+        check(self.lib.pm_reduce(self.h, arr, len(species), _ptr(rho), _ptr(acc), _ptr(out)),
+              "pm_reduce")
         return out.cpu().numpy()
 
     def pack_size(self, cs: CompressedSpecies) -> int:

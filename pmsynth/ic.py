@@ -18,18 +18,23 @@ seeded generators stand in for them with the same structure:
 Units: box side 1, total CDM mass 1 (mean CDM density 1). The neutrino particle mass
 is m_cdm / 8 * (Omega_nu / Omega_cdm) with Omega_nu / Omega_cdm = 0.01.
 
-All randomness comes from numpy's PCG64 generator, one independent stream per drawn
-quantity (SeedSequence.spawn), consumed in fixed chunks so that results do not depend
-on the machine. Every array is returned as float32, the precision the step consumes.
+All randomness comes from numpy's PCG64 generator: one independent stream per fixed
+chunk of 2^22 values (SeedSequence.spawn), each chunk drawing its quantities in a fixed
+order, so that results do not depend on the machine or on how many threads fill the
+chunks. Every array is returned as float32, the precision the step consumes.
 """
 
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
+import os
 
 import numpy as np
+import scipy.fft
 
 CHUNK = 1 << 22  # fixed draw granularity (part of the definition of the streams)
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 OMEGA_NU_OVER_OMEGA_C = 0.01
 NU_PER_CDM_SIDE = 2  # 8:1 in count
@@ -83,17 +88,19 @@ CONFIGS = {
 }
 
 
-def _streams(seed: int, k: int):
+def _chunk_streams(seed: int, n: int):
+    """One PCG64 stream per chunk of CHUNK values of an n-value quantity."""
     ss = np.random.SeedSequence(seed)
-    return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(k)]
+    return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn((n + CHUNK - 1) // CHUNK)]
 
 
-def _chunked(rng, n: int, draw, out: np.ndarray):
-    """Fill out[0:n] by drawing fixed-size chunks from one stream."""
-    for s in range(0, n, CHUNK):
-        e = min(n, s + CHUNK)
-        out[s:e] = draw(rng, e - s)
-    return out
+def _fill_chunks(n: int, seed: int, fill):
+    """Call fill(rng, start, end) for every chunk, the chunks spread over threads (numpy's
+    generators release the GIL while they fill)."""
+    rngs = _chunk_streams(seed, n)
+    with concurrent.futures.ThreadPoolExecutor(WORKERS) as ex:
+        list(ex.map(lambda k: fill(rngs[k], k * CHUNK, min(n, (k + 1) * CHUNK)),
+                    range(len(rngs))))
 
 
 def cdm_zeldovich(n_p: int, n_mesh: int, n_s: float, sigma_cells: float, seed: int):
@@ -102,12 +109,15 @@ def cdm_zeldovich(n_p: int, n_mesh: int, n_s: float, sigma_cells: float, seed: i
     Returns (x, v) float32 [n_p^3][3]; particle index (iz*n_p + iy)*n_p + ix,
     columns (x, y, z). The RMS of |psi| equals sigma_cells / n_mesh.
     """
-    (rng,) = _streams(seed, 1)
     n3 = n_p ** 3
     white = np.empty(n3, dtype=np.float64)
-    _chunked(rng, n3, lambda r, m: r.standard_normal(m), white)
+
+    def fill(r, a, b):
+        white[a:b] = r.standard_normal(b - a)
+
+    _fill_chunks(n3, seed, fill)
     white = white.reshape(n_p, n_p, n_p)  # [z][y][x]
-    dk = np.fft.rfftn(white)
+    dk = scipy.fft.rfftn(white, workers=WORKERS)
     del white
     fz = np.fft.fftfreq(n_p, d=1.0 / n_p)  # integer wave numbers
     fx = np.fft.rfftfreq(n_p, d=1.0 / n_p)
@@ -122,7 +132,8 @@ def cdm_zeldovich(n_p: int, n_mesh: int, n_s: float, sigma_cells: float, seed: i
     dk *= amp
     psi = np.empty((n3, 3), dtype=np.float64)
     for col, nn in ((0, nx), (1, ny), (2, nz)):
-        comp = np.fft.irfftn(1j * nn * inv_k2 * dk, s=(n_p, n_p, n_p), axes=(0, 1, 2))
+        comp = scipy.fft.irfftn(1j * nn * inv_k2 * dk, s=(n_p, n_p, n_p), axes=(0, 1, 2),
+                                workers=WORKERS)
         psi[:, col] = comp.reshape(-1)
         del comp
     del dk
@@ -157,24 +168,25 @@ FD_MEAN = 3.15137
 
 
 def neutrinos_fermi_dirac(n_p: int, mean_speed: float, seed: int):
-    """Uniform positions, isotropic directions, Fermi-Dirac speeds with the given mean."""
-    rpos, rdir, rspd = _streams(seed, 3)
+    """Uniform positions, isotropic directions, Fermi-Dirac speeds with the given mean.
+    Each chunk draws its positions, then directions, then speeds from its own stream."""
     n = n_p ** 3
     x = np.empty((n, 3), dtype=np.float32)
     v = np.empty((n, 3), dtype=np.float32)
     cdf, p = fd_speed_table()
     scale = mean_speed / FD_MEAN
-    for s in range(0, n, CHUNK):
-        e = min(n, s + CHUNK)
+
+    def fill(r, s, e):
         m = e - s
-        xs = rpos.random((m, 3))
-        xs32 = xs.astype(np.float32)
+        xs32 = r.random((m, 3)).astype(np.float32)
         xs32[xs32 >= np.float32(1.0)] = np.float32(0.0)
         x[s:e] = xs32
-        d = rdir.standard_normal((m, 3))
+        d = r.standard_normal((m, 3))
         d /= np.linalg.norm(d, axis=1, keepdims=True)
-        t = np.interp(rspd.random(m), cdf, p)
+        t = np.interp(r.random(m), cdf, p)
         v[s:e] = (d * (t * scale)[:, None]).astype(np.float32)
+
+    _fill_chunks(n, seed, fill)
     return x, v
 
 

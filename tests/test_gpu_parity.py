@@ -249,11 +249,68 @@ def test_compressed_step_species_count(n_sp, n_mesh):
     _step_against_oracle(c, species, n_mesh, a.n_cell, a.dt)
 
 
-def _step_against_oracle(c, species, n_mesh, n_cell, dt):
+def _dense_species(seed):
+    """The two-species recipe at 64^3 with four CDM clumps: cells holding 600, 256, 255
+    and 254 particles, nearly at rest, so that they keep >= 255 (escape) or < 255 through
+    the step; the neutrinos stream through the same cells."""
+    wl = small_two_species(16, 64, seed_offset=seed)
+    rng = np.random.default_rng(seed)
+    cdm, nu = wl.species
+    x = cdm.x.copy()
+    v = cdm.v.copy()
+    q = 1.0 / (256 * wl.n_cell)
+    at = 0
+    for cell, k in (((3, 4, 5), 600), ((10, 2, 7), 256), ((0, 15, 15), 255), ((8, 8, 8), 254)):
+        centre = (np.array(cell) + 0.5) / wl.n_cell
+        x[at:at + k] = (centre + q * rng.uniform(-20, 20, (k, 3))).astype(np.float32)
+        v[at:at + k] *= np.float32(1e-3)
+        at += k
+    return wl, [types.SimpleNamespace(x=x, v=v, mass=cdm.mass), nu]
+
+
+def test_compressed_step_dense_cells_match_oracle():
+    """Cells at and above the escape count (>= 255) before and after a step: counts,
+    escape table, codes (tie-zone rule) and the re-sort permutation against the oracle."""
+    wl, species = _dense_species(8)
+    c = ctx(64, wl.n_cell)
+    _step_against_oracle(c, species, 64, wl.n_cell, wl.dt)
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in species]
+    # the clumps share their cells with lattice particles: count with the oracle
+    want = codec.encode(species[0].x, species[0].v, wl.n_cell, c.brick)["esc"].shape[0]
+    assert int(dev[0].header()["n_esc"]) == want >= 3
+    c.close()
+
+
+def test_compressed_step_escape_capacity_latched():
+    """An output escape table too small for the step's cells >= 255: pm_sync reports
+    PM_ERR_CAPACITY with the entries needed, and the context keeps working."""
+    from paper_1611_01545_amd._lib import PMError
+    wl, species = _dense_species(9)
+    c = ctx(64, wl.n_cell)
+    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in species]
+    c.sync()
+    ok = c.step(dev, wl.dt)  # default capacity
+    c.sync()
+    need = int(ok[0].header()["n_esc"])
+    assert need >= 2
+    out = [c.empty_compressed(d.n, d.mass, cap_esc=1) for d in dev]
+    c.step(dev, wl.dt, out=out)
+    with pytest.raises(PMError) as e:
+        c.sync()
+    assert e.value.code == 5  # PM_ERR_CAPACITY
+    assert c.last_error_detail() == need
+    again = c.step(dev, wl.dt)  # the latch is cleared: the context works on
+    c.sync()
+    for a, b in zip(again, ok):
+        assert torch.equal(a.pos, b.pos) and torch.equal(a.count, b.count)
+    c.close()
+
+
+def _step_against_oracle(c, species, n_mesh, n_cell, dt, out=None):
     dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in species]
     rho = c.deposit(dev)
     acc, amax = c.force(rho)
-    out, perms = c.kick_drift_perm(dev, acc, amax, dt, dt)
+    out, perms = c.kick_drift_perm(dev, acc, amax, dt, dt, out=out)
     c.sync()
     states = [c.to_host(d) for d in dev]
     masses = [sp.mass for sp in species]
@@ -261,17 +318,21 @@ def _step_against_oracle(c, species, n_mesh, n_cell, dt):
     assert density_close(rho.cpu().numpy(), diag["rho"]) <= 1e-5
     assert rel_rms(acc.cpu().numpy(), diag["a_mesh"]) <= 1e-4
     S = 256 * n_cell
-    a_scale = np.sqrt(np.mean(diag["a_mesh"] ** 2))
+    a_rms = np.sqrt(np.mean(diag["a_mesh"] ** 2))
+    ties = 0
     for o, ns, d, perm in zip(out, new, diag["species"], perms):
         h = c.to_host(o)
         pm = perm.cpu().numpy()
         assert np.array_equal(np.sort(pm), np.arange(pm.size))
         ug, jg = _codes_old_order(h, pm)
-        # position codes: equal unless the oracle's pre-floor value is within the
-        # propagated tolerance of an integer (force tolerance 1e-4 of the mesh scale
-        # plus float32 rounding of v')
-        dv = abs(dt) * 1e-4 * a_scale * 10 + 2.0 ** -22 * np.abs(d["v_new"])
-        tau_x = dt * S * dv + 1e-6
+        # tie zone: the oracle's pre-floor value lies within the propagated tolerance of
+        # an integer. A force within the 1e-4 relative RMS tolerance differs at a particle
+        # by at most 1e-4 (|a_i| + RMS(a)); v' = v + c_k a_i rounds once more in float32
+        # (2^-23 |v'| + 2^-23 |c_k a_i|); the velocity code scales v' by a power of two
+        # and the drift multiplies it by c_d S / L in float64.
+        ai = np.abs(d["acc"])
+        dv = abs(dt) * (1e-4 * (ai + a_rms) + 2.0 ** -23 * ai) + 2.0 ** -23 * np.abs(d["v_new"])
+        tau_x = dt * S * dv + 1e-6 * np.maximum(1.0, np.abs(d["pos_pre"]))
         du = (ug - d["u_new"] + S // 2) % S - S // 2
         bad = du != 0
         assert np.all(np.abs(du[bad]) <= 1)
@@ -286,12 +347,23 @@ def _step_against_oracle(c, species, n_mesh, n_cell, dt):
         assert np.all(np.abs(dj[badv]) <= 1)
         assert np.all(frac_dist(d["vel_pre"][badv]) <= tau_v[badv])
         assert badv.mean() < 1e-3
+        ties += int(bad.sum() + badv.sum())
+        # counts and escape table: the oracle's when every code agrees, and in any case
+        # the counts of the GPU's own new codes (the escape rebuild after the kick)
+        keys_new = codec.cell_keys(ug >> 8, n_cell, c.brick)
+        cnt, esc = codec.build_counts(np.sort(keys_new), n_cell)
+        assert np.array_equal(h["count"], cnt)
+        assert np.array_equal(np.asarray(h["esc"], dtype=np.uint64).reshape(-1, 2), esc)
+        if not bad.any():
+            assert np.array_equal(h["count"], ns["count"])
+            assert np.array_equal(np.asarray(h["esc"]).reshape(-1, 2).astype(np.uint64),
+                                  np.asarray(ns["esc"]).reshape(-1, 2).astype(np.uint64))
         # the stream is the stable cell sort of the GPU's own new codes
-        keys = codec.cell_keys(ug >> 8, n_cell, c.brick)
-        order = np.argsort(keys, kind="stable")
+        order = np.argsort(keys_new, kind="stable")
         assert np.array_equal(order, pm)
         assert np.array_equal(codec.full_counts(h),
-                              np.bincount(keys, minlength=n_cell ** 3))
+                              np.bincount(keys_new, minlength=n_cell ** 3))
+    return ties
 
 
 def test_step_equals_pieces_and_is_deterministic():
@@ -356,20 +428,46 @@ def test_pack_escape_and_corruption():
         c.unpack(buf[:-3], cs.n)
 
 
-def test_reduce_mass_momentum():
+@pytest.mark.parametrize("layout", ["compressed", "float"])
+def test_reduce_mass_momentum_force(layout):
+    """pm_reduce against the oracle: mass, per-species momentum m sum v and m sum a with a
+    the CIC interpolation of the force mesh; the total sum m a vanishes (momentum
+    conservation, Sec. 2.1) up to the float32 rounding of the mesh force."""
     wl = small_two_species(16, 32, seed_offset=3)
     c = ctx(32, wl.n_cell)
-    dev = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    fl = [c.float_species(sp.x, sp.v, sp.mass) for sp in wl.species]
+    dev = [c.encode(f) for f in fl] if layout == "compressed" else fl
     rho = c.deposit(dev)
-    out = c.reduce(dev, rho)
+    acc, _ = c.force(c.deposit(dev))
+    out = c.reduce(dev, rho, acc)
     mtot = sum(sp.mass * sp.x.shape[0] for sp in wl.species)
     assert abs(out[1] - mtot) <= 1e-14 * mtot
     assert abs(out[0] - mtot) <= 1e-6 * mtot  # float32 mesh summed in float64
-    p = np.zeros(3)
+    xs, vs, masses = [], [], []
     for d, sp in zip(dev, wl.species):
-        _, v = codec.decode(c.to_host(d))
-        p += sp.mass * v.astype(np.float64).sum(0)
-    assert np.allclose(out[2:5], p, rtol=1e-12, atol=1e-15)
+        if layout == "compressed":
+            x, v = codec.decode(c.to_host(d))
+        else:
+            x, v = sp.x, sp.v
+        xs.append(x.astype(np.float64))
+        vs.append(v.astype(np.float64))
+        masses.append(sp.mass)
+    acc_o, _, _ = mesh.accelerations(list(zip(xs, masses)), 32)
+    scale = sum(m * np.abs(a).sum() for m, a in zip(masses, acc_o))
+    ptot, ftot = np.zeros(3), np.zeros(3)
+    for s_, (x, v, m, ai) in enumerate(zip(xs, vs, masses, acc_o)):
+        per = out[8 + 6 * s_: 14 + 6 * s_]
+        p = m * v.sum(0)
+        f = m * ai.sum(0)
+        assert np.allclose(per[:3], p, rtol=1e-12, atol=1e-15)
+        assert np.all(np.abs(per[3:] - f) <= 1e-4 * scale), (per[3:], f)
+        ptot += p
+        ftot += f
+    assert np.allclose(out[2:5], ptot, rtol=1e-12, atol=1e-15)
+    # the two species pull on each other: each has a net force, the total has none
+    assert np.max(np.abs(out[5:8])) <= 1e-5 * scale, (out[5:8], scale)
+    assert np.max(np.abs(ftot)) <= 1e-12 * scale
+    c.close()
 
 
 def test_bad_shapes_rejected():
