@@ -1,6 +1,6 @@
 """Throughput of the particle-mesh step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--config tile_1024]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config large_2048|tile_1024]
 
 One "step" is one pass of the whole hot path over one batch of particles: cell
 offsets, CIC deposit of both species, the fused FFT force solve, interpolate-kick-
@@ -8,11 +8,15 @@ drift-re-encode and the stable re-sort of both compressed streams (pm_step). Inp
 are resident in HBM before the timed region; W untimed warm-up steps are followed by
 exactly K timed steps bracketed by device synchronisation.
 
-Printed: one JSON line with the contract fields, a roofline object for the dominant
-kernel (algorithmic bytes per launch over the HIP-event launch duration measured on
-the stream the kernel runs on), the per-stage breakdown, the error of the same path
-against the FP64 oracle on a small sample of the workload, and the oracle's own
-throughput on that sample (CPU baseline).
+The default workload is the largest that fits one GPU: 512^3 CDM + 1024^3 neutrinos
+(1.21 G particles) on a 2048^3 mesh. Printed: one JSON line with the contract fields, a
+roofline object for the dominant kernel and for the deposit and the interpolate-kick-
+drift (algorithmic bytes per launch over the HIP-event launch duration measured on the
+stream the kernels run on), the per-stage breakdown, the peak HBM footprint, the
+fraction of particles whose position code does not change in a step, the comparison
+of three compressed float32 steps with an all-float64 uncompressed run on the
+[0, 128 Delta)^3 sub-box, the 1024^3 tile's step and step-adjoint rates, and the
+oracle's own throughput on a bounded sample (CPU baseline).
 """
 
 from __future__ import annotations
@@ -30,6 +34,9 @@ METRIC = "PM particle-updates/s (fwd and fwd+adjoint) at 1 GPU; % HBM roofline; 
 HBM_PEAK_GBS = 8000.0
 
 WORKLOAD_TEXT = {
+    "large_2048": "the largest single-GPU workload: 512^3 CDM + 1024^3 neutrinos (1.21 G "
+                  "particles), 2048^3 FP32 mesh, compressed particles (n_cell 512), dt "
+                  "0.005, seed 11/111",
     "tile_1024": "one GPU's production-shaped tile: 256^3 CDM + 512^3 neutrinos, 1024^3 "
                  "FP32 mesh, compressed particles (n_cell 256), dt 0.005, seed 0",
     "two_species_256": "two-species step: 128^3 CDM + 256^3 neutrinos, 256^3 FP32 mesh, "
@@ -111,8 +118,10 @@ def cpu_baseline_and_error(ctx_cls, make_workload, base: str):
 
     from oracle import codec, step
 
-    c = {"tile_1024": dict(n_p_c=64, n_p_nu=128, n_mesh=256, n_cell=64),
+    c = {"large_2048": dict(n_p_c=64, n_p_nu=128, n_mesh=256, n_cell=64),
+         "tile_1024": dict(n_p_c=64, n_p_nu=128, n_mesh=256, n_cell=64),
          "two_species_256": dict(n_p_c=32, n_p_nu=64, n_mesh=64, n_cell=32)}[base]
+    frac = {"large_2048": "1/8", "tile_1024": "1/4", "two_species_256": "1/4"}[base]
     wl = make_workload(base, **c)
     ctx = ctx_cls(wl.n_mesh, wl.n_cell)
     dev = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
@@ -150,7 +159,7 @@ def cpu_baseline_and_error(ctx_cls, make_workload, base: str):
     n = wl.n_particles
     return ({"value": n * n_steps / t_cpu, "unit": "particle-updates/s", "cores": 1,
              "kind": "oracle",
-             "sample": f"{base} recipe at 1/4 linear size ({c['n_p_c']}^3 CDM + "
+             "sample": f"{base} recipe at {frac} linear size ({c['n_p_c']}^3 CDM + "
                        f"{c['n_p_nu']}^3 nu, {c['n_mesh']}^3 mesh, n_cell {c['n_cell']}), "
                        f"{n_steps} compressed steps, numpy float64, one thread",
              "seconds": t_cpu},
@@ -197,15 +206,270 @@ def adjoint_rates(ctx_cls, make_workload, torch, name: str, reps: int = 3):
             "fwd_adjoint_updates_per_s": N * K / ((t_f + t_b) * 1e-3)}
 
 
+def mem_used(torch) -> int:
+    free, total = torch.cuda.mem_get_info()
+    return total - free
+
+
+def timed_steps(ctx, A, B, wl, torch, steps, warmup):
+    """W warm-up steps, then K timed steps of pm_step (ping-pong A <-> B) with the stage
+    profiler on. Returns (ms_step, value, stages, cur)."""
+    cur, nxt = A, B
+    for _ in range(warmup):
+        ctx.step(cur, wl.dt, out=nxt)
+        cur, nxt = nxt, cur
+    ctx.sync()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(cur, wl.dt, out=nxt)
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_step = (t1 - t0) * 1e3 / steps
+    value = wl.n_particles * steps / (t1 - t0)
+    stages = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        per = ms / cnt
+        b = stage_bytes(name, wl.n_mesh, wl)
+        stages[name] = {"ms_per_step": ms / steps, "launches_per_step": cnt / steps,
+                        "ms_per_launch": per,
+                        "gbs": (b / (per * 1e-3) / 1e9) if b else None}
+    return ms_step, value, stages, cur
+
+
+def roofline_of(stages, name, wl, config):
+    st = stages[name]
+    return {"bound": "hbm", "kernel": name, "achieved": st["gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": st["gbs"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic(name, config),
+            "bytes_per_launch": stage_bytes(name, wl.n_mesh, wl),
+            "ms_per_launch": st["ms_per_launch"]}
+
+
+def stream_cells(cs, torch):
+    """Cell key of every particle of a compressed stream, in stream order (int32)."""
+    nc3 = cs.count.numel()
+    cnt = cs.count.to(torch.int64)
+    ne = int(cs.header()["n_esc"])
+    if ne:
+        e = cs.esc[:ne]
+        cnt[e[:, 0]] = e[:, 1]
+    keys = torch.arange(nc3, dtype=torch.int32, device=cs.count.device)
+    return torch.repeat_interleave(keys, cnt, output_size=cs.n)
+
+
+def moved_fraction(old, new, perm, torch):
+    """Fraction of particles whose position code changed in a step: new stream
+    particle j was old stream particle perm[j]."""
+    c_old = stream_cells(old, torch)
+    c_new = stream_cells(new, torch)
+    moved = c_new != c_old[perm]
+    del c_old, c_new
+    moved |= (new.pos != old.pos[perm]).any(dim=1)
+    return float(moved.float().mean().item())
+
+
+SUB = 128  # side of the comparison sub-box in mesh nodes
+
+
+def large_comparison(ctx, wl, torch, log):
+    """Three compressed float32 steps from the encoded initial state, through the
+    separate calls (pm_deposit, pm_force, pm_kick_drift_perm) so that the density, the
+    force and the particle identities can be read: the sub-box of the first density and
+    force, the fraction of frozen position codes per step and species, the final
+    positions of the particles that start in the sub-box. Returns a dict of host arrays
+    and figures; frees its device buffers."""
+    import numpy as np
+    n = wl.n_mesh
+    dev = ctx.device
+    A, perm0 = [], []
+    for sp in wl.species:
+        fs = ctx.float_species(sp.x, sp.v, sp.mass)
+        cs, p = ctx.encode(fs, want_perm=True)
+        del fs
+        A.append(cs)
+        perm0.append(p)
+    B = [ctx.empty_like(s) for s in A]
+    acc = torch.empty((3, n, n, n), dtype=torch.float32, device=dev)
+    a_max = torch.zeros(1, dtype=torch.float32, device=dev)
+    peak = mem_used(torch)
+    idx = perm0  # stream position -> input index
+    frozen = []
+    rho_sub = a_sub = None
+    cur, nxt = A, B
+    for k in range(wl.steps):
+        ctx.deposit(cur, rho=acc[0])
+        if k == 0:
+            rho_sub = acc[0, :SUB, :SUB, :SUB].cpu().numpy()
+        ctx.force(acc[0], acc=acc, a_max=a_max)
+        if k == 0:
+            a_sub = acc[:, :SUB, :SUB, :SUB].cpu().numpy()
+        nxt, perms = ctx.kick_drift_perm(cur, acc, a_max, wl.dt, wl.dt, out=nxt)
+        peak = max(peak, mem_used(torch))
+        frozen.append([1.0 - moved_fraction(o, q, p, torch) for o, q, p in zip(cur, nxt, perms)])
+        idx = [i[p] for i, p in zip(idx, perms)]
+        del perms
+        cur, nxt = nxt, cur
+        log(f"[bench] comparison step {k + 1}: frozen fraction {frozen[-1]}")
+    del acc, nxt, A, B, perm0
+    torch.cuda.empty_cache()
+    final = {}
+    for s_, (cs, ix, sp) in enumerate(zip(cur, idx, wl.species)):
+        sel = np.flatnonzero(np.all(sp.x < np.float32(SUB / n), axis=1))
+        fs = ctx.decode(cs)
+        inv = torch.empty(cs.n, dtype=torch.int64, device=dev)
+        inv[ix] = torch.arange(cs.n, dtype=torch.int64, device=dev)
+        j = inv[torch.from_numpy(sel).to(dev)]
+        final[s_] = (sel, fs.x[j].cpu().numpy().astype(np.float64))
+        del fs, inv, j
+    del cur, idx
+    torch.cuda.empty_cache()
+    return {"rho_sub": rho_sub, "a_sub": a_sub, "frozen": frozen, "final": final,
+            "peak_used": peak}
+
+
+def window_density_oracle(wl):
+    """CPU oracle density on the sub-box nodes from the decoded (bin-centre) initial
+    positions of the particles that reach them: the GPU deposit's own input."""
+    import numpy as np
+
+    from oracle import codec, mesh
+    n = wl.n_mesh
+    lo, hi = np.float32(SUB / n), np.float32((n - 1) / n)
+    rho = np.zeros((SUB, SUB, SUB))
+    for sp in wl.species:
+        near = np.all((sp.x < lo) | (sp.x >= hi), axis=1)
+        x = sp.x[near]
+        u = codec.position_codes(x, wl.n_cell)
+        xd = (u.astype(np.float64) + 0.5) / (256 * wl.n_cell)
+        rho += mesh.deposit_window(xd, sp.mass, n, (0, 0, 0), SUB)
+    return rho
+
+
+def fp64_reference(wl, torch, log):
+    """The uncompressed float64 run (oracle.fp64_torch) of the same workload from the
+    generator's float32 positions and velocities: sub-box density and force of the first
+    step, positions after all steps, and its own time per step."""
+    import numpy as np
+
+    from oracle import fp64_torch
+    dev = torch.device("cuda")
+    sp = [(torch.from_numpy(s.x).to(dev).to(torch.float64),
+           torch.from_numpy(s.v).to(dev).to(torch.float64), s.mass) for s in wl.species]
+    kept = {}
+
+    def keep(key, m):
+        if "first" not in kept:
+            kept[key] = m[:SUB, :SUB, :SUB].cpu().numpy()
+
+    times = []
+    for k in range(wl.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp64_torch.step_float(sp, wl.n_mesh, wl.dt, wl.dt, keep=keep)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        kept["first"] = True
+        log(f"[bench] float64 reference step {k + 1}: {times[-1]:.1f} s")
+    peak = mem_used(torch)
+    final = {}
+    for s_, (x, _, _) in enumerate(sp):
+        sel = np.flatnonzero(np.all(wl.species[s_].x < np.float32(SUB / wl.n_mesh), axis=1))
+        final[s_] = x[torch.from_numpy(sel).to(dev)].cpu().numpy()
+    del sp
+    torch.cuda.empty_cache()
+    return {"rho_sub": kept["rho"], "a_sub": np.stack([kept[0], kept[1], kept[2]]),
+            "final": final, "s_per_step": float(np.median(times)), "peak_used": peak}
+
+
+def compare_figures(gpu, ref, rho_oracle, wl):
+    import numpy as np
+    mean = sum(sp.mass * sp.n for sp in wl.species)  # mean density (unit box)
+    scale = np.maximum(np.abs(ref["rho_sub"]), mean)
+    out = {
+        "sub_box": f"[0, {SUB} Delta)^3 of the {wl.n_mesh}^3 mesh",
+        "density_max_rel_vs_fp64": float(np.max(np.abs(gpu["rho_sub"] - ref["rho_sub"]) / scale)),
+        "density_rel_rms_vs_fp64": float(np.sqrt(np.mean((gpu["rho_sub"] - ref["rho_sub"]) ** 2)
+                                                 / np.mean(ref["rho_sub"] ** 2))),
+        "density_max_rel_vs_oracle_same_input": float(np.max(
+            np.abs(gpu["rho_sub"] - rho_oracle) / np.maximum(np.abs(rho_oracle), mean))),
+        "force_rel_rms_vs_fp64": float(np.sqrt(np.mean((gpu["a_sub"] - ref["a_sub"]) ** 2) /
+                                               np.mean(ref["a_sub"] ** 2))),
+    }
+    q = 1.0 / (256 * wl.n_cell)
+    for s_, name in enumerate(sp.name for sp in wl.species):
+        sel_g, xg = gpu["final"][s_]
+        xr = ref["final"][s_]
+        d = np.abs(xg - xr)
+        d = np.minimum(d, 1.0 - d)
+        out[f"position_{name}_particles"] = int(sel_g.size)
+        out[f"position_{name}_max_abs"] = float(d.max()) if d.size else 0.0
+        out[f"position_{name}_rms_abs"] = float(np.sqrt(np.mean(d ** 2))) if d.size else 0.0
+    out["position_quantum"] = q
+    out["after_steps"] = wl.steps
+    out["note"] = ("float32 mesh and FFT with compressed fixed-point positions, against "
+                   "float64 throughout from the uncompressed initial state: the position "
+                   "differences include the compression's quantisation (at most q/2 per "
+                   "axis at the start, q = L / (256 n_cell)) and its frozen drifts")
+    return out
+
+
+def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True):
+    """The 1024^3 tile (256^3 + 512^3): step rate, and the step adjoint at that size."""
+    wl = make_workload("tile_1024")
+    ctx = PMContext(wl.n_mesh, wl.n_cell)
+    A = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
+    B = [ctx.empty_like(s) for s in A]
+    ctx.sync()
+    ms_step, value, stages, cur = timed_steps(ctx, A, B, wl, torch, steps, warmup)
+    out = {"workload": WORKLOAD_TEXT["tile_1024"], "particles": wl.n_particles,
+           "ms_per_step": ms_step, "value": value,
+           "deposit_frac": stages["deposit"]["gbs"] / HBM_PEAK_GBS,
+           "interp_kick_drift_frac": stages["interp_kick_drift"]["gbs"] / HBM_PEAK_GBS}
+    log(f"[bench] tile_1024: {ms_step:.3f} ms/step, {value:.3e} particle-updates/s")
+    if adjoint:
+        lx = [torch.ones((sp.n, 3), dtype=torch.float32, device=ctx.device) for sp in cur]
+        lv = [torch.ones_like(t) for t in lx]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        t_vjp = []
+        for r in range(3):
+            ev[0].record()
+            gx, gv = ctx.step_vjp(cur, wl.dt, lx, lv)
+            ev[1].record()
+            torch.cuda.synchronize()
+            if r > 0:
+                t_vjp.append(ev[0].elapsed_time(ev[1]))
+        del gx, gv, lx, lv
+        t_vjp = min(t_vjp)
+        out.update({"step_vjp_ms": t_vjp, "vjp_over_step": t_vjp / ms_step,
+                    "fwd_adjoint_updates_per_s": wl.n_particles / ((ms_step + t_vjp) * 1e-3)})
+        log(f"[bench] tile_1024 step adjoint {t_vjp:.3f} ms ({t_vjp / ms_step:.2f}x the step)")
+    ctx.close()
+    del A, B, cur
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="tile_1024", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--config", default="large_2048", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the step-adjoint timings (fwd+adjoint rates)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the float64 sub-box comparison of the large workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 1024^3 tile measured beside the large workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run one elementwise kernel that reads and "
                          "writes exactly 1 GiB (reference for HBM byte counters)")
@@ -226,50 +490,25 @@ def main():
     wl = make_workload(args.config)
     log(f"[bench] workload {args.config}: {wl.n_particles} particles, mesh {wl.n_mesh}^3 "
         f"({time.perf_counter() - t:.1f} s to generate)")
+    used0 = mem_used(torch)
     ctx = PMContext(wl.n_mesh, wl.n_cell)
+    n_tot = wl.n_particles
+    sizes = PMContext.query_sizes(wl.n_mesh, wl.n_cell, ctx.brick, n_tot, len(wl.species))
+    large = args.config == "large_2048"
+    cmp_gpu = None
+    if large and not args.no_compare:
+        log("[bench] comparison run: 3 compressed steps through the separate calls")
+        cmp_gpu = large_comparison(ctx, wl, torch, log)
     A = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
     B = [ctx.empty_like(s) for s in A]
     ctx.sync()
     log("[bench] encoded; warming up")
-    cur, nxt = A, B
-    for _ in range(args.warmup):
-        ctx.step(cur, wl.dt, out=nxt)
-        cur, nxt = nxt, cur
-    ctx.sync()
-    log("[bench] timed steps")
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.step(cur, wl.dt, out=nxt)
-        cur, nxt = nxt, cur
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.sync()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = wl.n_particles * args.steps / (t1 - t0)
+    ms_step, value, stages, cur = timed_steps(ctx, A, B, wl, torch, args.steps, args.warmup)
+    peak_step = mem_used(torch) - used0
     log(f"[bench] {ms_step:.3f} ms/step, {value:.3e} particle-updates/s")
-
-    stages = {}
-    for name, (ms, cnt) in prof.items():
-        if cnt == 0:
-            continue
-        per = ms / cnt
-        b = stage_bytes(name, wl.n_mesh, wl)
-        stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": cnt / args.steps,
-                        "ms_per_launch": per,
-                        "gbs": (b / (per * 1e-3) / 1e9) if b else None}
     dom = max((k for k in stages if stage_bytes(k, wl.n_mesh, wl) > 0),
               key=lambda k: stages[k]["ms_per_step"])
-    ach = stages[dom]["gbs"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": measured_traffic(dom, args.config),
-                "bytes_per_launch": stage_bytes(dom, wl.n_mesh, wl),
-                "ms_per_launch": stages[dom]["ms_per_launch"]}
-    # the same figures for every stage with a byte model (the particle kernels included)
+    roofline = roofline_of(stages, dom, wl, args.config)
     for k, st in stages.items():
         if st["gbs"] is not None:
             st["frac"] = st["gbs"] / HBM_PEAK_GBS
@@ -278,8 +517,15 @@ def main():
                       for k in stages)
     step_frac = total_model / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=ctx.device)
+        b = torch.empty_like(a)
+        torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
     adj = None
-    if not args.no_adjoint:
+    if not large and not args.no_adjoint:
         log("[bench] step adjoint at the same workload")
         lx = [torch.ones((sp.n, 3), dtype=torch.float32, device=ctx.device) for sp in cur]
         lv = [torch.ones_like(t) for t in lx]
@@ -297,17 +543,48 @@ def main():
         adj = {"step_vjp_ms": t_vjp, "vjp_over_step": t_vjp / ms_step,
                "fwd_adjoint_updates_per_s": wl.n_particles / ((ms_step + t_vjp) * 1e-3)}
         log(f"[bench] step adjoint {t_vjp:.3f} ms ({t_vjp / ms_step:.2f}x the step)")
+    ctx.close()
+    del A, B, cur
+    torch.cuda.empty_cache()
+
+    footprint = {"timed_steps_gb": peak_step / 1e9,
+                 "query_sizes_gb": {k: v / 1e9 for k, v in sizes.items()},
+                 "note": "device memory in use (hipMemGetInfo) above the level before the "
+                         "context: after the timed steps (context tables and meshes, grown "
+                         "scratch, two compressed copies of every species), and at the "
+                         "peak of the comparison run (which also holds a caller-owned "
+                         "force mesh, permutations and the frozen-fraction counts)"}
+    if cmp_gpu is not None:
+        footprint["comparison_run_gb"] = (cmp_gpu["peak_used"] - used0) / 1e9
+
+    compare, frozen = None, None
+    if cmp_gpu is not None:
+        frozen = {"per_step": [dict(zip((sp.name for sp in wl.species), f))
+                               for f in cmp_gpu["frozen"]],
+                  "definition": "fraction of particles whose position code is unchanged "
+                                "by the step (|v' c_d S / L| < 1/2 on every axis)"}
+        log("[bench] oracle density on the sub-box (CPU)")
+        rho_or = window_density_oracle(wl)
+        log("[bench] float64 reference run")
+        ref = fp64_reference(wl, torch, log)
+        compare = compare_figures(cmp_gpu, ref, rho_or, wl)
+        compare["fp64_reference_s_per_step"] = ref["s_per_step"]
+        footprint["fp64_reference_peak_gb"] = (ref["peak_used"] - used0) / 1e9
+
+    extra = None
+    if large and not args.no_extra:
+        log("[bench] the 1024^3 tile")
+        extra = tile_extra(PMContext, make_workload, torch, log, args.steps, args.warmup,
+                           adjoint=not args.no_adjoint)
+        if not args.no_adjoint:
+            adj = {"tile_1024": {k: extra[k] for k in ("step_vjp_ms", "vjp_over_step",
+                                                      "fwd_adjoint_updates_per_s")}}
+    if not args.no_adjoint:
         a128 = adjoint_rates(PMContext, make_workload, torch, "adjoint_128")
+        adj = adj or {}
         adj["adjoint_128"] = a128
         log(f"[bench] adjoint_128: fwd {a128['fwd_ms']:.2f} ms, bwd {a128['bwd_ms']:.2f} ms "
             f"for {a128['steps']} steps")
-
-    if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device=ctx.device)
-        b = torch.empty_like(a)
-        torch.mul(a, 2.0, out=b)
-        torch.cuda.synchronize()
-        del a, b
 
     cpu, err = None, None
     if not args.no_cpu_baseline:
@@ -321,10 +598,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.config], "name": args.config,
                    "particles": wl.n_particles, "n_mesh": wl.n_mesh, "n_cell": wl.n_cell,
-                   "brick": ctx.brick, "parallelism": "single GPU"},
+                   "brick": PMContext.default_brick(wl.n_mesh, wl.n_cell),
+                   "parallelism": "single GPU"},
         "roofline": roofline,
+        "roofline_deposit": roofline_of(stages, "deposit", wl, args.config),
+        "roofline_interp_kick_drift": roofline_of(stages, "interp_kick_drift", wl, args.config),
         "step_hbm_frac_model": step_frac,
         "stages": stages,
+        "hbm_footprint": footprint,
+        "frozen_fraction": frozen,
+        "vs_fp64_sub_box": compare,
+        "tile_1024": extra,
         "adjoint": adj,
         "err_vs_fp64": err,
         "cpu_baseline": cpu,

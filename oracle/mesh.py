@@ -82,6 +82,37 @@ def density_at(x: np.ndarray, mass, n_g: int, nodes: np.ndarray) -> np.ndarray:
     return out
 
 
+def deposit_window(x: np.ndarray, mass, n_g: int, lo, size: int) -> np.ndarray:
+    """CIC density on the window of nodes lo_a <= c_a < lo_a + size (mod n_g) of the
+    periodic n_g^3 mesh, from the given particles only; returns [z][y][x] of side size.
+    The same weights as deposit(); a particle contributes to a window node when one of
+    its 8 corner nodes is that node. For the nodes of a large mesh that only the
+    particles near the window reach."""
+    x = np.asarray(x, dtype=np.float64)
+    m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (x.shape[0],))
+    lo = np.asarray(lo, dtype=np.int64).reshape(3)
+    out = np.zeros(size ** 3, dtype=np.float64)
+    u = x * n_g
+    i = np.floor(u)
+    f = u - i
+    i = i.astype(np.int64) % n_g
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                d = (dx, dy, dz)
+                w = m.copy()
+                inside = np.ones(x.shape[0], dtype=bool)
+                loc = []
+                for a in range(3):
+                    w = w * (f[:, a] if d[a] else 1.0 - f[:, a])
+                    c = (i[:, a] + d[a] - lo[a]) % n_g
+                    inside &= c < size
+                    loc.append(c)
+                idx = (loc[2] * size + loc[1]) * size + loc[0]
+                out += np.bincount(idx[inside], weights=w[inside], minlength=size ** 3)
+    return out.reshape(size, size, size) * float(n_g) ** 3
+
+
 def deposit_species(species, n_g: int) -> np.ndarray:
     """Both species onto the same mesh (Sec. 2.1 footnote): list of (x, mass)."""
     rho = np.zeros((n_g, n_g, n_g), dtype=np.float64)

@@ -104,7 +104,7 @@ class PMContext:
         self.device = dev
         torch.cuda.set_device(self.device)
         if brick is None:
-            brick = max(1, min(8, n_cell, 16 // max(1, n_mesh // n_cell)))
+            brick = self.default_brick(n_mesh, n_cell)
         self.n_mesh, self.n_cell, self.brick = n_mesh, n_cell, brick
         self.G, self.soft_cells, self.box = G, soft_cells, float(box)
         cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G, soft_cells)
@@ -124,6 +124,11 @@ class PMContext:
             self.close()
         except Exception:
             pass
+
+    @staticmethod
+    def default_brick(n_mesh: int, n_cell: int) -> int:
+        """Cells per brick side: 16 mesh nodes per brick side where the cells allow."""
+        return max(1, min(8, n_cell, 16 // max(1, n_mesh // n_cell)))
 
     @staticmethod
     def query_sizes(n_mesh: int, n_cell: int, brick: int, n_max: int, n_sp: int,

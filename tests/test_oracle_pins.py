@@ -334,3 +334,18 @@ def test_density_at_nodes_equals_full_deposit(n):
     got = mesh.density_at(x, m, n, nodes)
     want = full[nodes[:, 2], nodes[:, 1], nodes[:, 0]]
     assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * full.max())
+
+
+@pytest.mark.parametrize("lo,size", [((0, 0, 0), 4), ((5, 14, 0), 6), ((12, 3, 9), 8)])
+def test_deposit_window_equals_full_deposit(lo, size):
+    """The windowed deposit equals the corresponding nodes of the full periodic deposit,
+    windows that wrap around the box included."""
+    n = 16
+    rng = np.random.default_rng(sum(lo) + size)
+    x = rng.random((3000, 3))
+    m = rng.random(3000)
+    full = mesh.deposit(x, m, n)
+    zz, yy, xx = [(np.arange(size) + lo[a]) % n for a in (2, 1, 0)]
+    want = full[np.ix_(zz, yy, xx)]
+    got = mesh.deposit_window(x, m, n, lo, size)
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13 * full.max())
