@@ -264,6 +264,18 @@ pm_status pm_loss_density_vjp(pm_ctx ctx, const pm_species* sp, int n_sp,
 pm_status pm_reduce(pm_ctx ctx, const pm_species* sp, int n_sp, const float* rho,
                     const float* acc, double* out);
 
+/* pm_reduce for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same arguments, results
+ * and kernels as pm_reduce; it calls no allocator. Every buffer it needs (partial sums,
+ * the cell offsets of one compressed species, the scan's block sums) lives in one fixed
+ * array of 365 KB per device, held until the process ends, whose address pm_create takes
+ * once per device. Limit: compressed species need n_cell <= 32 (n_cell^3 <= 32768;
+ * PM_ERR_SHAPE beyond); float species and the meshes are not limited. Calls that
+ * overlap on one device (any context) share the array and race: order them on one
+ * stream or synchronise between them. */
+pm_status pm_reduce_noalloc(pm_ctx ctx, const pm_species* sp, int n_sp, const float* rho,
+                            const float* acc, double* out);
+
 /* Byte stream of one compressed species (Sec. 2.4 layout): a 64-byte header
  * {"PMC1", version 1, species_id, brick, N, n_cell, v_max, 0, mass, checksum,
  * body length}, then for every cell its count byte (255 + uint32 count when >= 255)

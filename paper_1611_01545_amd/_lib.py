@@ -89,6 +89,7 @@ EXPORTS = [
     ("pm_step_vjp", [P, PS, ctypes.c_int, ctypes.c_double, P, P, P, P]),
     ("pm_loss_density_vjp", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_reduce", [P, PS, ctypes.c_int, P, P, P]),
+    ("pm_reduce_noalloc", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_pack", [P, PS, ctypes.c_int32, P, I64, P]),
     ("pm_pack_size", [P, PS, ctypes.POINTER(I64)]),
     ("pm_unpack", [P, P, I64, PS, ctypes.POINTER(ctypes.c_double),

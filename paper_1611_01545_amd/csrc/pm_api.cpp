@@ -155,6 +155,7 @@ pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out) {
   if (s == PM_OK && hipMemsetAsync(c->err, 0, sizeof(DevErr), c->stream) != hipSuccess)
     s = PM_ERR_DEVICE;
   if (s == PM_OK) s = build_kernel_table(c);
+  if (s == PM_OK) s = noalloc_init(c);
   if (s == PM_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = PM_ERR_DEVICE;
   if (s != PM_OK) {
     pm_destroy(c);
@@ -413,6 +414,14 @@ pm_status pm_reduce(pm_ctx c, const pm_species* sp, int n_sp, const float* rho,
   for (int i = 0; i < n_sp; ++i)
     if (check_species(c, &sp[i], true) != PM_OK) return PM_ERR_ARG;
   return run_reduce(c, sp, n_sp, rho, acc, out);
+}
+
+pm_status pm_reduce_noalloc(pm_ctx c, const pm_species* sp, int n_sp, const float* rho,
+                            const float* acc, double* out) {
+  if (!c || !out || n_sp < 0 || n_sp > 4 || (n_sp > 0 && !sp)) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i)
+    if (check_species(c, &sp[i], true) != PM_OK) return PM_ERR_ARG;
+  return run_reduce_noalloc(c, sp, n_sp, rho, acc, out);
 }
 
 pm_status pm_pack(pm_ctx c, const pm_species* sp, int32_t species_id, uint8_t* buf,

@@ -2,6 +2,7 @@
 // particles, decode to bin centres, per-cell offsets of a compressed stream, the
 // count/escape table, the byte stream and the float64 global reductions.
 #include <cstring>
+#include <mutex>
 
 #include "pm_codec.h"
 #include "pm_scan.h"
@@ -432,7 +433,13 @@ __global__ void k_reduce_final(const double* pmesh, int nmesh_part, double cell_
 
 pm_status run_cell_offsets(pm_context* c, const pm_species* sp, int64_t* off) {
   ProfScope ps(c, ST_OFFSETS);
-  pm_status s = scan_counts(c, sp->count, sp->esc, sp->hdr, c->g.ncell3, off);
+  return scan_counts_into(c, sp, off, nullptr);
+}
+
+// cell offsets of a compressed stream and the check that the counts sum to n; bsum
+// (nullable) holds the scan's block sums
+pm_status scan_counts_into(pm_context* c, const pm_species* sp, int64_t* off, int64_t* bsum) {
+  pm_status s = scan_generic(c, GetCount{sp->count, sp->esc, sp->hdr}, c->g.ncell3, off, bsum);
   if (s != PM_OK) return s;
   hipLaunchKernelGGL(k_check_total, dim3(1), dim3(1), 0, c->stream, off, c->g.ncell3, sp->n,
                      c->err);
@@ -544,11 +551,15 @@ pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_
   return scan_generic(c, GetPackBytes{off}, n, out);
 }
 
-pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
-                     const float* acc, double* out) {
+namespace {
+// Float64 reductions with the caller's choice of buffers: part (RED_BLOCKS * 25 doubles),
+// off_of(s) the cell offsets of compressed species s ((ncell3 + 1) int64), bsum the scan's
+// block sums (nullptr: the context's scratch).
+template <typename OffOf>
+pm_status reduce_core(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
+                      const float* acc, double* out, double* part, OffOf off_of,
+                      int64_t* bsum) {
   if (n_sp < 0 || n_sp > 4) return PM_ERR_ARG;
-  double* part = (double*)scratch(c, SC_MISC, (size_t)(RED_BLOCKS * (6 * 4 + 1)) * 8);
-  if (!part) return PM_ERR_NOMEM;
   double* pmesh = part;
   double* ppart = part + RED_BLOCKS;
   RedMeta meta{};
@@ -564,9 +575,9 @@ pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float*
     meta.count[s] = sp[s].n;
     RedSpecies rs{sp[s], nullptr};
     if (sp[s].layout == PM_COMPRESSED) {
-      int64_t* off = (int64_t*)scratch(c, SC_SPOFF0 + s, (size_t)(c->g.ncell3 + 1) * 8);
+      int64_t* off = off_of(s);
       if (!off) return PM_ERR_NOMEM;
-      pm_status st = run_cell_offsets(c, &sp[s], off);
+      pm_status st = scan_counts_into(c, &sp[s], off, bsum);
       if (st != PM_OK) return st;
       rs.off = off;
     }
@@ -578,4 +589,59 @@ pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float*
                      meta, out);
   PM_LAUNCH_CHECK();
   return PM_OK;
+}
+}  // namespace
+
+pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
+                     const float* acc, double* out) {
+  double* part = (double*)scratch(c, SC_MISC, (size_t)(RED_BLOCKS * (6 * 4 + 1)) * 8);
+  if (!part) return PM_ERR_NOMEM;
+  return reduce_core(c, sp, n_sp, rho, acc, out, part, [&](int s) {
+    return (int64_t*)scratch(c, SC_SPOFF0 + s, (size_t)(c->g.ncell3 + 1) * 8);
+  }, nullptr);
+}
+
+// ------------------------------------------------------- allocation-free reduce --
+// For callers that cannot allocate device memory. Every buffer of pm_reduce_noalloc lives
+// in one fixed array per device: the per-workgroup partial sums, the cell offsets of one
+// compressed species at a time (species are reduced one after the other on the stream)
+// and the block sums of their scan. Its device address is taken once per device, when a
+// context is created there; calls that overlap on one device share the array and race.
+namespace noalloc {
+constexpr int64_t NC3_MAX = 32768;  // compressed species: n_cell^3 <= 32^3
+constexpr size_t PART_BYTES = (size_t)RED_BLOCKS * (6 * 4 + 1) * 8;
+constexpr size_t OFF_BYTES = (size_t)(NC3_MAX + 1) * 8;
+constexpr size_t BSUM_BYTES = 256;  // cdiv(NC3_MAX + 1, 4096) int64 block sums
+constexpr size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t BYTES = a256(PART_BYTES) + a256(OFF_BYTES) + BSUM_BYTES;
+static __device__ __align__(256) unsigned char scratch[BYTES];
+
+std::mutex mu;
+unsigned char* addr[256] = {};
+}  // namespace noalloc
+
+pm_status noalloc_init(pm_context* c) {
+  if (c->device < 0 || c->device >= 256) return PM_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(noalloc::mu);
+  if (!noalloc::addr[c->device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc::scratch)) != hipSuccess || !p)
+      return PM_ERR_DEVICE;
+    noalloc::addr[c->device] = (unsigned char*)p;
+  }
+  c->na_scratch = noalloc::addr[c->device];
+  return PM_OK;
+}
+
+pm_status run_reduce_noalloc(pm_context* c, const pm_species* sp, int n_sp,
+                             const float* rho, const float* acc, double* out) {
+  using namespace noalloc;
+  if (!c->na_scratch) return PM_ERR_DEVICE;
+  for (int s = 0; s < n_sp; ++s)
+    if (sp[s].layout == PM_COMPRESSED && c->g.ncell3 > NC3_MAX) return PM_ERR_SHAPE;
+  unsigned char* base = c->na_scratch;
+  double* part = (double*)base;
+  int64_t* off = (int64_t*)(base + a256(PART_BYTES));
+  int64_t* bsum = (int64_t*)(base + a256(PART_BYTES) + a256(OFF_BYTES));
+  return reduce_core(c, sp, n_sp, rho, acc, out, part, [&](int) { return off; }, bsum);
 }

@@ -106,6 +106,8 @@ struct pm_context {
   float* amax = nullptr;  // device scalar
   // grow-on-demand scratch
   DevBuf scratch[32];
+  // this device's fixed array of pm_reduce_noalloc (device address, set by pm_create)
+  unsigned char* na_scratch = nullptr;
   int64_t last_detail = 0;
   // stage profiler (pm_profile)
   int prof = 0;
@@ -204,12 +206,17 @@ pm_status radix_sort_pairs_dev(pm_context* c, uint32_t** keys, uint32_t** vals,
 pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64_t* perm);
 pm_status run_decode(pm_context* c, const pm_species* in, pm_species* out);
 pm_status run_cell_offsets(pm_context* c, const pm_species* sp, int64_t* off);
+pm_status scan_counts_into(pm_context* c, const pm_species* sp, int64_t* off, int64_t* bsum);
 pm_status run_finalize_counts(pm_context* c, const uint32_t* cnt32, const uint64_t* cnt64,
                               pm_species* out);
 pm_status run_pack(pm_context* c, const pm_species* sp, int32_t sid, uint8_t* buf,
                    int64_t cap, int64_t* used);
 pm_status run_reduce(pm_context* c, const pm_species* sp, int n_sp, const float* rho,
                      const float* acc, double* out);
+// the same reductions with every buffer in a fixed device array (no allocation)
+pm_status noalloc_init(pm_context* c);
+pm_status run_reduce_noalloc(pm_context* c, const pm_species* sp, int n_sp,
+                             const float* rho, const float* acc, double* out);
 
 // deposit (pm_deposit.hip)
 pm_status run_deposit(pm_context* c, const pm_species* sp, int n_sp, float* rho);

@@ -162,8 +162,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(Get g, int64_t n,
   }
 }
 
+// bsum_ext (nullable): caller-provided block sums of at least cdiv(n, SCAN_TILE) entries
+// instead of the context's scratch
 template <typename Get>
-pm_status scan_generic(pm_context* c, Get g, int64_t n, int64_t* out) {
+pm_status scan_generic(pm_context* c, Get g, int64_t n, int64_t* out,
+                       int64_t* bsum_ext = nullptr) {
   int64_t nb = cdiv(n, SCAN_TILE);
   if (nb == 0) {
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, c->stream, out, 1,
@@ -171,7 +174,7 @@ pm_status scan_generic(pm_context* c, Get g, int64_t n, int64_t* out) {
     PM_LAUNCH_CHECK();
     return PM_OK;
   }
-  int64_t* bsum = (int64_t*)scratch(c, SC_BSUM, (size_t)nb * sizeof(int64_t));
+  int64_t* bsum = bsum_ext ? bsum_ext : (int64_t*)scratch(c, SC_BSUM, (size_t)nb * sizeof(int64_t));
   if (!bsum) return PM_ERR_NOMEM;
   hipLaunchKernelGGL(k_scan_reduce<Get>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0,
                      c->stream, g, n, bsum);

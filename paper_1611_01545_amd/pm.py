@@ -273,6 +273,17 @@ class PMContext:
               "pm_reduce")
         return out.cpu().numpy()
 
+    def reduce_noalloc(self, species, out: torch.Tensor, rho: torch.Tensor | None = None,
+                       acc: torch.Tensor | None = None) -> torch.Tensor:
+        """pm_reduce_noalloc into a caller-owned float64 tensor of 8 + 6 n_sp entries
+        (asynchronous; the library allocates nothing)."""
+        if out.dtype != torch.float64 or out.numel() < 8 + 6 * len(species):
+            raise ValueError("out must be float64 with 8 + 6 n_sp entries")
+        arr = _species_array(species) if species else None
+        check(self.lib.pm_reduce_noalloc(self.h, arr, len(species), _ptr(rho), _ptr(acc),
+                                         _ptr(out)), "pm_reduce_noalloc")
+        return out
+
     def pack_size(self, cs: CompressedSpecies) -> int:
         v = ctypes.c_int64()
         a = cs.c()
