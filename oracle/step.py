@@ -78,8 +78,12 @@ def kick_codes(u: np.ndarray, v_dec: np.ndarray, a_i: np.ndarray, v_max_new, S: 
 
 
 def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
-                    soft_cells: float = 1.0, G: float = 1.0 / mesh.FOUR_PI):
+                    soft_cells: float = 1.0, G: float = 1.0 / mesh.FOUR_PI, extra=None):
     """states: list of codec state dicts (same n_c, brick) -> new states + diagnostics.
+
+    extra (optional): per species an additional acceleration [n][3] in old stream order
+    (the cell-local PP force of eq. (4)); it is added to the interpolated mesh force, and
+    the velocity bound takes A_max + max |extra_a| over all species and axes.
 
     Diagnostics per species: 'perm' (new stream index -> old stream index), the
     pre-floor values 'pos_pre' = d + 1/2 and 'vel_pre' = v' C + 32768 in old stream
@@ -93,6 +97,9 @@ def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
     xs = [(x.astype(np.float64), m) for (x, _), m in zip(decoded, masses)]
     acc, a_mesh, rho = mesh.accelerations(xs, n_g, soft_cells, G)
     a_max = float(np.max(np.abs(a_mesh))) if a_mesh.size else 0.0
+    if extra is not None:
+        acc = [ai + np.asarray(e, dtype=np.float64) for ai, e in zip(acc, extra)]
+        a_max += max((float(np.max(np.abs(e))) for e in extra if np.size(e)), default=0.0)
     new_states, diags = [], []
     for st, (x, v), ai in zip(states, decoded, acc):
         u, _ = codec.decode_codes(st)
