@@ -224,6 +224,25 @@ pm_status pm_kick_drift_perm(pm_ctx ctx, const pm_species* in, pm_species* out, 
  * context's own mesh buffers. Same layout rules as pm_kick_drift. */
 pm_status pm_step(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp, double dt);
 
+/* The particle-particle force of eq. (4) (Sec. 2.1) inside the cells of the PM mesh:
+ * a_i = G sum_j m_j (x_j - x_i) / |x_j - x_i|^3 over the particles j != i of every species
+ * that share particle i's mesh cell (side L / n_mesh), truncated below the softening length
+ * r_soft (pairs closer than r_soft exert no force; the paper takes r_soft = L / (20 n_p)).
+ * Compressed species only (positions at bin centres; the cut is decided on the integer
+ * code differences, |du|^2 >= (r_soft 256 n_cell / L)^2). app: host array of n_sp device
+ * float [n][3] results in stream order; app_max (device float, nullable) receives the
+ * largest |a| component. Float32 sums in stream order (deterministic). */
+pm_status pm_pp_accel(pm_ctx ctx, const pm_species* sp, int n_sp, double r_soft,
+                      float* const* app, float* app_max);
+
+/* pm_step with the PP force added to the interpolated mesh force in the kick (the P^3M
+ * step of Sec. 2.1 on one mesh): v' = v + dt (a_mesh + a_pp), x' = x + dt v'; the velocity
+ * bound of the re-encode uses max |a_mesh| + max |a_pp|. Compressed species only. perm
+ * (nullable host array of n_sp device int64 [n] pointers, entries nullable) receives the
+ * re-sort as in pm_kick_drift_perm. */
+pm_status pm_step_pp(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp, double dt,
+                     double r_soft, int64_t* const* perm);
+
 /* Adjoint of pm_step at state `in` (straight-through for the quantisation of
  * compressed states). lam_x1, lam_v1: per species device float [n][3] cotangents of
  * the step's outputs, in the output's particle order; lam_x0, lam_v0: results, in
@@ -301,7 +320,7 @@ pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species
  * milliseconds and the number of timed launches:
  *   0 cell offsets   1 deposit          2 FFT x r2c     3 FFT y forward
  *   4 FFT z sweeps   5 FFT y inverse    6 FFT x c2r     7 interpolate-kick-drift
- *   8 re-sort        9 encode/decode   10 adjoint scatter/gather */
+ *   8 re-sort        9 encode/decode   10 adjoint scatter/gather   11 PP force */
 pm_status pm_profile(pm_ctx ctx, int enable);
 pm_status pm_profile_read(pm_ctx ctx, double* ms, int64_t* launches, int cap);
 

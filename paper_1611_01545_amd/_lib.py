@@ -88,6 +88,8 @@ EXPORTS = [
     ("pm_step", [P, PS, PS, ctypes.c_int, ctypes.c_double]),
     ("pm_step_vjp", [P, PS, ctypes.c_int, ctypes.c_double, P, P, P, P]),
     ("pm_loss_density_vjp", [P, PS, ctypes.c_int, P, P, P]),
+    ("pm_pp_accel", [P, PS, ctypes.c_int, ctypes.c_double, P, P]),
+    ("pm_step_pp", [P, PS, PS, ctypes.c_int, ctypes.c_double, ctypes.c_double, P]),
     ("pm_reduce", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_reduce_noalloc", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_pack", [P, PS, ctypes.c_int32, P, I64, P]),

@@ -22,10 +22,6 @@
 #include "pm_scan.h"
 
 int deposit_tile_cells(const Geom& g);
-pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
-                                  int n_sp, int64_t* const* offs, const float* acc,
-                                  const float* amax, double ck, double cd,
-                                  int64_t* const* perm);
 
 namespace {
 

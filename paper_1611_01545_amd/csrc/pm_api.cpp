@@ -91,10 +91,6 @@ void prof_end(pm_context* c) {
 }
 
 // pm_kick.hip
-pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
-                                  int n_sp, int64_t* const* offs, const float* acc,
-                                  const float* amax, double ck, double cd,
-                                  int64_t* const* perm);
 int deposit_tile_cells(const Geom& g);
 
 extern "C" {
@@ -370,6 +366,58 @@ pm_status pm_step(pm_ctx c, const pm_species* in, pm_species* out, int n_sp, dou
   if ((s = run_deposit(c, in, n_sp, mesh)) != PM_OK) return s;
   if ((s = run_force(c, mesh, mesh, c->nyq, c->amax)) != PM_OK) return s;
   return kick_all(c, in, out, n_sp, mesh, c->amax, dt, dt, nullptr);
+}
+
+pm_status pm_pp_accel(pm_ctx c, const pm_species* sp, int n_sp, double r_soft,
+                      float* const* app, float* app_max) {
+  if (!c || !sp || !app || n_sp <= 0 || n_sp > 4) return PM_ERR_ARG;
+  if (!(r_soft >= 0.0) || !std::isfinite(r_soft)) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i) {
+    if (check_species(c, &sp[i], true) != PM_OK || sp[i].layout != PM_COMPRESSED)
+      return PM_ERR_ARG;
+    if (sp[i].n > 0 && !app[i]) return PM_ERR_ARG;
+  }
+  int64_t* offs[4] = {nullptr, nullptr, nullptr, nullptr};
+  pm_status s;
+  for (int i = 0; i < n_sp; ++i) {
+    offs[i] = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+    if (!offs[i]) return PM_ERR_NOMEM;
+    if ((s = run_cell_offsets(c, &sp[i], offs[i])) != PM_OK) return s;
+  }
+  return run_pp_accel(c, sp, n_sp, offs, r_soft, app, app_max ? app_max : c->amax + 1);
+}
+
+pm_status pm_step_pp(pm_ctx c, const pm_species* in, pm_species* out, int n_sp, double dt,
+                     double r_soft, int64_t* const* perm) {
+  if (!c) return PM_ERR_ARG;
+  pm_status s = check_kick_args(c, in, out, n_sp);
+  if (s != PM_OK) return s;
+  if (!std::isfinite(dt) || !(r_soft >= 0.0) || !std::isfinite(r_soft)) return PM_ERR_ARG;
+  if (in[0].layout != PM_COMPRESSED) return PM_ERR_ARG;
+  if ((s = ensure_step_meshes(c)) != PM_OK) return s;
+  float* mesh = c->mesh;
+  int64_t* offs[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t bytes = 0;
+  for (int i = 0; i < n_sp; ++i) {
+    offs[i] = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+    if (!offs[i]) return PM_ERR_NOMEM;
+    if ((s = run_cell_offsets(c, &in[i], offs[i])) != PM_OK) return s;
+    bytes += ((size_t)in[i].n * 12 + 255) & ~(size_t)255;
+  }
+  char* pool = (char*)scratch(c, SC_PPACC, bytes);
+  if (!pool) return PM_ERR_NOMEM;
+  float* app[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t at = 0;
+  for (int i = 0; i < n_sp; ++i) {
+    app[i] = (float*)(pool + at);
+    at += ((size_t)in[i].n * 12 + 255) & ~(size_t)255;
+  }
+  if ((s = run_deposit_tile(c, in, n_sp, offs, mesh)) != PM_OK) return s;
+  if ((s = run_force(c, mesh, mesh, c->nyq, c->amax)) != PM_OK) return s;
+  if ((s = run_pp_accel(c, in, n_sp, offs, r_soft, app, c->amax + 1)) != PM_OK) return s;
+  if ((s = run_add_max(c, c->amax, c->amax + 1, c->amax + 2)) != PM_OK) return s;
+  return run_kick_compressed_all(c, in, out, n_sp, offs, mesh, c->amax + 2, dt, dt, perm,
+                                 app);
 }
 
 pm_status pm_step_vjp(pm_ctx c, const pm_species* in, int n_sp, double dt,

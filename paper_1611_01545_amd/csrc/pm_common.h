@@ -105,7 +105,7 @@ struct pm_context {
   DevErr* err = nullptr;
   float* amax = nullptr;  // device scalar
   // grow-on-demand scratch
-  DevBuf scratch[32];
+  DevBuf scratch[40];
   // this device's fixed array of pm_reduce_noalloc (device address, set by pm_create)
   unsigned char* na_scratch = nullptr;
   int64_t last_detail = 0;
@@ -119,7 +119,7 @@ struct pm_context {
 
 enum ProfStage {
   ST_OFFSETS = 0, ST_DEPOSIT, ST_FFT_R2C, ST_FFT_YF, ST_FFT_Z, ST_FFT_YI, ST_FFT_C2R,
-  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_N
+  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_PP, ST_N
 };
 // Record a begin/end event pair around a group of launches (no-op unless profiling).
 void prof_begin(pm_context* c, int stage);
@@ -162,6 +162,8 @@ enum ScratchId {
   SC_SPEC,         // float [ng^3] spectrum scratch of the force transforms
   SC_FOLD,         // first-stage results of the grid min / max folds
   SC_NMOV,         // int64 [4]: mover count of each species (device-side)
+  SC_PPMAX,        // per-workgroup max |a| of the PP force
+  SC_PPACC,        // float [N][3] PP accelerations of pm_step_pp
   SC_N
 };
 
@@ -234,6 +236,18 @@ pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq);
 // kick-drift (pm_kick.hip)
 pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
                          const float* acc, double ck, double cd);
+// All species of a compressed state: the fused kick and the re-sort. offs[s]: input cell
+// offsets; perm[s] (nullable): new stream position -> old; app[s] (nullable array):
+// per-particle accelerations added to the interpolated force (the PP term).
+pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
+                                  int n_sp, int64_t* const* offs, const float* acc,
+                                  const float* amax, double ck, double cd,
+                                  int64_t* const* perm, const float* const* app = nullptr);
+// PP force of eq. (4) inside the mesh cells (pm_pp.hip): app[s] float [n][3], stream
+// order; pmax receives max |a| over all particles and axes
+pm_status run_pp_accel(pm_context* c, const pm_species* sp, int n_sp, int64_t* const* offs,
+                       double r_soft, float* const* app, float* pmax);
+pm_status run_add_max(pm_context* c, const float* a, const float* b, float* out);
 pm_status run_kick_compressed(pm_context* c, const pm_species* in, pm_species* out,
                               const float* acc, const float* amax, double ck, double cd,
                               uint32_t* perm_new_to_old);

@@ -122,6 +122,7 @@ struct KickSpecies {
   uint32_t* mcnt;      // movers per brick
   int32_t* pmn;        // per-brick extreme new velocity codes, folded into hout
   int32_t* pmx;
+  const float* app;    // nullable: per-particle acceleration added to the mesh force
 };
 struct KickArgs {
   KickSpecies sp[MAXSP];
@@ -200,6 +201,10 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
     }
     float acc3[3];
     gather(li, f, acc3);
+    if (S.app) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc3[a] += S.app[3 * j + a];
+    }
     const uint32_t Sm = (uint32_t)g.S - 1;
     const double Sd = (double)g.S, invS = 1.0 / Sd;  // powers of two
     uint8_t* tp = S.tpos + 3 * jc;
@@ -828,7 +833,7 @@ pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
 pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
                                   int n_sp, int64_t* const* offs, const float* acc,
                                   const float* amax, double ck, double cd,
-                                  int64_t* const* perm) {
+                                  int64_t* const* perm, const float* const* app) {
   const Geom& g = c->g;
   if (n_sp <= 0 || n_sp > MAXSP) return PM_ERR_ARG;
   const int B3 = g.B * g.B * g.B;
@@ -875,6 +880,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     S.mcnt = mcnt + (int64_t)s * g.nbrick;
     S.pmn = part + (int64_t)2 * s * g.nbrick;
     S.pmx = S.pmn + g.nbrick;
+    S.app = app ? app[s] : nullptr;
   }
   {
     pm_status st0;

@@ -240,6 +240,28 @@ class PMContext:
         check(self.lib.pm_step(self.h, a, b, len(species), float(dt)), "pm_step")
         return out
 
+    def pp_accel(self, species, r_soft: float, app_max: torch.Tensor | None = None):
+        """pm_pp_accel: PP accelerations [n][3] per species (stream order)."""
+        ns = len(species)
+        app = [torch.empty((s.n, 3), dtype=torch.float32, device=self.device) for s in species]
+        arr = _species_array(species)
+        check(self.lib.pm_pp_accel(self.h, arr, ns, float(r_soft),
+                                   (ctypes.c_void_p * ns)(*[_ptr(t) for t in app]),
+                                   _ptr(app_max)), "pm_pp_accel")
+        return app
+
+    def step_pp(self, species, dt: float, r_soft: float, out=None, want_perm: bool = False):
+        """pm_step_pp; with want_perm also the re-sort (new -> old stream position)."""
+        if out is None:
+            out = [self.empty_like(s) for s in species]
+        a, b = _species_array(species), _species_array(out)
+        perms = [torch.empty(s.n, dtype=torch.int64, device=self.device) for s in species] \
+            if want_perm else None
+        pp = (ctypes.c_void_p * len(species))(*[_ptr(p) for p in perms]) if perms else None
+        check(self.lib.pm_step_pp(self.h, a, b, len(species), float(dt), float(r_soft), pp),
+              "pm_step_pp")
+        return (out, perms) if want_perm else out
+
     def step_vjp(self, species, dt: float, lam_x1, lam_v1):
         ns = len(species)
         lam_x0 = [torch.empty_like(t) for t in lam_x1]
@@ -313,7 +335,8 @@ class PMContext:
         return out, sid.value
 
     STAGES = ["cell_offsets", "deposit", "fft_x_r2c", "fft_y_fwd", "fft_z",
-              "fft_y_inv", "fft_x_c2r", "interp_kick_drift", "resort", "codec", "adjoint"]
+              "fft_y_inv", "fft_x_c2r", "interp_kick_drift", "resort", "codec", "adjoint",
+              "pp"]
 
     def profile(self, enable: bool = True):
         check(self.lib.pm_profile(self.h, 1 if enable else 0), "pm_profile")
