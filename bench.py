@@ -434,6 +434,27 @@ def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True
            "deposit_frac": stages["deposit"]["gbs"] / HBM_PEAK_GBS,
            "interp_kick_drift_frac": stages["interp_kick_drift"]["gbs"] / HBM_PEAK_GBS}
     log(f"[bench] tile_1024: {ms_step:.3f} ms/step, {value:.3e} particle-updates/s")
+    # the same step with the cell-local PP force of eq. (4), r_soft = L / (20 n_p)
+    r_soft = 1.0 / (20 * 2 * wl.n_cell)
+    nxt = [ctx.empty_like(s) for s in cur]
+    ctx.step_pp(cur, wl.dt, r_soft, out=nxt)
+    ctx.sync()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step_pp(cur, wl.dt, r_soft, out=nxt)
+    torch.cuda.synchronize()
+    t_pp = (time.perf_counter() - t0) * 1e3 / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_pp, n_pp = prof["pp"]
+    out["pp_step"] = {"ms_per_step": t_pp, "pp_kernel_ms": ms_pp / max(1, n_pp),
+                      "r_soft": r_soft,
+                      "note": "pm_step_pp: the step with the cell-local PP force added"}
+    del nxt
+    log(f"[bench] tile_1024 with the PP force: {t_pp:.3f} ms/step "
+        f"(PP kernel {ms_pp / max(1, n_pp):.3f} ms)")
     if adjoint:
         lx = [torch.ones((sp.n, 3), dtype=torch.float32, device=ctx.device) for sp in cur]
         lv = [torch.ones_like(t) for t in lx]

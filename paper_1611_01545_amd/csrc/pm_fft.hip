@@ -221,11 +221,13 @@ __device__ __forceinline__ void tr_to_nat(float2 (&b)[Plan<N>::E], int t, float*
 // ------------------------------------------------------------ spectrum layout --
 // The half spectrum (kx < n/2, M = n/2 complex per row) is stored z-blocked:
 //   index(kx, y, z) = ((z / ZB) n + y) ZB M + (z % ZB) M + kx,   ZB = min(16, T(n)),
+// and ZB = 64 for split lines (2048 points, where a line's natural point stride is 64),
 // so that a z line visits n / ZB address blocks of ZB consecutive rows instead of n
 // blocks 4 n M bytes apart (one address translation per ZB points), while y lines keep
 // runs of W kx at a stride of ZB M. The Nyquist plane kx = n/2 is a separate [z][y]
 // array. T(n) is the four-step split of an n-point line, so ZB divides T and E.
 __host__ __device__ constexpr int zblk(int n) {
+  if (n >= 2048) return 64;  // split lines: the natural point stride H T = 64
   int t = 1 << (ilog2(n) / 2);
   return t < 16 ? t : 16;
 }
@@ -263,6 +265,100 @@ __device__ __forceinline__ int signed_k(int k, int n) { return k < n / 2 ? k : k
 // context's table gk[k], k < n (built in float64 on the host).
 __device__ __forceinline__ float grad_k(const float* __restrict__ gk, int k) { return gk[k]; }
 
+// ------------------------------------------------------------- line plans --
+// A column line of N points is held by H groups of T threads: H = 1 below 2048 points
+// (the four-step engine above on the whole line), H = 2 at 2048 points, where the even
+// and odd points are two lines of N/2 on their own thread groups (half the registers per
+// thread), joined by one radix-2 step through LDS. Natural layout: thread (t, h) holds
+// point H (t + T n1) + h, n1 < E; transposed layout: value v T + k2 is frequency
+// (t + T v) + E k2 + h N/2.
+template <int N>
+struct LP {
+  static constexpr int H = N >= 2048 ? 2 : 1;
+  static constexpr int NH = N / H;
+  using P = Plan<NH>;
+  static constexpr int T = P::T, E = P::E, V = P::V, TP = P::TP;
+  static constexpr int TL = H * T;          // threads per line
+  static constexpr int LF = H * E * TP;     // LDS floats per line
+};
+
+// Radix-2 step of a split line (H = 2). After the half-length transforms thread (t, h)
+// holds values of its half's spectrum at frequencies k = (t + T v) + E k2; the partner
+// (t, 1 - h) holds the same k of the other half. Real parts, then imaginary parts, go
+// through the line's LDS; w = exp(SIGN 2 pi i k / N).
+//   DIF = false (forward, after the half transforms): X[k] = Y0 + w Y1 on h = 0,
+//                X[k + N/2] = Y0 - w Y1 on h = 1;
+//   DIF = true  (before the half inverse transforms): Y0 = X[k] + X[k + N/2] on h = 0,
+//                Y1 = (X[k] - X[k + N/2]) w on h = 1.
+template <int N, int SIGN, bool DIF>
+__device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h, float* my,
+                                             const float2* __restrict__ tw, int tws,
+                                             int twmask) {
+  using L = LP<N>;
+  float* mine = my + h * (L::E * L::TP);
+  const float* other = my + (1 - h) * (L::E * L::TP);
+  float pre[L::E];
+#pragma unroll
+  for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].x;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < L::E; ++q) pre[q] = other[q * L::TP + t];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].y;
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < L::V; ++v)
+#pragma unroll
+    for (int k2 = 0; k2 < L::T; ++k2) {
+      const int q = v * L::T + k2;
+      const int k = (t + L::T * v) + L::E * k2;
+      const float2 pp = make_float2(pre[q], other[q * L::TP + t]);
+      float2 w = tw[(k * tws) & twmask];  // exp(-2 pi i k / N)
+      if (SIGN > 0) w.y = -w.y;
+      if (!DIF) {
+        if (h == 0) {
+          const float2 z = cmul(w, pp);
+          a[q] = make_float2(a[q].x + z.x, a[q].y + z.y);
+        } else {
+          const float2 z = cmul(w, a[q]);
+          a[q] = make_float2(pp.x - z.x, pp.y - z.y);
+        }
+      } else {
+        if (h == 0) a[q] = make_float2(a[q].x + pp.x, a[q].y + pp.y);
+        else a[q] = cmul(make_float2(pp.x - a[q].x, pp.y - a[q].y), w);
+      }
+    }
+  __syncthreads();
+}
+
+// Line transforms on the plan: natural -> transposed (forward or inverse) and
+// transposed -> natural. tw: table exp(-2 pi i j / n) of the full line, stride tws.
+template <int N, int SIGN>
+__device__ __forceinline__ void line_nat_to_tr(float2 (&a)[LP<N>::E], int t, int h, float* my,
+                                               const float2* __restrict__ tw, int tws,
+                                               int twmask) {
+  using L = LP<N>;
+  if constexpr (L::H == 1) {
+    nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
+  } else {
+    nat_to_tr<L::NH, SIGN>(a, t, my + h * (L::E * L::TP), tw, 2 * tws, twmask);
+    split_radix2<N, SIGN, false>(a, t, h, my, tw, tws, twmask);
+  }
+}
+template <int N, int SIGN>
+__device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int h, float* my,
+                                               const float2* __restrict__ tw, int tws,
+                                               int twmask) {
+  using L = LP<N>;
+  if constexpr (L::H == 1) {
+    tr_to_nat<N, SIGN>(a, t, my, tw, tws, twmask);
+  } else {
+    split_radix2<N, SIGN, true>(a, t, h, my, tw, tws, twmask);
+    tr_to_nat<L::NH, SIGN>(a, t, my + h * (L::E * L::TP), tw, 2 * tws, twmask);
+  }
+}
+
 // Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
 // only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
 // inverse y pass). OUT 3 (y lines of the transposed force): out0 = +i k_x FFT_SIGN(in) +
@@ -270,90 +366,94 @@ __device__ __forceinline__ float grad_k(const float* __restrict__ gk, int k) { r
 // the twiddles are staged in LDS (32-bit addresses), which keeps both line arrays in
 // registers without spilling.
 template <int N, int W, int SIGN, int OUT>
-__global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
-                                                            const float2* in1, float2* out0,
-                                                            float2* out1, Lines d,
-                                                            const float2* __restrict__ tw,
-                                                            int tws, int twmask, int n,
-                                                            const float* __restrict__ gk) {
-  using P = Plan<N>;
-  constexpr int CS = col_cs<W>(P::E * P::TP);
+__global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
+                                                           const float2* in1, float2* out0,
+                                                           float2* out1, Lines d,
+                                                           const float2* __restrict__ tw,
+                                                           int tws, int twmask, int n,
+                                                           const float* __restrict__ gk) {
+  using L = LP<N>;
+  constexpr int CS = col_cs<W>(L::LF);
   __shared__ float lds[W * CS];
   constexpr bool TWO = OUT == 2 || OUT == 3;
   __shared__ float2 stw[TWO ? N : 1];
   if constexpr (TWO) {
-    for (int i = threadIdx.x; i < N; i += W * P::T) stw[i] = tw[(i * tws) & twmask];
+    for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
     __syncthreads();
   }
   // the grid covers the lines exactly (W divides the line count; checked on the host)
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int c = threadIdx.x % W, tl = threadIdx.x / W;
+  const int t = tl % L::T, h = tl / L::T;
   // addresses: a workgroup-uniform 64-bit part plus a 32-bit per-thread offset
   const int64_t ubase = line_base(d, (int64_t)blockIdx.x * W, blockIdx.y);
-  const uint32_t lo_in = (uint32_t)(c * d.s1 + (int64_t)t * d.es);
+  const int e0 = L::H * t + h;  // natural point of n1 = 0; point n1 is e0 + H T n1
+  const uint32_t lo_in = (uint32_t)(c * d.s1 + (int64_t)e0 * d.es);
+  // transposed frequency (t + T v) + E k2 + h N/2: per-thread part and k2 stride
+  auto lo_out = [&](int v) {
+    return (uint32_t)(c * d.s1 + (int64_t)((t + L::T * v) + h * L::NH) * d.es);
+  };
   float* my = lds + c * CS;
-  float2 a[P::E];
+  float2 a[L::E];
 #pragma unroll
-  for (int n1 = 0; n1 < P::E; ++n1) a[n1] = (in + (ubase + (int64_t)P::T * n1 * d.es))[lo_in];
+  for (int n1 = 0; n1 < L::E; ++n1)
+    a[n1] = (in + (ubase + (int64_t)L::H * L::T * n1 * d.es))[lo_in];
   if constexpr (OUT == 1) {
     // -i k (x + i y) = k y - i k x; k is the line's own wave number
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) {
-      float k = grad_k(gk, t + P::T * n1);
+    for (int n1 = 0; n1 < L::E; ++n1) {
+      float k = grad_k(gk, e0 + L::H * L::T * n1);
       a[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
     }
     out0 = out1;
   }
   if constexpr (OUT == 3) {
-    float2 b[P::E];
+    float2 b[L::E];
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) b[n1] = (in1 + (ubase + (int64_t)P::T * n1 * d.es))[lo_in];
-    nat_to_tr<N, SIGN>(a, t, my, stw, 1, N - 1);
-    nat_to_tr<N, SIGN>(b, t, my, stw, 1, N - 1);
+    for (int n1 = 0; n1 < L::E; ++n1)
+      b[n1] = (in1 + (ubase + (int64_t)L::H * L::T * n1 * d.es))[lo_in];
+    line_nat_to_tr<N, SIGN>(a, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, SIGN>(b, t, h, my, stw, 1, N - 1);
     const float kxg = grad_k(gk, d.kx_mode ? d.kx_fixed : (int)(blockIdx.x * W) + c);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const float kyg = grad_k(gk, (t + P::T * v) + P::E * k2);
-        const float2 q = a[v * P::T + k2], p = b[v * P::T + k2];
+      for (int k2 = 0; k2 < L::T; ++k2) {
+        const float kyg = grad_k(gk, (t + L::T * v) + L::E * k2 + h * L::NH);
+        const float2 q = a[v * L::T + k2], p = b[v * L::T + k2];
         // + i (k_x q + k_y p)
-        a[v * P::T + k2] = make_float2(-(kxg * q.y + kyg * p.y), kxg * q.x + kyg * p.x);
+        a[v * L::T + k2] = make_float2(-(kxg * q.y + kyg * p.y), kxg * q.x + kyg * p.x);
       }
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2)
-        (out0 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
-            a[v * P::T + k2];
+      for (int k2 = 0; k2 < L::T; ++k2)
+        (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
   } else if constexpr (OUT == 2) {
-    float2 b[P::E];
+    float2 b[L::E];
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) {
-      float k = grad_k(gk, t + P::T * n1);
+    for (int n1 = 0; n1 < L::E; ++n1) {
+      float k = grad_k(gk, e0 + L::H * L::T * n1);
       b[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
     }
-    nat_to_tr<N, SIGN>(a, t, my, stw, 1, N - 1);
+    line_nat_to_tr<N, SIGN>(a, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2)
-        (out0 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
-            a[v * P::T + k2];
-    nat_to_tr<N, SIGN>(b, t, my, stw, 1, N - 1);
+      for (int k2 = 0; k2 < L::T; ++k2)
+        (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
+    line_nat_to_tr<N, SIGN>(b, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2)
-        (out1 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
-            b[v * P::T + k2];
+      for (int k2 = 0; k2 < L::T; ++k2)
+        (out1 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = b[v * L::T + k2];
   } else {
-    nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
+    line_nat_to_tr<N, SIGN>(a, t, h, my, tw, tws, twmask);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2)
-        (out0 + (ubase + (int64_t)P::E * k2 * d.es))[(uint32_t)(c * d.s1 + (int64_t)(t + P::T * v) * d.es)] =
-            a[v * P::T + k2];
+      for (int k2 = 0; k2 < L::T; ++k2)
+        (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
   }
 }
 
@@ -365,32 +465,35 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_fft(const float2* in,
 // already holds the x and y terms +i (k_x mu_x + k_y mu_y) from the y pass. BLK: the
 // lines are z-blocked (main spectrum) or plain strided (Nyquist plane).
 template <int N, int W, int MODE, bool BLK>
-__global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
+__global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     const float2* in0, const float2* in1, const float2* in2, float2* out0, float2* out1,
     Lines d,
     const float2* __restrict__ tw, int tws, int twmask, int n,
     const float* __restrict__ gtab, const float* __restrict__ gk) {
-  using P = Plan<N>;
+  using L = LP<N>;
   constexpr int ZB = zblk(N), LZB = ilog2(ZB);
-  static_assert(P::T % ZB == 0, "z blocks must divide the thread stride");
-  constexpr int CS = col_cs<W>(P::E * P::TP);
+  static_assert((L::H * L::T) % ZB == 0, "z blocks must divide the thread stride");
+  constexpr int CS = col_cs<W>(L::LF);
   __shared__ float lds[W * CS];
   // the line's twiddles exp(-2 pi i j / N) in LDS: 32-bit LDS addresses instead of
   // 64-bit global pointers per twiddle, which the two inverse transforms of MODE 3
   // would otherwise keep live together
   __shared__ float2 stw[N];
-  for (int i = threadIdx.x; i < N; i += W * P::T) stw[i] = tw[(i * tws) & twmask];
+  for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
   __syncthreads();
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int c = threadIdx.x % W, tl = threadIdx.x / W;
+  const int t = tl % L::T, h = tl / L::T;
   const int64_t l1 = (int64_t)blockIdx.x * W + c;
-  // element t + T n1 of the line: z-blocked lines split it as (block, row in block).
-  // Addresses are a workgroup-uniform 64-bit part (scalar registers) plus a 32-bit
-  // per-thread offset, so that no 64-bit address per point stays live in VGPRs.
+  // point e0 + H T n1 of the line (e0 = H t + h): z-blocked lines split it as (block,
+  // row in block). Addresses are a workgroup-uniform 64-bit part (scalar registers) plus
+  // a 32-bit per-thread offset, so that no 64-bit address per point stays live in VGPRs.
   const int64_t ubase = line_base(d, (int64_t)blockIdx.x * W, blockIdx.y);
+  const int e0 = L::H * t + h;
   const uint32_t toff =
-      (uint32_t)(c * d.s1 + (BLK ? (int64_t)(t >> LZB) * d.es + (int64_t)(t & (ZB - 1)) * d.esl
-                                 : (int64_t)t * d.es));
-  const int64_t step = BLK ? (int64_t)(P::T >> LZB) * d.es : (int64_t)P::T * d.es;
+      (uint32_t)(c * d.s1 + (BLK ? (int64_t)(e0 >> LZB) * d.es + (int64_t)(e0 & (ZB - 1)) * d.esl
+                                 : (int64_t)e0 * d.es));
+  const int64_t step = BLK ? (int64_t)((L::H * L::T) >> LZB) * d.es
+                           : (int64_t)L::H * L::T * d.es;
   float* my = lds + c * CS;
   const int kx = d.kx_mode ? d.kx_fixed : (int)l1;
   const int ky = d.ky_mode ? (int)l1 : (int)blockIdx.y;
@@ -399,84 +502,84 @@ __global__ __launch_bounds__(W * Plan<N>::T) void k_col_zconv(
   const int h1 = n / 2 + 1;
   const float* __restrict__ grow =
       gtab + ((int64_t)(sx < 0 ? -sx : sx) * h1 + (sy < 0 ? -sy : sy)) * h1;
-  float2 acc[P::E];
+  float2 acc[L::E];
   if constexpr (MODE == 3) {
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
-    nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
-    float2 gz[P::E];
+    for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
+    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
+    float2 gz[L::E];
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const int kz = (t + P::T * v) + P::E * k2;
+      for (int k2 = 0; k2 < L::T; ++k2) {
+        const int kz = (t + L::T * v) + L::E * k2 + h * L::NH;
         const int sz = signed_k(kz, n);
         const float G = grow[sz < 0 ? -sz : sz];
-        const float2 f = make_float2(G * acc[v * P::T + k2].x, G * acc[v * P::T + k2].y);
+        const float2 f = make_float2(G * acc[v * L::T + k2].x, G * acc[v * L::T + k2].y);
         const float kk = grad_k(gk, kz);
-        acc[v * P::T + k2] = f;
-        gz[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
+        acc[v * L::T + k2] = f;
+        gz[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
       }
-    tr_to_nat<N, +1>(acc, t, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
-    tr_to_nat<N, +1>(gz, t, my, stw, 1, N - 1);
+    for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
+    line_tr_to_nat<N, +1>(gz, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) (out1 + (ubase + n1 * step))[toff] = gz[n1];
+    for (int n1 = 0; n1 < L::E; ++n1) (out1 + (ubase + n1 * step))[toff] = gz[n1];
   } else if constexpr (MODE == 0 || MODE == 2) {
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
-    nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
+    for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
+    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const int kz = (t + P::T * v) + P::E * k2;
+      for (int k2 = 0; k2 < L::T; ++k2) {
+        const int kz = (t + L::T * v) + L::E * k2 + h * L::NH;
         const int sz = signed_k(kz, n);
         const float G = grow[sz < 0 ? -sz : sz];
-        const float2 f = acc[v * P::T + k2];
+        const float2 f = acc[v * L::T + k2];
         if constexpr (MODE == 2) {
           // -i k_z G (x + i y) = k_z G y - i k_z G x
           const float kk = grad_k(gk, kz) * G;
-          acc[v * P::T + k2] = make_float2(kk * f.y, -kk * f.x);
+          acc[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);
         } else {
-          acc[v * P::T + k2] = make_float2(G * f.x, G * f.y);
+          acc[v * L::T + k2] = make_float2(G * f.x, G * f.y);
         }
       }
-    tr_to_nat<N, +1>(acc, t, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
+    for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   } else {
     // sum_a (+i k_a) FFT_z(in_a): the x and y terms arrive summed in in0; k_z multiplies
     // after FFT_z(in2)
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) acc[n1] = (in2 + (ubase + n1 * step))[toff];
-    nat_to_tr<N, -1>(acc, t, my, stw, 1, N - 1);
+    for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in2 + (ubase + n1 * step))[toff];
+    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const float k = grad_k(gk, (t + P::T * v) + P::E * k2);
-        const float2 q = acc[v * P::T + k2];
-        acc[v * P::T + k2] = make_float2(-k * q.y, k * q.x);  // + i k (x + i y)
+      for (int k2 = 0; k2 < L::T; ++k2) {
+        const float k = grad_k(gk, (t + L::T * v) + L::E * k2 + h * L::NH);
+        const float2 q = acc[v * L::T + k2];
+        acc[v * L::T + k2] = make_float2(-k * q.y, k * q.x);  // + i k (x + i y)
       }
-    float2 f[P::E];
+    float2 f[L::E];
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) f[n1] = (in0 + (ubase + n1 * step))[toff];
-    nat_to_tr<N, -1>(f, t, my, stw, 1, N - 1);
+    for (int n1 = 0; n1 < L::E; ++n1) f[n1] = (in0 + (ubase + n1 * step))[toff];
+    line_nat_to_tr<N, -1>(f, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int v = 0; v < P::V; ++v)
+    for (int v = 0; v < L::V; ++v)
 #pragma unroll
-      for (int k2 = 0; k2 < P::T; ++k2) {
-        const int kz = (t + P::T * v) + P::E * k2;
+      for (int k2 = 0; k2 < L::T; ++k2) {
+        const int kz = (t + L::T * v) + L::E * k2 + h * L::NH;
         const int sz = signed_k(kz, n);
         const float G = grow[sz < 0 ? -sz : sz];
-        const float2 q = acc[v * P::T + k2], p = f[v * P::T + k2];
-        acc[v * P::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
+        const float2 q = acc[v * L::T + k2], p = f[v * L::T + k2];
+        acc[v * L::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
       }
-    tr_to_nat<N, +1>(acc, t, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
-    for (int n1 = 0; n1 < P::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
+    for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   }
 }
 
@@ -667,11 +770,16 @@ __global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h) {
 }
 
 // ------------------------------------------------------------------ dispatch --
-// columns per workgroup: at most 16, at most half the line length (the number of kx
-// lines is N/2, so W always divides the line count), and the LDS exchange <= 64 KB
-template <int N>
+// columns per workgroup: at most 16 and at most half the line length (the number of kx
+// lines is N/2, so W always divides the line count), W runs of 8-byte points per global
+// access; LDS per workgroup (the exchange tiles, plus staged twiddles for two-output
+// passes) within what one gfx950 workgroup may hold. Split lines (2048 points) take 16
+// columns (1024 threads: 128-byte runs) in one-output passes and 8 in two-output passes,
+// whose two register arrays do not fit 1024 threads.
+template <int N, bool TWO>
 constexpr int col_w() {
   int w = 16384 / N;
+  if (LP<N>::H == 2 && !TWO) w = 16;
   if (w > 16) w = 16;
   if (w > N / 2) w = N / 2;
   if (w < 1) w = 1;
@@ -689,15 +797,16 @@ struct FftCtx {
 template <int N>
 pm_status col_fft(const FftCtx& f, const float2* in, const float2* in1, float2* o0, float2* o1,
                   const Lines& d, int64_t L2, int sign) {
-  constexpr int W = col_w<N>();
-  if (d.L1 % W) return PM_ERR_SHAPE;
-  dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
-  dim3 block(W * Plan<N>::T);
+  constexpr int W1 = col_w<N, false>(), W2 = col_w<N, true>();
   const int out = in1 ? 3 : o1 ? (o0 ? 2 : 1) : 0;
   if (out == 3 && (sign > 0 || o1)) return PM_ERR_ARG;
-#define CLAUNCH(S, O)                                                                 \
-  hipLaunchKernelGGL((k_col_fft<N, W, S, O>), grid, block, 0, f.c->stream, in, in1, o0, \
-                     o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gk)
+  const int W = (out == 2 || out == 3) ? W2 : W1;
+  if (d.L1 % W) return PM_ERR_SHAPE;
+  dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
+  dim3 block(W * LP<N>::TL);
+#define CLAUNCH(S, O)                                                                     \
+  hipLaunchKernelGGL((k_col_fft<N, (O == 2 || O == 3) ? W2 : W1, S, O>), grid, block, 0,  \
+                     f.c->stream, in, in1, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gk)
   if (sign < 0) {
     if (out == 3) CLAUNCH(-1, 3);
     else if (out == 0) CLAUNCH(-1, 0);
@@ -716,13 +825,16 @@ pm_status col_fft(const FftCtx& f, const float2* in, const float2* in1, float2* 
 template <int N>
 pm_status col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0, const float2* i1,
                     const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
-  constexpr int W = col_w<N>();
+  // every fused z pass stages its twiddles; MODE 1 and 3 hold two line arrays
+  constexpr int W1 = col_w<N, false>(), W2 = col_w<N, true>();
+  const int W = (mode == 1 || mode == 3) ? W2 : W1;
   if (d.L1 % W) return PM_ERR_SHAPE;
   dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
-  dim3 block(W * Plan<N>::T);
-#define ZLAUNCH(MODE, BLK)                                                                 \
-  hipLaunchKernelGGL((k_col_zconv<N, W, MODE, BLK>), grid, block, 0, f.c->stream, i0, i1, \
-                     i2, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gtab, f.c->gk)
+  dim3 block(W * LP<N>::TL);
+#define ZLAUNCH(MODE, BLK)                                                                  \
+  hipLaunchKernelGGL((k_col_zconv<N, (MODE == 1 || MODE == 3) ? W2 : W1, MODE, BLK>), grid, \
+                     block, 0, f.c->stream, i0, i1, i2, o0, o1, d, f.c->tw, 1, f.twmask,    \
+                     f.n, f.c->gtab, f.c->gk)
   if (blk) {
     if (mode == 0) ZLAUNCH(0, true);
     else if (mode == 2) ZLAUNCH(2, true);
@@ -924,14 +1036,30 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
     if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, -1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
+  // Split lines (2048 points) run the two-output passes as two one-output launches, each
+  // at 16 columns per workgroup (128-byte runs) instead of 8: one more read of the input,
+  // against wider accesses in both.
+  const bool wide = n >= 2048;
   {
     ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_col_zconv(f, 3, true, A1, nullptr, nullptr, A1, S, zm, n)) != PM_OK) return s;
+    if (wide) {
+      if ((s = d_col_zconv(f, 2, true, A1, nullptr, nullptr, S, nullptr, zm, n)) != PM_OK)
+        return s;
+      if ((s = d_col_zconv(f, 0, true, A1, nullptr, nullptr, A1, nullptr, zm, n)) != PM_OK)
+        return s;
+    } else if ((s = d_col_zconv(f, 3, true, A1, nullptr, nullptr, A1, S, zm, n)) != PM_OK) {
+      return s;
+    }
   }
   if ((s = d_col_zconv(f, 3, false, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
   {
     ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, A1, A1, A2, ym, n, +1)) != PM_OK) return s;
+    if (wide) {
+      if ((s = d_col_fft(f, A1, nullptr, A2, ym, n, +1)) != PM_OK) return s;
+      if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, +1)) != PM_OK) return s;
+    } else if ((s = d_col_fft(f, A1, A1, A2, ym, n, +1)) != PM_OK) {
+      return s;
+    }
   }
   {
     ProfScope ps(c, ST_FFT_YI);

@@ -1,6 +1,7 @@
 """CPU replay of the index arithmetic of the HIP FFT passes (no GPU, no library call).
 
-The column passes (k_col_fft, k_col_zconv) give a workgroup W adjacent lines of N points;
+The column passes (k_col_fft, k_col_zconv) give a workgroup W adjacent lines of N points
+(from 2048 points on, each line as its even and odd halves on two thread groups);
 thread (c, t) = (tid % W, tid / W) holds points t + T n1 of line c in registers, moves them
 through a per-line LDS tile for the four-step exchange, and writes the result in the
 transposed order k = (t + T v) + E k2. The row passes pair X[k] with X[M - k] by lane
@@ -34,6 +35,15 @@ def plan(N):
     return T, E, E // T, T + 1
 
 
+def line_plan(N):
+    """(H, NH, T, E, V, TP): H thread groups of T threads per line, each group running
+    the four-step plan of NH = N / H points (H = 2 from 2048 points on)."""
+    H = 2 if N >= 2048 else 1
+    NH = N // H
+    T, E, V, TP = plan(NH)
+    return H, NH, T, E, V, TP
+
+
 def cmod(a, b):  # C++ remainder (sign of the dividend)
     r = abs(a) % b
     return -r if a < 0 else r
@@ -52,6 +62,8 @@ def col_w(N):
 
 
 def zblk(n):
+    if n >= 2048:
+        return 64
     t = 1 << (ilog2(n) // 2)
     return min(t, 16)
 
@@ -92,48 +104,54 @@ def line_base(d, l1, l2):
 
 
 def block_addresses(kind, n, W, bx, by, zpass):
-    """Addresses read for element e by thread (c, t), as the kernel computes them:
-    [W][T][E] arrays of (address, line l1, element e)."""
-    T, E, V, TP = plan(n)
+    """Addresses read for element e by thread (c, tl = (t, h)), as the kernel computes
+    them: [W][H T][E] arrays of (address, 32-bit offset, line l1, element e)."""
+    H, NH, T, E, V, TP = line_plan(n)
     d = lines(kind, n)
     s1, es, esl = d[0], d[4], d[5]
     ubase = line_base(d, bx * W, by)
     c = np.arange(W)[:, None, None]
-    t = np.arange(T)[None, :, None]
+    tl = np.arange(H * T)[None, :, None]
+    t, h = tl % T, tl // T
     n1 = np.arange(E)[None, None, :]
+    e0 = H * t + h
     blk = zpass and kind == "z_main"
     if blk:
         ZB = zblk(n)
         LZB = ilog2(ZB)
-        toff = c * s1 + (t >> LZB) * es + (t & (ZB - 1)) * esl
-        step = (T >> LZB) * es
+        toff = c * s1 + (e0 >> LZB) * es + (e0 & (ZB - 1)) * esl
+        step = ((H * T) >> LZB) * es
         addr = ubase + n1 * step + toff
+    elif zpass:
+        toff = c * s1 + e0 * es
+        addr = ubase + n1 * (H * T * es) + toff
     else:
-        toff = c * s1 + t * es
-        addr = ubase + T * n1 * es + toff
-    e = t + T * n1
+        toff = c * s1 + e0 * es
+        addr = ubase + H * T * n1 * es + toff
+    e = e0 + H * T * n1
     return addr, toff, bx * W + c + 0 * n1, e + 0 * c
 
 
 def write_addresses(kind, n, W, bx, by, zpass):
     """Addresses written for output point k = (t + T v) + E k2 (column passes) or point
     t + T n1 (the z pass writes back in natural order)."""
-    T, E, V, TP = plan(n)
+    H, NH, T, E, V, TP = line_plan(n)
     if zpass:
         return block_addresses(kind, n, W, bx, by, zpass)
     d = lines(kind, n)
     s1, es = d[0], d[4]
     ubase = line_base(d, bx * W, by)
     c = np.arange(W)[:, None, None, None]
-    t = np.arange(T)[None, :, None, None]
+    tl = np.arange(H * T)[None, :, None, None]
+    t, h = tl % T, tl // T
     v = np.arange(V)[None, None, :, None]
     k2 = np.arange(T)[None, None, None, :]
-    shp = (W, T, V, T)
-    off = np.broadcast_to(c * s1 + (t + T * v) * es, shp)
+    shp = (W, H * T, V, T)
+    off = np.broadcast_to(c * s1 + ((t + T * v) + h * NH) * es, shp)
     addr = ubase + E * k2 * es + off
-    k = np.broadcast_to((t + T * v) + E * k2, shp)
+    k = np.broadcast_to((t + T * v) + E * k2 + h * NH, shp)
     l1 = np.broadcast_to(bx * W + c, shp)
-    r = (W, T, V * T)
+    r = (W, H * T, V * T)
     return addr.reshape(r), off.reshape(r), l1.reshape(r), k.reshape(r)
 
 
@@ -144,8 +162,8 @@ LDS_MAX = 160 * 1024  # bytes of LDS one gfx950 workgroup may allocate
 def widths(n):
     ws = {col_w(n)}
     for w in (1, 2, 4, 8, 16):
-        T, E, V, TP = plan(n)
-        lds = w * col_cs(w, E * TP) * 4 + 8 * n  # exchange tiles + staged twiddles
+        H, NH, T, E, V, TP = line_plan(n)
+        lds = w * col_cs(w, H * E * TP) * 4 + 8 * n  # exchange tiles + staged twiddles
         if w <= n // 2 and lds <= LDS_MAX:
             ws.add(w)
     return sorted(ws)
@@ -153,21 +171,21 @@ def widths(n):
 
 @pytest.mark.parametrize("n", SIZES)
 def test_plan_and_lds_tiles(n):
-    T, E, V, TP = plan(n)
-    assert T * E == n and V in (1, 2) and E % T == 0
+    H, NH, T, E, V, TP = line_plan(n)
+    assert H * T * E == n and V in (1, 2) and E % T == 0
     ZB = zblk(n)
-    assert T % ZB == 0 and E % ZB == 0
+    assert (H * T) % ZB == 0 and (H == 2 or E % ZB == 0)
     for W in widths(n):
-        CS = col_cs(W, E * TP)
-        assert CS >= E * TP
-        nthreads = W * T
+        CS = col_cs(W, H * E * TP)
+        assert CS >= H * E * TP
+        nthreads = W * H * T
         assert nthreads <= 1024
-        # the twiddle staging loop: i = tid, tid + W T, ... < N fills stw once
+        # the twiddle staging loop: i = tid, tid + W H T, ... < N fills stw once
         filled = np.zeros(n, dtype=np.int64)
         for tid in range(nthreads):
             filled[np.arange(tid, n, nthreads)] += 1
         assert np.all(filled == 1)
-        # LDS exchange phases of nat_to_tr and tr_to_nat, per column c
+        # LDS exchange phases of nat_to_tr and tr_to_nat on each half's region
         t = np.arange(T)
         wr_nat = (np.arange(E)[:, None] * TP + t[None, :]).ravel()           # lds[k1 TP + t]
         rd_nat = ((t[:, None, None] + T * np.arange(V)[None, :, None]) * TP
@@ -175,7 +193,18 @@ def test_plan_and_lds_tiles(n):
         for wr, rd in ((wr_nat, rd_nat), (rd_nat, wr_nat)):  # tr_to_nat swaps the roles
             assert np.unique(wr).size == wr.size == E * T   # each word written once
             assert set(rd.tolist()) <= set(wr.tolist())      # reads only what was written
-            assert wr.max() < CS and wr.min() >= 0           # inside the line's column
+            assert wr.max() < E * TP and wr.min() >= 0       # inside the half's region
+        if H == 2:
+            # the radix-2 step: half h writes its region at q TP + t (q < E), reads the
+            # other half's at the same place; the two regions do not overlap
+            q = np.arange(E)[:, None]
+            reg = [(hh * E * TP + q * TP + t[None, :]).ravel() for hh in (0, 1)]
+            assert not set(reg[0].tolist()) & set(reg[1].tolist())
+            assert max(r.max() for r in reg) < H * E * TP <= CS
+            # every frequency k < N/2 is held once per half: (t + T v) + E k2
+            kk = ((t[:, None, None] + T * np.arange(V)[None, :, None]) +
+                  E * np.arange(T)[None, None, :]).ravel()
+            assert np.array_equal(np.sort(kk), np.arange(NH))
         assert W * CS * 4 + 8 * n <= LDS_MAX
 
 
