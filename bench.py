@@ -67,6 +67,52 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 2101697.0, "fetch_factor": 1.99988,
         "write_kib": 4196763.0, "write_factor": 1.0,
     },
+    # 2048^3: one FETCH_SIZE and one WRITE_SIZE pass of one step, per stage scope (the
+    # y inverse scope holds two launches and one, so its record is half the three)
+    ("fft_y_inv", "large_2048"): {
+        "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "fee8ab4b95eb970ed702acd84069a5625477433186960a9f567af59c10305585",
+        "fetch_kib": 25211604.0, "fetch_factor": 1.99993,
+        "write_kib": 50331648.0, "write_factor": 1.0,
+    },
+    ("fft_z", "large_2048"): {
+        "kernel": "k_col_zconv<2048, 16, 2, true> + k_col_zconv<2048, 16, 0, true>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "fee8ab4b95eb970ed702acd84069a5625477433186960a9f567af59c10305585",
+        "fetch_kib": 45692695.0, "fetch_factor": 1.99993,
+        "write_kib": 71827472.0, "write_factor": 1.0,
+    },
+    ("fft_x_c2r", "large_2048"): {
+        "kernel": "k_row_c2r<1024>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "fee8ab4b95eb970ed702acd84069a5625477433186960a9f567af59c10305585",
+        "fetch_kib": 16811505.0, "fetch_factor": 1.99993,
+        "write_kib": 33572408.0, "write_factor": 1.0,
+    },
+    ("interp_kick_drift", "large_2048"): {
+        "kernel": "k_kick_pair<256, 4>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h",
+                    "paper_1611_01545_amd/csrc/pm_codec.h",
+                    "paper_1611_01545_amd/csrc/pm_scan.h"],
+        "sha256": "fff91e06dcd39aebf869ff564980d4e06bd4f6624482a9ba47ec677e637439c8",
+        "fetch_kib": 66219485.0, "fetch_factor": 1.99993,
+        "write_kib": 17608274.0, "write_factor": 1.0,
+    },
+    ("deposit", "large_2048"): {
+        "kernel": "k_deposit_tile<4>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_deposit.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h",
+                    "paper_1611_01545_amd/csrc/pm_codec.h",
+                    "paper_1611_01545_amd/csrc/pm_scan.h"],
+        "sha256": "ba72a84f3d2c0869a96b140271e290639c4c739c55dcffafcb3a18a7a3831b71",
+        "fetch_kib": 4105054.0, "fetch_factor": 1.99993,
+        "write_kib": 33556300.0, "write_factor": 1.0,
+    },
 }
 
 
