@@ -25,4 +25,4 @@ design notes):
 Parity status of each function is stated in its module docstring.
 """
 
-from . import adjoint, codec, mesh, pp, step  # noqa: F401
+from . import adjoint, codec, mesh, pp, split, step  # noqa: F401

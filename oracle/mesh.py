@@ -140,11 +140,39 @@ def plummer_kernel_k(k: np.ndarray, eps: float, G: float) -> np.ndarray:
     return out
 
 
-def green(n_g: int, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI) -> np.ndarray:
-    """Kernel on the rfft grid [z][y][x<=n/2]; depends on |n|^2 only."""
+def split_factor(k: np.ndarray, split) -> np.ndarray:
+    """Gaussian force split of the two-level PM (oracle.split): split = (r_s, part) with
+    the split length r_s in box units; part 'long' gives exp(-k^2 r_s^2), 'short' gives
+    1 - exp(-k^2 r_s^2); None gives 1 (the one-level kernel)."""
+    k = np.asarray(k, dtype=np.float64)
+    if split is None:
+        return np.ones_like(k)
+    r_s, part = split
+    q = (k * r_s) ** 2
+    if part == "long":
+        return np.exp(-q)
+    if part == "short":
+        return -np.expm1(-q)
+    raise ValueError(f"unknown split part {part!r}")
+
+
+def cic_window2(nz, ny, nx, n_g: int) -> np.ndarray:
+    """Product of the CIC deposit and interpolation windows at integer wave numbers:
+    prod_a sinc(n_a / n_g)^4, sinc(t) = sin(pi t) / (pi t)."""
+    return (np.sinc(nx / n_g) * np.sinc(ny / n_g) * np.sinc(nz / n_g)) ** 4
+
+
+def green(n_g: int, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI,
+          split=None) -> np.ndarray:
+    """Kernel on the rfft grid [z][y][x<=n/2]. One level: a function of |n|^2 only.
+    split (see split_factor): the long-range part is also divided by the mesh's CIC
+    window product (oracle.split)."""
     nz, ny, nx = wave_numbers(n_g)
     k = 2.0 * np.pi * np.sqrt(nz * nz + ny * ny + nx * nx)
-    return plummer_kernel_k(k, soft_cells / n_g, G)
+    g = plummer_kernel_k(k, soft_cells / n_g, G) * split_factor(k, split)
+    if split is not None and split[1] == "long":
+        g = g / cic_window2(nz, ny, nx, n_g)
+    return g
 
 
 def gradient_symbol(nn, n_g: int):
@@ -163,11 +191,12 @@ def gradient_factors(n_g: int):
     return [-1j * gradient_symbol(nn, n_g) for nn in (nx, ny, nz)]  # x, y, z
 
 
-def force_mesh(rho: np.ndarray, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI) -> np.ndarray:
+def force_mesh(rho: np.ndarray, soft_cells: float = 1.0, G: float = 1.0 / FOUR_PI,
+               split=None) -> np.ndarray:
     """Acceleration mesh a[3][z][y][x] from density: eqs. (2)-(3) with F = m a and the
-    discrete gradient symbol."""
+    discrete gradient symbol (split: one part of the two-level kernel, see green)."""
     n_g = rho.shape[0]
-    phi_k = green(n_g, soft_cells, G) * np.fft.rfftn(rho)
+    phi_k = green(n_g, soft_cells, G, split) * np.fft.rfftn(rho)
     a = np.empty((3, n_g, n_g, n_g), dtype=np.float64)
     for ax, fac in enumerate(gradient_factors(n_g)):
         a[ax] = np.fft.irfftn(fac * phi_k, s=(n_g, n_g, n_g), axes=(0, 1, 2))
@@ -219,8 +248,8 @@ def gather_grad(mesh: np.ndarray, x: np.ndarray) -> np.ndarray:
 
 
 def accelerations(species, n_g: int, soft_cells: float = 1.0,
-                  G: float = 1.0 / FOUR_PI):
+                  G: float = 1.0 / FOUR_PI, split=None):
     """Full PM force: list of (x, mass) -> (list of a_i [n][3], mesh a[3][...])."""
     rho = deposit_species(species, n_g)
-    a = force_mesh(rho, soft_cells, G)
+    a = force_mesh(rho, soft_cells, G, split)
     return [interpolate(a, x) for x, _ in species], a, rho

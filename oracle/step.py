@@ -78,12 +78,15 @@ def kick_codes(u: np.ndarray, v_dec: np.ndarray, a_i: np.ndarray, v_max_new, S: 
 
 
 def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
-                    soft_cells: float = 1.0, G: float = 1.0 / mesh.FOUR_PI, extra=None):
+                    soft_cells: float = 1.0, G: float = 1.0 / mesh.FOUR_PI, extra=None,
+                    extra_max=None, split=None):
     """states: list of codec state dicts (same n_c, brick) -> new states + diagnostics.
 
     extra (optional): per species an additional acceleration [n][3] in old stream order
-    (the cell-local PP force of eq. (4)); it is added to the interpolated mesh force, and
-    the velocity bound takes A_max + max |extra_a| over all species and axes.
+    (the cell-local PP force of eq. (4), the long-range force of the two-level PM); it is
+    added to the interpolated mesh force, and the velocity bound takes A_max + extra_max,
+    by default max |extra_a| over all species and axes. split: the mesh kernel's part of
+    the two-level split (oracle.mesh.split_factor).
 
     Diagnostics per species: 'perm' (new stream index -> old stream index), the
     pre-floor values 'pos_pre' = d + 1/2 and 'vel_pre' = v' C + 32768 in old stream
@@ -95,11 +98,14 @@ def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
     S = 256 * n_c
     decoded = [codec.decode(st) for st in states]
     xs = [(x.astype(np.float64), m) for (x, _), m in zip(decoded, masses)]
-    acc, a_mesh, rho = mesh.accelerations(xs, n_g, soft_cells, G)
+    acc, a_mesh, rho = mesh.accelerations(xs, n_g, soft_cells, G, split)
     a_max = float(np.max(np.abs(a_mesh))) if a_mesh.size else 0.0
     if extra is not None:
         acc = [ai + np.asarray(e, dtype=np.float64) for ai, e in zip(acc, extra)]
-        a_max += max((float(np.max(np.abs(e))) for e in extra if np.size(e)), default=0.0)
+        if extra_max is None:
+            extra_max = max((float(np.max(np.abs(e))) for e in extra if np.size(e)),
+                            default=0.0)
+        a_max += extra_max
     new_states, diags = [], []
     for st, (x, v), ai in zip(states, decoded, acc):
         u, _ = codec.decode_codes(st)
