@@ -74,7 +74,12 @@ enum { PM_PREC_F32 = 0 };
  *              Delta = L / n_mesh and densities are mass per unit volume. A power of two
  *              keeps every position conversion exact (L = 1 is the unit box).
  *   G          gravitational constant (1/(4 pi) makes 4 pi G = 1).
- *   soft_cells Plummer softening length in mesh cells (>= 0). */
+ *   soft_cells Plummer softening length in mesh cells (>= 0).
+ *   kernel     which part of the two-level force split the context's force computes
+ *              (PM_KERNEL_*; 0 is the one-level kernel).
+ *   reserved   0.
+ *   r_split    split length r_s of the two-level force in units of length (> 0 for
+ *              PM_KERNEL_LONG and PM_KERNEL_SHORT, ignored otherwise). */
 typedef struct pm_config {
   int64_t n_mesh;
   int64_t n_cell;
@@ -83,7 +88,26 @@ typedef struct pm_config {
   double box;
   double G;
   double soft_cells;
+  int32_t kernel;
+  int32_t reserved;
+  double r_split;
 } pm_config;
+
+/* Two-level force split (Sec. 2.1: a long-range force on a coarse mesh spanning the box,
+ * a short-range force on a mesh 4 times finer; the paper gives no split kernel). With
+ * G(k) the softened kernel of pm_force and k the wave vector (2 pi n / L):
+ *   PM_KERNEL_FULL   G(k), one level;
+ *   PM_KERNEL_LONG   G(k) exp(-k^2 r_s^2) / prod_a sinc(n_a / n_mesh)^4, sinc(t) =
+ *                    sin(pi t) / (pi t): the long-range part for the coarse mesh, with
+ *                    that mesh's CIC deposit and interpolation windows divided out;
+ *   PM_KERNEL_SHORT  G(k) (1 - exp(-k^2 r_s^2)): the short-range part for the fine mesh.
+ * A two-level pair is a fine context (PM_KERNEL_SHORT) and a coarse one
+ * (PM_KERNEL_LONG) with the same r_split, softening length (soft_cells times the
+ * mesh spacing), n_cell, brick, box and G; pm_step_p3m steps them together. The
+ * paper's configuration is n_mesh(coarse) = n_cell = (n_p/2), n_mesh(fine) = 4 n_cell,
+ * and r_s = 1.25 coarse cells (the short-range force of a point mass is then below 1%
+ * of Newton's beyond 24 fine cells, the tile buffer the paper uses). */
+enum { PM_KERNEL_FULL = 0, PM_KERNEL_LONG = 1, PM_KERNEL_SHORT = 2 };
 
 /* Device-resident header of one compressed species (32 bytes).
  *   v_max  half-range of the velocity histogram (the paper keeps it in the file
@@ -138,7 +162,8 @@ const char* pm_status_str(pm_status s);
  *                     symbol, Nyquist planes), exact;
  *   step_mesh_bytes   the context's force meshes (3 n_mesh^3 floats, allocated by the
  *                     first pm_step, pm_step_vjp or pm_loss_density_vjp), exact;
- *   step_scratch_bytes  upper bound of the scratch that pm_encode and pm_step grow for
+ *   step_scratch_bytes  upper bound of the scratch that pm_encode and pm_step (also
+ *                     pm_step_pp and, for the fine context, pm_step_p3m) grow for
  *                     n_max particles in total over n_sp species (1 <= n_sp <= 4);
  *   vjp_scratch_bytes   upper bound of what pm_step_vjp adds to that;
  *   float_deposit_scratch_bytes  what a PM_FLOAT deposit adds (8 n_mesh^3);
@@ -243,6 +268,27 @@ pm_status pm_pp_accel(pm_ctx ctx, const pm_species* sp, int n_sp, double r_soft,
 pm_status pm_step_pp(pm_ctx ctx, const pm_species* in, pm_species* out, int n_sp, double dt,
                      double r_soft, int64_t* const* perm);
 
+/* CIC interpolation of the context's force meshes to the particles (the inverse force
+ * interpolation of Sec. 2.3, Fig. 2) without the kick: acc is device float
+ * [3][n_mesh^3] (as pm_force writes it); out is a host array of n_sp device float [n][3]
+ * results in stream order. accumulate = 0 writes out, 1 adds to it. Compressed species
+ * only (mesh positions (u + 1/2) n_mesh / (256 n_cell) per axis, exact in float32).
+ * Float32 sums over the 8 nodes in a fixed order. */
+pm_status pm_interp_accel(pm_ctx ctx, const pm_species* sp, int n_sp, const float* acc,
+                          float* const* out, int accumulate);
+
+/* One step of the two-level force (Sec. 2.1): the long-range force on the coarse
+ * context's mesh (deposit, pm_force with PM_KERNEL_LONG, interpolation), the short-range
+ * force on the fine context's mesh (PM_KERNEL_SHORT), and for r_soft > 0 the PP force of
+ * eq. (4) inside the fine mesh's cells (pm_pp_accel); then the kick-drift-re-encode of
+ * pm_step with v' = v + dt (a_short + a_long + a_pp), x' = x + dt v'. The velocity bound
+ * of the re-encode uses max |a_short| + max |a_long| (meshes) + max |a_pp|. Compressed
+ * species only; fine and coarse must be a two-level pair (see PM_KERNEL_LONG) created on
+ * the same stream; PM_ERR_ARG otherwise. perm as in pm_step_pp. Scratch (the long-range
+ * and PP accelerations, 12 bytes per particle each) is the fine context's. */
+pm_status pm_step_p3m(pm_ctx fine, pm_ctx coarse, const pm_species* in, pm_species* out,
+                      int n_sp, double dt, double r_soft, int64_t* const* perm);
+
 /* Adjoint of pm_step at state `in` (straight-through for the quantisation of
  * compressed states). lam_x1, lam_v1: per species device float [n][3] cotangents of
  * the step's outputs, in the output's particle order; lam_x0, lam_v0: results, in
@@ -320,12 +366,16 @@ pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species
  * milliseconds and the number of timed launches:
  *   0 cell offsets   1 deposit          2 FFT x r2c     3 FFT y forward
  *   4 FFT z sweeps   5 FFT y inverse    6 FFT x c2r     7 interpolate-kick-drift
- *   8 re-sort        9 encode/decode   10 adjoint scatter/gather   11 PP force */
+ *   8 re-sort        9 encode/decode   10 adjoint scatter/gather   11 PP force
+ *  12 force interpolation without the kick (pm_interp_accel, the long range of
+ *     pm_step_p3m) */
 pm_status pm_profile(pm_ctx ctx, int enable);
 pm_status pm_profile_read(pm_ctx ctx, double* ms, int64_t* launches, int cap);
 
 /* Diagnostics: copy the float32 kernel table L G(|n|^2)/n_mesh^3 (device float
- * [3 (n_mesh/2)^2 + 1], indexed by the integer |n|^2). */
+ * [3 (n_mesh/2)^2 + 1], indexed by the integer |n|^2), with the split factor of the
+ * context's kernel part (the long part's window division, which is not a function of
+ * |n|^2, is applied in the force only). */
 pm_status pm_kernel_table(pm_ctx ctx, float* out, int64_t cap);
 
 #ifdef __cplusplus

@@ -40,6 +40,9 @@ class PmConfig(ctypes.Structure):
         ("box", ctypes.c_double),
         ("G", ctypes.c_double),
         ("soft_cells", ctypes.c_double),
+        ("kernel", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("r_split", ctypes.c_double),
     ]
 
 
@@ -90,6 +93,8 @@ EXPORTS = [
     ("pm_loss_density_vjp", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_pp_accel", [P, PS, ctypes.c_int, ctypes.c_double, P, P]),
     ("pm_step_pp", [P, PS, PS, ctypes.c_int, ctypes.c_double, ctypes.c_double, P]),
+    ("pm_interp_accel", [P, PS, ctypes.c_int, P, P, ctypes.c_int]),
+    ("pm_step_p3m", [P, P, PS, PS, ctypes.c_int, ctypes.c_double, ctypes.c_double, P]),
     ("pm_reduce", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_reduce_noalloc", [P, PS, ctypes.c_int, P, P, P]),
     ("pm_pack", [P, PS, ctypes.c_int32, P, I64, P]),

@@ -120,6 +120,11 @@ pm_status pm_create(const pm_config* cfg, void* stream, pm_ctx* out) {
   if (!std::isfinite(cfg->G)) return PM_ERR_ARG;
   if (!(cfg->box > 0.0) || !std::isfinite(cfg->box)) return PM_ERR_ARG;
   if (cfg->prec != PM_PREC_F32) return PM_ERR_ARG;
+  if (cfg->kernel != PM_KERNEL_FULL && cfg->kernel != PM_KERNEL_LONG &&
+      cfg->kernel != PM_KERNEL_SHORT)
+    return PM_ERR_ARG;
+  if (cfg->kernel != PM_KERNEL_FULL && (!(cfg->r_split > 0.0) || !std::isfinite(cfg->r_split)))
+    return PM_ERR_ARG;
   pm_context* c = new (std::nothrow) pm_context();
   if (!c) return PM_ERR_NOMEM;
   c->cfg = *cfg;
@@ -193,6 +198,7 @@ pm_status pm_query_sizes(const pm_config* cfg, int64_t n_max, int n_sp, pm_sizes
   st += grown(rs_blocks * 256 * 4) + grown((rs_blocks * 256 + 1) * 8);  // radix histograms
   st += grown((std::max<int64_t>(std::max<int64_t>(nc3, N), rs_blocks * 256) / 4096 + 1) * 8);
   st += grown(4096) + grown(512 * 25 * 8) + grown(32);  // folds, reductions, mover counts
+  st += grown(N * 12 + n_sp * 256);                     // extra accelerations (PP, long range)
   out->step_scratch_bytes = st;
   // pm_step_vjp adds the three adjoint meshes, the decoded positions and the recomputed
   // re-sort (permutations and a copy of the stream)
@@ -418,6 +424,68 @@ pm_status pm_step_pp(pm_ctx c, const pm_species* in, pm_species* out, int n_sp, 
   if ((s = run_add_max(c, c->amax, c->amax + 1, c->amax + 2)) != PM_OK) return s;
   return run_kick_compressed_all(c, in, out, n_sp, offs, mesh, c->amax + 2, dt, dt, perm,
                                  app);
+}
+
+pm_status pm_interp_accel(pm_ctx c, const pm_species* sp, int n_sp, const float* acc,
+                          float* const* out, int accumulate) {
+  if (!c || !sp || !acc || !out || n_sp <= 0 || n_sp > 4) return PM_ERR_ARG;
+  for (int i = 0; i < n_sp; ++i) {
+    if (check_species(c, &sp[i], true) != PM_OK || sp[i].layout != PM_COMPRESSED)
+      return PM_ERR_ARG;
+    if (sp[i].n > 0 && !out[i]) return PM_ERR_ARG;
+  }
+  int64_t* offs[4] = {nullptr, nullptr, nullptr, nullptr};
+  pm_status s;
+  for (int i = 0; i < n_sp; ++i) {
+    offs[i] = (int64_t*)scratch(c, SC_SPOFF0 + i, (size_t)(c->g.ncell3 + 1) * 8);
+    if (!offs[i]) return PM_ERR_NOMEM;
+    if ((s = run_cell_offsets(c, &sp[i], offs[i])) != PM_OK) return s;
+  }
+  return run_interp_accel(c, sp, n_sp, offs, acc, out, accumulate);
+}
+
+pm_status pm_step_p3m(pm_ctx f, pm_ctx cc, const pm_species* in, pm_species* out, int n_sp,
+                      double dt, double r_soft, int64_t* const* perm) {
+  if (!f || !cc || f == cc) return PM_ERR_ARG;
+  if (!split_pair_ok(f, cc)) return PM_ERR_ARG;
+  pm_status s = check_kick_args(f, in, out, n_sp);
+  if (s != PM_OK) return s;
+  if (!std::isfinite(dt) || !(r_soft >= 0.0) || !std::isfinite(r_soft)) return PM_ERR_ARG;
+  if (in[0].layout != PM_COMPRESSED) return PM_ERR_ARG;
+  if ((s = ensure_step_meshes(f)) != PM_OK) return s;
+  if ((s = ensure_step_meshes(cc)) != PM_OK) return s;
+  // cell offsets depend on the counts, n_cell and brick only: the pair shares them
+  int64_t* offs[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t bytes = 0;
+  for (int i = 0; i < n_sp; ++i) {
+    offs[i] = (int64_t*)scratch(f, SC_SPOFF0 + i, (size_t)(f->g.ncell3 + 1) * 8);
+    if (!offs[i]) return PM_ERR_NOMEM;
+    if ((s = run_cell_offsets(f, &in[i], offs[i])) != PM_OK) return s;
+    bytes += ((size_t)in[i].n * 12 + 255) & ~(size_t)255;
+  }
+  char* pool = (char*)scratch(f, SC_LRACC, bytes > 0 ? bytes : 256);
+  if (!pool) return PM_ERR_NOMEM;
+  float* app[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t at = 0;
+  for (int i = 0; i < n_sp; ++i) {
+    app[i] = (float*)(pool + at);
+    at += ((size_t)in[i].n * 12 + 255) & ~(size_t)255;
+  }
+  // long range: coarse deposit, force, interpolation into app
+  float* cm = cc->mesh;
+  if ((s = run_deposit_tile(cc, in, n_sp, offs, cm)) != PM_OK) return s;
+  if ((s = run_force(cc, cm, cm, cc->nyq, cc->amax)) != PM_OK) return s;
+  const bool pp = r_soft > 0.0;
+  if (pp && (s = run_pp_accel(f, in, n_sp, offs, r_soft, app, f->amax + 1)) != PM_OK) return s;
+  if ((s = run_interp_accel(cc, in, n_sp, offs, cm, app, pp ? 1 : 0)) != PM_OK) return s;
+  // short range on the fine mesh
+  float* fm = f->mesh;
+  if ((s = run_deposit_tile(f, in, n_sp, offs, fm)) != PM_OK) return s;
+  if ((s = run_force(f, fm, fm, f->nyq, f->amax)) != PM_OK) return s;
+  // velocity bound: max |a_short| + max |a_long| (+ max |a_pp|)
+  if ((s = run_add_max(f, f->amax, cc->amax, f->amax + 2)) != PM_OK) return s;
+  if (pp && (s = run_add_max(f, f->amax + 2, f->amax + 1, f->amax + 2)) != PM_OK) return s;
+  return run_kick_compressed_all(f, in, out, n_sp, offs, fm, f->amax + 2, dt, dt, perm, app);
 }
 
 pm_status pm_step_vjp(pm_ctx c, const pm_species* in, int n_sp, double dt,

@@ -119,7 +119,7 @@ struct pm_context {
 
 enum ProfStage {
   ST_OFFSETS = 0, ST_DEPOSIT, ST_FFT_R2C, ST_FFT_YF, ST_FFT_Z, ST_FFT_YI, ST_FFT_C2R,
-  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_PP, ST_N
+  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_PP, ST_INTERP, ST_N
 };
 // Record a begin/end event pair around a group of launches (no-op unless profiling).
 void prof_begin(pm_context* c, int stage);
@@ -164,6 +164,7 @@ enum ScratchId {
   SC_NMOV,         // int64 [4]: mover count of each species (device-side)
   SC_PPMAX,        // per-workgroup max |a| of the PP force
   SC_PPACC,        // float [N][3] PP accelerations of pm_step_pp
+  SC_LRACC,        // float [N][3] long-range accelerations of pm_step_p3m
   SC_N
 };
 
@@ -248,6 +249,13 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
 pm_status run_pp_accel(pm_context* c, const pm_species* sp, int n_sp, int64_t* const* offs,
                        double r_soft, float* const* app, float* pmax);
 pm_status run_add_max(pm_context* c, const float* a, const float* b, float* out);
+// two-level force (pm_split.hip): CIC interpolation of force meshes to compressed
+// particles (out per species [n][3], stream order; accumulate adds), and the check that
+// two contexts form a fine/coarse pair of the split
+pm_status run_interp_accel(pm_context* c, const pm_species* sp, int n_sp,
+                           int64_t* const* offs, const float* acc, float* const* out,
+                           int accumulate);
+bool split_pair_ok(const pm_context* fine, const pm_context* coarse);
 pm_status run_kick_compressed(pm_context* c, const pm_species* in, pm_species* out,
                               const float* acc, const float* amax, double ck, double cd,
                               uint32_t* perm_new_to_old);

@@ -741,8 +741,11 @@ __device__ double bessel_k1(double x) {
   return sum * h;
 }
 
+// Kernel of |n|^2 = q in the unit box (k = 2 pi sqrt(q)), times the split factor of the
+// two-level force (Sec. 2.1): exp(-k^2 rs^2) for the long-range part, 1 - exp(-k^2 rs^2)
+// for the short-range part, rs = r_split / L.
 __global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, double eps,
-                             double box) {
+                             double box, int kernel, double rs) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nent) return;
   double val = 0.0;
@@ -751,6 +754,8 @@ __global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, dou
     double g;
     if (eps > 0) g = -4.0 * 3.141592653589793238462643 * G * eps * bessel_k1(k * eps) / k;
     else g = -4.0 * 3.141592653589793238462643 * G / (k * k);
+    if (kernel == PM_KERNEL_LONG) g *= exp(-(k * rs) * (k * rs));
+    else if (kernel == PM_KERNEL_SHORT) g *= -expm1(-(k * rs) * (k * rs));
     // the 1/n^3 of the inverse transform, and the box: a density in mass per unit volume
     // of a box of side L has the force L a_1 of the same mesh values in the unit box
     val = g * box / ((double)n * (double)n * (double)n);
@@ -758,15 +763,39 @@ __global__ void k_build_ktab(float* ktab, int64_t nent, int64_t n, double G, dou
   ktab[q] = (float)val;
 }
 
+// sinc(t)^4 = (sin(pi t) / (pi t))^4, 1 at t = 0: one axis of the CIC deposit window
+// times the CIC interpolation window at wave number t n
+__device__ inline double sinc4(double t) {
+  if (t == 0.0) return 1.0;
+  const double a = 3.141592653589793238462643 * t;
+  const double s = sin(a) / a;
+  return (s * s) * (s * s);
+}
+
 // Octant copy of the kernel table: gtab[(kx (h+1) + ay) (h+1) + az] = ktab[kx^2 + ay^2 +
-// az^2] for kx, ay, az in [0, h], h = n/2 (the kernel depends on |k| only). A z line at
-// fixed (kx, ky) then reads its kernel values as one contiguous run.
-__global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h) {
+// az^2] for kx, ay, az in [0, h], h = n/2. A z line at fixed (kx, ky) then reads its
+// kernel values as one contiguous run. The long-range part of the two-level split is
+// also divided by the mesh's CIC windows (a function of the three components, even in
+// each), in float64 from the float64 kernel value.
+__global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h, int kernel,
+                             double G, double eps, double box, double rs) {
   const int64_t h1 = h + 1, tot = h1 * h1 * h1;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= tot) return;
   const int64_t az = q % h1, ay = (q / h1) % h1, kx = q / (h1 * h1);
-  gtab[q] = ktab[kx * kx + ay * ay + az * az];
+  const int64_t n2 = kx * kx + ay * ay + az * az;
+  if (kernel != PM_KERNEL_LONG || n2 == 0) {
+    gtab[q] = ktab[n2];
+    return;
+  }
+  const double n = (double)(2 * h);
+  const double k = 2.0 * 3.141592653589793238462643 * sqrt((double)n2);
+  double g;
+  if (eps > 0) g = -4.0 * 3.141592653589793238462643 * G * eps * bessel_k1(k * eps) / k;
+  else g = -4.0 * 3.141592653589793238462643 * G / (k * k);
+  g *= exp(-(k * rs) * (k * rs));
+  g /= sinc4((double)kx / n) * sinc4((double)ay / n) * sinc4((double)az / n);
+  gtab[q] = (float)(g * box / (n * n * n));
 }
 
 // ------------------------------------------------------------------ dispatch --
@@ -963,13 +992,15 @@ pm_status build_kernel_table(pm_context* c) {
   c->ktab_n = 3 * (n / 2) * (n / 2) + 1;
   PM_HIP_CHECK(hipMalloc(&c->ktab, (size_t)c->ktab_n * sizeof(float)));
   double eps = c->cfg.soft_cells / (double)n;
+  const int kernel = c->cfg.kernel;
+  const double rs = kernel == PM_KERNEL_FULL ? 0.0 : c->cfg.r_split / c->cfg.box;
   hipLaunchKernelGGL(k_build_ktab, dim3((unsigned)cdiv(c->ktab_n, 256)), dim3(256), 0,
-                     c->stream, c->ktab, c->ktab_n, n, c->cfg.G, eps, c->cfg.box);
+                     c->stream, c->ktab, c->ktab_n, n, c->cfg.G, eps, c->cfg.box, kernel, rs);
   PM_LAUNCH_CHECK();
   const int64_t h1 = n / 2 + 1, ng3 = h1 * h1 * h1;
   PM_HIP_CHECK(hipMalloc(&c->gtab, (size_t)ng3 * sizeof(float)));
   hipLaunchKernelGGL(k_build_gtab, dim3((unsigned)cdiv(ng3, 256)), dim3(256), 0, c->stream,
-                     c->ktab, c->gtab, n / 2);
+                     c->ktab, c->gtab, n / 2, kernel, c->cfg.G, eps, c->cfg.box, rs);
   PM_LAUNCH_CHECK();
   // twiddles exp(-2 pi i k / n), k < n, built in float64 on the host
   float2* h = (float2*)malloc(sizeof(float2) * n);

@@ -1,0 +1,124 @@
+// The two-level particle-mesh force of Sec. 2.1 on one device: the long-range force on
+// a coarse mesh spanning the box (a context with the long-range kernel part), the
+// short-range force on the fine mesh (a context with the short-range part), and the PP
+// force of eq. (4) inside the fine mesh's cells, summed in the kick of the fine context.
+//
+// The paper solves the short-range part on per-tile meshes with a buffer of 24 fine
+// cells so that each node works in its own memory. One device holds the whole box's fine
+// mesh, which is then a single periodic tile: no buffer, no per-tile transforms (a batch
+// of power-of-two tile meshes with such buffers would transform at least 8 times the
+// fine mesh's cells).
+//
+// k_interp_cells interpolates a context's force meshes to compressed particles (the
+// inverse force interpolation of Sec. 2.3, Fig. 2): one thread per compression cell,
+// walking the cell's particles in stream order. A particle's mesh coordinate per axis is
+// (2 u + 1) r / 512 mesh cells (u its position code, r mesh cells per compression cell),
+// an exact binary fraction, so the node index and the CIC weights (multiples of 1/512)
+// are exact; the 8-node sum is float32 in a fixed order.
+#include "pm_codec.h"
+
+namespace {
+
+constexpr int IT = 256;
+constexpr int IMAXSP = 4;
+
+struct ISpecies {
+  int64_t n;
+  const uint8_t* pos;
+  const int64_t* off;  // cell offsets [ncell3 + 1]
+  float* out;          // [n][3], stream order
+};
+
+struct IArgs {
+  ISpecies sp[IMAXSP];
+  int n_sp;
+  int accumulate;
+};
+
+__global__ __launch_bounds__(IT) void k_interp_cells(IArgs A, Geom g,
+                                                     const float* __restrict__ acc) {
+  const ISpecies& S = A.sp[blockIdx.y];
+  const int64_t key = (int64_t)blockIdx.x * IT + threadIdx.x;
+  if (key >= g.ncell3 || S.n == 0) return;
+  const int64_t j0 = S.off[key], j1 = S.off[key + 1];
+  if (j0 >= j1) return;
+  uint32_t cx, cy, cz;
+  key_cell(g, (uint32_t)key, cx, cy, cz);
+  const int64_t n = g.ng, n3 = n * n * n;
+  const int nm = (int)n - 1;  // n is a power of two
+  const float* ax = acc;
+  const float* ay = acc + n3;
+  const float* az = acc + 2 * n3;
+  for (int64_t j = j0; j < j1; ++j) {
+    // mesh coordinate (2u + 1) r / 512 per axis: node = t >> 9, weight of node + 1 =
+    // (t & 511) / 512
+    const int tx = (2 * (int)((cx << 8) | S.pos[3 * j]) + 1) * g.r;
+    const int ty = (2 * (int)((cy << 8) | S.pos[3 * j + 1]) + 1) * g.r;
+    const int tz = (2 * (int)((cz << 8) | S.pos[3 * j + 2]) + 1) * g.r;
+    const int ix = (tx >> 9) & nm, iy = (ty >> 9) & nm, iz = (tz >> 9) & nm;
+    const float fx = (float)(tx & 511) * (1.0f / 512.0f);
+    const float fy = (float)(ty & 511) * (1.0f / 512.0f);
+    const float fz = (float)(tz & 511) * (1.0f / 512.0f);
+    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+    const int xs[2] = {ix, (ix + 1) & nm}, ys[2] = {iy, (iy + 1) & nm};
+    const int zs[2] = {iz, (iz + 1) & nm};
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int64_t q = ((int64_t)zs[dz] * n + ys[dy]) * n + xs[dx];
+          const float w = wz[dz] * wy[dy] * wx[dx];
+          sx += w * ax[q];
+          sy += w * ay[q];
+          sz += w * az[q];
+        }
+    float* o = S.out + 3 * j;
+    if (A.accumulate) {
+      sx += o[0];
+      sy += o[1];
+      sz += o[2];
+    }
+    o[0] = sx;
+    o[1] = sy;
+    o[2] = sz;
+  }
+}
+
+}  // namespace
+
+pm_status run_interp_accel(pm_context* c, const pm_species* sp, int n_sp,
+                           int64_t* const* offs, const float* acc, float* const* out,
+                           int accumulate) {
+  if (n_sp <= 0 || n_sp > IMAXSP) return PM_ERR_ARG;
+  const Geom& g = c->g;
+  IArgs A{};
+  A.n_sp = n_sp;
+  A.accumulate = accumulate ? 1 : 0;
+  for (int s = 0; s < n_sp; ++s) {
+    A.sp[s].n = sp[s].n;
+    A.sp[s].pos = sp[s].pos;
+    A.sp[s].off = offs[s];
+    A.sp[s].out = out[s];
+  }
+  ProfScope ps(c, ST_INTERP);
+  hipLaunchKernelGGL(k_interp_cells, dim3((unsigned)cdiv(g.ncell3, IT), (unsigned)n_sp),
+                     dim3(IT), 0, c->stream, A, g, acc);
+  PM_LAUNCH_CHECK();
+  return PM_OK;
+}
+
+// A fine (short-range) and a coarse (long-range) context form a two-level pair when they
+// split the same kernel at the same length and share the particle format and units.
+bool split_pair_ok(const pm_context* f, const pm_context* c) {
+  const pm_config &a = f->cfg, &b = c->cfg;
+  if (a.kernel != PM_KERNEL_SHORT || b.kernel != PM_KERNEL_LONG) return false;
+  if (f->stream != c->stream || f->device != c->device) return false;
+  if (a.n_cell != b.n_cell || a.brick != b.brick || a.box != b.box || a.G != b.G) return false;
+  if (a.r_split != b.r_split || b.n_mesh > a.n_mesh) return false;
+  // the same softening length on both meshes
+  const double ea = a.soft_cells / (double)a.n_mesh, eb = b.soft_cells / (double)b.n_mesh;
+  return fabs(ea - eb) <= 1e-12 * fmax(ea, eb);
+}

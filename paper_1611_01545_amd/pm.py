@@ -92,9 +92,11 @@ def _species_array(species):
 class PMContext:
     """A libpm context: one mesh size, one compression-cell size, one HIP stream."""
 
+    KERNEL_FULL, KERNEL_LONG, KERNEL_SHORT = 0, 1, 2
+
     def __init__(self, n_mesh: int, n_cell: int, brick: int | None = None,
                  G: float = G_UNIT, soft_cells: float = 1.0, device: str = "cuda",
-                 box: float = 1.0):
+                 box: float = 1.0, kernel: int = 0, r_split: float = 0.0):
         self.lib = _lib.lib()
         dev = torch.device(device)
         if dev.type != "cuda" or not torch.cuda.is_available():
@@ -107,7 +109,9 @@ class PMContext:
             brick = self.default_brick(n_mesh, n_cell)
         self.n_mesh, self.n_cell, self.brick = n_mesh, n_cell, brick
         self.G, self.soft_cells, self.box = G, soft_cells, float(box)
-        cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G, soft_cells)
+        self.kernel, self.r_split = int(kernel), float(r_split)
+        cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G, soft_cells, int(kernel), 0,
+                       float(r_split))
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         check(self.lib.pm_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -135,7 +139,7 @@ class PMContext:
                     box: float = 1.0) -> dict:
         """pm_query_sizes: device bytes of a configuration (no GPU needed)."""
         lib = _lib.lib()
-        cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G_UNIT, 1.0)
+        cfg = PmConfig(n_mesh, n_cell, brick, 0, float(box), G_UNIT, 1.0, 0, 0, 0.0)
         out = _lib.PmSizes()
         check(lib.pm_query_sizes(ctypes.byref(cfg), int(n_max), int(n_sp), ctypes.byref(out)),
               "pm_query_sizes")
@@ -262,6 +266,50 @@ class PMContext:
               "pm_step_pp")
         return (out, perms) if want_perm else out
 
+    @classmethod
+    def two_level(cls, n_mesh: int, n_cell: int, brick: int | None = None,
+                  ratio: int = 4, r_split: float | None = None, G: float = G_UNIT,
+                  soft_cells: float = 1.0, device: str = "cuda", box: float = 1.0):
+        """A fine (short-range) and a coarse (long-range) context of the two-level force:
+        coarse mesh n_mesh / ratio, the same softening length, r_split = 1.25 coarse cells
+        unless given."""
+        nc_mesh = n_mesh // ratio
+        if r_split is None:
+            r_split = 1.25 * box / nc_mesh
+        if brick is None:
+            brick = cls.default_brick(n_mesh, n_cell)
+        fine = cls(n_mesh, n_cell, brick, G, soft_cells, device, box, cls.KERNEL_SHORT,
+                   r_split)
+        coarse = cls(nc_mesh, n_cell, brick, G, soft_cells * nc_mesh / n_mesh, device, box,
+                     cls.KERNEL_LONG, r_split)
+        return fine, coarse
+
+    def interp_accel(self, species, acc: torch.Tensor, out=None, accumulate: bool = False):
+        """pm_interp_accel: CIC interpolation of force meshes acc [3][n^3] to compressed
+        particles, [n][3] per species (stream order)."""
+        ns = len(species)
+        if out is None:
+            out = [torch.empty((s.n, 3), dtype=torch.float32, device=self.device)
+                   for s in species]
+        arr = _species_array(species)
+        check(self.lib.pm_interp_accel(self.h, arr, ns, _ptr(acc.contiguous()),
+                                       (ctypes.c_void_p * ns)(*[_ptr(t) for t in out]),
+                                       1 if accumulate else 0), "pm_interp_accel")
+        return out
+
+    def step_p3m(self, coarse: "PMContext", species, dt: float, r_soft: float = 0.0,
+                 out=None, want_perm: bool = False):
+        """pm_step_p3m with this context as the fine (short-range) one."""
+        if out is None:
+            out = [self.empty_like(s) for s in species]
+        a, b = _species_array(species), _species_array(out)
+        perms = [torch.empty(s.n, dtype=torch.int64, device=self.device) for s in species] \
+            if want_perm else None
+        pp = (ctypes.c_void_p * len(species))(*[_ptr(p) for p in perms]) if perms else None
+        check(self.lib.pm_step_p3m(self.h, coarse.h, a, b, len(species), float(dt),
+                                   float(r_soft), pp), "pm_step_p3m")
+        return (out, perms) if want_perm else out
+
     def step_vjp(self, species, dt: float, lam_x1, lam_v1):
         ns = len(species)
         lam_x0 = [torch.empty_like(t) for t in lam_x1]
@@ -336,7 +384,7 @@ class PMContext:
 
     STAGES = ["cell_offsets", "deposit", "fft_x_r2c", "fft_y_fwd", "fft_z",
               "fft_y_inv", "fft_x_c2r", "interp_kick_drift", "resort", "codec", "adjoint",
-              "pp"]
+              "pp", "interp"]
 
     def profile(self, enable: bool = True):
         check(self.lib.pm_profile(self.h, 1 if enable else 0), "pm_profile")

@@ -62,13 +62,15 @@ def _codes_old_order(host_state, perm):
     return uo, jo
 
 
-def check_codes(c, out, perms, new, diag, n_cell, dt):
+def check_codes(c, out, perms, new, diag, n_cell, dt, a_rms=None):
     """GPU step outputs against oracle.step.step_compressed: position and velocity codes
     equal in old stream order except in the tie zone, counts and escapes consistent, the
-    stream the stable cell sort of the new codes. Returns the number of tie-zone codes."""
+    stream the stable cell sort of the new codes. Returns the number of tie-zone codes.
+    a_rms: the force scale of the tolerance (default: RMS of the oracle's force mesh)."""
     from oracle import codec
     S = 256 * n_cell
-    a_rms = np.sqrt(np.mean(diag["a_mesh"] ** 2))
+    if a_rms is None:
+        a_rms = np.sqrt(np.mean(diag["a_mesh"] ** 2))
     ties = 0
     for o, ns, d, perm in zip(out, new, diag["species"], perms):
         h = c.to_host(o)

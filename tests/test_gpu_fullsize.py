@@ -69,14 +69,15 @@ def _node_cells(node, n_g, n_c, brick):
 
 
 def test_fullsize_density_sampled(full):
-    wl, c = full.wl, full.c
-    n = wl.n_mesh
+    _density_sampled(full.wl, full.c, full.st, full.rho, full.wl.n_mesh)
+
+
+def _density_sampled(wl, c, st, rho, n):
     rng = np.random.default_rng(11)
     nodes = rng.integers(0, n, size=(48, 3))
     nodes = np.concatenate([nodes, [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 3]]])
-    hosts = [c.to_host(s) for s in full.st]
+    hosts = [c.to_host(s) for s in st]
     offs = [codec.cell_offsets(h) for h in hosts]
-    rho = full.rho
     got = np.array([float(rho[z, y, x]) for x, y, z in nodes])
     want = np.zeros(len(nodes))
     for k, node in enumerate(nodes):
@@ -149,21 +150,27 @@ def test_fullsize_mode_sum_force(full):
 
 
 def test_fullsize_kick_sampled(full):
-    wl, c = full.wl, full.c
-    n, n_c = wl.n_mesh, wl.n_cell
-    S = 256 * n_c
-    dt = wl.dt
     acc_h = full.acc.cpu().numpy()
     a_max = float(np.max(np.abs(acc_h)))
     assert a_max == float(full.amax.item())
-    a_scale = float(np.sqrt(np.mean(acc_h[:, ::8, ::8, ::8].astype(np.float64) ** 2)))
+    _kick_sampled(full.wl, full.c, full.st, full.out, full.perms, [acc_h], a_max, "kick")
+
+
+def _kick_sampled(wl, c, sts, outs, perms, meshes, a_max, tag):
+    """Codes of every particle of 4000 sampled cells per species after the kick from the
+    sum of the interpolated host force meshes, against oracle.step.kick_codes."""
+    n_c = wl.n_cell
+    S = 256 * n_c
+    dt = wl.dt
+    a_scale = float(np.sqrt(sum(np.mean(m[:, ::8, ::8, ::8].astype(np.float64) ** 2)
+                                for m in meshes)))
     rng = np.random.default_rng(5)
-    for st, o, perm in zip(full.st, full.out, full.perms):
+    for st, o, perm in zip(sts, outs, perms):
         h = c.to_host(st)
         ho = c.to_host(o)
         keys = rng.choice(n_c ** 3, size=4000, replace=False)
         x, v, idx = codec.decode_cells(h, keys)
-        ai = mesh.interpolate(acc_h, x.astype(np.float64))
+        ai = sum(mesh.interpolate(m, x.astype(np.float64)) for m in meshes)
         jv = h["vel"]
         ext = codec.decode_velocity(np.array([jv.min(), jv.max()]), np.float32(h["v_max"]))
         V = float(np.max(np.abs(ext.astype(np.float64))))
@@ -195,8 +202,69 @@ def test_fullsize_kick_sampled(full):
         assert np.all(np.abs(dj[badv]) <= 1)
         assert np.all(frac_dist(vel_pre[badv]) <= tau_v[badv])
         assert badv.mean() < 1e-3
-        print(f"[fullsize] kick sample {idx.size}: {int(bad.sum())} position and "
+        print(f"[fullsize] {tag} sample {idx.size}: {int(bad.sum())} position and "
               f"{int(badv.sum())} velocity codes in the tie zone", flush=True)
+
+
+# ------------------------------------------------------------- two-level force --
+
+@pytest.fixture(scope="module")
+def two_level(full):
+    """The two-level pair of the tile (fine 1024^3 short range, coarse 256^3 long range,
+    one coarse mesh cell per compression cell) and its step."""
+    from paper_1611_01545_amd import PMContext
+    wl, c = full.wl, full.c
+    fine, coarse = PMContext.two_level(wl.n_mesh, wl.n_cell, brick=c.brick)
+    rho_c = coarse.deposit(full.st)
+    acc_c, amax_c = coarse.force(rho_c.clone())
+    a_long = coarse.interp_accel(full.st, acc_c)
+    acc_f, amax_f = fine.force(fine.deposit(full.st))
+    out, perms = fine.step_p3m(coarse, full.st, wl.dt, want_perm=True)
+    fine.sync()
+    print("[fullsize] two-level step done", flush=True)
+    yield types.SimpleNamespace(fine=fine, coarse=coarse, rho_c=rho_c, acc_c=acc_c,
+                                amax_c=amax_c, a_long=a_long, acc_f=acc_f, amax_f=amax_f,
+                                out=out, perms=perms)
+    fine.close()
+    coarse.close()
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_long_range_density_sampled(full, two_level):
+    # the coarse mesh deposits with 16^3-cell tiles (one mesh cell per compression cell)
+    _density_sampled(full.wl, full.c, full.st, two_level.rho_c, two_level.coarse.n_mesh)
+
+
+def test_fullsize_long_range_force(two_level):
+    co = two_level.coarse
+    rho = two_level.rho_c.cpu().numpy().astype(np.float64)
+    want = mesh.force_mesh(rho, co.soft_cells, co.G, (co.r_split, "long"))
+    got = two_level.acc_c.cpu().numpy()
+    for a in range(3):
+        e = np.sqrt(np.mean((got[a] - want[a]) ** 2) / np.mean(want[a] ** 2))
+        assert e <= 1e-4, (a, e)
+    assert abs(float(two_level.amax_c.item()) - np.max(np.abs(want))) <= \
+        1e-4 * np.max(np.abs(want))
+
+
+def test_fullsize_long_range_interp_sampled(full, two_level):
+    acc_h = two_level.acc_c.cpu().numpy().astype(np.float64)
+    scale = np.max(np.abs(acc_h))
+    rng = np.random.default_rng(9)
+    for st, a in zip(full.st, two_level.a_long):
+        h = full.c.to_host(st)
+        keys = rng.choice(full.wl.n_cell ** 3, size=2000, replace=False)
+        x, _, idx = codec.decode_cells(h, keys)
+        want = mesh.interpolate(acc_h, x.astype(np.float64))
+        got = a[torch.from_numpy(idx).to(a.device)].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - want)) <= 2e-6 * scale
+
+
+def test_fullsize_p3m_kick_sampled(full, two_level):
+    meshes = [two_level.acc_f.cpu().numpy(), two_level.acc_c.cpu().numpy()]
+    a_max = float(two_level.amax_f.item()) + float(two_level.amax_c.item())
+    _kick_sampled(full.wl, two_level.fine, full.st, two_level.out, two_level.perms, meshes,
+                  a_max, "two-level kick")
 
 
 def test_force_2048():
