@@ -15,8 +15,10 @@ drift (algorithmic bytes per launch over the HIP-event launch duration measured 
 stream the kernels run on), the per-stage breakdown, the peak HBM footprint, the
 fraction of particles whose position code does not change in a step, the comparison
 of three compressed float32 steps with an all-float64 uncompressed run on the
-[0, 128 Delta)^3 sub-box, the 1024^3 tile's step and step-adjoint rates, and the
-oracle's own throughput on a bounded sample (CPU baseline).
+[0, 128 Delta)^3 sub-box, the step with the two-level force of Sec. 2.1 (coarse
+long-range mesh n/4, fine short-range mesh n, with and without the PP force), the
+1024^3 tile's step, PP, two-level and step-adjoint rates, and the oracle's own
+throughput on a bounded sample (CPU baseline).
 """
 
 from __future__ import annotations
@@ -467,6 +469,46 @@ def compare_figures(gpu, ref, rho_oracle, wl):
     return out
 
 
+def two_level_rates(PMContext, wl, cur, brick, torch, log, steps, warmup, ms_one):
+    """The two-level force of Sec. 2.1 (pm_step_p3m): coarse long-range mesh n/4, r_s =
+    1.25 coarse cells, fine short-range mesh n, on the compressed states cur; timed
+    without and with the PP force (r_soft = L / (20 n_p)), stage times of both meshes."""
+    fine, coarse = PMContext.two_level(wl.n_mesh, wl.n_cell, brick=brick)
+    nxt = [fine.empty_like(s) for s in cur]
+    r_soft = 1.0 / (20 * 2 * wl.n_cell)
+    res = {"coarse_mesh": coarse.n_mesh, "r_split_coarse_cells": 1.25,
+           "r_split": fine.r_split}
+    for tag, rs in (("p3m_step", 0.0), ("p3m_step_with_pp", r_soft)):
+        for _ in range(max(1, warmup)):
+            fine.step_p3m(coarse, cur, wl.dt, r_soft=rs, out=nxt)
+        fine.sync()
+        fine.profile(True)
+        coarse.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fine.step_p3m(coarse, cur, wl.dt, r_soft=rs, out=nxt)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        pf, pc = fine.profile_read(), coarse.profile_read()
+        fine.profile(False)
+        coarse.profile(False)
+        res[tag] = {
+            "ms_per_step": ms, "value": wl.n_particles / (ms * 1e-3),
+            "over_one_level_step": ms / ms_one,
+            "fine_stage_ms": {k: v[0] / steps for k, v in pf.items() if v[1]},
+            "coarse_stage_ms": {k: v[0] / steps for k, v in pc.items() if v[1]}}
+        if rs > 0:
+            res[tag]["r_soft"] = rs
+        log(f"[bench] two-level {tag}: {ms:.3f} ms/step ({ms / ms_one:.2f}x the one-level "
+            "step)")
+    fine.close()
+    coarse.close()
+    del nxt
+    torch.cuda.empty_cache()
+    return res
+
+
 def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True):
     """The 1024^3 tile (256^3 + 512^3): step rate, and the step adjoint at that size."""
     wl = make_workload("tile_1024")
@@ -501,6 +543,8 @@ def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True
     del nxt
     log(f"[bench] tile_1024 with the PP force: {t_pp:.3f} ms/step "
         f"(PP kernel {ms_pp / max(1, n_pp):.3f} ms)")
+    out["two_level"] = two_level_rates(PMContext, wl, cur, ctx.brick, torch, log, steps,
+                                       warmup, ms_step)
     if adjoint:
         lx = [torch.ones((sp.n, 3), dtype=torch.float32, device=ctx.device) for sp in cur]
         lv = [torch.ones_like(t) for t in lx]
@@ -537,6 +581,8 @@ def main():
                     help="skip the float64 sub-box comparison of the large workload")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 1024^3 tile measured beside the large workload")
+    ap.add_argument("--no-two-level", action="store_true",
+                    help="skip the two-level force (pm_step_p3m) timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run one elementwise kernel that reads and "
                          "writes exactly 1 GiB (reference for HBM byte counters)")
@@ -610,7 +656,14 @@ def main():
         adj = {"step_vjp_ms": t_vjp, "vjp_over_step": t_vjp / ms_step,
                "fwd_adjoint_updates_per_s": wl.n_particles / ((ms_step + t_vjp) * 1e-3)}
         log(f"[bench] step adjoint {t_vjp:.3f} ms ({t_vjp / ms_step:.2f}x the step)")
+    brick = ctx.brick
     ctx.close()
+    two_level = None
+    if not args.no_two_level:
+        # the one-level context is gone; the compressed states stay on the device
+        log("[bench] two-level force (pm_step_p3m)")
+        two_level = two_level_rates(PMContext, wl, cur, brick, torch, log, args.steps,
+                                    args.warmup, ms_step)
     del A, B, cur
     torch.cuda.empty_cache()
 
@@ -675,6 +728,7 @@ def main():
         "hbm_footprint": footprint,
         "frozen_fraction": frozen,
         "vs_fp64_sub_box": compare,
+        "two_level": two_level,
         "tile_1024": extra,
         "adjoint": adj,
         "err_vs_fp64": err,

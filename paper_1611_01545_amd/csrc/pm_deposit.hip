@@ -264,7 +264,10 @@ __global__ __launch_bounds__(256) void k_fixed_to_float(const unsigned long long
 }  // namespace
 
 int deposit_tile_cells(const Geom& g) {
-  int T = 16 / g.r;
+  // 16 nodes per tile side (T r = 16), except with one mesh cell per compression cell
+  // (the coarse mesh of the two-level force): 8^3-cell tiles, since 16^3 cells would
+  // hold 83 KB of LDS and run one workgroup per CU
+  int T = g.r == 1 ? 8 : 16 / g.r;
   if (T < 1) T = 1;
   if (T > g.nc) T = (int)g.nc;
   return T;

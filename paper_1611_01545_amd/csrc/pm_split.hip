@@ -9,9 +9,11 @@
 // of power-of-two tile meshes with such buffers would transform at least 8 times the
 // fine mesh's cells).
 //
-// k_interp_cells interpolates a context's force meshes to compressed particles (the
-// inverse force interpolation of Sec. 2.3, Fig. 2): one thread per compression cell,
-// walking the cell's particles in stream order. A particle's mesh coordinate per axis is
+// k_interp_bricks interpolates a context's force meshes to compressed particles (the
+// inverse force interpolation of Sec. 2.3, Fig. 2): one workgroup per brick of the
+// stream order, whose particles are one contiguous range; threads take consecutive
+// particles (coalesced code loads and result stores) and find their cell among the
+// brick's cell offsets staged in LDS. A particle's mesh coordinate per axis is
 // (2 u + 1) r / 512 mesh cells (u its position code, r mesh cells per compression cell),
 // an exact binary fraction, so the node index and the CIC weights (multiples of 1/512)
 // are exact; the 8-node sum is float32 in a fixed order.
@@ -35,21 +37,33 @@ struct IArgs {
   int accumulate;
 };
 
-__global__ __launch_bounds__(IT) void k_interp_cells(IArgs A, Geom g,
-                                                     const float* __restrict__ acc) {
+__global__ __launch_bounds__(IT) void k_interp_bricks(IArgs A, Geom g,
+                                                      const float* __restrict__ acc) {
   const ISpecies& S = A.sp[blockIdx.y];
-  const int64_t key = (int64_t)blockIdx.x * IT + threadIdx.x;
-  if (key >= g.ncell3 || S.n == 0) return;
-  const int64_t j0 = S.off[key], j1 = S.off[key + 1];
-  if (j0 >= j1) return;
-  uint32_t cx, cy, cz;
-  key_cell(g, (uint32_t)key, cx, cy, cz);
+  if (S.n == 0) return;
+  __shared__ int64_t so[8 * 8 * 8 + 1];  // the brick's cell offsets (B <= 8)
+  const int B3 = 1 << (3 * g.lgB);
+  const int64_t k0 = (int64_t)blockIdx.x * B3;  // first cell key of the brick
+  for (int i = threadIdx.x; i <= B3; i += IT) so[i] = S.off[k0 + i];
+  __syncthreads();
+  const int64_t base = so[0];
+  const int64_t P = so[B3] - base;
   const int64_t n = g.ng, n3 = n * n * n;
   const int nm = (int)n - 1;  // n is a power of two
   const float* ax = acc;
   const float* ay = acc + n3;
   const float* az = acc + 2 * n3;
-  for (int64_t j = j0; j < j1; ++j) {
+  for (int64_t q = threadIdx.x; q < P; q += IT) {
+    const int64_t j = base + q;
+    if (j >= S.n) break;  // offsets inconsistent with n: latched by the offset check
+    // local cell: the largest l with so[l] <= j (skips empty cells)
+    int lo = 0, hi = B3;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (so[mid] <= j) lo = mid; else hi = mid;
+    }
+    uint32_t cx, cy, cz;
+    key_cell(g, (uint32_t)(k0 + lo), cx, cy, cz);
     // mesh coordinate (2u + 1) r / 512 per axis: node = t >> 9, weight of node + 1 =
     // (t & 511) / 512
     const int tx = (2 * (int)((cx << 8) | S.pos[3 * j]) + 1) * g.r;
@@ -69,11 +83,11 @@ __global__ __launch_bounds__(IT) void k_interp_cells(IArgs A, Geom g,
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
-          const int64_t q = ((int64_t)zs[dz] * n + ys[dy]) * n + xs[dx];
+          const int64_t qn = ((int64_t)zs[dz] * n + ys[dy]) * n + xs[dx];
           const float w = wz[dz] * wy[dy] * wx[dx];
-          sx += w * ax[q];
-          sy += w * ay[q];
-          sz += w * az[q];
+          sx += w * ax[qn];
+          sy += w * ay[qn];
+          sz += w * az[qn];
         }
     float* o = S.out + 3 * j;
     if (A.accumulate) {
@@ -104,8 +118,8 @@ pm_status run_interp_accel(pm_context* c, const pm_species* sp, int n_sp,
     A.sp[s].out = out[s];
   }
   ProfScope ps(c, ST_INTERP);
-  hipLaunchKernelGGL(k_interp_cells, dim3((unsigned)cdiv(g.ncell3, IT), (unsigned)n_sp),
-                     dim3(IT), 0, c->stream, A, g, acc);
+  hipLaunchKernelGGL(k_interp_bricks, dim3((unsigned)g.nbrick, (unsigned)n_sp), dim3(IT), 0,
+                     c->stream, A, g, acc);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
