@@ -23,9 +23,21 @@ Readings where the paper is silent (each listed in the design notes):
     v_max, mass, checksum, body length), then every cell's count (with the escape)
     followed by its particles as x, y, z bytes and vx, vy, vz little-endian u16.
 
+Adjustable code widths (Sec. 2.4, closing remark: a memory-light variant stores
+positions and velocities in 8 or 16 bits): a state may carry pos_bytes in {1, 2} and
+vel_bytes in {1, 2} (absent: 1 and 2, the format above). With P position bytes the
+offset inside a cell has 256^P steps, S = 256^P n_c and u = cell 256^P + offset; with V
+velocity bytes the histogram has 2^(8V) bins over [-v_max, v_max] (half range H =
+2^(8V - 1): j = clamp(floor(v H / v_max + H), 0, 2H - 1), bin centre (j - H + 1/2)
+v_max / H). Multi-byte codes are little-endian in the stream, and the header's
+otherwise reserved word holds P | V << 8 (0 for the paper's 1 and 2 bytes, so such
+streams are unchanged).
+
 Pins: tests/golden/stream_escape.txt is a byte stream written by hand from the
 paper's description; round trips encode(decode(s)) == s and the |dx| <= q/2,
-|dv| <= v_max/65536 bounds; stream length formula; hand-checked sort order.
+|dv| <= v_max/65536 bounds; stream length formula; hand-checked sort order; for the
+other widths a hand-written stream, the same round-trip bounds with q = L / S and
+v_max / 2^(8V), and the 1-byte code as the top byte of the 2-byte one.
 """
 
 from __future__ import annotations
@@ -64,30 +76,47 @@ def key_to_cell(key: np.ndarray, n_c: int, brick: int) -> np.ndarray:
     return out
 
 
-def position_codes(x: np.ndarray, n_c: int) -> np.ndarray:
-    """u = floor(x S) mod S per axis (int64), S = 256 n_c."""
-    S = 256 * n_c
+def widths(state):
+    """(position bytes, velocity bytes) of a state: (1, 2) unless it says otherwise."""
+    return int(state.get("pos_bytes", 1)), int(state.get("vel_bytes", 2))
+
+
+def pos_scale(n_c: int, pos_bytes: int = 1) -> int:
+    """S = 256^P n_c position steps per box side."""
+    return (256 ** pos_bytes) * n_c
+
+
+def half_range(vel_bytes: int = 2) -> int:
+    """H = 2^(8V - 1): half the number of velocity bins."""
+    return 2 ** (8 * vel_bytes - 1)
+
+
+def position_codes(x: np.ndarray, n_c: int, pos_bytes: int = 1) -> np.ndarray:
+    """u = floor(x S) mod S per axis (int64), S = 256^P n_c."""
+    S = pos_scale(n_c, pos_bytes)
     u = np.floor(np.asarray(x, dtype=np.float64) * S).astype(np.int64)
     return np.mod(u, S)
 
 
-def velocity_codes(v32: np.ndarray, v_max: np.float32) -> np.ndarray:
-    """2^16-bin histogram index of each component over [-v_max, v_max]."""
+def velocity_codes(v32: np.ndarray, v_max: np.float32, vel_bytes: int = 2) -> np.ndarray:
+    """2^(8V)-bin histogram index of each component over [-v_max, v_max]."""
+    H = float(half_range(vel_bytes))
     v = np.asarray(v32, dtype=np.float32).astype(np.float64)
     if float(v_max) == 0.0:
-        return np.full(v.shape, 32768, dtype=np.int64)
-    C = 32768.0 / np.float64(v_max)
+        return np.full(v.shape, int(H), dtype=np.int64)
+    C = H / np.float64(v_max)
     t = v * C
-    t = t + 32768.0
-    return np.clip(np.floor(t), 0, 65535).astype(np.int64)
+    t = t + H
+    return np.clip(np.floor(t), 0, 2 * H - 1).astype(np.int64)
 
 
-def decode_velocity(j: np.ndarray, v_max: np.float32) -> np.ndarray:
-    """Bin centre (j - 32767.5) * v_max / 32768, rounded once to float32."""
+def decode_velocity(j: np.ndarray, v_max: np.float32, vel_bytes: int = 2) -> np.ndarray:
+    """Bin centre (j - H + 1/2) * v_max / H, rounded once to float32."""
     if float(v_max) == 0.0:
         return np.zeros(np.shape(j), dtype=np.float32)
-    w = np.float64(v_max) * 2.0 ** -15
-    return ((np.asarray(j, dtype=np.float64) - 32767.5) * w).astype(np.float32)
+    H = float(half_range(vel_bytes))
+    w = np.float64(v_max) / H
+    return ((np.asarray(j, dtype=np.float64) - (H - 0.5)) * w).astype(np.float32)
 
 
 def full_counts(state) -> np.ndarray:
@@ -109,28 +138,32 @@ def build_counts(keys_sorted: np.ndarray, n_c: int):
 
 
 def encode(x32: np.ndarray, v32: np.ndarray, n_c: int, brick: int,
-           v_max: np.float32 | None = None):
+           v_max: np.float32 | None = None, pos_bytes: int = 1, vel_bytes: int = 2):
     """Float particles -> compressed state dict (plus 'perm': stream -> input index)."""
     x32 = np.asarray(x32, dtype=np.float32)
     v32 = np.asarray(v32, dtype=np.float32)
     if v_max is None:
         v_max = np.float32(np.max(np.abs(v32))) if v32.size else np.float32(0.0)
-    u = position_codes(x32, n_c)
-    keys = cell_keys(u >> 8, n_c, brick)
+    u = position_codes(x32, n_c, pos_bytes)
+    keys = cell_keys(u >> (8 * pos_bytes), n_c, brick)
     perm = np.argsort(keys, kind="stable")
-    return assemble(u[perm], velocity_codes(v32, v_max)[perm], keys[perm], v_max,
-                    n_c, brick, perm)
+    return assemble(u[perm], velocity_codes(v32, v_max, vel_bytes)[perm], keys[perm], v_max,
+                    n_c, brick, perm, pos_bytes, vel_bytes)
 
 
-def assemble(u_sorted, j_sorted, keys_sorted, v_max, n_c, brick, perm=None):
+def assemble(u_sorted, j_sorted, keys_sorted, v_max, n_c, brick, perm=None, pos_bytes=1,
+             vel_bytes=2):
     count, esc = build_counts(keys_sorted, n_c)
     st = {
         "n_c": n_c, "brick": brick,
         "count": count, "esc": esc,
-        "pos": (u_sorted & 255).astype(np.uint8),
-        "vel": j_sorted.astype(np.uint16),
+        "pos": (u_sorted & (256 ** pos_bytes - 1)).astype(
+            np.uint8 if pos_bytes == 1 else np.uint16),
+        "vel": j_sorted.astype(np.uint16 if vel_bytes == 2 else np.uint8),
         "v_max": np.float32(v_max),
     }
+    if (pos_bytes, vel_bytes) != (1, 2):
+        st["pos_bytes"], st["vel_bytes"] = pos_bytes, vel_bytes
     if perm is not None:
         st["perm"] = perm
     return st
@@ -145,17 +178,19 @@ def stream_keys(state) -> np.ndarray:
 def decode_codes(state):
     """Integer position codes u [n][3] (int64) and velocity codes j [n][3]."""
     n_c, brick = state["n_c"], state["brick"]
+    pb, _ = widths(state)
     cell = key_to_cell(stream_keys(state), n_c, brick)
-    u = cell * 256 + state["pos"].astype(np.int64)
+    u = cell * (256 ** pb) + state["pos"].astype(np.int64)
     return u, state["vel"].astype(np.int64)
 
 
 def decode(state):
     """Compressed state -> float32 x, v [n][3] in stream order (bin centres)."""
     u, j = decode_codes(state)
-    S = 256 * state["n_c"]
+    pb, vb = widths(state)
+    S = pos_scale(state["n_c"], pb)
     x = ((u.astype(np.float64) + 0.5) / S).astype(np.float32)
-    v = decode_velocity(j, state["v_max"])
+    v = decode_velocity(j, state["v_max"], vb)
     return x, v
 
 
@@ -177,10 +212,11 @@ def decode_cells(state, keys, offsets=None):
         np.zeros(0, dtype=np.int64)
     kk = np.repeat(keys, off[keys + 1] - off[keys])
     cell = key_to_cell(kk, n_c, brick)
-    u = cell * 256 + state["pos"][idx].astype(np.int64)
-    S = 256 * n_c
+    pb, vb = widths(state)
+    u = cell * (256 ** pb) + state["pos"][idx].astype(np.int64)
+    S = pos_scale(n_c, pb)
     x = ((u.astype(np.float64) + 0.5) / S).astype(np.float32)
-    v = decode_velocity(state["vel"][idx].astype(np.int64), np.float32(state["v_max"]))
+    v = decode_velocity(state["vel"][idx].astype(np.int64), np.float32(state["v_max"]), vb)
     return x, v, idx
 
 
@@ -202,10 +238,26 @@ def checksum(body: bytes) -> int:
         return int(np.sum((np.uint64(2) * i + np.uint64(1)) * b, dtype=np.uint64))
 
 
+def width_word(pos_bytes: int, vel_bytes: int) -> int:
+    """Header word of the code widths: 0 for the paper's (1, 2), else P | V << 8."""
+    return 0 if (pos_bytes, vel_bytes) == (1, 2) else pos_bytes | (vel_bytes << 8)
+
+
+def _le_bytes(a: np.ndarray, nbytes: int) -> np.ndarray:
+    """[n][3] codes as little-endian bytes [n][3 nbytes]."""
+    n = a.shape[0]
+    if nbytes == 1:
+        return a.astype(np.uint8).reshape(n, 3)
+    return a.astype("<u2").view(np.uint8).reshape(n, 6)
+
+
 def pack(state, mass: float, species_id: int) -> bytes:
-    """Cell-ordered byte stream: counts with the 255 escape, then 9-byte records."""
+    """Cell-ordered byte stream: counts with the 255 escape, then the particle records
+    (3 P position bytes, then 3 V velocity bytes)."""
     full = full_counts(state)
     pos, vel = state["pos"], state["vel"]
+    pb, vb = widths(state)
+    rb = 3 * (pb + vb)
     parts = []
     p = 0
     for c in range(full.size):
@@ -215,15 +267,15 @@ def pack(state, mass: float, species_id: int) -> bytes:
         else:
             parts.append(bytes([n]))
         if n:
-            rec = np.zeros((n, 9), dtype=np.uint8)
-            rec[:, 0:3] = pos[p:p + n]
-            rec[:, 3:9] = vel[p:p + n].astype("<u2").view(np.uint8).reshape(n, 6)
+            rec = np.zeros((n, rb), dtype=np.uint8)
+            rec[:, 0:3 * pb] = _le_bytes(pos[p:p + n], pb)
+            rec[:, 3 * pb:rb] = _le_bytes(vel[p:p + n], vb)
             parts.append(rec.tobytes())
             p += n
     body = b"".join(parts)
     hdr = struct.pack("<4sIIIQQfIdQQ", MAGIC, VERSION, species_id, state["brick"],
-                      int(pos.shape[0]), state["n_c"], float(state["v_max"]), 0,
-                      float(mass), checksum(body), len(body))
+                      int(pos.shape[0]), state["n_c"], float(state["v_max"]),
+                      width_word(pb, vb), float(mass), checksum(body), len(body))
     assert len(hdr) == HEADER_BYTES
     return hdr + body
 
@@ -236,10 +288,15 @@ def unpack(buf: bytes):
     """Inverse of pack with the integrity checks; returns (state, mass, species_id)."""
     if len(buf) < HEADER_BYTES:
         raise StreamError("truncated header")
-    (magic, ver, sid, brick, n, n_c, v_max, _r, mass, csum, blen) = struct.unpack(
+    (magic, ver, sid, brick, n, n_c, v_max, wword, mass, csum, blen) = struct.unpack(
         "<4sIIIQQfIdQQ", buf[:HEADER_BYTES])
     if magic != MAGIC or ver != VERSION:
         raise StreamError("bad magic/version")
+    pb, vb = (1, 2) if wword == 0 else (wword & 255, wword >> 8)
+    # (1, 2) is written as 0, so its explicit word is not a valid header either
+    if pb not in (1, 2) or vb not in (1, 2) or wword == 0x201:
+        raise StreamError("bad code widths")
+    rb = 3 * (pb + vb)
     body = buf[HEADER_BYTES:]
     if len(body) != blen:
         raise StreamError("body length mismatch")
@@ -248,8 +305,8 @@ def unpack(buf: bytes):
     ncell = n_c ** 3
     count = np.zeros(ncell, dtype=np.uint8)
     esc = []
-    pos = np.zeros((n, 3), dtype=np.uint8)
-    vel = np.zeros((n, 3), dtype=np.uint16)
+    pos = np.zeros((n, 3), dtype=np.uint8 if pb == 1 else np.uint16)
+    vel = np.zeros((n, 3), dtype=np.uint16 if vb == 2 else np.uint8)
     off, p = 0, 0
     for c in range(ncell):
         if off >= len(body):
@@ -261,21 +318,26 @@ def unpack(buf: bytes):
             off += 4
             esc.append((c, k))
         count[c] = min(k, ESCAPE)
-        if p + k > n or off + 9 * k > len(body):
+        if p + k > n or off + rb * k > len(body):
             raise StreamError("count exceeds N or body")
-        rec = np.frombuffer(body[off:off + 9 * k], dtype=np.uint8).reshape(k, 9)
-        pos[p:p + k] = rec[:, 0:3]
-        vel[p:p + k] = rec[:, 3:9].copy().view("<u2").reshape(k, 3)
-        off += 9 * k
+        rec = np.frombuffer(body[off:off + rb * k], dtype=np.uint8).reshape(k, rb)
+        rp, rv = rec[:, 0:3 * pb], rec[:, 3 * pb:rb]
+        pos[p:p + k] = rp if pb == 1 else rp.copy().view("<u2").reshape(k, 3)
+        vel[p:p + k] = rv if vb == 1 else rv.copy().view("<u2").reshape(k, 3)
+        off += rb * k
         p += k
     if p != n or off != len(body):
         raise StreamError("sum of counts != N")
     st = {"n_c": n_c, "brick": brick, "count": count,
           "esc": np.array(esc, dtype=np.uint64).reshape(-1, 2),
           "pos": pos, "vel": vel, "v_max": np.float32(v_max)}
+    if (pb, vb) != (1, 2):
+        st["pos_bytes"], st["vel_bytes"] = pb, vb
     return st, mass, sid
 
 
 def stream_length(state) -> int:
     full = full_counts(state)
-    return HEADER_BYTES + 9 * int(full.sum()) + full.size + 4 * int(np.sum(full >= ESCAPE))
+    pb, vb = widths(state)
+    return (HEADER_BYTES + 3 * (pb + vb) * int(full.sum()) + full.size +
+            4 * int(np.sum(full >= ESCAPE)))

@@ -11,7 +11,7 @@ Readings where the paper is silent:
     interpolated from; particles of every species in that cell take part;
   * "truncated" is read as a hard cut: a pair closer than r_soft exerts no force;
   * compressed particles sit at their bin centres; the cut is decided on the exact integer
-    code differences du (|du|^2 >= (r_soft S / L)^2 with S = 256 n_cell), so that it does not
+    code differences du (|du|^2 >= (r_soft S / L)^2 with S = 256^P n_cell), so that it does not
     depend on rounding;
   * the acceleration is a_i = F_i / m_i.
 
@@ -72,7 +72,9 @@ def pp_accel_positions(xs, masses, n_g: int, r_soft: float, G: float, box: float
 def pp_accel(states, masses, n_g: int, r_soft: float, G: float, box: float = 1.0):
     """PP accelerations of compressed states, per species in stream order."""
     xs, us = [], []
-    S = 256 * states[0]["n_c"]
+    pb = codec.widths(states[0])[0]
+    assert all(codec.widths(st)[0] == pb for st in states), "one position width per call"
+    S = codec.pos_scale(states[0]["n_c"], pb)
     for st in states:
         u, _ = codec.decode_codes(st)
         us.append(u)

@@ -11,7 +11,8 @@ static box) are readings.
 On compressed particles (Sec. 2.4 format) the step decodes the bin centres, runs the
 same float64 step, and re-encodes:
   * positions in fixed point: u' = (u + floor(d + 1/2)) mod S with d = v' c_d S, which
-    is the encoding of the decoded centre plus the displacement;
+    is the encoding of the decoded centre plus the displacement (S = 256^P n_c for P
+    position bytes, oracle.codec);
   * velocities with a new v_max' = the smallest power of two >= V + |c_k| A_max, where
     V is the largest decoded |v_a| of the species and A_max the largest |a_a| over
     the acceleration mesh; CIC interpolation is a convex combination of mesh values,
@@ -56,24 +57,26 @@ def step_float(species, n_g: int, c_k: float, c_d: float, soft_cells: float = 1.
 
 
 def kick_codes(u: np.ndarray, v_dec: np.ndarray, a_i: np.ndarray, v_max_new, S: int,
-               c_k: float, c_d: float):
+               c_k: float, c_d: float, vel_bytes: int = 2):
     """Kick, fixed-point drift and velocity re-binning of decoded particles.
 
-    u: position codes [n][3]; v_dec: decoded velocities; a_i: interpolated accelerations;
-    v_max_new: the new bin range. Returns (u_new, j_new, v_new, pos_pre, vel_pre) with
-    the pre-floor values d + 1/2 and v' C + 32768.
+    u: position codes [n][3] (S steps per box side); v_dec: decoded velocities; a_i:
+    interpolated accelerations; v_max_new: the new bin range; vel_bytes: 2^(8 vel_bytes)
+    velocity bins, half range H. Returns (u_new, j_new, v_new, pos_pre, vel_pre) with the
+    pre-floor values d + 1/2 and v' C + H, C = H / v_max_new.
     """
+    H = float(codec.half_range(vel_bytes))
     v1 = np.asarray(v_dec, dtype=np.float64) + c_k * np.asarray(a_i, dtype=np.float64)
     d = v1 * (c_d * S)
     pos_pre = d + 0.5
     u1 = np.mod(np.asarray(u, dtype=np.int64) + np.floor(pos_pre).astype(np.int64), S)
     if float(v_max_new) > 0:
-        C = 32768.0 / np.float64(v_max_new)
-        vel_pre = v1 * C + 32768.0
-        j1 = np.clip(np.floor(vel_pre), 0, 65535).astype(np.int64)
+        C = H / np.float64(v_max_new)
+        vel_pre = v1 * C + H
+        j1 = np.clip(np.floor(vel_pre), 0, 2 * H - 1).astype(np.int64)
     else:
-        vel_pre = np.full(v1.shape, 32768.0)
-        j1 = np.full(v1.shape, 32768, dtype=np.int64)
+        vel_pre = np.full(v1.shape, H)
+        j1 = np.full(v1.shape, int(H), dtype=np.int64)
     return u1, j1, v1, pos_pre, vel_pre
 
 
@@ -95,7 +98,6 @@ def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
     """
     n_c = states[0]["n_c"]
     brick = states[0]["brick"]
-    S = 256 * n_c
     decoded = [codec.decode(st) for st in states]
     xs = [(x.astype(np.float64), m) for (x, _), m in zip(decoded, masses)]
     acc, a_mesh, rho = mesh.accelerations(xs, n_g, soft_cells, G, split)
@@ -112,10 +114,13 @@ def step_compressed(states, masses, n_g: int, c_k: float, c_d: float,
         v_dec = v.astype(np.float64)
         V = float(np.max(np.abs(v_dec))) if v_dec.size else 0.0
         v_max_new = np.float32(pow2_ceil(V + abs(c_k) * a_max))
-        u1, j1, v1, pos_pre, vel_pre = kick_codes(u, v_dec, ai, v_max_new, S, c_k, c_d)
-        keys = codec.cell_keys(u1 >> 8, n_c, brick)
+        pb, vb = codec.widths(st)
+        S = codec.pos_scale(n_c, pb)
+        u1, j1, v1, pos_pre, vel_pre = kick_codes(u, v_dec, ai, v_max_new, S, c_k, c_d, vb)
+        keys = codec.cell_keys(u1 >> (8 * pb), n_c, brick)
         perm = np.argsort(keys, kind="stable")
-        ns = codec.assemble(u1[perm], j1[perm], keys[perm], v_max_new, n_c, brick)
+        ns = codec.assemble(u1[perm], j1[perm], keys[perm], v_max_new, n_c, brick, None,
+                            pb, vb)
         new_states.append(ns)
         diags.append({"perm": perm, "pos_pre": pos_pre, "vel_pre": vel_pre,
                       "v_max_new": v_max_new, "acc": ai, "v_new": v1,

@@ -24,7 +24,8 @@ def load_stream_cases(path=None):
                 repeat = 1
             elif key == "end":
                 n_c = cur["n_c"]
-                S = 256 * n_c
+                pb = cur.get("widths", (1, 2))[0]
+                S = (256 ** pb) * n_c
                 P = np.array(cur["particles"], dtype=np.float64).reshape(-1, 6)
                 cur["x"] = (P[:, :3] / S).astype(np.float32)
                 cur["v"] = P[:, 3:].astype(np.float32)
@@ -32,6 +33,8 @@ def load_stream_cases(path=None):
                 cur = None
             elif key in ("n_c", "brick"):
                 cur[key] = int(tok[1])
+            elif key == "widths":
+                cur["widths"] = (int(tok[1]), int(tok[2]))
             elif key == "repeat":
                 repeat = int(tok[1])
             elif key == "particle":
