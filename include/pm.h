@@ -138,10 +138,19 @@ enum { PM_FLOAT = 0, PM_COMPRESSED = 1 };
  *             esc    device uint64 [cap_esc][2], (cell, count) for every cell with
  *                    count >= 255, sorted by cell;
  *             hdr    device pm_shdr.
+ *   widths  code widths of a compressed species (Sec. 2.4, closing remark: a memory-light
+ *           variant keeps positions and velocities in 8 or 16 bits): 0 for the format
+ *           above (1-byte positions, 2-byte velocities), else P | V << 8 with P, V in
+ *           {1, 2}. P = 2: pos holds uint16 [n][3] offsets in units of 1/(65536 n_cell)
+ *           (S = 65536 n_cell position steps per box side); V = 1: vel holds uint8
+ *           [n][3] indices into 256 bins over [-v_max, v_max] (code floor(v 128 / v_max
+ *           + 128) clamped to [0, 255], bin centre (j - 127.5) v_max / 128). The pointers
+ *           keep their C types and are read as those arrays. All species of one call
+ *           have the same widths (PM_ERR_ARG otherwise). Ignored for PM_FLOAT.
  *   n       particle count (>= 0); mass  mass per particle. */
 typedef struct pm_species {
   int32_t layout;
-  int32_t reserved;
+  int32_t widths;
   int64_t n;
   double mass;
   float* x;
@@ -196,14 +205,15 @@ pm_status pm_sync(pm_ctx ctx);
 /* After PM_ERR_CAPACITY: the capacity (elements) that would have been needed. */
 pm_status pm_last_error_detail(pm_ctx ctx, int64_t* needed);
 
-/* Compress float particles (Sec. 2.4): position code u = floor(x 256 n_cell / L) mod
- * 256 n_cell per axis (cell u >> 8, byte u & 255); v_max = largest |v_a| of the species;
- * cells of the n_cell^3 mesh in stream order; particles of a cell in input order.
+/* Compress float particles (Sec. 2.4): position code u = floor(x S / L) mod S per axis
+ * (S = 256 n_cell, cell u >> 8, byte u & 255; with out->widths P = 2, S = 65536 n_cell,
+ * cell u >> 16, offset u & 65535); v_max = largest |v_a| of the species; cells of the
+ * n_cell^3 mesh in stream order; particles of a cell in input order.
  * in: PM_FLOAT; out: PM_COMPRESSED with out->n == in->n. perm (device int64 [n],
  * nullable) receives, for each stream position, the input index of that particle. */
 pm_status pm_encode(pm_ctx ctx, const pm_species* in, pm_species* out, int64_t* perm);
 
-/* Decompress to bin centres (u + 1/2) L / (256 n_cell), in stream order (Sec. 2.4,
+/* Decompress to bin centres (u + 1/2) L / S (S = 256^P n_cell), in stream order (Sec. 2.4,
  * used for restarts).
  * in: PM_COMPRESSED; out: PM_FLOAT with out->n == in->n. */
 pm_status pm_decode(pm_ctx ctx, const pm_species* in, pm_species* out);
@@ -212,8 +222,10 @@ pm_status pm_decode(pm_ctx ctx, const pm_species* in, pm_species* out);
  * (Sec. 2.1 footnote: both species on the same mesh). rho: device float [n_mesh^3].
  * Species must all be PM_FLOAT or all PM_COMPRESSED. Deterministic: PM_COMPRESSED
  * sums each species' exact CIC weights as integers per node, scales each sum by the
- * species' mass in FP64, rounds it to float and adds the species in a fixed order;
- * PM_FLOAT sums all contributions in 64-bit fixed point. */
+ * species' mass in FP64, rounds it to float and adds the species in a fixed order
+ * (with 2-byte positions each node's weight is the exact product rounded to a multiple
+ * of 2^-27, the 1-byte form's exact unit); PM_FLOAT sums all contributions in 64-bit
+ * fixed point. */
 pm_status pm_deposit(pm_ctx ctx, const pm_species* sp, int n_sp, float* rho);
 
 /* Accelerations a_a(c) from a density mesh, eqs. (2)-(3): a = IDFT(-i D(k) G(k) DFT(rho))
@@ -228,7 +240,7 @@ pm_status pm_force(pm_ctx ctx, const float* rho, float* acc, float* a_max);
 /* Interpolate acc to the particles (CIC), kick v' = v + c_kick a, drift
  * x' = x + c_drift v' (mod L). PM_FLOAT: in and out may be the same arrays.
  * PM_COMPRESSED: in and out must be distinct; positions drift in fixed point
- * (u' = u + floor(v' c_drift 256 n_cell / L + 1/2)), velocities are re-binned with
+ * (u' = u + floor(v' c_drift S / L + 1/2), S = 256^P n_cell), velocities are re-binned with
  * v_max' = the smallest power of two >= max|v_decoded| + |c_kick| a_max, and the
  * stream is re-sorted stably into cell order. a_max: device float from pm_force
  * (required for PM_COMPRESSED). */
@@ -342,20 +354,23 @@ pm_status pm_reduce_noalloc(pm_ctx ctx, const pm_species* sp, int n_sp, const fl
                             const float* acc, double* out);
 
 /* Byte stream of one compressed species (Sec. 2.4 layout): a 64-byte header
- * {"PMC1", version 1, species_id, brick, N, n_cell, v_max, 0, mass, checksum,
+ * {"PMC1", version 1, species_id, brick, N, n_cell, v_max, widths, mass, checksum,
  * body length}, then for every cell its count byte (255 + uint32 count when >= 255)
- * followed by its particles' 9-byte records (x, y, z bytes; vx, vy, vz little-endian
- * uint16). The checksum is sum_i (2 i + 1) b_i mod 2^64 over the body bytes.
- * buf: device uint8 [cap]; used: device int64 (bytes written). */
+ * followed by its particles' records: 3 P position bytes (x, y, z) then 3 V velocity
+ * bytes (vx, vy, vz), multi-byte codes little-endian; with the paper's widths (header
+ * word 0) a record is 9 bytes (x, y, z bytes; vx, vy, vz uint16). The widths word is
+ * P | V << 8 otherwise. The checksum is sum_i (2 i + 1) b_i mod 2^64 over the body
+ * bytes. buf: device uint8 [cap]; used: device int64 (bytes written). */
 pm_status pm_pack(pm_ctx ctx, const pm_species* sp, int32_t species_id, uint8_t* buf,
                   int64_t cap, int64_t* used);
 /* Exact stream length of a compressed species (host value; synchronises). */
 pm_status pm_pack_size(pm_ctx ctx, const pm_species* sp, int64_t* bytes);
 
 /* Parse and verify a byte stream held in HOST memory into a compressed species
- * (synchronous). Checks magic, version, brick and n_cell against the context, body
- * length, checksum, and that the counts sum to N == out->n; returns PM_ERR_CORRUPT
- * otherwise. The species mass and id from the header are returned via the pointers
+ * (synchronous). Checks magic, version, brick and n_cell against the context, the code
+ * widths against out->widths (PM_ERR_ARG when they differ, PM_ERR_CORRUPT when the word
+ * is not a valid one), body length, checksum, and that the counts sum to N == out->n;
+ * returns PM_ERR_CORRUPT otherwise. The species mass and id from the header are returned via the pointers
  * (nullable). */
 pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species* out,
                     double* mass, int32_t* species_id);

@@ -4,4 +4,4 @@ The compute path is libpm.so (HIP kernels for gfx950 behind the C ABI in
 include/pm.h); this package is its Python binding.
 """
 
-from .pm import CompressedSpecies, FloatSpecies, G_UNIT, PMContext  # noqa: F401
+from .pm import CompressedSpecies, FloatSpecies, G_UNIT, PMContext, widths_word  # noqa: F401

@@ -55,7 +55,7 @@ class PmSizes(ctypes.Structure):
 class PmSpecies(ctypes.Structure):
     _fields_ = [
         ("layout", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("widths", ctypes.c_int32),
         ("n", ctypes.c_int64),
         ("mass", ctypes.c_double),
         ("x", ctypes.c_void_p),

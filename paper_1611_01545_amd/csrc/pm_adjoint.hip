@@ -582,7 +582,9 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
   const Geom& g = c->g;
   const bool comp = in[0].layout == PM_COMPRESSED;
   const int tt = comp ? deposit_tile_cells(g) : 0;
-  const bool tiled = comp && tt * g.r == 16 && (tt == 4 || tt == 8) && g.B * g.r == 16;
+  // (the tiled kernels read the paper's 1-byte position codes; other code widths decode)
+  const bool tiled = comp && tt * g.r == 16 && (tt == 4 || tt == 8) && g.B * g.r == 16 &&
+                     common_width_kind(in, n_sp) == 0;
   Positions P;
   if ((s = positions(c, in, n_sp, SC_VJP2, P, !tiled)) != PM_OK) return s;
   // forward recomputation: density, acceleration mesh (in the context mesh)
@@ -597,7 +599,8 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
     for (int i = 0; i < n_sp; ++i) {
       const int64_t cap = in[i].n / 255 + 1;
       bytes += align256((size_t)in[i].n * 8) + align256((size_t)nc3) +
-               align256((size_t)in[i].n * 3) + align256((size_t)in[i].n * 6) +
+               align256((size_t)in[i].n * 3 * width_pos(in[i])) +
+               align256((size_t)in[i].n * 3 * width_vel(in[i])) +
                align256((size_t)cap * 16) + align256(sizeof(pm_shdr));
     }
     char* pool = (char*)scratch(c, SC_VJP3, bytes);
@@ -612,9 +615,9 @@ pm_status run_step_vjp(pm_context* c, const pm_species* in, int n_sp, double dt,
       out[i].count = (uint8_t*)(pool + at);
       at += align256((size_t)nc3);
       out[i].pos = (uint8_t*)(pool + at);
-      at += align256((size_t)n * 3);
+      at += align256((size_t)n * 3 * width_pos(in[i]));
       out[i].vel = (uint16_t*)(pool + at);
-      at += align256((size_t)n * 6);
+      at += align256((size_t)n * 3 * width_vel(in[i]));
       out[i].esc = (uint64_t*)(pool + at);
       out[i].cap_esc = cap;
       at += align256((size_t)cap * 16);

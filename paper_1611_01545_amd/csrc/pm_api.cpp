@@ -29,6 +29,7 @@ pm_status check_species(const pm_context* c, const pm_species* s, bool need_floa
   }
   if (s->layout == PM_COMPRESSED) {
     if (!s->count || !s->hdr) return PM_ERR_ARG;
+    if (!widths_valid(s->widths)) return PM_ERR_ARG;
     if (s->n > 0 && (!s->pos || !s->vel)) return PM_ERR_ARG;
     if (s->cap_esc < 0 || (s->cap_esc > 0 && !s->esc)) return PM_ERR_ARG;
     return PM_OK;
@@ -323,6 +324,9 @@ static pm_status check_kick_args(pm_context* c, const pm_species* in, pm_species
     if (in[i].layout != out[i].layout || in[i].n != out[i].n) return PM_ERR_ARG;
     if (in[i].layout != in[0].layout) return PM_ERR_ARG;
     if (in[i].layout == PM_COMPRESSED &&
+        (width_kind(in[i]) != width_kind(in[0]) || width_kind(out[i]) != width_kind(in[0])))
+      return PM_ERR_ARG;
+    if (in[i].layout == PM_COMPRESSED &&
         (in[i].pos == out[i].pos || in[i].vel == out[i].vel || in[i].count == out[i].count ||
          in[i].hdr == out[i].hdr))
       return PM_ERR_ARG;
@@ -553,7 +557,8 @@ pm_status pm_pack_size(pm_ctx c, const pm_species* sp, int64_t* bytes) {
   pm_shdr h;
   PM_HIP_CHECK(hipStreamSynchronize(c->stream));
   PM_HIP_CHECK(hipMemcpy(&h, sp->hdr, sizeof(h), hipMemcpyDeviceToHost));
-  *bytes = 64 + 9 * sp->n + c->g.ncell3 + 4 * h.n_esc;
+  const int64_t rb = 3 * (width_pos(*sp) + width_vel(*sp));
+  *bytes = 64 + rb * sp->n + c->g.ncell3 + 4 * h.n_esc;
   return PM_OK;
 }
 
@@ -562,7 +567,7 @@ pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, 
   if (!c || !buf || !out || len < 0) return PM_ERR_ARG;
   if (check_species(c, out, false) != PM_OK || out->layout != PM_COMPRESSED) return PM_ERR_ARG;
   if (len < 64) return PM_ERR_CORRUPT;
-  uint32_t ver, sid, brick;
+  uint32_t ver, sid, brick, wword;
   uint64_t n, nc, csum, blen;
   float vmax;
   double m;
@@ -573,12 +578,18 @@ pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, 
   std::memcpy(&n, buf + 16, 8);
   std::memcpy(&nc, buf + 24, 8);
   std::memcpy(&vmax, buf + 32, 4);
+  std::memcpy(&wword, buf + 36, 4);
   std::memcpy(&m, buf + 40, 8);
   std::memcpy(&csum, buf + 48, 8);
   std::memcpy(&blen, buf + 56, 8);
   if (ver != 1 || brick != (uint32_t)c->g.B || nc != (uint64_t)c->g.nc) return PM_ERR_CORRUPT;
   if (blen != (uint64_t)(len - 64) || n != (uint64_t)out->n) return PM_ERR_CORRUPT;
   if (!(vmax >= 0.f) || !std::isfinite(vmax)) return PM_ERR_CORRUPT;
+  // code widths: a valid word, equal to the destination's
+  if (wword > 0xffffu || !widths_valid((int32_t)wword)) return PM_ERR_CORRUPT;
+  if ((int32_t)wword != out->widths) return PM_ERR_ARG;
+  const int P = width_pos(*out), V = width_vel(*out);
+  const uint64_t RB = 3 * (uint64_t)(P + V);
   const uint8_t* body = buf + 64;
   uint64_t cs = 0;
   for (uint64_t i = 0; i < blen; ++i) cs += (2ull * i + 1ull) * body[i];
@@ -586,8 +597,8 @@ pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, 
   const int64_t ncell = c->g.ncell3;
   std::vector<uint8_t> count((size_t)ncell);
   std::vector<uint64_t> esc;
-  std::vector<uint8_t> pos((size_t)n * 3);
-  std::vector<uint16_t> vel((size_t)n * 3);
+  std::vector<uint8_t> pos((size_t)n * 3 * P);
+  std::vector<uint8_t> vel((size_t)n * 3 * V);
   uint64_t off = 0, p = 0;
   int32_t jmin = 65536, jmax = -1;
   for (int64_t cc = 0; cc < ncell; ++cc) {
@@ -604,18 +615,19 @@ pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, 
       esc.push_back(k);
     }
     count[(size_t)cc] = (uint8_t)(k >= 255 ? 255 : k);
-    if (p + k > n || off + 9 * k > blen) return PM_ERR_CORRUPT;
-    for (uint64_t q = 0; q < k; ++q, ++p, off += 9) {
+    if (p + k > n || off + RB * k > blen) return PM_ERR_CORRUPT;
+    for (uint64_t q = 0; q < k; ++q, ++p, off += RB) {
+      // little-endian codes in the stream; the device arrays hold them in the host's
+      // byte order, which is little-endian on every machine this library runs on
       const uint8_t* r = body + off;
-      pos[3 * p] = r[0];
-      pos[3 * p + 1] = r[1];
-      pos[3 * p + 2] = r[2];
+      std::memcpy(&pos[3 * P * p], r, 3 * P);
       for (int a = 0; a < 3; ++a) {
-        uint16_t w = (uint16_t)(r[3 + 2 * a] | (r[4 + 2 * a] << 8));
-        vel[3 * p + a] = w;
+        int32_t w = r[3 * P + V * a];
+        if (V == 2) w |= (int32_t)r[3 * P + V * a + 1] << 8;
         jmin = w < jmin ? w : jmin;
         jmax = w > jmax ? w : jmax;
       }
+      std::memcpy(&vel[3 * V * p], r + 3 * P, 3 * V);
     }
   }
   if (p != n || off != blen) return PM_ERR_CORRUPT;
@@ -633,7 +645,7 @@ pm_status pm_unpack(pm_ctx c, const uint8_t* buf, int64_t len, pm_species* out, 
   PM_HIP_CHECK(hipMemcpy(out->count, count.data(), (size_t)ncell, hipMemcpyHostToDevice));
   if (n > 0) {
     PM_HIP_CHECK(hipMemcpy(out->pos, pos.data(), pos.size(), hipMemcpyHostToDevice));
-    PM_HIP_CHECK(hipMemcpy(out->vel, vel.data(), vel.size() * 2, hipMemcpyHostToDevice));
+    PM_HIP_CHECK(hipMemcpy(out->vel, vel.data(), vel.size(), hipMemcpyHostToDevice));
   }
   if (n_esc > 0)
     PM_HIP_CHECK(hipMemcpy(out->esc, esc.data(), esc.size() * 8, hipMemcpyHostToDevice));

@@ -4,6 +4,8 @@
 // inexact product in the velocity code is a single correctly rounded float64
 // operation with contraction disabled.
 #pragma once
+#include <type_traits>
+
 #include "pm_common.h"
 
 #define PM_STREAM_HEADER 64
@@ -73,4 +75,77 @@ __device__ inline float vel_decode_w(uint32_t j, float w) {
   return ((float)j - 32767.5f) * w;
 }
 
-pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_t* out);
+// ---------------------------------------------------------------- code widths --
+// Adjustable widths (Sec. 2.4, closing remark): P position bytes per axis (offset inside
+// the cell in units of 1/(256^P n_c), S = 256^P n_c) and V velocity bytes per axis
+// (2^(8V) bins, half range H = 2^(8V - 1)). P = 1, V = 2 is the paper's format; the
+// functions below reduce to the ones above there.
+template <int P> struct PosCode;
+template <> struct PosCode<1> { using T = uint8_t; };
+template <> struct PosCode<2> { using T = uint16_t; };
+template <int V> struct VelCode;
+template <> struct VelCode<1> { using T = uint8_t; };
+template <> struct VelCode<2> { using T = uint16_t; };
+
+// j = clamp(floor(v C + H), 0, 2H - 1), C = H / v_max, as vel_code
+template <int V>
+__device__ inline int vel_code_v(float v, float vmax) {
+#pragma clang fp contract(off)
+  constexpr double H = (double)(1 << (8 * V - 1));
+  if (vmax == 0.f) return (int)H;
+  double C = H / (double)vmax;
+  double t = (double)v * C;
+  t = t + H;
+  if (!(t >= 0.0)) return 0;
+  if (t >= 2.0 * H - 1.0) return (int)(2.0 * H - 1.0);
+  return (int)floor(t);
+}
+
+// Bin centre (j - H + 1/2) v_max / H, as vel_decode
+template <int V>
+__device__ inline float vel_decode_v(uint32_t j, float vmax) {
+#pragma clang fp contract(off)
+  constexpr double H = (double)(1 << (8 * V - 1));
+  double w = (double)vmax / H;
+  return (float)(((double)j - (H - 0.5)) * w);
+}
+
+// vel_code_v for a power-of-two v_max in [2^-90, 2^90] in float32, as vel_code_p2: the
+// float64 sum x + H rounds up to H exactly when -2^(log2 H - 54) <= x < 0. C = H / v_max.
+template <int V>
+__device__ inline int vel_code_p2_v(float v, float C) {
+#pragma clang fp contract(off)
+  constexpr float H = (float)(1 << (8 * V - 1));
+  constexpr float TIE = V == 2 ? 0x1p-39f : 0x1p-47f;
+  const float x = v * C;
+  float fl = floorf(x);
+  if (x < 0.f && x >= -TIE) fl = 0.f;
+  if (!(fl >= -H)) return 0;  // also NaN
+  if (fl >= H - 1.f) return (int)(2.f * H - 1.f);
+  return (int)fl + (int)H;
+}
+
+// vel_decode_v for v_max in [2^-90, 2^90] in float32, as vel_decode_w: w = v_max / H.
+template <int V>
+__device__ inline float vel_decode_w_v(uint32_t j, float w) {
+#pragma clang fp contract(off)
+  constexpr float H = (float)(1 << (8 * V - 1));
+  return ((float)j - (H - 0.5f)) * w;
+}
+
+// Call f(integral_constant P, integral_constant V) for the widths kind k.
+template <int N> using IC = std::integral_constant<int, N>;
+template <typename F>
+inline pm_status width_dispatch(int k, F&& f) {
+  switch (k) {
+    case 0: return f(IC<1>{}, IC<2>{});
+    case 1: return f(IC<2>{}, IC<2>{});
+    case 2: return f(IC<1>{}, IC<1>{});
+    case 3: return f(IC<2>{}, IC<1>{});
+  }
+  return PM_ERR_ARG;
+}
+
+// exclusive prefix of the stream bytes of each cell (count byte, escape, rb-byte records)
+pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_t* out,
+                            int64_t rb = 9);

@@ -75,10 +75,20 @@ __device__ inline void block_minmax_store(int jmin, int jmax, int32_t* pmn, int3
   }
 }
 
+// P position bytes, V velocity bytes per axis (P = 1, V = 2: the paper's format)
+template <int P, int V>
 __global__ __launch_bounds__(T256) void k_encode_gather(
     const float* x, const float* v, int64_t n, Geom g, const uint32_t* keys_sorted,
-    const uint32_t* idx_sorted, uint8_t* pos, uint16_t* vel, int64_t* perm,
+    const uint32_t* idx_sorted, void* pos_, void* vel_, int64_t* perm,
     uint32_t* run_start, pm_shdr* h, int32_t* pmn, int32_t* pmx) {
+  using PT = typename PosCode<P>::T;
+  using VT = typename VelCode<V>::T;
+  PT* pos = (PT*)pos_;
+  VT* vel = (VT*)vel_;
+  // S and S / L of the P-byte code (powers-of-two multiples of the 1-byte ones)
+  const int64_t S = g.S << (8 * (P - 1));
+  const double SL = P == 1 ? g.SL : g.SL * 256.0;
+  constexpr uint32_t OFF_MASK = (1u << (8 * P)) - 1u;
   int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
   int jmin = 65536, jmax = -1;
   if (j < n) {
@@ -87,10 +97,10 @@ __global__ __launch_bounds__(T256) void k_encode_gather(
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       uint32_t u;
-      pos_code(x[3 * (int64_t)p + a], g.SL, g.S, u);
-      pos[3 * j + a] = (uint8_t)(u & 255u);
-      int c = vel_code(v[3 * (int64_t)p + a], vmax);
-      vel[3 * j + a] = (uint16_t)c;
+      pos_code(x[3 * (int64_t)p + a], SL, S, u);
+      pos[3 * j + a] = (PT)(u & OFF_MASK);
+      int c = vel_code_v<V>(v[3 * (int64_t)p + a], vmax);
+      vel[3 * j + a] = (VT)c;
       jmin = min(jmin, c);
       jmax = max(jmax, c);
     }
@@ -164,9 +174,12 @@ __device__ inline int64_t find_cell(const int64_t* off, int64_t ncell, int64_t j
   return lo;
 }
 
-__global__ __launch_bounds__(T256) void k_decode(const uint8_t* pos, const uint16_t* vel,
+template <int P, int V>
+__global__ __launch_bounds__(T256) void k_decode(const void* pos_, const void* vel_,
                                                 const pm_shdr* h, const int64_t* off,
                                                 int64_t n, Geom g, float* x, float* v) {
+  const typename PosCode<P>::T* pos = (const typename PosCode<P>::T*)pos_;
+  const typename VelCode<V>::T* vel = (const typename VelCode<V>::T*)vel_;
   int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (j >= n) return;
   uint32_t cell[3];
@@ -174,9 +187,12 @@ __global__ __launch_bounds__(T256) void k_decode(const uint8_t* pos, const uint1
   float vmax = h->v_max;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    uint32_t u = (cell[a] << 8) | pos[3 * j + a];
-    x[3 * j + a] = pos_decode(u, g.LS);
-    v[3 * j + a] = vel_decode(vel[3 * j + a], vmax);
+    const uint32_t u = (cell[a] << (8 * P)) | pos[3 * j + a];
+    // 2-byte codes reach 2^26: the bin centre in float64, rounded once (as the 1-byte
+    // form's float32 arithmetic is exact)
+    x[3 * j + a] = P == 1 ? pos_decode(u, g.LS)
+                          : (float)(((double)u + 0.5) * ((double)g.LS * 0x1p-8));
+    v[3 * j + a] = vel_decode_v<V>(vel[3 * j + a], vmax);
   }
 }
 
@@ -195,9 +211,10 @@ __device__ inline void block_sum_store(uint64_t s, uint64_t* part) {
 
 struct GetPackBytes {
   const int64_t* off;
+  int64_t rb;  // record bytes: 3 (P + V)
   __device__ int64_t operator()(int64_t c) const {
     int64_t k = off[c + 1] - off[c];
-    return 1 + (k >= 255 ? 4 : 0) + 9 * k;
+    return 1 + (k >= 255 ? 4 : 0) + rb * k;
   }
 };
 
@@ -224,30 +241,37 @@ __global__ __launch_bounds__(T256) void k_pack_cells(const int64_t* off, const i
   block_sum_store(s, csum);
 }
 
-__global__ __launch_bounds__(T256) void k_pack_records(const uint8_t* pos, const uint16_t* vel,
+template <int P, int V>
+__global__ __launch_bounds__(T256) void k_pack_records(const void* pos_, const void* vel_,
                                                       const int64_t* off, const int64_t* boff,
                                                       int64_t n, int64_t ncell, uint8_t* body,
                                                       int64_t cap_body, uint64_t* csum) {
+  constexpr int RB = 3 * (P + V);  // record: x, y, z codes, then vx, vy, vz (little-endian)
+  const typename PosCode<P>::T* pos = (const typename PosCode<P>::T*)pos_;
+  const typename VelCode<V>::T* vel = (const typename VelCode<V>::T*)vel_;
   int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x;
   uint64_t s = 0;
   if (j < n && boff[ncell] <= cap_body) {
     int64_t c = find_cell(off, ncell, j);
     int64_t k = off[c + 1] - off[c];
-    int64_t o = boff[c] + (k >= 255 ? 5 : 1) + 9 * (j - off[c]);
+    int64_t o = boff[c] + (k >= 255 ? 5 : 1) + RB * (j - off[c]);
     // counts inconsistent with n (latched by the offset check): write nothing
-    if (o + 9 > boff[ncell]) o = -1;
-    uint8_t b[9];
-    b[0] = pos[3 * j];
-    b[1] = pos[3 * j + 1];
-    b[2] = pos[3 * j + 2];
+    if (o + RB > boff[ncell]) o = -1;
+    uint8_t b[RB];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      uint16_t w = vel[3 * j + a];
-      b[3 + 2 * a] = (uint8_t)(w & 255);
-      b[4 + 2 * a] = (uint8_t)(w >> 8);
+      const uint32_t w = pos[3 * j + a];
+#pragma unroll
+      for (int q = 0; q < P; ++q) b[P * a + q] = (uint8_t)((w >> (8 * q)) & 255u);
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int a = 0; a < 3; ++a) {
+      const uint32_t w = vel[3 * j + a];
+#pragma unroll
+      for (int q = 0; q < V; ++q) b[3 * P + V * a + q] = (uint8_t)((w >> (8 * q)) & 255u);
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
       if (o < 0) break;
       body[o + q] = b[q];
       s += (2ull * (uint64_t)(o + q) + 1ull) * b[q];
@@ -272,8 +296,8 @@ __global__ __launch_bounds__(1024) void k_fold_sum(uint64_t* csum, int64_t npart
 
 __global__ void k_pack_header(uint8_t* buf, int64_t cap, const int64_t* boff, int64_t ncell,
                               const uint64_t* csum, const pm_shdr* h, int32_t sid, int32_t B,
-                              int64_t n, int64_t nc, double mass, int64_t* used,
-                              DevErr* err) {
+                              int64_t n, int64_t nc, double mass, uint32_t widths,
+                              int64_t* used, DevErr* err) {
   int64_t body = boff[ncell];
   int64_t total = PM_STREAM_HEADER + body;
   *used = total;
@@ -288,7 +312,7 @@ __global__ void k_pack_header(uint8_t* buf, int64_t cap, const int64_t* boff, in
     for (int i = 0; i < len; ++i) hb[o + i] = q[i];
   };
   const char magic[4] = {'P', 'M', 'C', '1'};
-  uint32_t ver = 1, usid = (uint32_t)sid, ub = (uint32_t)B, zero = 0;
+  uint32_t ver = 1, usid = (uint32_t)sid, ub = (uint32_t)B;
   const uint64_t cs = *csum;
   uint64_t un = (uint64_t)n, unc = (uint64_t)nc, ubl = (uint64_t)body;
   float vmax = h->v_max;
@@ -299,7 +323,7 @@ __global__ void k_pack_header(uint8_t* buf, int64_t cap, const int64_t* boff, in
   put(16, &un, 8);
   put(24, &unc, 8);
   put(32, &vmax, 4);
-  put(36, &zero, 4);
+  put(36, &widths, 4);  // code widths, 0 for the paper's 1-byte positions, 2-byte velocities
   put(40, &mass, 8);
   put(48, &cs, 8);
   put(56, &ubl, 8);
@@ -357,12 +381,15 @@ __device__ inline void cic_accumulate(const float* acc, int64_t ng, const float 
       }
 }
 
+template <int P, int V>
 __global__ __launch_bounds__(T256) void k_reduce_particles(RedSpecies rs, const float* acc,
                                                           Geom g, double* part) {
   const pm_species& sp = rs.sp;
+  const typename PosCode<P>::T* pos = (const typename PosCode<P>::T*)sp.pos;
+  const typename VelCode<V>::T* vel = (const typename VelCode<V>::T*)sp.vel;
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const float fng = g.ngL;
-  const float rs_cell = (float)g.r / 256.f;  // mesh cells per position quantum
+  const float rs_cell = (float)g.r / 256.f;  // mesh cells per 1-byte position quantum
   for (int64_t j = (int64_t)blockIdx.x * T256 + threadIdx.x; j < sp.n;
        j += (int64_t)gridDim.x * T256) {
     float xm[3];
@@ -378,9 +405,12 @@ __global__ __launch_bounds__(T256) void k_reduce_particles(RedSpecies rs, const 
       const float vmax = sp.hdr->v_max;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        s[a] += (double)vel_decode(sp.vel[3 * j + a], vmax);
-        const uint32_t u = (cell[a] << 8) | sp.pos[3 * j + a];
-        xm[a] = ((float)u + 0.5f) * rs_cell;  // bin centre in mesh units, exact
+        s[a] += (double)vel_decode_v<V>(vel[3 * j + a], vmax);
+        const uint32_t u = (cell[a] << (8 * P)) | pos[3 * j + a];
+        // bin centre in mesh units: exact in float32 for 1-byte codes, in float64 (then
+        // rounded once) for 2-byte codes
+        xm[a] = P == 1 ? ((float)u + 0.5f) * rs_cell
+                       : (float)(((double)u + 0.5) * ((double)g.r * 0x1p-16));
       }
     }
     if (acc) cic_accumulate(acc, g.ng, xm, s + 3);
@@ -497,8 +527,14 @@ pm_status run_encode(pm_context* c, const pm_species* in, pm_species* out, int64
     int32_t* part = (int32_t*)scratch(c, SC_PARTS, (size_t)nb * 8);
     uint32_t* rstart = (uint32_t*)scratch(c, SC_FLAG, (size_t)g.ncell3 * 4);
     if (!part || !rstart) return PM_ERR_NOMEM;
-    hipLaunchKernelGGL(k_encode_gather, dim3(nbk), dim3(T256), 0, c->stream, in->x, in->v, n,
-                       g, ka, va, out->pos, out->vel, perm, rstart, out->hdr, part, part + nb);
+    s = width_dispatch(width_kind(*out), [&](auto P_, auto V_) {
+      hipLaunchKernelGGL((k_encode_gather<decltype(P_)::value, decltype(V_)::value>),
+                         dim3(nbk), dim3(T256), 0, c->stream, in->x, in->v, n, g, ka, va,
+                         (void*)out->pos, (void*)out->vel, perm, rstart, out->hdr, part,
+                         part + nb);
+      return PM_OK;
+    });
+    if (s != PM_OK) return s;
     PM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_run_counts, dim3(nbk), dim3(T256), 0, c->stream, ka, n, rstart, cnt32);
     PM_LAUNCH_CHECK();
@@ -513,8 +549,14 @@ pm_status run_decode(pm_context* c, const pm_species* in, pm_species* out) {
   if (!off) return PM_ERR_NOMEM;
   pm_status s = run_cell_offsets(c, in, off);
   if (s != PM_OK || n == 0) return s;
-  hipLaunchKernelGGL(k_decode, dim3((unsigned)cdiv(n, T256)), dim3(T256), 0, c->stream,
-                     in->pos, in->vel, in->hdr, off, n, c->g, out->x, out->v);
+  s = width_dispatch(width_kind(*in), [&](auto P_, auto V_) {
+    hipLaunchKernelGGL((k_decode<decltype(P_)::value, decltype(V_)::value>),
+                       dim3((unsigned)cdiv(n, T256)), dim3(T256), 0, c->stream,
+                       (const void*)in->pos, (const void*)in->vel, in->hdr, off, n, c->g,
+                       out->x, out->v);
+    return PM_OK;
+  });
+  if (s != PM_OK) return s;
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -529,26 +571,34 @@ pm_status run_pack(pm_context* c, const pm_species* sp, int32_t sid, uint8_t* bu
   if (!off || !boff || !csum) return PM_ERR_NOMEM;
   pm_status s = run_cell_offsets(c, sp, off);
   if (s != PM_OK) return s;
-  s = scan_generic_pack(c, off, nc3, boff);
+  const int64_t rb = 3 * (width_pos(*sp) + width_vel(*sp));
+  s = scan_generic_pack(c, off, nc3, boff, rb);
   if (s != PM_OK) return s;
   int64_t cap_body = cap - PM_STREAM_HEADER;
   uint8_t* body = buf + PM_STREAM_HEADER;
   hipLaunchKernelGGL(k_pack_cells, dim3((unsigned)nbc), dim3(T256), 0, c->stream,
                      off, boff, nc3, body, cap_body, csum);
-  if (nbr > 0)
-    hipLaunchKernelGGL(k_pack_records, dim3((unsigned)nbr), dim3(T256), 0,
-                       c->stream, sp->pos, sp->vel, off, boff, sp->n, nc3, body, cap_body,
-                       csum + nbc);
+  if (nbr > 0) {
+    s = width_dispatch(width_kind(*sp), [&](auto P_, auto V_) {
+      hipLaunchKernelGGL((k_pack_records<decltype(P_)::value, decltype(V_)::value>),
+                         dim3((unsigned)nbr), dim3(T256), 0, c->stream, (const void*)sp->pos,
+                         (const void*)sp->vel, off, boff, sp->n, nc3, body, cap_body,
+                         csum + nbc);
+      return PM_OK;
+    });
+    if (s != PM_OK) return s;
+  }
   hipLaunchKernelGGL(k_fold_sum, dim3(1), dim3(1024), 0, c->stream, csum, nbc + nbr);
   hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, c->stream, buf, cap, boff, nc3,
-                     csum + nbc + nbr, sp->hdr, sid, c->g.B, sp->n, c->g.nc, sp->mass, used,
-                     c->err);
+                     csum + nbc + nbr, sp->hdr, sid, c->g.B, sp->n, c->g.nc, sp->mass,
+                     (uint32_t)sp->widths, used, c->err);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
 
-pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_t* out) {
-  return scan_generic(c, GetPackBytes{off}, n, out);
+pm_status scan_generic_pack(pm_context* c, const int64_t* off, int64_t n, int64_t* out,
+                            int64_t rb) {
+  return scan_generic(c, GetPackBytes{off, rb}, n, out);
 }
 
 namespace {
@@ -581,8 +631,14 @@ pm_status reduce_core(pm_context* c, const pm_species* sp, int n_sp, const float
       if (st != PM_OK) return st;
       rs.off = off;
     }
-    hipLaunchKernelGGL(k_reduce_particles, dim3(RED_BLOCKS), dim3(T256), 0, c->stream, rs,
-                       acc, c->g, ppart + 6 * (int64_t)s * RED_BLOCKS);
+    double* pp = ppart + 6 * (int64_t)s * RED_BLOCKS;
+    const int kind = sp[s].layout == PM_COMPRESSED ? width_kind(sp[s]) : 0;
+    pm_status st = width_dispatch(kind, [&](auto P_, auto V_) {
+      hipLaunchKernelGGL((k_reduce_particles<decltype(P_)::value, decltype(V_)::value>),
+                         dim3(RED_BLOCKS), dim3(T256), 0, c->stream, rs, acc, c->g, pp);
+      return PM_OK;
+    });
+    if (st != PM_OK) return st;
   }
   const double dv = c->g.box * c->g.box * c->g.box / ((double)c->g.ng * c->g.ng * c->g.ng);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1), 0, c->stream, pmesh, nmp, dv, ppart,

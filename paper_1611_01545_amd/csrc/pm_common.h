@@ -82,6 +82,27 @@ __host__ __device__ inline void key_cell(const Geom& g, uint32_t key, uint32_t& 
   cz = ((b >> (2 * g.lgnb)) << g.lgB) + (l >> (2 * g.lgB));
 }
 
+// Code widths of a compressed species (pm_species.widths): 0 is the paper's 1-byte
+// positions and 2-byte velocities, otherwise P | V << 8 with P, V in {1, 2}.
+inline int width_pos(const pm_species& s) { return s.widths == 0 ? 1 : (s.widths & 255); }
+inline int width_vel(const pm_species& s) { return s.widths == 0 ? 2 : (s.widths >> 8); }
+// kind 0: (1, 2), 1: (2, 2), 2: (1, 1), 3: (2, 1)
+inline int width_kind(const pm_species& s) {
+  return (width_pos(s) - 1) | ((2 - width_vel(s)) << 1);
+}
+inline bool widths_valid(int32_t w) {
+  if (w == 0) return true;
+  const int p = w & 255, v = w >> 8;
+  return (p == 1 || p == 2) && (v == 1 || v == 2) && w != (1 | (2 << 8));
+}
+// the one widths kind of the species of a call, or -1 when they differ
+inline int common_width_kind(const pm_species* sp, int n_sp) {
+  const int k = width_kind(sp[0]);
+  for (int i = 1; i < n_sp; ++i)
+    if (width_kind(sp[i]) != k) return -1;
+  return k;
+}
+
 // --------------------------------------------------------------- scratch pool --
 struct DevBuf {
   void* p = nullptr;

@@ -33,7 +33,7 @@ constexpr int MAX_SP = 4;
 
 struct DepSpecies {
   int64_t n;           // particles (bounds guard against inconsistent counts)
-  const uint8_t* pos;
+  const void* pos;     // position codes, P bytes per axis
   const int64_t* off;  // [ncell3 + 1]
   double unit;         // density per weight unit 2^-27: m_s n_g^3 2^-27
 };
@@ -52,8 +52,16 @@ __host__ __device__ inline size_t dep_cst_offset(int R3) {
 
 __device__ inline int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-template <int TT>  // tile side in cells (compile time, 0: runtime A.T)
+// TT: tile side in cells (compile time, 0: runtime A.T); PB: position bytes per axis. With
+// PB = 2 the offset inside a cell has 17 fractional bits of a mesh cell per axis, and each
+// node's weight (the exact product, a multiple of 2^-51) is rounded to a multiple of
+// 2^-27, the unit of the 1-byte form, so that the same integer sums apply.
+template <int TT, int PB = 1>
 __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g, float* rho) {
+  using PT = typename PosCode<PB>::T;
+  constexpr int FB = 8 * PB + 1;              // fractional bits of a mesh coordinate
+  constexpr int ONE = 1 << FB;                // one mesh cell
+  constexpr uint32_t FMASK = (uint32_t)ONE - 1u;
   extern __shared__ unsigned char smem[];
   // compile-time tiles have T r = 16 nodes per side (T = 16 / r)
   const int T = TT ? TT : A.T, R = TT ? 16 : A.R, r = TT ? 16 / TT : A.r;
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int a = 0; a < 3; ++a) pb[u][a] = sp.pos[3 * ju[u] + a];
+          for (int a = 0; a < 3; ++a) pb[u][a] = ((const PT*)sp.pos)[3 * ju[u] + a];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (!ok[u]) continue;
@@ -154,26 +162,33 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
           const int le[3] = {ex - 1, ey - 1, ez - 1};
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            int gl = (2 * (int)pb[u][a] + 1) * r;  // position inside the cell, 1/512 mesh cell
-            li[a] = le[a] * r + (gl >> 9);
-            f[a] = gl & 511;
+            // position inside the cell in units of 2^-FB mesh cells (1/512 for PB = 1)
+            int gl = (2 * (int)pb[u][a] + 1) * r;
+            li[a] = le[a] * r + (gl >> FB);
+            f[a] = (int)((uint32_t)gl & FMASK);
           }
 #pragma unroll
           for (int dz = 0; dz < 2; ++dz) {
             int nz = li[2] + dz;
-            int wz = dz ? f[2] : 512 - f[2];
+            int wz = dz ? f[2] : ONE - f[2];
             if (nz < 0 || nz >= R || wz == 0) continue;
 #pragma unroll
             for (int dy = 0; dy < 2; ++dy) {
               int ny = li[1] + dy;
-              int wy = dy ? f[1] : 512 - f[1];
+              int wy = dy ? f[1] : ONE - f[1];
               if (ny < 0 || ny >= R || wy == 0) continue;
 #pragma unroll
               for (int dx = 0; dx < 2; ++dx) {
                 int nx = li[0] + dx;
-                int wx = dx ? f[0] : 512 - f[0];
+                int wx = dx ? f[0] : ONE - f[0];
                 if (nx < 0 || nx >= R || wx == 0) continue;
-                const uint32_t W = (uint32_t)(wx * wy) * (uint32_t)wz;  // exact, 2^-27
+                uint32_t W;  // units of 2^-27
+                if constexpr (PB == 1) {
+                  W = (uint32_t)(wx * wy) * (uint32_t)wz;  // exact
+                } else {
+                  const uint64_t w3 = (uint64_t)wx * (uint64_t)wy * (uint64_t)wz;
+                  W = (uint32_t)((w3 + (1ull << 23)) >> 24);  // 2^-51 -> 2^-27, rounded
+                }
                 const int i = (nz * R + ny) * R + nx;
                 const uint32_t old = atomicAdd(&wlo[i], W);
                 if (old > 0xffffffffu - W) atomicAdd(&whi[i >> 1], 1u << ((i & 1) * 16));
@@ -297,13 +312,24 @@ pm_status run_deposit_tile(pm_context* c, const pm_species* sp, int n_sp,
   size_t lds = dep_cst_offset(A.R * A.R * A.R) + ne * 8 + (ne + 1) * 4;
   ProfScope ps(c, ST_DEPOSIT);
   const dim3 grid((unsigned)((int64_t)nt * nt * nt));
-  // the compile-time variants assume T r = 16
-  if (A.T == 4 && A.r == 4)
-    hipLaunchKernelGGL(k_deposit_tile<4>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
-  else if (A.T == 8 && A.r == 2)
-    hipLaunchKernelGGL(k_deposit_tile<8>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
-  else
-    hipLaunchKernelGGL(k_deposit_tile<0>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
+  // the compile-time variants assume T r = 16; one position width for every species
+  const int kind = common_width_kind(sp, n_sp);
+  if (kind < 0) return PM_ERR_ARG;
+  if (width_pos(sp[0]) == 1) {
+    if (A.T == 4 && A.r == 4)
+      hipLaunchKernelGGL(k_deposit_tile<4>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
+    else if (A.T == 8 && A.r == 2)
+      hipLaunchKernelGGL(k_deposit_tile<8>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
+    else
+      hipLaunchKernelGGL(k_deposit_tile<0>, grid, dim3(DEP_THREADS), lds, c->stream, A, g, rho);
+  } else {
+    if (A.T == 4 && A.r == 4)
+      hipLaunchKernelGGL((k_deposit_tile<4, 2>), grid, dim3(DEP_THREADS), lds, c->stream, A, g,
+                         rho);
+    else
+      hipLaunchKernelGGL((k_deposit_tile<0, 2>), grid, dim3(DEP_THREADS), lds, c->stream, A, g,
+                         rho);
+  }
   PM_LAUNCH_CHECK();
   return PM_OK;
 }

@@ -80,12 +80,13 @@ __global__ __launch_bounds__(KT) void k_kick_float(const float* x, const float* 
 }
 
 // ------------------------------------------------------- compressed layout --
+template <int VB = 2>  // velocity bytes per axis
 __global__ void k_vmax_next(const pm_shdr* hin, pm_shdr* hout, const float* amax, double ck,
                             int64_t n) {
   double V = 0.0;
   if (n > 0 && hin->j_max >= 0) {
-    double a = fabs((double)vel_decode((uint32_t)hin->j_min, hin->v_max));
-    double b = fabs((double)vel_decode((uint32_t)hin->j_max, hin->v_max));
+    double a = fabs((double)vel_decode_v<VB>((uint32_t)hin->j_min, hin->v_max));
+    double b = fabs((double)vel_decode_v<VB>((uint32_t)hin->j_max, hin->v_max));
     V = a > b ? a : b;
   }
   double bound = V + fabs(ck) * (double)(*amax);
@@ -109,13 +110,13 @@ constexpr int MAXSP = 4;
 
 struct KickSpecies {
   int64_t n;
-  const uint8_t* pos;
-  const uint16_t* vel;
+  const void* pos;     // position codes, P bytes per axis
+  const void* vel;     // velocity codes, V bytes per axis
   const pm_shdr* hin;
   pm_shdr* hout;
   const int64_t* off;  // input cell offsets [ncell3 + 1]
-  uint8_t* tpos;       // new codes, old stream order
-  uint16_t* tvel;
+  void* tpos;          // new codes, old stream order
+  void* tvel;
   uint16_t* tdig;      // new local cell in the brick, or B^3 for movers
   uint32_t* mkey;      // movers: new cell key, at the old stream index
   uint64_t* cnt;       // per cell: stayers (low 32 bits)
@@ -132,16 +133,19 @@ struct KickArgs {
   double cdS;        // c_d S / L (position codes per unit velocity)
 };
 
-// Codec constants of one species (uniform).
+// Codec constants of one species (uniform), V velocity bytes per axis (half range
+// H = 2^(8V - 1)): wd = v_max / H, ce = H / v_max' (v_max' a power of two: exponent
+// field of 2^(8V - 1 - e) is 253 + 8V minus that of v_max').
 struct Codec {
   float vmi, vmo, wd, ce;
 };
+template <int V>
 __device__ inline Codec codec_of(const KickSpecies& S) {
   Codec k;
   k.vmi = S.hin->v_max;
   k.vmo = S.hout->v_max;
-  k.wd = k.vmi * 0x1p-15f;
-  k.ce = __uint_as_float((269u - (__float_as_uint(k.vmo) >> 23)) << 23);  // 2^15 / v_max'
+  k.wd = k.vmi * (V == 2 ? 0x1p-15f : 0x1p-7f);
+  k.ce = __uint_as_float(((253u + 8u * V) - (__float_as_uint(k.vmo) >> 23)) << 23);
   return k;
 }
 // float32 codec forms valid for every species (see vel_code_p2, vel_decode_w)
@@ -161,12 +165,18 @@ __device__ inline bool codec_fast(const KickArgs& A) {
 // particle's digit (new local cell, or B^3 when it leaves the brick; movers also get
 // their new cell key), counts stayers per new cell and movers in LDS, and folds the
 // wave's extreme velocity codes into smm. No barrier: waves are independent.
-template <bool FAST, typename Gather>
+// P position bytes and V velocity bytes per axis (P = 1, V = 2: the paper's format).
+template <bool FAST, int P, int V, typename Gather>
 __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const Geom& g,
                                   const Codec& cd, int64_t jc, int64_t jend, int64_t l0,
                                   const uint32_t* rel, int lo0, int hi0, const uint32_t bc[3],
                                   uint32_t* run, uint32_t* mvc, int* smm, bool& bad,
                                   Gather gather) {
+  using PC = typename PosCode<P>::T;
+  using VC = typename VelCode<V>::T;
+  constexpr int SH = 8 * P, FB = 8 * P + 1;  // offset bits, fractional bits of a mesh cell
+  constexpr uint32_t FMASK = (1u << FB) - 1u, OMASK = (1u << SH) - 1u;
+  constexpr float UNIT = 1.0f / (float)(1u << FB);
   const int lane = threadIdx.x & 63;
   const int64_t j = jc + lane;
   const int B3 = g.B * g.B * g.B;
@@ -174,8 +184,8 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
   int jmn = 65536, jmx = -1;
   if (j < jend) {
     const uint32_t t3 = 3 * (uint32_t)lane;
-    const uint8_t* pp = S.pos + 3 * jc;
-    const uint16_t* vp = S.vel + 3 * jc;
+    const PC* pp = (const PC*)S.pos + 3 * jc;
+    const VC* vp = (const VC*)S.vel + 3 * jc;
     uint32_t pb[3], vc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -194,10 +204,10 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
     float f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      // position in 1/512 mesh cells from the brick's corner node: (2 u + 1) r
-      const uint32_t gl = (2 * ((lc[a] << 8) | pb[a]) + 1) * (uint32_t)g.r;
-      li[a] = (int)(gl >> 9);
-      f[a] = (float)(gl & 511u) * (1.0f / 512.0f);
+      // position in 2^-FB mesh cells (1/512 for P = 1) from the brick's corner node
+      const uint32_t gl = (2 * ((lc[a] << SH) | pb[a]) + 1) * (uint32_t)g.r;
+      li[a] = (int)(gl >> FB);
+      f[a] = (float)(gl & FMASK) * UNIT;
     }
     float acc3[3];
     gather(li, f, acc3);
@@ -205,25 +215,26 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
 #pragma unroll
       for (int a = 0; a < 3; ++a) acc3[a] += S.app[3 * j + a];
     }
-    const uint32_t Sm = (uint32_t)g.S - 1;
-    const double Sd = (double)g.S, invS = 1.0 / Sd;  // powers of two
-    uint8_t* tp = S.tpos + 3 * jc;
-    uint16_t* tv = S.tvel + 3 * jc;
+    const int64_t SP = g.S << (8 * (P - 1));  // position steps per box side
+    const uint32_t Sm = (uint32_t)SP - 1;
+    const double Sd = (double)SP, invS = 1.0 / Sd;  // powers of two
+    PC* tp = (PC*)S.tpos + 3 * jc;
+    VC* tv = (VC*)S.tvel + 3 * jc;
     uint32_t un[3], nl[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float v0 = FAST ? vel_decode_w(vc[a], cd.wd) : vel_decode(vc[a], cd.vmi);
+      const float v0 = FAST ? vel_decode_w_v<V>(vc[a], cd.wd) : vel_decode_v<V>(vc[a], cd.vmi);
       const float v1 = v0 + A.ck * acc3[a];
       const double d = floor((double)v1 * A.cdS + 0.5);
       const bool okd = fabs(d) < 4.0e15;
       bad |= !okd;
       // d mod S, exact in float64 (d is an integer below 2^52, S a power of two)
       const double dm = okd ? d - Sd * floor(d * invS) : 0.0;
-      un[a] = ((((bc[a] + lc[a]) << 8) | pb[a]) + (uint32_t)dm) & Sm;
-      nl[a] = (un[a] >> 8) - bc[a];  // new local cell (wraps above B when outside)
-      const int jv = FAST ? vel_code_p2(v1, cd.ce) : vel_code(v1, cd.vmo);
-      tp[t3 + a] = (uint8_t)(un[a] & 255u);
-      tv[t3 + a] = (uint16_t)jv;
+      un[a] = ((((bc[a] + lc[a]) << SH) | pb[a]) + (uint32_t)dm) & Sm;
+      nl[a] = (un[a] >> SH) - bc[a];  // new local cell (wraps above B when outside)
+      const int jv = FAST ? vel_code_p2_v<V>(v1, cd.ce) : vel_code_v<V>(v1, cd.vmo);
+      tp[t3 + a] = (PC)(un[a] & OMASK);
+      tv[t3 + a] = (VC)jv;
       jmn = min(jmn, jv);
       jmx = max(jmx, jv);
     }
@@ -233,7 +244,7 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
       atomicAdd(&run[digit], 1u);
     } else {
       S.tdig[j] = (uint16_t)B3;
-      S.mkey[j] = cell_key(g, un[0] >> 8, un[1] >> 8, un[2] >> 8);
+      S.mkey[j] = cell_key(g, un[0] >> SH, un[1] >> SH, un[2] >> SH);
       atomicAdd(mvc, 1u);
     }
   }
@@ -259,7 +270,8 @@ struct Seg {
 // ---- one brick per workgroup (any shape; R = B r nodes per side) ----
 // With STAGE the brick's force nodes [b R, b R + R]^3 are copied to LDS first and every
 // particle gathers its 8 CIC nodes from there.
-template <int RS>  // staged tile side in nodes (compile time), or 0: gather from HBM
+// RS: staged tile side in nodes (compile time), or 0: gather from HBM; P, V: code widths
+template <int RS, int P = 1, int V = 2>
 __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* err) {
   constexpr bool STAGE = RS > 0;
   const int B = g.B, B3 = B * B * B, L = B3 + 1;
@@ -399,12 +411,12 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       const int64_t l0 = l0s[s];
       const int64_t j0 = min(l0, S.n), j1 = min(l0 + (int64_t)rel[s * L + B3], S.n);
       const int64_t nch = j1 > j0 ? (j1 - j0 + 63) >> 6 : 0;
-      const Codec cd = codec_of(S);
+      const Codec cd = codec_of<V>(S);
       // this wave's chunks of species s: global chunk index = cbase + c, dealt round-robin
       int64_t c = ((int64_t)w - cbase) % NWK;
       if (c < 0) c += NWK;
       for (; c < nch; c += NWK)
-        kick_chunk<FAST>(S, A, g, cd, j0 + 64 * c, j1, l0, rel + s * L, 0, B3, bc,
+        kick_chunk<FAST, P, V>(S, A, g, cd, j0 + 64 * c, j1, l0, rel + s * L, 0, B3, bc,
                          run + s * L, &mvc[s], &smm[2 * s], bad, gather);
       cbase += nch;
     }
@@ -435,7 +447,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
 // and 256 threads the tile is 34 KB and four workgroups share a CU, each staging while
 // the others compute.
 constexpr int PR = 16;
-template <int NT, int NZ>  // threads per workgroup, z passes
+template <int NT, int NZ, int P = 1, int V = 2>  // threads per workgroup, z passes, widths
 __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
   constexpr int KB = NT, NWK = NT / 64;
   constexpr int X1 = 2 * PR + 1, Y1 = PR + 1, Z1 = PR / NZ + 1;
@@ -599,11 +611,11 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
         const int64_t j0 = min(l0 + (int64_t)rs[h * H], S.n);
         const int64_t j1 = min(l0 + (int64_t)rs[(h + 1) * H], S.n);
         const int64_t nch = j1 > j0 ? (j1 - j0 + 63) >> 6 : 0;
-        const Codec cd = codec_of(S);
+        const Codec cd = codec_of<V>(S);
         int64_t c = ((int64_t)w - cbase) % NWK;
         if (c < 0) c += NWK;
         for (; c < nch; c += NWK)
-          kick_chunk<FAST>(S, A, g, cd, j0 + 64 * c, j1, l0, rs, h * H, (h + 1) * H, bc,
+          kick_chunk<FAST, P, V>(S, A, g, cd, j0 + 64 * c, j1, l0, rs, h * H, (h + 1) * H, bc,
                            run + (k * MAXSP + s) * L, &mvc[k * MAXSP + s], &smm[2 * s], bad,
                            gather);
         cbase += nch;
@@ -713,11 +725,18 @@ __global__ __launch_bounds__(64 * WB) void k_compact_movers(
 // brick's stayers in each new cell (cell offset + arrivals from earlier bricks), plus
 // the stayer's rank among the brick's stayers of that cell in old stream order (a
 // stable multi-split of each chunk by digit and a running count per cell).
+template <int P = 1, int V = 2>  // code widths
 __global__ __launch_bounds__(64 * WB) void k_place_stayers(
-    const int64_t* off_in, const uint16_t* tdig, const uint8_t* tpos, const uint16_t* tvel,
+    const int64_t* off_in, const uint16_t* tdig, const void* tpos_, const void* tvel_,
     const uint64_t* cnt, const int64_t* off_new, int B3, int nbits, int64_t nbrick,
     const uint32_t* skey, const uint32_t* sidx, const int64_t* astart,
-    uint8_t* pos, uint16_t* vel, int64_t* perm, int64_t n, DevErr* err) {
+    void* pos_, void* vel_, int64_t* perm, int64_t n, DevErr* err) {
+  using PC = typename PosCode<P>::T;
+  using VC = typename VelCode<V>::T;
+  const PC* tpos = (const PC*)tpos_;
+  const VC* tvel = (const VC*)tvel_;
+  PC* pos = (PC*)pos_;
+  VC* vel = (VC*)vel_;
   extern __shared__ int64_t lds[];  // dbase [WB][B3], then run [WB][B3] (uint32)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int64_t* dbase = lds + (int64_t)wv * B3;
@@ -775,8 +794,8 @@ __global__ __launch_bounds__(64 * WB) void k_place_stayers(
         } else {
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            pos[3 * dst + a] = (uint8_t)p[u][a];
-            vel[3 * dst + a] = (uint16_t)v[u][a];
+            pos[3 * dst + a] = (PC)p[u][a];
+            vel[3 * dst + a] = (VC)v[u][a];
           }
           if (perm) perm[dst] = j;
         }
@@ -829,11 +848,12 @@ pm_status run_kick_float(pm_context* c, const pm_species* in, pm_species* out,
 
 // All species of a compressed state: one brick kernel launch, then the re-sort of each
 // species. offs[s]: input cell offsets; perm[s] (device int64 [n], nullable): new stream
-// position -> old stream position.
-pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
-                                  int n_sp, int64_t* const* offs, const float* acc,
-                                  const float* amax, double ck, double cd,
-                                  int64_t* const* perm, const float* const* app) {
+// position -> old stream position. P, V: the species' code widths.
+template <int P, int V>
+static pm_status kick_compressed_t(pm_context* c, const pm_species* in, pm_species* out,
+                                   int n_sp, int64_t* const* offs, const float* acc,
+                                   const float* amax, double ck, double cd,
+                                   int64_t* const* perm, const float* const* app) {
   const Geom& g = c->g;
   if (n_sp <= 0 || n_sp > MAXSP) return PM_ERR_ARG;
   const int B3 = g.B * g.B * g.B;
@@ -846,8 +866,8 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
   const size_t nn = (size_t)(ntot > 0 ? ntot : 1);
   uint64_t* cnt = (uint64_t*)scratch(c, SC_CNT, (size_t)g.ncell3 * 8 * n_sp);
   int64_t* off_new = (int64_t*)scratch(c, SC_OFF2, (size_t)(g.ncell3 + 1) * 8);
-  uint8_t* tpos = (uint8_t*)scratch(c, SC_TPOS, nn * 3);
-  uint16_t* tvel = (uint16_t*)scratch(c, SC_TVEL, nn * 6);
+  char* tpos = (char*)scratch(c, SC_TPOS, nn * 3 * P);
+  char* tvel = (char*)scratch(c, SC_TVEL, nn * 3 * V);
   uint16_t* tdig = (uint16_t*)scratch(c, SC_TDST, nn * 2);
   uint32_t* mkey = (uint32_t*)scratch(c, SC_KEYA, nn * 4);
   uint32_t* midx = (uint32_t*)scratch(c, SC_VALA, nn * 4);
@@ -863,7 +883,7 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
   A.n_sp = n_sp;
   A.acc = acc;
   A.ck = (float)ck;
-  A.cdS = cd * g.SL;
+  A.cdS = cd * g.SL * (P == 1 ? 1.0 : 256.0);
   for (int s = 0; s < n_sp; ++s) {
     KickSpecies& S = A.sp[s];
     S.n = in[s].n;
@@ -872,8 +892,8 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     S.hin = in[s].hdr;
     S.hout = out[s].hdr;
     S.off = offs[s];
-    S.tpos = tpos + 3 * nbase[s];
-    S.tvel = tvel + 3 * nbase[s];
+    S.tpos = tpos + 3 * P * nbase[s];
+    S.tvel = tvel + 3 * V * nbase[s];
     S.tdig = tdig + nbase[s];
     S.cnt = cnt + (int64_t)s * g.ncell3;
     S.mkey = mkey + nbase[s];
@@ -885,8 +905,8 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
   {
     pm_status st0;
     for (int s = 0; s < n_sp; ++s)
-      hipLaunchKernelGGL(k_vmax_next, dim3(1), dim3(1), 0, c->stream, in[s].hdr, out[s].hdr,
-                         amax, ck, in[s].n);
+      hipLaunchKernelGGL(k_vmax_next<V>, dim3(1), dim3(1), 0, c->stream, in[s].hdr,
+                         out[s].hdr, amax, ck, in[s].n);
     ProfScope ps(c, ST_KICK);
     const int R = g.B * g.r;
     const size_t tail = (size_t)MAXSP * (B3 + 1) * 4 * 2;
@@ -895,16 +915,16 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     const size_t pbytes = (size_t)3 * (2 * PR + 1) * (PR + 1) * (PR / 4 + 1) * 4 + 2 * tail;
     const size_t fbytes = (size_t)3 * (R + 1) * (R + 1) * (R + 1) * 4;
     if (R == PR && g.lgnb >= 1 && (g.B % 4) == 0 && pbytes <= 48 * 1024)
-      hipLaunchKernelGGL((k_kick_pair<256, 4>), dim3((unsigned)(g.nbrick / 2)), dim3(256),
-                         pbytes, c->stream, A, g, c->err);
+      hipLaunchKernelGGL((k_kick_pair<256, 4, P, V>), dim3((unsigned)(g.nbrick / 2)),
+                         dim3(256), pbytes, c->stream, A, g, c->err);
     else if (R == 16 && fbytes + tail <= 96 * 1024)
-      hipLaunchKernelGGL(k_kick_brick<16>, dim3((unsigned)g.nbrick), dim3(KB), fbytes + tail,
-                         c->stream, A, g, c->err);
+      hipLaunchKernelGGL((k_kick_brick<16, P, V>), dim3((unsigned)g.nbrick), dim3(KB),
+                         fbytes + tail, c->stream, A, g, c->err);
     else if (R == 8)
-      hipLaunchKernelGGL(k_kick_brick<8>, dim3((unsigned)g.nbrick), dim3(KB), fbytes + tail,
-                         c->stream, A, g, c->err);
+      hipLaunchKernelGGL((k_kick_brick<8, P, V>), dim3((unsigned)g.nbrick), dim3(KB),
+                         fbytes + tail, c->stream, A, g, c->err);
     else
-      hipLaunchKernelGGL(k_kick_brick<0>, dim3((unsigned)g.nbrick), dim3(KB), tail,
+      hipLaunchKernelGGL((k_kick_brick<0, P, V>), dim3((unsigned)g.nbrick), dim3(KB), tail,
                          c->stream, A, g, c->err);
     PM_LAUNCH_CHECK();
     prof_end(c);  // the scope covers the brick kernel only
@@ -951,15 +971,29 @@ pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_specie
     st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
-    hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)cdiv(g.nbrick, WB)), dim3(64 * WB),
-                       place_lds, c->stream, S.off, S.tdig, S.tpos, S.tvel, S.cnt, off_new,
-                       B3, 3 * g.lgB, g.nbrick, sk, si, moff, out[s].pos, out[s].vel, pm, n,
-                       c->err);
+    hipLaunchKernelGGL((k_place_stayers<P, V>), dim3((unsigned)cdiv(g.nbrick, WB)),
+                       dim3(64 * WB), place_lds, c->stream, S.off, S.tdig,
+                       (const void*)S.tpos, (const void*)S.tvel, S.cnt, off_new, B3,
+                       3 * g.lgB, g.nbrick, sk, si, moff, (void*)out[s].pos,
+                       (void*)out[s].vel, pm, n, c->err);
     PM_LAUNCH_CHECK();
     st = run_finalize_counts(c, nullptr, S.cnt, &out[s]);
     if (st != PM_OK) return st;
   }
   return PM_OK;
+}
+
+pm_status run_kick_compressed_all(pm_context* c, const pm_species* in, pm_species* out,
+                                  int n_sp, int64_t* const* offs, const float* acc,
+                                  const float* amax, double ck, double cd,
+                                  int64_t* const* perm, const float* const* app) {
+  if (n_sp <= 0 || n_sp > MAXSP) return PM_ERR_ARG;
+  const int kind = common_width_kind(in, n_sp);
+  if (kind < 0) return PM_ERR_ARG;
+  return width_dispatch(kind, [&](auto P_, auto V_) {
+    return kick_compressed_t<decltype(P_)::value, decltype(V_)::value>(
+        c, in, out, n_sp, offs, acc, amax, ck, cd, perm, app);
+  });
 }
 
 pm_status run_kick_compressed(pm_context* c, const pm_species* in, pm_species* out,

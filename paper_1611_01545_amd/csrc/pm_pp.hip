@@ -21,7 +21,7 @@ constexpr int PMAXSP = 4;
 
 struct PPSpecies {
   int64_t n;
-  const uint8_t* pos;
+  const void* pos;     // position codes, P bytes per axis
   const int64_t* off;  // cell offsets [ncell3 + 1]
   float mass;
   float* app;          // [n][3] accelerations, stream order
@@ -43,37 +43,44 @@ __device__ inline int64_t pp_find_cell(const int64_t* off, int64_t ncell, int64_
   return lo;
 }
 
+// P: position bytes per axis (codes u = cell 256^P + offset; (2u + 1) r < 2^28)
+template <int P>
 __global__ __launch_bounds__(PT) void k_pp_accel(PPArgs A, Geom g, uint32_t* part) {
+  using PC = typename PosCode<P>::T;
+  using DT = typename std::conditional<P == 1, int, int64_t>::type;  // code differences
+  constexpr int SH = 8 * P, FB = 8 * P + 1;
   const int s = blockIdx.y;
   const PPSpecies& S = A.sp[s];
+  const PC* spos = (const PC*)S.pos;
   const int64_t i = (int64_t)blockIdx.x * PT + threadIdx.x;
   float m = 0.f;
   if (i < S.n) {
     const int64_t key = pp_find_cell(S.off, g.ncell3, i);
     uint32_t cx, cy, cz;
     key_cell(g, (uint32_t)key, cx, cy, cz);
-    const int ui[3] = {(int)((cx << 8) | S.pos[3 * i]), (int)((cy << 8) | S.pos[3 * i + 1]),
-                       (int)((cz << 8) | S.pos[3 * i + 2])};
-    // mesh cell of a code: floor((2 u + 1) r / 512)
-    const int ci[3] = {((2 * ui[0] + 1) * g.r) >> 9, ((2 * ui[1] + 1) * g.r) >> 9,
-                       ((2 * ui[2] + 1) * g.r) >> 9};
-    const float unit = (float)g.r * (1.0f / 256.0f);  // mesh cells per position code
+    const int ui[3] = {(int)((cx << SH) | spos[3 * i]), (int)((cy << SH) | spos[3 * i + 1]),
+                       (int)((cz << SH) | spos[3 * i + 2])};
+    // mesh cell of a code: floor((2 u + 1) r / 2^FB)
+    const int ci[3] = {((2 * ui[0] + 1) * g.r) >> FB, ((2 * ui[1] + 1) * g.r) >> FB,
+                       ((2 * ui[2] + 1) * g.r) >> FB};
+    const float unit = (float)g.r * (P == 1 ? (1.0f / 256.0f) : (1.0f / 65536.0f));
     float ax = 0.f, ay = 0.f, az = 0.f;
     for (int t = 0; t < A.n_sp; ++t) {
       const PPSpecies& T = A.sp[t];
       if (T.n == 0) continue;
       const int64_t j0 = T.off[key], j1 = T.off[key + 1];
       float sx = 0.f, sy = 0.f, sz = 0.f;
+      const PC* tpos = (const PC*)T.pos;
       for (int64_t j = j0; j < j1; ++j) {
         if (t == s && j == i) continue;
-        const int uj0 = (int)((cx << 8) | T.pos[3 * j]);
-        const int uj1 = (int)((cy << 8) | T.pos[3 * j + 1]);
-        const int uj2 = (int)((cz << 8) | T.pos[3 * j + 2]);
-        if ((((2 * uj0 + 1) * g.r) >> 9) != ci[0] || (((2 * uj1 + 1) * g.r) >> 9) != ci[1] ||
-            (((2 * uj2 + 1) * g.r) >> 9) != ci[2])
+        const int uj0 = (int)((cx << SH) | tpos[3 * j]);
+        const int uj1 = (int)((cy << SH) | tpos[3 * j + 1]);
+        const int uj2 = (int)((cz << SH) | tpos[3 * j + 2]);
+        if ((((2 * uj0 + 1) * g.r) >> FB) != ci[0] || (((2 * uj1 + 1) * g.r) >> FB) != ci[1] ||
+            (((2 * uj2 + 1) * g.r) >> FB) != ci[2])
           continue;
-        const int d0 = uj0 - ui[0], d1 = uj1 - ui[1], d2 = uj2 - ui[2];
-        const int r2c = d0 * d0 + d1 * d1 + d2 * d2;
+        const DT d0 = uj0 - ui[0], d1 = uj1 - ui[1], d2 = uj2 - ui[2];
+        const DT r2c = d0 * d0 + d1 * d1 + d2 * d2;
         if ((double)r2c < A.cut2) continue;
         const float dx = (float)d0 * unit, dy = (float)d1 * unit, dz = (float)d2 * unit;
         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -118,7 +125,10 @@ pm_status run_pp_accel(pm_context* c, const pm_species* sp, int n_sp, int64_t* c
   A.n_sp = n_sp;
   const double delta = g.box / (double)g.ng;
   A.g_scale = (float)(c->cfg.G / (delta * delta));
-  const double rc = r_soft * g.SL;  // r_soft in position codes
+  const int kind = common_width_kind(sp, n_sp);
+  if (kind < 0) return PM_ERR_ARG;
+  const int P = width_pos(sp[0]);
+  const double rc = r_soft * g.SL * (P == 1 ? 1.0 : 256.0);  // r_soft in position codes
   A.cut2 = rc * rc;
   int64_t nmax = 0;
   for (int s = 0; s < n_sp; ++s) {
@@ -134,8 +144,12 @@ pm_status run_pp_accel(pm_context* c, const pm_species* sp, int n_sp, int64_t* c
   if (!part) return PM_ERR_NOMEM;
   {
     ProfScope ps(c, ST_PP);
-    hipLaunchKernelGGL(k_pp_accel, dim3((unsigned)nb, (unsigned)n_sp), dim3(PT), 0, c->stream,
-                       A, g, part);
+    if (P == 1)
+      hipLaunchKernelGGL(k_pp_accel<1>, dim3((unsigned)nb, (unsigned)n_sp), dim3(PT), 0,
+                         c->stream, A, g, part);
+    else
+      hipLaunchKernelGGL(k_pp_accel<2>, dim3((unsigned)nb, (unsigned)n_sp), dim3(PT), 0,
+                         c->stream, A, g, part);
     PM_LAUNCH_CHECK();
   }
   return fold_max_u32(c, part, nb * n_sp, (uint32_t*)pmax);

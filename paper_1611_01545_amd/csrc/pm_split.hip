@@ -26,7 +26,7 @@ constexpr int IMAXSP = 4;
 
 struct ISpecies {
   int64_t n;
-  const uint8_t* pos;
+  const void* pos;     // position codes, P bytes per axis
   const int64_t* off;  // cell offsets [ncell3 + 1]
   float* out;          // [n][3], stream order
 };
@@ -37,23 +37,29 @@ struct IArgs {
   int accumulate;
 };
 
+template <int P>  // position bytes per axis
 __global__ __launch_bounds__(IT) void k_interp_bricks(IArgs A, Geom g,
                                                       const float* __restrict__ acc) {
+  using PC = typename PosCode<P>::T;
+  constexpr int SH = 8 * P, FB = 8 * P + 1;
+  constexpr uint32_t FMASK = (1u << FB) - 1u;
+  constexpr float UNIT = 1.0f / (float)(1u << FB);
   const ISpecies& S = A.sp[blockIdx.y];
   if (S.n == 0) return;
+  const PC* spos = (const PC*)S.pos;
   __shared__ int64_t so[8 * 8 * 8 + 1];  // the brick's cell offsets (B <= 8)
   const int B3 = 1 << (3 * g.lgB);
   const int64_t k0 = (int64_t)blockIdx.x * B3;  // first cell key of the brick
   for (int i = threadIdx.x; i <= B3; i += IT) so[i] = S.off[k0 + i];
   __syncthreads();
   const int64_t base = so[0];
-  const int64_t P = so[B3] - base;
+  const int64_t np = so[B3] - base;  // the brick's particles
   const int64_t n = g.ng, n3 = n * n * n;
   const int nm = (int)n - 1;  // n is a power of two
   const float* ax = acc;
   const float* ay = acc + n3;
   const float* az = acc + 2 * n3;
-  for (int64_t q = threadIdx.x; q < P; q += IT) {
+  for (int64_t q = threadIdx.x; q < np; q += IT) {
     const int64_t j = base + q;
     if (j >= S.n) break;  // offsets inconsistent with n: latched by the offset check
     // local cell: the largest l with so[l] <= j (skips empty cells)
@@ -64,15 +70,15 @@ __global__ __launch_bounds__(IT) void k_interp_bricks(IArgs A, Geom g,
     }
     uint32_t cx, cy, cz;
     key_cell(g, (uint32_t)(k0 + lo), cx, cy, cz);
-    // mesh coordinate (2u + 1) r / 512 per axis: node = t >> 9, weight of node + 1 =
-    // (t & 511) / 512
-    const int tx = (2 * (int)((cx << 8) | S.pos[3 * j]) + 1) * g.r;
-    const int ty = (2 * (int)((cy << 8) | S.pos[3 * j + 1]) + 1) * g.r;
-    const int tz = (2 * (int)((cz << 8) | S.pos[3 * j + 2]) + 1) * g.r;
-    const int ix = (tx >> 9) & nm, iy = (ty >> 9) & nm, iz = (tz >> 9) & nm;
-    const float fx = (float)(tx & 511) * (1.0f / 512.0f);
-    const float fy = (float)(ty & 511) * (1.0f / 512.0f);
-    const float fz = (float)(tz & 511) * (1.0f / 512.0f);
+    // mesh coordinate (2u + 1) r / 2^FB per axis (2^FB = 512 for 1-byte codes): node =
+    // t >> FB, weight of node + 1 = (t mod 2^FB) / 2^FB; (2u + 1) r < 2^28
+    const int tx = (2 * (int)((cx << SH) | spos[3 * j]) + 1) * g.r;
+    const int ty = (2 * (int)((cy << SH) | spos[3 * j + 1]) + 1) * g.r;
+    const int tz = (2 * (int)((cz << SH) | spos[3 * j + 2]) + 1) * g.r;
+    const int ix = (tx >> FB) & nm, iy = (ty >> FB) & nm, iz = (tz >> FB) & nm;
+    const float fx = (float)((uint32_t)tx & FMASK) * UNIT;
+    const float fy = (float)((uint32_t)ty & FMASK) * UNIT;
+    const float fz = (float)((uint32_t)tz & FMASK) * UNIT;
     const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
     const int xs[2] = {ix, (ix + 1) & nm}, ys[2] = {iy, (iy + 1) & nm};
     const int zs[2] = {iz, (iz + 1) & nm};
@@ -117,9 +123,15 @@ pm_status run_interp_accel(pm_context* c, const pm_species* sp, int n_sp,
     A.sp[s].off = offs[s];
     A.sp[s].out = out[s];
   }
+  const int kind = common_width_kind(sp, n_sp);
+  if (kind < 0) return PM_ERR_ARG;
   ProfScope ps(c, ST_INTERP);
-  hipLaunchKernelGGL(k_interp_bricks, dim3((unsigned)g.nbrick, (unsigned)n_sp), dim3(IT), 0,
-                     c->stream, A, g, acc);
+  if (width_pos(sp[0]) == 1)
+    hipLaunchKernelGGL(k_interp_bricks<1>, dim3((unsigned)g.nbrick, (unsigned)n_sp), dim3(IT),
+                       0, c->stream, A, g, acc);
+  else
+    hipLaunchKernelGGL(k_interp_bricks<2>, dim3((unsigned)g.nbrick, (unsigned)n_sp), dim3(IT),
+                       0, c->stream, A, g, acc);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }

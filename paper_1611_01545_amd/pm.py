@@ -44,22 +44,39 @@ class FloatSpecies:
         return s
 
 
+def widths_word(pos_bytes: int = 1, vel_bytes: int = 2) -> int:
+    """pm_species.widths: 0 for 1-byte positions and 2-byte velocities, else P | V << 8."""
+    if pos_bytes not in (1, 2) or vel_bytes not in (1, 2):
+        raise ValueError("code widths are 1 or 2 bytes")
+    return 0 if (pos_bytes, vel_bytes) == (1, 2) else pos_bytes | (vel_bytes << 8)
+
+
 @dataclass
 class CompressedSpecies:
     count: torch.Tensor  # uint8 [n_cell^3]
-    pos: torch.Tensor    # uint8 [n, 3]
-    vel: torch.Tensor    # int16 [n, 3] holding uint16 codes
+    pos: torch.Tensor    # [n, 3]: uint8 (1-byte codes) or int16 holding uint16 codes
+    vel: torch.Tensor    # [n, 3]: int16 holding uint16 codes, or uint8 (1-byte codes)
     esc: torch.Tensor    # int64 [cap, 2] holding uint64 (cell, count)
     hdr: torch.Tensor    # uint8 [32]: pm_shdr
     mass: float
+    widths: int = 0      # pm_species.widths (widths_word)
 
     @property
     def n(self) -> int:
         return int(self.pos.shape[0])
 
+    @property
+    def pos_bytes(self) -> int:
+        return 1 if self.widths == 0 else self.widths & 255
+
+    @property
+    def vel_bytes(self) -> int:
+        return 2 if self.widths == 0 else self.widths >> 8
+
     def c(self) -> PmSpecies:
         s = PmSpecies()
         s.layout = PM_COMPRESSED
+        s.widths = self.widths
         s.n = self.n
         s.mass = self.mass
         s.count = _ptr(self.count)
@@ -156,22 +173,25 @@ class PMContext:
         v = torch.as_tensor(v, dtype=torch.float32).to(self.device).contiguous()
         return FloatSpecies(x.reshape(-1, 3), v.reshape(-1, 3), float(mass))
 
-    def empty_compressed(self, n: int, mass: float, cap_esc: int | None = None) -> CompressedSpecies:
+    def empty_compressed(self, n: int, mass: float, cap_esc: int | None = None,
+                         widths: int = 0) -> CompressedSpecies:
         if cap_esc is None:
             cap_esc = max(16, n // 255 + 1)
         d = self.device
+        pb = 1 if widths == 0 else widths & 255
+        vb = 2 if widths == 0 else widths >> 8
         return CompressedSpecies(
             count=torch.empty(self.n_cell ** 3, dtype=torch.uint8, device=d),
-            pos=torch.empty((n, 3), dtype=torch.uint8, device=d),
-            vel=torch.empty((n, 3), dtype=torch.int16, device=d),
+            pos=torch.empty((n, 3), dtype=torch.uint8 if pb == 1 else torch.int16, device=d),
+            vel=torch.empty((n, 3), dtype=torch.int16 if vb == 2 else torch.uint8, device=d),
             esc=torch.zeros((cap_esc, 2), dtype=torch.int64, device=d),
             hdr=torch.zeros(32, dtype=torch.uint8, device=d),
-            mass=float(mass))
+            mass=float(mass), widths=int(widths))
 
     def empty_like(self, s):
         if isinstance(s, FloatSpecies):
             return FloatSpecies(torch.empty_like(s.x), torch.empty_like(s.v), s.mass)
-        return self.empty_compressed(s.n, s.mass, int(s.esc.shape[0]))
+        return self.empty_compressed(s.n, s.mass, int(s.esc.shape[0]), s.widths)
 
     # ------------------------------------------------------------ the calls --
     def sync(self):
@@ -182,8 +202,10 @@ class PMContext:
         check(self.lib.pm_last_error_detail(self.h, ctypes.byref(v)), "pm_last_error_detail")
         return v.value
 
-    def encode(self, fs: FloatSpecies, want_perm: bool = False, cap_esc: int | None = None):
-        out = self.empty_compressed(fs.n, fs.mass, cap_esc)
+    def encode(self, fs: FloatSpecies, want_perm: bool = False, cap_esc: int | None = None,
+               widths: int = 0):
+        """pm_encode; widths: code widths of the result (widths_word)."""
+        out = self.empty_compressed(fs.n, fs.mass, cap_esc, widths)
         perm = torch.empty(fs.n, dtype=torch.int64, device=self.device) if want_perm else None
         a, b = fs.c(), out.c()
         check(self.lib.pm_encode(self.h, ctypes.byref(a), ctypes.byref(b), _ptr(perm)),
@@ -371,7 +393,10 @@ class PMContext:
         return buf[: int(used.item())].cpu().numpy().tobytes()
 
     def unpack(self, data: bytes, n: int, cap_esc: int | None = None):
-        out = self.empty_compressed(n, 0.0, cap_esc)
+        import struct
+        w = struct.unpack("<I", data[36:40])[0] if len(data) >= 64 else 0
+        w = w if w in (0x101, 0x102, 0x202) else 0  # anything else: pm_unpack rejects it
+        out = self.empty_compressed(n, 0.0, cap_esc, w)
         a = out.c()
         mass = ctypes.c_double()
         sid = ctypes.c_int32()
@@ -408,21 +433,29 @@ class PMContext:
         self.sync()
         h = cs.header()
         esc = cs.esc[: h["n_esc"]].cpu().numpy().astype(np.uint64).reshape(-1, 2)
-        return {"n_c": self.n_cell, "brick": self.brick,
-                "count": cs.count.cpu().numpy(), "esc": esc,
-                "pos": cs.pos.cpu().numpy(),
-                "vel": cs.vel.cpu().numpy().view(np.uint16),
-                "v_max": h["v_max"], "j_min": h["j_min"], "j_max": h["j_max"]}
+        pos = cs.pos.cpu().numpy()
+        vel = cs.vel.cpu().numpy()
+        st = {"n_c": self.n_cell, "brick": self.brick,
+              "count": cs.count.cpu().numpy(), "esc": esc,
+              "pos": pos if cs.pos_bytes == 1 else pos.view(np.uint16),
+              "vel": vel.view(np.uint16) if cs.vel_bytes == 2 else vel,
+              "v_max": h["v_max"], "j_min": h["j_min"], "j_max": h["j_max"]}
+        if cs.widths:
+            st["pos_bytes"], st["vel_bytes"] = cs.pos_bytes, cs.vel_bytes
+        return st
 
     def from_host(self, st: dict, mass: float, cap_esc: int | None = None) -> CompressedSpecies:
         """Oracle state dict -> device compressed species (header j_min/j_max derived)."""
         import struct
         n = int(st["pos"].shape[0])
-        cs = self.empty_compressed(n, mass, cap_esc)
+        w = widths_word(int(st.get("pos_bytes", 1)), int(st.get("vel_bytes", 2)))
+        cs = self.empty_compressed(n, mass, cap_esc, w)
         cs.count.copy_(torch.from_numpy(np.ascontiguousarray(st["count"])))
         if n:
-            cs.pos.copy_(torch.from_numpy(np.ascontiguousarray(st["pos"])))
-            cs.vel.copy_(torch.from_numpy(np.ascontiguousarray(st["vel"]).view(np.int16)))
+            pos = np.ascontiguousarray(st["pos"])
+            vel = np.ascontiguousarray(st["vel"])
+            cs.pos.copy_(torch.from_numpy(pos if cs.pos_bytes == 1 else pos.view(np.int16)))
+            cs.vel.copy_(torch.from_numpy(vel.view(np.int16) if cs.vel_bytes == 2 else vel))
         esc = np.asarray(st["esc"], dtype=np.uint64).reshape(-1, 2)
         if esc.shape[0] > cs.esc.shape[0]:
             raise ValueError("escape table larger than capacity")

@@ -68,12 +68,14 @@ def check_codes(c, out, perms, new, diag, n_cell, dt, a_rms=None):
     stream the stable cell sort of the new codes. Returns the number of tie-zone codes.
     a_rms: the force scale of the tolerance (default: RMS of the oracle's force mesh)."""
     from oracle import codec
-    S = 256 * n_cell
     if a_rms is None:
         a_rms = np.sqrt(np.mean(diag["a_mesh"] ** 2))
     ties = 0
     for o, ns, d, perm in zip(out, new, diag["species"], perms):
         h = c.to_host(o)
+        pb, vb = codec.widths(ns)
+        assert codec.widths(h) == (pb, vb)
+        S = codec.pos_scale(n_cell, pb)
         pm = perm.cpu().numpy()
         assert np.array_equal(np.sort(pm), np.arange(pm.size))
         ug, jg = _codes_old_order(h, pm)
@@ -92,7 +94,7 @@ def check_codes(c, out, perms, new, diag, n_cell, dt, a_rms=None):
         assert bad.mean() < 1e-3
         # velocity codes (same v_max' on both sides in these cases)
         assert float(h["v_max"]) == float(d["v_max_new"])
-        C = 32768.0 / float(d["v_max_new"])
+        C = codec.half_range(vb) / float(d["v_max_new"])
         tau_v = C * dv + 1e-6
         dj = jg - d["j_new"]
         badv = dj != 0
@@ -102,7 +104,7 @@ def check_codes(c, out, perms, new, diag, n_cell, dt, a_rms=None):
         ties += int(bad.sum() + badv.sum())
         # counts and escape table: the oracle's when every code agrees, and in any case
         # the counts of the GPU's own new codes (the escape rebuild after the kick)
-        keys_new = codec.cell_keys(ug >> 8, n_cell, c.brick)
+        keys_new = codec.cell_keys(ug >> (8 * pb), n_cell, c.brick)
         cnt, esc = codec.build_counts(np.sort(keys_new), n_cell)
         assert np.array_equal(h["count"], cnt)
         assert np.array_equal(np.asarray(h["esc"], dtype=np.uint64).reshape(-1, 2), esc)
