@@ -16,7 +16,8 @@ stream the kernels run on), the per-stage breakdown, the peak HBM footprint, the
 fraction of particles whose position code does not change in a step, the comparison
 of three compressed float32 steps with an all-float64 uncompressed run on the
 [0, 128 Delta)^3 sub-box, the step with the two-level force of Sec. 2.1 (coarse
-long-range mesh n/4, fine short-range mesh n, with and without the PP force), the
+long-range mesh n/4, fine short-range mesh n, with and without the PP force), the step
+and frozen fraction with 2-byte positions and with 1-byte velocities, the
 1024^3 tile's step, PP, two-level and step-adjoint rates, and the oracle's own
 throughput on a bounded sample (CPU baseline).
 """
@@ -509,6 +510,42 @@ def two_level_rates(PMContext, wl, cur, brick, torch, log, steps, warmup, ms_one
     return res
 
 
+def width_rates(PMContext, wl, torch, log, steps, warmup, ms_one,
+                pairs=((2, 2), (1, 1))):
+    """Adjustable code widths (Sec. 2.4, closing remark: 8- or 16-bit positions and
+    velocities): for each (position bytes, velocity bytes) pair, the pm_step rate on the
+    same particles and, per species, the fraction of position codes one step leaves
+    unchanged (from a step with the PP force cut everywhere, r_soft = L, which is pm_step
+    with the re-sort reported)."""
+    from paper_1611_01545_amd import widths_word
+    res = {}
+    for pb, vb in pairs:
+        ctx = PMContext(wl.n_mesh, wl.n_cell)
+        w = widths_word(pb, vb)
+        A = []
+        for sp in wl.species:
+            fs = ctx.float_species(sp.x, sp.v, sp.mass)
+            A.append(ctx.encode(fs, widths=w))
+            del fs
+        B = [ctx.empty_like(s) for s in A]
+        B, perms = ctx.step_pp(A, wl.dt, ctx.box, out=B, want_perm=True)
+        frozen = {sp.name: 1.0 - moved_fraction(a, b, p, torch)
+                  for sp, a, b, p in zip(wl.species, A, B, perms)}
+        del perms
+        ms, value, _, cur = timed_steps(ctx, A, B, wl, torch, steps, warmup)
+        res[f"{pb}_{vb}"] = {
+            "position_bytes": pb, "velocity_bytes": vb,
+            "bytes_per_particle": 3 * (pb + vb),
+            "ms_per_step": ms, "value": value, "over_paper_widths": ms / ms_one,
+            "frozen_fraction": frozen}
+        log(f"[bench] code widths ({pb}, {vb}): {ms:.3f} ms/step, frozen "
+            + ", ".join(f"{k} {v:.4f}" for k, v in frozen.items()))
+        ctx.close()
+        del A, B, cur
+        torch.cuda.empty_cache()
+    return res
+
+
 def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True):
     """The 1024^3 tile (256^3 + 512^3): step rate, and the step adjoint at that size."""
     wl = make_workload("tile_1024")
@@ -545,6 +582,7 @@ def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True
         f"(PP kernel {ms_pp / max(1, n_pp):.3f} ms)")
     out["two_level"] = two_level_rates(PMContext, wl, cur, ctx.brick, torch, log, steps,
                                        warmup, ms_step)
+    out["code_widths"] = width_rates(PMContext, wl, torch, log, steps, warmup, ms_step)
     if adjoint:
         lx = [torch.ones((sp.n, 3), dtype=torch.float32, device=ctx.device) for sp in cur]
         lv = [torch.ones_like(t) for t in lx]
@@ -583,6 +621,8 @@ def main():
                     help="skip the 1024^3 tile measured beside the large workload")
     ap.add_argument("--no-two-level", action="store_true",
                     help="skip the two-level force (pm_step_p3m) timings")
+    ap.add_argument("--no-widths", action="store_true",
+                    help="skip the 2-byte-position and 1-byte-velocity code widths")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run one elementwise kernel that reads and "
                          "writes exactly 1 GiB (reference for HBM byte counters)")
@@ -666,6 +706,10 @@ def main():
                                     args.warmup, ms_step)
     del A, B, cur
     torch.cuda.empty_cache()
+    widths = None
+    if not args.no_widths:
+        log("[bench] adjustable code widths")
+        widths = width_rates(PMContext, wl, torch, log, args.steps, args.warmup, ms_step)
 
     footprint = {"timed_steps_gb": peak_step / 1e9,
                  "query_sizes_gb": {k: v / 1e9 for k, v in sizes.items()},
@@ -729,6 +773,7 @@ def main():
         "frozen_fraction": frozen,
         "vs_fp64_sub_box": compare,
         "two_level": two_level,
+        "code_widths": widths,
         "tile_1024": extra,
         "adjoint": adj,
         "err_vs_fp64": err,
