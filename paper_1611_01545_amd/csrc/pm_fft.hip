@@ -593,6 +593,21 @@ __device__ __forceinline__ int64_t spec_row(int64_t row) {
   const int64_t z = row >> LN, y = row & (n - 1);
   return (((z >> LZB) << LN) + y) * ((int64_t)ZB * M) + (z & (ZB - 1)) * M;
 }
+// The inverse row pass visits rows in the spectrum's storage order: index s = ((z / ZB)
+// n + y) ZB + z % ZB, so the spectrum rows of consecutive workgroups are one contiguous
+// run and their real rows a few runs in each of ZB planes (instead of rows ZB M complex
+// apart across a whole z block of the spectrum): 17.9 -> 17.5 ms per launch at 2048^3.
+// The forward pass keeps the natural order (its spectrum writes are not slowed by the
+// stride, and the planes' runs slowed it 15.0 -> 16.4 ms). Returns the natural row
+// z n + y of s.
+template <int M>
+__device__ __forceinline__ int64_t row_of(int64_t s) {
+  constexpr int n = 2 * M, ZB = zblk(n), LZB = ilog2(ZB), LN = ilog2(n);
+  const int64_t zl = s & (ZB - 1), t2 = s >> LZB;
+  const int64_t y = t2 & (n - 1), zb = t2 >> LN;
+  return ((zb << LZB) + zl) * n + y;
+}
+
 // rows per workgroup of the row passes: up to 256 threads, and LDS for the FFT exchange
 // only (the pairing of k with M - k goes through lane shuffles)
 template <int M>
@@ -619,7 +634,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
   __shared__ float lds[R * LF];
   // R divides the row count (checked on the host): no bounds guards
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
-  const int64_t row = (int64_t)blockIdx.x * R + rr;
+  const int64_t row = (int64_t)blockIdx.x * R + rr;  // natural order (faster here)
   float* my = lds + rr * LF;
   const float2* zin = (const float2*)(in + row * 2 * M);
   float2 a[P::E];
@@ -667,7 +682,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   constexpr int LF = P::E * P::TP;
   __shared__ float lds[R * LF];
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
-  const int64_t row = (int64_t)blockIdx.x * R + rr;
+  const int64_t row = row_of<M>((int64_t)blockIdx.x * R + rr);
   float* my = lds + rr * LF;
   const float2* xi = in + spec_row<M>(row);
   const int n = 2 * M;
