@@ -547,7 +547,9 @@ def width_rates(PMContext, wl, torch, log, steps, warmup, ms_one,
 
 
 def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True):
-    """The 1024^3 tile (256^3 + 512^3): step rate, and the step adjoint at that size."""
+    """The 1024^3 tile (256^3 + 512^3): step rate over its 8 seeds, the PP, two-level and
+    code-width steps, and the step adjoint at that size."""
+    import numpy as np
     wl = make_workload("tile_1024")
     ctx = PMContext(wl.n_mesh, wl.n_cell)
     A = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in wl.species]
@@ -559,6 +561,22 @@ def tile_extra(PMContext, make_workload, torch, log, steps, warmup, adjoint=True
            "deposit_frac": stages["deposit"]["gbs"] / HBM_PEAK_GBS,
            "interp_kick_drift_frac": stages["interp_kick_drift"]["gbs"] / HBM_PEAK_GBS}
     log(f"[bench] tile_1024: {ms_step:.3f} ms/step, {value:.3e} particle-updates/s")
+    # the tile's 8 random seeds (seed 0 above): each re-generated, encoded and stepped
+    # `steps` times on the same context
+    per_seed = [ms_step]
+    for seed in range(1, 8):
+        w2 = make_workload("tile_1024", seed_offset=seed)
+        A2 = [ctx.encode(ctx.float_species(sp.x, sp.v, sp.mass)) for sp in w2.species]
+        B2 = [ctx.empty_like(s_) for s_ in A2]
+        ms2, _, _, _ = timed_steps(ctx, A2, B2, w2, torch, steps, min(warmup, 1))
+        per_seed.append(ms2)
+        del w2, A2, B2
+    torch.cuda.empty_cache()
+    out["seeds"] = {"ms_per_step": per_seed, "mean_ms": float(np.mean(per_seed)),
+                    "min_ms": float(np.min(per_seed)), "max_ms": float(np.max(per_seed)),
+                    "mean_value": wl.n_particles / (float(np.mean(per_seed)) * 1e-3)}
+    log(f"[bench] tile_1024 over 8 seeds: {np.mean(per_seed):.3f} ms/step "
+        f"({np.min(per_seed):.3f}-{np.max(per_seed):.3f})")
     # the same step with the cell-local PP force of eq. (4), r_soft = L / (20 n_p)
     r_soft = 1.0 / (20 * 2 * wl.n_cell)
     nxt = [ctx.empty_like(s) for s in cur]

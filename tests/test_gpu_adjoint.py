@@ -179,7 +179,8 @@ def test_loss_density_vjp_matches_oracle(layout):
     c.close()
 
 
-def test_multistep_gradient_along_compressed_trajectory():
+@pytest.mark.parametrize("full", [False, True], ids=["32^3-mesh", "adjoint_128"])
+def test_multistep_gradient_along_compressed_trajectory(full):
     """K compressed steps forward, then the chain of step VJPs backward from a density
     loss, against the float64 oracle's chain along the same (decoded) trajectory with
     the oracle's own re-sort permutations. Errors of the K chained float32 VJPs add, so
@@ -188,10 +189,18 @@ def test_multistep_gradient_along_compressed_trajectory():
     Also reported, not asserted: the gradient through K uncompressed float64 steps from
     the decoded initial state. The two trajectories differ (at this size most CDM
     particles move less than half a position quantum per step and stay frozen in the
-    fixed-point drift), so the gradients differ by several per cent."""
-    wl = make_workload("adjoint_128", n_p_c=16, n_mesh=32, n_cell=16)
-    tgt = make_workload("adjoint_128", seed_offset=1, n_p_c=16, n_mesh=32, n_cell=16)
-    K = 3
+    fixed-point drift), so the gradients differ by several per cent.
+
+    Run at a 32^3 mesh for 3 steps and at the differentiable workload's full size
+    (64^3 CDM, 128^3 mesh, 10 steps of dt 0.02)."""
+    if full:
+        wl = make_workload("adjoint_128")
+        tgt = make_workload("adjoint_128", seed_offset=1)
+        K = wl.steps
+    else:
+        wl = make_workload("adjoint_128", n_p_c=16, n_mesh=32, n_cell=16)
+        tgt = make_workload("adjoint_128", seed_offset=1, n_p_c=16, n_mesh=32, n_cell=16)
+        K = 3
     from oracle import mesh
     rho_t = sum(mesh.deposit(s.x, s.mass, wl.n_mesh) for s in tgt.species)
     masses = [s.mass for s in wl.species]
@@ -220,7 +229,8 @@ def test_multistep_gradient_along_compressed_trajectory():
     ev = rel_rms(lv[0].cpu().numpy(), rv[0])
     x0, v0 = codec.decode(hosts[0][0])
     _, fx, fv = adjoint.grad_float_loss([(x0, v0, masses[0])], rho_t, wl.n_mesh, wl.dt, K)
-    print(f"chain vs oracle: x {ex:.2e} v {ev:.2e}; compressed vs float trajectory: "
+    print(f"{K} steps on {wl.n_mesh}^3: chain vs oracle: x {ex:.2e} v {ev:.2e}; "
+          f"compressed vs float trajectory: "
           f"x {rel_rms(lx[0].cpu().numpy(), fx[0]):.3f} v {rel_rms(lv[0].cpu().numpy(), fv[0]):.3f}")
     assert ex <= K * TOL, ex
     assert ev <= K * TOL, ev

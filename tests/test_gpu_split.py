@@ -153,3 +153,24 @@ def test_step_p3m_rejects_a_mismatched_pair():
         PMContext(16, 8, kernel=LONG, r_split=0.0)
     for c in (fine, coarse, other, full, soft):
         c.close()
+
+
+def test_step_p3m_with_two_byte_positions_matches_oracle():
+    # the two-level step on (2, 2)-byte codes (the adjustable widths of Sec. 2.4)
+    from paper_1611_01545_amd import widths_word
+    wl = small_two_species(16, 64, seed_offset=9, n_cell=16)
+    fine, coarse = PMContext.two_level(64, 16)
+    st = [fine.encode(fine.float_species(s.x, s.v, s.mass), widths=widths_word(2, 2))
+          for s in wl.species]
+    out, perms = fine.step_p3m(coarse, st, wl.dt, want_perm=True)
+    fine.sync()
+    states = [fine.to_host(s) for s in st]
+    masses = [sp.mass for sp in wl.species]
+    new, diag = split.step_two_level(states, masses, 64, 16, wl.dt, wl.dt, fine.r_split,
+                                     1.0, G)
+    a_rms = np.sqrt(np.mean(diag["a_mesh"] ** 2) + np.mean(diag["a_long"] ** 2))
+    ties = check_codes(fine, out, perms, new, diag, 16, wl.dt, a_rms=a_rms)
+    print(f"[split] two-level step, 2-byte positions: {ties} codes in the tie zone",
+          flush=True)
+    fine.close()
+    coarse.close()
