@@ -376,8 +376,11 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
   constexpr int CS = col_cs<W>(L::LF);
   __shared__ float lds[W * CS];
   constexpr bool TWO = OUT == 2 || OUT == 3;
-  __shared__ float2 stw[TWO ? N : 1];
-  if constexpr (TWO) {
+  // Split lines stage their twiddles as well: at 1024 threads (128 VGPRs) the compiler
+  // issues the global twiddle loads one at a time, each waited for (y passes at 2048^3)
+  constexpr bool STW = TWO || L::H == 2;
+  __shared__ float2 stw[STW ? N : 1];
+  if constexpr (STW) {
     for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
     __syncthreads();
   }
@@ -448,7 +451,8 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
       for (int k2 = 0; k2 < L::T; ++k2)
         (out1 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = b[v * L::T + k2];
   } else {
-    line_nat_to_tr<N, SIGN>(a, t, h, my, tw, tws, twmask);
+    if constexpr (STW) line_nat_to_tr<N, SIGN>(a, t, h, my, stw, 1, N - 1);
+    else line_nat_to_tr<N, SIGN>(a, t, h, my, tw, tws, twmask);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -480,6 +484,10 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   // would otherwise keep live together
   __shared__ float2 stw[N];
   for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
+  // the gradient symbol too (shared by the workgroup's lines): loaded from global memory
+  // next to the kernel values, the compiler waits for its loads one by one
+  __shared__ float sgk[N];
+  for (int i = threadIdx.x; i < N; i += W * L::TL) sgk[i] = gk[i];
   __syncthreads();
   const int c = threadIdx.x % W, tl = threadIdx.x / W;
   const int t = tl % L::T, h = tl / L::T;
@@ -516,7 +524,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
         const int sz = signed_k(kz, n);
         const float G = grow[sz < 0 ? -sz : sz];
         const float2 f = make_float2(G * acc[v * L::T + k2].x, G * acc[v * L::T + k2].y);
-        const float kk = grad_k(gk, kz);
+        const float kk = sgk[kz];
         acc[v * L::T + k2] = f;
         gz[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
       }
@@ -540,7 +548,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
         const float2 f = acc[v * L::T + k2];
         if constexpr (MODE == 2) {
           // -i k_z G (x + i y) = k_z G y - i k_z G x
-          const float kk = grad_k(gk, kz) * G;
+          const float kk = sgk[kz] * G;
           acc[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);
         } else {
           acc[v * L::T + k2] = make_float2(G * f.x, G * f.y);
@@ -559,7 +567,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
       for (int k2 = 0; k2 < L::T; ++k2) {
-        const float k = grad_k(gk, (t + L::T * v) + L::E * k2 + h * L::NH);
+        const float k = sgk[(t + L::T * v) + L::E * k2 + h * L::NH];
         const float2 q = acc[v * L::T + k2];
         acc[v * L::T + k2] = make_float2(-k * q.y, k * q.x);  // + i k (x + i y)
       }
@@ -632,6 +640,11 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
   constexpr int R = rows_per_wg<M>();
   constexpr int LF = P::E * P::TP;
   __shared__ float lds[R * LF];
+  // the twiddles in LDS: from global memory the compiler issues most of them one at a
+  // time, each waited for (13.2 against 14.5 ms at 2048^3)
+  __shared__ float2 stw[2 * M];
+  for (int i = threadIdx.x; i < 2 * M; i += R * P::T) stw[i] = tw[i];
+  __syncthreads();
   // R divides the row count (checked on the host): no bounds guards
   const int t = threadIdx.x % P::T, rr = threadIdx.x / P::T;
   const int64_t row = (int64_t)blockIdx.x * R + rr;  // natural order (faster here)
@@ -641,7 +654,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
 #pragma unroll
   for (int n1 = 0; n1 < P::E; ++n1) a[n1] = zin[t + P::T * n1];
   // M-point DFT: tw table is for n = 2M points, stride 2
-  nat_to_tr<M, -1>(a, t, my, tw, 2, twmask);
+  nat_to_tr<M, -1>(a, t, my, stw, 2, twmask);
   // a[v T + k2] = Z[k], k = (t + T v) + E k2. Z[M - k] is held by lane (T - t) of the
   // row's lane group at index (V - 1 - v) T + (T - 1 - k2); lane t = 0 holds it itself,
   // at index (V - v) T + (T - 1 - k2) for v >= 1 and (T - k2) mod T for v = 0 (Z[M] =
@@ -661,7 +674,7 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
       // A = (Z[k] + conj Z[M-k]) / 2, B = -i (Z[k] - conj Z[M-k]) / 2, X = A + W^k B
       float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-      float2 w = tw[k];
+      float2 w = stw[k];
       float2 wb = cmul(w, B);
       float2 X = make_float2(A.x + wb.x, A.y + wb.y);
       if (k == 0) X = make_float2(zk.x + zk.y, 0.f);
@@ -687,15 +700,17 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   const float2* xi = in + spec_row<M>(row);
   const int n = 2 * M;
   float2 xr[P::E];
+  // every load is issued before the first use: with the -i k_x factor inside the load
+  // loop, the branch on grad made each load wait for the one before it (the a_x launch
+  // took 25 ms against 15 for the other two at 2048^3; now all three 14.5 ms)
 #pragma unroll
-  for (int j = 0; j < P::E; ++j) {
-    const int k = t + P::T * j;
-    float2 X = xi[k];
-    if (grad) {
-      float kk = grad_k(gk, k);
-      X = make_float2(kk * X.y, -kk * X.x);
+  for (int j = 0; j < P::E; ++j) xr[j] = xi[t + P::T * j];
+  if (grad) {
+#pragma unroll
+    for (int j = 0; j < P::E; ++j) {
+      const float kk = grad_k(gk, t + P::T * j);
+      xr[j] = make_float2(kk * xr[j].y, -kk * xr[j].x);
     }
-    xr[j] = X;
   }
   float2 xn = make_float2(0.f, 0.f);  // X[M], held by lane t = 0
   if (t == 0 && !grad) xn = nyq[row];  // -i k_x is zero on the Nyquist index
