@@ -53,68 +53,125 @@ WORKLOAD_TEXT = {
 # that reads and writes exactly 1 GiB. A record holds only for the kernel sources it was
 # taken on (sha256 over `sources`); otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    ("interp_kick_drift", "tile_1024"): {
-        "kernel": "k_kick_pair<256, 4>",
-        "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
+    ("deposit", "tile_1024"): {
+        "kernel": "k_deposit_tile<4, 1>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_deposit.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
-                    "paper_1611_01545_amd/csrc/pm_codec.h"],
-        "sha256": "1dc0117ead72af659fd28f6f6dc1cfa1f50eabd20de7c5455a87155bccba33e1",
-        "fetch_kib": 8164916.25, "fetch_factor": 1.99988,
-        "write_kib": 2200561.28, "write_factor": 1.0,
+                    "paper_1611_01545_amd/csrc/pm_codec.h",
+                    "paper_1611_01545_amd/csrc/pm_scan.h"],
+        "sha256": "7c2c31e32471659a1aa7150e42d2aebc0d4b678020bda6d9609b0cc9b8a7ceb8",
+        "fetch_kib": 509653.56, "fetch_factor": 1.99989,
+        "write_kib": 4195480.94, "write_factor": 1.0,
+    },
+    ("fft_x_r2c", "tile_1024"): {
+        "kernel": "k_row_r2c<512>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 2097316.62, "fetch_factor": 1.99989,
+        "write_kib": 4202740.09, "write_factor": 1.0,
+    },
+    ("fft_y_fwd", "tile_1024"): {
+        "kernel": "k_col_fft<1024, 16, -1, 0>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 2097342.44, "fetch_factor": 1.99989,
+        "write_kib": 4194304.12, "write_factor": 1.0,
+    },
+    ("fft_z", "tile_1024"): {
+        "kernel": "k_col_zconv<1024, 16, 3, true>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 2632884.31, "fetch_factor": 1.99989,
+        "write_kib": 8388608.00, "write_factor": 1.0,
+    },
+    ("fft_y_inv", "tile_1024"): {
+        "kernel": "k_col_fft<1024, 16, 1, 2> + k_col_fft<1024, 16, 1, 0>, per scope",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 2099779.81, "fetch_factor": 1.99989,
+        "write_kib": 6291456.00, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
-        "kernel": "k_row_c2r<512>",
+        "kernel": "k_row_c2r<512>, mean of three",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "b4c65a62e4abf37a64be1ac3a81a194d3b65c53b2a438f4e666e0963fe4c84fc",
-        "fetch_kib": 2101697.0, "fetch_factor": 1.99988,
-        "write_kib": 4196763.0, "write_factor": 1.0,
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 2121003.67, "fetch_factor": 1.99989,
+        "write_kib": 4196656.57, "write_factor": 1.0,
     },
-    # 2048^3: one FETCH_SIZE and one WRITE_SIZE pass of one step, per stage scope (the
-    # y inverse scope holds two launches and one, so its record is half the three)
-    ("fft_y_inv", "large_2048"): {
-        "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
+    ("interp_kick_drift", "tile_1024"): {
+        "kernel": "k_kick_pair<256, 4, 1, 2>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h",
+                    "paper_1611_01545_amd/csrc/pm_codec.h",
+                    "paper_1611_01545_amd/csrc/pm_scan.h"],
+        "sha256": "b84818d2567edf7f461105c83a6a11c6567a60a380121ce48cf322610954d453",
+        "fetch_kib": 8188016.31, "fetch_factor": 1.99989,
+        "write_kib": 2199180.94, "write_factor": 1.0,
+    },
+    ("deposit", "large_2048"): {
+        "kernel": "k_deposit_tile<4, 1>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_deposit.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h",
+                    "paper_1611_01545_amd/csrc/pm_codec.h",
+                    "paper_1611_01545_amd/csrc/pm_scan.h"],
+        "sha256": "7c2c31e32471659a1aa7150e42d2aebc0d4b678020bda6d9609b0cc9b8a7ceb8",
+        "fetch_kib": 4112578.56, "fetch_factor": 1.99993,
+        "write_kib": 33556057.94, "write_factor": 1.0,
+    },
+    ("fft_x_r2c", "large_2048"): {
+        "kernel": "k_row_r2c<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "fee8ab4b95eb970ed702acd84069a5625477433186960a9f567af59c10305585",
-        "fetch_kib": 25211604.0, "fetch_factor": 1.99993,
-        "write_kib": 50331648.0, "write_factor": 1.0,
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 16778444.44, "fetch_factor": 1.99993,
+        "write_kib": 33587745.34, "write_factor": 1.0,
+    },
+    ("fft_y_fwd", "large_2048"): {
+        "kernel": "k_col_fft<2048, 16, -1, 0>",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 16817200.94, "fetch_factor": 1.99993,
+        "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_z", "large_2048"): {
         "kernel": "k_col_zconv<2048, 16, 2, true> + k_col_zconv<2048, 16, 0, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "fee8ab4b95eb970ed702acd84069a5625477433186960a9f567af59c10305585",
-        "fetch_kib": 45692695.0, "fetch_factor": 1.99993,
-        "write_kib": 71827472.0, "write_factor": 1.0,
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 46658851.88, "fetch_factor": 1.99993,
+        "write_kib": 74448926.75, "write_factor": 1.0,
     },
-    ("fft_x_c2r", "large_2048"): {
-        "kernel": "k_row_c2r<1024>",
+    ("fft_y_inv", "large_2048"): {
+        "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "fee8ab4b95eb970ed702acd84069a5625477433186960a9f567af59c10305585",
-        "fetch_kib": 16811505.0, "fetch_factor": 1.99993,
-        "write_kib": 33572408.0, "write_factor": 1.0,
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 25229838.84, "fetch_factor": 1.99993,
+        "write_kib": 50331648.00, "write_factor": 1.0,
+    },
+    ("fft_x_c2r", "large_2048"): {
+        "kernel": "k_row_c2r<1024>, mean of three",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "d0c28139acac78139c691ede8ce209b7a4ae398fca6f0b95b5443e7a5d3673d5",
+        "fetch_kib": 16788433.69, "fetch_factor": 1.99993,
+        "write_kib": 33572964.34, "write_factor": 1.0,
     },
     ("interp_kick_drift", "large_2048"): {
-        "kernel": "k_kick_pair<256, 4>",
+        "kernel": "k_kick_pair<256, 4, 1, 2>",
         "sources": ["paper_1611_01545_amd/csrc/pm_kick.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "fff91e06dcd39aebf869ff564980d4e06bd4f6624482a9ba47ec677e637439c8",
-        "fetch_kib": 66219485.0, "fetch_factor": 1.99993,
-        "write_kib": 17608274.0, "write_factor": 1.0,
-    },
-    ("deposit", "large_2048"): {
-        "kernel": "k_deposit_tile<4>",
-        "sources": ["paper_1611_01545_amd/csrc/pm_deposit.hip",
-                    "paper_1611_01545_amd/csrc/pm_common.h",
-                    "paper_1611_01545_amd/csrc/pm_codec.h",
-                    "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "ba72a84f3d2c0869a96b140271e290639c4c739c55dcffafcb3a18a7a3831b71",
-        "fetch_kib": 4105054.0, "fetch_factor": 1.99993,
-        "write_kib": 33556300.0, "write_factor": 1.0,
+        "sha256": "b84818d2567edf7f461105c83a6a11c6567a60a380121ce48cf322610954d453",
+        "fetch_kib": 66213073.31, "fetch_factor": 1.99993,
+        "write_kib": 17607598.88, "write_factor": 1.0,
     },
 }
 

@@ -28,7 +28,15 @@ def test_measured_traffic_is_tied_to_the_kernel_sources():
     t = bench.measured_traffic("interp_kick_drift", "tile_1024")
     want = rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
     assert t is None or abs(t - want) < 1.0
-    assert bench.measured_traffic("deposit", "tile_1024") is None
+    assert bench.measured_traffic("resort", "tile_1024") is None  # no record
+    # a record taken on other sources is not used
+    bad = dict(rec, sha256="0" * 64)
+    saved = bench.MEASURED_TRAFFIC[("interp_kick_drift", "tile_1024")]
+    try:
+        bench.MEASURED_TRAFFIC[("interp_kick_drift", "tile_1024")] = bad
+        assert bench.measured_traffic("interp_kick_drift", "tile_1024") is None
+    finally:
+        bench.MEASURED_TRAFFIC[("interp_kick_drift", "tile_1024")] = saved
 
 
 def test_more_than_one_gpu_is_refused():
