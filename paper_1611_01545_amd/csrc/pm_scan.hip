@@ -40,51 +40,90 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, in
   hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Scatter of one digit pass, a tile of up to RS_TILE pairs at a time: each round of
+// RS_THREADS pairs is ranked by a wave multi-split (stable: round, wave, lane), the
+// tile's pairs are placed in LDS in digit order, and then written out in that order, so
+// that a digit's pairs of the tile go to consecutive destinations (one run per digit
+// and tile, instead of one or two pairs per digit and round: the written lines are whole
+// and the scatter of a sort of 1.07 G pairs stops re-fetching them).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
                                                            const uint32_t* vin, int64_t n,
                                                            const int64_t* n_dev, int shift,
                                                            int64_t nblk,
                                                            const int64_t* hoff,
                                                            uint32_t* kout, uint32_t* vout) {
-  __shared__ uint32_t run[256];
+  __shared__ int64_t dbase[256];        // destination of the digit's next pair
+  __shared__ uint32_t tcnt[256];        // the tile's pairs per digit, so far
+  __shared__ int tstart[256];           // their first LDS slot
   __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+  __shared__ int wsum[RS_THREADS / 64];
+  __shared__ uint32_t skey[RS_TILE], sval[RS_TILE];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  run[threadIdx.x] = 0;
   int64_t lo, hi;
   rs_range(n, n_dev, nblk, blockIdx.x, lo, hi);
-  for (int64_t base = lo; base < hi; base += RS_THREADS) {  // uniform across the block
+  dbase[threadIdx.x] = hoff[(int64_t)threadIdx.x * nblk + blockIdx.x];
+  for (int64_t tb = lo; tb < hi; tb += RS_TILE) {  // uniform across the block
+    const int64_t te = tb + RS_TILE < hi ? tb + RS_TILE : hi;
+    tcnt[threadIdx.x] = 0;
+    uint32_t key[RS_ROUNDS], val[RS_ROUNDS], lrank[RS_ROUNDS];
 #pragma unroll
-    for (int q = 0; q < RS_THREADS / 64; ++q) wcnt[q][threadIdx.x] = 0;
-    __syncthreads();
-    int64_t i = base + threadIdx.x;
-    bool valid = i < hi;
-    uint32_t key = valid ? kin[i] : 0u;
-    uint32_t val = valid ? vin[i] : 0u;
-    uint32_t d = (key >> shift) & 255u;
-    uint64_t match = __ballot(valid);
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+      const int64_t i = tb + (int64_t)r * RS_THREADS + threadIdx.x;
+      key[r] = i < te ? kin[i] : 0u;
+      val[r] = i < te ? vin[i] : 0u;
+    }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      uint64_t m = __ballot(valid && ((d >> b) & 1u));
-      match &= ((d >> b) & 1u) ? m : ~m;
-    }
-    uint32_t rank = (uint32_t)__popcll(match & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
-    __syncthreads();
-    if (valid) {
-      uint32_t pre = run[d];
-      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-      int64_t dst = hoff[(int64_t)d * nblk + blockIdx.x] + pre + rank;
-      kout[dst] = key;
-      vout[dst] = val;
-    }
-    __syncthreads();
-    {
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+      const bool valid = tb + (int64_t)r * RS_THREADS + threadIdx.x < te;
+      const uint32_t d = (key[r] >> shift) & 255u;
+#pragma unroll
+      for (int q = 0; q < RS_THREADS / 64; ++q) wcnt[q][threadIdx.x] = 0;
+      __syncthreads();
+      uint64_t match = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t m = __ballot(valid && ((d >> b) & 1u));
+        match &= ((d >> b) & 1u) ? m : ~m;
+      }
+      const uint32_t rank = (uint32_t)__popcll(match & lt);
+      if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+      __syncthreads();
+      if (valid) {
+        uint32_t pre = tcnt[d];
+        for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+        lrank[r] = pre + rank;
+      }
+      __syncthreads();
       uint32_t add = 0;
 #pragma unroll
       for (int q = 0; q < RS_THREADS / 64; ++q) add += wcnt[q][threadIdx.x];
-      run[threadIdx.x] += add;
+      tcnt[threadIdx.x] += add;
     }
+    __syncthreads();
+    // first LDS slot of each digit
+    const int start = pmscan::block_excl_scan_i32((int)tcnt[threadIdx.x], wsum);
+    tstart[threadIdx.x] = start;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+      if (tb + (int64_t)r * RS_THREADS + threadIdx.x < te) {
+        const int slot = tstart[(key[r] >> shift) & 255u] + (int)lrank[r];
+        skey[slot] = key[r];
+        sval[slot] = val[r];
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)(te - tb);
+    for (int slot = threadIdx.x; slot < cnt; slot += RS_THREADS) {
+      const uint32_t k = skey[slot];
+      const uint32_t d = (k >> shift) & 255u;
+      const int64_t dst = dbase[d] + (slot - tstart[d]);
+      kout[dst] = k;
+      vout[dst] = sval[slot];
+    }
+    __syncthreads();
+    dbase[threadIdx.x] += tcnt[threadIdx.x];
     __syncthreads();
   }
 }
