@@ -65,6 +65,7 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
   extern __shared__ unsigned char smem[];
   // compile-time tiles have T r = 16 nodes per side (T = 16 / r)
   const int T = TT ? TT : A.T, R = TT ? 16 : A.R, r = TT ? 16 / TT : A.r;
+  const bool spread = !TT && r == 1;  // the coarse mesh of the two-level force
   const int E = T + 1;              // extended cells per side
   const int NE = E * E * E;
   const int R3 = R * R * R;
@@ -122,20 +123,26 @@ __global__ __launch_bounds__(DEP_THREADS) void k_deposit_tile(DepArgs A, Geom g,
     const int P = pre[NE];
     // U particles per thread per round: their code loads are issued together
     constexpr int U = 2;
+    static_assert(DEP_THREADS * U == 512, "the spread order is a transpose of 8 x 64 slots");
     // the carries count at most 2^16 wraps, i.e. 2^48 weight units per node: segments
     // of 2^21 particles (each adds < 2^27 to a node) are flushed one by one; every
     // tile of a realistic input has a single segment
     constexpr int SEG = 1 << 21;
     for (int s0 = 0;; s0 += SEG) {
       const int s1 = P - s0 > SEG ? s0 + SEG : P;
-      for (int q0 = s0 + (int)threadIdx.x; q0 < s1; q0 += DEP_THREADS * U) {
+      for (int rb = s0; rb < s1; rb += DEP_THREADS * U) {  // uniform across the block
         int eu[U];
         int64_t ju[U];
         uint32_t pb[U][3];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int q = q0 + u * DEP_THREADS;
+          // slot l of the round takes particle l, or, with one mesh cell per compression
+          // cell (8 neutrinos per cell on 8^3 nodes), particle (l % 8) 64 + l / 8: the
+          // lanes of one atomic then hit the nodes of eight different cells instead of
+          // the same eight nodes (spread)
+          const int l = (int)threadIdx.x + u * DEP_THREADS;
+          const int q = rb + (spread ? ((l & 7) << 6) + (l >> 3) : l);
           // extended cell of flat particle q: largest e with pre[e] <= q
           int lo = 0, hi = NE;
           while (hi - lo > 1) {
