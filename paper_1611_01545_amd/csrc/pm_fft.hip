@@ -110,6 +110,17 @@ __device__ __forceinline__ void dft_reg(float2* a) {
         float dx = u.x - w.x, dy = u.y - w.y;
         if constexpr (j == 0) {
           a[i1] = make_float2(dx, dy);
+        } else if constexpr (4 * j == len) {
+          // exp(SIGN 2 pi i / 4) = SIGN i: a swap, no multiply (the products by the
+          // table's 0 and 1 are kept by IEEE rules otherwise)
+          a[i1] = SIGN < 0 ? make_float2(dy, -dx) : make_float2(-dy, dx);
+        } else if constexpr (8 * j == len || 8 * j == 3 * len) {
+          // w = exp(SIGN 2 pi i j / len) = h (1 + SIGN i) at 45 degrees, h (-1 + SIGN i)
+          // at 135, h = 1/sqrt(2): (dx + i dy) w from p = dx - SIGN dy, q = dy + SIGN dx
+          constexpr float h = (float)turn_sin(1, 8);
+          const float p = SIGN < 0 ? dx + dy : dx - dy, q = SIGN < 0 ? dy - dx : dy + dx;
+          if constexpr (8 * j == len) a[i1] = make_float2(h * p, h * q);
+          else a[i1] = SIGN < 0 ? make_float2(h * q, -h * p) : make_float2(-h * q, h * p);
         } else {
           constexpr float wr = (float)turn_cos(j, len);
           constexpr float wi = (float)(SIGN * turn_sin(j, len));
