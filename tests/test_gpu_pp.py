@@ -37,6 +37,25 @@ def _r_soft(wl):
 @pytest.mark.parametrize("seed,n_mesh,n_cell", [(1, 64, 16), (2, 32, 16), (3, 64, 32)])
 def test_pp_accel_matches_oracle(seed, n_mesh, n_cell):
     wl, species = _clustered(seed, n_mesh, n_cell)
+    _check_pp(wl, species, n_mesh, n_cell)
+
+
+def test_pp_accel_dense_brick_matches_oracle():
+    # a brick whose codes exceed what a wave stages in LDS (4 KB: 1365 particles with
+    # 1-byte codes) reads its partners from the stream: a clump of 2400 CDM particles
+    # in one mesh cell
+    wl = small_two_species(16, 64, seed_offset=8, n_cell=16)
+    cdm, nu = wl.species
+    rng = np.random.default_rng(8)
+    x = cdm.x.copy()
+    q = 1.0 / (256 * 16)
+    x[:2400] = np.mod(rng.random(3) + q * rng.uniform(-20, 20, (2400, 3)), 1.0).astype(np.float32)
+    x[x >= 1] = 0
+    species = [types.SimpleNamespace(x=x, v=cdm.v, mass=cdm.mass), nu]
+    _check_pp(wl, species, 64, 16, min_pairs=2000)
+
+
+def _check_pp(wl, species, n_mesh, n_cell, min_pairs=100):
     c = ctx(n_mesh, n_cell)
     st = [c.encode(c.float_species(sp.x, sp.v, sp.mass)) for sp in species]
     pmax = torch.zeros(1, dtype=torch.float32, device=c.device)
@@ -54,7 +73,7 @@ def test_pp_accel_matches_oracle(seed, n_mesh, n_cell):
         assert np.all(err <= 1e-5 * (np.abs(w) + scale)), err.max()
         assert np.array_equal(g_ == 0, w == 0)  # the same particles have partners
         pairs += int(np.count_nonzero(np.any(w != 0, axis=1)))
-    assert pairs > 100
+    assert pairs > min_pairs
     assert float(pmax.item()) == max(float(np.max(np.abs(a.cpu().numpy()))) for a in app)
     # Newton's third law: sum m a = 0 up to float32 rounding
     tot = sum(m * g_.sum(0) for m, g_ in zip(masses, got))
