@@ -4,6 +4,7 @@ single-GPU guard (no GPU needed)."""
 import os
 import subprocess
 import sys
+import types
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -44,3 +45,17 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_dominant_kernel_is_one_template():
+    # at 2048 points the z pass and the y inverse run two kernel templates each: the
+    # roofline goes to the single-template stage with the largest time per step
+    wl = types.SimpleNamespace(n_particles=10 ** 9, species=[0, 1], n_cell=512, n_mesh=2048)
+    st = {k: {"ms_per_step": ms} for k, ms in (("fft_z", 46.8), ("fft_y_inv", 46.1),
+                                               ("fft_x_c2r", 42.8), ("interp_kick_drift", 39.4),
+                                               ("deposit", 23.1), ("resort", 16.7))}
+    assert bench.dominant_kernel_stage(st, 2048, wl) == "fft_x_c2r"
+    assert bench.stage_kernel("fft_x_c2r", 2048) == "k_row_c2r<1024>"
+    assert bench.stage_kernel("fft_z", 1024) == "k_col_zconv<1024, 16, 3, true>"
+    st["fft_z"]["ms_per_step"] = 50.0
+    assert bench.dominant_kernel_stage(st, 1024, wl) == "fft_z"
