@@ -159,45 +159,39 @@ __device__ inline bool codec_fast(const KickArgs& A) {
   return fast;
 }
 
-// One wave kicks up to 64 consecutive particles [jc, min(jc + 64, jend)) of one species
-// in one brick: decode, gather a through `gather(li, f)` (node index inside the brick,
-// CIC fractions), kick, fixed-point drift, new codes. Writes the new codes and the
-// particle's digit (new local cell, or B^3 when it leaves the brick; movers also get
-// their new cell key), counts stayers per new cell and movers in LDS, and folds the
-// wave's extreme velocity codes into smm. No barrier: waves are independent.
+// One lane kicks particle j of one species in one brick (jr: its index from the
+// brick's first particle of that species): decode, gather a through `gather(li, f)`
+// (node index inside the brick, CIC fractions), kick, fixed-point drift, new codes.
+// Writes the new codes and the particle's digit (new local cell, or B^3 when it leaves
+// the brick; movers also get their new cell key), counts stayers per new cell and movers
+// in LDS, and folds the new velocity codes into the lane's running extremes jmn, jmx
+// (reduced over the wave once per kernel, by VelExt). No barrier: waves are
+// independent, and the lanes of a wave may take particles of different bricks. The cell
+// search range [lo0, hi0) spans a power-of-two number of cells.
 // P position bytes and V velocity bytes per axis (P = 1, V = 2: the paper's format).
 template <bool FAST, int P, int V, typename Gather>
-__device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const Geom& g,
-                                  const Codec& cd, int64_t jc, int64_t jend, int64_t l0,
-                                  const uint32_t* rel, int lo0, int hi0, const uint32_t bc[3],
-                                  uint32_t* run, uint32_t* mvc, int* smm, bool& bad,
-                                  Gather gather) {
+__device__ inline void kick_lane(const KickSpecies& S, const KickArgs& A, const Geom& g,
+                                 const Codec& cd, int64_t j, uint32_t jr, const uint32_t* rel,
+                                 int lo0, int hi0, const uint32_t bc[3], uint32_t* run,
+                                 uint32_t* mvc, int& jmn, int& jmx, bool& bad, Gather gather) {
   using PC = typename PosCode<P>::T;
   using VC = typename VelCode<V>::T;
   constexpr int SH = 8 * P, FB = 8 * P + 1;  // offset bits, fractional bits of a mesh cell
   constexpr uint32_t FMASK = (1u << FB) - 1u, OMASK = (1u << SH) - 1u;
   constexpr float UNIT = 1.0f / (float)(1u << FB);
-  const int lane = threadIdx.x & 63;
-  const int64_t j = jc + lane;
   const int B3 = g.B * g.B * g.B;
   const uint32_t mB = (uint32_t)g.B - 1;
-  int jmn = 65536, jmx = -1;
-  if (j < jend) {
-    const uint32_t t3 = 3 * (uint32_t)lane;
-    const PC* pp = (const PC*)S.pos + 3 * jc;
-    const VC* vp = (const VC*)S.vel + 3 * jc;
+  {
+    const PC* pp = (const PC*)S.pos + 3 * j;
+    const VC* vp = (const VC*)S.vel + 3 * j;
     uint32_t pb[3], vc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      pb[a] = pp[t3 + a];
-      vc[a] = vp[t3 + a];
+      pb[a] = pp[a];
+      vc[a] = vp[a];
     }
-    const uint32_t jr = (uint32_t)(j - l0);
-    int lo = lo0, hi = hi0;  // local cell: largest l with rel[l] <= jr
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (rel[mid] <= jr) lo = mid; else hi = mid;
-    }
+    int lo = lo0;  // local cell: largest l in [lo0, hi0) with rel[l] <= jr
+    for (int st = (hi0 - lo0) >> 1; st > 0; st >>= 1) lo += rel[lo + st] <= jr ? st : 0;
     const uint32_t lc[3] = {(uint32_t)lo & mB, ((uint32_t)lo >> g.lgB) & mB,
                             (uint32_t)lo >> (2 * g.lgB)};
     int li[3];
@@ -218,8 +212,8 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
     const int64_t SP = g.S << (8 * (P - 1));  // position steps per box side
     const uint32_t Sm = (uint32_t)SP - 1;
     const double Sd = (double)SP, invS = 1.0 / Sd;  // powers of two
-    PC* tp = (PC*)S.tpos + 3 * jc;
-    VC* tv = (VC*)S.tvel + 3 * jc;
+    PC* tp = (PC*)S.tpos + 3 * j;
+    VC* tv = (VC*)S.tvel + 3 * j;
     uint32_t un[3], nl[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -233,8 +227,8 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
       un[a] = ((((bc[a] + lc[a]) << SH) | pb[a]) + (uint32_t)dm) & Sm;
       nl[a] = (un[a] >> SH) - bc[a];  // new local cell (wraps above B when outside)
       const int jv = FAST ? vel_code_p2_v<V>(v1, cd.ce) : vel_code_v<V>(v1, cd.vmo);
-      tp[t3 + a] = (PC)(un[a] & OMASK);
-      tv[t3 + a] = (VC)jv;
+      tp[a] = (PC)(un[a] & OMASK);
+      tv[a] = (VC)jv;
       jmn = min(jmn, jv);
       jmx = max(jmx, jv);
     }
@@ -248,15 +242,52 @@ __device__ inline void kick_chunk(const KickSpecies& S, const KickArgs& A, const
       atomicAdd(mvc, 1u);
     }
   }
-  for (int d = 32; d >= 1; d >>= 1) {
-    jmn = min(jmn, __shfl_xor(jmn, d, 64));
-    jmx = max(jmx, __shfl_xor(jmx, d, 64));
-  }
-  if (lane == 0 && jmx >= 0) {
-    atomicMin(&smm[0], jmn);
-    atomicMax(&smm[1], jmx);
-  }
 }
+
+// A workgroup-uniform 64-bit value read from LDS, moved to scalar registers.
+__device__ inline int64_t uniform64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Each lane's extreme new velocity codes per species over all the chunks it kicked
+// (statically indexed, so they stay in registers), reduced over the wave and folded into
+// the workgroup's smm[2 s], smm[2 s + 1] once at the end.
+struct VelExt {
+  int mn[MAXSP], mx[MAXSP];
+  __device__ VelExt() {
+#pragma unroll
+    for (int t = 0; t < MAXSP; ++t) {
+      mn[t] = 65536;
+      mx[t] = -1;
+    }
+  }
+  __device__ void fold(int s, int a, int b) {
+#pragma unroll
+    for (int t = 0; t < MAXSP; ++t)
+      if (t == s) {
+        mn[t] = min(mn[t], a);
+        mx[t] = max(mx[t], b);
+      }
+  }
+  __device__ void flush(int n_sp, int* smm) const {
+#pragma unroll
+    for (int t = 0; t < MAXSP; ++t) {
+      if (t >= n_sp) break;
+      int a = mn[t], b = mx[t];
+      for (int d = 32; d >= 1; d >>= 1) {
+        a = min(a, __shfl_xor(a, d, 64));
+        b = max(b, __shfl_xor(b, d, 64));
+      }
+      if ((threadIdx.x & 63) == 0 && b >= 0) {
+        atomicMin(&smm[2 * t], a);
+        atomicMax(&smm[2 * t + 1], b);
+      }
+    }
+  }
+};
 
 // Chunks of 64 particles over a list of segments (one species' particles in one brick,
 // or in one z half of it), dealt to the waves of the workgroup in turn. seg(i) gives
@@ -403,6 +434,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
         }
   };
   bool bad = false;
+  VelExt ext;
   auto run_all = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
     int64_t cbase = 0;  // chunks of the earlier species
@@ -415,14 +447,20 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
       // this wave's chunks of species s: global chunk index = cbase + c, dealt round-robin
       int64_t c = ((int64_t)w - cbase) % NWK;
       if (c < 0) c += NWK;
-      for (; c < nch; c += NWK)
-        kick_chunk<FAST, P, V>(S, A, g, cd, j0 + 64 * c, j1, l0, rel + s * L, 0, B3, bc,
-                         run + s * L, &mvc[s], &smm[2 * s], bad, gather);
+      int jmn = 65536, jmx = -1;
+      for (; c < nch; c += NWK) {
+        const int64_t j = j0 + 64 * c + (threadIdx.x & 63);
+        if (j < j1)
+          kick_lane<FAST, P, V>(S, A, g, cd, j, (uint32_t)(j - l0), rel + s * L, 0, B3, bc,
+                                run + s * L, &mvc[s], jmn, jmx, bad, gather);
+      }
+      ext.fold(s, jmn, jmx);
       cbase += nch;
     }
   };
   if (codec_fast(A)) run_all(std::true_type{});
   else run_all(std::false_type{});
+  ext.flush(n_sp, smm);
   __syncthreads();
   for (int i = threadIdx.x; i < n_sp * L; i += KB) {
     const int s = i / L, l = i - s * L;
@@ -448,7 +486,7 @@ __global__ __launch_bounds__(KB) void k_kick_brick(KickArgs A, Geom g, DevErr* e
 // the others compute.
 constexpr int PR = 16;
 template <int NT, int NZ, int P = 1, int V = 2>  // threads per workgroup, z passes, widths
-__global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
+__global__ __launch_bounds__(NT, 4) void k_kick_pair(KickArgs A, Geom g, DevErr* err) {
   constexpr int KB = NT, NWK = NT / 64;
   constexpr int X1 = 2 * PR + 1, Y1 = PR + 1, Z1 = PR / NZ + 1;
   constexpr int TS = X1 * Y1 * Z1;  // nodes per component
@@ -488,6 +526,7 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
   }
   const bool fast = codec_fast(A);
   bool bad = false;
+  VelExt ext;
 
   // The z passes share their boundary layer: pass h needs node layers 4h..4h+4 (for
   // PR / NZ = 4), pass h + 1 starts at 4h + 4. F holds the Z1 layers as a ring, layer
@@ -577,12 +616,16 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
     __syncthreads();
   };
 
+  // A pass deals 64-particle chunks over each species' particles of the z slice, brick
+  // b0's then brick b0 + 1's (the two ranges are apart in the stream), so that a lane's
+  // brick k is its own: a species with few particles per slice (16 CDM particles per
+  // brick at one per cell) fills one chunk instead of two part-empty ones.
   auto pass = [&](auto fast_tag, int h) {
     constexpr bool FAST = decltype(fast_tag)::value;
-    int64_t cbase = 0;  // chunks of the earlier segments of this pass
-    for (int k = 0; k < 2; ++k) {
-      uint32_t bc[3];
-      key_cell(g, kb0 + (uint32_t)(k * B3), bc[0], bc[1], bc[2]);
+    int64_t cbase = 0;  // chunks of the earlier species of this pass
+    const int lane = threadIdx.x & 63;
+    {
+      int k = 0;  // this lane's brick, set per chunk
       auto gather = [&](const int li[3], const float f[3], float acc3[3]) {
         const int tx = li[0] + k * PR, ty = li[1];
         // ring slots of the node layers tz and tz + 1 (local to this pass)
@@ -606,18 +649,36 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
       };
       for (int s = 0; s < n_sp; ++s) {
         const KickSpecies& S = A.sp[s];
-        const uint32_t* rs = rel + (k * MAXSP + s) * L;
-        const int64_t l0 = l0s[k * MAXSP + s];
-        const int64_t j0 = min(l0 + (int64_t)rs[h * H], S.n);
-        const int64_t j1 = min(l0 + (int64_t)rs[(h + 1) * H], S.n);
-        const int64_t nch = j1 > j0 ? (j1 - j0 + 63) >> 6 : 0;
+        int64_t l0[2], j0[2], nk[2];  // per brick: first particle, slice start, slice size
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          const uint32_t* rs = rel + (kk * MAXSP + s) * L;
+          l0[kk] = uniform64(l0s[kk * MAXSP + s]);
+          j0[kk] = min(l0[kk] + (int64_t)__builtin_amdgcn_readfirstlane(rs[h * H]), S.n);
+          const int64_t j1 =
+              min(l0[kk] + (int64_t)__builtin_amdgcn_readfirstlane(rs[(h + 1) * H]), S.n);
+          nk[kk] = j1 > j0[kk] ? j1 - j0[kk] : 0;
+        }
+        const int64_t nt = nk[0] + nk[1];
+        const int64_t nch = (nt + 63) >> 6;
         const Codec cd = codec_of<V>(S);
         int64_t c = ((int64_t)w - cbase) % NWK;
         if (c < 0) c += NWK;
-        for (; c < nch; c += NWK)
-          kick_chunk<FAST, P, V>(S, A, g, cd, j0 + 64 * c, j1, l0, rs, h * H, (h + 1) * H, bc,
-                           run + (k * MAXSP + s) * L, &mvc[k * MAXSP + s], &smm[2 * s], bad,
-                           gather);
+        int jmn = 65536, jmx = -1;
+        for (; c < nch; c += NWK) {
+          const int64_t q = 64 * c + lane;  // position in the two slices, one after the other
+          if (q < nt) {
+            k = q >= nk[0];
+            const int64_t j = k ? j0[1] + (q - nk[0]) : j0[0] + q;
+            // brick b0 + 1 is brick b0's neighbour along x (b0 even)
+            const uint32_t bc[3] = {bc0[0] + (uint32_t)(k * B), bc0[1], bc0[2]};
+            const int sl = k * MAXSP + s;
+            kick_lane<FAST, P, V>(S, A, g, cd, j, (uint32_t)(j - (k ? l0[1] : l0[0])),
+                                  rel + sl * L, h * H, (h + 1) * H, bc, run + sl * L, &mvc[sl],
+                                  jmn, jmx, bad, gather);
+          }
+        }
+        ext.fold(s, jmn, jmx);
         cbase += nch;
       }
     }
@@ -631,6 +692,7 @@ __global__ __launch_bounds__(NT) void k_kick_pair(KickArgs A, Geom g, DevErr* er
     if (fast) pass(std::true_type{}, h);
     else pass(std::false_type{}, h);
   }
+  ext.flush(n_sp, smm);
   __syncthreads();
   for (int i = threadIdx.x; i < 2 * MAXSP * L; i += KB) {
     const int k = i / (MAXSP * L), rem = i - k * (MAXSP * L);
