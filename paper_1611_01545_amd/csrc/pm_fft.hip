@@ -370,6 +370,18 @@ __device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int
   }
 }
 
+// Workgroups go round-robin over the chip's 8 XCDs (each with its own L2). A workgroup of
+// 8 split-line columns reads and writes 64-byte halves of 128-byte runs; the tile order
+// below gives tiles 2i and 2i + 1 (the two halves) to blocks 16a + r and 16a + 8 + r,
+// which run on the same XCD at about the same time, so that one L2 serves both halves.
+// A bijection of [0, gx) when 16 divides gx (else the identity).
+__device__ __forceinline__ unsigned xcd_pair(unsigned x, unsigned gx) {
+  if (gx % 16u) return x;
+  return (x & ~15u) | ((x & 7u) << 1) | ((x >> 3) & 1u);
+}
+template <int N, int W>
+constexpr bool col_pair() { return LP<N>::H == 2 && W == 8; }
+
 // Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
 // only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
 // inverse y pass). OUT 3 (y lines of the transposed force): out0 = +i k_x FFT_SIGN(in) +
@@ -395,11 +407,12 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
     for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
     __syncthreads();
   }
+  const unsigned bx = col_pair<N, W>() ? xcd_pair(blockIdx.x, gridDim.x) : blockIdx.x;
   // the grid covers the lines exactly (W divides the line count; checked on the host)
   const int c = threadIdx.x % W, tl = threadIdx.x / W;
   const int t = tl % L::T, h = tl / L::T;
   // addresses: a workgroup-uniform 64-bit part plus a 32-bit per-thread offset
-  const int64_t ubase = line_base(d, (int64_t)blockIdx.x * W, blockIdx.y);
+  const int64_t ubase = line_base(d, (int64_t)bx * W, blockIdx.y);
   const int e0 = L::H * t + h;  // natural point of n1 = 0; point n1 is e0 + H T n1
   const uint32_t lo_in = (uint32_t)(c * d.s1 + (int64_t)e0 * d.es);
   // transposed frequency (t + T v) + E k2 + h N/2: per-thread part and k2 stride
@@ -427,7 +440,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
       b[n1] = (in1 + (ubase + (int64_t)L::H * L::T * n1 * d.es))[lo_in];
     line_nat_to_tr<N, SIGN>(a, t, h, my, stw, 1, N - 1);
     line_nat_to_tr<N, SIGN>(b, t, h, my, stw, 1, N - 1);
-    const float kxg = grad_k(gk, d.kx_mode ? d.kx_fixed : (int)(blockIdx.x * W) + c);
+    const float kxg = grad_k(gk, d.kx_mode ? d.kx_fixed : (int)(bx * W) + c);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -510,13 +523,14 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   __shared__ float sgk[N];
   for (int i = threadIdx.x; i < N; i += W * L::TL) sgk[i] = gk[i];
   __syncthreads();
+  const unsigned bx = col_pair<N, W>() ? xcd_pair(blockIdx.x, gridDim.x) : blockIdx.x;
   const int c = threadIdx.x % W, tl = threadIdx.x / W;
   const int t = tl % L::T, h = tl / L::T;
-  const int64_t l1 = (int64_t)blockIdx.x * W + c;
+  const int64_t l1 = (int64_t)bx * W + c;
   // point e0 + H T n1 of the line (e0 = H t + h): z-blocked lines split it as (block,
   // row in block). Addresses are a workgroup-uniform 64-bit part (scalar registers) plus
   // a 32-bit per-thread offset, so that no 64-bit address per point stays live in VGPRs.
-  const int64_t ubase = line_base(d, (int64_t)blockIdx.x * W, blockIdx.y);
+  const int64_t ubase = line_base(d, (int64_t)bx * W, blockIdx.y);
   const int e0 = L::H * t + h;
   const uint32_t toff =
       (uint32_t)(c * d.s1 + (BLK ? (int64_t)(e0 >> LZB) * d.es + (int64_t)(e0 & (ZB - 1)) * d.esl
@@ -1128,20 +1142,15 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
     if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, -1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
-  // Split lines (2048 points) run the two-output passes as two one-output launches, each
-  // at 16 columns per workgroup (128-byte runs) instead of 8: one more read of the input,
-  // against wider accesses in both.
+  // The z pass is one two-output launch at every size (at 2048 points 8 columns per
+  // workgroup, 64-byte runs paired on one XCD: 43.5 ms at 2048^3 against 46.8 ms for two
+  // one-output launches of 16 columns, which read the input twice and transform it four
+  // times instead of three). The y inverse of split lines runs its two outputs as two
+  // one-output launches of 16 columns instead (46.8 against 49.4 ms at 2048^3).
   const bool wide = n >= 2048;
   {
     ProfScope ps(c, ST_FFT_Z);
-    if (wide) {
-      if ((s = d_col_zconv(f, 2, true, A1, nullptr, nullptr, S, nullptr, zm, n)) != PM_OK)
-        return s;
-      if ((s = d_col_zconv(f, 0, true, A1, nullptr, nullptr, A1, nullptr, zm, n)) != PM_OK)
-        return s;
-    } else if ((s = d_col_zconv(f, 3, true, A1, nullptr, nullptr, A1, S, zm, n)) != PM_OK) {
-      return s;
-    }
+    if ((s = d_col_zconv(f, 3, true, A1, nullptr, nullptr, A1, S, zm, n)) != PM_OK) return s;
   }
   if ((s = d_col_zconv(f, 3, false, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
   {
