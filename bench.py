@@ -354,7 +354,7 @@ def stage_kernel(name: str, n: int):
     """The one kernel template a stage's launches run at mesh side n (the bench workloads:
     4 mesh cells per compression cell, bricks of 4^3 cells), or None when the stage runs
     several: a kernel's roofline needs that kernel's own launch duration. The z pass is one
-    two-output template (8 columns per workgroup at 2048 points, 16 below); the y inverse
+    two-output template (4 columns per workgroup at 2048 points, 16 below); the y inverse
     is two (at 2048 points the -i k_y launch and two plain ones, below a two-output and a
     plain one)."""
     split = n >= 2048
@@ -362,7 +362,7 @@ def stage_kernel(name: str, n: int):
         "deposit": "k_deposit_tile<4, 1>",
         "fft_x_r2c": f"k_row_r2c<{n // 2}>",
         "fft_y_fwd": f"k_col_fft<{n}, 16, -1, 0>",
-        "fft_z": f"k_col_zconv<{n}, {8 if split else 16}, 3, true>",
+        "fft_z": f"k_col_zconv<{n}, {4 if split else 16}, 3, true>",
         "fft_x_c2r": f"k_row_c2r<{n // 2}>",
         "interp_kick_drift": "k_kick_pair<256, 4, 1, 2>",
     }.get(name)

@@ -371,16 +371,19 @@ __device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int
 }
 
 // Workgroups go round-robin over the chip's 8 XCDs (each with its own L2). A workgroup of
-// 8 split-line columns reads and writes 64-byte halves of 128-byte runs; the tile order
-// below gives tiles 2i and 2i + 1 (the two halves) to blocks 16a + r and 16a + 8 + r,
-// which run on the same XCD at about the same time, so that one L2 serves both halves.
-// A bijection of [0, gx) when 16 divides gx (else the identity).
-__device__ __forceinline__ unsigned xcd_pair(unsigned x, unsigned gx) {
-  if (gx % 16u) return x;
-  return (x & ~15u) | ((x & 7u) << 1) | ((x >> 3) & 1u);
+// W < 16 split-line columns reads and writes 8W-byte parts of 128-byte runs; the tile
+// order below gives the G = 16 / W tiles Gi .. Gi + G - 1 of a run to the blocks
+// 8Ga + 8b + r, b < G (r = i mod 8, a = i / 8), which run on the same XCD at about the
+// same time, so that one L2 serves the whole run. A bijection of [0, gx) when 8G divides
+// gx (else the identity).
+template <int G>
+__device__ __forceinline__ unsigned xcd_group(unsigned x, unsigned gx) {
+  if (G == 1 || gx % (8u * G)) return x;
+  const unsigned a = x / (8u * G), b = (x / 8u) % G, r = x % 8u;
+  return (8u * G) * a + G * r + b;
 }
 template <int N, int W>
-constexpr bool col_pair() { return LP<N>::H == 2 && W == 8; }
+constexpr int col_group() { return LP<N>::H == 2 && W < 16 ? 16 / W : 1; }
 
 // Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
 // only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
@@ -407,7 +410,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
     for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
     __syncthreads();
   }
-  const unsigned bx = col_pair<N, W>() ? xcd_pair(blockIdx.x, gridDim.x) : blockIdx.x;
+  const unsigned bx = xcd_group<col_group<N, W>()>(blockIdx.x, gridDim.x);
   // the grid covers the lines exactly (W divides the line count; checked on the host)
   const int c = threadIdx.x % W, tl = threadIdx.x / W;
   const int t = tl % L::T, h = tl / L::T;
@@ -523,7 +526,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   __shared__ float sgk[N];
   for (int i = threadIdx.x; i < N; i += W * L::TL) sgk[i] = gk[i];
   __syncthreads();
-  const unsigned bx = col_pair<N, W>() ? xcd_pair(blockIdx.x, gridDim.x) : blockIdx.x;
+  const unsigned bx = xcd_group<col_group<N, W>()>(blockIdx.x, gridDim.x);
   const int c = threadIdx.x % W, tl = threadIdx.x / W;
   const int t = tl % L::T, h = tl / L::T;
   const int64_t l1 = (int64_t)bx * W + c;
@@ -889,6 +892,12 @@ constexpr int col_w() {
   if (w < 1) w = 1;
   return w;
 }
+// the fused z pass with split lines (two line arrays per thread, 225 VGPRs) takes 4
+// columns: 256 threads and 58 KB of LDS, two workgroups per CU
+template <int N, bool TWO>
+constexpr int zconv_w() {
+  return LP<N>::H == 2 && TWO ? 4 : col_w<N, TWO>();
+}
 
 struct FftCtx {
   pm_context* c;
@@ -930,7 +939,7 @@ template <int N>
 pm_status col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0, const float2* i1,
                     const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
   // every fused z pass stages its twiddles; MODE 1 and 3 hold two line arrays
-  constexpr int W1 = col_w<N, false>(), W2 = col_w<N, true>();
+  constexpr int W1 = zconv_w<N, false>(), W2 = zconv_w<N, true>();
   const int W = (mode == 1 || mode == 3) ? W2 : W1;
   if (d.L1 % W) return PM_ERR_SHAPE;
   dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
@@ -1142,10 +1151,10 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
     if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, -1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
-  // The z pass is one two-output launch at every size (at 2048 points 8 columns per
-  // workgroup, 64-byte runs paired on one XCD: 43.5 ms at 2048^3 against 46.8 ms for two
-  // one-output launches of 16 columns, which read the input twice and transform it four
-  // times instead of three). The y inverse of split lines runs its two outputs as two
+  // The z pass is one two-output launch at every size (at 2048 points 4 columns per
+  // workgroup, the parts of a 128-byte run grouped on one XCD: 42.4 ms at 2048^3 against
+  // 46.8 ms for two one-output launches of 16 columns, which read the input twice and
+  // transform it four times instead of three). The y inverse of split lines runs its two outputs as two
   // one-output launches of 16 columns instead (46.8 against 49.4 ms at 2048^3).
   const bool wide = n >= 2048;
   {

@@ -55,7 +55,7 @@ def test_dominant_kernel_is_one_template():
                                                ("fft_x_c2r", 38.7), ("interp_kick_drift", 38.0),
                                                ("deposit", 23.1), ("resort", 16.7))}
     assert bench.dominant_kernel_stage(st, 2048, wl) == "fft_z"
-    assert bench.stage_kernel("fft_z", 2048) == "k_col_zconv<2048, 8, 3, true>"
+    assert bench.stage_kernel("fft_z", 2048) == "k_col_zconv<2048, 4, 3, true>"
     assert bench.stage_kernel("fft_y_inv", 2048) is None
     assert bench.stage_kernel("fft_x_c2r", 2048) == "k_row_c2r<1024>"
     assert bench.stage_kernel("fft_z", 1024) == "k_col_zconv<1024, 16, 3, true>"
