@@ -289,3 +289,43 @@ def test_row_pass_shuffle_partners(n):
                     ip = (V - 1 - v) * T + (T - 1 - k2)
                     kp = (tp + T * (ip // T)) + E * (ip % T)
                     assert kp == M - k
+
+
+def xcd_group(x, gx, G):
+    """Tile of block x in a grid of gx blocks (the column passes' XCD-aware order): the G
+    tiles G i .. G i + G - 1 of one 128-byte run go to blocks 8 G a + 8 b + r (b < G,
+    r = i mod 8, a = i / 8); the identity unless 8 G divides gx."""
+    if G == 1 or gx % (8 * G):
+        return x
+    a, b, r = x // (8 * G), (x // 8) % G, x % 8
+    return 8 * G * a + G * r + b
+
+
+def col_group(n, W):
+    return 16 // W if n >= 2048 and W < 16 else 1
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind", ["y_main", "y_nyq", "z_main", "z_nyq"])
+def test_xcd_tile_order(n, kind):
+    # workgroups are dispatched round-robin over 8 XCDs (block x on XCD x mod 8 when 8
+    # divides the grid's x extent); the reordered tiles must cover the lines once, and the
+    # G tiles of a 128-byte run must share an XCD and be dispatched within 8 G blocks
+    d = lines(kind, n)
+    L1 = d[6]
+    for W in widths(n):
+        if L1 % W:
+            continue
+        gx, G = L1 // W, col_group(n, W)
+        tiles = [xcd_group(x, gx, G) for x in range(gx)]
+        assert sorted(tiles) == list(range(gx))
+        if G > 1 and gx % (8 * G) == 0:
+            blocks_of_run = {}
+            for x, t in enumerate(tiles):
+                blocks_of_run.setdefault(t // G, []).append(x)
+            for xs in blocks_of_run.values():
+                assert len(xs) == G
+                assert len({x % 8 for x in xs}) == 1
+                assert max(xs) - min(xs) < 8 * G
+            # a run is G W columns of 8 bytes: 128 bytes
+            assert G * W * 8 == 128
