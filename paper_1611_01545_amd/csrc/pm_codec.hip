@@ -131,31 +131,40 @@ struct CountSrc {
   }
 };
 
+// Per block of T256 cells: the byte counts, and the block's number of escapes in bcnt.
 __global__ __launch_bounds__(T256) void k_count_bytes(CountSrc src, int64_t ncell,
-                                                     uint8_t* count, uint32_t* flag) {
-  int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
-  if (i >= ncell) return;
-  uint32_t c = src(i);
-  count[i] = (uint8_t)(c >= 255u ? 255u : c);
-  flag[i] = c >= 255u ? 1u : 0u;
+                                                     uint8_t* count, uint32_t* bcnt) {
+  const int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  const uint32_t c = i < ncell ? src(i) : 0u;
+  if (i < ncell) count[i] = (uint8_t)(c >= 255u ? 255u : c);
+  const int ne = __syncthreads_count(c >= 255u);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = (uint32_t)ne;
 }
 
-__global__ __launch_bounds__(T256) void k_escapes(CountSrc src, int64_t ncell,
-                                                 const int64_t* foff, uint64_t* esc,
-                                                 int64_t cap, pm_shdr* h, DevErr* err) {
-  int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
-  if (i == 0) {
-    int64_t ne = foff[ncell];
+// The escape table in cell order: one thread per block of T256 cells writes that block's
+// escapes from boff[b] (the exclusive prefix of the block counts, boff[nb] the total);
+// blocks without escapes, nearly all of them, read one word.
+__global__ __launch_bounds__(T256) void k_escapes(CountSrc src, int64_t ncell, int64_t nb,
+                                                 const uint32_t* bcnt, const int64_t* boff,
+                                                 uint64_t* esc, int64_t cap, pm_shdr* h,
+                                                 DevErr* err) {
+  const int64_t b = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (b == 0) {
+    const int64_t ne = boff[nb];
     h->n_esc = ne;
     if (ne > cap) latch_error(err, ERRBIT_CAPACITY, ne);
   }
-  if (i >= ncell) return;
-  uint32_t c = src(i);
-  if (c >= 255u) {
-    int64_t k = foff[i];
-    if (k < cap) {
-      esc[2 * k] = (uint64_t)i;
-      esc[2 * k + 1] = (uint64_t)c;
+  if (b >= nb || bcnt[b] == 0) return;
+  int64_t k = boff[b];
+  const int64_t i1 = min((b + 1) * T256, ncell);
+  for (int64_t i = b * T256; i < i1; ++i) {
+    const uint32_t c = src(i);
+    if (c >= 255u) {
+      if (k < cap) {
+        esc[2 * k] = (uint64_t)i;
+        esc[2 * k + 1] = (uint64_t)c;
+      }
+      ++k;
     }
   }
 }
@@ -480,18 +489,18 @@ pm_status scan_counts_into(pm_context* c, const pm_species* sp, int64_t* off, in
 pm_status run_finalize_counts(pm_context* c, const uint32_t* cnt32, const uint64_t* cnt64,
                               pm_species* out) {
   const int64_t nc3 = c->g.ncell3;
-  uint32_t* flag = (uint32_t*)scratch(c, SC_FLAG, (size_t)nc3 * 4);
-  int64_t* foff = (int64_t*)scratch(c, SC_FOFF, (size_t)(nc3 + 1) * 8);
-  if (!flag || !foff) return PM_ERR_NOMEM;
+  const int64_t nb = cdiv(nc3, T256);  // blocks of T256 cells
+  uint32_t* bcnt = (uint32_t*)scratch(c, SC_FLAG, (size_t)nb * 4);
+  int64_t* boff = (int64_t*)scratch(c, SC_FOFF, (size_t)(nb + 1) * 8);
+  if (!bcnt || !boff) return PM_ERR_NOMEM;
   CountSrc src{cnt32, cnt64};
-  unsigned nb = (unsigned)cdiv(nc3, T256);
-  hipLaunchKernelGGL(k_count_bytes, dim3(nb), dim3(T256), 0, c->stream, src, nc3, out->count,
-                     flag);
+  hipLaunchKernelGGL(k_count_bytes, dim3((unsigned)nb), dim3(T256), 0, c->stream, src, nc3,
+                     out->count, bcnt);
   PM_LAUNCH_CHECK();
-  pm_status s = scan_u32(c, flag, nc3, foff);
+  pm_status s = scan_u32(c, bcnt, nb, boff);
   if (s != PM_OK) return s;
-  hipLaunchKernelGGL(k_escapes, dim3(nb), dim3(T256), 0, c->stream, src, nc3, foff, out->esc,
-                     out->cap_esc, out->hdr, c->err);
+  hipLaunchKernelGGL(k_escapes, dim3((unsigned)cdiv(nb, T256)), dim3(T256), 0, c->stream, src,
+                     nc3, nb, bcnt, boff, out->esc, out->cap_esc, out->hdr, c->err);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
