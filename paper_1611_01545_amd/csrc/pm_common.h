@@ -153,7 +153,7 @@ struct ProfScope {
 
 enum ScratchId {
   SC_OFF = 0,      // int64 [ncell3+1] cell offsets (species A)
-  SC_OFF2,         // int64 [ncell3+1] new cell offsets
+  SC_OFF2,         // int64 [nbrick+1] first new stream position of each brick (re-sort)
   SC_CNT,          // uint64 [ncell3] counts (stay | arrivals-before << 32)
   SC_BSUM,         // int64 block sums for scans
   SC_KEYA,         // uint32 [N]
@@ -168,8 +168,8 @@ enum ScratchId {
   SC_MCNT,         // uint32 [nbrick] movers per brick
   SC_MOFF,         // int64 [nbrick+1]
   SC_ACC64,        // uint64 [ng^3] fixed-point accumulator (float layout deposit)
-  SC_FLAG,         // uint32 [ncell3] escape flags / misc
-  SC_FOFF,         // int64 [ncell3+1] flag offsets
+  SC_FLAG,         // uint32: escape counts per block of cells / misc
+  SC_FOFF,         // int64: their offsets / misc
   SC_MISC,         // small
   SC_VJP,          // float [3][ng^3] adjoint meshes
   SC_VJP2,         // decoded positions of compressed species (adjoint)
@@ -186,6 +186,7 @@ enum ScratchId {
   SC_PPMAX,        // per-workgroup max |a| of the PP force
   SC_PPACC,        // float [N][3] PP accelerations of pm_step_pp
   SC_LRACC,        // float [N][3] long-range accelerations of pm_step_p3m
+  SC_BTOT,         // uint32 [nbrick] new particles per brick (re-sort)
   SC_N
 };
 

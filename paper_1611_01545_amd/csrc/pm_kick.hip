@@ -790,7 +790,7 @@ __global__ __launch_bounds__(64 * WB) void k_compact_movers(
 template <int P = 1, int V = 2>  // code widths
 __global__ __launch_bounds__(64 * WB) void k_place_stayers(
     const int64_t* off_in, const uint16_t* tdig, const void* tpos_, const void* tvel_,
-    const uint64_t* cnt, const int64_t* off_new, int B3, int nbits, int64_t nbrick,
+    const uint64_t* cnt, const int64_t* bstart, int B3, int nbits, int64_t nbrick,
     const uint32_t* skey, const uint32_t* sidx, const int64_t* astart,
     void* pos_, void* vel_, int64_t* perm, int64_t n, DevErr* err) {
   using PC = typename PosCode<P>::T;
@@ -807,9 +807,24 @@ __global__ __launch_bounds__(64 * WB) void k_place_stayers(
   if (b >= nbrick) return;  // the whole wave
   const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
   const int64_t kbase = b * B3;
-  for (int l = lane; l < B3; l += 64) {
-    dbase[l] = off_new[kbase + l] + (int64_t)(cnt[kbase + l] >> 32);
-    run[l] = 0;
+  // new cell offsets of the brick: its first new position bstart[b] plus the exclusive
+  // prefix of its cells' new counts (low 32 bits of cnt); stayers of a cell follow its
+  // arrivals from earlier bricks (high 32 bits)
+  int64_t carry = bstart[b];
+  for (int l0 = 0; l0 < B3; l0 += 64) {
+    const int l = l0 + lane;
+    const uint64_t cv = l < B3 ? cnt[kbase + l] : 0ull;
+    const uint32_t x = (uint32_t)cv;
+    uint32_t inc = x;  // inclusive prefix over the 64 lanes
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
+    }
+    if (l < B3) {
+      dbase[l] = carry + (int64_t)(inc - x) + (int64_t)(cv >> 32);
+      run[l] = 0;
+    }
+    carry += (int64_t)__shfl(inc, 63, 64);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -877,7 +892,8 @@ __global__ __launch_bounds__(64 * WB) void k_place_stayers(
       const int64_t before = (int64_t)(cv >> 32), total = (int64_t)(cv & 0xffffffffull);
       const int64_t stay = total - (ge - gs);
       const int64_t jg = s - gs;
-      const int64_t dst = off_new[k] + (jg < before ? jg : stay + jg);
+      // the cell's new offset is its stayers' base less the arrivals that precede them
+      const int64_t dst = dbase[k - kbase] - before + (jg < before ? jg : stay + jg);
       const int64_t j = sidx[s];
       if (dst < 0 || dst >= n || j < 0 || j >= n) {
         latch_error(err, ERRBIT_CORRUPT);
@@ -894,6 +910,19 @@ __global__ __launch_bounds__(64 * WB) void k_place_stayers(
 }
 
 __global__ void k_read_total(const int64_t* moff, int64_t nb, int64_t* out) { *out = moff[nb]; }
+
+// New particles of each brick: its old particles less its movers, plus its arrivals (the
+// brick's run [astart[b], astart[b + 1]) of the sorted movers); their scan gives each
+// brick's first new stream position, so that no scan over all cells is needed.
+__global__ __launch_bounds__(KT) void k_brick_totals(const int64_t* off_in, const uint32_t* mcnt,
+                                                    const int64_t* astart, int B3,
+                                                    int64_t nbrick, int64_t n, uint32_t* tot) {
+  const int64_t b = (int64_t)blockIdx.x * KT + threadIdx.x;
+  if (b >= nbrick) return;
+  const int64_t j0 = min(off_in[b * B3], n), j1 = min(off_in[(b + 1) * B3], n);
+  const int64_t t = (j1 > j0 ? j1 - j0 : 0) - (int64_t)mcnt[b] + (astart[b + 1] - astart[b]);
+  tot[b] = (uint32_t)(t > 0 ? t : 0);
+}
 
 }  // namespace
 
@@ -927,7 +956,8 @@ static pm_status kick_compressed_t(pm_context* c, const pm_species* in, pm_speci
   nbase[n_sp] = ntot;
   const size_t nn = (size_t)(ntot > 0 ? ntot : 1);
   uint64_t* cnt = (uint64_t*)scratch(c, SC_CNT, (size_t)g.ncell3 * 8 * n_sp);
-  int64_t* off_new = (int64_t*)scratch(c, SC_OFF2, (size_t)(g.ncell3 + 1) * 8);
+  int64_t* bstart = (int64_t*)scratch(c, SC_OFF2, (size_t)(g.nbrick + 1) * 8);
+  uint32_t* btot = (uint32_t*)scratch(c, SC_BTOT, (size_t)g.nbrick * 4);
   char* tpos = (char*)scratch(c, SC_TPOS, nn * 3 * P);
   char* tvel = (char*)scratch(c, SC_TVEL, nn * 3 * V);
   uint16_t* tdig = (uint16_t*)scratch(c, SC_TDST, nn * 2);
@@ -938,7 +968,7 @@ static pm_status kick_compressed_t(pm_context* c, const pm_species* in, pm_speci
   uint32_t* mcnt = (uint32_t*)scratch(c, SC_MCNT, (size_t)g.nbrick * 4 * n_sp);
   int64_t* moff = (int64_t*)scratch(c, SC_MOFF, (size_t)(g.nbrick + 1) * 8);
   int32_t* part = (int32_t*)scratch(c, SC_PARTS, (size_t)g.nbrick * 8 * n_sp);
-  if (!cnt || !off_new || !tpos || !tvel || !tdig || !mkey || !midx || !skey || !sidx ||
+  if (!cnt || !bstart || !btot || !tpos || !tvel || !tdig || !mkey || !midx || !skey || !sidx ||
       !mcnt || !moff || !part)
     return PM_ERR_NOMEM;
   KickArgs A{};
@@ -1030,12 +1060,15 @@ static pm_status kick_compressed_t(pm_context* c, const pm_species* in, pm_speci
     hipLaunchKernelGGL(k_brick_arrivals, dim3((unsigned)cdiv(g.nbrick + 1, KT)), dim3(KT), 0,
                        c->stream, sk, nmd, B3, g.nbrick, moff);
     PM_LAUNCH_CHECK();
-    st = scan_u64lo(c, S.cnt, g.ncell3, off_new);
+    hipLaunchKernelGGL(k_brick_totals, dim3((unsigned)cdiv(g.nbrick, KT)), dim3(KT), 0,
+                       c->stream, S.off, S.mcnt, moff, B3, g.nbrick, n, btot);
+    PM_LAUNCH_CHECK();
+    st = scan_u32(c, btot, g.nbrick, bstart);
     if (st != PM_OK) return st;
     int64_t* pm = perm ? perm[s] : nullptr;
     hipLaunchKernelGGL((k_place_stayers<P, V>), dim3((unsigned)cdiv(g.nbrick, WB)),
                        dim3(64 * WB), place_lds, c->stream, S.off, S.tdig,
-                       (const void*)S.tpos, (const void*)S.tvel, S.cnt, off_new, B3,
+                       (const void*)S.tpos, (const void*)S.tvel, S.cnt, bstart, B3,
                        3 * g.lgB, g.nbrick, sk, si, moff, (void*)out[s].pos,
                        (void*)out[s].vel, pm, n, c->err);
     PM_LAUNCH_CHECK();
