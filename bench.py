@@ -59,49 +59,49 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "d8eb32282c109618dfd5050b0e92ddc30689fda28dded15b88304163610cb36e",
-        "fetch_kib": 509621.00, "fetch_factor": 1.99989,
-        "write_kib": 4195393.50, "write_factor": 1.0,
+        "sha256": "77daf695b28dd1c3a3a1d49a6992e6cfb2849c814ab3b4a2d3cdb04413beca77",
+        "fetch_kib": 509628.88, "fetch_factor": 1.99990,
+        "write_kib": 4195273.81, "write_factor": 1.0,
     },
     ("fft_x_r2c", "tile_1024"): {
         "kernel": "k_row_r2c<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 2097303.75, "fetch_factor": 1.99989,
-        "write_kib": 4202749.41, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 2097308.62, "fetch_factor": 1.99990,
+        "write_kib": 4202745.44, "write_factor": 1.0,
     },
     ("fft_y_fwd", "tile_1024"): {
         "kernel": "k_col_fft<1024, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 2097341.00, "fetch_factor": 1.99989,
-        "write_kib": 4194304.00, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 2097336.00, "fetch_factor": 1.99990,
+        "write_kib": 4194304.12, "write_factor": 1.0,
     },
     ("fft_z", "tile_1024"): {
         "kernel": "k_col_zconv<1024, 16, 3, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 2633553.94, "fetch_factor": 1.99989,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 2633480.56, "fetch_factor": 1.99990,
         "write_kib": 8388608.00, "write_factor": 1.0,
     },
     ("fft_y_inv", "tile_1024"): {
         "kernel": "k_col_fft<1024, 16, 1, 2> + k_col_fft<1024, 16, 1, 0>, per scope",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 2099785.66, "fetch_factor": 1.99989,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 2099684.78, "fetch_factor": 1.99990,
         "write_kib": 6291456.00, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
         "kernel": "k_row_c2r<512>, mean of three",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 2121035.21, "fetch_factor": 1.99989,
-        "write_kib": 4196693.16, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 2121014.96, "fetch_factor": 1.99990,
+        "write_kib": 4196661.75, "write_factor": 1.0,
     },
     ("interp_kick_drift", "tile_1024"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -109,9 +109,9 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "855215514f23299f9b2c4421a163d22c6c6ec27454d725c31d3f7704d0400cda",
-        "fetch_kib": 8190380.38, "fetch_factor": 1.99989,
-        "write_kib": 2258613.19, "write_factor": 1.0,
+        "sha256": "6db1dbf185f2bdd098c42bb815dc13f3197fd023486fc7daeeac1e55481af195",
+        "fetch_kib": 8187862.94, "fetch_factor": 1.99990,
+        "write_kib": 2258578.66, "write_factor": 1.0,
     },
     ("deposit", "large_2048"): {
         "kernel": "k_deposit_tile<4, 1>",
@@ -119,49 +119,49 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "d8eb32282c109618dfd5050b0e92ddc30689fda28dded15b88304163610cb36e",
-        "fetch_kib": 4111421.06, "fetch_factor": 1.99990,
-        "write_kib": 33555678.19, "write_factor": 1.0,
+        "sha256": "77daf695b28dd1c3a3a1d49a6992e6cfb2849c814ab3b4a2d3cdb04413beca77",
+        "fetch_kib": 4074235.12, "fetch_factor": 1.99990,
+        "write_kib": 33555608.50, "write_factor": 1.0,
     },
     ("fft_x_r2c", "large_2048"): {
         "kernel": "k_row_r2c<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 16778401.56, "fetch_factor": 1.99990,
-        "write_kib": 33587752.16, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 16778401.25, "fetch_factor": 1.99990,
+        "write_kib": 33587768.69, "write_factor": 1.0,
     },
     ("fft_y_fwd", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 16818047.06, "fetch_factor": 1.99990,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 16816836.19, "fetch_factor": 1.99990,
         "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_z", "large_2048"): {
-        "kernel": "k_col_zconv<2048, 8, 3, true>",
+        "kernel": "k_col_zconv<2048, 4, 3, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 21171449.56, "fetch_factor": 1.99990,
-        "write_kib": 73089156.00, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 21662590.81, "fetch_factor": 1.99990,
+        "write_kib": 84198297.22, "write_factor": 1.0,
     },
     ("fft_y_inv", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 25223786.41, "fetch_factor": 1.99990,
-        "write_kib": 50379596.09, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 25223737.28, "fetch_factor": 1.99990,
+        "write_kib": 50379867.44, "write_factor": 1.0,
     },
     ("fft_x_c2r", "large_2048"): {
         "kernel": "k_row_c2r<1024>, mean of three",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "7516a0759b92618b99131c1295b2f9ee0b4320e7b9c55bda170e92045ce55fd2",
-        "fetch_kib": 16788731.23, "fetch_factor": 1.99990,
-        "write_kib": 33573498.61, "write_factor": 1.0,
+        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "fetch_kib": 16788718.46, "fetch_factor": 1.99990,
+        "write_kib": 33573536.99, "write_factor": 1.0,
     },
     ("interp_kick_drift", "large_2048"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -169,9 +169,9 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "855215514f23299f9b2c4421a163d22c6c6ec27454d725c31d3f7704d0400cda",
-        "fetch_kib": 65892392.44, "fetch_factor": 1.99990,
-        "write_kib": 18034810.41, "write_factor": 1.0,
+        "sha256": "6db1dbf185f2bdd098c42bb815dc13f3197fd023486fc7daeeac1e55481af195",
+        "fetch_kib": 66429765.19, "fetch_factor": 1.99990,
+        "write_kib": 17960947.66, "write_factor": 1.0,
     },
 }
 
