@@ -31,8 +31,11 @@ struct GetCount {
   const uint64_t* esc;
   const pm_shdr* hdr;
   __device__ int64_t operator()(int64_t i) const {
-    uint32_t c = count[i];
-    if (c != 255u) return c;
+    const uint32_t c = count[i];
+    return c != 255u ? (int64_t)c : escaped(i);
+  }
+  // the full count of a cell whose byte is 255, from the escape table
+  __device__ int64_t escaped(int64_t i) const {
     int64_t lo = 0, hi = hdr->n_esc;  // binary search (esc sorted by cell)
     while (lo < hi) {
       int64_t mid = (lo + hi) >> 1;
@@ -42,6 +45,29 @@ struct GetCount {
     return 255;  // inconsistent table: treated as 255 (sum check flags it)
   }
 };
+
+// Element access in two phases: each getter's plain load first, then what needs the loaded
+// value (GetCount's escape lookup), so that a thread issues the loads of all its items
+// before it uses any (with a branch between them the compiler waited for each load).
+template <typename Get>
+struct Phase {
+  using R = int64_t;
+  __device__ static R raw(const Get& g, int64_t i) { return g(i); }
+  __device__ static int64_t fix(const Get&, int64_t, R r) { return r; }
+};
+template <>
+struct Phase<GetCount> {
+  using R = uint32_t;
+  __device__ static R raw(const GetCount& g, int64_t i) { return g.count[i]; }
+  __device__ static int64_t fix(const GetCount& g, int64_t i, R c) {
+    return c != 255u ? (int64_t)c : g.escaped(i);
+  }
+};
+
+// LDS index of tile element e with one pad word per SCAN_ITEMS: a thread's SCAN_ITEMS
+// consecutive elements then start 17 words apart, not 16 (which put every lane on the
+// same banks)
+__device__ inline int scan_pad(int e) { return e + e / SCAN_ITEMS; }
 
 __device__ inline int64_t wave_incl_scan(int64_t v) {
   const int lane = threadIdx.x & 63;
@@ -104,12 +130,19 @@ template <typename Get>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(Get g, int64_t n,
                                                               int64_t* bsum) {
   __shared__ int64_t lw[SCAN_THREADS / 64 + 1];
-  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  int64_t s = 0;
-#pragma unroll 4
+  using PH = Phase<Get>;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  typename PH::R r[SCAN_ITEMS];
+#pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int64_t i = base + k * SCAN_THREADS + threadIdx.x;
-    if (i < n) s += g(i);
+    const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+    r[k] = PH::raw(g, i < n ? i : n - 1);  // n > 0 whenever a block runs
+  }
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+    if (i < n) s += PH::fix(g, i, r[k]);
   }
   int64_t tot;
   block_excl_scan(s, lw, &tot);
@@ -135,12 +168,22 @@ template <typename Get>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(Get g, int64_t n,
                                                             const int64_t* bsum,
                                                             int64_t* out) {
-  __shared__ int64_t vals[SCAN_TILE];
+  __shared__ int64_t vals[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
   __shared__ int64_t lw[SCAN_THREADS / 64 + 1];
-  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int64_t i = base + k * SCAN_THREADS + threadIdx.x;
-    vals[k * SCAN_THREADS + threadIdx.x] = i < n ? g(i) : 0;
+  using PH = Phase<Get>;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  {
+    typename PH::R r[SCAN_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+      r[k] = PH::raw(g, i < n ? i : n - 1);  // n > 0 whenever a block runs
+    }
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+      vals[scan_pad(k * SCAN_THREADS + threadIdx.x)] = i < n ? PH::fix(g, i, r[k]) : 0;
+    }
   }
   __syncthreads();
   int64_t loc[SCAN_ITEMS];
@@ -148,17 +191,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(Get g, int64_t n,
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     loc[k] = s;
-    s += vals[threadIdx.x * SCAN_ITEMS + k];
+    s += vals[scan_pad(threadIdx.x * SCAN_ITEMS + k)];
   }
   int64_t ex = block_excl_scan(s, lw, nullptr);
   int64_t off = bsum[blockIdx.x] + ex;
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) vals[threadIdx.x * SCAN_ITEMS + k] = off + loc[k];
+  for (int k = 0; k < SCAN_ITEMS; ++k) vals[scan_pad(threadIdx.x * SCAN_ITEMS + k)] = off + loc[k];
   __syncthreads();
+#pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int64_t i = base + k * SCAN_THREADS + threadIdx.x;
-    if (i < n) out[i] = vals[k * SCAN_THREADS + threadIdx.x];
+    const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+    if (i < n) out[i] = vals[scan_pad(k * SCAN_THREADS + threadIdx.x)];
   }
 }
 
