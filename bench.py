@@ -59,32 +59,32 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "77daf695b28dd1c3a3a1d49a6992e6cfb2849c814ab3b4a2d3cdb04413beca77",
-        "fetch_kib": 509628.88, "fetch_factor": 1.99990,
-        "write_kib": 4195273.81, "write_factor": 1.0,
+        "sha256": "e57d8ef1bb500837b2346c4c10e22c7652ae39f7d1b32f9533c1198416ab5f13",
+        "fetch_kib": 509484.44, "fetch_factor": 1.99991,
+        "write_kib": 4195057.31, "write_factor": 1.0,
     },
     ("fft_x_r2c", "tile_1024"): {
         "kernel": "k_row_r2c<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 2097308.62, "fetch_factor": 1.99990,
-        "write_kib": 4202745.44, "write_factor": 1.0,
+        "fetch_kib": 2097308.81, "fetch_factor": 1.99991,
+        "write_kib": 4202764.06, "write_factor": 1.0,
     },
     ("fft_y_fwd", "tile_1024"): {
         "kernel": "k_col_fft<1024, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 2097336.00, "fetch_factor": 1.99990,
-        "write_kib": 4194304.12, "write_factor": 1.0,
+        "fetch_kib": 2097353.88, "fetch_factor": 1.99991,
+        "write_kib": 4194304.25, "write_factor": 1.0,
     },
     ("fft_z", "tile_1024"): {
         "kernel": "k_col_zconv<1024, 16, 3, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 2633480.56, "fetch_factor": 1.99990,
+        "fetch_kib": 2632786.31, "fetch_factor": 1.99991,
         "write_kib": 8388608.00, "write_factor": 1.0,
     },
     ("fft_y_inv", "tile_1024"): {
@@ -92,7 +92,7 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 2099684.78, "fetch_factor": 1.99990,
+        "fetch_kib": 2099723.41, "fetch_factor": 1.99991,
         "write_kib": 6291456.00, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
@@ -100,8 +100,8 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 2121014.96, "fetch_factor": 1.99990,
-        "write_kib": 4196661.75, "write_factor": 1.0,
+        "fetch_kib": 2121053.69, "fetch_factor": 1.99991,
+        "write_kib": 4196639.47, "write_factor": 1.0,
     },
     ("interp_kick_drift", "tile_1024"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -109,9 +109,9 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "6db1dbf185f2bdd098c42bb815dc13f3197fd023486fc7daeeac1e55481af195",
-        "fetch_kib": 8187862.94, "fetch_factor": 1.99990,
-        "write_kib": 2258578.66, "write_factor": 1.0,
+        "sha256": "437cc566a89a502efbac922bd7296c781f38386a5ba0df6fb01d777150c59b30",
+        "fetch_kib": 8183697.75, "fetch_factor": 1.99991,
+        "write_kib": 2258109.12, "write_factor": 1.0,
     },
     ("deposit", "large_2048"): {
         "kernel": "k_deposit_tile<4, 1>",
@@ -119,24 +119,24 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "77daf695b28dd1c3a3a1d49a6992e6cfb2849c814ab3b4a2d3cdb04413beca77",
-        "fetch_kib": 4074235.12, "fetch_factor": 1.99990,
-        "write_kib": 33555608.50, "write_factor": 1.0,
+        "sha256": "e57d8ef1bb500837b2346c4c10e22c7652ae39f7d1b32f9533c1198416ab5f13",
+        "fetch_kib": 4073997.38, "fetch_factor": 1.99991,
+        "write_kib": 33555551.94, "write_factor": 1.0,
     },
     ("fft_x_r2c", "large_2048"): {
         "kernel": "k_row_r2c<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 16778401.25, "fetch_factor": 1.99990,
-        "write_kib": 33587768.69, "write_factor": 1.0,
+        "fetch_kib": 16778450.19, "fetch_factor": 1.99991,
+        "write_kib": 33587762.97, "write_factor": 1.0,
     },
     ("fft_y_fwd", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 16816836.19, "fetch_factor": 1.99990,
+        "fetch_kib": 16817560.25, "fetch_factor": 1.99991,
         "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_z", "large_2048"): {
@@ -144,24 +144,24 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 21662590.81, "fetch_factor": 1.99990,
-        "write_kib": 84198297.22, "write_factor": 1.0,
+        "fetch_kib": 21600719.19, "fetch_factor": 1.99991,
+        "write_kib": 82437744.69, "write_factor": 1.0,
     },
     ("fft_y_inv", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 25223737.28, "fetch_factor": 1.99990,
-        "write_kib": 50379867.44, "write_factor": 1.0,
+        "fetch_kib": 25223424.53, "fetch_factor": 1.99991,
+        "write_kib": 50378232.62, "write_factor": 1.0,
     },
     ("fft_x_c2r", "large_2048"): {
         "kernel": "k_row_c2r<1024>, mean of three",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
         "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
-        "fetch_kib": 16788718.46, "fetch_factor": 1.99990,
-        "write_kib": 33573536.99, "write_factor": 1.0,
+        "fetch_kib": 16788719.65, "fetch_factor": 1.99991,
+        "write_kib": 33573340.29, "write_factor": 1.0,
     },
     ("interp_kick_drift", "large_2048"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -169,9 +169,9 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "6db1dbf185f2bdd098c42bb815dc13f3197fd023486fc7daeeac1e55481af195",
-        "fetch_kib": 66429765.19, "fetch_factor": 1.99990,
-        "write_kib": 17960947.66, "write_factor": 1.0,
+        "sha256": "437cc566a89a502efbac922bd7296c781f38386a5ba0df6fb01d777150c59b30",
+        "fetch_kib": 65930780.81, "fetch_factor": 1.99991,
+        "write_kib": 18014930.00, "write_factor": 1.0,
     },
 }
 
