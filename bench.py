@@ -67,7 +67,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_row_r2c<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 2097308.81, "fetch_factor": 1.99991,
         "write_kib": 4202764.06, "write_factor": 1.0,
     },
@@ -75,7 +75,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_col_fft<1024, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 2097353.88, "fetch_factor": 1.99991,
         "write_kib": 4194304.25, "write_factor": 1.0,
     },
@@ -83,7 +83,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_col_zconv<1024, 16, 3, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 2632786.31, "fetch_factor": 1.99991,
         "write_kib": 8388608.00, "write_factor": 1.0,
     },
@@ -91,7 +91,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_col_fft<1024, 16, 1, 2> + k_col_fft<1024, 16, 1, 0>, per scope",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 2099723.41, "fetch_factor": 1.99991,
         "write_kib": 6291456.00, "write_factor": 1.0,
     },
@@ -99,7 +99,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_row_c2r<512>, mean of three",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 2121053.69, "fetch_factor": 1.99991,
         "write_kib": 4196639.47, "write_factor": 1.0,
     },
@@ -127,7 +127,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_row_r2c<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 16778450.19, "fetch_factor": 1.99991,
         "write_kib": 33587762.97, "write_factor": 1.0,
     },
@@ -135,7 +135,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_col_fft<2048, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 16817560.25, "fetch_factor": 1.99991,
         "write_kib": 33554432.00, "write_factor": 1.0,
     },
@@ -143,7 +143,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_col_zconv<2048, 4, 3, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 21600719.19, "fetch_factor": 1.99991,
         "write_kib": 82437744.69, "write_factor": 1.0,
     },
@@ -151,7 +151,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 25223424.53, "fetch_factor": 1.99991,
         "write_kib": 50378232.62, "write_factor": 1.0,
     },
@@ -159,7 +159,7 @@ MEASURED_TRAFFIC = {
         "kernel": "k_row_c2r<1024>, mean of three",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "85b7fa2e5226e6d2eec4eaeecdb1e0ccbb3e2d55bddcce029ab7eb2322745962",
+        "sha256": "f0058f83c37dafa7b9ab65cb24a7e8e31b29e5beb999f1d2bfc6c1bb12f15616",
         "fetch_kib": 16788719.65, "fetch_factor": 1.99991,
         "write_kib": 33573340.29, "write_factor": 1.0,
     },

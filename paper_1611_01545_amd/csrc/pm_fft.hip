@@ -881,8 +881,9 @@ __global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h, int kern
 // lines is N/2, so W always divides the line count), W runs of 8-byte points per global
 // access; LDS per workgroup (the exchange tiles, plus staged twiddles for two-output
 // passes) within what one gfx950 workgroup may hold. Split lines (2048 points) take 16
-// columns (1024 threads: 128-byte runs) in one-output passes and 8 in two-output passes,
-// whose two register arrays do not fit 1024 threads.
+// columns (1024 threads: 128-byte runs) in one-output passes and 8 in two-output y
+// passes, whose two register arrays do not fit 1024 threads (the fused z pass takes 4,
+// zconv_w); narrower workgroups read their parts of 128-byte runs in tile order xcd_group.
 template <int N, bool TWO>
 constexpr int col_w() {
   int w = 16384 / N;
