@@ -189,7 +189,8 @@ pm_status pm_query_sizes(const pm_config* cfg, int64_t n_max, int n_sp, pm_sizes
   st += grown(n3 * 4);                                  // spectrum scratch mesh
   st += grown(3 * n2 * 4);                              // per-row max |a| partials (bound)
   st += n_sp * grown((nc3 + 1) * 8);                    // cell offsets per species
-  st += grown((nc3 + 1) * 8) * 2;                       // new offsets, decode/pack offsets
+  st += grown((nc3 + 1) * 8);                           // decode/pack offsets
+  st += grown((nb + 1) * 8) + grown(nb * 4);            // re-sort: brick starts and totals
   st += grown(nc3 * 8 * n_sp);                          // new counts per cell
   st += grown(nc3 * 4) * 2 + grown((nc3 + 1) * 8);      // escape flags, their scan, counts
   st += grown(N * 3) + grown(N * 6) + grown(N * 2);     // new codes and digits, old order
