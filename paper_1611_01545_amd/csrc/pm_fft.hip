@@ -295,13 +295,16 @@ struct LP {
 
 // Radix-2 step of a split line (H = 2). After the half-length transforms thread (t, h)
 // holds values of its half's spectrum at frequencies k = (t + T v) + E k2; the partner
-// (t, 1 - h) holds the same k of the other half. Real parts, then imaginary parts, go
-// through the line's LDS; w = exp(SIGN 2 pi i k / N).
+// (t, 1 - h) holds the same k of the other half, 32 lanes away in the same wave (the
+// thread mapping col_thread puts half h in lanes 32 h .. 32 h + 31). SHUF: each value is
+// exchanged across the wave's halves, with no LDS and no barrier (the lane permutes need
+// registers that 1024-thread workgroups, at 128 VGPRs, do not have); otherwise real parts,
+// then imaginary parts, go through the line's LDS. w = exp(SIGN 2 pi i k / N).
 //   DIF = false (forward, after the half transforms): X[k] = Y0 + w Y1 on h = 0,
 //                X[k + N/2] = Y0 - w Y1 on h = 1;
 //   DIF = true  (before the half inverse transforms): Y0 = X[k] + X[k + N/2] on h = 0,
 //                Y1 = (X[k] - X[k + N/2]) w on h = 1.
-template <int N, int SIGN, bool DIF>
+template <int N, int SIGN, bool DIF, bool SHUF>
 __device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h, float* my,
                                              const float2* __restrict__ tw, int tws,
                                              int twmask) {
@@ -309,22 +312,25 @@ __device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h
   float* mine = my + h * (L::E * L::TP);
   const float* other = my + (1 - h) * (L::E * L::TP);
   float pre[L::E];
+  if constexpr (!SHUF) {
 #pragma unroll
-  for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].x;
-  __syncthreads();
+    for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].x;
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < L::E; ++q) pre[q] = other[q * L::TP + t];
-  __syncthreads();
+    for (int q = 0; q < L::E; ++q) pre[q] = other[q * L::TP + t];
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].y;
-  __syncthreads();
+    for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].y;
+    __syncthreads();
+  }
 #pragma unroll
   for (int v = 0; v < L::V; ++v)
 #pragma unroll
     for (int k2 = 0; k2 < L::T; ++k2) {
       const int q = v * L::T + k2;
       const int k = (t + L::T * v) + L::E * k2;
-      const float2 pp = make_float2(pre[q], other[q * L::TP + t]);
+      const float2 pp = SHUF ? make_float2(__shfl_xor(a[q].x, 32, 64), __shfl_xor(a[q].y, 32, 64))
+                             : make_float2(pre[q], other[q * L::TP + t]);
       float2 w = tw[(k * tws) & twmask];  // exp(-2 pi i k / N)
       if (SIGN > 0) w.y = -w.y;
       if (!DIF) {
@@ -340,12 +346,37 @@ __device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h
         else a[q] = cmul(make_float2(pp.x - a[q].x, pp.y - a[q].y), w);
       }
     }
-  __syncthreads();
+  if constexpr (!SHUF) __syncthreads();
+}
+
+// Thread (c, t, h) of a column workgroup: column c < W, line thread t < T, half h:
+// c = tid mod W, (t, h) = (tl mod T, tl / T) for tl = tid / W. PAIRED (split lines whose
+// radix-2 step exchanges lanes): c = lane mod W, t = (lane / W) mod (32 / W) + (32 / W)
+// wave, h = lane / 32, so that a thread's partner (t, 1 - h) is lane ^ 32 of its wave (a
+// wave still covers 16 consecutive points of its W columns; the 16-column passes keep the
+// first mapping, which they run faster: y forward 15.1 against 17.2 ms at 2048^3).
+template <int N, int W, bool PAIRED = false>
+__device__ __forceinline__ void col_thread(int& c, int& t, int& h) {
+  using L = LP<N>;
+  if constexpr (PAIRED && L::H == 2) {
+    static_assert(L::T == 32 && 32 % W == 0, "a half line's threads fill wave halves");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    c = lane % W;
+    t = (lane / W) % (32 / W) + (32 / W) * wv;
+    h = lane >> 5;
+  } else {
+    c = threadIdx.x % W;
+    const int tl = threadIdx.x / W;
+    t = tl % L::T;
+    h = tl / L::T;
+  }
 }
 
 // Line transforms on the plan: natural -> transposed (forward or inverse) and
 // transposed -> natural. tw: table exp(-2 pi i j / n) of the full line, stride tws.
-template <int N, int SIGN>
+// SHUF: the radix-2 step of split lines by lane exchanges (workgroups narrower than 16
+// columns, whose threads have the registers for them)
+template <int N, int SIGN, bool SHUF = false>
 __device__ __forceinline__ void line_nat_to_tr(float2 (&a)[LP<N>::E], int t, int h, float* my,
                                                const float2* __restrict__ tw, int tws,
                                                int twmask) {
@@ -354,10 +385,10 @@ __device__ __forceinline__ void line_nat_to_tr(float2 (&a)[LP<N>::E], int t, int
     nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
   } else {
     nat_to_tr<L::NH, SIGN>(a, t, my + h * (L::E * L::TP), tw, 2 * tws, twmask);
-    split_radix2<N, SIGN, false>(a, t, h, my, tw, tws, twmask);
+    split_radix2<N, SIGN, false, SHUF>(a, t, h, my, tw, tws, twmask);
   }
 }
-template <int N, int SIGN>
+template <int N, int SIGN, bool SHUF = false>
 __device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int h, float* my,
                                                const float2* __restrict__ tw, int tws,
                                                int twmask) {
@@ -365,7 +396,7 @@ __device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int
   if constexpr (L::H == 1) {
     tr_to_nat<N, SIGN>(a, t, my, tw, tws, twmask);
   } else {
-    split_radix2<N, SIGN, true>(a, t, h, my, tw, tws, twmask);
+    split_radix2<N, SIGN, true, SHUF>(a, t, h, my, tw, tws, twmask);
     tr_to_nat<L::NH, SIGN>(a, t, my + h * (L::E * L::TP), tw, 2 * tws, twmask);
   }
 }
@@ -412,8 +443,8 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
   }
   const unsigned bx = xcd_group<col_group<N, W>()>(blockIdx.x, gridDim.x);
   // the grid covers the lines exactly (W divides the line count; checked on the host)
-  const int c = threadIdx.x % W, tl = threadIdx.x / W;
-  const int t = tl % L::T, h = tl / L::T;
+  int c, t, h;
+  col_thread<N, W>(c, t, h);
   // addresses: a workgroup-uniform 64-bit part plus a 32-bit per-thread offset
   const int64_t ubase = line_base(d, (int64_t)bx * W, blockIdx.y);
   const int e0 = L::H * t + h;  // natural point of n1 = 0; point n1 is e0 + H T n1
@@ -512,6 +543,9 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     const float2* __restrict__ tw, int tws, int twmask, int n,
     const float* __restrict__ gtab, const float* __restrict__ gk) {
   using L = LP<N>;
+  // the radix-2 step of split lines by lane exchanges in the fused forward pass (4 columns
+  // per workgroup at 2048 points: 13 barriers instead of 25)
+  constexpr bool SH = W < 16 && MODE == 3;
   constexpr int ZB = zblk(N), LZB = ilog2(ZB);
   static_assert((L::H * L::T) % ZB == 0, "z blocks must divide the thread stride");
   constexpr int CS = col_cs<W>(L::LF);
@@ -527,8 +561,8 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   for (int i = threadIdx.x; i < N; i += W * L::TL) sgk[i] = gk[i];
   __syncthreads();
   const unsigned bx = xcd_group<col_group<N, W>()>(blockIdx.x, gridDim.x);
-  const int c = threadIdx.x % W, tl = threadIdx.x / W;
-  const int t = tl % L::T, h = tl / L::T;
+  int c, t, h;
+  col_thread<N, W, SH>(c, t, h);
   const int64_t l1 = (int64_t)bx * W + c;
   // point e0 + H T n1 of the line (e0 = H t + h): z-blocked lines split it as (block,
   // row in block). Addresses are a workgroup-uniform 64-bit part (scalar registers) plus
@@ -552,7 +586,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   if constexpr (MODE == 3) {
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1, SH>(acc, t, h, my, stw, 1, N - 1);
     float2 gz[L::E];
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
@@ -566,16 +600,16 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
         acc[v * L::T + k2] = f;
         gz[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
       }
-    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1, SH>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
-    line_tr_to_nat<N, +1>(gz, t, h, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1, SH>(gz, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) (out1 + (ubase + n1 * step))[toff] = gz[n1];
   } else if constexpr (MODE == 0 || MODE == 2) {
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1, SH>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -592,7 +626,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
           acc[v * L::T + k2] = make_float2(G * f.x, G * f.y);
         }
       }
-    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1, SH>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   } else {
@@ -600,7 +634,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     // after FFT_z(in2)
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in2 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1, SH>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -612,7 +646,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     float2 f[L::E];
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) f[n1] = (in0 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1>(f, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1, SH>(f, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -623,7 +657,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
         const float2 q = acc[v * L::T + k2], p = f[v * L::T + k2];
         acc[v * L::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
       }
-    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1, SH>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   }
