@@ -205,9 +205,10 @@ def stage_bytes(name: str, n: int, wl) -> float:
     return {
         "fft_x_r2c": 8 * n3 + 8 * n2,          # real mesh in, half spectrum + Nyquist out
         "fft_y_fwd": 8 * n3,                    # half spectrum in and out
-        "fft_z": 12 * n3,                       # fused z pass, one in, two out
-        "fft_y_inv": 10 * n3,                   # 2 launches: one in two out, one in one out
+        "fft_z": 8 * n3,                        # the potential's spectrum, in place
+        "fft_y_inv": 8 * n3,                    # in place
         "fft_x_c2r": 8 * n3 + 8 * n2,           # half spectrum + Nyquist in, real out
+        "force_grad": 16 * n3,                  # the potential in, three components out
         "deposit": 3 * N + ns * nc3 + 4 * n3,   # positions, counts, density
         # one launch moves every species: codes in and out, counts, the 3 force meshes
         "interp_kick_drift": 9 * N + 9 * N + 2 * ns * nc3 + 12 * n3,
@@ -353,17 +354,17 @@ def timed_steps(ctx, A, B, wl, torch, steps, warmup):
 def stage_kernel(name: str, n: int):
     """The one kernel template a stage's launches run at mesh side n (the bench workloads:
     4 mesh cells per compression cell, bricks of 4^3 cells), or None when the stage runs
-    several: a kernel's roofline needs that kernel's own launch duration. The z pass is one
-    two-output template (4 columns per workgroup at 2048 points, 16 below); the y inverse
-    is two (at 2048 points the -i k_y launch and two plain ones, below a two-output and a
-    plain one)."""
-    split = n >= 2048
+    several: a kernel's roofline needs that kernel's own launch duration. The force takes
+    one transform of the potential (one launch per pass) and the stencil pass for its
+    three components."""
     return {
         "deposit": "k_deposit_tile<4, 1>",
         "fft_x_r2c": f"k_row_r2c<{n // 2}>",
         "fft_y_fwd": f"k_col_fft<{n}, 16, -1, 0>",
-        "fft_z": f"k_col_zconv<{n}, {4 if split else 16}, 3, true>",
+        "fft_z": f"k_col_zconv<{n}, 16, 0, true>",
+        "fft_y_inv": f"k_col_fft<{n}, 16, 1, 0>",
         "fft_x_c2r": f"k_row_c2r<{n // 2}>",
+        "force_grad": "k_grad4",
         "interp_kick_drift": "k_kick_pair<256, 4, 1, 2>",
     }.get(name)
 

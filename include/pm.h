@@ -383,7 +383,7 @@ pm_status pm_unpack(pm_ctx ctx, const uint8_t* host_buf, int64_t len, pm_species
  *   4 FFT z sweeps   5 FFT y inverse    6 FFT x c2r     7 interpolate-kick-drift
  *   8 re-sort        9 encode/decode   10 adjoint scatter/gather   11 PP force
  *  12 force interpolation without the kick (pm_interp_accel, the long range of
- *     pm_step_p3m) */
+ *     pm_step_p3m)   13 force components from the potential (difference stencil) */
 pm_status pm_profile(pm_ctx ctx, int enable);
 pm_status pm_profile_read(pm_ctx ctx, double* ms, int64_t* launches, int cap);
 

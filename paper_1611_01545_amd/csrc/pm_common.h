@@ -140,7 +140,7 @@ struct pm_context {
 
 enum ProfStage {
   ST_OFFSETS = 0, ST_DEPOSIT, ST_FFT_R2C, ST_FFT_YF, ST_FFT_Z, ST_FFT_YI, ST_FFT_C2R,
-  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_PP, ST_INTERP, ST_N
+  ST_KICK, ST_RESORT, ST_CODEC, ST_ADJOINT, ST_PP, ST_INTERP, ST_GRAD, ST_N
 };
 // Record a begin/end event pair around a group of launches (no-op unless profiling).
 void prof_begin(pm_context* c, int stage);

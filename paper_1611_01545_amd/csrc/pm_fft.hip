@@ -837,6 +837,122 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   }
 }
 
+// ------------------------------------------------------------- force gradient --
+// a_c = -D_c phi for the three axes c, D the fourth-order central difference of eq. (3)'s
+// gradient: D f(x) = n (8 (f(x + 1) - f(x - 1)) - (f(x + 2) - f(x - 2))) / 12 (mesh
+// spacing 1/n, periodic). Its Fourier symbol is i D(k) with the D(k) of the spectral
+// form, so the components equal the three inverse transforms of -i D(k_c) G rho but take
+// one transform of G rho and this pass. A workgroup owns a tile of GX x GY nodes of the
+// (x, y) plane and walks GZ planes along z: each thread keeps a window of five z values
+// of its RPT rows in registers (the z difference), and the current plane, with a halo of
+// two nodes in x and y, is staged in LDS (the x and y differences). Writes the per-block
+// max |a| (float bits) to part[block].
+constexpr int GRAD_T = 256;
+__global__ __launch_bounds__(GRAD_T) void k_grad4(const float* __restrict__ phi, float* ax,
+                                                  float* ay, float* az, int lgn, int GX,
+                                                  int GY, int GZ, float scale,
+                                                  unsigned int* part) {
+  constexpr int RPT = 8;  // rows of the tile per thread
+  __shared__ float tile[(32 + 4) * (64 + 4)];
+  __shared__ float wmax[GRAD_T / 64];
+  const int64_t n = (int64_t)1 << lgn, n2 = n * n;
+  const uint32_t m = (uint32_t)n - 1u;
+  const int LX = GX + 4;                       // staged row length
+  const int nty = (int)(n / GY), ntx = (int)(n / GX);
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty;
+  const int bz = blockIdx.x / (ntx * nty);
+  const int x0 = bx * GX, y0 = by * GY, z0 = bz * GZ;
+  const int nthr = GX * GY / RPT;
+  const int tid = threadIdx.x;
+  const bool act = tid < nthr;
+  const int lx = tid % GX, ly0 = tid / GX;     // rows ly0 + (GY / RPT) r
+  const int ystep = GY / RPT;
+  const uint32_t gx = (uint32_t)(x0 + lx);
+  float w[RPT][5];  // phi at z - 2 .. z + 2 of the thread's rows
+  auto at = [&](uint32_t x, uint32_t y, uint32_t z) {
+    return phi[((int64_t)(z & m) * n + (y & m)) * n + (x & m)];
+  };
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        w[r][k + 1] = at(gx, (uint32_t)(y0 + ly0 + ystep * r), (uint32_t)(z0 - 2 + k));
+  }
+  float amx = 0.f;
+  for (int dz = 0; dz < GZ; ++dz) {
+    const uint32_t z = (uint32_t)(z0 + dz);
+    // the window moves on by one plane: z + 2 comes in
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[r][k] = w[r][k + 1];
+        w[r][4] = at(gx, (uint32_t)(y0 + ly0 + ystep * r), z + 2);
+      }
+    }
+    __syncthreads();  // the previous plane's tile has been read
+    // plane z into LDS: the tile's own nodes from the windows, the halo from memory
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) tile[(ly0 + ystep * r + 2) * LX + lx + 2] = w[r][2];
+    }
+    const int nh = 4 * LX + 4 * GY;  // halo rows (2 above, 2 below) and halo columns
+    for (int i = tid; i < nh; i += GRAD_T) {
+      int ty, tx;
+      if (i < 4 * LX) {
+        const int hr = i / LX;
+        ty = hr < 2 ? hr : GY + hr;  // rows 0, 1 and GY + 2, GY + 3
+        tx = i % LX;
+      } else {
+        const int j = i - 4 * LX;
+        ty = 2 + j / 4;
+        const int hc = j % 4;
+        tx = hc < 2 ? hc : GX + hc;  // columns 0, 1 and GX + 2, GX + 3
+      }
+      tile[ty * LX + tx] = at((uint32_t)(x0 - 2 + tx), (uint32_t)(y0 - 2 + ty), z);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int ty = ly0 + ystep * r + 2, tx = lx + 2;
+        const float* c = tile + ty * LX + tx;
+        const float gxv = 8.f * (c[1] - c[-1]) - (c[2] - c[-2]);
+        const float gyv = 8.f * (c[LX] - c[-LX]) - (c[2 * LX] - c[-2 * LX]);
+        const float gzv = 8.f * (w[r][3] - w[r][1]) - (w[r][4] - w[r][0]);
+        const float a0 = -scale * gxv, a1 = -scale * gyv, a2 = -scale * gzv;
+        const int64_t o = (int64_t)z * n2 + (int64_t)(y0 + ly0 + ystep * r) * n + gx;
+        ax[o] = a0;
+        ay[o] = a1;
+        az[o] = a2;
+        amx = fmaxf(amx, fmaxf(fabsf(a0), fmaxf(fabsf(a1), fabsf(a2))));
+      }
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) amx = fmaxf(amx, __shfl_xor(amx, d, 64));
+  if ((tid & 63) == 0) wmax[tid >> 6] = amx;
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) amx = fmaxf(amx, wmax[q]);
+    part[blockIdx.x] = __float_as_uint(amx);
+  }
+}
+
+// tile of the gradient pass at mesh side n: GX x GY nodes, GZ planes per workgroup
+struct GradTile {
+  int gx, gy, gz;
+  int64_t blocks;
+};
+GradTile grad_tile(int64_t n) {
+  GradTile t;
+  t.gx = (int)std::min<int64_t>(n, 64);
+  t.gy = (int)std::min<int64_t>(n, 32);
+  t.gz = (int)std::min<int64_t>(n, 64);
+  t.blocks = (n / t.gx) * (n / t.gy) * (n / t.gz);
+  return t;
+}
+
 // ---------------------------------------------------------------- kernel table --
 // K1(x) = int_0^inf exp(-x cosh s) cosh s ds by the trapezoidal rule, which converges
 // exponentially fast for this analytic, doubly-exponentially decaying integrand.
@@ -1159,20 +1275,17 @@ pm_status build_kernel_table(pm_context* c) {
 //   c2r   a_x = IFFT_x(-i k_x U1): A1 -> A0;  a_y: A2 -> A1;  a_z: S -> A2
 pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, float* amax) {
   const int n = (int)c->g.ng;
-  const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  const int64_t n3 = (int64_t)n * n * n;
   FftCtx f{c, n, n - 1};
-  float2* A0 = (float2*)acc;
   float2* A1 = (float2*)(acc + n3);
-  float2* A2 = (float2*)(acc + 2 * n3);
-  float2* S = (float2*)scratch(c, SC_SPEC, (size_t)n3 * sizeof(float));
-  if (!S) return PM_ERR_NOMEM;
-  float2 *N0 = nyq, *N1 = nyq + n2, *N2 = nyq + 2 * n2;
+  float* phi = (float*)scratch(c, SC_SPEC, (size_t)n3 * sizeof(float));
+  if (!phi) return PM_ERR_NOMEM;
+  float2* N0 = nyq;
   pm_status s;
-  // per-block partial maxima of |a| of the three c2r launches
-  const int64_t nrow_blocks = d_row_blocks(n);
+  const GradTile gt = grad_tile(n);
   unsigned int* part = nullptr;
   if (amax) {
-    part = (unsigned int*)scratch(c, SC_PARTS, (size_t)3 * nrow_blocks * 4);
+    part = (unsigned int*)scratch(c, SC_PARTS, (size_t)gt.blocks * 4);
     if (!part) return PM_ERR_NOMEM;
   }
   {
@@ -1186,50 +1299,34 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
     if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, -1)) != PM_OK) return s;
   }
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, -1)) != PM_OK) return s;
-  // The z pass is one two-output launch at every size (at 2048 points 4 columns per
-  // workgroup, the parts of a 128-byte run grouped on one XCD: 42.4 ms at 2048^3 against
-  // 46.8 ms for two one-output launches of 16 columns, which read the input twice and
-  // transform it four times instead of three). The y inverse of split lines runs its two outputs as two
-  // one-output launches of 16 columns instead (46.8 against 49.4 ms at 2048^3).
-  const bool wide = n >= 2048;
+  // the potential's spectrum G rho, in place
   {
     ProfScope ps(c, ST_FFT_Z);
-    if ((s = d_col_zconv(f, 3, true, A1, nullptr, nullptr, A1, S, zm, n)) != PM_OK) return s;
-  }
-  if ((s = d_col_zconv(f, 3, false, N0, nullptr, nullptr, N0, N2, zn, 1)) != PM_OK) return s;
-  {
-    ProfScope ps(c, ST_FFT_YI);
-    if (wide) {
-      if ((s = d_col_fft(f, A1, nullptr, A2, ym, n, +1)) != PM_OK) return s;
-      if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, +1)) != PM_OK) return s;
-    } else if ((s = d_col_fft(f, A1, A1, A2, ym, n, +1)) != PM_OK) {
+    if ((s = d_col_zconv(f, 0, true, A1, nullptr, nullptr, A1, nullptr, zm, n)) != PM_OK)
       return s;
-    }
   }
+  if ((s = d_col_zconv(f, 0, false, N0, nullptr, nullptr, N0, nullptr, zn, 1)) != PM_OK)
+    return s;
   {
     ProfScope ps(c, ST_FFT_YI);
-    if ((s = d_col_fft(f, S, S, nullptr, ym, n, +1)) != PM_OK) return s;
+    if ((s = d_col_fft(f, A1, A1, nullptr, ym, n, +1)) != PM_OK) return s;
   }
-  if ((s = d_col_fft(f, N0, N0, N1, yn, 1, +1)) != PM_OK) return s;
-  if ((s = d_col_fft(f, N2, N2, nullptr, yn, 1, +1)) != PM_OK) return s;
-  const float2* ins[3] = {A1, A2, S};
-  float* outs[3] = {(float*)A0, (float*)A1, (float*)A2};
-  const float2* nqs[3] = {N0, N1, N2};
-  for (int ax = 0; ax < 3; ++ax) {
+  if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, +1)) != PM_OK) return s;
+  {
     ProfScope ps(c, ST_FFT_C2R);
-    if ((s = d_row_c2r(f, ins[ax], nqs[ax], outs[ax], ax == 0 ? 1 : 0,
-                       part ? part + ax * nrow_blocks : nullptr)) != PM_OK)
-      return s;
+    if ((s = d_row_c2r(f, A1, N0, phi, 0, nullptr)) != PM_OK) return s;
   }
-  if (amax) return fold_max_u32(c, part, 3 * nrow_blocks, (uint32_t*)amax);
+  // the three components from the potential by the difference stencil
+  {
+    ProfScope ps(c, ST_GRAD);
+    hipLaunchKernelGGL(k_grad4, dim3((unsigned)gt.blocks), dim3(GRAD_T), 0, c->stream,
+                       (const float*)phi, acc, acc + n3, acc + 2 * n3, ilog2(n), gt.gx, gt.gy,
+                       gt.gz, (float)((double)n / 12.0), part);
+    PM_LAUNCH_CHECK();
+  }
+  if (amax) return fold_max_u32(c, part, gt.blocks, (uint32_t*)amax);
   return PM_OK;
 }
-
-// nu = sum_a IDFT(+i k_a G DFT(mu_a)) with mu_a in A0..A2 (destroyed); nu lands in A0.
-//   r2c   mu_z: A2 -> S;  mu_y: A1 -> A2;  mu_x: A0 -> A1
-//   Y     S in place;  +i (k_x Y(A1) + k_y Y(A2)) -> A1 (one pass, k_x is constant along
-//         a y line, so the x and y terms need one stored spectrum instead of two)
-//   Z     (A1, S) -> A1;   Y^-1 A1;   c2r A1 -> A0
 pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
   const int n = (int)c->g.ng;
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;

@@ -409,7 +409,7 @@ class PMContext:
 
     STAGES = ["cell_offsets", "deposit", "fft_x_r2c", "fft_y_fwd", "fft_z",
               "fft_y_inv", "fft_x_c2r", "interp_kick_drift", "resort", "codec", "adjoint",
-              "pp", "interp"]
+              "pp", "interp", "force_grad"]
 
     def profile(self, enable: bool = True):
         check(self.lib.pm_profile(self.h, 1 if enable else 0), "pm_profile")

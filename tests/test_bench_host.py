@@ -17,8 +17,9 @@ def test_byte_model_headline_totals():
     wl = make_workload("plain_cdm_64")  # shape only; the model is linear in N and n^3
     n = 1024
     n3 = float(n) ** 3
-    assert bench.stage_bytes("fft_z", n, wl) == 12 * n3
+    assert bench.stage_bytes("fft_z", n, wl) == 8 * n3
     assert bench.stage_bytes("fft_y_fwd", n, wl) == 8 * n3
+    assert bench.stage_bytes("force_grad", n, wl) == 16 * n3  # 4 n^3 in, 12 n^3 out
     assert bench.stage_bytes("unknown", n, wl) == 0.0
     N = wl.n_particles
     assert bench.stage_bytes("interp_kick_drift", n, wl) == 18 * N + 2 * wl.n_cell ** 3 + 12 * n3
@@ -48,16 +49,17 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_dominant_kernel_is_one_template():
-    # the y inverse runs two kernel templates: the roofline goes to the single-template
-    # stage with the largest time per step, even when the y inverse takes longer
+    # the roofline goes to the single-template stage with the largest time per step; the
+    # re-sort (several templates) is never picked, even when it takes longest
     wl = types.SimpleNamespace(n_particles=10 ** 9, species=[0, 1], n_cell=512, n_mesh=2048)
-    st = {k: {"ms_per_step": ms} for k, ms in (("fft_z", 43.5), ("fft_y_inv", 46.8),
-                                               ("fft_x_c2r", 38.7), ("interp_kick_drift", 38.0),
-                                               ("deposit", 23.1), ("resort", 16.7))}
-    assert bench.dominant_kernel_stage(st, 2048, wl) == "fft_z"
-    assert bench.stage_kernel("fft_z", 2048) == "k_col_zconv<2048, 4, 3, true>"
-    assert bench.stage_kernel("fft_y_inv", 2048) is None
-    assert bench.stage_kernel("fft_x_c2r", 2048) == "k_row_c2r<1024>"
-    assert bench.stage_kernel("fft_z", 1024) == "k_col_zconv<1024, 16, 3, true>"
-    st["fft_z"]["ms_per_step"] = 30.0
-    assert bench.dominant_kernel_stage(st, 2048, wl) == "fft_x_c2r"
+    st = {k: {"ms_per_step": ms} for k, ms in (("fft_z", 27.8), ("fft_y_inv", 14.8),
+                                               ("fft_x_c2r", 12.5), ("interp_kick_drift", 38.0),
+                                               ("force_grad", 27.2), ("deposit", 23.1),
+                                               ("resort", 40.0))}
+    assert bench.dominant_kernel_stage(st, 2048, wl) == "interp_kick_drift"
+    assert bench.stage_kernel("fft_z", 2048) == "k_col_zconv<2048, 16, 0, true>"
+    assert bench.stage_kernel("fft_y_inv", 2048) == "k_col_fft<2048, 16, 1, 0>"
+    assert bench.stage_kernel("force_grad", 2048) == "k_grad4"
+    assert bench.stage_kernel("resort", 2048) is None
+    st["force_grad"]["ms_per_step"] = 50.0
+    assert bench.dominant_kernel_stage(st, 2048, wl) == "force_grad"
