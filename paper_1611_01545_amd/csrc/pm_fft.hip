@@ -1264,15 +1264,17 @@ pm_status build_kernel_table(pm_context* c) {
   return PM_OK;
 }
 
-// Buffers: A0, A1, A2 are the three force meshes (acc), S one scratch mesh; N0..N2 the
-// Nyquist planes. Spectra are z-blocked, real meshes natural, so the x passes are out of
-// place:
-//   r2c   rho -> A1                        (rho may be A0)
-//   Y     A1 in place
-//   Z     T1 = G F: A1 in place and T2 = -i k_z G F: A1 -> S, one launch
-//   Y^-1  U1 = IFFT_y(T1): A1 and U2 = IFFT_y(-i k_y T1): A1 -> A2 (one read);
-//         U3 = IFFT_y(T2): S
-//   c2r   a_x = IFFT_x(-i k_x U1): A1 -> A0;  a_y: A2 -> A1;  a_z: S -> A2
+// Buffers: A0, A1, A2 are the three force meshes (acc), S one scratch mesh; N0 the
+// Nyquist plane. Spectra are z-blocked, real meshes natural, so the x passes are out of
+// place. The components of eq. (3) are the inverse transforms of -i D(k_a) G rho; D is
+// the symbol of the fourth-order difference, so they are -D phi of the potential phi,
+// which takes one inverse transform:
+//   r2c    rho -> A1                       (rho may be A0)
+//   Y      A1 in place
+//   Z      G F: A1 in place
+//   Y^-1   A1 in place
+//   c2r    phi: A1 -> S
+//   k_grad4  a = -D phi: S -> A0, A1, A2, and the per-block max |a|
 pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, float* amax) {
   const int n = (int)c->g.ng;
   const int64_t n3 = (int64_t)n * n * n;
