@@ -59,49 +59,57 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "e57d8ef1bb500837b2346c4c10e22c7652ae39f7d1b32f9533c1198416ab5f13",
-        "fetch_kib": 509671.56, "fetch_factor": 1.99989,
-        "write_kib": 4195358.56, "write_factor": 1.0,
+        "sha256": "b9a87e867dd2bf2cbf2a0cc2afdd62c96ded767a8296bfd572bb2c7e4006dc23",
+        "fetch_kib": 509663.50, "fetch_factor": 1.99992,
+        "write_kib": 4195391.69, "write_factor": 1.0,
     },
     ("fft_x_r2c", "tile_1024"): {
         "kernel": "k_row_r2c<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 2097298.81, "fetch_factor": 1.99989,
-        "write_kib": 4202754.31, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 2097315.06, "fetch_factor": 1.99992,
+        "write_kib": 4202742.31, "write_factor": 1.0,
     },
     ("fft_y_fwd", "tile_1024"): {
         "kernel": "k_col_fft<1024, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 2097346.94, "fetch_factor": 1.99989,
-        "write_kib": 4194304.00, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 2097347.69, "fetch_factor": 1.99992,
+        "write_kib": 4194304.25, "write_factor": 1.0,
     },
     ("fft_z", "tile_1024"): {
-        "kernel": "k_col_zconv<1024, 16, 3, true>",
+        "kernel": "k_col_zconv<1024, 16, 0, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 2633818.94, "fetch_factor": 1.99989,
-        "write_kib": 8388608.00, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 2628546.44, "fetch_factor": 1.99992,
+        "write_kib": 4194304.00, "write_factor": 1.0,
     },
     ("fft_y_inv", "tile_1024"): {
-        "kernel": "k_col_fft<1024, 16, 1, 2> + k_col_fft<1024, 16, 1, 0>, per scope",
+        "kernel": "k_col_fft<1024, 16, 1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 2099763.34, "fetch_factor": 1.99989,
-        "write_kib": 6291456.00, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 2097338.06, "fetch_factor": 1.99992,
+        "write_kib": 4194304.00, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
-        "kernel": "k_row_c2r<512>, mean of three",
+        "kernel": "k_row_c2r<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 2121045.31, "fetch_factor": 1.99989,
-        "write_kib": 4196659.88, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 2132864.81, "fetch_factor": 1.99992,
+        "write_kib": 4194304.00, "write_factor": 1.0,
+    },
+    ("force_grad", "tile_1024"): {
+        "kernel": "k_grad4",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 4659877.19, "fetch_factor": 1.99992,
+        "write_kib": 12583242.62, "write_factor": 1.0,
     },
     ("interp_kick_drift", "tile_1024"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -109,9 +117,9 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "437cc566a89a502efbac922bd7296c781f38386a5ba0df6fb01d777150c59b30",
-        "fetch_kib": 8193622.19, "fetch_factor": 1.99989,
-        "write_kib": 2259008.03, "write_factor": 1.0,
+        "sha256": "b0a02528713e05ab4f8f47f7431efcc8e69725f6a97ff51bc2254cfa6440b90d",
+        "fetch_kib": 8193834.38, "fetch_factor": 1.99992,
+        "write_kib": 2258991.50, "write_factor": 1.0,
     },
     ("deposit", "large_2048"): {
         "kernel": "k_deposit_tile<4, 1>",
@@ -119,49 +127,57 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "e57d8ef1bb500837b2346c4c10e22c7652ae39f7d1b32f9533c1198416ab5f13",
-        "fetch_kib": 4071072.25, "fetch_factor": 1.99991,
-        "write_kib": 33555468.12, "write_factor": 1.0,
+        "sha256": "b9a87e867dd2bf2cbf2a0cc2afdd62c96ded767a8296bfd572bb2c7e4006dc23",
+        "fetch_kib": 4074326.56, "fetch_factor": 1.99993,
+        "write_kib": 33555593.81, "write_factor": 1.0,
     },
     ("fft_x_r2c", "large_2048"): {
         "kernel": "k_row_r2c<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 16778410.31, "fetch_factor": 1.99991,
-        "write_kib": 33587756.22, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 16778411.31, "fetch_factor": 1.99993,
+        "write_kib": 33587747.56, "write_factor": 1.0,
     },
     ("fft_y_fwd", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 16816752.50, "fetch_factor": 1.99991,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 16817976.69, "fetch_factor": 1.99993,
         "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_z", "large_2048"): {
-        "kernel": "k_col_zconv<2048, 4, 3, true>",
+        "kernel": "k_col_zconv<2048, 16, 0, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 21263849.75, "fetch_factor": 1.99991,
-        "write_kib": 78307153.78, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 24614965.31, "fetch_factor": 1.99993,
+        "write_kib": 41418794.00, "write_factor": 1.0,
     },
     ("fft_y_inv", "large_2048"): {
-        "kernel": "k_col_fft<2048, 16, 1, 1> + 2 x k_col_fft<2048, 16, 1, 0>, per scope",
+        "kernel": "k_col_fft<2048, 16, 1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 25223111.69, "fetch_factor": 1.99991,
-        "write_kib": 50377023.69, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 16817226.25, "fetch_factor": 1.99993,
+        "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_x_c2r", "large_2048"): {
-        "kernel": "k_row_c2r<1024>, mean of three",
+        "kernel": "k_row_c2r<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "f624a57733987bbe684df3e2a6d9413e63982d3d37e42e6d37f0fec396d7b0d7",
-        "fetch_kib": 16788714.23, "fetch_factor": 1.99991,
-        "write_kib": 33573490.81, "write_factor": 1.0,
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 16794152.75, "fetch_factor": 1.99993,
+        "write_kib": 33554436.00, "write_factor": 1.0,
+    },
+    ("force_grad", "large_2048"): {
+        "kernel": "k_grad4",
+        "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
+                    "paper_1611_01545_amd/csrc/pm_common.h"],
+        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
+        "fetch_kib": 37806086.62, "fetch_factor": 1.99993,
+        "write_kib": 100666023.06, "write_factor": 1.0,
     },
     ("interp_kick_drift", "large_2048"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -169,9 +185,9 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_common.h",
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
-        "sha256": "437cc566a89a502efbac922bd7296c781f38386a5ba0df6fb01d777150c59b30",
-        "fetch_kib": 66443233.81, "fetch_factor": 1.99991,
-        "write_kib": 17974312.31, "write_factor": 1.0,
+        "sha256": "b0a02528713e05ab4f8f47f7431efcc8e69725f6a97ff51bc2254cfa6440b90d",
+        "fetch_kib": 66453990.88, "fetch_factor": 1.99993,
+        "write_kib": 17961556.25, "write_factor": 1.0,
     },
 }
 
