@@ -2,21 +2,20 @@
 //
 // The paper transforms each tile with three threaded 1-D FFTW calls, one per
 // dimension (Sec. 2.3). Here every axis pass is one HBM pass over the mesh, and the
-// kernel multiply and gradient factors are fused into the passes; the four transforms
-// of a step (one forward, three inverse) take these sweeps:
+// kernel multiply is fused into the z pass; the potential of a step takes these sweeps:
 //   X  r2c      rho(x) -> rho~(kx)                     rows; Nyquist column kx = n/2
 //                                                      kept in a side plane
 //   Y  fwd      -> rho~(kx, ky)                        columns, in place
 //   Z  fused    forward z FFT, multiply by G(|k|^2) (softened kernel table), inverse z
-//               FFT: T1 = IFFT_z(G rho~) and T2 = IFFT_z(-i k_z G rho~) from one read
-//   Y  inv      U1 = IFFT_y(T1) and U2 = IFFT_y(-i k_y T1) from one read, U3 = IFFT_y(T2)
-//   X  c2r      a_x = IFFT_x(-i k_x U1), a_y = IFFT_x(U2), a_z = IFFT_x(U3), and
-//               max |a| for the velocity bound of the re-encode
-// 8 launches moving 72 n^3 bytes, against 12 plain passes and separate multiplies.
-// The gradient factor of eq. (3) is -i D(k_a), D the symbol of the fourth-order central
-// difference (written k below; zero on the Nyquist index: the bare -i k truncated at the
-// Nyquist cube rings along the mesh axes); the 1/n^3 of the inverse transform is folded
-// into the kernel table.
+//               FFT, in place
+//   Y  inv      columns, in place
+//   X  c2r      phi(x), real
+// and the force a = -D phi (eq. (3)), D the fourth-order central difference, is one
+// stencil pass over phi (k_grad4) that also takes max |a| for the velocity bound of the
+// re-encode: 6 launches moving 52 n^3 bytes. The stencil is the exact real-space form of
+// the spectral factor -i D(k_a), D(k) its symbol (which is zero on the Nyquist index).
+// The transposed force (adjoint) applies that factor in the spectrum, in the y and z
+// passes. The 1/n^3 of the inverse transform is folded into the kernel table.
 //
 // A line of N points is transformed as N = T x E (four-step): each of T threads holds
 // E points strided by T, does an E-point DFT in registers, multiplies by twiddles,
@@ -295,16 +294,13 @@ struct LP {
 
 // Radix-2 step of a split line (H = 2). After the half-length transforms thread (t, h)
 // holds values of its half's spectrum at frequencies k = (t + T v) + E k2; the partner
-// (t, 1 - h) holds the same k of the other half, 32 lanes away in the same wave (the
-// thread mapping col_thread puts half h in lanes 32 h .. 32 h + 31). SHUF: each value is
-// exchanged across the wave's halves, with no LDS and no barrier (the lane permutes need
-// registers that 1024-thread workgroups, at 128 VGPRs, do not have); otherwise real parts,
-// then imaginary parts, go through the line's LDS. w = exp(SIGN 2 pi i k / N).
+// (t, 1 - h) holds the same k of the other half. Real parts, then imaginary parts, go
+// through the line's LDS; w = exp(SIGN 2 pi i k / N).
 //   DIF = false (forward, after the half transforms): X[k] = Y0 + w Y1 on h = 0,
 //                X[k + N/2] = Y0 - w Y1 on h = 1;
 //   DIF = true  (before the half inverse transforms): Y0 = X[k] + X[k + N/2] on h = 0,
 //                Y1 = (X[k] - X[k + N/2]) w on h = 1.
-template <int N, int SIGN, bool DIF, bool SHUF>
+template <int N, int SIGN, bool DIF>
 __device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h, float* my,
                                              const float2* __restrict__ tw, int tws,
                                              int twmask) {
@@ -312,25 +308,22 @@ __device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h
   float* mine = my + h * (L::E * L::TP);
   const float* other = my + (1 - h) * (L::E * L::TP);
   float pre[L::E];
-  if constexpr (!SHUF) {
 #pragma unroll
-    for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].x;
-    __syncthreads();
+  for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].x;
+  __syncthreads();
 #pragma unroll
-    for (int q = 0; q < L::E; ++q) pre[q] = other[q * L::TP + t];
-    __syncthreads();
+  for (int q = 0; q < L::E; ++q) pre[q] = other[q * L::TP + t];
+  __syncthreads();
 #pragma unroll
-    for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].y;
-    __syncthreads();
-  }
+  for (int q = 0; q < L::E; ++q) mine[q * L::TP + t] = a[q].y;
+  __syncthreads();
 #pragma unroll
   for (int v = 0; v < L::V; ++v)
 #pragma unroll
     for (int k2 = 0; k2 < L::T; ++k2) {
       const int q = v * L::T + k2;
       const int k = (t + L::T * v) + L::E * k2;
-      const float2 pp = SHUF ? make_float2(__shfl_xor(a[q].x, 32, 64), __shfl_xor(a[q].y, 32, 64))
-                             : make_float2(pre[q], other[q * L::TP + t]);
+      const float2 pp = make_float2(pre[q], other[q * L::TP + t]);
       float2 w = tw[(k * tws) & twmask];  // exp(-2 pi i k / N)
       if (SIGN > 0) w.y = -w.y;
       if (!DIF) {
@@ -346,37 +339,23 @@ __device__ __forceinline__ void split_radix2(float2 (&a)[LP<N>::E], int t, int h
         else a[q] = cmul(make_float2(pp.x - a[q].x, pp.y - a[q].y), w);
       }
     }
-  if constexpr (!SHUF) __syncthreads();
+  __syncthreads();
 }
 
 // Thread (c, t, h) of a column workgroup: column c < W, line thread t < T, half h:
-// c = tid mod W, (t, h) = (tl mod T, tl / T) for tl = tid / W. PAIRED (split lines whose
-// radix-2 step exchanges lanes): c = lane mod W, t = (lane / W) mod (32 / W) + (32 / W)
-// wave, h = lane / 32, so that a thread's partner (t, 1 - h) is lane ^ 32 of its wave (a
-// wave still covers 16 consecutive points of its W columns; the 16-column passes keep the
-// first mapping, which they run faster: y forward 15.1 against 17.2 ms at 2048^3).
-template <int N, int W, bool PAIRED = false>
+// c = tid mod W, (t, h) = (tl mod T, tl / T) for tl = tid / W.
+template <int N, int W>
 __device__ __forceinline__ void col_thread(int& c, int& t, int& h) {
   using L = LP<N>;
-  if constexpr (PAIRED && L::H == 2) {
-    static_assert(L::T == 32 && 32 % W == 0, "a half line's threads fill wave halves");
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    c = lane % W;
-    t = (lane / W) % (32 / W) + (32 / W) * wv;
-    h = lane >> 5;
-  } else {
-    c = threadIdx.x % W;
-    const int tl = threadIdx.x / W;
-    t = tl % L::T;
-    h = tl / L::T;
-  }
+  c = threadIdx.x % W;
+  const int tl = threadIdx.x / W;
+  t = tl % L::T;
+  h = tl / L::T;
 }
 
 // Line transforms on the plan: natural -> transposed (forward or inverse) and
 // transposed -> natural. tw: table exp(-2 pi i j / n) of the full line, stride tws.
-// SHUF: the radix-2 step of split lines by lane exchanges (workgroups narrower than 16
-// columns, whose threads have the registers for them)
-template <int N, int SIGN, bool SHUF = false>
+template <int N, int SIGN>
 __device__ __forceinline__ void line_nat_to_tr(float2 (&a)[LP<N>::E], int t, int h, float* my,
                                                const float2* __restrict__ tw, int tws,
                                                int twmask) {
@@ -385,10 +364,10 @@ __device__ __forceinline__ void line_nat_to_tr(float2 (&a)[LP<N>::E], int t, int
     nat_to_tr<N, SIGN>(a, t, my, tw, tws, twmask);
   } else {
     nat_to_tr<L::NH, SIGN>(a, t, my + h * (L::E * L::TP), tw, 2 * tws, twmask);
-    split_radix2<N, SIGN, false, SHUF>(a, t, h, my, tw, tws, twmask);
+    split_radix2<N, SIGN, false>(a, t, h, my, tw, tws, twmask);
   }
 }
-template <int N, int SIGN, bool SHUF = false>
+template <int N, int SIGN>
 __device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int h, float* my,
                                                const float2* __restrict__ tw, int tws,
                                                int twmask) {
@@ -396,7 +375,7 @@ __device__ __forceinline__ void line_tr_to_nat(float2 (&a)[LP<N>::E], int t, int
   if constexpr (L::H == 1) {
     tr_to_nat<N, SIGN>(a, t, my, tw, tws, twmask);
   } else {
-    split_radix2<N, SIGN, true, SHUF>(a, t, h, my, tw, tws, twmask);
+    split_radix2<N, SIGN, true>(a, t, h, my, tw, tws, twmask);
     tr_to_nat<L::NH, SIGN>(a, t, my + h * (L::E * L::TP), tw, 2 * tws, twmask);
   }
 }
@@ -416,12 +395,10 @@ __device__ __forceinline__ unsigned xcd_group(unsigned x, unsigned gx) {
 template <int N, int W>
 constexpr int col_group() { return LP<N>::H == 2 && W < 16 ? 16 / W : 1; }
 
-// Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in); OUT 1: out1 = FFT_SIGN(-i k(e) in)
-// only; OUT 2: both from one read. k(e) is the line's own wave number (-i k_y in the
-// inverse y pass). OUT 3 (y lines of the transposed force): out0 = +i k_x FFT_SIGN(in) +
-// i k(e) FFT_SIGN(in1), k_x being constant along a y line. With two lines per thread
-// the twiddles are staged in LDS (32-bit addresses), which keeps both line arrays in
-// registers without spilling.
+// Generic c2c column FFT. OUT 0: out0 = FFT_SIGN(in). OUT 3 (y lines of the transposed
+// force): out0 = +i k_x FFT_SIGN(in) + i k(e) FFT_SIGN(in1), k(e) the line's own wave
+// number, k_x constant along a y line. With two lines per thread the twiddles are staged
+// in LDS (32-bit addresses), which keeps both line arrays in registers without spilling.
 template <int N, int W, int SIGN, int OUT>
 __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
                                                            const float2* in1, float2* out0,
@@ -432,7 +409,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
   using L = LP<N>;
   constexpr int CS = col_cs<W>(L::LF);
   __shared__ float lds[W * CS];
-  constexpr bool TWO = OUT == 2 || OUT == 3;
+  constexpr bool TWO = OUT == 3;
   // Split lines stage their twiddles as well: at 1024 threads (128 VGPRs) the compiler
   // issues the global twiddle loads one at a time, each waited for (y passes at 2048^3)
   constexpr bool STW = TWO || L::H == 2;
@@ -458,15 +435,6 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
 #pragma unroll
   for (int n1 = 0; n1 < L::E; ++n1)
     a[n1] = (in + (ubase + (int64_t)L::H * L::T * n1 * d.es))[lo_in];
-  if constexpr (OUT == 1) {
-    // -i k (x + i y) = k y - i k x; k is the line's own wave number
-#pragma unroll
-    for (int n1 = 0; n1 < L::E; ++n1) {
-      float k = grad_k(gk, e0 + L::H * L::T * n1);
-      a[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
-    }
-    out0 = out1;
-  }
   if constexpr (OUT == 3) {
     float2 b[L::E];
 #pragma unroll
@@ -489,25 +457,6 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
 #pragma unroll
       for (int k2 = 0; k2 < L::T; ++k2)
         (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
-  } else if constexpr (OUT == 2) {
-    float2 b[L::E];
-#pragma unroll
-    for (int n1 = 0; n1 < L::E; ++n1) {
-      float k = grad_k(gk, e0 + L::H * L::T * n1);
-      b[n1] = make_float2(k * a[n1].y, -k * a[n1].x);
-    }
-    line_nat_to_tr<N, SIGN>(a, t, h, my, stw, 1, N - 1);
-#pragma unroll
-    for (int v = 0; v < L::V; ++v)
-#pragma unroll
-      for (int k2 = 0; k2 < L::T; ++k2)
-        (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
-    line_nat_to_tr<N, SIGN>(b, t, h, my, stw, 1, N - 1);
-#pragma unroll
-    for (int v = 0; v < L::V; ++v)
-#pragma unroll
-      for (int k2 = 0; k2 < L::T; ++k2)
-        (out1 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = b[v * L::T + k2];
   } else {
     if constexpr (STW) line_nat_to_tr<N, SIGN>(a, t, h, my, stw, 1, N - 1);
     else line_nat_to_tr<N, SIGN>(a, t, h, my, tw, tws, twmask);
@@ -515,26 +464,14 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_fft(const float2* in,
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
       for (int k2 = 0; k2 < L::T; ++k2)
-        if constexpr (OUT == 1) {
-          // the -i k pass writes out of place (a fresh spectrum): nontemporal stores,
-          // which do not displace the cached input (17.3 against 18.6-19.4 ms at 2048^3;
-          // the in-place passes are slower with them)
-          double dv;
-          __builtin_memcpy(&dv, &a[v * L::T + k2], 8);
-          __builtin_nontemporal_store(
-              dv, (double*)&(out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)]);
-        } else {
-          (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
-        }
+        (out0 + (ubase + (int64_t)L::E * k2 * d.es))[lo_out(v)] = a[v * L::T + k2];
   }
 }
 
 // ---------------------------------------------------------------- fused z pass --
-// F = FFT_z(in0) per line, then MODE 0: out0 = IFFT_z(G F); MODE 2: out0 =
-// IFFT_z(-i k_z G F); MODE 3: both, out0 = IFFT_z(G F) and out1 = IFFT_z(-i k_z G F)
-// from one read (the two inverse transforms run one after the other); MODE 1
-// (transpose of the force): out0 = IFFT_z(G (FFT_z(in0) + i k_z FFT_z(in2))), where in0
-// already holds the x and y terms +i (k_x mu_x + k_y mu_y) from the y pass. BLK: the
+// F = FFT_z(in0) per line, then MODE 0: out0 = IFFT_z(G F) (the potential's spectrum);
+// MODE 1 (transpose of the force): out0 = IFFT_z(G (FFT_z(in0) + i k_z FFT_z(in2))),
+// where in0 already holds the x and y terms +i (k_x mu_x + k_y mu_y) from the y pass. BLK: the
 // lines are z-blocked (main spectrum) or plain strided (Nyquist plane).
 template <int N, int W, int MODE, bool BLK>
 __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
@@ -543,16 +480,13 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     const float2* __restrict__ tw, int tws, int twmask, int n,
     const float* __restrict__ gtab, const float* __restrict__ gk) {
   using L = LP<N>;
-  // the radix-2 step of split lines by lane exchanges in the fused forward pass (4 columns
-  // per workgroup at 2048 points: 13 barriers instead of 25)
-  constexpr bool SH = W < 16 && MODE == 3;
   constexpr int ZB = zblk(N), LZB = ilog2(ZB);
   static_assert((L::H * L::T) % ZB == 0, "z blocks must divide the thread stride");
   constexpr int CS = col_cs<W>(L::LF);
   __shared__ float lds[W * CS];
   // the line's twiddles exp(-2 pi i j / N) in LDS: 32-bit LDS addresses instead of
-  // 64-bit global pointers per twiddle, which the two inverse transforms of MODE 3
-  // would otherwise keep live together
+  // 64-bit global pointers per twiddle, which the two line arrays of MODE 1 would
+  // otherwise keep live together
   __shared__ float2 stw[N];
   for (int i = threadIdx.x; i < N; i += W * L::TL) stw[i] = tw[(i * tws) & twmask];
   // the gradient symbol too (shared by the workgroup's lines): loaded from global memory
@@ -562,7 +496,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   __syncthreads();
   const unsigned bx = xcd_group<col_group<N, W>()>(blockIdx.x, gridDim.x);
   int c, t, h;
-  col_thread<N, W, SH>(c, t, h);
+  col_thread<N, W>(c, t, h);
   const int64_t l1 = (int64_t)bx * W + c;
   // point e0 + H T n1 of the line (e0 = H t + h): z-blocked lines split it as (block,
   // row in block). Addresses are a workgroup-uniform 64-bit part (scalar registers) plus
@@ -583,33 +517,10 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
   const float* __restrict__ grow =
       gtab + ((int64_t)(sx < 0 ? -sx : sx) * h1 + (sy < 0 ? -sy : sy)) * h1;
   float2 acc[L::E];
-  if constexpr (MODE == 3) {
+  if constexpr (MODE == 0) {
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1, SH>(acc, t, h, my, stw, 1, N - 1);
-    float2 gz[L::E];
-#pragma unroll
-    for (int v = 0; v < L::V; ++v)
-#pragma unroll
-      for (int k2 = 0; k2 < L::T; ++k2) {
-        const int kz = (t + L::T * v) + L::E * k2 + h * L::NH;
-        const int sz = signed_k(kz, n);
-        const float G = grow[sz < 0 ? -sz : sz];
-        const float2 f = make_float2(G * acc[v * L::T + k2].x, G * acc[v * L::T + k2].y);
-        const float kk = sgk[kz];
-        acc[v * L::T + k2] = f;
-        gz[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);  // -i k_z G F
-      }
-    line_tr_to_nat<N, +1, SH>(acc, t, h, my, stw, 1, N - 1);
-#pragma unroll
-    for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
-    line_tr_to_nat<N, +1, SH>(gz, t, h, my, stw, 1, N - 1);
-#pragma unroll
-    for (int n1 = 0; n1 < L::E; ++n1) (out1 + (ubase + n1 * step))[toff] = gz[n1];
-  } else if constexpr (MODE == 0 || MODE == 2) {
-#pragma unroll
-    for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in0 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1, SH>(acc, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -618,15 +529,9 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
         const int sz = signed_k(kz, n);
         const float G = grow[sz < 0 ? -sz : sz];
         const float2 f = acc[v * L::T + k2];
-        if constexpr (MODE == 2) {
-          // -i k_z G (x + i y) = k_z G y - i k_z G x
-          const float kk = sgk[kz] * G;
-          acc[v * L::T + k2] = make_float2(kk * f.y, -kk * f.x);
-        } else {
-          acc[v * L::T + k2] = make_float2(G * f.x, G * f.y);
-        }
+        acc[v * L::T + k2] = make_float2(G * f.x, G * f.y);
       }
-    line_tr_to_nat<N, +1, SH>(acc, t, h, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   } else {
@@ -634,7 +539,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     // after FFT_z(in2)
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) acc[n1] = (in2 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1, SH>(acc, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -646,7 +551,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
     float2 f[L::E];
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) f[n1] = (in0 + (ubase + n1 * step))[toff];
-    line_nat_to_tr<N, -1, SH>(f, t, h, my, stw, 1, N - 1);
+    line_nat_to_tr<N, -1>(f, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int v = 0; v < L::V; ++v)
 #pragma unroll
@@ -657,7 +562,7 @@ __global__ __launch_bounds__(W * LP<N>::TL) void k_col_zconv(
         const float2 q = acc[v * L::T + k2], p = f[v * L::T + k2];
         acc[v * L::T + k2] = make_float2(G * (q.x + p.x), G * (q.y + p.y));
       }
-    line_tr_to_nat<N, +1, SH>(acc, t, h, my, stw, 1, N - 1);
+    line_tr_to_nat<N, +1>(acc, t, h, my, stw, 1, N - 1);
 #pragma unroll
     for (int n1 = 0; n1 < L::E; ++n1) (out0 + (ubase + n1 * step))[toff] = acc[n1];
   }
@@ -755,15 +660,13 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_r2c(
   if (t == 0) nyq[row] = make_float2(z0.x - z0.y, 0.f);
 }
 
-// X c2r: in main rows (M complex) + nyq[row] -> out real rows; optional -i k_x factor;
-// max |out| into amax (float bits, non-negative).
+// X c2r: in main rows (M complex) + nyq[row] -> out real rows.
 template <int M>
 constexpr bool c2r_stw() { return M >= 1024; }
 template <int M>
 __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
-    const float2* in, const float2* nyq, float* out, int64_t nrows, int grad,
-    const float2* __restrict__ tw, int twmask, unsigned int* amax,
-    const float* __restrict__ gk) {
+    const float2* in, const float2* nyq, float* out, int64_t nrows,
+    const float2* __restrict__ tw, int twmask) {
   using P = Plan<M>;
   constexpr int R = rows_per_wg<M>();
   constexpr int LF = P::E * P::TP;
@@ -781,21 +684,11 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   const float2* xi = in + spec_row<M>(row);
   const int n = 2 * M;
   float2 xr[P::E];
-  // every load is issued before the first use: with the -i k_x factor inside the load
-  // loop, the branch on grad made each load wait for the one before it (the a_x launch
-  // took 25 ms against 15 for the other two at 2048^3; now all three 14.5 ms)
 #pragma unroll
   for (int j = 0; j < P::E; ++j) xr[j] = xi[t + P::T * j];
   if constexpr (STW) __syncthreads();  // the staged twiddles
-  if (grad) {
-#pragma unroll
-    for (int j = 0; j < P::E; ++j) {
-      const float kk = grad_k(gk, t + P::T * j);
-      xr[j] = make_float2(kk * xr[j].y, -kk * xr[j].x);
-    }
-  }
   float2 xn = make_float2(0.f, 0.f);  // X[M], held by lane t = 0
-  if (t == 0 && !grad) xn = nyq[row];  // -i k_x is zero on the Nyquist index
+  if (t == 0) xn = nyq[row];
   // X[M - k] for k = t + T j: lane (T - t) of the row's lane group holds it at index
   // E - 1 - j; lane t = 0 holds it itself, at index E - j (X[M] for j = 0). The row's T
   // lanes are consecutive and T divides 64, so the partner is in the same wave.
@@ -816,25 +709,10 @@ __global__ __launch_bounds__(rows_per_wg<M>() * Plan<M>::T) void k_row_c2r(
   }
   nat_to_tr<M, +1>(a, t, my, twr, 2, twmask);
   float2* zo = (float2*)(out + row * 2 * M);
-  float m = 0.f;
 #pragma unroll
   for (int v = 0; v < P::V; ++v)
 #pragma unroll
-    for (int k2 = 0; k2 < P::T; ++k2) {
-      float2 z = a[v * P::T + k2];
-      zo[(t + P::T * v) + P::E * k2] = z;
-      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
-    }
-  if (amax) {
-    __shared__ float wmax[16];
-    for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd, 64));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmaxf(m, wmax[q]);
-      amax[blockIdx.x] = __float_as_uint(m);  // per-block partial, folded afterwards
-    }
-  }
+    for (int k2 = 0; k2 < P::T; ++k2) zo[(t + P::T * v) + P::E * k2] = a[v * P::T + k2];
 }
 
 // ------------------------------------------------------------- force gradient --
@@ -1029,11 +907,12 @@ __global__ void k_build_gtab(const float* ktab, float* gtab, int64_t h, int kern
 // ------------------------------------------------------------------ dispatch --
 // columns per workgroup: at most 16 and at most half the line length (the number of kx
 // lines is N/2, so W always divides the line count), W runs of 8-byte points per global
-// access; LDS per workgroup (the exchange tiles, plus staged twiddles for two-output
+// access; LDS per workgroup (the exchange tiles, plus staged twiddles for two-input
 // passes) within what one gfx950 workgroup may hold. Split lines (2048 points) take 16
-// columns (1024 threads: 128-byte runs) in one-output passes and 8 in two-output y
-// passes, whose two register arrays do not fit 1024 threads (the fused z pass takes 4,
-// zconv_w); narrower workgroups read their parts of 128-byte runs in tile order xcd_group.
+// columns (1024 threads: 128-byte runs) in one-line passes and 8 in the two-input y pass
+// of the transposed force, whose two register arrays do not fit 1024 threads (its z
+// pass takes 4, zconv_w); narrower workgroups read their parts of 128-byte runs in tile
+// order xcd_group.
 template <int N, bool TWO>
 constexpr int col_w() {
   int w = 16384 / N;
@@ -1043,7 +922,7 @@ constexpr int col_w() {
   if (w < 1) w = 1;
   return w;
 }
-// the fused z pass with split lines (two line arrays per thread, 225 VGPRs) takes 4
+// the two-input z pass with split lines (two line arrays per thread, 225 VGPRs) takes 4
 // columns: 256 threads and 58 KB of LDS, two workgroups per CU
 template <int N, bool TWO>
 constexpr int zconv_w() {
@@ -1056,30 +935,26 @@ struct FftCtx {
   int twmask;
 };
 
-// out: 0 plain (o0), 1 only the -i k output (o1), 2 both
-// in1 (forward only): the two-input pass OUT 3 into o0
+// out 0: plain, o0 = FFT(in); in1 (forward only): the two-input pass OUT 3 into o0; o1
+// must be null
 template <int N>
 pm_status col_fft(const FftCtx& f, const float2* in, const float2* in1, float2* o0, float2* o1,
                   const Lines& d, int64_t L2, int sign) {
   constexpr int W1 = col_w<N, false>(), W2 = col_w<N, true>();
-  const int out = in1 ? 3 : o1 ? (o0 ? 2 : 1) : 0;
-  if (out == 3 && (sign > 0 || o1)) return PM_ERR_ARG;
-  const int W = (out == 2 || out == 3) ? W2 : W1;
+  const int out = in1 ? 3 : 0;
+  if (o1 || !o0 || (out == 3 && sign > 0)) return PM_ERR_ARG;
+  const int W = out == 3 ? W2 : W1;
   if (d.L1 % W) return PM_ERR_SHAPE;
   dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
   dim3 block(W * LP<N>::TL);
 #define CLAUNCH(S, O)                                                                     \
-  hipLaunchKernelGGL((k_col_fft<N, (O == 2 || O == 3) ? W2 : W1, S, O>), grid, block, 0,  \
+  hipLaunchKernelGGL((k_col_fft<N, O == 3 ? W2 : W1, S, O>), grid, block, 0,             \
                      f.c->stream, in, in1, o0, o1, d, f.c->tw, 1, f.twmask, f.n, f.c->gk)
   if (sign < 0) {
     if (out == 3) CLAUNCH(-1, 3);
-    else if (out == 0) CLAUNCH(-1, 0);
-    else if (out == 1) CLAUNCH(-1, 1);
-    else CLAUNCH(-1, 2);
+    else CLAUNCH(-1, 0);
   } else {
-    if (out == 0) CLAUNCH(1, 0);
-    else if (out == 1) CLAUNCH(1, 1);
-    else CLAUNCH(1, 2);
+    CLAUNCH(1, 0);
   }
 #undef CLAUNCH
   PM_LAUNCH_CHECK();
@@ -1089,25 +964,22 @@ pm_status col_fft(const FftCtx& f, const float2* in, const float2* in1, float2* 
 template <int N>
 pm_status col_zconv(const FftCtx& f, int mode, bool blk, const float2* i0, const float2* i1,
                     const float2* i2, float2* o0, float2* o1, const Lines& d, int64_t L2) {
-  // every fused z pass stages its twiddles; MODE 1 and 3 hold two line arrays
+  // every z pass stages its twiddles; MODE 1 holds two line arrays
+  if (mode != 0 && mode != 1) return PM_ERR_ARG;
   constexpr int W1 = zconv_w<N, false>(), W2 = zconv_w<N, true>();
-  const int W = (mode == 1 || mode == 3) ? W2 : W1;
+  const int W = mode == 1 ? W2 : W1;
   if (d.L1 % W) return PM_ERR_SHAPE;
   dim3 grid((unsigned)(d.L1 / W), (unsigned)L2);
   dim3 block(W * LP<N>::TL);
 #define ZLAUNCH(MODE, BLK)                                                                  \
-  hipLaunchKernelGGL((k_col_zconv<N, (MODE == 1 || MODE == 3) ? W2 : W1, MODE, BLK>), grid, \
+  hipLaunchKernelGGL((k_col_zconv<N, MODE == 1 ? W2 : W1, MODE, BLK>), grid,              \
                      block, 0, f.c->stream, i0, i1, i2, o0, o1, d, f.c->tw, 1, f.twmask,    \
                      f.n, f.c->gtab, f.c->gk)
   if (blk) {
     if (mode == 0) ZLAUNCH(0, true);
-    else if (mode == 2) ZLAUNCH(2, true);
-    else if (mode == 3) ZLAUNCH(3, true);
     else ZLAUNCH(1, true);
   } else {
     if (mode == 0) ZLAUNCH(0, false);
-    else if (mode == 2) ZLAUNCH(2, false);
-    else if (mode == 3) ZLAUNCH(3, false);
     else ZLAUNCH(1, false);
   }
 #undef ZLAUNCH
@@ -1127,13 +999,12 @@ pm_status row_r2c(const FftCtx& f, const float* in, float2* out, float2* nyq) {
 }
 
 template <int M>
-pm_status row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* out, int grad,
-                  unsigned int* amax) {
+pm_status row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* out) {
   constexpr int R = rows_per_wg<M>();
   int64_t nrows = (int64_t)f.n * f.n;
   if (nrows % R) return PM_ERR_SHAPE;
   hipLaunchKernelGGL(k_row_c2r<M>, dim3((unsigned)cdiv(nrows, R)), dim3(R * Plan<M>::T), 0,
-                     f.c->stream, in, nyq, out, nrows, grad, f.c->tw, f.twmask, amax, f.c->gk);
+                     f.c->stream, in, nyq, out, nrows, f.c->tw, f.twmask);
   PM_LAUNCH_CHECK();
   return PM_OK;
 }
@@ -1182,11 +1053,10 @@ pm_status d_row_r2c(const FftCtx& f, const float* in, float2* out, float2* nyq) 
   }
   return PM_ERR_SHAPE;
 }
-pm_status d_row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* out, int grad,
-                    unsigned int* amax) {
+pm_status d_row_c2r(const FftCtx& f, const float2* in, const float2* nyq, float* out) {
   switch (f.n) {
 #define CASE(N) \
-  case N: return row_c2r<N / 2>(f, in, nyq, out, grad, amax);
+  case N: return row_c2r<N / 2>(f, in, nyq, out);
     PM_FFT_SIZES(CASE)
 #undef CASE
   }
@@ -1316,7 +1186,7 @@ pm_status run_force(pm_context* c, const float* rho, float* acc, float2* nyq, fl
   if ((s = d_col_fft(f, N0, N0, nullptr, yn, 1, +1)) != PM_OK) return s;
   {
     ProfScope ps(c, ST_FFT_C2R);
-    if ((s = d_row_c2r(f, A1, N0, phi, 0, nullptr)) != PM_OK) return s;
+    if ((s = d_row_c2r(f, A1, N0, phi)) != PM_OK) return s;
   }
   // the three components from the potential by the difference stencil
   {
@@ -1354,5 +1224,5 @@ pm_status run_force_transpose(pm_context* c, float* acc, float2* nyq) {
     return s;
   if ((s = d_col_fft(f, spec[0], spec[0], nullptr, ym, n, +1)) != PM_OK) return s;
   if ((s = d_col_fft(f, Nq[0], Nq[0], nullptr, yn, 1, +1)) != PM_OK) return s;
-  return d_row_c2r(f, spec[0], Nq[0], (float*)A[0], 0, nullptr);
+  return d_row_c2r(f, spec[0], Nq[0], (float*)A[0]);
 }

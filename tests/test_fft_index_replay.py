@@ -331,35 +331,20 @@ def test_xcd_tile_order(n, kind):
             assert G * W * 8 == 128
 
 
-def col_thread(tid, W, paired):
+def col_thread(tid, W):
     """(c, t, h) of thread tid in a split-line column workgroup (T = 32 threads per half
     line), as the kernels compute it."""
-    if paired:
-        lane, wv = tid & 63, tid >> 6
-        return lane % W, (lane // W) % (32 // W) + (32 // W) * wv, lane >> 5
     tl = tid // W
     return tid % W, tl % 32, tl // 32
 
 
 @pytest.mark.parametrize("W", [1, 2, 4, 8, 16, 32])
-@pytest.mark.parametrize("paired", [False, True])
-def test_split_line_thread_mapping(W, paired):
-    # both mappings cover every (column, line thread, half) once; the paired one puts a
-    # thread's radix-2 partner (t, 1 - h) at lane ^ 32 of the same wave, which the lane
-    # exchange of the split radix-2 step reads
+def test_split_line_thread_mapping(W):
+    # the mapping covers every (column, line thread, half) once, with the W columns of
+    # one (t, h) in consecutive threads (a W x 8 byte run per access)
     n = 64 * W
-    seen = {col_thread(tid, W, paired) for tid in range(n)}
+    seen = {col_thread(tid, W) for tid in range(n)}
     assert seen == {(c, t, h) for c in range(W) for t in range(32) for h in range(2)}
-    if paired:
-        for tid in range(n):
-            c, t, h = col_thread(tid, W, True)
-            assert col_thread(tid ^ 32, W, True) == (c, t, 1 - h)
-            assert (tid ^ 32) >> 6 == tid >> 6
-        # a wave covers 16 consecutive natural points e0 = 2 t + h of each of its columns
-        for wv in range(W):
-            pts = {}
-            for lane in range(64):
-                c, t, h = col_thread(64 * wv + lane, W, True)
-                pts.setdefault(c, set()).add(2 * t + h)
-            for ps in pts.values():
-                assert len(ps) == 64 // W and max(ps) - min(ps) == 64 // W - 1
+    for tid in range(0, n, W):
+        assert [col_thread(tid + c, W) for c in range(W)] == \
+            [(c,) + col_thread(tid, W)[1:] for c in range(W)]
