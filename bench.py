@@ -60,56 +60,56 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
         "sha256": "b9a87e867dd2bf2cbf2a0cc2afdd62c96ded767a8296bfd572bb2c7e4006dc23",
-        "fetch_kib": 509663.50, "fetch_factor": 1.99992,
-        "write_kib": 4195391.69, "write_factor": 1.0,
+        "fetch_kib": 509670.50, "fetch_factor": 1.99992,
+        "write_kib": 4195298.69, "write_factor": 1.0,
     },
     ("fft_x_r2c", "tile_1024"): {
         "kernel": "k_row_r2c<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 2097315.06, "fetch_factor": 1.99992,
-        "write_kib": 4202742.31, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 2097307.62, "fetch_factor": 1.99992,
+        "write_kib": 4202753.28, "write_factor": 1.0,
     },
     ("fft_y_fwd", "tile_1024"): {
         "kernel": "k_col_fft<1024, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 2097347.69, "fetch_factor": 1.99992,
-        "write_kib": 4194304.25, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 2097320.19, "fetch_factor": 1.99992,
+        "write_kib": 4194304.00, "write_factor": 1.0,
     },
     ("fft_z", "tile_1024"): {
         "kernel": "k_col_zconv<1024, 16, 0, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 2628546.44, "fetch_factor": 1.99992,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 2628255.31, "fetch_factor": 1.99992,
         "write_kib": 4194304.00, "write_factor": 1.0,
     },
     ("fft_y_inv", "tile_1024"): {
         "kernel": "k_col_fft<1024, 16, 1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 2097338.06, "fetch_factor": 1.99992,
-        "write_kib": 4194304.00, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 2097342.38, "fetch_factor": 1.99992,
+        "write_kib": 4194304.12, "write_factor": 1.0,
     },
     ("fft_x_c2r", "tile_1024"): {
         "kernel": "k_row_c2r<512>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 2132864.81, "fetch_factor": 1.99992,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 2132485.69, "fetch_factor": 1.99992,
         "write_kib": 4194304.00, "write_factor": 1.0,
     },
     ("force_grad", "tile_1024"): {
         "kernel": "k_grad4",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 4659877.19, "fetch_factor": 1.99992,
-        "write_kib": 12583242.62, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 4654232.88, "fetch_factor": 1.99992,
+        "write_kib": 12583241.62, "write_factor": 1.0,
     },
     ("interp_kick_drift", "tile_1024"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -118,8 +118,8 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
         "sha256": "b0a02528713e05ab4f8f47f7431efcc8e69725f6a97ff51bc2254cfa6440b90d",
-        "fetch_kib": 8193834.38, "fetch_factor": 1.99992,
-        "write_kib": 2258991.50, "write_factor": 1.0,
+        "fetch_kib": 8184960.06, "fetch_factor": 1.99992,
+        "write_kib": 2258737.00, "write_factor": 1.0,
     },
     ("deposit", "large_2048"): {
         "kernel": "k_deposit_tile<4, 1>",
@@ -128,56 +128,56 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
         "sha256": "b9a87e867dd2bf2cbf2a0cc2afdd62c96ded767a8296bfd572bb2c7e4006dc23",
-        "fetch_kib": 4074326.56, "fetch_factor": 1.99993,
-        "write_kib": 33555593.81, "write_factor": 1.0,
+        "fetch_kib": 4074093.69, "fetch_factor": 1.99991,
+        "write_kib": 33555662.69, "write_factor": 1.0,
     },
     ("fft_x_r2c", "large_2048"): {
         "kernel": "k_row_r2c<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 16778411.31, "fetch_factor": 1.99993,
-        "write_kib": 33587747.56, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 16778414.75, "fetch_factor": 1.99991,
+        "write_kib": 33587757.28, "write_factor": 1.0,
     },
     ("fft_y_fwd", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, -1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 16817976.69, "fetch_factor": 1.99993,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 16817661.50, "fetch_factor": 1.99991,
         "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_z", "large_2048"): {
         "kernel": "k_col_zconv<2048, 16, 0, true>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 24614965.31, "fetch_factor": 1.99993,
-        "write_kib": 41418794.00, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 24430745.19, "fetch_factor": 1.99991,
+        "write_kib": 41418787.88, "write_factor": 1.0,
     },
     ("fft_y_inv", "large_2048"): {
         "kernel": "k_col_fft<2048, 16, 1, 0>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 16817226.25, "fetch_factor": 1.99993,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 16816735.56, "fetch_factor": 1.99991,
         "write_kib": 33554432.00, "write_factor": 1.0,
     },
     ("fft_x_c2r", "large_2048"): {
         "kernel": "k_row_c2r<1024>",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 16794152.75, "fetch_factor": 1.99993,
-        "write_kib": 33554436.00, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 16794199.69, "fetch_factor": 1.99991,
+        "write_kib": 33554432.50, "write_factor": 1.0,
     },
     ("force_grad", "large_2048"): {
         "kernel": "k_grad4",
         "sources": ["paper_1611_01545_amd/csrc/pm_fft.hip",
                     "paper_1611_01545_amd/csrc/pm_common.h"],
-        "sha256": "713d76ba82b7635162067f5ffab15c8eb0db3d2f44d992b1fc751f11460d657c",
-        "fetch_kib": 37806086.62, "fetch_factor": 1.99993,
-        "write_kib": 100666023.06, "write_factor": 1.0,
+        "sha256": "4e4f6cc89a2e2681720fffdfb260f2762f1fff1ff8fe8c7ac1a081a52cac4a3a",
+        "fetch_kib": 37783092.44, "fetch_factor": 1.99991,
+        "write_kib": 100666016.34, "write_factor": 1.0,
     },
     ("interp_kick_drift", "large_2048"): {
         "kernel": "k_kick_pair<256, 4, 1, 2>",
@@ -186,8 +186,8 @@ MEASURED_TRAFFIC = {
                     "paper_1611_01545_amd/csrc/pm_codec.h",
                     "paper_1611_01545_amd/csrc/pm_scan.h"],
         "sha256": "b0a02528713e05ab4f8f47f7431efcc8e69725f6a97ff51bc2254cfa6440b90d",
-        "fetch_kib": 66453990.88, "fetch_factor": 1.99993,
-        "write_kib": 17961556.25, "write_factor": 1.0,
+        "fetch_kib": 66441099.62, "fetch_factor": 1.99991,
+        "write_kib": 17960036.72, "write_factor": 1.0,
     },
 }
 
